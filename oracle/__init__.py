@@ -1,0 +1,139 @@
+"""ORACLE -- test infrastructure only.
+
+The plain sequential CPU implementation of G-ES-MC (``gesmc_oracle.cpp``,
+compiled with g++ into ``liboracle.so``) and a naive pure-Python replay
+(``naive.py``).  Only the tests, the smoke check and the benchmark's CPU
+baseline leg may import this package; the HIP library never does, and the
+two share no code.  See ``gesmc_oracle.cpp`` for the definitions followed.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gesmc_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+LEGAL, LOOP, EXISTS, PL = 1, 2, 3, 4
+
+MUT_FLIP_G = 1
+MUT_NO_LOOP = 2
+MUT_NO_EXISTS = 4
+MUT_TAU_SWAP = 8
+MUT_WRITE_SWAP = 16
+MUT_NO_ERASE = 32
+MUT_PAIR_SHIFT = 64
+MUT_KEY_SWAP = 128
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("rej_loop", ctypes.c_uint64),
+                ("rej_exists", ctypes.c_uint64), ("rej_pl", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def build() -> str:
+    """Compile the oracle with g++ (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    u32, u64, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+    lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_perm_key.argtypes = [u64, u32, u64]
+    lib.oracle_perm_key.restype = u64
+    lib.oracle_perm_keys.argtypes = [u64, u32, u64, vp]
+    lib.oracle_perm_keys.restype = None
+    lib.oracle_pl_skip.argtypes = [u64, u32, u64, u32]
+    lib.oracle_pl_skip.restype = ctypes.c_int
+    lib.oracle_permutation_mut.argtypes = [u64, u64, u32, vp, u32]
+    lib.oracle_permutation_mut.restype = None
+    lib.oracle_permutation.argtypes = [u64, u64, u32, vp]
+    lib.oracle_permutation.restype = None
+    lib.oracle_validate.argtypes = [vp, u64, u32]
+    lib.oracle_validate.restype = ctypes.c_int
+    lib.oracle_global_switch.argtypes = [vp, u64, vp, vp, vp, vp, u32]
+    lib.oracle_global_switch.restype = ctypes.c_int
+    lib.oracle_run.argtypes = [vp, u64, u32, u64, u32, u32, u32, vp, vp, u32]
+    lib.oracle_run.restype = ctypes.c_int
+    lib.oracle_selftest_edgeset.argtypes = [u64, u64]
+    lib.oracle_selftest_edgeset.restype = u64
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def perm_keys(m: int, seed: int, t: int) -> np.ndarray:
+    out = np.empty(max(m, 1), dtype=np.uint64)
+    _load().oracle_perm_keys(seed, t, m, _p(out))
+    return out[:m]
+
+
+def pl_skip(seed: int, t: int, k: int, pl: int) -> bool:
+    return bool(_load().oracle_pl_skip(seed, t, k, pl))
+
+
+def permutation(m: int, seed: int, t: int, mutate: int = 0) -> np.ndarray:
+    pi = np.empty(max(m, 1), dtype=np.uint32)
+    _load().oracle_permutation_mut(m, seed, t, _p(pi), mutate)
+    return pi[:m]
+
+
+def validate(E: np.ndarray, n: int) -> int:
+    E = np.ascontiguousarray(E, dtype=np.uint64)
+    return _load().oracle_validate(_p(E), len(E), n)
+
+
+def global_switch(E: np.ndarray, pi, skip=None, mutate: int = 0):
+    """One global switch with explicit pi / skip mask.  Returns (E', outcomes, counts)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    m = len(E)
+    pi = np.ascontiguousarray(pi, dtype=np.uint32)
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
+    oc = np.zeros(max(m // 2, 1), dtype=np.uint8)
+    c = Counts()
+    _load().oracle_global_switch(_p(E), m, _p(pi), _p(sk), _p(oc), ctypes.byref(c), mutate)
+    return E, oc[: m // 2], c.as_dict()
+
+
+def run(E: np.ndarray, n: int, seed: int, t0: int, r: int, pl: int = 0, mutate: int = 0, outcomes: bool = False):
+    """r global switches.  Returns (status, E', [per-superstep counts], last outcomes or None)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    m = len(E)
+    per = (Counts * max(r, 1))()
+    oc = np.zeros(max(m // 2, 1), dtype=np.uint8) if outcomes else None
+    rc = _load().oracle_run(_p(E), m, n, seed, t0, r, pl, per, _p(oc), mutate)
+    counts = [per[s].as_dict() for s in range(r)]
+    return rc, E, counts, (oc[: m // 2] if outcomes else None)
+
+
+def selftest_edgeset(ops: int = 200000, seed: int = 1) -> int:
+    return int(_load().oracle_selftest_edgeset(ops, seed))
