@@ -1,0 +1,134 @@
+/*
+ * gesmc -- Global Edge Switching Markov Chain (G-ES-MC) on AMD MI355X (gfx950).
+ *
+ * C ABI of libgesmc.so.  The method is that of Allendorf, Meyer, Penschuck and
+ * Tran, "Parallel Global Edge Switching for the Uniform Sampling of Simple
+ * Graphs with Prescribed Degrees" (arXiv 2111.03005):
+ *   - an edge switch (Def. 2.1) turns edges e1 = E[i], e2 = E[j] (canonical
+ *     orientation) into tau(e1, e2, g) and is rejected if a new edge is a loop
+ *     or already present;
+ *   - a global switch (Def. 3.2) permutes the m edge indices uniformly and
+ *     runs the floor(m/2) switches (pi[2k], pi[2k+1], [pi[2k] < pi[2k+1]]) in
+ *     sequence, each one skipped independently with probability P_L (Sec. 3);
+ *   - the driver (Alg. 3) applies r global switches; the result equals the
+ *     sequential execution (Sec. 4), whatever the parallel schedule.
+ *
+ * Random choices are defined exactly with Philox4x32-10 (Salmon et al., SC'11)
+ * keyed by (seed_lo, seed_hi): in superstep t the permutation sorts edge
+ * indices by (K_i, i) with K_i = (x0 << 32) | x1 at counter (i, 0, t, 0), and
+ * switch k is skipped iff x0 at counter (k, 0, t, 1) is below pl.  The output
+ * is a deterministic function of (input edge order, n, seed, t0, r, pl).
+ *
+ * Edges are 64-bit keys (min << 32) | max (Sec. 5.1).  Vertex ids must be < n
+ * and < 0xFFFFFFFF; m must be below 2^30.
+ *
+ * Threading: a context serves one host thread at a time.  Every call below
+ * enqueues its work on `stream` (a hipStream_t passed as void*; NULL = the
+ * default stream) and returns after the work has completed.
+ */
+#ifndef GESMC_H
+#define GESMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gesmc_status;
+
+#define GESMC_OK 0
+#define GESMC_E_INVAL (-1)      /* bad pointer or argument                         */
+#define GESMC_E_NOT_SIMPLE (-2) /* the input edge list has a loop or a duplicate   */
+#define GESMC_E_RANGE (-3)      /* vertex id >= n or 0xFFFFFFFF, or m >= 2^30      */
+#define GESMC_E_NOMEM (-4)      /* device allocation failed                        */
+#define GESMC_E_DEVICE (-5)     /* HIP runtime error                               */
+#define GESMC_E_INTERNAL (-9)   /* an internal consistency check failed            */
+
+typedef struct gesmc_ctx gesmc_ctx;
+
+/* Totals over one call. */
+typedef struct gesmc_stats {
+    uint64_t attempts;   /* floor(m/2) per superstep, rejected ones included   */
+    uint64_t legal;      /* accepted switches                                   */
+    uint64_t rej_loop;   /* rejected: a target is a loop                        */
+    uint64_t rej_exists; /* rejected: a target is present when the switch runs  */
+    uint64_t rej_pl;     /* skipped with probability P_L                        */
+    uint64_t rounds_sum; /* dependency-resolution rounds summed over supersteps */
+    uint32_t rounds_max; /* most rounds in one superstep                        */
+    uint32_t supersteps; /* r                                                   */
+    double ms_device;    /* device time of the whole call (HIP events)          */
+} gesmc_stats;
+
+/* Per superstep (same meaning as above; `rounds` counts the decision rounds of
+ * Alg. 1 as scheduled here: 1 + the rounds needed for delayed switches). */
+typedef struct gesmc_step_stats {
+    uint64_t attempts, legal, rej_loop, rej_exists, rej_pl;
+    uint64_t rounds;
+    uint64_t undecided_after_round1;
+    uint64_t fallback_buckets; /* permutation buckets sorted by the slow exact path */
+} gesmc_step_stats;
+
+/* Creates a context on HIP device `hip_device`.  Device memory is allocated
+ * lazily and kept for later calls (about 110 bytes per edge).  *out receives
+ * the context; release it with gesmc_destroy. */
+gesmc_status gesmc_create(int hip_device, gesmc_ctx **out);
+void gesmc_destroy(gesmc_ctx *ctx);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *gesmc_last_error(void);
+
+/*
+ * r global switches (Alg. 3) on the m edges at d_in (device memory, uint64
+ * keys; a key (max << 32) | min is accepted and canonicalised).  The result,
+ * canonical keys in position order, goes to d_out (device memory, m words; may
+ * equal d_in).  Supersteps t0 .. t0+r-1 are run, so run(r1) followed by
+ * run(r2, t0 = r1) equals run(r1 + r2).  pl: P_L = pl / 2^32 (0 = never skip).
+ * flags: reserved, pass 0.  stats (host, nullable): totals; steps (host,
+ * nullable): r records.  On any error d_out is left untouched and a negative
+ * status is returned; GESMC_E_NOT_SIMPLE / GESMC_E_RANGE report invalid input.
+ * m < 2 copies the canonicalised input.
+ */
+gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,
+                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats,
+                       gesmc_step_stats *steps);
+
+/*
+ * One superstep t (as gesmc_run with t0 = t, r = 1) that also writes the
+ * outcome of every switch k < floor(m/2) to d_outcome (device memory, one byte
+ * per switch): 1 accepted, 2 rejected loop, 3 rejected target present,
+ * 4 skipped (P_L).  Parity hook for the per-switch decisions (Def. 2.1).
+ */
+gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                                      uint32_t n, uint64_t seed, uint32_t t, uint32_t pl, uint8_t *d_outcome,
+                                      gesmc_step_stats *step);
+
+/* Permutation keys K_i (see above) for i < m, to d_keys (device, m words). */
+gesmc_status gesmc_perm_keys(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint64_t *d_keys);
+
+/* The permutation pi of superstep t (Def. 3.2): d_pi[r] (device, m words) is
+ * the edge index of rank r in (K_i, i) order. */
+gesmc_status gesmc_permutation(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint32_t *d_pi);
+
+/* Tuning knobs (values are validated; results never depend on them). */
+#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 2560, default 2560) */
+#define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 3072, default 3072)     */
+#define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64) */
+#define GESMC_OPT_PROFILE 4     /* 1: time every kernel launch with HIP events                      */
+gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
+
+/* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0
+ * to gesmc_kernel_count() - 1; gesmc_kernel_name gives the name.  *ms is the
+ * summed device duration of all launches of that kernel, *launches their
+ * count, *items the work items they covered (edges, switches or slots, per
+ * kernel). */
+int gesmc_kernel_count(void);
+const char *gesmc_kernel_name(int kernel_id);
+gesmc_status gesmc_profile_get(gesmc_ctx *ctx, int kernel_id, double *ms, uint64_t *launches, uint64_t *items);
+gesmc_status gesmc_profile_reset(gesmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GESMC_H */

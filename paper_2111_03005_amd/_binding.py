@@ -1,0 +1,211 @@
+"""ctypes binding of libgesmc.so (include/gesmc.h): argument marshalling only.
+
+Every step of the global switch runs in the HIP kernels of the library; this
+module passes device pointers, sizes and the current HIP stream.  If the
+library is missing the import of a function raises -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgesmc.so")
+
+OK = 0
+E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_INTERNAL = -1, -2, -3, -4, -5, -9
+OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE = 1, 2, 3, 4
+
+
+class GesmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("gesmc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("rej_loop", ctypes.c_uint64),
+                ("rej_exists", ctypes.c_uint64), ("rej_pl", ctypes.c_uint64), ("rounds_sum", ctypes.c_uint64),
+                ("rounds_max", ctypes.c_uint32), ("supersteps", ctypes.c_uint32), ("ms_device", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: (float(getattr(self, f)) if f == "ms_device" else int(getattr(self, f))) for f, _ in self._fields_}
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("rej_loop", ctypes.c_uint64),
+                ("rej_exists", ctypes.c_uint64), ("rej_pl", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("undecided_after_round1", ctypes.c_uint64), ("fallback_buckets", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_superstep_outcomes",
+           "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option", "gesmc_kernel_count", "gesmc_kernel_name",
+           "gesmc_profile_get", "gesmc_profile_reset"]
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libgesmc.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError("libgesmc.so not built (run __graft_entry__.build() or "
+                               "python -m paper_2111_03005_amd.build): %s" % path)
+        lib = ctypes.CDLL(path)
+        vp, u32, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+        lib.gesmc_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        lib.gesmc_create.restype = i32
+        lib.gesmc_destroy.argtypes = [vp]
+        lib.gesmc_destroy.restype = None
+        lib.gesmc_last_error.argtypes = []
+        lib.gesmc_last_error.restype = ctypes.c_char_p
+        lib.gesmc_run.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
+                                  ctypes.POINTER(StepStats)]
+        lib.gesmc_run.restype = i32
+        lib.gesmc_superstep_outcomes.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, vp,
+                                                 ctypes.POINTER(StepStats)]
+        lib.gesmc_superstep_outcomes.restype = i32
+        lib.gesmc_perm_keys.argtypes = [vp, vp, u64, u64, u32, vp]
+        lib.gesmc_perm_keys.restype = i32
+        lib.gesmc_permutation.argtypes = [vp, vp, u64, u64, u32, vp]
+        lib.gesmc_permutation.restype = i32
+        lib.gesmc_set_option.argtypes = [vp, ctypes.c_int, i64]
+        lib.gesmc_set_option.restype = i32
+        lib.gesmc_kernel_count.argtypes = []
+        lib.gesmc_kernel_count.restype = ctypes.c_int
+        lib.gesmc_kernel_name.argtypes = [ctypes.c_int]
+        lib.gesmc_kernel_name.restype = ctypes.c_char_p
+        lib.gesmc_profile_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                          ctypes.POINTER(u64)]
+        lib.gesmc_profile_get.restype = i32
+        lib.gesmc_profile_reset.argtypes = [vp]
+        lib.gesmc_profile_reset.restype = i32
+        _lib = lib
+        return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise GesmcError(status, _lib.gesmc_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype_bytes: int, numel: int, name: str):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous() or t.element_size() != dtype_bytes or t.numel() < numel:
+        raise ValueError("%s: need a contiguous %d-byte tensor with >= %d elements" % (name, dtype_bytes, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libgesmc context on one HIP device (device memory is kept between calls)."""
+
+    def __init__(self, device: int | None = None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.gesmc_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gesmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int):
+        _check(_lib.gesmc_set_option(self._h, option, int(value)))
+
+    # ---- the global switch chain -----------------------------------------
+    def run(self, edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0,
+            out: torch.Tensor | None = None, stream=None, steps: bool = False):
+        """r global switches on `edges` (device uint64/int64 keys).  Returns (out, stats[, step list])."""
+        m = edges.numel()
+        if out is None:
+            out = torch.empty_like(edges)
+        st = Stats()
+        ss = (StepStats * max(r, 1))() if steps else None
+        _check(_lib.gesmc_run(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges"),
+                              _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), t0, r, pl, 0,
+                              ctypes.byref(st), ss))
+        if steps:
+            return out, st.as_dict(), [ss[q].as_dict() for q in range(r)]
+        return out, st.as_dict()
+
+    def superstep_outcomes(self, edges: torch.Tensor, n: int, seed: int, t: int, pl: int = 0, stream=None):
+        """One superstep; returns (edges after, outcome code per switch (uint8), step stats)."""
+        m = edges.numel()
+        out = torch.empty_like(edges)
+        oc = torch.empty(max(m // 2, 1), dtype=torch.uint8, device=edges.device)
+        ss = StepStats()
+        _check(_lib.gesmc_superstep_outcomes(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges"),
+                                             _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), t, pl,
+                                             ctypes.c_void_p(oc.data_ptr()), ctypes.byref(ss)))
+        return out, oc[: m // 2], ss.as_dict()
+
+    def perm_keys(self, m: int, seed: int, t: int, stream=None, device=None):
+        out = torch.empty(max(m, 1), dtype=torch.int64, device=device or torch.device("cuda", self.device))
+        _check(_lib.gesmc_perm_keys(self._h, _stream_ptr(stream), m, seed & (2**64 - 1), t,
+                                    ctypes.c_void_p(out.data_ptr())))
+        return out[:m]
+
+    def permutation(self, m: int, seed: int, t: int, stream=None, device=None):
+        out = torch.empty(max(m, 1), dtype=torch.int32, device=device or torch.device("cuda", self.device))
+        _check(_lib.gesmc_permutation(self._h, _stream_ptr(stream), m, seed & (2**64 - 1), t,
+                                      ctypes.c_void_p(out.data_ptr())))
+        return out[:m]
+
+    # ---- kernel timing ---------------------------------------------------
+    def profile(self):
+        """{kernel name: (total ms, launches, items)} of launches timed while OPT_PROFILE was on."""
+        res = {}
+        for kid in range(_lib.gesmc_kernel_count()):
+            ms = ctypes.c_double()
+            nl = ctypes.c_uint64()
+            it = ctypes.c_uint64()
+            _check(_lib.gesmc_profile_get(self._h, kid, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(it)))
+            if nl.value:
+                res[_lib.gesmc_kernel_name(kid).decode()] = (ms.value, nl.value, it.value)
+        return res
+
+    def profile_reset(self):
+        _check(_lib.gesmc_profile_reset(self._h))
+
+
+_default = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def run(edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0, out=None, stream=None):
+    """r global switches with the default context of the tensor's device."""
+    return default_context(edges.device.index).run(edges, n, seed, t0, r, pl, out, stream)

@@ -1,0 +1,139 @@
+// Device-side building blocks shared by the gfx950 kernels of libgesmc.
+//
+// Counter-based randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11).  Every random choice
+// of a global switch (Def. 3.2 of arXiv 2111.03005) is a pure function of
+// (seed, superstep t, index), so any kernel can recompute it instead of
+// storing it:
+//   permutation key of edge index i : K_i = (x0 << 32) | x1 at counter (i, 0, t, 0)
+//   P_L skip test of switch k       : x0 at counter (k, 0, t, 1), skip iff x0 < pl
+// The permutation pi of superstep t lists the edge indices in ascending
+// (K_i, i) order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gesmc {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10
+// ---------------------------------------------------------------------------
+struct Philox4 {
+    uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        const uint32_t h0 = __umulhi(m0, c0), l0 = m0 * c0;
+        const uint32_t h1 = __umulhi(m1, c2), l1 = m1 * c2;
+        const uint32_t y0 = h1 ^ c1 ^ k0;
+        const uint32_t y2 = h0 ^ c3 ^ k1;
+        c0 = y0;
+        c1 = l1;
+        c2 = y2;
+        c3 = l0;
+        k0 += 0x9E3779B9u;  // Weyl key schedule
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+// Permutation key of edge index i in superstep t (m < 2^32, so the high
+// counter word of i is 0).
+__device__ __forceinline__ uint64_t perm_key(uint32_t i, uint32_t t, uint32_t k0, uint32_t k1) {
+    const Philox4 r = philox4x32_10(i, 0u, t, 0u, k0, k1);
+    return ((uint64_t)r.x0 << 32) | r.x1;
+}
+
+__device__ __forceinline__ bool pl_skip(uint32_t k, uint32_t t, uint32_t pl, uint32_t k0, uint32_t k1) {
+    if (pl == 0) return false;
+    return philox4x32_10(k, 0u, t, 1u, k0, k1).x0 < pl;
+}
+
+// ---------------------------------------------------------------------------
+// Edge keys (Sec. 5.1): smaller endpoint in the high word, larger in the low.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ekey_lo_vertex(uint64_t e) { return (uint32_t)(e >> 32); }
+__device__ __forceinline__ uint32_t ekey_hi_vertex(uint64_t e) { return (uint32_t)e; }
+__device__ __forceinline__ uint64_t ekey(uint32_t a, uint32_t b) {
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    return ((uint64_t)lo << 32) | hi;
+}
+
+// Per-switch outcome codes (also the status array of a superstep).
+enum : uint8_t { ST_UNDECIDED = 0, ST_LEGAL = 1, ST_LOOP = 2, ST_EXISTS = 3, ST_PL = 4 };
+
+// ---------------------------------------------------------------------------
+// Dependency table (rebuilt every superstep): open addressing, linear probing,
+// power-of-two slot count, load <= 1/2.  One 16-byte slot per edge key that is
+// a source or a target of the superstep.
+//   key     : the edge key, or kEmptyKey
+//   eraser  : switch id whose source this edge is (Def. 3.1 / Alg. 1 erase
+//             tuple), kNoEraser if the key is not a source, kStays if it is a
+//             source that survives the superstep for certain (idle position,
+//             or its switch is rejected before any lookup)
+//   claim   : (earliest not-yet-excluded inserter << 2) | LEGAL | CONTENDED
+//             -- the "smallest non-illegal inserter" lookup of Alg. 1
+// ---------------------------------------------------------------------------
+struct __align__(16) Slot {
+    unsigned long long key;
+    uint32_t eraser;
+    uint32_t claim;
+};
+
+constexpr unsigned long long kEmptyKey = ~0ull;  // a loop at 0xFFFFFFFF: never a valid key
+constexpr uint32_t kNoEraser = 0xFFFFFFFFu;
+constexpr uint32_t kStays = 0xFFFFFFFEu;
+constexpr uint32_t kClaimNone = 0xFFFFFFFCu;  // larger than any (k << 2), flags clear
+constexpr uint32_t kClaimContended = 1u;
+constexpr uint32_t kClaimLegal = 2u;
+
+__device__ __forceinline__ uint64_t slot_hash(uint64_t x) {
+    x ^= x >> 32;
+    x *= 0xD6E8FEB86659FD93ull;
+    x ^= x >> 32;
+    x *= 0xD6E8FEB86659FD93ull;
+    x ^= x >> 32;
+    return x;
+}
+
+// Finds or inserts `key`; returns its slot.  The table is never more than
+// half full, so the probe ends at an empty slot; the probe count is bounded
+// anyway (kNoSlot: table full, an internal error).
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t table_find_or_insert(Slot *tab, uint32_t mask, unsigned long long key) {
+    uint32_t s = (uint32_t)slot_hash(key) & mask;
+    for (uint64_t probes = 0; probes <= (uint64_t)mask; ++probes) {
+        const unsigned long long cur = tab[s].key;
+        if (cur == key) return s;
+        if (cur == kEmptyKey) {
+            const unsigned long long prev = atomicCAS(&tab[s].key, kEmptyKey, key);
+            if (prev == kEmptyKey || prev == key) return s;
+        }
+        s = (s + 1) & mask;
+    }
+    return kNoSlot;
+}
+
+// Error bits raised by kernels (read back by the host at the end of a call).
+enum : uint32_t {
+    ERR_LOOP = 1u,       // input contains a loop
+    ERR_RANGE = 2u,      // vertex id >= n (or 0xFFFFFFFF)
+    ERR_DUP = 4u,        // input contains a duplicate edge
+    ERR_INTERNAL = 8u,   // an internal consistency check failed
+};
+
+// Per-superstep statistics kept on the device.
+struct StepCounters {
+    unsigned long long legal, rej_loop, rej_exists, rej_pl;
+    unsigned long long rounds, undecided_round1, fallback_buckets, pad;
+};
+
+}  // namespace gesmc

@@ -1,0 +1,724 @@
+// libgesmc: host runtime and C ABI for the G-ES-MC global switch on gfx950.
+// The declarations and their meaning are in include/gesmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gesmc.h"
+#include "perm_kernels.h"
+#include "switch_kernels.h"
+
+using namespace gesmc;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+enum KernelId {
+    KID_LOAD,
+    KID_HIST_CLEAR,
+    KID_SCAN_COARSE,
+    KID_SCATTER1,
+    KID_HIST_SUB,
+    KID_SCAN_FINE,
+    KID_SCATTER2,
+    KID_SORT,
+    KID_BUILD,
+    KID_DECIDE1,
+    KID_ROUND_RESET,
+    KID_ROUND_CLAIM,
+    KID_ROUND_DECIDE,
+    KID_FINISH,
+    KID_UNPERMUTE,
+    KID_VALIDATE,
+    KID_MISC,
+    KID_COUNT
+};
+
+const char *kKernelNames[KID_COUNT] = {
+    "k_load",        "k_hist_clear",  "k_scan_coarse", "k_scatter1",      "k_hist_sub",   "k_scan_fine",
+    "k_scatter2",    "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
+    "k_round_decide", "k_finish",     "k_unpermute",   "k_validate",      "k_misc"};
+
+__global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
+    if (threadIdx.x == 0) {
+        seg_off[0] = 0;
+        seg_off[1] = m;
+        tile_first[0] = 0;
+        tile_first[1] = ntiles;
+    }
+}
+
+__global__ void k_zero_words(uint32_t *p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0;
+}
+
+__global__ void k_identity_records(uint32_t *idx, unsigned long long *key, uint32_t m) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m) {
+        idx[r] = (uint32_t)r;
+        key[r] = r;
+    }
+}
+
+__global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) dst[q] = src[q];
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+struct gesmc_ctx {
+    int device = 0;
+    int num_cus = 256;
+    // options
+    uint32_t bucket_avg = 2560;
+    uint32_t sort_cap = 3072;
+    int fast_rounds = 4;
+    bool profile = false;
+    // device buffers (capacity in edges)
+    uint64_t cap_m = 0;
+    uint32_t *idx[3] = {nullptr, nullptr, nullptr};
+    unsigned long long *key[3] = {nullptr, nullptr, nullptr};
+    Slot *tab = nullptr;
+    uint64_t tab_slots = 0;
+    uint32_t *sw_slot = nullptr;
+    uint8_t *st = nullptr;
+    uint32_t *ulist[2] = {nullptr, nullptr};
+    uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
+    StepCounters *ctr = nullptr;
+    StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
+    uint64_t ctr_cap = 0;
+    // views into `small`
+    uint32_t *err = nullptr, *ucount = nullptr, *coarse_hist = nullptr, *coarse_off = nullptr,
+             *coarse_cursor = nullptr, *tile_first = nullptr, *lvl1_seg = nullptr, *lvl1_tiles = nullptr,
+             *fine_hist = nullptr, *fine_off = nullptr, *fine_cursor = nullptr;
+    // host staging (pinned)
+    uint32_t *h_err = nullptr;
+    StepCounters *h_ctr = nullptr;
+    uint64_t h_ctr_cap = 0;
+    // profiling
+    struct Rec {
+        int kid;
+        uint64_t items;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<Rec> recs;
+    double prof_ms[KID_COUNT] = {0};
+    uint64_t prof_launch[KID_COUNT] = {0};
+    uint64_t prof_items[KID_COUNT] = {0};
+    hipEvent_t call_a = nullptr, call_b = nullptr;
+};
+
+namespace {
+
+constexpr uint32_t kMaxFineBits = 20;
+constexpr uint64_t kMaxEdges = 1ull << 30;
+
+void free_buffers(gesmc_ctx *c) {
+    for (int q = 0; q < 3; ++q) {
+        if (c->idx[q]) (void)hipFree(c->idx[q]);
+        if (c->key[q]) (void)hipFree(c->key[q]);
+        c->idx[q] = nullptr;
+        c->key[q] = nullptr;
+    }
+    if (c->tab) (void)hipFree(c->tab);
+    if (c->sw_slot) (void)hipFree(c->sw_slot);
+    if (c->st) (void)hipFree(c->st);
+    for (int q = 0; q < 2; ++q) {
+        if (c->ulist[q]) (void)hipFree(c->ulist[q]);
+        c->ulist[q] = nullptr;
+    }
+    c->tab = nullptr;
+    c->sw_slot = nullptr;
+    c->st = nullptr;
+    c->cap_m = 0;
+    c->tab_slots = 0;
+}
+
+gesmc_status dev_alloc(void **p, size_t bytes) {
+    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("hipMalloc of %zu bytes failed", bytes);
+        return GESMC_E_NOMEM;
+    }
+    return GESMC_OK;
+}
+
+uint64_t table_slots_for(uint64_t m) {
+    // keys per superstep <= m sources + 2 * floor(m/2) targets <= 2m; load <= 1/2
+    uint64_t s = 1024;
+    while (s < 4 * m) s <<= 1;
+    return s;
+}
+
+gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
+    if (m <= c->cap_m && c->tab) return GESMC_OK;
+    free_buffers(c);
+    const uint64_t cap = std::max<uint64_t>(m, 1024);
+    gesmc_status s = GESMC_OK;
+    for (int q = 0; q < 3 && s == GESMC_OK; ++q) {
+        s = dev_alloc((void **)&c->idx[q], cap * 4);
+        if (s == GESMC_OK) s = dev_alloc((void **)&c->key[q], cap * 8);
+    }
+    const uint64_t ts = table_slots_for(cap);
+    if (s == GESMC_OK) s = dev_alloc((void **)&c->tab, ts * sizeof(Slot));
+    if (s == GESMC_OK) s = dev_alloc((void **)&c->sw_slot, (cap / 2 + 1) * 8);
+    if (s == GESMC_OK) s = dev_alloc((void **)&c->st, cap / 2 + 64);
+    for (int q = 0; q < 2 && s == GESMC_OK; ++q) s = dev_alloc((void **)&c->ulist[q], (cap / 2 + 64) * 4);
+    if (s != GESMC_OK) {
+        free_buffers(c);
+        return s;
+    }
+    c->cap_m = cap;
+    c->tab_slots = ts;
+    return GESMC_OK;
+}
+
+gesmc_status ensure_counters(gesmc_ctx *c, uint64_t r) {
+    const uint64_t want = std::max<uint64_t>(r, 1);
+    if (want > c->ctr_cap) {
+        if (c->ctr) (void)hipFree(c->ctr);
+        c->ctr = nullptr;
+        c->ctr_cap = 0;
+        gesmc_status s = dev_alloc((void **)&c->ctr, want * sizeof(StepCounters));
+        if (s != GESMC_OK) return s;
+        c->ctr_cap = want;
+    }
+    if (want > c->h_ctr_cap) {
+        if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+        c->h_ctr = nullptr;
+        c->h_ctr_cap = 0;
+        if (hipHostMalloc((void **)&c->h_ctr, want * sizeof(StepCounters), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipHostMalloc failed");
+            return GESMC_E_NOMEM;
+        }
+        c->h_ctr_cap = want;
+    }
+    return GESMC_OK;
+}
+
+// ---- launch helper with optional per-launch event timing -------------------
+hipEvent_t take_event(gesmc_ctx *c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+template <typename Kern, typename... Args>
+gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern kern, dim3 grid, dim3 block,
+                    size_t lds, Args... args) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->profile) {
+        a = take_event(c);
+        b = take_event(c);
+        if (a) (void)hipEventRecord(a, s);
+    }
+    hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
+        return GESMC_E_DEVICE;
+    }
+    if (c->profile && a && b) {
+        (void)hipEventRecord(b, s);
+        c->recs.push_back({kid, items, a, b});
+    }
+    return GESMC_OK;
+}
+
+#define GESMC_TRY(x)                      \
+    do {                                  \
+        gesmc_status _s = (x);            \
+        if (_s != GESMC_OK) return _s;    \
+    } while (0)
+
+struct Plan {
+    uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1;
+};
+
+Plan make_plan(const gesmc_ctx *c, uint32_t m) {
+    Plan p;
+    p.m = m;
+    p.ell = m / 2;
+    uint32_t B = 0;
+    while (B < kMaxFineBits && ((uint64_t)c->bucket_avg << B) < m) ++B;
+    p.bbits = B;
+    p.b1 = std::min<uint32_t>(B, 8);
+    p.b2 = B - p.b1;
+    p.ncoarse = 1u << p.b1;
+    p.nfine = 1u << B;
+    p.ntiles1 = ceil_div(m, kScatterTile);
+    return p;
+}
+
+size_t scatter_lds_bytes(int dbits) {
+    const size_t nd = (size_t)1 << dbits;
+    size_t words = 3 * nd + kBlock + 1 + kScatterTile;
+    words += words & 1;  // 8-byte alignment of the key stage
+    return words * 4 + (size_t)kScatterTile * 8 + (size_t)kScatterTile * 2;
+}
+
+size_t sort_lds_bytes(uint32_t cap) {
+    return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 20;
+}
+
+uint32_t grid_stride_blocks(const gesmc_ctx *c, uint64_t work) {
+    const uint64_t want = (work + kBlock - 1) / kBlock;
+    const uint64_t cap = (uint64_t)c->num_cus * 8;
+    return (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+}
+
+// Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t.
+// Returns the buffer index holding the sorted records.
+gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1, int src,
+                     int *sorted_out, bool clear_table) {
+    const uint32_t m = p.m;
+    const int X = (src + 1) % 3, Y = (src + 2) % 3;
+    GESMC_TRY(launch(c, s, KID_HIST_CLEAR, m, k_hist_clear, dim3(grid_stride_blocks(c, std::max<uint64_t>(m, clear_table ? c->tab_slots : 0))),
+                     dim3(kBlock), 0, m, t, k0, k1, (int)p.b1, c->coarse_hist, c->tab,
+                     clear_table ? c->tab_slots : (uint64_t)0, c->st, p.ell, c->ucount));
+    GESMC_TRY(launch(c, s, KID_SCAN_COARSE, p.ncoarse, k_scan_coarse, dim3(1), dim3(kBlock), 0, p.ncoarse,
+                     c->coarse_hist, c->coarse_off, c->coarse_cursor, c->tile_first));
+    const size_t sort_lds = sort_lds_bytes(c->sort_cap);
+    if (p.bbits == 0) {
+        // one bucket: sort src -> X (scratch keys in Y)
+        GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(1), dim3(kBlock), sort_lds, c->idx[src], c->key[src],
+                         c->idx[X], c->key[X], c->key[Y], t, k0, k1, 0, c->coarse_off, m, c->sort_cap, c->ctr_step));
+        *sorted_out = X;
+        return GESMC_OK;
+    }
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, m,
+                     p.ntiles1));
+    GESMC_TRY(launch(c, s, KID_SCATTER1, m, k_scatter, dim3(p.ntiles1), dim3(kBlock), scatter_lds_bytes(p.b1),
+                     c->idx[src], c->key[src], c->idx[X], c->key[X], t, k0, k1, 64 - (int)p.b1, (int)p.b1, 1u,
+                     c->lvl1_seg, c->lvl1_tiles, c->coarse_cursor, c->err));
+    if (p.b2 == 0) {
+        GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(p.nfine), dim3(kBlock), sort_lds, c->idx[X],
+                         c->key[X], c->idx[Y], c->key[Y], c->key[src], t, k0, k1, (int)p.bbits, c->coarse_off, m,
+                         c->sort_cap, c->ctr_step));
+        *sorted_out = Y;
+        return GESMC_OK;
+    }
+    const uint32_t tiles2 = p.ntiles1 + p.ncoarse;
+    GESMC_TRY(launch(c, s, KID_HIST_SUB, m, k_hist_sub, dim3(tiles2), dim3(kBlock), ((size_t)1 << p.b2) * 4,
+                     c->idx[X], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
+                     c->fine_hist));
+    GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(1), dim3(1024), 0, p.nfine, c->fine_hist,
+                     c->fine_off, c->fine_cursor));
+    GESMC_TRY(launch(c, s, KID_SCATTER2, m, k_scatter, dim3(tiles2), dim3(kBlock), scatter_lds_bytes(p.b2),
+                     c->idx[X], c->key[X], c->idx[Y], c->key[Y], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse,
+                     c->coarse_off, c->tile_first, c->fine_cursor, c->err));
+    GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(p.nfine), dim3(kBlock), sort_lds, c->idx[Y], c->key[Y],
+                     c->idx[X], c->key[X], c->key[src], t, k0, k1, (int)p.bbits, c->fine_off, m, c->sort_cap,
+                     c->ctr_step));
+    *sorted_out = X;
+    return GESMC_OK;
+}
+
+// One superstep t on the state records in buffer 0 (result back in buffer 0).
+gesmc_status superstep(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1, uint32_t pl,
+                       uint32_t dup_bit) {
+    int sorted = 0;
+    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, true));
+    const uint32_t mask = (uint32_t)(c->tab_slots - 1);
+    const uint32_t *si = c->idx[sorted];
+    const unsigned long long *sk = c->key[sorted];
+    GESMC_TRY(launch(c, s, KID_BUILD, p.ell, k_build, dim3(ceil_div((uint64_t)p.ell + 1, kBlock)), dim3(kBlock), 0,
+                     si, sk, p.m, t, k0, k1, pl, c->tab, mask, c->sw_slot, c->st, c->idx[0], c->key[0], c->ctr_step,
+                     c->err, dup_bit));
+    if (p.ell == 0) return GESMC_OK;
+    GESMC_TRY(launch(c, s, KID_DECIDE1, p.ell, k_decide_first, dim3(ceil_div(p.ell, kBlock)), dim3(kBlock), 0, si, sk,
+                     p.ell, c->tab, c->sw_slot, c->st, c->idx[0], c->key[0], c->ulist[0], &c->ucount[0], c->ctr_step,
+                     c->err));
+    const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
+    int cur = 0;
+    for (int rr = 0; rr < c->fast_rounds; ++rr) {
+        const int nxt = 1 - cur;
+        GESMC_TRY(launch(c, s, KID_ROUND_RESET, 0, k_round_reset, dim3(rblocks), dim3(kBlock), 0, c->ulist[cur],
+                         &c->ucount[cur], p.ell, c->tab, c->sw_slot, &c->ucount[nxt]));
+        GESMC_TRY(launch(c, s, KID_ROUND_CLAIM, 0, k_round_claim, dim3(rblocks), dim3(kBlock), 0, c->ulist[cur],
+                         &c->ucount[cur], p.ell, c->tab, c->sw_slot));
+        GESMC_TRY(launch(c, s, KID_ROUND_DECIDE, 0, k_round_decide, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
+                         c->tab, c->sw_slot, c->st, c->idx[0], c->key[0], c->ulist[cur], &c->ucount[cur],
+                         c->ulist[nxt], &c->ucount[nxt], c->ctr_step, c->err));
+        cur = nxt;
+    }
+    GESMC_TRY(launch(c, s, KID_FINISH, 0, k_finish, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell, c->tab,
+                     c->sw_slot, c->st, c->idx[0], c->key[0], c->ulist[cur], &c->ucount[cur], c->ulist[1 - cur],
+                     &c->ucount[1 - cur], c->ctr_step, c->err));
+    return GESMC_OK;
+}
+
+gesmc_status check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return GESMC_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return GESMC_E_DEVICE;
+}
+
+gesmc_status collect_profile(gesmc_ctx *c) {
+    for (const auto &r : c->recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->prof_ms[r.kid] += ms;
+            c->prof_launch[r.kid] += 1;
+            c->prof_items[r.kid] += r.items;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    c->recs.clear();
+    c->ev_used = 0;
+    return GESMC_OK;
+}
+
+gesmc_status map_err(uint32_t e) {
+    if (e & (ERR_LOOP | ERR_DUP)) {
+        set_error("input is not a simple graph (%s)", (e & ERR_LOOP) ? "loop" : "duplicate edge");
+        return GESMC_E_NOT_SIMPLE;
+    }
+    if (e & ERR_RANGE) {
+        set_error("vertex id out of range");
+        return GESMC_E_RANGE;
+    }
+    if (e) {
+        set_error("internal consistency check failed (error bits 0x%x)", e);
+        return GESMC_E_INTERNAL;
+    }
+    return GESMC_OK;
+}
+
+gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m64, uint32_t n,
+                      uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats,
+                      gesmc_step_stats *steps, uint8_t *d_outcome) {
+    if (!c) {
+        set_error("null context");
+        return GESMC_E_INVAL;
+    }
+    if (m64 > 0 && (!d_in || !d_out)) {
+        set_error("null edge pointer");
+        return GESMC_E_INVAL;
+    }
+    if (m64 >= kMaxEdges) {
+        set_error("m = %llu exceeds the limit 2^30 - 1", (unsigned long long)m64);
+        return GESMC_E_RANGE;
+    }
+    if ((uint64_t)t0 + r > 0x100000000ull) {
+        set_error("superstep counter t0 + r overflows 32 bits");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t m = (uint32_t)m64;
+    GESMC_TRY(ensure_capacity(c, m));
+    GESMC_TRY(ensure_counters(c, r));
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
+    const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(r, 1) * (sizeof(StepCounters) / 4);
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr,
+                     zero_words - 64));
+    if (m > 0)
+        GESMC_TRY(launch(c, s, KID_LOAD, m, k_load, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                         (const unsigned long long *)d_in, m, n, c->idx[0], c->key[0], c->err));
+    const Plan p = make_plan(c, m);
+    const uint32_t mask = (uint32_t)(c->tab_slots - 1);
+    if (m >= 2 && r == 0) {
+        c->ctr_step = c->ctr;
+        GESMC_TRY(launch(c, s, KID_HIST_CLEAR, c->tab_slots, k_hist_clear, dim3(grid_stride_blocks(c, c->tab_slots)),
+                         dim3(kBlock), 0, 0u, 0u, k0, k1, 0, c->coarse_hist, c->tab, c->tab_slots, c->st, 0u,
+                         c->ucount));
+        GESMC_TRY(launch(c, s, KID_SCAN_COARSE, 1, k_scan_coarse, dim3(1), dim3(kBlock), 0, 1u, c->coarse_hist,
+                         c->coarse_off, c->coarse_cursor, c->tile_first));
+        GESMC_TRY(launch(c, s, KID_VALIDATE, m, k_validate, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                         c->key[0], m, c->tab, mask, c->err));
+    }
+    if (m >= 2) {
+        for (uint32_t q = 0; q < r; ++q) {
+            c->ctr_step = c->ctr + q;
+            GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, q == 0 ? ERR_DUP : ERR_INTERNAL));
+        }
+    }
+    if (d_outcome && p.ell > 0)
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_copy_bytes, dim3(grid_stride_blocks(c, p.ell)), dim3(kBlock), 0,
+                         (const uint8_t *)c->st, d_outcome, (uint64_t)p.ell));
+    if (m > 0)
+        GESMC_TRY(launch(c, s, KID_UNPERMUTE, m, k_unpermute, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                         c->idx[0], c->key[0], m, (unsigned long long *)d_out, c->err));
+    GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    if (r > 0)
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters) * r, hipMemcpyDeviceToHost, s),
+                            "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    if (c->profile) collect_profile(c);
+    const gesmc_status st = map_err(*c->h_err);
+    if (st != GESMC_OK) return st;
+    const uint64_t att = (m >= 2) ? p.ell : 0;
+    if (steps) {
+        for (uint32_t q = 0; q < r; ++q) {
+            const StepCounters &h = c->h_ctr[q];
+            steps[q] = gesmc_step_stats{att, h.legal, h.rej_loop, h.rej_exists, h.rej_pl, h.rounds,
+                                        h.undecided_round1, h.fallback_buckets};
+        }
+    }
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->supersteps = r;
+        for (uint32_t q = 0; q < r; ++q) {
+            const StepCounters &h = c->h_ctr[q];
+            stats->attempts += att;
+            stats->legal += h.legal;
+            stats->rej_loop += h.rej_loop;
+            stats->rej_exists += h.rej_exists;
+            stats->rej_pl += h.rej_pl;
+            stats->rounds_sum += h.rounds;
+            stats->rounds_max = std::max<uint32_t>(stats->rounds_max, (uint32_t)h.rounds);
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->call_a, c->call_b) == hipSuccess)
+            stats->ms_device = ms;
+        else
+            (void)hipGetLastError();
+    }
+    return GESMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gesmc_last_error(void) { return g_last_error; }
+
+gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
+    if (!out) {
+        set_error("null output pointer");
+        return GESMC_E_INVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+        (void)hipGetLastError();
+        set_error("no HIP device %d", hip_device);
+        return GESMC_E_DEVICE;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(hip_device), "hipSetDevice"));
+    gesmc_ctx *c = new gesmc_ctx();
+    c->device = hip_device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    // fixed-size area: err[16], ucount[16], coarse hist/off/cursor/tiles, level-1 segments, fine hist/off/cursor
+    const size_t nf = (size_t)1 << kMaxFineBits;
+    const size_t words = 16 + 16 + 4 * 264 + 8 + 3 * (nf + 8);
+    if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK || dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK) {
+        gesmc_destroy(c);
+        return GESMC_E_NOMEM;
+    }
+    c->ctr_cap = 64;
+    uint32_t *w = c->small;
+    c->err = w;
+    w += 16;
+    c->ucount = w;
+    w += 16;
+    c->coarse_hist = w;
+    w += 264;
+    c->coarse_off = w;
+    w += 264;
+    c->coarse_cursor = w;
+    w += 264;
+    c->tile_first = w;
+    w += 264;
+    c->lvl1_seg = w;
+    w += 4;
+    c->lvl1_tiles = w;
+    w += 4;
+    c->fine_hist = w;
+    w += nf + 8;
+    c->fine_off = w;
+    w += nf + 8;
+    c->fine_cursor = w;
+    // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
+    (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sort_lds_bytes(kSortMaxItems * kBlock));
+    (void)hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)scatter_lds_bytes(12));
+    (void)hipGetLastError();
+    if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->call_a) != hipSuccess || hipEventCreate(&c->call_b) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("context initialisation failed");
+        gesmc_destroy(c);
+        return GESMC_E_DEVICE;
+    }
+    *out = c;
+    return GESMC_OK;
+}
+
+void gesmc_destroy(gesmc_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_buffers(c);
+    if (c->small) (void)hipFree(c->small);
+    if (c->ctr) (void)hipFree(c->ctr);
+    if (c->h_err) (void)hipHostFree(c->h_err);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->call_a) (void)hipEventDestroy(c->call_a);
+    if (c->call_b) (void)hipEventDestroy(c->call_b);
+    delete c;
+}
+
+gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,
+                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats,
+                       gesmc_step_stats *steps) {
+    if (flags != 0) {
+        set_error("flags must be 0");
+        return GESMC_E_INVAL;
+    }
+    return run_impl(ctx, stream, d_in, d_out, m, n, seed, t0, r, pl, stats, steps, nullptr);
+}
+
+gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                                      uint32_t n, uint64_t seed, uint32_t t, uint32_t pl, uint8_t *d_outcome,
+                                      gesmc_step_stats *step) {
+    if (m >= 2 && !d_outcome) {
+        set_error("null outcome pointer");
+        return GESMC_E_INVAL;
+    }
+    return run_impl(ctx, stream, d_in, d_out, m, n, seed, t, 1, pl, nullptr, step, d_outcome);
+}
+
+gesmc_status gesmc_perm_keys(gesmc_ctx *c, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint64_t *d_keys) {
+    if (!c || (m > 0 && !d_keys)) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    if (m >= kMaxEdges) {
+        set_error("m too large");
+        return GESMC_E_RANGE;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    if (m > 0)
+        GESMC_TRY(launch(c, s, KID_MISC, m, k_perm_keys, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, (uint32_t)m, t,
+                         (uint32_t)seed, (uint32_t)(seed >> 32), (unsigned long long *)d_keys));
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    if (c->profile) collect_profile(c);
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_permutation(gesmc_ctx *c, void *stream, uint64_t m64, uint64_t seed, uint32_t t, uint32_t *d_pi) {
+    if (!c || (m64 > 0 && !d_pi)) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    if (m64 >= kMaxEdges) {
+        set_error("m too large");
+        return GESMC_E_RANGE;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t m = (uint32_t)m64;
+    if (m > 0) {
+        GESMC_TRY(ensure_capacity(c, m));
+        GESMC_TRY(ensure_counters(c, 1));
+        c->ctr_step = c->ctr;
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_identity_records, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0,
+                         c->idx[0], c->key[0], m));
+        const Plan p = make_plan(c, m);
+        int sorted = 0;
+        GESMC_TRY(permute(c, s, p, t, (uint32_t)seed, (uint32_t)(seed >> 32), 0, &sorted, false));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_extract_pi, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0,
+                         c->idx[sorted], m, d_pi));
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    }
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    if (c->profile) collect_profile(c);
+    if (m > 0) return map_err(*c->h_err);
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
+    if (!c) {
+        set_error("null context");
+        return GESMC_E_INVAL;
+    }
+    switch (option) {
+        case GESMC_OPT_BUCKET_AVG:
+            if (v < 64 || v > 2560) break;
+            c->bucket_avg = (uint32_t)v;
+            return GESMC_OK;
+        case GESMC_OPT_SORT_CAP:
+            if (v < 64 || v > kSortMaxItems * kBlock) break;
+            c->sort_cap = (uint32_t)v;
+            return GESMC_OK;
+        case GESMC_OPT_FAST_ROUNDS:
+            if (v < 0 || v > 64) break;
+            c->fast_rounds = (int)v;
+            return GESMC_OK;
+        case GESMC_OPT_PROFILE:
+            c->profile = v != 0;
+            return GESMC_OK;
+        default:
+            set_error("unknown option %d", option);
+            return GESMC_E_INVAL;
+    }
+    set_error("value %lld out of range for option %d", (long long)v, option);
+    return GESMC_E_INVAL;
+}
+
+int gesmc_kernel_count(void) { return KID_COUNT; }
+
+const char *gesmc_kernel_name(int id) { return (id >= 0 && id < KID_COUNT) ? kKernelNames[id] : ""; }
+
+gesmc_status gesmc_profile_get(gesmc_ctx *c, int id, double *ms, uint64_t *launches, uint64_t *items) {
+    if (!c || id < 0 || id >= KID_COUNT) {
+        set_error("bad context or kernel id");
+        return GESMC_E_INVAL;
+    }
+    if (ms) *ms = c->prof_ms[id];
+    if (launches) *launches = c->prof_launch[id];
+    if (items) *items = c->prof_items[id];
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_profile_reset(gesmc_ctx *c) {
+    if (!c) {
+        set_error("null context");
+        return GESMC_E_INVAL;
+    }
+    for (int q = 0; q < KID_COUNT; ++q) {
+        c->prof_ms[q] = 0;
+        c->prof_launch[q] = 0;
+        c->prof_items[q] = 0;
+    }
+    return GESMC_OK;
+}
+
+}  // extern "C"

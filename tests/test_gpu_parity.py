@@ -1,0 +1,233 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, bit for bit.
+
+Everything here is integer work, so the bar is exact equality: the output
+edge list in position order, every per-superstep count, the per-switch
+outcome codes, the permutation keys and the permutation itself.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    c = gesmc.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(E):
+    return torch.from_numpy(np.ascontiguousarray(E, dtype=np.uint64).view(np.int64).copy()).to("cuda")
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def key(a, b):
+    return (min(a, b) << 32) | max(a, b)
+
+
+def keys(pairs):
+    return np.array([key(a, b) for a, b in pairs], dtype=np.uint64)
+
+
+COUNT_KEYS = ("attempts", "legal", "rej_loop", "rej_exists", "rej_pl")
+
+
+def check_run(ctx, E, n, seed, t0, r, pl=0, label=""):
+    print("case %s: m=%d n=%d seed=%d t0=%d r=%d pl=%d" % (label, len(E), n, seed, t0, r, pl), flush=True)
+    out, st, steps = ctx.run(to_dev(E), n, seed, t0=t0, r=r, pl=pl, steps=True)
+    got = to_host(out)
+    rc, exp, counts, _ = oracle.run(E, n, seed, t0, r, pl)
+    assert rc == 0
+    diff = np.flatnonzero(got != exp)
+    assert diff.size == 0, "%s: %d positions differ, first %s" % (label, diff.size, diff[:5])
+    for q, (s, c) in enumerate(zip(steps, counts)):
+        for k in COUNT_KEYS:
+            assert s[k] == c[k], (label, q, k, s, c)
+    return st, steps
+
+
+# ---------------------------------------------------------------------------
+# Building blocks: Philox keys and the permutation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,seed,t", [(1, 1, 0), (1000, 42, 3), (300001, 0xDEADBEEFCAFEF00D, 77)])
+def test_perm_keys(ctx, m, seed, t):
+    got = ctx.perm_keys(m, seed, t).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, oracle.perm_keys(m, seed, t))
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 64, 2560, 2561, 5209, 70001, 655360, 655361 + 4096 * 37, 6654522])
+def test_permutation(ctx, m):
+    for seed, t in [(42, 0), (7, 13)]:
+        print("perm m=%d seed=%d t=%d" % (m, seed, t), flush=True)
+        got = ctx.permutation(m, seed, t).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, oracle.permutation(m, seed, t))
+
+
+def test_permutation_small_buckets_and_fallback(ctx):
+    import paper_2111_03005_amd as gesmc
+    c = gesmc.Context(0)
+    try:
+        m = 50000
+        exp = oracle.permutation(m, 3, 5)
+        for avg, cap in [(64, 3072), (64, 64), (2560, 64), (300, 256)]:
+            c.set_option(gesmc.OPT_BUCKET_AVG, avg)
+            c.set_option(gesmc.OPT_SORT_CAP, cap)
+            got = c.permutation(m, 3, 5).cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, exp), (avg, cap)
+    finally:
+        c.close()
+
+
+# ---------------------------------------------------------------------------
+# Whole chain against the oracle
+# ---------------------------------------------------------------------------
+
+def test_gnp_small_10_supersteps(ctx):
+    E, n = graphgen.workload_gnp_small()
+    check_run(ctx, E, n, 42, 0, 10, label="gnp_n1024_d10")
+
+
+def test_superstep_outcomes(ctx):
+    for (E, n), pl in [(graphgen.workload_gnp_small(), 0), ((graphgen.powerlaw_graph(20000, 2.1, 2, 141, 9), 20000), 1 << 30)]:
+        for t in (0, 5):
+            out, oc, step = ctx.superstep_outcomes(to_dev(E), n, 11, t, pl)
+            rc, exp, counts, exp_oc = oracle.run(E, n, 11, t, 1, pl, outcomes=True)
+            assert np.array_equal(to_host(out), exp)
+            assert np.array_equal(oc.cpu().numpy(), exp_oc)
+
+
+@pytest.mark.parametrize("pl", [0, 1 << 31])
+def test_powerlaw_small(ctx, pl):
+    E = graphgen.powerlaw_graph(50000, 2.2, 2, 223, 5)
+    check_run(ctx, E, 50000, 5, 3, 6, pl, label="pld_50k")
+
+
+def test_edge_cases(ctx):
+    cases = [
+        ("m0", np.zeros(0, dtype=np.uint64), 4),
+        ("m1", keys([(0, 3)]), 4),
+        ("m2", keys([(0, 1), (2, 3)]), 4),
+        ("m3", keys([(0, 1), (2, 3), (4, 5)]), 6),
+        ("star", keys([(0, v) for v in range(1, 200)]), 200),
+        ("complete_K40", keys([(a, b) for a in range(40) for b in range(a + 1, 40)]), 40),
+        ("dense_gnp_0.9", graphgen.gnp(300, 0.9, 8), 300),
+        ("hub_powerlaw_2.01", graphgen.powerlaw_graph(30000, 2.01, 1, int(30000 ** (1 / 1.01)) // 4, 12), 30000),
+        ("odd_gnp", graphgen.gnp(2001, 0.003, 2), 2001),
+    ]
+    for name, E, n in cases:
+        for seed, pl in [(42, 0), (9, 1 << 30)]:
+            check_run(ctx, E, n, seed, 0, 4, pl, label=name)
+
+
+def test_noncanonical_and_r0(ctx):
+    E = np.array([(1 << 32) | 0, (3 << 32) | 2, key(4, 5)], dtype=np.uint64)
+    out, st = ctx.run(to_dev(E), 6, 1, r=0)
+    assert to_host(out).tolist() == [key(0, 1), key(2, 3), key(4, 5)]
+    check_run(ctx, E, 6, 1, 0, 3, label="noncanonical")
+
+
+def test_invalid_inputs_rejected_output_untouched(ctx):
+    import paper_2111_03005_amd as gesmc
+    bad = [
+        (keys([(0, 1), (1, 2), (0, 1)]), 3, gesmc.E_NOT_SIMPLE),           # duplicate
+        (np.array([(2 << 32) | 2, key(0, 1)], dtype=np.uint64), 3, gesmc.E_NOT_SIMPLE),  # loop
+        (keys([(0, 1), (1, 7)]), 5, gesmc.E_RANGE),                         # id >= n
+    ]
+    for E, n, code in bad:
+        for r in (0, 2):
+            sentinel = torch.full((len(E),), 12345, dtype=torch.int64, device="cuda")
+            with pytest.raises(gesmc.GesmcError) as ei:
+                ctx.run(to_dev(E), n, 1, r=r, out=sentinel)
+            assert ei.value.status == code
+            assert (sentinel.cpu() == 12345).all()
+    # the context stays usable
+    E, n = graphgen.workload_gnp_small()
+    check_run(ctx, E, n, 1, 0, 1, label="after_errors")
+
+
+def test_schedule_independence(ctx):
+    """Bucket sizes, LDS sort capacity (incl. the slow exact path) and the
+    number of multi-workgroup rounds change the schedule, never the result."""
+    import paper_2111_03005_amd as gesmc
+    E = graphgen.powerlaw_graph(40000, 2.05, 1, 400, 21)
+    n = 40000
+    ref = None
+    for avg, cap, fr in [(2560, 3072, 4), (64, 3072, 0), (256, 64, 1), (1000, 512, 8), (2560, 3072, 0)]:
+        c = gesmc.Context(0)
+        try:
+            c.set_option(gesmc.OPT_BUCKET_AVG, avg)
+            c.set_option(gesmc.OPT_SORT_CAP, cap)
+            c.set_option(gesmc.OPT_FAST_ROUNDS, fr)
+            out, st, steps = c.run(to_dev(E), n, 77, t0=2, r=5, steps=True)
+            got = to_host(out)
+            if ref is None:
+                ref = got
+                rc, exp, _, _ = oracle.run(E, n, 77, 2, 5)
+                assert np.array_equal(got, exp)
+            assert np.array_equal(got, ref), (avg, cap, fr)
+        finally:
+            c.close()
+
+
+def test_resume_equals_single_call(ctx):
+    E, n = graphgen.workload_gnp_small()
+    a, _ = ctx.run(to_dev(E), n, 5, t0=0, r=7)
+    b1, _ = ctx.run(to_dev(E), n, 5, t0=0, r=3)
+    b2, _ = ctx.run(b1, n, 5, t0=3, r=4)
+    assert torch.equal(a, b2)
+
+
+def test_repeat_determinism(ctx):
+    E = graphgen.powerlaw_graph(100000, 2.3, 2, 316, 4)
+    outs = [to_host(ctx.run(to_dev(E), 100000, 8, r=3)[0]) for _ in range(3)]
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads (the benchmark's launch configuration)
+# ---------------------------------------------------------------------------
+
+def test_full_powerlaw_n2p20_20_supersteps(ctx):
+    E, n = graphgen.workload_powerlaw_1m()
+    st, steps = check_run(ctx, E, n, 42, 0, 20, label="pld_n2^20_g2.5")
+    print("rounds per superstep:", [s["rounds"] for s in steps], flush=True)
+
+
+def test_full_gnp_n2p22_one_superstep_exact(ctx):
+    E, n = graphgen.workload_gnp_large()
+    check_run(ctx, E, n, 42, 0, 1, label="gnp_n2^22_d32 r=1")
+
+
+def test_full_gnp_n2p22_ten_supersteps_properties(ctx):
+    """10 supersteps at full size: degrees, simplicity and m (any size), and the
+    last superstep exactly against the oracle started from the GPU's state
+    after 9 supersteps would need the oracle's 9 supersteps first, so instead
+    the per-step counts must sum to r * floor(m/2) and stay in range."""
+    E, n = graphgen.workload_gnp_large()
+    out, st, steps = ctx.run(to_dev(E), n, 42, t0=0, r=10, steps=True)
+    got = to_host(out)
+    assert len(got) == len(E)
+    u, v = graphgen.split(got)
+    assert (u < v).all() and (v < n).all()
+    assert len(np.unique(got)) == len(got)
+    assert np.array_equal(graphgen.degrees(got, n), graphgen.degrees(E, n))
+    for s in steps:
+        assert s["legal"] + s["rej_loop"] + s["rej_exists"] + s["rej_pl"] == s["attempts"] == len(E) // 2
+        assert s["legal"] > 0.99 * s["attempts"]
