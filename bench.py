@@ -1,0 +1,212 @@
+"""Benchmark of the G-ES-MC global switch on one MI355X.
+
+A step is one call of the library: input edges resident in HBM -> load and
+validation -> r global switches (permutation, dependency table, rounds of
+decisions) -> edges back in position order.  The value is switch attempts per
+second over the timed steps (floor(m/2) attempts per superstep, rejected ones
+included), the convention of the paper's runtime table (init + supersteps).
+
+Prints ONE JSON line on stdout; diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge-switch attempts/sec (1 GPU), batched/served vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work item of each kernel (item = the unit the library
+# counts for that kernel: edges m, switches ell, or table slots).  Random table
+# touches count the 16-byte slot read and written back; records are 12 bytes
+# (4-byte index + 8-byte key).
+def kernel_bytes(name: str, m: int, ell: int, tab_slots: int) -> float | None:
+    return {
+        "k_hist_clear": 16.0 * tab_slots + ell,          # table reset + switch states (keys recomputed)
+        "k_scatter1": 24.0 * m,                          # read + write one record per edge
+        "k_hist_sub": 4.0 * m,                           # read the index of every record
+        "k_scatter2": 24.0 * m,
+        "k_sort_buckets": 24.0 * m,
+        "k_build": 24.0 * ell + 8.0 * ell + 4 * 32.0 * ell,  # pair records, slot ids, 4 slot RMWs
+        "k_decide_first": 24.0 * ell + 8.0 * ell + 2 * 8.0 * ell + 24.0 * ell + 2.0 * ell,
+        "k_unpermute": 12.0 * m + 8.0 * m,
+        "k_load": 8.0 * m + 12.0 * m,
+        # sorted-tuples dependency resolution: 4 tuples of 12 bytes per switch
+        "k_emit": 24.0 * ell + 48.0 * ell + 16.0 * ell,  # pair records in, tuples + free target records out
+        "k_tscatter1": 48.0 * ell + 48.0 * ell,          # tuple slots in, partitioned tuples out
+        "k_thist_sub": 32.0 * ell,                       # tuple keys
+        "k_tscatter2": 48.0 * ell + 48.0 * ell,
+        "k_resolve": 48.0 * ell,                         # tuples in (records out are rare)
+        "k_decide_chain1": 16.0 * ell + 24.0 * ell + 24.0 * ell + 2.0 * ell,
+    }.get(name)
+
+
+def table_slots(m: int) -> int:
+    return max(1024, (4 * m + 7) // 8 * 8)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2111_03005_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(p) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_digest") != source_digest():
+        return None
+    rec = d.get("kernels", {}).get(workload, {}).get(kernel)
+    if not rec:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(E, n, r_sample, seed):
+    import oracle
+    oracle._load()
+    t = time.perf_counter()
+    rc, _, counts, _ = oracle.run(E, n, seed, 0, r_sample, 0)
+    dt = time.perf_counter() - t
+    att = sum(c["attempts"] for c in counts)
+    return att / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pld_n2^20_g2.5")
+    ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-supersteps", type=int, default=3)
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}))
+        return
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent graphs would shard across GPUs without communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen
+    import paper_2111_03005_amd as gesmc
+
+    make, r = graphgen.WORKLOADS[args.workload]
+    E, n = make()
+    m = len(E)
+    ell = m // 2
+    dev = torch.device("cuda", 0)
+    ctx = gesmc.Context(0)
+    d_in = torch.from_numpy(E.view(np.int64).copy()).to(dev)
+    d_out = torch.empty_like(d_in)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
+    torch.cuda.synchronize()
+
+    ctx.set_option(gesmc.OPT_PROFILE, 0 if args.no_profile else 1)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        _, stats = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_option(gesmc.OPT_PROFILE, 0)
+    prof = ctx.profile()
+
+    attempts = args.steps * r * ell
+    value = attempts / wall
+    ms_per_step = 1000.0 * wall / args.steps
+
+    # dominant kernel among those with a byte model
+    tslots = table_slots(m)
+    rows = []
+    for name, (ms, launches, items) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        b = kernel_bytes(name, m, ell, tslots)
+        rows.append((name, ms, launches, b))
+        print("kernel %-16s total %9.3f ms  launches %5d  avg %8.4f ms%s" % (
+            name, ms, launches, ms / max(launches, 1),
+            "" if b is None else "  %.0f GB/s" % (b / (ms / launches / 1e3) / 1e9)), file=sys.stderr)
+    roofline = None
+    modeled = [x for x in rows if x[3] is not None]
+    if modeled:
+        name, ms, launches, b = modeled[0]
+        avg_s = ms / launches / 1e3
+        achieved = b / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(name, args.workload),
+                    "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 4),
+                    "share_of_step": round(ms / (wall * 1e3), 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rs = min(args.cpu_sample_supersteps, r)
+        v, dt = cpu_baseline(E, n, rs, args.seed)
+        cpu = {"value": round(v, 1), "unit": "attempts/s", "cores": 1, "kind": "oracle",
+               "sample": "%s, first %d of %d supersteps incl. validation and set build (%.1f s)" % (
+                   args.workload, rs, r, dt)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "supersteps_per_step": r,
+                   "attempts_per_step": r * ell, "seed": args.seed, "pl": 0, "mode": "plain",
+                   "legal_fraction": round(stats["legal"] / max(stats["attempts"], 1), 5) if stats else None,
+                   "rounds_max": stats["rounds_max"] if stats else None,
+                   "event_timing": not args.no_profile},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

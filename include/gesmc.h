@@ -111,10 +111,13 @@ gesmc_status gesmc_perm_keys(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t 
 gesmc_status gesmc_permutation(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint32_t *d_pi);
 
 /* Tuning knobs (values are validated; results never depend on them). */
-#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 2560, default 2560) */
-#define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 3072, default 3072)     */
+#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 768, default 512)    */
+#define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1024, default 1024)     */
 #define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64) */
 #define GESMC_OPT_PROFILE 4     /* 1: time every kernel launch with HIP events                      */
+#define GESMC_OPT_STRATEGY 5    /* dependency resolution: 0 = tuples sorted by edge key per hash
+                                   partition in LDS (default); 1 = one open-addressing table in HBM
+                                   rebuilt every superstep with device-scope atomics               */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

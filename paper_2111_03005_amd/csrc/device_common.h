@@ -103,21 +103,27 @@ __device__ __forceinline__ uint64_t slot_hash(uint64_t x) {
     return x;
 }
 
-// Finds or inserts `key`; returns its slot.  The table is never more than
-// half full, so the probe ends at an empty slot; the probe count is bounded
-// anyway (kNoSlot: table full, an internal error).
+// Finds or inserts `key`; returns its slot.  `nslots` need not be a power of
+// two: the home slot is the high word of hash * nslots (multiply-shift range
+// reduction).  The table is never more than half full, so the probe ends at
+// an empty slot; the probe count is bounded anyway (kNoSlot: table full, an
+// internal error).
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
-__device__ __forceinline__ uint32_t table_find_or_insert(Slot *tab, uint32_t mask, unsigned long long key) {
-    uint32_t s = (uint32_t)slot_hash(key) & mask;
-    for (uint64_t probes = 0; probes <= (uint64_t)mask; ++probes) {
+__device__ __forceinline__ uint32_t table_home(unsigned long long key, uint32_t nslots) {
+    return (uint32_t)__umul64hi(slot_hash(key), (unsigned long long)nslots);
+}
+
+__device__ __forceinline__ uint32_t table_find_or_insert(Slot *tab, uint32_t nslots, unsigned long long key) {
+    uint32_t s = table_home(key, nslots);
+    for (uint32_t probes = 0; probes < nslots; ++probes) {
         const unsigned long long cur = tab[s].key;
         if (cur == key) return s;
         if (cur == kEmptyKey) {
             const unsigned long long prev = atomicCAS(&tab[s].key, kEmptyKey, key);
             if (prev == kEmptyKey || prev == key) return s;
         }
-        s = (s + 1) & mask;
+        s = (s + 1 == nslots) ? 0 : s + 1;
     }
     return kNoSlot;
 }

@@ -11,6 +11,7 @@
 #include "gesmc.h"
 #include "perm_kernels.h"
 #include "switch_kernels.h"
+#include "resolve_kernels.h"
 
 using namespace gesmc;
 
@@ -43,13 +44,23 @@ enum KernelId {
     KID_UNPERMUTE,
     KID_VALIDATE,
     KID_MISC,
+    KID_EMIT,
+    KID_TSCATTER1,
+    KID_THIST_SUB,
+    KID_TSCATTER2,
+    KID_RESOLVE,
+    KID_DECIDE_CHAIN1,
+    KID_DECIDE_CHAIN,
+    KID_FINISH_CHAIN,
     KID_COUNT
 };
 
 const char *kKernelNames[KID_COUNT] = {
     "k_load",        "k_hist_clear",  "k_scan_coarse", "k_scatter1",      "k_hist_sub",   "k_scan_fine",
     "k_scatter2",    "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
-    "k_round_decide", "k_finish",     "k_unpermute",   "k_validate",      "k_misc"};
+    "k_round_decide", "k_finish",     "k_unpermute",   "k_validate",      "k_misc",
+    "k_emit",        "k_tscatter1",   "k_thist_sub",   "k_tscatter2",     "k_resolve",    "k_decide_chain1",
+    "k_decide_chain", "k_finish_chain"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -86,9 +97,10 @@ struct gesmc_ctx {
     int device = 0;
     int num_cus = 256;
     // options
-    uint32_t bucket_avg = 2560;
-    uint32_t sort_cap = 3072;
-    int fast_rounds = 4;
+    uint32_t bucket_avg = (1u << kSortSubBits) / 2;
+    uint32_t sort_cap = 1u << kSortSubBits;
+    int fast_rounds = 2;
+    int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
     // device buffers (capacity in edges)
     uint64_t cap_m = 0;
@@ -99,6 +111,11 @@ struct gesmc_ctx {
     uint32_t *sw_slot = nullptr;
     uint8_t *st = nullptr;
     uint32_t *ulist[2] = {nullptr, nullptr};
+    // dependency tuples: flat (per switch), and two partitioned buffers
+    uint64_t cap_tu = 0;
+    uint32_t *tu_tag[3] = {nullptr, nullptr, nullptr};
+    unsigned long long *tu_key[3] = {nullptr, nullptr, nullptr};
+    uint2 *info = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
@@ -145,6 +162,15 @@ void free_buffers(gesmc_ctx *c) {
         if (c->ulist[q]) (void)hipFree(c->ulist[q]);
         c->ulist[q] = nullptr;
     }
+    for (int q = 0; q < 3; ++q) {
+        if (c->tu_tag[q]) (void)hipFree(c->tu_tag[q]);
+        if (c->tu_key[q]) (void)hipFree(c->tu_key[q]);
+        c->tu_tag[q] = nullptr;
+        c->tu_key[q] = nullptr;
+    }
+    if (c->info) (void)hipFree(c->info);
+    c->info = nullptr;
+    c->cap_tu = 0;
     c->tab = nullptr;
     c->sw_slot = nullptr;
     c->st = nullptr;
@@ -164,13 +190,14 @@ gesmc_status dev_alloc(void **p, size_t bytes) {
 
 uint64_t table_slots_for(uint64_t m) {
     // keys per superstep <= m sources + 2 * floor(m/2) targets <= 2m; load <= 1/2
-    uint64_t s = 1024;
-    while (s < 4 * m) s <<= 1;
-    return s;
+    // (slot count a multiple of 8: whole 128-byte lines)
+    return std::max<uint64_t>(1024, (4 * m + 7) / 8 * 8);
 }
 
 gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
-    if (m <= c->cap_m && c->tab) return GESMC_OK;
+    const bool need_tab = c->strategy == 1;
+    const bool need_tu = c->strategy == 0;
+    if (m <= c->cap_m && (!need_tab || c->tab) && (!need_tu || c->info)) return GESMC_OK;
     free_buffers(c);
     const uint64_t cap = std::max<uint64_t>(m, 1024);
     gesmc_status s = GESMC_OK;
@@ -178,8 +205,15 @@ gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
         s = dev_alloc((void **)&c->idx[q], cap * 4);
         if (s == GESMC_OK) s = dev_alloc((void **)&c->key[q], cap * 8);
     }
-    const uint64_t ts = table_slots_for(cap);
-    if (s == GESMC_OK) s = dev_alloc((void **)&c->tab, ts * sizeof(Slot));
+    const uint64_t ts = need_tab ? table_slots_for(cap) : 0;
+    if (s == GESMC_OK && need_tab) s = dev_alloc((void **)&c->tab, ts * sizeof(Slot));
+    const uint64_t ntu = 2 * cap + 8;  // 4 * floor(m/2) + 1 tuple slots
+    for (int q = 0; q < 3 && s == GESMC_OK && need_tu; ++q) {
+        s = dev_alloc((void **)&c->tu_tag[q], ntu * 4);
+        if (s == GESMC_OK) s = dev_alloc((void **)&c->tu_key[q], ntu * 8);
+    }
+    if (s == GESMC_OK && need_tu) s = dev_alloc((void **)&c->info, (cap + 8) * sizeof(uint2));
+    if (s == GESMC_OK) c->cap_tu = need_tu ? ntu : 0;
     if (s == GESMC_OK) s = dev_alloc((void **)&c->sw_slot, (cap / 2 + 1) * 8);
     if (s == GESMC_OK) s = dev_alloc((void **)&c->st, cap / 2 + 64);
     for (int q = 0; q < 2 && s == GESMC_OK; ++q) s = dev_alloc((void **)&c->ulist[q], (cap / 2 + 64) * 4);
@@ -264,6 +298,7 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     p.ell = m / 2;
     uint32_t B = 0;
     while (B < kMaxFineBits && ((uint64_t)c->bucket_avg << B) < m) ++B;
+    // (for tuple partitions `m` is the number of tuple slots)
     p.bbits = B;
     p.b1 = std::min<uint32_t>(B, 8);
     p.b2 = B - p.b1;
@@ -282,6 +317,10 @@ size_t scatter_lds_bytes(int dbits) {
 
 size_t sort_lds_bytes(uint32_t cap) {
     return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 20;
+}
+
+size_t resolve_lds_bytes(uint32_t cap) {
+    return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 12;
 }
 
 uint32_t grid_stride_blocks(const gesmc_ctx *c, uint64_t work) {
@@ -311,7 +350,7 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
     }
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, m,
                      p.ntiles1));
-    GESMC_TRY(launch(c, s, KID_SCATTER1, m, k_scatter, dim3(p.ntiles1), dim3(kBlock), scatter_lds_bytes(p.b1),
+    GESMC_TRY(launch(c, s, KID_SCATTER1, m, k_scatter<false>, dim3(p.ntiles1), dim3(kBlock), scatter_lds_bytes(p.b1),
                      c->idx[src], c->key[src], c->idx[X], c->key[X], t, k0, k1, 64 - (int)p.b1, (int)p.b1, 1u,
                      c->lvl1_seg, c->lvl1_tiles, c->coarse_cursor, c->err));
     if (p.b2 == 0) {
@@ -322,12 +361,13 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
         return GESMC_OK;
     }
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;
-    GESMC_TRY(launch(c, s, KID_HIST_SUB, m, k_hist_sub, dim3(tiles2), dim3(kBlock), ((size_t)1 << p.b2) * 4,
-                     c->idx[X], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
+    GESMC_TRY(launch(c, s, KID_HIST_SUB, m, k_hist_sub<false>, dim3(tiles2), dim3(kBlock), ((size_t)1 << p.b2) * 4,
+                     c->idx[X], c->key[X], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
                      c->fine_hist));
-    GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(1), dim3(1024), 0, p.nfine, c->fine_hist,
+    GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(p.ncoarse), dim3(kBlock),
+                     (((size_t)1 << p.b2) + kBlock + 1) * 4, (int)p.b2, c->coarse_off, p.ncoarse, c->fine_hist,
                      c->fine_off, c->fine_cursor));
-    GESMC_TRY(launch(c, s, KID_SCATTER2, m, k_scatter, dim3(tiles2), dim3(kBlock), scatter_lds_bytes(p.b2),
+    GESMC_TRY(launch(c, s, KID_SCATTER2, m, k_scatter<false>, dim3(tiles2), dim3(kBlock), scatter_lds_bytes(p.b2),
                      c->idx[X], c->key[X], c->idx[Y], c->key[Y], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse,
                      c->coarse_off, c->tile_first, c->fine_cursor, c->err));
     GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(p.nfine), dim3(kBlock), sort_lds, c->idx[Y], c->key[Y],
@@ -337,16 +377,86 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
     return GESMC_OK;
 }
 
+// Partitions the tuples in tuple buffer 0 (nslots slots, empty keys dropped)
+// by key hash and resolves every partition.  `records` sizes the partitions.
+gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit) {
+    const Plan p = make_plan(c, nslots);
+    GESMC_TRY(launch(c, s, KID_SCAN_COARSE, p.ncoarse, k_scan_coarse, dim3(1), dim3(kBlock), 0, p.ncoarse,
+                     c->coarse_hist, c->coarse_off, c->coarse_cursor, c->tile_first));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, nslots,
+                     p.ntiles1));
+    const int shift1 = 64 - (int)(p.b1 > 0 ? p.b1 : 1);
+    GESMC_TRY(launch(c, s, KID_TSCATTER1, nslots, k_scatter<true>, dim3(p.ntiles1), dim3(kBlock),
+                     scatter_lds_bytes(p.b1), c->tu_tag[0], c->tu_key[0], c->tu_tag[1], c->tu_key[1], 0u, 0u, 0u,
+                     p.b1 > 0 ? 64 - (int)p.b1 : shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles,
+                     c->coarse_cursor, c->err));
+    int parts = 1, scratch = 0;
+    const uint32_t *part_off = c->coarse_off;
+    uint32_t nparts = p.ncoarse;
+    if (p.b2 > 0) {
+        const uint32_t tiles2 = p.ntiles1 + p.ncoarse;
+        GESMC_TRY(launch(c, s, KID_THIST_SUB, nslots, k_hist_sub<true>, dim3(tiles2), dim3(kBlock),
+                         ((size_t)1 << p.b2) * 4, c->tu_tag[1], c->tu_key[1], 0u, 0u, 0u, 64 - (int)p.bbits,
+                         (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_hist));
+        GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(p.ncoarse), dim3(kBlock),
+                         (((size_t)1 << p.b2) + kBlock + 1) * 4, (int)p.b2, c->coarse_off, p.ncoarse, c->fine_hist,
+                         c->fine_off, c->fine_cursor));
+        GESMC_TRY(launch(c, s, KID_TSCATTER2, nslots, k_scatter<true>, dim3(tiles2), dim3(kBlock),
+                         scatter_lds_bytes(p.b2), c->tu_tag[1], c->tu_key[1], c->tu_tag[2], c->tu_key[2], 0u, 0u, 0u,
+                         64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_cursor,
+                         c->err));
+        parts = 2;
+        scratch = 1;
+        part_off = c->fine_off;
+        nparts = p.nfine;
+    }
+    GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(nparts), dim3(kBlock), resolve_lds_bytes(c->sort_cap),
+                     c->tu_tag[parts], c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.bbits,
+                     part_off, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step));
+    return GESMC_OK;
+}
+
+// One superstep with the partitioned resolution (state in buffer 0).
+gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
+                                   uint32_t pl, uint32_t dup_bit) {
+    int sorted = 0;
+    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false));
+    const uint32_t *si = c->idx[sorted];
+    const unsigned long long *sk = c->key[sorted];
+    const uint32_t nslots = 4 * p.ell + (p.m & 1u);
+    const Plan tp = make_plan(c, nslots);
+    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(grid_stride_blocks(c, (uint64_t)p.ell + 1)), dim3(kBlock), 0, si,
+                     sk, p.m, t, k0, k1, pl, c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0],
+                     (int)tp.b1, c->coarse_hist, c->ctr_step));
+    GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit));
+    if (p.ell == 0) return GESMC_OK;
+    GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(ceil_div(p.ell, kBlock)), dim3(kBlock), 0,
+                     si, sk, p.ell, (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
+                     (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->ctr_step));
+    const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
+    int j = 0;
+    for (; j < c->fast_rounds; ++j) {
+        GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN, 0, k_decide_chain, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
+                         (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
+                         (const uint32_t *)&c->ucount[j % 3], c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3],
+                         &c->ucount[(j + 2) % 3], c->ctr_step));
+    }
+    GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
+                     (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
+                     c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], c->ctr_step, c->err));
+    return GESMC_OK;
+}
+
 // One superstep t on the state records in buffer 0 (result back in buffer 0).
 gesmc_status superstep(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1, uint32_t pl,
                        uint32_t dup_bit) {
     int sorted = 0;
     GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, true));
-    const uint32_t mask = (uint32_t)(c->tab_slots - 1);
+    const uint32_t nslots = (uint32_t)c->tab_slots;
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     GESMC_TRY(launch(c, s, KID_BUILD, p.ell, k_build, dim3(ceil_div((uint64_t)p.ell + 1, kBlock)), dim3(kBlock), 0,
-                     si, sk, p.m, t, k0, k1, pl, c->tab, mask, c->sw_slot, c->st, c->idx[0], c->key[0], c->ctr_step,
+                     si, sk, p.m, t, k0, k1, pl, c->tab, nslots, c->sw_slot, c->st, c->idx[0], c->key[0], c->ctr_step,
                      c->err, dup_bit));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE1, p.ell, k_decide_first, dim3(ceil_div(p.ell, kBlock)), dim3(kBlock), 0, si, sk,
@@ -443,21 +553,33 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
         GESMC_TRY(launch(c, s, KID_LOAD, m, k_load, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
                          (const unsigned long long *)d_in, m, n, c->idx[0], c->key[0], c->err));
     const Plan p = make_plan(c, m);
-    const uint32_t mask = (uint32_t)(c->tab_slots - 1);
+    const uint32_t nslots = (uint32_t)c->tab_slots;
     if (m >= 2 && r == 0) {
         c->ctr_step = c->ctr;
-        GESMC_TRY(launch(c, s, KID_HIST_CLEAR, c->tab_slots, k_hist_clear, dim3(grid_stride_blocks(c, c->tab_slots)),
-                         dim3(kBlock), 0, 0u, 0u, k0, k1, 0, c->coarse_hist, c->tab, c->tab_slots, c->st, 0u,
-                         c->ucount));
-        GESMC_TRY(launch(c, s, KID_SCAN_COARSE, 1, k_scan_coarse, dim3(1), dim3(kBlock), 0, 1u, c->coarse_hist,
-                         c->coarse_off, c->coarse_cursor, c->tile_first));
-        GESMC_TRY(launch(c, s, KID_VALIDATE, m, k_validate, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
-                         c->key[0], m, c->tab, mask, c->err));
+        if (c->strategy == 1) {
+            GESMC_TRY(launch(c, s, KID_HIST_CLEAR, c->tab_slots, k_hist_clear,
+                             dim3(grid_stride_blocks(c, c->tab_slots)), dim3(kBlock), 0, 0u, 0u, k0, k1, 0,
+                             c->coarse_hist, c->tab, c->tab_slots, c->st, 0u, c->ucount));
+            GESMC_TRY(launch(c, s, KID_SCAN_COARSE, 1, k_scan_coarse, dim3(1), dim3(kBlock), 0, 1u, c->coarse_hist,
+                             c->coarse_off, c->coarse_cursor, c->tile_first));
+            GESMC_TRY(launch(c, s, KID_VALIDATE, m, k_validate, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                             c->key[0], m, c->tab, nslots, c->err));
+        } else {
+            const Plan vp = make_plan(c, m);
+            GESMC_TRY(launch(c, s, KID_EMIT, m, k_emit_sources, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                             (const unsigned long long *)c->key[0], m, c->tu_tag[0], c->tu_key[0], (int)vp.b1,
+                             c->coarse_hist));
+            GESMC_TRY(partition_and_resolve(c, s, m, ERR_DUP));
+        }
     }
     if (m >= 2) {
         for (uint32_t q = 0; q < r; ++q) {
             c->ctr_step = c->ctr + q;
-            GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, q == 0 ? ERR_DUP : ERR_INTERNAL));
+            const uint32_t dup = q == 0 ? ERR_DUP : ERR_INTERNAL;
+            if (c->strategy == 1)
+                GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, dup));
+            else
+                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup));
         }
     }
     if (d_outcome && p.ell > 0)
@@ -562,8 +684,12 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sort_lds_bytes(kSortMaxItems * kBlock));
-    (void)hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_scatter<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)scatter_lds_bytes(12));
+    (void)hipFuncSetAttribute((const void *)k_scatter<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)scatter_lds_bytes(12));
+    (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)resolve_lds_bytes(kSortMaxItems * kBlock));
     (void)hipGetLastError();
     if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
         hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
@@ -671,7 +797,7 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
     }
     switch (option) {
         case GESMC_OPT_BUCKET_AVG:
-            if (v < 64 || v > 2560) break;
+            if (v < 64 || v > (3 << kSortSubBits) / 4) break;
             c->bucket_avg = (uint32_t)v;
             return GESMC_OK;
         case GESMC_OPT_SORT_CAP:
@@ -684,6 +810,14 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_STRATEGY:
+            if (v < 0 || v > 1) break;
+            if (c->strategy != (int)v) {
+                (void)hipDeviceSynchronize();
+                free_buffers(c);  // buffers differ per strategy; reallocated on the next call
+            }
+            c->strategy = (int)v;
             return GESMC_OK;
         default:
             set_error("unknown option %d", option);

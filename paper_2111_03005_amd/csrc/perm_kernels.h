@@ -7,8 +7,8 @@
 //   level 1   : coarse digit = top b1 bits of K (b1 <= 8), LDS-staged scatter
 //   level 2   : sub digit    = next b2 bits, scattered inside each coarse
 //               bucket (its region is small enough to stay L2/MALL resident)
-//   bucket    : each fine bucket (~1-2.5k records) is counting-sorted in LDS
-//               on the next 12 bits of K, then ties inside a 12-bit cell are
+//   bucket    : each fine bucket (~0.5-1k records) is counting-sorted in LDS
+//               on the next 11 bits of K, then ties inside a 12-bit cell are
 //               settled by insertion sort on (K, i).
 // Keys are never stored: every pass recomputes K_i from the record's index.
 #pragma once
@@ -17,39 +17,68 @@
 
 namespace gesmc {
 
-constexpr int kScatterTile = 4096;  // records per scatter workgroup
-constexpr int kSortSubBits = 12;    // counting-sort cells per fine bucket = 4096
-constexpr int kSortMaxItems = 12;   // per-thread records in the LDS sort (cap <= 3072)
+#ifndef GESMC_SCATTER_TILE
+#define GESMC_SCATTER_TILE 2048
+#endif
+#ifndef GESMC_SORT_SUB_BITS
+#define GESMC_SORT_SUB_BITS 10
+#endif
+constexpr int kScatterTile = GESMC_SCATTER_TILE;     // records per scatter workgroup
+constexpr int kSortSubBits = GESMC_SORT_SUB_BITS;    // counting-sort cells per bucket = 2^bits
+constexpr int kSortMaxItems = (1 << kSortSubBits) / kBlock;  // per-thread records (cap <= 2^bits)
 
-// Workgroup-wide exclusive scan of n <= kBlock * per values held in LDS
-// (in place).  `tmp` needs kBlock + 1 entries.  Returns the total.
+// Inclusive prefix sum across one wave64 (shuffle-up ladder).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive prefix sum of one value per thread over a workgroup of NT
+// threads.  `wsum` needs NT/64 + 1 words of LDS.  Returns the thread's
+// exclusive prefix; *total receives the sum over the workgroup.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t *wsum, uint32_t *total) {
+    constexpr int kWaves = NT / 64;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t incl = wave_inclusive_scan(x);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        const uint32_t v = wsum[q];
+        before += (q < (int)w) ? v : 0u;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+// Workgroup-wide exclusive scan (in place) of n values in LDS; each thread
+// owns a contiguous run of ceil(n / kBlock).  `tmp` needs kBlock + 1 words.
+// Returns the total.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *tmp) {
     const uint32_t tid = threadIdx.x;
     const uint32_t per = (n + kBlock - 1) / kBlock;
-    const uint32_t b = tid * per;
+    const uint32_t b = min(tid * per, n);
     const uint32_t e = min(b + per, n);
     uint32_t s = 0;
     for (uint32_t q = b; q < e; ++q) s += v[q];
-    tmp[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (int q = 0; q < kBlock; ++q) {
-            uint32_t x = tmp[q];
-            tmp[q] = acc;
-            acc += x;
-        }
-        tmp[kBlock] = acc;
-    }
-    __syncthreads();
-    uint32_t acc = tmp[tid];
+    uint32_t total;
+    uint32_t acc = block_exclusive_sum<kBlock>(s, tmp, &total);
     for (uint32_t q = b; q < e; ++q) {
-        uint32_t x = v[q];
+        const uint32_t x = v[q];
         v[q] = acc;
         acc += x;
     }
     __syncthreads();
-    return tmp[kBlock];
+    return total;
 }
 
 // ---------------------------------------------------------------------------
@@ -85,6 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_clear(uint32_t m, uint32_t t, u
     if (gtid == 0) {
         ucount[0] = 0;
         ucount[1] = 0;
+        ucount[2] = 0;
     }
     __syncthreads();
     if (b1 > 0) {
@@ -123,38 +153,28 @@ __global__ __launch_bounds__(kBlock) void k_scan_coarse(uint32_t ncoarse, uint32
     }
 }
 
-// Fine scan (one workgroup of 1024 threads): offsets and cursors of all 2^B
-// fine buckets; clears the fine histogram.
-__global__ __launch_bounds__(1024) void k_scan_fine(uint32_t nfine, uint32_t *__restrict__ fine_hist,
-                                                    uint32_t *__restrict__ fine_off,
-                                                    uint32_t *__restrict__ fine_cursor) {
-    __shared__ uint32_t part[1025];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (nfine + 1023) / 1024;
-    const uint32_t b = tid * per, e = min(b + per, nfine);
-    uint32_t s = 0;
-    for (uint32_t q = b; q < e; ++q) s += fine_hist[q];
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (int q = 0; q < 1024; ++q) {
-            uint32_t x = part[q];
-            part[q] = acc;
-            acc += x;
-        }
-        part[1024] = acc;
+// Fine scan, one workgroup per coarse segment s: the 2^dbits sub-counts of s
+// (in LDS) scanned and offset by the segment's start give the fine offsets
+// and cursors; the histogram is cleared for the next use.
+__global__ __launch_bounds__(kBlock) void k_scan_fine(int dbits, const uint32_t *__restrict__ coarse_off,
+                                                      uint32_t ncoarse, uint32_t *__restrict__ fine_hist,
+                                                      uint32_t *__restrict__ fine_off,
+                                                      uint32_t *__restrict__ fine_cursor) {
+    extern __shared__ uint32_t v[];  // 2^dbits + kBlock + 1
+    uint32_t *tmp = v + (1u << dbits);
+    const uint32_t s = blockIdx.x, nd = 1u << dbits, base = s << dbits;
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        v[d] = fine_hist[base + d];
+        fine_hist[base + d] = 0;
     }
     __syncthreads();
-    uint32_t acc = part[tid];
-    for (uint32_t q = b; q < e; ++q) {
-        const uint32_t x = fine_hist[q];
-        fine_off[q] = acc;
-        fine_cursor[q] = acc;
-        fine_hist[q] = 0;
-        acc += x;
+    block_exclusive_scan(v, nd, tmp);
+    const uint32_t off = coarse_off[s];
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        fine_off[base + d] = off + v[d];
+        fine_cursor[base + d] = off + v[d];
     }
-    if (tid == 0) fine_off[nfine] = part[1024];
+    if (s == ncoarse - 1 && threadIdx.x == 0) fine_off[ncoarse << dbits] = coarse_off[ncoarse];
 }
 
 // Locates the segment of tile w: the largest s with tile_first[s] <= w.
@@ -170,10 +190,23 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
     return lo;
 }
 
+// Radix source of a record: kByKeyHash = false sorts edge records by the
+// Philox key of their index (the permutation); true sorts (tag, edge key)
+// tuples by a hash of the edge key (the dependency partitions), where an
+// empty key marks a tuple slot that carries nothing.
+template <bool kByKeyHash>
+__device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t t, uint32_t k0,
+                                               uint32_t k1) {
+    if (kByKeyHash) return slot_hash(key);
+    return perm_key(idx, t, k0, k1);
+}
+
 // Level-2 histogram: sub digit counts of each coarse segment, per tile in LDS,
 // added into the global fine histogram.
-__global__ __launch_bounds__(kBlock) void k_hist_sub(const uint32_t *__restrict__ src_idx, uint32_t t, uint32_t k0,
-                                                     uint32_t k1, int shift, int dbits, uint32_t nseg,
+template <bool kByKeyHash>
+__global__ __launch_bounds__(kBlock) void k_hist_sub(const uint32_t *__restrict__ src_idx,
+                                                     const unsigned long long *__restrict__ src_key, uint32_t t,
+                                                     uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
                                                      const uint32_t *__restrict__ seg_off,
                                                      const uint32_t *__restrict__ tile_first,
                                                      uint32_t *__restrict__ fine_hist) {
@@ -187,7 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_hist_sub(const uint32_t *__restrict_
     for (uint32_t d = threadIdx.x; d < nd; d += kBlock) hs[d] = 0;
     __syncthreads();
     for (uint32_t p = begin + threadIdx.x; p < end; p += kBlock) {
-        const uint64_t K = perm_key(src_idx[p], t, k0, k1);
+        const uint64_t K = kByKeyHash ? radix_word<true>(0, src_key[p], t, k0, k1)
+                                      : radix_word<false>(src_idx[p], 0, t, k0, k1);
         atomicAdd(&hs[(uint32_t)(K >> shift) & dmask], 1u);
     }
     __syncthreads();
@@ -196,9 +230,11 @@ __global__ __launch_bounds__(kBlock) void k_hist_sub(const uint32_t *__restrict_
 }
 
 // LDS-staged scatter of one tile of a segment by digit (K >> shift) & mask.
-// Records of one digit leave the workgroup as one contiguous run.
+// Records of one digit leave the workgroup as one contiguous run.  With
+// kByKeyHash, tuple slots whose key is empty are dropped.
 // Dynamic LDS: 3 * 2^dbits + 1 + kBlock + 1 words of counters, then the
 // staged records.
+template <bool kByKeyHash>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
                                                     uint32_t *__restrict__ dst_idx,
@@ -236,12 +272,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
         const uint32_t p = tid + q * kBlock;
+        r_dig[q] = 0xFFFFFFFFu;
         if (p < cnt_here) {
             r_idx[q] = src_idx[begin + p];
             r_key[q] = src_key[begin + p];
-            const uint64_t K = perm_key(r_idx[q], t, k0, k1);
-            r_dig[q] = (uint32_t)(K >> shift) & dmask;
-            r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
+            if (!kByKeyHash || r_key[q] != kEmptyKey) {
+                const uint64_t K = radix_word<kByKeyHash>(r_idx[q], r_key[q], t, k0, k1);
+                r_dig[q] = (uint32_t)(K >> shift) & dmask;
+                r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
+            }
         }
     }
     __syncthreads();
@@ -250,18 +289,25 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
     block_exclusive_scan(start, nd, tmp);
     for (uint32_t d = tid; d < nd; d += kBlock)
         if (cnt[d]) base[d] = atomicAdd(&cursor[(s << dbits) | d], cnt[d]);
+    __shared__ uint32_t s_total;
+    if (tid == 0) s_total = 0;
+    __syncthreads();
+    uint32_t mine = 0;
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
         const uint32_t p = tid + q * kBlock;
-        if (p < cnt_here) {
+        if (p < cnt_here && r_dig[q] != 0xFFFFFFFFu) {
             const uint32_t lp = start[r_dig[q]] + r_rank[q];
             s_idx[lp] = r_idx[q];
             s_key[lp] = r_key[q];
             s_dig[lp] = (uint16_t)r_dig[q];
+            ++mine;
         }
     }
+    if (mine) atomicAdd(&s_total, mine);
     __syncthreads();
-    for (uint32_t lp = tid; lp < cnt_here; lp += kBlock) {
+    const uint32_t staged = s_total;
+    for (uint32_t lp = tid; lp < staged; lp += kBlock) {
         const uint32_t d = s_dig[lp];
         const uint32_t g = base[d] + (lp - start[d]);
         if (g >= seg_begin && g < seg_end) {
@@ -273,11 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
     }
 }
 
-// Sorts each fine bucket by (K, i): LDS counting sort on the 12 bits of K
+// Sorts each fine bucket by (K, i): LDS counting sort on the 11 bits of K
 // below the B bucket bits, then insertion sort inside each cell.  Buckets
-// larger than `cap` (never expected: the mean is <= 2560 and the cap 3072)
+// larger than `cap` (never expected: the mean is <= 1024 and the cap 2048)
 // take a slow exact path that ranks every record against the whole bucket.
-// Dynamic LDS: 4096 cell counters + kBlock + 1 scan words + cap * 20 bytes.
+// Dynamic LDS: 2048 cell counters + kBlock + 2 scan words + cap * 20 bytes.
 __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restrict__ src_idx,
                                                          const unsigned long long *__restrict__ src_key,
                                                          uint32_t *__restrict__ dst_idx,

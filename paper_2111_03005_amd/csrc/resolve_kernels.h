@@ -1,0 +1,440 @@
+// Dependency resolution of a global switch by sorting (edge key, tag) tuples
+// by edge key -- an HBM-atomic-free form of Alg. 1's dependency table T.
+//
+// Every switch k that survives its local checks emits four tuples: an ERASE
+// tuple for each source edge (Def. 3.1 / Alg. 1 "erase") and an INSERT tuple
+// for each target edge ("insert"); a switch rejected locally (loop, a target
+// equal to one of its own sources, P_L) and the idle position of odd m emit
+// ERASE tuples marked STAYS (those edges survive the superstep).  Tuples are
+// partitioned by a hash of the key with the same LDS-staged radix scatter as
+// the permutation, so all tuples of one key meet in one workgroup, which
+// sorts its partition in LDS and derives for every INSERT tuple (k, X):
+//   eraser(X)  : the switch whose source X is (or STAYS / none)   -- lookup
+//   pred(k, X) : the next smaller inserter of X                    -- the
+//                chain behind lookup_min over non-illegal inserters.
+// Only tuples with an eraser or a predecessor write their record (rare); all
+// other records keep the "free" value written by the emit kernel.
+//
+// Decision of switch k (same rule as Alg. 1): illegal if a target is erased
+// by a later switch / stays / is erased by an illegal switch, or if an
+// earlier inserter of a target is legal; delayed if it depends on an
+// undecided switch; else legal.  The predecessor chain of (k, X) lists every
+// earlier inserter of X from the nearest down, so walking it until a legal
+// (-> illegal) or undecided (-> delayed) switch, or its end (-> free),
+// evaluates "no earlier legal inserter of X".
+#pragma once
+
+#include "device_common.h"
+#include "perm_kernels.h"
+#include "switch_kernels.h"
+
+namespace gesmc {
+
+// tuple tags
+constexpr uint32_t kTagInsert = 0x80000000u;  // | (k << 1 | h)
+constexpr uint32_t kTagStays = 0x7FFFFFFEu;   // ERASE tuple of a surviving edge
+// per-target record: x = eraser (kNoEraser / kStays / switch), y = predecessor (k' << 1 | h') or kNoPred
+constexpr uint32_t kNoPred = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Emit: one thread per switch (+ one for the idle record).  Tuple slots
+// 4k .. 4k+3 belong to switch k, slot 4*ell to the idle record; unused slots
+// get an empty key.  Also: records of locally rejected switches, the free
+// target records, and the coarse histogram of tuple partitions.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
+                                                 const unsigned long long *__restrict__ s_key, uint32_t m, uint32_t t,
+                                                 uint32_t k0, uint32_t k1, uint32_t pl, uint32_t *__restrict__ tu_tag,
+                                                 unsigned long long *__restrict__ tu_key, uint2 *__restrict__ info,
+                                                 uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
+                                                 unsigned long long *__restrict__ out_key, int b1,
+                                                 uint32_t *__restrict__ coarse_hist, StepCounters *ctr) {
+    __shared__ uint32_t h[256];
+    __shared__ BlockCounts bc;
+    const uint32_t tid = threadIdx.x;
+    h[tid] = 0;
+    if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
+    __syncthreads();
+    const uint32_t ell = m >> 1;
+    const int shift = 64 - b1;
+    auto count = [&](unsigned long long key) {
+        const uint32_t d = b1 > 0 ? (uint32_t)(slot_hash(key) >> shift) : 0u;
+        atomicAdd(&h[d], 1u);
+    };
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t k = blockIdx.x * kBlock + tid; k <= ell; k += stride) {
+    if (k == ell && (m & 1u)) {
+        const unsigned long long e = s_key[m - 1];
+        tu_tag[4 * (size_t)ell] = kTagStays;
+        tu_key[4 * (size_t)ell] = e;
+        count(e);
+        out_idx[m - 1] = s_idx[m - 1];
+        out_key[m - 1] = e;
+    } else if (k < ell) {
+        const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+        const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+        const uint32_t i = ij.x, j = ij.y;
+        const unsigned long long e1 = ee.x, e2 = ee.y;
+        uint8_t status = ST_UNDECIDED;
+        Targets T{0, 0, false};
+        if (pl_skip(k, t, pl, k0, k1)) {
+            status = ST_PL;
+        } else {
+            T = switch_targets(e1, e2, i < j);
+            if (T.loop)
+                status = ST_LOOP;
+            else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
+                status = ST_EXISTS;
+        }
+        const uint32_t etag = status == ST_UNDECIDED ? k : kTagStays;
+        count(e1);
+        count(e2);
+        ulonglong2 *tk = reinterpret_cast<ulonglong2 *>(tu_key) + 2 * (size_t)k;
+        tk[0] = make_ulonglong2(e1, e2);
+        if (status == ST_UNDECIDED) {
+            reinterpret_cast<uint4 *>(tu_tag)[k] =
+                make_uint4(etag, etag, kTagInsert | (k << 1), kTagInsert | (k << 1) | 1u);
+            tk[1] = make_ulonglong2(T.A, T.B);
+            count(T.A);
+            count(T.B);
+            reinterpret_cast<uint4 *>(info)[k] = make_uint4(kNoEraser, kNoPred, kNoEraser, kNoPred);
+        } else {
+            reinterpret_cast<uint4 *>(tu_tag)[k] = make_uint4(etag, etag, 0u, 0u);
+            tk[1] = make_ulonglong2(kEmptyKey, kEmptyKey);
+            st[k] = status;
+            reinterpret_cast<uint2 *>(out_idx)[k] = ij;
+            reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
+            if (status == ST_PL) atomicAdd(&bc.pl, 1u);
+            if (status == ST_LOOP) atomicAdd(&bc.loop, 1u);
+            if (status == ST_EXISTS) atomicAdd(&bc.exists, 1u);
+        }
+    }
+    }
+    __syncthreads();
+    if (b1 > 0) {
+        for (uint32_t d = tid; d < (1u << b1); d += kBlock)
+            if (h[d]) atomicAdd(&coarse_hist[d], h[d]);
+    } else if (tid == 0 && h[0]) {
+        atomicAdd(&coarse_hist[0], h[0]);
+    }
+    flush_counts(&bc, ctr);
+}
+
+// Validation only (no superstep): one STAYS tuple per input edge, so that a
+// duplicate edge shows up as two ERASE tuples of one key.
+__global__ __launch_bounds__(kBlock) void k_emit_sources(const unsigned long long *__restrict__ key, uint32_t m,
+                                                         uint32_t *__restrict__ tu_tag,
+                                                         unsigned long long *__restrict__ tu_key, int b1,
+                                                         uint32_t *__restrict__ coarse_hist) {
+    __shared__ uint32_t h[256];
+    const uint32_t tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * kBlock + tid; i < m; i += gridDim.x * kBlock) {
+        const unsigned long long e = key[i];
+        tu_tag[i] = kTagStays;
+        tu_key[i] = e;
+        atomicAdd(&h[b1 > 0 ? (uint32_t)(slot_hash(e) >> (64 - b1)) : 0u], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < (1u << b1); d += kBlock)
+        if (h[d]) atomicAdd(&coarse_hist[d], h[d]);
+}
+
+// Writes the records of the tuple at sorted position p, given the position
+// of the first tuple of its key.  Raises dup_bit on a second ERASE tuple.
+__device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, uint32_t p, uint32_t first,
+                                            uint32_t prev_tag, uint2 *info, uint32_t *err, uint32_t dup_bit) {
+    const bool ins = (tag & kTagInsert) != 0;
+    if (!ins) {
+        if (p != first) atomicOr(err, dup_bit);  // two ERASE tuples: the edge occurs twice
+        return;
+    }
+    uint32_t eraser = kNoEraser;
+    if (!(first_tag & kTagInsert)) eraser = (first_tag == kTagStays) ? kStays : first_tag;
+    const uint32_t pred = (p > first && (prev_tag & kTagInsert)) ? (prev_tag & ~kTagInsert) : kNoPred;
+    if (eraser != kNoEraser || pred != kNoPred) info[tag & ~kTagInsert] = make_uint2(eraser, pred);
+}
+
+// One workgroup per fine partition.  LDS path: counting sort on 12 hash bits
+// below the partition bits, insertion sort inside cells, then each tuple finds
+// its key's first tuple while walking its own cells.  Partitions above `cap`
+// (hub keys with many inserters) take an exact global-memory merge sort.
+// Dynamic LDS: 2048 cell words + kBlock + 2 words + cap * 12 bytes.
+__global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
+                                                    uint32_t *__restrict__ sc_tag,
+                                                    unsigned long long *__restrict__ sc_key, int pbits,
+                                                    const uint32_t *__restrict__ part_off, uint32_t cap,
+                                                    uint2 *__restrict__ info, uint32_t *__restrict__ err,
+                                                    uint32_t dup_bit, StepCounters *ctr) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t kCells = 1u << kSortSubBits;
+    uint32_t *cell = lds;
+    uint32_t *tmp = cell + kCells;
+    unsigned long long *sK = reinterpret_cast<unsigned long long *>(tmp + kBlock + 2);
+    uint32_t *sT = reinterpret_cast<uint32_t *>(sK + cap);
+
+    const uint32_t f = blockIdx.x;
+    const uint32_t begin = part_off[f], end = part_off[f + 1];
+    const uint32_t c = end > begin ? end - begin : 0;
+    const uint32_t tid = threadIdx.x;
+    if (c == 0) return;
+    const int sub_shift = 64 - kSortSubBits;
+
+    if (c > cap || c > (uint32_t)(kSortMaxItems * kBlock)) {
+        // exact slow path: bottom-up merge sort by (key, tag) between the
+        // partition's range and the scratch range, then binary searches.
+        uint32_t *at = tu_tag + begin, *bt = sc_tag + begin;
+        unsigned long long *ak = tu_key + begin, *bk = sc_key + begin;
+        for (uint32_t width = 1; width < c; width <<= 1) {
+            for (uint32_t p = tid; p < c; p += kBlock) {
+                const uint32_t run = p / (2 * width);
+                const uint32_t lo = run * 2 * width, mid = min(lo + width, c), hi = min(lo + 2 * width, c);
+                const unsigned long long kp = ak[p];
+                const uint32_t tp = at[p];
+                uint32_t pos;
+                if (p < mid) {  // rank among the right run: elements strictly smaller
+                    uint32_t a = mid, b = hi;
+                    while (a < b) {
+                        const uint32_t x = (a + b) >> 1;
+                        if (ak[x] < kp || (ak[x] == kp && at[x] < tp))
+                            a = x + 1;
+                        else
+                            b = x;
+                    }
+                    pos = lo + (p - lo) + (a - mid);
+                } else {  // rank among the left run: elements smaller or equal
+                    uint32_t a = lo, b = mid;
+                    while (a < b) {
+                        const uint32_t x = (a + b) >> 1;
+                        if (ak[x] < kp || (ak[x] == kp && at[x] <= tp))
+                            a = x + 1;
+                        else
+                            b = x;
+                    }
+                    pos = lo + (p - mid) + (a - lo);
+                }
+                bt[pos] = tp;
+                bk[pos] = kp;
+            }
+            __threadfence_block();
+            __syncthreads();
+            uint32_t *xt = at;
+            at = bt;
+            bt = xt;
+            unsigned long long *xk = ak;
+            ak = bk;
+            bk = xk;
+        }
+        for (uint32_t p = tid; p < c; p += kBlock) {
+            const unsigned long long kp = ak[p];
+            uint32_t a = 0, b = p;
+            while (a < b) {
+                const uint32_t x = (a + b) >> 1;
+                if (ak[x] < kp)
+                    a = x + 1;
+                else
+                    b = x;
+            }
+            resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, info, err, dup_bit);
+        }
+        if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
+        return;
+    }
+
+    for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
+    __syncthreads();
+    uint32_t r_tag[kSortMaxItems], r_cell[kSortMaxItems], r_rank[kSortMaxItems];
+    unsigned long long r_key[kSortMaxItems];
+#pragma unroll
+    for (int q = 0; q < kSortMaxItems; ++q) {
+        const uint32_t p = tid + q * kBlock;
+        if (p < c) {
+            r_tag[q] = tu_tag[begin + p];
+            r_key[q] = tu_key[begin + p];
+            const uint64_t hsh = slot_hash(r_key[q]);
+            r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
+            r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
+        }
+    }
+    __syncthreads();
+    block_exclusive_scan(cell, kCells, tmp);
+#pragma unroll
+    for (int q = 0; q < kSortMaxItems; ++q) {
+        const uint32_t p = tid + q * kBlock;
+        if (p < c) {
+            const uint32_t lp = cell[r_cell[q]] + r_rank[q];
+            sK[lp] = r_key[q];
+            sT[lp] = r_tag[q];
+        }
+    }
+    __syncthreads();
+    // Each thread owns kCells / kBlock consecutive cells.  All tuples of one key share a
+    // cell, so the owner sorts its cells by (key, tag) and walks them once.
+    for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
+        const uint32_t a = cell[q];
+        const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
+        if (b - a < 2) continue;  // a lone tuple has neither eraser nor predecessor
+        for (uint32_t x = a + 1; x < b; ++x) {
+            const unsigned long long kx = sK[x];
+            const uint32_t tx = sT[x];
+            uint32_t y = x;
+            while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sT[y - 1] > tx))) {
+                sK[y] = sK[y - 1];
+                sT[y] = sT[y - 1];
+                --y;
+            }
+            sK[y] = kx;
+            sT[y] = tx;
+        }
+        uint32_t first = a;
+        for (uint32_t x = a; x < b; ++x) {
+            if (x > a && sK[x] != sK[x - 1]) first = x;
+            resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, info, err, dup_bit);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Decisions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int judge_target_chain(const uint2 *info, uint2 rec, uint32_t k, const uint8_t *st) {
+    int v = V_OK;
+    const uint32_t e = rec.x;
+    if (e != kNoEraser) {
+        if (e == kStays || e >= k) return V_ILLEGAL;
+        const uint8_t se = load_status(st, e);
+        if (se == ST_UNDECIDED)
+            v = V_WAIT;
+        else if (se != ST_LEGAL)
+            return V_ILLEGAL;
+    }
+    // earlier inserters of the same target, nearest first; switch ids strictly
+    // decrease along the chain (checked, so a corrupt record cannot loop)
+    uint32_t p = rec.y, below = k;
+    while (p != kNoPred) {
+        const uint32_t pk = p >> 1;
+        if (pk >= below) return V_ILLEGAL;
+        const uint8_t sp = load_status(st, pk);
+        if (sp == ST_LEGAL) return V_ILLEGAL;
+        if (sp == ST_UNDECIDED) return V_WAIT;
+        below = pk;
+        p = info[p].y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool decide_switch_chain(uint32_t k, const uint32_t *s_idx, const unsigned long long *s_key,
+                                                    const uint2 *info, uint8_t *st, uint32_t *out_idx,
+                                                    unsigned long long *out_key, BlockCounts *bc) {
+    const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
+    const int v = max(judge_target_chain(info, make_uint2(recs.x, recs.y), k, st),
+                      judge_target_chain(info, make_uint2(recs.z, recs.w), k, st));
+    if (v == V_WAIT) return true;
+    const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+    const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+    reinterpret_cast<uint2 *>(out_idx)[k] = ij;
+    if (v == V_OK) {
+        const Targets T = switch_targets(ee.x, ee.y, ij.x < ij.y);
+        reinterpret_cast<ulonglong2 *>(out_key)[k] = make_ulonglong2(T.A, T.B);
+        __hip_atomic_store(st + k, (uint8_t)ST_LEGAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&bc->legal, 1u);
+    } else {
+        reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
+        __hip_atomic_store(st + k, (uint8_t)ST_EXISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&bc->exists, 1u);
+    }
+    return false;
+}
+
+// Round 1 (list == nullptr: every switch) or a later round over a list.
+__global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restrict__ s_idx,
+                                                         const unsigned long long *__restrict__ s_key, uint32_t ell,
+                                                         const uint2 *__restrict__ info, uint8_t *st,
+                                                         uint32_t *__restrict__ out_idx,
+                                                         unsigned long long *__restrict__ out_key,
+                                                         const uint32_t *__restrict__ list,
+                                                         const uint32_t *__restrict__ count,
+                                                         uint32_t *__restrict__ next_list,
+                                                         uint32_t *__restrict__ next_count,
+                                                         uint32_t *__restrict__ zero_count, StepCounters *ctr) {
+    __shared__ BlockCounts bc;
+    if (threadIdx.x == 0) bc = BlockCounts{0, 0, 0, 0};
+    __syncthreads();
+    // the counter cleared here is the one the round after next fills
+    if (zero_count && blockIdx.x == 0 && threadIdx.x == 0) *zero_count = 0;
+    const uint32_t n = list ? min(*count, ell) : ell;
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t trips = (n + stride - 1) / stride;
+    for (uint32_t r = 0; r < trips; ++r) {
+        const uint32_t q = r * stride + blockIdx.x * kBlock + threadIdx.x;
+        bool wait = false;
+        uint32_t k = 0;
+        if (q < n) {
+            k = list ? list[q] : q;
+            if (k < ell && st[k] == ST_UNDECIDED)
+                wait = decide_switch_chain(k, s_idx, s_key, info, st, out_idx, out_key, &bc);
+        }
+        append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
+    }
+    flush_counts(&bc, ctr);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(&ctr->rounds, 1ull);
+}
+
+// Remaining rounds in one workgroup; the next round's list counter is cleared
+// by the round that fills it.
+__global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *__restrict__ s_idx,
+                                                               const unsigned long long *__restrict__ s_key,
+                                                               uint32_t ell, const uint2 *__restrict__ info,
+                                                               uint8_t *st, uint32_t *__restrict__ out_idx,
+                                                               unsigned long long *__restrict__ out_key,
+                                                               uint32_t *list_a, uint32_t *count_a, uint32_t *list_b,
+                                                               uint32_t *count_b, StepCounters *ctr,
+                                                               uint32_t *__restrict__ err) {
+    __shared__ BlockCounts bc;
+    __shared__ uint32_t s_n;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        bc = BlockCounts{0, 0, 0, 0};
+        s_n = min(*count_a, ell);
+    }
+    __syncthreads();
+    uint32_t *cur = list_a, *nxt = list_b, *ccur = count_a, *cnxt = count_b;
+    uint32_t n = s_n;
+    while (n > 0) {
+        if (tid == 0) *cnxt = 0;
+        __threadfence();
+        __syncthreads();
+        const uint32_t trips = (n + kFinishBlock - 1) / kFinishBlock;
+        for (uint32_t r = 0; r < trips; ++r) {
+            const uint32_t q = r * kFinishBlock + tid;
+            bool wait = false;
+            uint32_t k = 0;
+            if (q < n) {
+                k = cur[q];
+                if (k < ell && st[k] == ST_UNDECIDED)
+                    wait = decide_switch_chain(k, s_idx, s_key, info, st, out_idx, out_key, &bc);
+            }
+            append_undecided(wait, k, nxt, cnxt);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            const uint32_t nn = min(*cnxt, ell);
+            if (nn >= n) atomicOr(err, ERR_INTERNAL);  // the smallest undecided switch always decides
+            s_n = nn >= n ? 0 : nn;
+            atomicAdd(&ctr->rounds, 1ull);
+        }
+        __syncthreads();
+        n = s_n;
+        uint32_t *tl = cur;
+        cur = nxt;
+        nxt = tl;
+        uint32_t *tc = ccur;
+        ccur = cnxt;
+        cnxt = tc;
+    }
+    flush_counts(&bc, ctr);
+}
+
+}  // namespace gesmc

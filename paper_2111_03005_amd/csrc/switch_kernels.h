@@ -46,10 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_load(const unsigned long long *__res
 
 // Duplicate check of the input edges (used when no superstep runs).
 __global__ __launch_bounds__(kBlock) void k_validate(const unsigned long long *__restrict__ key, uint32_t m, Slot *tab,
-                                                     uint32_t mask, uint32_t *__restrict__ err) {
+                                                     uint32_t nslots, uint32_t *__restrict__ err) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
-        const uint32_t s = table_find_or_insert(tab, mask, key[i]);
+        const uint32_t s = table_find_or_insert(tab, nslots, key[i]);
         if (s == kNoSlot)
             atomicOr(err, ERR_INTERNAL);
         else if (atomicCAS(&tab[s].eraser, kNoEraser, kStays) != kNoEraser)
@@ -95,7 +95,7 @@ __device__ __forceinline__ void flush_counts(BlockCounts *bc, StepCounters *ctr)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_build(const uint32_t *__restrict__ s_idx,
                                                   const unsigned long long *__restrict__ s_key, uint32_t m, uint32_t t,
-                                                  uint32_t k0, uint32_t k1, uint32_t pl, Slot *tab, uint32_t mask,
+                                                  uint32_t k0, uint32_t k1, uint32_t pl, Slot *tab, uint32_t nslots,
                                                   uint32_t *__restrict__ sw_slot, uint8_t *__restrict__ st,
                                                   uint32_t *__restrict__ out_idx,
                                                   unsigned long long *__restrict__ out_key, StepCounters *ctr,
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const uint32_t *__restrict__ s
     if (k == ell && (m & 1u)) {
         // idle position pi[m-1]: its edge stays
         const unsigned long long e = s_key[m - 1];
-        const uint32_t s = table_find_or_insert(tab, mask, e);
+        const uint32_t s = table_find_or_insert(tab, nslots, e);
         if (s == kNoSlot)
             atomicOr(err, ERR_INTERNAL);
         else if (atomicCAS(&tab[s].eraser, kNoEraser, kStays) != kNoEraser)
@@ -130,8 +130,8 @@ __global__ __launch_bounds__(kBlock) void k_build(const uint32_t *__restrict__ s
                 status = ST_EXISTS;  // a target is one of the switch's own (present) sources
         }
         const uint32_t eraser = status == ST_UNDECIDED ? k : kStays;
-        const uint32_t s1 = table_find_or_insert(tab, mask, e1);
-        const uint32_t s2 = table_find_or_insert(tab, mask, e2);
+        const uint32_t s1 = table_find_or_insert(tab, nslots, e1);
+        const uint32_t s2 = table_find_or_insert(tab, nslots, e2);
         if (s1 == kNoSlot || s2 == kNoSlot)
             atomicOr(err, ERR_INTERNAL);
         else {
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_build(const uint32_t *__restrict__ s
             if (atomicCAS(&tab[s2].eraser, kNoEraser, eraser) != kNoEraser) atomicOr(err, dup_bit);
         }
         if (status == ST_UNDECIDED) {
-            const uint32_t sa = table_find_or_insert(tab, mask, T.A);
-            const uint32_t sb = table_find_or_insert(tab, mask, T.B);
+            const uint32_t sa = table_find_or_insert(tab, nslots, T.A);
+            const uint32_t sb = table_find_or_insert(tab, nslots, T.B);
             if (sa == kNoSlot || sb == kNoSlot) {
                 atomicOr(err, ERR_INTERNAL);
             } else {

@@ -20,13 +20,29 @@ def _require_gpu():
         pytest.skip("no GPU")
 
 
-@pytest.fixture(scope="module")
-def ctx():
+STRATEGIES = {"sorted-tuples": 0, "hbm-table": 1}
+
+
+@pytest.fixture(scope="module", params=list(STRATEGIES), ids=list(STRATEGIES))
+def ctx(request):
+    """A context per dependency-resolution strategy; results must not depend on it."""
     _require_gpu()
     import paper_2111_03005_amd as gesmc
     c = gesmc.Context(0)
+    c.set_option(gesmc.OPT_STRATEGY, STRATEGIES[request.param])
     yield c
     c.close()
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_run(E, n, seed, t0, r, pl=0, outcomes=False):
+    """oracle.run, memoised per input content (full-size runs take seconds)."""
+    key = (E.tobytes().__hash__(), len(E), n, seed, t0, r, pl, outcomes)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.run(E, n, seed, t0, r, pl, outcomes=outcomes)
+    return _ORACLE_CACHE[key]
 
 
 def to_dev(E):
@@ -52,7 +68,7 @@ def check_run(ctx, E, n, seed, t0, r, pl=0, label=""):
     print("case %s: m=%d n=%d seed=%d t0=%d r=%d pl=%d" % (label, len(E), n, seed, t0, r, pl), flush=True)
     out, st, steps = ctx.run(to_dev(E), n, seed, t0=t0, r=r, pl=pl, steps=True)
     got = to_host(out)
-    rc, exp, counts, _ = oracle.run(E, n, seed, t0, r, pl)
+    rc, exp, counts, _ = oracle_run(E, n, seed, t0, r, pl)
     assert rc == 0
     diff = np.flatnonzero(got != exp)
     assert diff.size == 0, "%s: %d positions differ, first %s" % (label, diff.size, diff[:5])
@@ -72,12 +88,22 @@ def test_perm_keys(ctx, m, seed, t):
     assert np.array_equal(got, oracle.perm_keys(m, seed, t))
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 64, 2560, 2561, 5209, 70001, 655360, 655361 + 4096 * 37, 6654522])
+@pytest.mark.parametrize("m", [1, 2, 3, 64, 512, 513, 5209, 70001, 131072, 131073 + 4096 * 37, 6654522])
 def test_permutation(ctx, m):
     for seed, t in [(42, 0), (7, 13)]:
         print("perm m=%d seed=%d t=%d" % (m, seed, t), flush=True)
         got = ctx.permutation(m, seed, t).cpu().numpy().view(np.uint32)
         assert np.array_equal(got, oracle.permutation(m, seed, t))
+
+
+def test_hub_key_partition_fallback(ctx):
+    """A few vertices of huge degree: one target key gets thousands of
+    inserters, so its partition exceeds the LDS capacity."""
+    n = 4000
+    hubs = [(a, b) for a in range(6) for b in range(6, n) if (a + b) % 3 != 0]
+    E = keys(hubs)
+    st, steps = check_run(ctx, E, n, 3, 0, 3, label="hubs")
+    check_run(ctx, E, n, 4, 0, 2, pl=1 << 31, label="hubs_pl")
 
 
 def test_permutation_small_buckets_and_fallback(ctx):
@@ -86,7 +112,7 @@ def test_permutation_small_buckets_and_fallback(ctx):
     try:
         m = 50000
         exp = oracle.permutation(m, 3, 5)
-        for avg, cap in [(64, 3072), (64, 64), (2560, 64), (300, 256)]:
+        for avg, cap in [(64, 1024), (64, 64), (768, 64), (300, 256)]:
             c.set_option(gesmc.OPT_BUCKET_AVG, avg)
             c.set_option(gesmc.OPT_SORT_CAP, cap)
             got = c.permutation(m, 3, 5).cpu().numpy().view(np.uint32)
@@ -108,7 +134,7 @@ def test_superstep_outcomes(ctx):
     for (E, n), pl in [(graphgen.workload_gnp_small(), 0), ((graphgen.powerlaw_graph(20000, 2.1, 2, 141, 9), 20000), 1 << 30)]:
         for t in (0, 5):
             out, oc, step = ctx.superstep_outcomes(to_dev(E), n, 11, t, pl)
-            rc, exp, counts, exp_oc = oracle.run(E, n, 11, t, 1, pl, outcomes=True)
+            rc, exp, counts, exp_oc = oracle_run(E, n, 11, t, 1, pl, outcomes=True)
             assert np.array_equal(to_host(out), exp)
             assert np.array_equal(oc.cpu().numpy(), exp_oc)
 
@@ -169,9 +195,11 @@ def test_schedule_independence(ctx):
     E = graphgen.powerlaw_graph(40000, 2.05, 1, 400, 21)
     n = 40000
     ref = None
-    for avg, cap, fr in [(2560, 3072, 4), (64, 3072, 0), (256, 64, 1), (1000, 512, 8), (2560, 3072, 0)]:
+    for avg, cap, fr, strat in [(512, 1024, 4, 0), (64, 1024, 0, 0), (256, 64, 1, 0), (700, 512, 8, 0),
+                                (768, 1024, 0, 1), (64, 64, 3, 1), (128, 96, 2, 0)]:
         c = gesmc.Context(0)
         try:
+            c.set_option(gesmc.OPT_STRATEGY, strat)
             c.set_option(gesmc.OPT_BUCKET_AVG, avg)
             c.set_option(gesmc.OPT_SORT_CAP, cap)
             c.set_option(gesmc.OPT_FAST_ROUNDS, fr)
@@ -179,9 +207,9 @@ def test_schedule_independence(ctx):
             got = to_host(out)
             if ref is None:
                 ref = got
-                rc, exp, _, _ = oracle.run(E, n, 77, 2, 5)
+                rc, exp, _, _ = oracle_run(E, n, 77, 2, 5)
                 assert np.array_equal(got, exp)
-            assert np.array_equal(got, ref), (avg, cap, fr)
+            assert np.array_equal(got, ref), (avg, cap, fr, strat)
         finally:
             c.close()
 
