@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-supersteps", type=int, default=3)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
+                    help="library option (e.g. PERSIST=2, STRATEGY=1); results never depend on options")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
     args = ap.parse_args()
@@ -131,6 +133,9 @@ def main():
     ell = m // 2
     dev = torch.device("cuda", 0)
     ctx = gesmc.Context(0)
+    for opt in args.option:
+        name, val = opt.split("=")
+        ctx.set_option(getattr(gesmc, "OPT_" + name.upper()), int(val))
     d_in = torch.from_numpy(E.view(np.int64).copy()).to(dev)
     d_out = torch.empty_like(d_in)
     stream = torch.cuda.current_stream()
@@ -201,7 +206,7 @@ def main():
                    "attempts_per_step": r * ell, "seed": args.seed, "pl": 0, "mode": "plain",
                    "legal_fraction": round(stats["legal"] / max(stats["attempts"], 1), 5) if stats else None,
                    "rounds_max": stats["rounds_max"] if stats else None,
-                   "event_timing": not args.no_profile},
+                   "event_timing": not args.no_profile, "options": args.option},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -118,6 +118,8 @@ gesmc_status gesmc_permutation(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_
 #define GESMC_OPT_STRATEGY 5    /* dependency resolution: 0 = tuples sorted by edge key per hash
                                    partition in LDS (default); 1 = one open-addressing table in HBM
                                    rebuilt every superstep with device-scope atomics               */
+#define GESMC_OPT_PERSIST 6     /* workgroups of the tile/bucket kernels: resident count x value;
+                                   0 = one workgroup per tile or bucket (default 0)                */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgesmc.so")
 
 OK = 0
 E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_INTERNAL = -1, -2, -3, -4, -5, -9
-OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY = 1, 2, 3, 4, 5
+OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST = 1, 2, 3, 4, 5, 6
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 

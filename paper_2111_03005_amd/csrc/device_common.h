@@ -18,6 +18,15 @@ namespace gesmc {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// fences global memory, which makes every wave wait for its outstanding
+// global loads -- including loads issued early to prefetch the next tile.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10
 // ---------------------------------------------------------------------------

@@ -28,11 +28,11 @@ void set_error(const char *fmt, ...) {
 
 enum KernelId {
     KID_LOAD,
-    KID_HIST_CLEAR,
-    KID_SCAN_COARSE,
+    KID_STEP_CLEAR,
+    KID_COUNTS1,
     KID_SCATTER1,
-    KID_HIST_SUB,
-    KID_SCAN_FINE,
+    KID_COUNTS2,
+    KID_SCAN,
     KID_SCATTER2,
     KID_SORT,
     KID_BUILD,
@@ -45,8 +45,9 @@ enum KernelId {
     KID_VALIDATE,
     KID_MISC,
     KID_EMIT,
+    KID_TCOUNTS1,
     KID_TSCATTER1,
-    KID_THIST_SUB,
+    KID_TCOUNTS2,
     KID_TSCATTER2,
     KID_RESOLVE,
     KID_DECIDE_CHAIN1,
@@ -56,11 +57,11 @@ enum KernelId {
 };
 
 const char *kKernelNames[KID_COUNT] = {
-    "k_load",        "k_hist_clear",  "k_scan_coarse", "k_scatter1",      "k_hist_sub",   "k_scan_fine",
-    "k_scatter2",    "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
-    "k_round_decide", "k_finish",     "k_unpermute",   "k_validate",      "k_misc",
-    "k_emit",        "k_tscatter1",   "k_thist_sub",   "k_tscatter2",     "k_resolve",    "k_decide_chain1",
-    "k_decide_chain", "k_finish_chain"};
+    "k_load",         "k_step_clear",   "k_counts1",    "k_scatter1",      "k_counts2",     "k_scan",
+    "k_scatter2",     "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
+    "k_round_decide", "k_finish",       "k_unpermute",  "k_validate",      "k_misc",
+    "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
+    "k_decide_chain1", "k_decide_chain", "k_finish_chain"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -100,6 +101,7 @@ struct gesmc_ctx {
     uint32_t bucket_avg = (1u << kSortSubBits) / 2;
     uint32_t sort_cap = 1u << kSortSubBits;
     int fast_rounds = 2;
+    int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
     // device buffers (capacity in edges)
@@ -116,14 +118,16 @@ struct gesmc_ctx {
     uint32_t *tu_tag[3] = {nullptr, nullptr, nullptr};
     unsigned long long *tu_key[3] = {nullptr, nullptr, nullptr};
     uint2 *info = nullptr;
+    // radix bookkeeping: per-tile digit counts / run bases of both levels, chunk sums
+    uint64_t cap_counts1 = 0, cap_counts2 = 0, cap_partial = 0;
+    uint32_t *counts1 = nullptr, *counts2 = nullptr, *partial = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
     uint64_t ctr_cap = 0;
     // views into `small`
-    uint32_t *err = nullptr, *ucount = nullptr, *coarse_hist = nullptr, *coarse_off = nullptr,
-             *coarse_cursor = nullptr, *tile_first = nullptr, *lvl1_seg = nullptr, *lvl1_tiles = nullptr,
-             *fine_hist = nullptr, *fine_off = nullptr, *fine_cursor = nullptr;
+    uint32_t *err = nullptr, *ucount = nullptr, *coarse_off = nullptr, *tile_first = nullptr,
+             *lvl1_seg = nullptr, *lvl1_tiles = nullptr, *fine_off = nullptr;
     // host staging (pinned)
     uint32_t *h_err = nullptr;
     StepCounters *h_ctr = nullptr;
@@ -170,6 +174,11 @@ void free_buffers(gesmc_ctx *c) {
     }
     if (c->info) (void)hipFree(c->info);
     c->info = nullptr;
+    for (uint32_t **pp : {&c->counts1, &c->counts2, &c->partial}) {
+        if (*pp) (void)hipFree(*pp);
+        *pp = nullptr;
+    }
+    c->cap_counts1 = c->cap_counts2 = c->cap_partial = 0;
     c->cap_tu = 0;
     c->tab = nullptr;
     c->sw_slot = nullptr;
@@ -292,19 +301,20 @@ struct Plan {
     uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1;
 };
 
+// Radix plan for n records: B bucket bits (mean bucket <= bucket_avg), split
+// into a coarse level of <= 8 bits and a second level of the rest.
 Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     Plan p;
     p.m = m;
     p.ell = m / 2;
     uint32_t B = 0;
     while (B < kMaxFineBits && ((uint64_t)c->bucket_avg << B) < m) ++B;
-    // (for tuple partitions `m` is the number of tuple slots)
     p.bbits = B;
     p.b1 = std::min<uint32_t>(B, 8);
     p.b2 = B - p.b1;
     p.ncoarse = 1u << p.b1;
     p.nfine = 1u << B;
-    p.ntiles1 = ceil_div(m, kScatterTile);
+    p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, kScatterTile));
     return p;
 }
 
@@ -323,10 +333,93 @@ size_t resolve_lds_bytes(uint32_t cap) {
     return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 12;
 }
 
+// Workgroups of a persistent kernel: as many as can be resident at once
+// (occupancy query for its LDS size), never more than the work units.
+template <typename Kern>
+uint32_t persistent_blocks(const gesmc_ctx *c, Kern kern, size_t lds, uint64_t units) {
+    if (c->persist_mult == 0) return (uint32_t)std::max<uint64_t>(1, units);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    const uint64_t want = (uint64_t)per_cu * c->num_cus * c->persist_mult;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, units));
+}
+
 uint32_t grid_stride_blocks(const gesmc_ctx *c, uint64_t work) {
     const uint64_t want = (work + kBlock - 1) / kBlock;
     const uint64_t cap = (uint64_t)c->num_cus * 8;
     return (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+}
+
+// Grows a word buffer of the radix bookkeeping.
+gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
+    if (want <= *cap && *p) return GESMC_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    GESMC_TRY(dev_alloc((void **)p, std::max<uint64_t>(want, 1024) * 4));
+    *cap = std::max<uint64_t>(want, 1024);
+    return GESMC_OK;
+}
+
+// Two-level MSD radix distribution of the n records (idx/tag, key) in buffer
+// set `src` into `dst` (one level) or via `mid` into `dst` (two levels), by
+// the radix word of kByKeyHash.  Leaves c->coarse_off / c->fine_off as the
+// bucket boundaries; returns the buffer index holding the result in *out.
+template <bool kByKeyHash>
+gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
+                              uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
+                              int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
+                              int kid_scatter1, int kid_counts2, int kid_scatter2) {
+    const uint32_t nd1 = 1u << p.b1;
+    const uint32_t nchunks = ceil_div(p.ntiles1, kScanChunk);
+    GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
+    GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, (uint64_t)nchunks * nd1));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, n,
+                     p.ntiles1));
+    const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;
+    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kByKeyHash>,
+                     dim3(persistent_blocks(c, k_tile_counts<kByKeyHash>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
+                     (size_t)nd1 * 4, idx[src], key[src], t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
+                     c->lvl1_tiles, c->counts1));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1, (int)p.b1,
+                     c->partial));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kBlock), 0, c->partial, nchunks, (int)p.b1,
+                     c->coarse_off, c->tile_first));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1,
+                     (int)p.b1, c->partial, c->coarse_off));
+    const int lvl1_out = p.b2 > 0 ? mid : dst;
+    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kByKeyHash>,
+                     dim3(persistent_blocks(c, k_scatter<kByKeyHash>, scatter_lds_bytes(p.b1), p.ntiles1)),
+                     dim3(kBlock), scatter_lds_bytes(p.b1), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0, k1, shift1,
+                     (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err));
+    if (p.b2 == 0) {
+        *out = dst;
+        *bucket_off = c->coarse_off;
+        *nbuckets = p.ncoarse;
+        return GESMC_OK;
+    }
+    const uint32_t nd2 = 1u << p.b2;
+    const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
+    GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
+    const int shift2 = 64 - (int)p.bbits;
+    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kByKeyHash>,
+                     dim3(persistent_blocks(c, k_tile_counts<kByKeyHash>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
+                     (size_t)nd2 * 4,
+                     idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
+                     c->counts2));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
+                     c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kByKeyHash>,
+                     dim3(persistent_blocks(c, k_scatter<kByKeyHash>, scatter_lds_bytes(p.b2), tiles2)),
+                     dim3(kBlock), scatter_lds_bytes(p.b2), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+                     p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err));
+    *out = dst;
+    *bucket_off = c->fine_off;
+    *nbuckets = p.nfine;
+    return GESMC_OK;
 }
 
 // Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t.
@@ -335,84 +428,48 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
                      int *sorted_out, bool clear_table) {
     const uint32_t m = p.m;
     const int X = (src + 1) % 3, Y = (src + 2) % 3;
-    GESMC_TRY(launch(c, s, KID_HIST_CLEAR, m, k_hist_clear, dim3(grid_stride_blocks(c, std::max<uint64_t>(m, clear_table ? c->tab_slots : 0))),
-                     dim3(kBlock), 0, m, t, k0, k1, (int)p.b1, c->coarse_hist, c->tab,
-                     clear_table ? c->tab_slots : (uint64_t)0, c->st, p.ell, c->ucount));
-    GESMC_TRY(launch(c, s, KID_SCAN_COARSE, p.ncoarse, k_scan_coarse, dim3(1), dim3(kBlock), 0, p.ncoarse,
-                     c->coarse_hist, c->coarse_off, c->coarse_cursor, c->tile_first));
+    const uint64_t tslots = clear_table ? c->tab_slots : 0;
+    GESMC_TRY(launch(c, s, KID_STEP_CLEAR, tslots, k_step_clear,
+                     dim3(grid_stride_blocks(c, std::max<uint64_t>(p.ell, tslots) + 1)), dim3(kBlock), 0, c->tab,
+                     tslots, c->st, p.ell, c->ucount));
     const size_t sort_lds = sort_lds_bytes(c->sort_cap);
     if (p.bbits == 0) {
         // one bucket: sort src -> X (scratch keys in Y)
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, m,
+                         p.ntiles1));
         GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(1), dim3(kBlock), sort_lds, c->idx[src], c->key[src],
-                         c->idx[X], c->key[X], c->key[Y], t, k0, k1, 0, c->coarse_off, m, c->sort_cap, c->ctr_step));
+                         c->idx[X], c->key[X], c->key[Y], t, k0, k1, 0, (const uint32_t *)c->lvl1_seg, 1u, m,
+                         c->sort_cap, c->ctr_step));
         *sorted_out = X;
         return GESMC_OK;
     }
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, m,
-                     p.ntiles1));
-    GESMC_TRY(launch(c, s, KID_SCATTER1, m, k_scatter<false>, dim3(p.ntiles1), dim3(kBlock), scatter_lds_bytes(p.b1),
-                     c->idx[src], c->key[src], c->idx[X], c->key[X], t, k0, k1, 64 - (int)p.b1, (int)p.b1, 1u,
-                     c->lvl1_seg, c->lvl1_tiles, c->coarse_cursor, c->err));
-    if (p.b2 == 0) {
-        GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(p.nfine), dim3(kBlock), sort_lds, c->idx[X],
-                         c->key[X], c->idx[Y], c->key[Y], c->key[src], t, k0, k1, (int)p.bbits, c->coarse_off, m,
-                         c->sort_cap, c->ctr_step));
-        *sorted_out = Y;
-        return GESMC_OK;
-    }
-    const uint32_t tiles2 = p.ntiles1 + p.ncoarse;
-    GESMC_TRY(launch(c, s, KID_HIST_SUB, m, k_hist_sub<false>, dim3(tiles2), dim3(kBlock), ((size_t)1 << p.b2) * 4,
-                     c->idx[X], c->key[X], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
-                     c->fine_hist));
-    GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(p.ncoarse), dim3(kBlock),
-                     (((size_t)1 << p.b2) + kBlock + 1) * 4, (int)p.b2, c->coarse_off, p.ncoarse, c->fine_hist,
-                     c->fine_off, c->fine_cursor));
-    GESMC_TRY(launch(c, s, KID_SCATTER2, m, k_scatter<false>, dim3(tiles2), dim3(kBlock), scatter_lds_bytes(p.b2),
-                     c->idx[X], c->key[X], c->idx[Y], c->key[Y], t, k0, k1, 64 - (int)p.bbits, (int)p.b2, p.ncoarse,
-                     c->coarse_off, c->tile_first, c->fine_cursor, c->err));
-    GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(p.nfine), dim3(kBlock), sort_lds, c->idx[Y], c->key[Y],
-                     c->idx[X], c->key[X], c->key[src], t, k0, k1, (int)p.bbits, c->fine_off, m, c->sort_cap,
-                     c->ctr_step));
-    *sorted_out = X;
+    int dist = 0;
+    const uint32_t *boff = nullptr;
+    uint32_t nb = 0;
+    GESMC_TRY(radix_distribute<false>(c, s, p, m, t, k0, k1, c->idx, c->key, src, X, p.b2 > 0 ? Y : X, &dist, &boff,
+                                      &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2, KID_SCATTER2));
+    const int sorted = (dist == X) ? Y : X;  // sort into the buffer not holding the buckets
+    GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(persistent_blocks(c, k_sort_buckets, sort_lds, nb)),
+                     dim3(kBlock), sort_lds, c->idx[dist], c->key[dist], c->idx[sorted], c->key[sorted], c->key[src],
+                     t, k0, k1, (int)p.bbits, boff, nb, m, c->sort_cap, c->ctr_step));
+    *sorted_out = sorted;
     return GESMC_OK;
 }
 
 // Partitions the tuples in tuple buffer 0 (nslots slots, empty keys dropped)
-// by key hash and resolves every partition.  `records` sizes the partitions.
+// by key hash and resolves every partition.
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit) {
     const Plan p = make_plan(c, nslots);
-    GESMC_TRY(launch(c, s, KID_SCAN_COARSE, p.ncoarse, k_scan_coarse, dim3(1), dim3(kBlock), 0, p.ncoarse,
-                     c->coarse_hist, c->coarse_off, c->coarse_cursor, c->tile_first));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, nslots,
-                     p.ntiles1));
-    const int shift1 = 64 - (int)(p.b1 > 0 ? p.b1 : 1);
-    GESMC_TRY(launch(c, s, KID_TSCATTER1, nslots, k_scatter<true>, dim3(p.ntiles1), dim3(kBlock),
-                     scatter_lds_bytes(p.b1), c->tu_tag[0], c->tu_key[0], c->tu_tag[1], c->tu_key[1], 0u, 0u, 0u,
-                     p.b1 > 0 ? 64 - (int)p.b1 : shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles,
-                     c->coarse_cursor, c->err));
-    int parts = 1, scratch = 0;
-    const uint32_t *part_off = c->coarse_off;
-    uint32_t nparts = p.ncoarse;
-    if (p.b2 > 0) {
-        const uint32_t tiles2 = p.ntiles1 + p.ncoarse;
-        GESMC_TRY(launch(c, s, KID_THIST_SUB, nslots, k_hist_sub<true>, dim3(tiles2), dim3(kBlock),
-                         ((size_t)1 << p.b2) * 4, c->tu_tag[1], c->tu_key[1], 0u, 0u, 0u, 64 - (int)p.bbits,
-                         (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_hist));
-        GESMC_TRY(launch(c, s, KID_SCAN_FINE, p.nfine, k_scan_fine, dim3(p.ncoarse), dim3(kBlock),
-                         (((size_t)1 << p.b2) + kBlock + 1) * 4, (int)p.b2, c->coarse_off, p.ncoarse, c->fine_hist,
-                         c->fine_off, c->fine_cursor));
-        GESMC_TRY(launch(c, s, KID_TSCATTER2, nslots, k_scatter<true>, dim3(tiles2), dim3(kBlock),
-                         scatter_lds_bytes(p.b2), c->tu_tag[1], c->tu_key[1], c->tu_tag[2], c->tu_key[2], 0u, 0u, 0u,
-                         64 - (int)p.bbits, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_cursor,
-                         c->err));
-        parts = 2;
-        scratch = 1;
-        part_off = c->fine_off;
-        nparts = p.nfine;
-    }
-    GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(nparts), dim3(kBlock), resolve_lds_bytes(c->sort_cap),
-                     c->tu_tag[parts], c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.bbits,
-                     part_off, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step));
+    int parts = 0;
+    const uint32_t *poff = nullptr;
+    uint32_t np = 0;
+    GESMC_TRY(radix_distribute<true>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1,
+                                     &parts, &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2));
+    const int scratch = parts == 2 ? 1 : 0;
+    const size_t rlds = resolve_lds_bytes(c->sort_cap);
+    GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(persistent_blocks(c, k_resolve, rlds, np)),
+                     dim3(kBlock), rlds, c->tu_tag[parts], c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch],
+                     (int)p.bbits, poff, np, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step));
     return GESMC_OK;
 }
 
@@ -424,10 +481,9 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
-    const Plan tp = make_plan(c, nslots);
     GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(grid_stride_blocks(c, (uint64_t)p.ell + 1)), dim3(kBlock), 0, si,
                      sk, p.m, t, k0, k1, pl, c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0],
-                     (int)tp.b1, c->coarse_hist, c->ctr_step));
+                     c->ctr_step));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(ceil_div(p.ell, kBlock)), dim3(kBlock), 0,
@@ -557,18 +613,14 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     if (m >= 2 && r == 0) {
         c->ctr_step = c->ctr;
         if (c->strategy == 1) {
-            GESMC_TRY(launch(c, s, KID_HIST_CLEAR, c->tab_slots, k_hist_clear,
-                             dim3(grid_stride_blocks(c, c->tab_slots)), dim3(kBlock), 0, 0u, 0u, k0, k1, 0,
-                             c->coarse_hist, c->tab, c->tab_slots, c->st, 0u, c->ucount));
-            GESMC_TRY(launch(c, s, KID_SCAN_COARSE, 1, k_scan_coarse, dim3(1), dim3(kBlock), 0, 1u, c->coarse_hist,
-                             c->coarse_off, c->coarse_cursor, c->tile_first));
+            GESMC_TRY(launch(c, s, KID_STEP_CLEAR, c->tab_slots, k_step_clear,
+                             dim3(grid_stride_blocks(c, c->tab_slots)), dim3(kBlock), 0, c->tab, c->tab_slots, c->st,
+                             0u, c->ucount));
             GESMC_TRY(launch(c, s, KID_VALIDATE, m, k_validate, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
                              c->key[0], m, c->tab, nslots, c->err));
         } else {
-            const Plan vp = make_plan(c, m);
             GESMC_TRY(launch(c, s, KID_EMIT, m, k_emit_sources, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
-                             (const unsigned long long *)c->key[0], m, c->tu_tag[0], c->tu_key[0], (int)vp.b1,
-                             c->coarse_hist));
+                             (const unsigned long long *)c->key[0], m, c->tu_tag[0], c->tu_key[0]));
             GESMC_TRY(partition_and_resolve(c, s, m, ERR_DUP));
         }
     }
@@ -651,9 +703,9 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
-    // fixed-size area: err[16], ucount[16], coarse hist/off/cursor/tiles, level-1 segments, fine hist/off/cursor
+    // fixed-size area: err[16], ucount[16], coarse offsets / tile map, level-1 segment, fine offsets
     const size_t nf = (size_t)1 << kMaxFineBits;
-    const size_t words = 16 + 16 + 4 * 264 + 8 + 3 * (nf + 8);
+    const size_t words = 16 + 16 + 2 * 264 + 8 + (nf + 8);
     if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK || dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK) {
         gesmc_destroy(c);
         return GESMC_E_NOMEM;
@@ -664,11 +716,7 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     w += 16;
     c->ucount = w;
     w += 16;
-    c->coarse_hist = w;
-    w += 264;
     c->coarse_off = w;
-    w += 264;
-    c->coarse_cursor = w;
     w += 264;
     c->tile_first = w;
     w += 264;
@@ -676,11 +724,7 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     w += 4;
     c->lvl1_tiles = w;
     w += 4;
-    c->fine_hist = w;
-    w += nf + 8;
     c->fine_off = w;
-    w += nf + 8;
-    c->fine_cursor = w;
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sort_lds_bytes(kSortMaxItems * kBlock));
@@ -810,6 +854,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_PERSIST:
+            if (v < 0 || v > 64) break;
+            c->persist_mult = (int)v;
             return GESMC_OK;
         case GESMC_OPT_STRATEGY:
             if (v < 0 || v > 1) break;

@@ -4,7 +4,8 @@
 // Philox key of edge index i in superstep t.
 //
 // MSD radix layout for gfx950:
-//   level 1   : coarse digit = top b1 bits of K (b1 <= 8), LDS-staged scatter
+//   level 1   : coarse digit = top b1 bits of K (b1 <= 8), LDS-staged scatter;
+//               run bases from per-tile digit counts and a column scan
 //   level 2   : sub digit    = next b2 bits, scattered inside each coarse
 //               bucket (its region is small enough to stay L2/MALL resident)
 //   bucket    : each fine bucket (~0.5-1k records) is counting-sorted in LDS
@@ -47,7 +48,7 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t *ws
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t incl = wave_inclusive_scan(x);
     if (lane == 63) wsum[w] = incl;
-    __syncthreads();
+    lds_barrier();
     uint32_t before = 0, all = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
@@ -55,7 +56,7 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t *ws
         before += (q < (int)w) ? v : 0u;
         all += v;
     }
-    __syncthreads();
+    lds_barrier();
     *total = all;
     return before + incl - x;
 }
@@ -77,104 +78,26 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, uint32_t n
         v[q] = acc;
         acc += x;
     }
-    __syncthreads();
+    lds_barrier();
     return total;
 }
 
 // ---------------------------------------------------------------------------
-// Histogram of the coarse digit over all edge indices i in [0, m) -- the set
-// of indices is the same every superstep, so nothing is read -- fused with
-// the per-superstep reset of the dependency table and switch states.
+// Per-superstep reset: switch states, list counters and (table strategy only)
+// the dependency table.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_hist_clear(uint32_t m, uint32_t t, uint32_t k0, uint32_t k1, int b1,
-                                                       uint32_t *__restrict__ coarse_hist, Slot *__restrict__ tab,
-                                                       uint64_t tab_slots, uint8_t *__restrict__ st, uint32_t ell,
+__global__ __launch_bounds__(kBlock) void k_step_clear(Slot *__restrict__ tab, uint64_t tab_slots,
+                                                       uint8_t *__restrict__ st, uint32_t ell,
                                                        uint32_t *__restrict__ ucount) {
-    __shared__ uint32_t h[256];
-    const uint32_t tid = threadIdx.x;
-    h[tid] = 0;
-    __syncthreads();
     const uint64_t nthreads = (uint64_t)gridDim.x * kBlock;
-    const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + tid;
-    if (b1 > 0) {
-        const int shift = 64 - b1;
-        for (uint64_t i = gtid; i < m; i += nthreads) {
-            const uint64_t K = perm_key((uint32_t)i, t, k0, k1);
-            atomicAdd(&h[(uint32_t)(K >> shift)], 1u);
-        }
-    } else if (gtid == 0) {
-        atomicAdd(&h[0], m);
-    }
+    const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     // table reset: 16-byte vector stores of {empty key, no eraser, no claim}
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     u32x4 *t4 = reinterpret_cast<u32x4 *>(tab);
     const u32x4 empty = {0xFFFFFFFFu, 0xFFFFFFFFu, kNoEraser, kClaimNone};
     for (uint64_t s = gtid; s < tab_slots; s += nthreads) __builtin_nontemporal_store(empty, &t4[s]);
     for (uint64_t k = gtid; k < ell; k += nthreads) st[k] = ST_UNDECIDED;
-    if (gtid == 0) {
-        ucount[0] = 0;
-        ucount[1] = 0;
-        ucount[2] = 0;
-    }
-    __syncthreads();
-    if (b1 > 0) {
-        for (uint32_t d = tid; d < (1u << b1); d += kBlock)
-            if (h[d]) atomicAdd(&coarse_hist[d], h[d]);
-    } else if (tid == 0) {
-        atomicAdd(&coarse_hist[0], h[0]);
-    }
-}
-
-// Coarse scan (one workgroup): coarse offsets, level-1 cursors, and the
-// level-2 tile map (tiles of kScatterTile records inside each coarse bucket).
-// Clears the histogram for the next superstep.
-__global__ __launch_bounds__(kBlock) void k_scan_coarse(uint32_t ncoarse, uint32_t *__restrict__ coarse_hist,
-                                                        uint32_t *__restrict__ coarse_off,
-                                                        uint32_t *__restrict__ coarse_cursor,
-                                                        uint32_t *__restrict__ tile_first) {
-    __shared__ uint32_t v[257], w[257], tmp[kBlock + 1];
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t d = tid; d < ncoarse; d += kBlock) {
-        v[d] = coarse_hist[d];
-        w[d] = (v[d] + kScatterTile - 1) / kScatterTile;
-        coarse_hist[d] = 0;
-    }
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan(v, ncoarse, tmp);
-    const uint32_t tiles = block_exclusive_scan(w, ncoarse, tmp);
-    for (uint32_t d = tid; d < ncoarse; d += kBlock) {
-        coarse_off[d] = v[d];
-        coarse_cursor[d] = v[d];
-        tile_first[d] = w[d];
-    }
-    if (tid == 0) {
-        coarse_off[ncoarse] = total;
-        tile_first[ncoarse] = tiles;
-    }
-}
-
-// Fine scan, one workgroup per coarse segment s: the 2^dbits sub-counts of s
-// (in LDS) scanned and offset by the segment's start give the fine offsets
-// and cursors; the histogram is cleared for the next use.
-__global__ __launch_bounds__(kBlock) void k_scan_fine(int dbits, const uint32_t *__restrict__ coarse_off,
-                                                      uint32_t ncoarse, uint32_t *__restrict__ fine_hist,
-                                                      uint32_t *__restrict__ fine_off,
-                                                      uint32_t *__restrict__ fine_cursor) {
-    extern __shared__ uint32_t v[];  // 2^dbits + kBlock + 1
-    uint32_t *tmp = v + (1u << dbits);
-    const uint32_t s = blockIdx.x, nd = 1u << dbits, base = s << dbits;
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
-        v[d] = fine_hist[base + d];
-        fine_hist[base + d] = 0;
-    }
-    __syncthreads();
-    block_exclusive_scan(v, nd, tmp);
-    const uint32_t off = coarse_off[s];
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
-        fine_off[base + d] = off + v[d];
-        fine_cursor[base + d] = off + v[d];
-    }
-    if (s == ncoarse - 1 && threadIdx.x == 0) fine_off[ncoarse << dbits] = coarse_off[ncoarse];
+    if (gtid < 3) ucount[gtid] = 0;
 }
 
 // Locates the segment of tile w: the largest s with tile_first[s] <= w.
@@ -201,39 +124,221 @@ __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long 
     return perm_key(idx, t, k0, k1);
 }
 
-// Level-2 histogram: sub digit counts of each coarse segment, per tile in LDS,
-// added into the global fine histogram.
+// ---------------------------------------------------------------------------
+// Atomic-free radix bookkeeping.  Every scatter tile w of a segment counts
+// its records per digit and writes the row counts[w][0..nd) (tile-major).
+// A column scan turns the rows into run bases: the records of digit d from
+// tile w go to [offs[w][d], offs[w][d] + counts[w][d]), i.e. after all
+// records of smaller digits and after digit d's records of earlier tiles of
+// the same segment.  No global atomics are needed (device-scope atomics are
+// executed memory-side on gfx950).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kScanChunk = 256;  // tiles per chunk of the level-1 column scan
+
+struct TileSpan {
+    uint32_t seg, seg_begin, seg_end, begin, cnt;
+};
+
+__device__ __forceinline__ TileSpan tile_span(const uint32_t *seg_off, const uint32_t *tile_first, uint32_t nseg,
+                                              uint32_t w) {
+    TileSpan ts;
+    ts.seg = tile_segment(tile_first, nseg, w);
+    ts.seg_begin = seg_off[ts.seg];
+    ts.seg_end = seg_off[ts.seg + 1];
+    ts.begin = ts.seg_begin + (w - tile_first[ts.seg]) * kScatterTile;
+    const uint32_t end = min(ts.begin + kScatterTile, ts.seg_end);
+    ts.cnt = end > ts.begin ? end - ts.begin : 0;
+    return ts;
+}
+
+constexpr int kTileItems = kScatterTile / kBlock;
+
+// Tiles are processed by persistent workgroups; the records of the next
+// tile are loaded into registers while the current one is counted.
 template <bool kByKeyHash>
-__global__ __launch_bounds__(kBlock) void k_hist_sub(const uint32_t *__restrict__ src_idx,
-                                                     const unsigned long long *__restrict__ src_key, uint32_t t,
-                                                     uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
-                                                     const uint32_t *__restrict__ seg_off,
-                                                     const uint32_t *__restrict__ tile_first,
-                                                     uint32_t *__restrict__ fine_hist) {
+__global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restrict__ src_idx,
+                                                        const unsigned long long *__restrict__ src_key, uint32_t t,
+                                                        uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
+                                                        const uint32_t *__restrict__ seg_off,
+                                                        const uint32_t *__restrict__ tile_first,
+                                                        uint32_t *__restrict__ counts) {
     extern __shared__ uint32_t hs[];
-    const uint32_t w = blockIdx.x;
-    if (w >= tile_first[nseg]) return;
-    const uint32_t s = tile_segment(tile_first, nseg, w);
-    const uint32_t begin = seg_off[s] + (w - tile_first[s]) * kScatterTile;
-    const uint32_t end = min(begin + kScatterTile, seg_off[s + 1]);
-    const uint32_t nd = 1u << dbits, dmask = nd - 1;
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) hs[d] = 0;
-    __syncthreads();
-    for (uint32_t p = begin + threadIdx.x; p < end; p += kBlock) {
-        const uint64_t K = kByKeyHash ? radix_word<true>(0, src_key[p], t, k0, k1)
-                                      : radix_word<false>(src_idx[p], 0, t, k0, k1);
-        atomicAdd(&hs[(uint32_t)(K >> shift) & dmask], 1u);
+    const uint32_t nt = tile_first[nseg];
+    const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
+    uint32_t w = blockIdx.x;
+    if (w >= nt) return;
+    TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
+    uint32_t cur_i[kTileItems];
+    unsigned long long cur_k[kTileItems];
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const uint32_t p = tid + q * kBlock;
+        if (kByKeyHash)
+            cur_k[q] = p < ts.cnt ? src_key[ts.begin + p] : kEmptyKey;
+        else
+            cur_i[q] = p < ts.cnt ? src_idx[ts.begin + p] : 0u;
+    }
+    for (;;) {
+        const uint32_t wn = w + gridDim.x;
+        TileSpan tn = ts;
+        uint32_t nxt_i[kTileItems];
+        unsigned long long nxt_k[kTileItems];
+        if (wn < nt) {
+            tn = tile_span(seg_off, tile_first, nseg, wn);
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (kByKeyHash)
+                    nxt_k[q] = p < tn.cnt ? src_key[tn.begin + p] : kEmptyKey;
+                else
+                    nxt_i[q] = p < tn.cnt ? src_idx[tn.begin + p] : 0u;
+            }
+        }
+        for (uint32_t d = tid; d < nd; d += kBlock) hs[d] = 0;
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            const uint32_t p = tid + q * kBlock;
+            if (p >= ts.cnt) continue;
+            if (kByKeyHash) {
+                if (cur_k[q] == kEmptyKey) continue;
+                atomicAdd(&hs[(uint32_t)(radix_word<true>(0, cur_k[q], t, k0, k1) >> shift) & dmask], 1u);
+            } else {
+                atomicAdd(&hs[(uint32_t)(radix_word<false>(cur_i[q], 0, t, k0, k1) >> shift) & dmask], 1u);
+            }
+        }
+        lds_barrier();
+        for (uint32_t d = tid; d < nd; d += kBlock) counts[(size_t)w * nd + d] = hs[d];
+        lds_barrier();
+        if (wn >= nt) break;
+        w = wn;
+        ts = tn;
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            if (kByKeyHash)
+                cur_k[q] = nxt_k[q];
+            else
+                cur_i[q] = nxt_i[q];
+        }
+    }
+}
+
+// Level-1 column scan, phase 1: per chunk of kScanChunk tiles, the column sums.
+__global__ __launch_bounds__(kBlock) void k_colsum(const uint32_t *__restrict__ counts, uint32_t ntiles, int dbits,
+                                                   uint32_t *__restrict__ partial) {
+    const uint32_t nd = 1u << dbits, b = blockIdx.x;
+    const uint32_t w0 = b * kScanChunk, w1 = min(w0 + kScanChunk, ntiles);
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        uint32_t acc = 0;
+#pragma unroll 8
+        for (uint32_t w = w0; w < w1; ++w) acc += counts[(size_t)w * nd + d];
+        partial[(size_t)b * nd + d] = acc;
+    }
+}
+
+// Phase 2 (one workgroup): exclusive scan of the chunk sums per digit, digit
+// totals -> digit bases (the coarse offsets), and the level-2 tile map.
+__global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ partial, uint32_t nchunks, int dbits,
+                                                        uint32_t *__restrict__ coarse_off,
+                                                        uint32_t *__restrict__ tile_first) {
+    __shared__ uint32_t tot[257], tiles[257], tmp[kBlock + 1];
+    const uint32_t nd = 1u << dbits;
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        uint32_t run = 0;
+        for (uint32_t b0 = 0; b0 < nchunks; b0 += 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = (b0 + j < nchunks) ? partial[(size_t)(b0 + j) * nd + d] : 0u;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (b0 + j < nchunks) partial[(size_t)(b0 + j) * nd + d] = run;
+                run += x[j];
+            }
+        }
+        tot[d] = run;
+        tiles[d] = (run + kScatterTile - 1) / kScatterTile;
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock)
-        if (hs[d]) atomicAdd(&fine_hist[(s << dbits) | d], hs[d]);
+    uint32_t total_tiles;
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) tmp[d] = 0;
+    const uint32_t total = block_exclusive_scan(tot, nd, tmp);
+    total_tiles = block_exclusive_scan(tiles, nd, tmp);
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        coarse_off[d] = tot[d];
+        tile_first[d] = tiles[d];
+    }
+    if (threadIdx.x == 0) {
+        coarse_off[nd] = total;
+        tile_first[nd] = total_tiles;
+    }
+}
+
+// Phase 3: run bases of every (tile, digit), in place of the counts.
+__global__ __launch_bounds__(kBlock) void k_colapply(uint32_t *__restrict__ counts, uint32_t ntiles, int dbits,
+                                                     const uint32_t *__restrict__ partial,
+                                                     const uint32_t *__restrict__ coarse_off) {
+    const uint32_t nd = 1u << dbits, b = blockIdx.x;
+    const uint32_t w0 = b * kScanChunk, w1 = min(w0 + kScanChunk, ntiles);
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        uint32_t run = coarse_off[d] + partial[(size_t)b * nd + d];
+        for (uint32_t wb = w0; wb < w1; wb += 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = (wb + j < w1) ? counts[(size_t)(wb + j) * nd + d] : 0u;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (wb + j < w1) counts[(size_t)(wb + j) * nd + d] = run;
+                run += x[j];
+            }
+        }
+    }
+}
+
+// Level-2 scan, one workgroup per coarse segment: sub-bucket totals -> fine
+// offsets, then run bases of the segment's tiles (in place of the counts).
+__global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ counts, int dbits, uint32_t nseg,
+                                                    const uint32_t *__restrict__ coarse_off,
+                                                    const uint32_t *__restrict__ tile_first,
+                                                    uint32_t *__restrict__ fine_off) {
+    extern __shared__ uint32_t v[];  // 2^dbits + kBlock + 1
+    uint32_t *tmp = v + (1u << dbits);
+    const uint32_t s = blockIdx.x, nd = 1u << dbits;
+    const uint32_t w0 = tile_first[s], w1 = tile_first[s + 1];
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        uint32_t acc = 0;
+#pragma unroll 8
+        for (uint32_t w = w0; w < w1; ++w) acc += counts[(size_t)w * nd + d];
+        v[d] = acc;
+    }
+    __syncthreads();
+    block_exclusive_scan(v, nd, tmp);
+    const uint32_t off = coarse_off[s];
+    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        uint32_t run = off + v[d];
+        fine_off[((size_t)s << dbits) + d] = run;
+        for (uint32_t wb = w0; wb < w1; wb += 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = (wb + j < w1) ? counts[(size_t)(wb + j) * nd + d] : 0u;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (wb + j < w1) counts[(size_t)(wb + j) * nd + d] = run;
+                run += x[j];
+            }
+        }
+    }
+    if (s == nseg - 1 && threadIdx.x == 0) fine_off[(size_t)nseg << dbits] = coarse_off[nseg];
 }
 
 // LDS-staged scatter of one tile of a segment by digit (K >> shift) & mask.
-// Records of one digit leave the workgroup as one contiguous run.  With
-// kByKeyHash, tuple slots whose key is empty are dropped.
-// Dynamic LDS: 3 * 2^dbits + 1 + kBlock + 1 words of counters, then the
-// staged records.
+// Records of one digit leave the workgroup as one contiguous run starting at
+// the run base offs[w][d].  With kByKeyHash, tuple slots whose key is empty
+// are dropped.  Persistent workgroups: the next tile's records and run bases
+// are loaded into registers while the current tile is staged in LDS.
+// Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then the staged
+// records.
+constexpr int kScatterOffRegs = 4;  // run bases prefetched per thread (2^dbits <= 1024)
+
 template <bool kByKeyHash>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
@@ -242,8 +347,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     uint32_t k1, int shift, int dbits, uint32_t nseg,
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ tile_first,
-                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ err) {
+                                                    const uint32_t *__restrict__ offs, uint32_t *__restrict__ err) {
     extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_total;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
@@ -254,84 +360,123 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         reinterpret_cast<unsigned long long *>(s_idx + kScatterTile + ((kBlock + 1 + 3 * nd + kScatterTile) & 1));
     uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kScatterTile);
 
-    const uint32_t w = blockIdx.x;
-    if (w >= tile_first[nseg]) return;
-    const uint32_t s = tile_segment(tile_first, nseg, w);
-    const uint32_t seg_begin = seg_off[s], seg_end = seg_off[s + 1];
-    const uint32_t begin = seg_begin + (w - tile_first[s]) * kScatterTile;
-    const uint32_t end = min(begin + kScatterTile, seg_end);
-    const uint32_t cnt_here = end > begin ? end - begin : 0;
+    const uint32_t nt = tile_first[nseg];
     const uint32_t tid = threadIdx.x;
+    uint32_t w = blockIdx.x;
+    if (w >= nt) return;
 
-    for (uint32_t d = tid; d < nd; d += kBlock) cnt[d] = 0;
-    __syncthreads();
-
-    constexpr int kItems = kScatterTile / kBlock;
-    uint32_t r_idx[kItems], r_dig[kItems], r_rank[kItems];
-    unsigned long long r_key[kItems];
+    TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
+    uint32_t c_idx[kTileItems], c_off[kScatterOffRegs];
+    unsigned long long c_key[kTileItems];
 #pragma unroll
-    for (int q = 0; q < kItems; ++q) {
+    for (int q = 0; q < kTileItems; ++q) {
         const uint32_t p = tid + q * kBlock;
-        r_dig[q] = 0xFFFFFFFFu;
-        if (p < cnt_here) {
-            r_idx[q] = src_idx[begin + p];
-            r_key[q] = src_key[begin + p];
-            if (!kByKeyHash || r_key[q] != kEmptyKey) {
-                const uint64_t K = radix_word<kByKeyHash>(r_idx[q], r_key[q], t, k0, k1);
+        c_idx[q] = p < ts.cnt ? src_idx[ts.begin + p] : 0u;
+        c_key[q] = p < ts.cnt ? src_key[ts.begin + p] : kEmptyKey;
+    }
+#pragma unroll
+    for (int j = 0; j < kScatterOffRegs; ++j) {
+        const uint32_t d = tid + j * kBlock;
+        c_off[j] = d < nd ? offs[(size_t)w * nd + d] : 0u;
+    }
+
+    for (;;) {
+        const uint32_t wn = w + gridDim.x;
+        TileSpan tn = ts;
+        uint32_t n_idx[kTileItems], n_off[kScatterOffRegs];
+        unsigned long long n_key[kTileItems];
+        if (wn < nt) {
+            tn = tile_span(seg_off, tile_first, nseg, wn);
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                n_idx[q] = p < tn.cnt ? src_idx[tn.begin + p] : 0u;
+                n_key[q] = p < tn.cnt ? src_key[tn.begin + p] : kEmptyKey;
+            }
+#pragma unroll
+            for (int j = 0; j < kScatterOffRegs; ++j) {
+                const uint32_t d = tid + j * kBlock;
+                n_off[j] = d < nd ? offs[(size_t)wn * nd + d] : 0u;
+            }
+        }
+
+        for (uint32_t d = tid; d < nd; d += kBlock) cnt[d] = 0;
+        if (tid == 0) s_total = 0;
+        lds_barrier();
+        uint32_t r_dig[kTileItems], r_rank[kTileItems];
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            const uint32_t p = tid + q * kBlock;
+            r_dig[q] = 0xFFFFFFFFu;
+            if (p < ts.cnt && (!kByKeyHash || c_key[q] != kEmptyKey)) {
+                const uint64_t K = radix_word<kByKeyHash>(c_idx[q], c_key[q], t, k0, k1);
                 r_dig[q] = (uint32_t)(K >> shift) & dmask;
                 r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
             }
         }
-    }
-    __syncthreads();
-    for (uint32_t d = tid; d < nd; d += kBlock) start[d] = cnt[d];
-    __syncthreads();
-    block_exclusive_scan(start, nd, tmp);
-    for (uint32_t d = tid; d < nd; d += kBlock)
-        if (cnt[d]) base[d] = atomicAdd(&cursor[(s << dbits) | d], cnt[d]);
-    __shared__ uint32_t s_total;
-    if (tid == 0) s_total = 0;
-    __syncthreads();
-    uint32_t mine = 0;
+        lds_barrier();
+        for (uint32_t d = tid; d < nd; d += kBlock) start[d] = cnt[d];
+        lds_barrier();
+        block_exclusive_scan(start, nd, tmp);
 #pragma unroll
-    for (int q = 0; q < kItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (p < cnt_here && r_dig[q] != 0xFFFFFFFFu) {
-            const uint32_t lp = start[r_dig[q]] + r_rank[q];
-            s_idx[lp] = r_idx[q];
-            s_key[lp] = r_key[q];
-            s_dig[lp] = (uint16_t)r_dig[q];
-            ++mine;
+        for (int j = 0; j < kScatterOffRegs; ++j) {
+            const uint32_t d = tid + j * kBlock;
+            if (d < nd) base[d] = c_off[j];
         }
-    }
-    if (mine) atomicAdd(&s_total, mine);
-    __syncthreads();
-    const uint32_t staged = s_total;
-    for (uint32_t lp = tid; lp < staged; lp += kBlock) {
-        const uint32_t d = s_dig[lp];
-        const uint32_t g = base[d] + (lp - start[d]);
-        if (g >= seg_begin && g < seg_end) {
-            dst_idx[g] = s_idx[lp];
-            dst_key[g] = s_key[lp];
-        } else {
-            atomicOr(err, ERR_INTERNAL);
+        for (uint32_t d = tid + kScatterOffRegs * kBlock; d < nd; d += kBlock) base[d] = offs[(size_t)w * nd + d];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            if (r_dig[q] != 0xFFFFFFFFu) {
+                const uint32_t lp = start[r_dig[q]] + r_rank[q];
+                s_idx[lp] = c_idx[q];
+                s_key[lp] = c_key[q];
+                s_dig[lp] = (uint16_t)r_dig[q];
+                ++mine;
+            }
         }
+        if (mine) atomicAdd(&s_total, mine);
+        lds_barrier();
+        const uint32_t staged = s_total;
+        for (uint32_t lp = tid; lp < staged; lp += kBlock) {
+            const uint32_t d = s_dig[lp];
+            const uint32_t g = base[d] + (lp - start[d]);
+            if (g >= ts.seg_begin && g < ts.seg_end) {
+                dst_idx[g] = s_idx[lp];
+                dst_key[g] = s_key[lp];
+            } else {
+                atomicOr(err, ERR_INTERNAL);
+            }
+        }
+        lds_barrier();
+        if (wn >= nt) break;
+        w = wn;
+        ts = tn;
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            c_idx[q] = n_idx[q];
+            c_key[q] = n_key[q];
+        }
+#pragma unroll
+        for (int j = 0; j < kScatterOffRegs; ++j) c_off[j] = n_off[j];
     }
 }
 
-// Sorts each fine bucket by (K, i): LDS counting sort on the 11 bits of K
-// below the B bucket bits, then insertion sort inside each cell.  Buckets
-// larger than `cap` (never expected: the mean is <= 1024 and the cap 2048)
-// take a slow exact path that ranks every record against the whole bucket.
-// Dynamic LDS: 2048 cell counters + kBlock + 2 scan words + cap * 20 bytes.
+// Sorts each fine bucket by (K, i): LDS counting sort on the kSortSubBits
+// bits of K below the B bucket bits, then insertion sort inside each cell.
+// Persistent workgroups prefetch the next bucket into registers.  Buckets
+// larger than `cap` (not expected: the mean is cap / 2 and sizes are
+// binomial) take a slow exact path that ranks every record against the whole
+// bucket.  Dynamic LDS: 2^kSortSubBits cell counters + kBlock + 2 scan words
+// + cap * 20 bytes.
 __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restrict__ src_idx,
                                                          const unsigned long long *__restrict__ src_key,
                                                          uint32_t *__restrict__ dst_idx,
                                                          unsigned long long *__restrict__ dst_key,
                                                          unsigned long long *__restrict__ scratch_k, uint32_t t,
                                                          uint32_t k0, uint32_t k1, int bbits,
-                                                         const uint32_t *__restrict__ fine_off, uint32_t m, uint32_t cap,
-                                                         StepCounters *__restrict__ ctr) {
+                                                         const uint32_t *__restrict__ fine_off, uint32_t nb,
+                                                         uint32_t m, uint32_t cap, StepCounters *__restrict__ ctr) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t kCells = 1u << kSortSubBits;
     uint32_t *cell = lds;                    // kCells
@@ -339,86 +484,117 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
     unsigned long long *sK = reinterpret_cast<unsigned long long *>(tmp + kBlock + 2);
     unsigned long long *sE = sK + cap;
     uint32_t *sI = reinterpret_cast<uint32_t *>(sE + cap);
-
-    const uint32_t f = blockIdx.x;
-    const uint32_t begin = min(fine_off[f], m), end = min(fine_off[f + 1], m);
-    const uint32_t c = end > begin ? end - begin : 0;
     const uint32_t tid = threadIdx.x;
-    if (c == 0) return;
-
-    if (c > cap || c > (uint32_t)(kSortMaxItems * kBlock)) {
-        // exact slow path: rank_p = #{q : (K_q, i_q) < (K_p, i_p)}
-        for (uint32_t p = tid; p < c; p += kBlock) scratch_k[begin + p] = perm_key(src_idx[begin + p], t, k0, k1);
-        __threadfence_block();
-        __syncthreads();
-        for (uint32_t p = tid; p < c; p += kBlock) {
-            const unsigned long long kp = scratch_k[begin + p];
-            const uint32_t ip = src_idx[begin + p];
-            uint32_t rank = 0;
-            for (uint32_t q = 0; q < c; ++q) {
-                const unsigned long long kq = scratch_k[begin + q];
-                const uint32_t iq = src_idx[begin + q];
-                rank += (kq < kp) || (kq == kp && iq < ip);
-            }
-            dst_idx[begin + rank] = ip;
-            dst_key[begin + rank] = src_key[begin + p];
-        }
-        if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
-        return;
-    }
-
-    for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
-    __syncthreads();
     const int sub_shift = 64 - kSortSubBits;
-    uint32_t r_idx[kSortMaxItems], r_cell[kSortMaxItems], r_rank[kSortMaxItems];
-    unsigned long long r_key[kSortMaxItems], r_K[kSortMaxItems];
+    const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
+
+    uint32_t f = blockIdx.x;
+    if (f >= nb) return;
+    uint32_t begin = min(fine_off[f], m), end = min(fine_off[f + 1], m);
+    uint32_t c_idx[kSortMaxItems];
+    unsigned long long c_key[kSortMaxItems];
 #pragma unroll
     for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (p < c) {
-            r_idx[q] = src_idx[begin + p];
-            r_key[q] = src_key[begin + p];
-            r_K[q] = perm_key(r_idx[q], t, k0, k1);
-            r_cell[q] = (uint32_t)((bbits >= 64 ? 0ull : (r_K[q] << bbits)) >> sub_shift);
-            r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
-        }
+        const uint32_t p = begin + tid + q * kBlock;
+        c_idx[q] = p < end ? src_idx[p] : 0u;
+        c_key[q] = p < end ? src_key[p] : 0ull;
     }
-    __syncthreads();
-    block_exclusive_scan(cell, kCells, tmp);
+    for (;;) {
+        const uint32_t fn = f + gridDim.x;
+        uint32_t nbegin = 0, nend = 0, n_idx[kSortMaxItems];
+        unsigned long long n_key[kSortMaxItems];
+        if (fn < nb) {
+            nbegin = min(fine_off[fn], m);
+            nend = min(fine_off[fn + 1], m);
 #pragma unroll
-    for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (p < c) {
-            const uint32_t lp = cell[r_cell[q]] + r_rank[q];
-            sK[lp] = r_K[q];
-            sE[lp] = r_key[q];
-            sI[lp] = r_idx[q];
-        }
-    }
-    __syncthreads();
-    // settle ties of the counting sort: each thread owns 16 consecutive cells
-    for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
-        const uint32_t a = cell[q];
-        const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
-        for (uint32_t x = a + 1; x < b; ++x) {
-            const unsigned long long kx = sK[x], ex = sE[x];
-            const uint32_t ix = sI[x];
-            uint32_t y = x;
-            while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sI[y - 1] > ix))) {
-                sK[y] = sK[y - 1];
-                sE[y] = sE[y - 1];
-                sI[y] = sI[y - 1];
-                --y;
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = nbegin + tid + q * kBlock;
+                n_idx[q] = p < nend ? src_idx[p] : 0u;
+                n_key[q] = p < nend ? src_key[p] : 0ull;
             }
-            sK[y] = kx;
-            sE[y] = ex;
-            sI[y] = ix;
         }
-    }
-    __syncthreads();
-    for (uint32_t p = tid; p < c; p += kBlock) {
-        dst_idx[begin + p] = sI[p];
-        dst_key[begin + p] = sE[p];
+        const uint32_t c = end > begin ? end - begin : 0;
+        if (c > lds_cap) {
+            // exact slow path: rank_p = #{q : (K_q, i_q) < (K_p, i_p)}
+            for (uint32_t p = tid; p < c; p += kBlock) scratch_k[begin + p] = perm_key(src_idx[begin + p], t, k0, k1);
+            __threadfence_block();
+            __syncthreads();
+            for (uint32_t p = tid; p < c; p += kBlock) {
+                const unsigned long long kp = scratch_k[begin + p];
+                const uint32_t ip = src_idx[begin + p];
+                uint32_t rank = 0;
+                for (uint32_t q = 0; q < c; ++q) {
+                    const unsigned long long kq = scratch_k[begin + q];
+                    const uint32_t iq = src_idx[begin + q];
+                    rank += (kq < kp) || (kq == kp && iq < ip);
+                }
+                dst_idx[begin + rank] = ip;
+                dst_key[begin + rank] = src_key[begin + p];
+            }
+            if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
+            __syncthreads();
+        } else if (c > 0) {
+            for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
+            lds_barrier();
+            uint32_t r_cell[kSortMaxItems], r_rank[kSortMaxItems];
+            unsigned long long r_K[kSortMaxItems];
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    r_K[q] = perm_key(c_idx[q], t, k0, k1);
+                    r_cell[q] = (uint32_t)((bbits >= 64 ? 0ull : (r_K[q] << bbits)) >> sub_shift);
+                    r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
+                }
+            }
+            lds_barrier();
+            block_exclusive_scan(cell, kCells, tmp);
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    const uint32_t lp = cell[r_cell[q]] + r_rank[q];
+                    sK[lp] = r_K[q];
+                    sE[lp] = c_key[q];
+                    sI[lp] = c_idx[q];
+                }
+            }
+            lds_barrier();
+            // settle ties of the counting sort: each thread owns kCells / kBlock consecutive cells
+            for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
+                const uint32_t a = cell[q];
+                const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
+                for (uint32_t x = a + 1; x < b; ++x) {
+                    const unsigned long long kx = sK[x], ex = sE[x];
+                    const uint32_t ix = sI[x];
+                    uint32_t y = x;
+                    while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sI[y - 1] > ix))) {
+                        sK[y] = sK[y - 1];
+                        sE[y] = sE[y - 1];
+                        sI[y] = sI[y - 1];
+                        --y;
+                    }
+                    sK[y] = kx;
+                    sE[y] = ex;
+                    sI[y] = ix;
+                }
+            }
+            lds_barrier();
+            for (uint32_t p = tid; p < c; p += kBlock) {
+                dst_idx[begin + p] = sI[p];
+                dst_key[begin + p] = sE[p];
+            }
+            lds_barrier();
+        }
+        if (fn >= nb) break;
+        f = fn;
+        begin = nbegin;
+        end = nend;
+#pragma unroll
+        for (int q = 0; q < kSortMaxItems; ++q) {
+            c_idx[q] = n_idx[q];
+            c_key[q] = n_key[q];
+        }
     }
 }
 

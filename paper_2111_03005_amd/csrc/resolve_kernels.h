@@ -40,34 +40,25 @@ constexpr uint32_t kNoPred = 0xFFFFFFFFu;
 // Emit: one thread per switch (+ one for the idle record).  Tuple slots
 // 4k .. 4k+3 belong to switch k, slot 4*ell to the idle record; unused slots
 // get an empty key.  Also: records of locally rejected switches, the free
-// target records, and the coarse histogram of tuple partitions.
+// target records.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
                                                  const unsigned long long *__restrict__ s_key, uint32_t m, uint32_t t,
                                                  uint32_t k0, uint32_t k1, uint32_t pl, uint32_t *__restrict__ tu_tag,
                                                  unsigned long long *__restrict__ tu_key, uint2 *__restrict__ info,
                                                  uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
-                                                 unsigned long long *__restrict__ out_key, int b1,
-                                                 uint32_t *__restrict__ coarse_hist, StepCounters *ctr) {
-    __shared__ uint32_t h[256];
+                                                 unsigned long long *__restrict__ out_key, StepCounters *ctr) {
     __shared__ BlockCounts bc;
     const uint32_t tid = threadIdx.x;
-    h[tid] = 0;
     if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
     __syncthreads();
     const uint32_t ell = m >> 1;
-    const int shift = 64 - b1;
-    auto count = [&](unsigned long long key) {
-        const uint32_t d = b1 > 0 ? (uint32_t)(slot_hash(key) >> shift) : 0u;
-        atomicAdd(&h[d], 1u);
-    };
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t k = blockIdx.x * kBlock + tid; k <= ell; k += stride) {
     if (k == ell && (m & 1u)) {
         const unsigned long long e = s_key[m - 1];
         tu_tag[4 * (size_t)ell] = kTagStays;
         tu_key[4 * (size_t)ell] = e;
-        count(e);
         out_idx[m - 1] = s_idx[m - 1];
         out_key[m - 1] = e;
     } else if (k < ell) {
@@ -87,16 +78,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
                 status = ST_EXISTS;
         }
         const uint32_t etag = status == ST_UNDECIDED ? k : kTagStays;
-        count(e1);
-        count(e2);
         ulonglong2 *tk = reinterpret_cast<ulonglong2 *>(tu_key) + 2 * (size_t)k;
         tk[0] = make_ulonglong2(e1, e2);
         if (status == ST_UNDECIDED) {
             reinterpret_cast<uint4 *>(tu_tag)[k] =
                 make_uint4(etag, etag, kTagInsert | (k << 1), kTagInsert | (k << 1) | 1u);
             tk[1] = make_ulonglong2(T.A, T.B);
-            count(T.A);
-            count(T.B);
             reinterpret_cast<uint4 *>(info)[k] = make_uint4(kNoEraser, kNoPred, kNoEraser, kNoPred);
         } else {
             reinterpret_cast<uint4 *>(tu_tag)[k] = make_uint4(etag, etag, 0u, 0u);
@@ -110,13 +97,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         }
     }
     }
-    __syncthreads();
-    if (b1 > 0) {
-        for (uint32_t d = tid; d < (1u << b1); d += kBlock)
-            if (h[d]) atomicAdd(&coarse_hist[d], h[d]);
-    } else if (tid == 0 && h[0]) {
-        atomicAdd(&coarse_hist[0], h[0]);
-    }
     flush_counts(&bc, ctr);
 }
 
@@ -124,21 +104,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
 // duplicate edge shows up as two ERASE tuples of one key.
 __global__ __launch_bounds__(kBlock) void k_emit_sources(const unsigned long long *__restrict__ key, uint32_t m,
                                                          uint32_t *__restrict__ tu_tag,
-                                                         unsigned long long *__restrict__ tu_key, int b1,
-                                                         uint32_t *__restrict__ coarse_hist) {
-    __shared__ uint32_t h[256];
-    const uint32_t tid = threadIdx.x;
-    h[tid] = 0;
-    __syncthreads();
-    for (uint32_t i = blockIdx.x * kBlock + tid; i < m; i += gridDim.x * kBlock) {
-        const unsigned long long e = key[i];
+                                                         unsigned long long *__restrict__ tu_key) {
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
         tu_tag[i] = kTagStays;
-        tu_key[i] = e;
-        atomicAdd(&h[b1 > 0 ? (uint32_t)(slot_hash(e) >> (64 - b1)) : 0u], 1u);
+        tu_key[i] = key[i];
     }
-    __syncthreads();
-    for (uint32_t d = tid; d < (1u << b1); d += kBlock)
-        if (h[d]) atomicAdd(&coarse_hist[d], h[d]);
 }
 
 // Writes the records of the tuple at sorted position p, given the position
@@ -156,15 +126,16 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
     if (eraser != kNoEraser || pred != kNoPred) info[tag & ~kTagInsert] = make_uint2(eraser, pred);
 }
 
-// One workgroup per fine partition.  LDS path: counting sort on 12 hash bits
-// below the partition bits, insertion sort inside cells, then each tuple finds
-// its key's first tuple while walking its own cells.  Partitions above `cap`
-// (hub keys with many inserters) take an exact global-memory merge sort.
-// Dynamic LDS: 2048 cell words + kBlock + 2 words + cap * 12 bytes.
+// Persistent workgroups over the fine partitions; the next partition's
+// tuples are prefetched into registers.  LDS path: counting sort on
+// kSortSubBits hash bits below the partition bits, then each thread sorts the
+// cells it owns by (key, tag) and walks them.  Partitions above `cap` (hub
+// keys with many inserters) take an exact global-memory merge sort.
+// Dynamic LDS: 2^kSortSubBits cell words + kBlock + 2 words + cap * 12 bytes.
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
                                                     uint32_t *__restrict__ sc_tag,
                                                     unsigned long long *__restrict__ sc_key, int pbits,
-                                                    const uint32_t *__restrict__ part_off, uint32_t cap,
+                                                    const uint32_t *__restrict__ part_off, uint32_t np, uint32_t cap,
                                                     uint2 *__restrict__ info, uint32_t *__restrict__ err,
                                                     uint32_t dup_bit, StepCounters *ctr) {
     extern __shared__ uint32_t lds[];
@@ -173,124 +144,155 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
     uint32_t *tmp = cell + kCells;
     unsigned long long *sK = reinterpret_cast<unsigned long long *>(tmp + kBlock + 2);
     uint32_t *sT = reinterpret_cast<uint32_t *>(sK + cap);
-
-    const uint32_t f = blockIdx.x;
-    const uint32_t begin = part_off[f], end = part_off[f + 1];
-    const uint32_t c = end > begin ? end - begin : 0;
     const uint32_t tid = threadIdx.x;
-    if (c == 0) return;
     const int sub_shift = 64 - kSortSubBits;
+    const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
 
-    if (c > cap || c > (uint32_t)(kSortMaxItems * kBlock)) {
-        // exact slow path: bottom-up merge sort by (key, tag) between the
-        // partition's range and the scratch range, then binary searches.
-        uint32_t *at = tu_tag + begin, *bt = sc_tag + begin;
-        unsigned long long *ak = tu_key + begin, *bk = sc_key + begin;
-        for (uint32_t width = 1; width < c; width <<= 1) {
-            for (uint32_t p = tid; p < c; p += kBlock) {
-                const uint32_t run = p / (2 * width);
-                const uint32_t lo = run * 2 * width, mid = min(lo + width, c), hi = min(lo + 2 * width, c);
-                const unsigned long long kp = ak[p];
-                const uint32_t tp = at[p];
-                uint32_t pos;
-                if (p < mid) {  // rank among the right run: elements strictly smaller
-                    uint32_t a = mid, b = hi;
-                    while (a < b) {
-                        const uint32_t x = (a + b) >> 1;
-                        if (ak[x] < kp || (ak[x] == kp && at[x] < tp))
-                            a = x + 1;
-                        else
-                            b = x;
+    uint32_t f = blockIdx.x;
+    if (f >= np) return;
+    uint32_t begin = part_off[f], end = part_off[f + 1];
+    uint32_t c_tag[kSortMaxItems];
+    unsigned long long c_key[kSortMaxItems];
+#pragma unroll
+    for (int q = 0; q < kSortMaxItems; ++q) {
+        const uint32_t p = begin + tid + q * kBlock;
+        c_tag[q] = p < end ? tu_tag[p] : 0u;
+        c_key[q] = p < end ? tu_key[p] : 0ull;
+    }
+    for (;;) {
+        const uint32_t fn = f + gridDim.x;
+        uint32_t nbegin = 0, nend = 0, n_tag[kSortMaxItems];
+        unsigned long long n_key[kSortMaxItems];
+        if (fn < np) {
+            nbegin = part_off[fn];
+            nend = part_off[fn + 1];
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = nbegin + tid + q * kBlock;
+                n_tag[q] = p < nend ? tu_tag[p] : 0u;
+                n_key[q] = p < nend ? tu_key[p] : 0ull;
+            }
+        }
+        const uint32_t c = end > begin ? end - begin : 0;
+        if (c > lds_cap) {
+            // exact slow path: bottom-up merge sort by (key, tag) between the
+            // partition's range and the scratch range, then binary searches.
+            uint32_t *at = tu_tag + begin, *bt = sc_tag + begin;
+            unsigned long long *ak = tu_key + begin, *bk = sc_key + begin;
+            for (uint32_t width = 1; width < c; width <<= 1) {
+                for (uint32_t p = tid; p < c; p += kBlock) {
+                    const uint32_t run = p / (2 * width);
+                    const uint32_t lo = run * 2 * width, mid = min(lo + width, c), hi = min(lo + 2 * width, c);
+                    const unsigned long long kp = ak[p];
+                    const uint32_t tp = at[p];
+                    uint32_t pos;
+                    if (p < mid) {  // rank among the right run: elements strictly smaller
+                        uint32_t a = mid, b = hi;
+                        while (a < b) {
+                            const uint32_t x = (a + b) >> 1;
+                            if (ak[x] < kp || (ak[x] == kp && at[x] < tp))
+                                a = x + 1;
+                            else
+                                b = x;
+                        }
+                        pos = lo + (p - lo) + (a - mid);
+                    } else {  // rank among the left run: elements smaller or equal
+                        uint32_t a = lo, b = mid;
+                        while (a < b) {
+                            const uint32_t x = (a + b) >> 1;
+                            if (ak[x] < kp || (ak[x] == kp && at[x] <= tp))
+                                a = x + 1;
+                            else
+                                b = x;
+                        }
+                        pos = lo + (p - mid) + (a - lo);
                     }
-                    pos = lo + (p - lo) + (a - mid);
-                } else {  // rank among the left run: elements smaller or equal
-                    uint32_t a = lo, b = mid;
-                    while (a < b) {
-                        const uint32_t x = (a + b) >> 1;
-                        if (ak[x] < kp || (ak[x] == kp && at[x] <= tp))
-                            a = x + 1;
-                        else
-                            b = x;
-                    }
-                    pos = lo + (p - mid) + (a - lo);
+                    bt[pos] = tp;
+                    bk[pos] = kp;
                 }
-                bt[pos] = tp;
-                bk[pos] = kp;
+                __threadfence_block();
+                __syncthreads();
+                uint32_t *xt = at;
+                at = bt;
+                bt = xt;
+                unsigned long long *xk = ak;
+                ak = bk;
+                bk = xk;
             }
-            __threadfence_block();
+            for (uint32_t p = tid; p < c; p += kBlock) {
+                const unsigned long long kp = ak[p];
+                uint32_t a = 0, b = p;
+                while (a < b) {
+                    const uint32_t x = (a + b) >> 1;
+                    if (ak[x] < kp)
+                        a = x + 1;
+                    else
+                        b = x;
+                }
+                resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, info, err, dup_bit);
+            }
+            if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
             __syncthreads();
-            uint32_t *xt = at;
-            at = bt;
-            bt = xt;
-            unsigned long long *xk = ak;
-            ak = bk;
-            bk = xk;
-        }
-        for (uint32_t p = tid; p < c; p += kBlock) {
-            const unsigned long long kp = ak[p];
-            uint32_t a = 0, b = p;
-            while (a < b) {
-                const uint32_t x = (a + b) >> 1;
-                if (ak[x] < kp)
-                    a = x + 1;
-                else
-                    b = x;
-            }
-            resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, info, err, dup_bit);
-        }
-        if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
-        return;
-    }
-
-    for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
-    __syncthreads();
-    uint32_t r_tag[kSortMaxItems], r_cell[kSortMaxItems], r_rank[kSortMaxItems];
-    unsigned long long r_key[kSortMaxItems];
+        } else if (c > 0) {
+            for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
+            lds_barrier();
+            uint32_t r_cell[kSortMaxItems], r_rank[kSortMaxItems];
 #pragma unroll
-    for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (p < c) {
-            r_tag[q] = tu_tag[begin + p];
-            r_key[q] = tu_key[begin + p];
-            const uint64_t hsh = slot_hash(r_key[q]);
-            r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
-            r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
-        }
-    }
-    __syncthreads();
-    block_exclusive_scan(cell, kCells, tmp);
-#pragma unroll
-    for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (p < c) {
-            const uint32_t lp = cell[r_cell[q]] + r_rank[q];
-            sK[lp] = r_key[q];
-            sT[lp] = r_tag[q];
-        }
-    }
-    __syncthreads();
-    // Each thread owns kCells / kBlock consecutive cells.  All tuples of one key share a
-    // cell, so the owner sorts its cells by (key, tag) and walks them once.
-    for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
-        const uint32_t a = cell[q];
-        const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
-        if (b - a < 2) continue;  // a lone tuple has neither eraser nor predecessor
-        for (uint32_t x = a + 1; x < b; ++x) {
-            const unsigned long long kx = sK[x];
-            const uint32_t tx = sT[x];
-            uint32_t y = x;
-            while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sT[y - 1] > tx))) {
-                sK[y] = sK[y - 1];
-                sT[y] = sT[y - 1];
-                --y;
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    const uint64_t hsh = slot_hash(c_key[q]);
+                    r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
+                    r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
+                }
             }
-            sK[y] = kx;
-            sT[y] = tx;
+            lds_barrier();
+            block_exclusive_scan(cell, kCells, tmp);
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    const uint32_t lp = cell[r_cell[q]] + r_rank[q];
+                    sK[lp] = c_key[q];
+                    sT[lp] = c_tag[q];
+                }
+            }
+            lds_barrier();
+            // Each thread owns kCells / kBlock consecutive cells.  All tuples of
+            // one key share a cell, so the owner sorts its cells by (key, tag)
+            // and walks them once.
+            for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
+                const uint32_t a = cell[q];
+                const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
+                if (b - a < 2) continue;  // a lone tuple has neither eraser nor predecessor
+                for (uint32_t x = a + 1; x < b; ++x) {
+                    const unsigned long long kx = sK[x];
+                    const uint32_t tx = sT[x];
+                    uint32_t y = x;
+                    while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sT[y - 1] > tx))) {
+                        sK[y] = sK[y - 1];
+                        sT[y] = sT[y - 1];
+                        --y;
+                    }
+                    sK[y] = kx;
+                    sT[y] = tx;
+                }
+                uint32_t first = a;
+                for (uint32_t x = a; x < b; ++x) {
+                    if (x > a && sK[x] != sK[x - 1]) first = x;
+                    resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, info, err, dup_bit);
+                }
+            }
+            lds_barrier();
         }
-        uint32_t first = a;
-        for (uint32_t x = a; x < b; ++x) {
-            if (x > a && sK[x] != sK[x - 1]) first = x;
-            resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, info, err, dup_bit);
+        if (fn >= np) break;
+        f = fn;
+        begin = nbegin;
+        end = nend;
+#pragma unroll
+        for (int q = 0; q < kSortMaxItems; ++q) {
+            c_tag[q] = n_tag[q];
+            c_key[q] = n_key[q];
         }
     }
 }
@@ -324,24 +326,23 @@ __device__ __forceinline__ int judge_target_chain(const uint2 *info, uint2 rec, 
     return v;
 }
 
-__device__ __forceinline__ bool decide_switch_chain(uint32_t k, const uint32_t *s_idx, const unsigned long long *s_key,
-                                                    const uint2 *info, uint8_t *st, uint32_t *out_idx,
-                                                    unsigned long long *out_key, BlockCounts *bc) {
-    const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
+// Decides switch k from its two target records; the pair's records (ij, ee)
+// are passed in so that callers can issue every load of the switch at once.
+__device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint2 ij, ulonglong2 ee, const uint2 *info,
+                                                    uint8_t *st, uint32_t *out_idx, unsigned long long *out_key,
+                                                    BlockCounts *bc) {
     const int v = max(judge_target_chain(info, make_uint2(recs.x, recs.y), k, st),
                       judge_target_chain(info, make_uint2(recs.z, recs.w), k, st));
     if (v == V_WAIT) return true;
-    const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
-    const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
     reinterpret_cast<uint2 *>(out_idx)[k] = ij;
     if (v == V_OK) {
         const Targets T = switch_targets(ee.x, ee.y, ij.x < ij.y);
         reinterpret_cast<ulonglong2 *>(out_key)[k] = make_ulonglong2(T.A, T.B);
-        __hip_atomic_store(st + k, (uint8_t)ST_LEGAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st[k] = ST_LEGAL;
         atomicAdd(&bc->legal, 1u);
     } else {
         reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
-        __hip_atomic_store(st + k, (uint8_t)ST_EXISTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st[k] = ST_EXISTS;
         atomicAdd(&bc->exists, 1u);
     }
     return false;
@@ -372,8 +373,13 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
         uint32_t k = 0;
         if (q < n) {
             k = list ? list[q] : q;
-            if (k < ell && st[k] == ST_UNDECIDED)
-                wait = decide_switch_chain(k, s_idx, s_key, info, st, out_idx, out_key, &bc);
+            if (k < ell) {
+                const uint8_t sk = st[k];
+                const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
+                const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+                const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+                if (sk == ST_UNDECIDED) wait = decide_switch_chain(k, recs, ij, ee, info, st, out_idx, out_key, &bc);
+            }
         }
         append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
     }
@@ -413,7 +419,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
             if (q < n) {
                 k = cur[q];
                 if (k < ell && st[k] == ST_UNDECIDED)
-                    wait = decide_switch_chain(k, s_idx, s_key, info, st, out_idx, out_key, &bc);
+                    wait = decide_switch_chain(k, reinterpret_cast<const uint4 *>(info)[k],
+                                               reinterpret_cast<const uint2 *>(s_idx)[k],
+                                               reinterpret_cast<const ulonglong2 *>(s_key)[k], info, st, out_idx,
+                                               out_key, &bc);
             }
             append_undecided(wait, k, nxt, cnxt);
         }
