@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-supersteps", type=int, default=3)
-    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-profile", action="store_true", help="no kernel events at all (no roofline)")
     ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
                     help="library option (e.g. PERSIST=2, STRATEGY=1); results never depend on options")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -140,44 +140,58 @@ def main():
     d_out = torch.empty_like(d_in)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
-    torch.cuda.synchronize()
-
+    # Warm-up: the first pass times every kernel (events between all launches)
+    # to find the dominant one; the timed steps then carry events around that
+    # kernel only, so the clock around them is barely disturbed.
+    tslots = table_slots(m)
     ctx.set_option(gesmc.OPT_PROFILE, 0 if args.no_profile else 1)
+    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
+    ctx.profile_reset()
+    for w in range(max(args.warmup, 1)):
+        ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
+        if w == 0:
+            torch.cuda.synchronize()
+            ctx.set_option(gesmc.OPT_PROFILE, 0)
+    torch.cuda.synchronize()
+    warm_prof = ctx.profile()
+    dominant = None
+    for name, (ms, launches, items) in sorted(warm_prof.items(), key=lambda kv: -kv[1][0]):
+        print("warm-up kernel %-16s total %9.3f ms  launches %5d" % (name, ms, launches), file=sys.stderr)
+        if dominant is None and kernel_bytes(name, m, ell, tslots) is not None:
+            dominant = name
+
+    if dominant is not None:
+        ctx.set_option(gesmc.OPT_PROFILE, 1)
+        ctx.set_option(gesmc.OPT_PROFILE_ONLY, gesmc.Context.kernel_names().index(dominant))
     ctx.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
+    step_ms = []
     for _ in range(args.steps):
         _, stats = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream)
+        step_ms.append(stats["ms_device"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.set_option(gesmc.OPT_PROFILE, 0)
+    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
     prof = ctx.profile()
 
     attempts = args.steps * r * ell
     value = attempts / wall
     ms_per_step = 1000.0 * wall / args.steps
 
-    # dominant kernel among those with a byte model
-    tslots = table_slots(m)
-    rows = []
-    for name, (ms, launches, items) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
-        b = kernel_bytes(name, m, ell, tslots)
-        rows.append((name, ms, launches, b))
-        print("kernel %-16s total %9.3f ms  launches %5d  avg %8.4f ms%s" % (
-            name, ms, launches, ms / max(launches, 1),
-            "" if b is None else "  %.0f GB/s" % (b / (ms / launches / 1e3) / 1e9)), file=sys.stderr)
     roofline = None
-    modeled = [x for x in rows if x[3] is not None]
-    if modeled:
-        name, ms, launches, b = modeled[0]
+    if dominant is not None and dominant in prof:
+        ms, launches, items = prof[dominant]
+        b = kernel_bytes(dominant, m, ell, tslots)
         avg_s = ms / launches / 1e3
         achieved = b / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        print("timed kernel %s: %d launches, avg %.4f ms, %.0f GB/s" % (dominant, launches, avg_s * 1e3, achieved),
+              file=sys.stderr)
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(name, args.workload),
+                    "traffic": load_traffic(dominant, args.workload),
                     "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 4),
                     "share_of_step": round(ms / (wall * 1e3), 3)}
 
@@ -195,7 +209,7 @@ def main():
         "unit": "attempts/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": max(args.warmup, 1),
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -206,7 +220,8 @@ def main():
                    "attempts_per_step": r * ell, "seed": args.seed, "pl": 0, "mode": "plain",
                    "legal_fraction": round(stats["legal"] / max(stats["attempts"], 1), 5) if stats else None,
                    "rounds_max": stats["rounds_max"] if stats else None,
-                   "event_timing": not args.no_profile, "options": args.option},
+                   "step_ms_device_p50": round(float(np.median(step_ms)), 3) if step_ms else None,
+                   "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -120,6 +120,9 @@ gesmc_status gesmc_permutation(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_
                                    rebuilt every superstep with device-scope atomics               */
 #define GESMC_OPT_PERSIST 6     /* workgroups of the tile/bucket kernels: resident count x value;
                                    0 = one workgroup per tile or bucket (default 0)                */
+#define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
+                                    kernel (default).  Events between launches cost time, so timing
+                                    one kernel disturbs the rest least                              */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

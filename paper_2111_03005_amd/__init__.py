@@ -1,16 +1,16 @@
 """G-ES-MC global edge switching on AMD MI355X (gfx950).
 
 The hot path -- Philox permutation keys, the radix permutation, the dependency
-table and the rounds of decisions of each global switch -- runs in the HIP
+resolution and the rounds of decisions of each global switch -- runs in the HIP
 kernels of ``libgesmc.so`` (C ABI in ``include/gesmc.h``); this package is its
 thin ctypes binding.  PyTorch supplies device memory and streams only.
 """
 from ._binding import (E_DEVICE, E_INTERNAL, E_INVAL, E_NOMEM, E_NOT_SIMPLE, E_RANGE, EXPORTS, LIB_PATH, OK,
-                       OPT_BUCKET_AVG, OPT_FAST_ROUNDS, OPT_PERSIST, OPT_PROFILE, OPT_SORT_CAP, OPT_STRATEGY,
-                       STRATEGY_HBM_TABLE, STRATEGY_SORTED_TUPLES, Context, GesmcError, default_context,
-                       load_library, run)
+                       OPT_BUCKET_AVG, OPT_FAST_ROUNDS, OPT_PERSIST, OPT_PROFILE, OPT_PROFILE_ONLY, OPT_SORT_CAP,
+                       OPT_STRATEGY, STRATEGY_HBM_TABLE, STRATEGY_SORTED_TUPLES, Context, GesmcError,
+                       default_context, load_library, run)
 
 __all__ = ["Context", "GesmcError", "default_context", "load_library", "run", "EXPORTS", "LIB_PATH", "OK",
            "E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_INTERNAL", "OPT_BUCKET_AVG",
-           "OPT_SORT_CAP", "OPT_FAST_ROUNDS", "OPT_PROFILE", "OPT_STRATEGY", "OPT_PERSIST", "STRATEGY_SORTED_TUPLES",
-           "STRATEGY_HBM_TABLE"]
+           "OPT_SORT_CAP", "OPT_FAST_ROUNDS", "OPT_PROFILE", "OPT_STRATEGY", "OPT_PERSIST", "OPT_PROFILE_ONLY",
+           "STRATEGY_SORTED_TUPLES", "STRATEGY_HBM_TABLE"]

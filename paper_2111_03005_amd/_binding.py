@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libgesmc.so")
 
 OK = 0
 E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_INTERNAL = -1, -2, -3, -4, -5, -9
-OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST = 1, 2, 3, 4, 5, 6
+OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST, OPT_PROFILE_ONLY = (
+    1, 2, 3, 4, 5, 6, 7)
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 
@@ -180,6 +181,11 @@ class Context:
         return out[:m]
 
     # ---- kernel timing ---------------------------------------------------
+    @staticmethod
+    def kernel_names():
+        """Kernel names by kernel id."""
+        return [_lib.gesmc_kernel_name(k).decode() for k in range(_lib.gesmc_kernel_count())]
+
     def profile(self):
         """{kernel name: (total ms, launches, items)} of launches timed while OPT_PROFILE was on."""
         res = {}

@@ -104,6 +104,7 @@ struct gesmc_ctx {
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
+    int profile_only = -1;  // kernel id timed while profiling (-1: every kernel)
     // device buffers (capacity in edges)
     uint64_t cap_m = 0;
     uint32_t *idx[3] = {nullptr, nullptr, nullptr};
@@ -273,7 +274,7 @@ template <typename Kern, typename... Args>
 gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern kern, dim3 grid, dim3 block,
                     size_t lds, Args... args) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (c->profile) {
+    if (c->profile && (c->profile_only < 0 || c->profile_only == kid)) {
         a = take_event(c);
         b = take_event(c);
         if (a) (void)hipEventRecord(a, s);
@@ -284,7 +285,7 @@ gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern k
         set_error("launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
         return GESMC_E_DEVICE;
     }
-    if (c->profile && a && b) {
+    if (a && b) {
         (void)hipEventRecord(b, s);
         c->recs.push_back({kid, items, a, b});
     }
@@ -854,6 +855,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_PROFILE_ONLY:
+            if (v < -1 || v >= KID_COUNT) break;
+            c->profile_only = (int)v;
             return GESMC_OK;
         case GESMC_OPT_PERSIST:
             if (v < 0 || v > 64) break;
