@@ -123,6 +123,7 @@ struct gesmc_ctx {
     uint64_t cap_counts1 = 0, cap_counts2 = 0, cap_partial = 0;
     uint32_t *counts1 = nullptr, *counts2 = nullptr, *partial = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
+    uint4 *bslot = nullptr;     // per-block counts of the grid-stride kernels (2 grids)
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
     uint64_t ctr_cap = 0;
@@ -482,25 +483,28 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
-    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(grid_stride_blocks(c, (uint64_t)p.ell + 1)), dim3(kBlock), 0, si,
-                     sk, p.m, t, k0, k1, pl, c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0],
-                     c->ctr_step));
+    // per-block counts of emit and the first round go to slots [0, ge) and [ge, ge + gd)
+    const uint32_t ge = grid_stride_blocks(c, (uint64_t)p.ell + 1), gd = grid_stride_blocks(c, p.ell);
+    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
+                     c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit));
     if (p.ell == 0) return GESMC_OK;
-    GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(ceil_div(p.ell, kBlock)), dim3(kBlock), 0,
-                     si, sk, p.ell, (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
-                     (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->ctr_step));
+    GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
+                     (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
+                     (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->bslot + ge,
+                     c->ctr_step));
     const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
     int j = 0;
     for (; j < c->fast_rounds; ++j) {
         GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN, 0, k_decide_chain, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
                          (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
                          (const uint32_t *)&c->ucount[j % 3], c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3],
-                         &c->ucount[(j + 2) % 3], c->ctr_step));
+                         &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step));
     }
     GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
-                     c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], c->ctr_step, c->err));
+                     c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
+                     c->ctr_step, c->err));
     return GESMC_OK;
 }
 
@@ -707,7 +711,9 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     // fixed-size area: err[16], ucount[16], coarse offsets / tile map, level-1 segment, fine offsets
     const size_t nf = (size_t)1 << kMaxFineBits;
     const size_t words = 16 + 16 + 2 * 264 + 8 + (nf + 8);
-    if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK || dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK) {
+    if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK ||
+        dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK ||
+        dev_alloc((void **)&c->bslot, 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1) * sizeof(uint4)) != GESMC_OK) {
         gesmc_destroy(c);
         return GESMC_E_NOMEM;
     }
@@ -755,6 +761,7 @@ void gesmc_destroy(gesmc_ctx *c) {
     (void)hipDeviceSynchronize();
     free_buffers(c);
     if (c->small) (void)hipFree(c->small);
+    if (c->bslot) (void)hipFree(c->bslot);
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);

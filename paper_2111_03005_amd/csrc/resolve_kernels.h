@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
                                                  uint32_t k0, uint32_t k1, uint32_t pl, uint32_t *__restrict__ tu_tag,
                                                  unsigned long long *__restrict__ tu_key, uint2 *__restrict__ info,
                                                  uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
-                                                 unsigned long long *__restrict__ out_key, StepCounters *ctr) {
+                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot) {
     __shared__ BlockCounts bc;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         }
     }
     }
-    flush_counts(&bc, ctr);
+    store_counts(&bc, bslot + blockIdx.x);
 }
 
 // Validation only (no superstep): one STAYS tuple per input edge, so that a
@@ -358,7 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
                                                          const uint32_t *__restrict__ count,
                                                          uint32_t *__restrict__ next_list,
                                                          uint32_t *__restrict__ next_count,
-                                                         uint32_t *__restrict__ zero_count, StepCounters *ctr) {
+                                                         uint32_t *__restrict__ zero_count,
+                                                         uint4 *__restrict__ bslot, StepCounters *ctr) {
     __shared__ BlockCounts bc;
     if (threadIdx.x == 0) bc = BlockCounts{0, 0, 0, 0};
     __syncthreads();
@@ -383,7 +384,10 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
         }
         append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
     }
-    flush_counts(&bc, ctr);
+    if (bslot)
+        store_counts(&bc, bslot + blockIdx.x);
+    else
+        flush_counts(&bc, ctr);
     if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(&ctr->rounds, 1ull);
 }
 
@@ -395,7 +399,8 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
                                                                uint8_t *st, uint32_t *__restrict__ out_idx,
                                                                unsigned long long *__restrict__ out_key,
                                                                uint32_t *list_a, uint32_t *count_a, uint32_t *list_b,
-                                                               uint32_t *count_b, StepCounters *ctr,
+                                                               uint32_t *count_b, const uint4 *__restrict__ bslot,
+                                                               uint32_t nbslot, StepCounters *ctr,
                                                                uint32_t *__restrict__ err) {
     __shared__ BlockCounts bc;
     __shared__ uint32_t s_n;
@@ -405,6 +410,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
         s_n = min(*count_a, ell);
     }
     __syncthreads();
+    {  // fold the per-block counts of the emit and first-round kernels
+        uint4 acc = make_uint4(0, 0, 0, 0);
+        for (uint32_t q = tid; q < nbslot; q += kFinishBlock) {
+            const uint4 v = bslot[q];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+        if (acc.x) atomicAdd(&bc.legal, acc.x);
+        if (acc.y) atomicAdd(&bc.loop, acc.y);
+        if (acc.z) atomicAdd(&bc.exists, acc.z);
+        if (acc.w) atomicAdd(&bc.pl, acc.w);
+    }
     uint32_t *cur = list_a, *nxt = list_b, *ccur = count_a, *cnxt = count_b;
     uint32_t n = s_n;
     while (n > 0) {

@@ -90,6 +90,14 @@ __device__ __forceinline__ void flush_counts(BlockCounts *bc, StepCounters *ctr)
     }
 }
 
+// Stores the block's counts into a slot of its own (plain stores, no
+// device-scope atomics, which would serialise memory-side on one address);
+// a single-workgroup kernel folds the slots later.
+__device__ __forceinline__ void store_counts(BlockCounts *bc, uint4 *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = make_uint4(bc->legal, bc->loop, bc->exists, bc->pl);
+}
+
 // ---------------------------------------------------------------------------
 // Build: one thread per switch (plus one for the idle record of odd m).
 // ---------------------------------------------------------------------------
