@@ -163,6 +163,38 @@ def workload_gnp_large():
     return gnp(n, 32.0 / (n - 1), 3), n
 
 
+def batch_specs(G: int, seed: int, n_lo: float, n_hi: float, g_lo: float = 2.1, g_hi: float = 3.0):
+    """Per-graph (n, gamma, d_max) of a batch: n log-uniform in [n_lo, n_hi],
+    gamma uniform in [g_lo, g_hi], d_max = floor(sqrt(n))."""
+    u = uniforms(seed, 2 * G)
+    out = []
+    for g in range(G):
+        n = int(round(math.exp(math.log(n_lo) + u[2 * g] * (math.log(n_hi) - math.log(n_lo)))))
+        gamma = g_lo + u[2 * g + 1] * (g_hi - g_lo)
+        out.append((n, gamma, max(2, int(math.isqrt(n)))))
+    return out
+
+
+def batch_graphs(G: int, seed: int, n_lo: float, n_hi: float, dmin: int = 2):
+    """G power-law graphs (Havel-Hakimi, ids shuffled): list of (edges, n)."""
+    return [(powerlaw_graph(n, gamma, dmin, dmax, seed * 1000003 + g), n)
+            for g, (n, gamma, dmax) in enumerate(batch_specs(G, seed, n_lo, n_hi))]
+
+
+def concat(graphs):
+    """[(edges, n)] -> (edges concatenated, offsets[G+1] int64, n[G] int64)."""
+    offs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(e) for e, _ in graphs])
+    E = np.concatenate([e for e, _ in graphs]) if graphs else np.zeros(0, dtype=np.uint64)
+    return E.astype(np.uint64), offs, np.array([n for _, n in graphs], dtype=np.int64)
+
+
+def workload_batch_4096():
+    """4096 power-law graphs, n log-uniform in [1e2, 1e5], gamma in [2.1, 3.0],
+    d_min = 2, d_max = floor(sqrt(n)); generator seed 4."""
+    return batch_graphs(4096, 4, 1e2, 1e5)
+
+
 WORKLOADS = {
     "gnp_n1024_d10": (workload_gnp_small, 10),
     "pld_n2^20_g2.5": (workload_powerlaw_1m, 20),

@@ -94,6 +94,28 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
                        gesmc_step_stats *steps);
 
 /*
+ * G independent graphs in one call: the batched form of gesmc_run.  Graph g
+ * is d_in[offsets[g] .. offsets[g+1]) (device memory, uint64 keys of local
+ * vertex ids < n[g]); it runs r[g] global switches from superstep t0[g] with
+ * seed seed[g], and its result goes to the same range of d_out (device; may
+ * equal d_in).  Every graph's result equals gesmc_run on that graph alone
+ * with the same (n, seed, t0, r, pl) -- bit for bit, whatever the rest of the
+ * batch holds.  Host arrays: offsets (G + 1 entries, offsets[0] = 0,
+ * non-decreasing), n, seed and r (G each), t0 (G, nullable: all 0).
+ * stats (host, nullable): G records, one per graph (attempts and outcome
+ * counts of that graph; rounds_* count the batch's rounds of the supersteps
+ * the graph took part in; ms_device is the whole call's).  total (host,
+ * nullable): the batch's sums.  Limits: offsets[G] + G < 2^30, the sum of n
+ * below 2^32 - 1, G <= 2^20, and at most 2^20 permutation buckets (about
+ * offsets[G] / GESMC_OPT_BUCKET_AVG + G).  Needs GESMC_OPT_STRATEGY 0.  Any
+ * invalid graph fails the whole call with d_out untouched; the message names
+ * the graph for loops and out-of-range ids.  flags: reserved, pass 0.
+ */
+gesmc_status gesmc_run_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uint64_t *d_in, uint64_t *d_out,
+                             const uint64_t *offsets, const uint32_t *n, const uint64_t *seed, const uint32_t *t0,
+                             const uint32_t *r, uint32_t pl, uint32_t flags, gesmc_stats *stats, gesmc_stats *total);
+
+/*
  * One superstep t (as gesmc_run with t0 = t, r = 1) that also writes the
  * outcome of every switch k < floor(m/2) to d_outcome (device memory, one byte
  * per switch): 1 accepted, 2 rejected loop, 3 rejected target present,

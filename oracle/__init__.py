@@ -135,5 +135,17 @@ def run(E: np.ndarray, n: int, seed: int, t0: int, r: int, pl: int = 0, mutate: 
     return rc, E, counts, (oc[: m // 2] if outcomes else None)
 
 
+def run_batch(graphs, seeds, rs, t0s=None, pl: int = 0):
+    """Independent graphs, each run on its own: [(E_g, n_g)] -> list of
+    (status, E_g', counts).  A batch has no arithmetic of its own -- every
+    graph is a separate chain (Alg. 3 with its own seed, t0 and r), so this
+    is the definition the batched form must equal."""
+    out = []
+    for g, (E, n) in enumerate(graphs):
+        rc, E2, counts, _ = run(E, n, seeds[g], 0 if t0s is None else t0s[g], rs[g], pl)
+        out.append((rc, E2, counts))
+    return out
+
+
 def selftest_edgeset(ops: int = 200000, seed: int = 1) -> int:
     return int(_load().oracle_selftest_edgeset(ops, seed))

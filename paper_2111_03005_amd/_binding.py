@@ -46,9 +46,9 @@ class StepStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
-EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_superstep_outcomes",
-           "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option", "gesmc_kernel_count", "gesmc_kernel_name",
-           "gesmc_profile_get", "gesmc_profile_reset"]
+EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_batch",
+           "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
+           "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset"]
 
 _lib = None
 _lock = threading.Lock()
@@ -74,6 +74,10 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_run.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
                                   ctypes.POINTER(StepStats)]
         lib.gesmc_run.restype = i32
+        lib.gesmc_run_batch.argtypes = [vp, vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                        ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32), u32, u32,
+                                        ctypes.POINTER(Stats), ctypes.POINTER(Stats)]
+        lib.gesmc_run_batch.restype = i32
         lib.gesmc_superstep_outcomes.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, vp,
                                                  ctypes.POINTER(StepStats)]
         lib.gesmc_superstep_outcomes.restype = i32
@@ -156,6 +160,29 @@ class Context:
         if steps:
             return out, st.as_dict(), [ss[q].as_dict() for q in range(r)]
         return out, st.as_dict()
+
+    def run_batch(self, edges: torch.Tensor, offsets, n, seed, r, t0=None, pl: int = 0,
+                  out: torch.Tensor | None = None, stream=None, stats: bool = True):
+        """G graphs in one call: graph g is edges[offsets[g]:offsets[g+1]] (device
+        uint64/int64 keys, local ids < n[g]).  Returns (out, per-graph stats or
+        None, total stats)."""
+        G = len(offsets) - 1
+        if not (len(n) == len(seed) == len(r) == G) or (t0 is not None and len(t0) != G):
+            raise ValueError("per-graph arrays need G = len(offsets) - 1 entries")
+        total_m = int(offsets[-1])
+        if out is None:
+            out = torch.empty_like(edges)
+        h_off = (ctypes.c_uint64 * (G + 1))(*[int(x) for x in offsets])
+        h_n = (ctypes.c_uint32 * G)(*[int(x) for x in n])
+        h_seed = (ctypes.c_uint64 * G)(*[int(x) & (2**64 - 1) for x in seed])
+        h_r = (ctypes.c_uint32 * G)(*[int(x) for x in r])
+        h_t0 = (ctypes.c_uint32 * G)(*[int(x) for x in t0]) if t0 is not None else None
+        st = (Stats * G)() if stats else None
+        tot = Stats()
+        _check(_lib.gesmc_run_batch(self._h, _stream_ptr(stream), G, _dev_ptr(edges, 8, total_m, "edges"),
+                                    _dev_ptr(out, 8, total_m, "out"), h_off, h_n, h_seed, h_t0, h_r, pl, 0,
+                                    st, ctypes.byref(tot)))
+        return out, ([st[g].as_dict() for g in range(G)] if stats else None), tot.as_dict()
 
     def superstep_outcomes(self, edges: torch.Tensor, n: int, seed: int, t: int, pl: int = 0, stream=None):
         """One superstep; returns (edges after, outcome code per switch (uint8), step stats)."""

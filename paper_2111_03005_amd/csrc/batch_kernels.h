@@ -1,0 +1,116 @@
+// Kernels of the batched form: G independent graphs run as one disjoint
+// union (layout and numbering in device_common.h, BatchGraph).  The per
+// superstep kernels are those of the single graph; these kernels load the
+// graphs into their segments, map positions to graphs, count outcomes per
+// graph and write every graph's result back in its input order.
+#pragma once
+
+#include "device_common.h"
+
+namespace gesmc {
+
+// Largest g < ng with key(g) <= x for a non-decreasing key (binary search).
+template <typename KeyOf>
+__device__ __forceinline__ uint32_t upper_index(uint32_t ng, uint64_t x, KeyOf key) {
+    uint32_t lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (key(mid) <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Input edge i of graph g (in the caller's graph order, in_off = input
+// offsets, G + 1 words) -> record (i, shifted canonical key) at position
+// poff + (i - goff) of its segment; also the padding record of an odd graph
+// that is switched.  Flags loops (ERR_LOOP) and ids >= n (ERR_RANGE), and
+// keeps the smallest failing input position in *bad_pos (as its complement,
+// with atomicMax, so that 0 means none).
+__global__ __launch_bounds__(kBlock) void k_load_batch(const unsigned long long *__restrict__ in, uint32_t total,
+                                                       const uint64_t *__restrict__ in_off, uint32_t G,
+                                                       const uint32_t *__restrict__ rank_of,
+                                                       const BatchGraph *__restrict__ gr, uint32_t *__restrict__ idx,
+                                                       unsigned long long *__restrict__ key,
+                                                       uint32_t *__restrict__ err, uint32_t *__restrict__ bad_pos) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint32_t f = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
+        const uint32_t g = upper_index(G, i, [&](uint32_t x) { return in_off[x]; });  // skips empty graphs
+        const BatchGraph b = gr[rank_of[g]];
+        const unsigned long long e = in[i];
+        const uint32_t u = (uint32_t)(e >> 32), v = (uint32_t)e;
+        uint32_t fe = 0;
+        if (u == v) fe |= ERR_LOOP;
+        if (u >= b.n || v >= b.n) fe |= ERR_RANGE;
+        const uint32_t p = b.poff + ((uint32_t)i - b.goff);
+        idx[p] = (uint32_t)i;
+        key[p] = fe ? kEmptyKey : ekey(u + b.vbase, v + b.vbase);
+        if (fe) {
+            f |= fe;
+            atomicMax(bad_pos, ~(uint32_t)i);
+        }
+        if ((uint32_t)i == b.goff && b.mpad > b.m) {  // padding record of an odd switched graph
+            idx[b.poff + b.m] = kPadIdx;
+            key[b.poff + b.m] = kEmptyKey;
+        }
+    }
+    if (f) atomicOr(err, f);
+}
+
+// pg[p] = rank of the graph whose segment holds position p (p < total).
+__global__ __launch_bounds__(kBlock) void k_fill_pg(const BatchGraph *__restrict__ gr, uint32_t ngraphs,
+                                                    uint32_t total, uint32_t *__restrict__ pg) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride)
+        pg[p] = upper_index(ngraphs, p, [&](uint32_t x) { return (uint64_t)gr[x].poff; });
+}
+
+// Outcomes of one superstep per graph: workgroup q counts graph q's switch
+// states into acc[4q .. 4q+3] = legal, loop, exists, P_L (one workgroup per
+// graph, so plain read-modify-writes).
+__global__ __launch_bounds__(kBlock) void k_graph_stats(const uint8_t *__restrict__ st,
+                                                        const BatchGraph *__restrict__ gr,
+                                                        unsigned long long *__restrict__ acc) {
+    __shared__ uint32_t cnt[4];
+    const uint32_t q = blockIdx.x, tid = threadIdx.x;
+    if (tid < 4) cnt[tid] = 0;
+    __syncthreads();
+    const BatchGraph b = gr[q];
+    const uint32_t k0 = b.poff >> 1, k1 = (b.poff + b.mpad) >> 1;
+    uint32_t c[4] = {0, 0, 0, 0};
+    for (uint32_t k = k0 + tid; k < k1; k += kBlock) {
+        const uint8_t s = st[k];
+        c[0] += s == ST_LEGAL;
+        c[1] += s == ST_LOOP;
+        c[2] += s == ST_EXISTS;
+        c[3] += s == ST_PL;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (c[j]) atomicAdd(&cnt[j], c[j]);
+    __syncthreads();
+    if (tid < 4) acc[4 * (size_t)q + tid] += cnt[tid];
+}
+
+// Record at position p -> out[input position] = key with the graph's vertex
+// shift removed.  Skipped entirely if an error flag is set (output untouched).
+__global__ __launch_bounds__(kBlock) void k_unpermute_batch(const uint32_t *__restrict__ idx,
+                                                            const unsigned long long *__restrict__ key,
+                                                            const uint32_t *__restrict__ pg,
+                                                            const BatchGraph *__restrict__ gr, uint32_t total,
+                                                            unsigned long long *__restrict__ out,
+                                                            const uint32_t *__restrict__ err) {
+    if (*err) return;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+        const uint32_t i = idx[p];
+        if (i == kPadIdx) continue;
+        const uint64_t vb = gr[pg[p]].vbase;
+        out[i] = key[p] - ((vb << 32) | vb);
+    }
+}
+
+}  // namespace gesmc

@@ -75,8 +75,46 @@ __device__ __forceinline__ uint64_t ekey(uint32_t a, uint32_t b) {
     return ((uint64_t)lo << 32) | hi;
 }
 
-// Per-switch outcome codes (also the status array of a superstep).
-enum : uint8_t { ST_UNDECIDED = 0, ST_LEGAL = 1, ST_LOOP = 2, ST_EXISTS = 3, ST_PL = 4 };
+// Per-switch outcome codes (also the status array of a superstep).  ST_IDLE
+// marks a pair holding a graph's padding record in a batch (no attempt).
+enum : uint8_t { ST_UNDECIDED = 0, ST_LEGAL = 1, ST_LOOP = 2, ST_EXISTS = 3, ST_PL = 4, ST_IDLE = 5 };
+
+// ---------------------------------------------------------------------------
+// Batches of independent graphs.  Graph vertex ids are shifted by a per-graph
+// base so that the batch is one simple graph (a disjoint union) whose
+// switches never mix graphs: every graph owns an even-length segment of the
+// switch positions (a graph of odd m gets one padding record that the
+// permutation places last, so its pair is idle -- the idle position of odd m).
+// The permutation of graph g sorts by (K_i, i) with g's own seed, local
+// index i and superstep t0_g + s; its buckets are numbered globally so that
+// bucket order is (graph, K range).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPadIdx = 0xFFFFFFFFu;  // index of a padding record (its key sorts last)
+
+struct BatchGraph {
+    uint32_t poff;   // first switch position of the graph's segment (even)
+    uint32_t mpad;   // records in the segment: m, +1 if m is odd
+    uint32_t goff;   // first input position (local index = input position - goff)
+    uint32_t vbase;  // vertex id shift
+    uint32_t k0, k1; // Philox key (seed)
+    uint32_t t0;     // superstep of the batch's first superstep
+    uint32_t nb;     // permutation buckets of the graph
+    uint32_t bbase;  // its first global bucket
+    uint32_t m, n;   // edges, vertices
+    uint32_t pad;
+};
+
+// Permutation key of record (input position idx) of graph g in batch superstep s.
+__device__ __forceinline__ uint64_t batch_perm_key(const BatchGraph &g, uint32_t idx, uint32_t s) {
+    if (idx == kPadIdx) return ~0ull;
+    return perm_key(idx - g.goff, g.t0 + s, g.k0, g.k1);
+}
+
+// Global bucket of permutation key K in graph g: monotone in K (fast range
+// reduction of its high word).
+__device__ __forceinline__ uint32_t batch_bucket(const BatchGraph &g, uint64_t K) {
+    return g.bbase + (uint32_t)(((K >> 32) * (uint64_t)g.nb) >> 32);
+}
 
 // ---------------------------------------------------------------------------
 // Dependency table (rebuilt every superstep): open addressing, linear probing,

@@ -12,6 +12,7 @@
 #include "perm_kernels.h"
 #include "switch_kernels.h"
 #include "resolve_kernels.h"
+#include "batch_kernels.h"
 
 using namespace gesmc;
 
@@ -124,6 +125,16 @@ struct gesmc_ctx {
     uint32_t *counts1 = nullptr, *counts2 = nullptr, *partial = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
     uint4 *bslot = nullptr;     // per-block counts of the grid-stride kernels (2 grids)
+    // batches: per graph (rank order) and per position
+    uint64_t cap_g = 0, cap_pos = 0;
+    BatchGraph *gr = nullptr;
+    uint64_t *in_off = nullptr;
+    uint32_t *rank_of = nullptr;
+    unsigned long long *gacc = nullptr;
+    unsigned long long *h_gacc = nullptr;
+    uint32_t *pg = nullptr, *bk = nullptr;
+    std::vector<BatchGraph> h_gr;
+    std::vector<uint32_t> h_rank_of, h_order;
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
     uint64_t ctr_cap = 0;
@@ -324,7 +335,8 @@ size_t scatter_lds_bytes(int dbits) {
     const size_t nd = (size_t)1 << dbits;
     size_t words = 3 * nd + kBlock + 1 + kScatterTile;
     words += words & 1;  // 8-byte alignment of the key stage
-    return words * 4 + (size_t)kScatterTile * 8 + (size_t)kScatterTile * 2;
+    // staged keys, digits and (batch level 1) global buckets
+    return words * 4 + (size_t)kScatterTile * 8 + (size_t)kScatterTile * 2 + (size_t)kScatterTile * 4;
 }
 
 size_t sort_lds_bytes(uint32_t cap) {
@@ -368,13 +380,15 @@ gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
 
 // Two-level MSD radix distribution of the n records (idx/tag, key) in buffer
 // set `src` into `dst` (one level) or via `mid` into `dst` (two levels), by
-// the radix word of kByKeyHash.  Leaves c->coarse_off / c->fine_off as the
-// bucket boundaries; returns the buffer index holding the result in *out.
-template <bool kByKeyHash>
+// the radix word of source kSrc1 (level 1) and kSrc2 (level 2), with the
+// batch arguments ba1 / ba2 of those levels.  Leaves c->coarse_off /
+// c->fine_off as the bucket boundaries; returns the buffer index holding the
+// result in *out.
+template <int kSrc1, int kSrc2>
 gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
-                              int kid_scatter1, int kid_counts2, int kid_scatter2) {
+                              int kid_scatter1, int kid_counts2, int kid_scatter2, BatchArgs ba1, BatchArgs ba2) {
     const uint32_t nd1 = 1u << p.b1;
     const uint32_t nchunks = ceil_div(p.ntiles1, kScanChunk);
     GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
@@ -382,10 +396,10 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, n,
                      p.ntiles1));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;
-    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kByKeyHash>,
-                     dim3(persistent_blocks(c, k_tile_counts<kByKeyHash>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
+    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc1>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
                      (size_t)nd1 * 4, idx[src], key[src], t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
-                     c->lvl1_tiles, c->counts1));
+                     c->lvl1_tiles, c->counts1, ba1));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1, (int)p.b1,
                      c->partial));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kBlock), 0, c->partial, nchunks, (int)p.b1,
@@ -393,10 +407,11 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1,
                      (int)p.b1, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
-    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kByKeyHash>,
-                     dim3(persistent_blocks(c, k_scatter<kByKeyHash>, scatter_lds_bytes(p.b1), p.ntiles1)),
-                     dim3(kBlock), scatter_lds_bytes(p.b1), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0, k1, shift1,
-                     (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err));
+    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc1>, scatter_lds_bytes(p.b1), p.ntiles1)),
+                     dim3(kBlock), scatter_lds_bytes(p.b1), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0,
+                     k1, shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err,
+                     ba1));
     if (p.b2 == 0) {
         *out = dst;
         *bucket_off = c->coarse_off;
@@ -407,27 +422,39 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
     GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
     const int shift2 = 64 - (int)p.bbits;
-    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kByKeyHash>,
-                     dim3(persistent_blocks(c, k_tile_counts<kByKeyHash>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
-                     (size_t)nd2 * 4,
-                     idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first,
-                     c->counts2));
+    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc2>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
+                     (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, c->coarse_off,
+                     c->tile_first, c->counts2, ba2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
-    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kByKeyHash>,
-                     dim3(persistent_blocks(c, k_scatter<kByKeyHash>, scatter_lds_bytes(p.b2), tiles2)),
-                     dim3(kBlock), scatter_lds_bytes(p.b2), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
-                     p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err));
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2>, scatter_lds_bytes(p.b2), tiles2)), dim3(kBlock),
+                     scatter_lds_bytes(p.b2), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+                     p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
     *bucket_off = c->fine_off;
     *nbuckets = p.nfine;
     return GESMC_OK;
 }
 
-// Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t.
-// Returns the buffer index holding the sorted records.
+// One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
+// prefix of the rank order) and the per-position arrays of the batch.
+struct BatchStep {
+    const BatchGraph *gr;      // device, per rank
+    uint32_t ngraphs;          // ranks switched in this superstep
+    uint32_t step;             // batch superstep s (graph g runs its superstep t0_g + s)
+    const uint32_t *pg;        // device: rank of the graph holding each position
+    uint32_t *bk;              // device: global bucket of each record between the radix levels
+    unsigned long long *acc;   // device: per-rank outcome counts (nullable)
+};
+
+// Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t --
+// per graph with its own keys if `bs` describes a batch (plan bits then
+// number the global buckets).  Returns the buffer index holding the sorted
+// records.
 gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1, int src,
-                     int *sorted_out, bool clear_table) {
+                     int *sorted_out, bool clear_table, const BatchStep *bs = nullptr) {
     const uint32_t m = p.m;
     const int X = (src + 1) % 3, Y = (src + 2) % 3;
     const uint64_t tslots = clear_table ? c->tab_slots : 0;
@@ -441,19 +468,31 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
                          p.ntiles1));
         GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(1), dim3(kBlock), sort_lds, c->idx[src], c->key[src],
                          c->idx[X], c->key[X], c->key[Y], t, k0, k1, 0, (const uint32_t *)c->lvl1_seg, 1u, m,
-                         c->sort_cap, c->ctr_step));
+                         c->sort_cap, c->ctr_step, bs ? bs->gr : nullptr, bs ? bs->ngraphs : 0u,
+                         bs ? bs->step : 0u));
         *sorted_out = X;
         return GESMC_OK;
     }
     int dist = 0;
     const uint32_t *boff = nullptr;
     uint32_t nb = 0;
-    GESMC_TRY(radix_distribute<false>(c, s, p, m, t, k0, k1, c->idx, c->key, src, X, p.b2 > 0 ? Y : X, &dist, &boff,
-                                      &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2, KID_SCATTER2));
+    const int mid = X, dst = p.b2 > 0 ? Y : X;
+    if (bs) {
+        const BatchArgs ba1{bs->gr, bs->pg, bs->bk, bs->step, (int)p.bbits};
+        const BatchArgs ba2{bs->gr, bs->bk, nullptr, bs->step, (int)p.bbits};
+        GESMC_TRY((radix_distribute<kSrcBatch, kSrcBucket>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
+                                                           &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
+                                                           KID_SCATTER2, ba1, ba2)));
+    } else {
+        GESMC_TRY((radix_distribute<kSrcPerm, kSrcPerm>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
+                                                        &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
+                                                        KID_SCATTER2, BatchArgs{}, BatchArgs{})));
+    }
     const int sorted = (dist == X) ? Y : X;  // sort into the buffer not holding the buckets
     GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(persistent_blocks(c, k_sort_buckets, sort_lds, nb)),
                      dim3(kBlock), sort_lds, c->idx[dist], c->key[dist], c->idx[sorted], c->key[sorted], c->key[src],
-                     t, k0, k1, (int)p.bbits, boff, nb, m, c->sort_cap, c->ctr_step));
+                     t, k0, k1, (int)p.bbits, boff, nb, m, c->sort_cap, c->ctr_step, bs ? bs->gr : nullptr,
+                     bs ? bs->ngraphs : 0u, bs ? bs->step : 0u));
     *sorted_out = sorted;
     return GESMC_OK;
 }
@@ -465,8 +504,9 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
     int parts = 0;
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
-    GESMC_TRY(radix_distribute<true>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1,
-                                     &parts, &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2));
+    GESMC_TRY((radix_distribute<kSrcHash, kSrcHash>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
+                                                    p.b2 > 0 ? 2 : 1, &parts, &poff, &np, KID_TCOUNTS1, KID_TSCATTER1,
+                                                    KID_TCOUNTS2, KID_TSCATTER2, BatchArgs{}, BatchArgs{})));
     const int scratch = parts == 2 ? 1 : 0;
     const size_t rlds = resolve_lds_bytes(c->sort_cap);
     GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(persistent_blocks(c, k_resolve, rlds, np)),
@@ -477,16 +517,22 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
 
 // One superstep with the partitioned resolution (state in buffer 0).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
-                                   uint32_t pl, uint32_t dup_bit) {
+                                   uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr) {
     int sorted = 0;
-    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false));
+    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs));
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
     // per-block counts of emit and the first round go to slots [0, ge) and [ge, ge + gd)
     const uint32_t ge = grid_stride_blocks(c, (uint64_t)p.ell + 1), gd = grid_stride_blocks(c, p.ell);
-    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
-                     c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot));
+    if (bs)
+        GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit<true>, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
+                         c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot, bs->gr, bs->pg,
+                         bs->step));
+    else
+        GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit<false>, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
+                         c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot,
+                         (const BatchGraph *)nullptr, (const uint32_t *)nullptr, 0u));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
@@ -505,6 +551,9 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
                      c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
                      c->ctr_step, c->err));
+    if (bs && bs->acc)
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_graph_stats, dim3(bs->ngraphs), dim3(kBlock), 0, (const uint8_t *)c->st,
+                         bs->gr, bs->acc));
     return GESMC_OK;
 }
 
@@ -684,6 +733,270 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     return GESMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
+    if (G > c->cap_g) {
+        for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
+        }
+        if (c->h_gacc) (void)hipHostFree(c->h_gacc);
+        c->h_gacc = nullptr;
+        c->cap_g = 0;
+        const uint64_t cap = std::max<uint64_t>(G, 64);
+        GESMC_TRY(dev_alloc((void **)&c->gr, cap * sizeof(BatchGraph)));
+        GESMC_TRY(dev_alloc((void **)&c->in_off, (cap + 1) * 8));
+        GESMC_TRY(dev_alloc((void **)&c->rank_of, cap * 4));
+        GESMC_TRY(dev_alloc((void **)&c->gacc, cap * 4 * 8));
+        if (hipHostMalloc((void **)&c->h_gacc, cap * 4 * 8, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->h_gacc = nullptr;
+            set_error("hipHostMalloc failed");
+            return GESMC_E_NOMEM;
+        }
+        c->cap_g = cap;
+    }
+    if (npos > c->cap_pos) {
+        for (void **q : {(void **)&c->pg, (void **)&c->bk}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
+        }
+        c->cap_pos = 0;
+        const uint64_t cap = std::max<uint64_t>(npos, 1024);
+        GESMC_TRY(dev_alloc((void **)&c->pg, cap * 4));
+        GESMC_TRY(dev_alloc((void **)&c->bk, cap * 4));
+        c->cap_pos = cap;
+    }
+    return GESMC_OK;
+}
+
+gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64_t *d_in, uint64_t *d_out,
+                            const uint64_t *offsets, const uint32_t *nv, const uint64_t *seed, const uint32_t *t0v,
+                            const uint32_t *rv, uint32_t pl, gesmc_stats *stats, gesmc_stats *total) {
+    if (!c) {
+        set_error("null context");
+        return GESMC_E_INVAL;
+    }
+    if (G == 0) {
+        if (total) memset(total, 0, sizeof(*total));
+        return GESMC_OK;
+    }
+    if (!offsets || !nv || !seed || !rv) {
+        set_error("null per-graph array");
+        return GESMC_E_INVAL;
+    }
+    if (G > (1u << kMaxFineBits)) {
+        set_error("G = %u exceeds the limit 2^%u", G, kMaxFineBits);
+        return GESMC_E_RANGE;
+    }
+    if (offsets[0] != 0) {
+        set_error("offsets[0] must be 0");
+        return GESMC_E_INVAL;
+    }
+    uint64_t vsum = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+        if (offsets[g + 1] < offsets[g]) {
+            set_error("offsets decrease at graph %u", g);
+            return GESMC_E_INVAL;
+        }
+        const uint32_t t0 = t0v ? t0v[g] : 0u;
+        if ((uint64_t)t0 + rv[g] > 0x100000000ull) {
+            set_error("graph %u: superstep counter t0 + r overflows 32 bits", g);
+            return GESMC_E_INVAL;
+        }
+        vsum += nv[g];
+    }
+    const uint64_t total_m = offsets[G];
+    if (total_m + G >= kMaxEdges) {
+        set_error("batch of %llu edges exceeds the limit 2^30 - G", (unsigned long long)total_m);
+        return GESMC_E_RANGE;
+    }
+    if (vsum > 0xFFFFFFFEull) {
+        set_error("batch vertex count %llu exceeds 2^32 - 2", (unsigned long long)vsum);
+        return GESMC_E_RANGE;
+    }
+    if (total_m > 0 && (!d_in || !d_out)) {
+        set_error("null edge pointer");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    if (c->strategy != 0) {
+        set_error("batches need the sorted-tuples strategy (GESMC_OPT_STRATEGY 0)");
+        return GESMC_E_INVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    // rank order: switched graphs (m >= 2, r >= 1) by r descending, then the rest
+    auto m_of = [&](uint32_t g) { return offsets[g + 1] - offsets[g]; };
+    auto r_eff = [&](uint32_t g) { return m_of(g) >= 2 ? rv[g] : 0u; };
+    std::vector<uint32_t> &order = c->h_order;
+    order.resize(G);
+    for (uint32_t g = 0; g < G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return r_eff(a) > r_eff(b); });
+    std::vector<BatchGraph> &gr = c->h_gr;
+    gr.assign(G, BatchGraph{});
+    c->h_rank_of.assign(G, 0);
+    uint64_t poff = 0, vbase = 0, bbase = 0;
+    uint32_t nactive = 0, rmax = 0;
+    bool need_validation = false;
+    for (uint32_t q = 0; q < G; ++q) {
+        const uint32_t g = order[q];
+        const uint64_t m = m_of(g);
+        const bool active = r_eff(g) > 0;
+        BatchGraph &b = gr[q];
+        b.poff = (uint32_t)poff;
+        b.mpad = (uint32_t)(m + (active ? (m & 1) : 0));
+        b.goff = (uint32_t)offsets[g];
+        b.vbase = (uint32_t)vbase;
+        b.k0 = (uint32_t)seed[g];
+        b.k1 = (uint32_t)(seed[g] >> 32);
+        b.t0 = t0v ? t0v[g] : 0u;
+        b.nb = active ? (uint32_t)std::max<uint64_t>(1, ceil_div((uint32_t)b.mpad, c->bucket_avg)) : 0u;
+        b.bbase = (uint32_t)bbase;
+        b.m = (uint32_t)m;
+        b.n = nv[g];
+        c->h_rank_of[g] = q;
+        poff += b.mpad;
+        vbase += nv[g];
+        bbase += b.nb;
+        if (active) {
+            ++nactive;
+            rmax = std::max(rmax, rv[g]);
+        } else if (m >= 2) {
+            need_validation = true;  // never switched: duplicates are checked up front
+        }
+    }
+    if (bbase > (1ull << kMaxFineBits)) {
+        set_error("batch needs %llu permutation buckets (limit 2^%u): raise GESMC_OPT_BUCKET_AVG",
+                  (unsigned long long)bbase, kMaxFineBits);
+        return GESMC_E_RANGE;
+    }
+    const uint32_t npos = (uint32_t)poff;
+    GESMC_TRY(ensure_capacity(c, npos));
+    GESMC_TRY(ensure_counters(c, rmax));
+    GESMC_TRY(ensure_batch(c, G, npos));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->in_off, offsets, (G + 1) * 8ull, hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->rank_of, c->h_rank_of.data(), G * 4ull, hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
+    const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(rmax, 1) * (sizeof(StepCounters) / 4);
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr, zero_words - 64));
+    if (stats)
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
+                         (uint64_t)G * 8));
+    uint32_t *bad_pos = c->err + 4;
+    if (total_m > 0) {
+        GESMC_TRY(launch(c, s, KID_LOAD, total_m, k_load_batch, dim3(grid_stride_blocks(c, total_m)), dim3(kBlock), 0,
+                         (const unsigned long long *)d_in, (uint32_t)total_m, (const uint64_t *)c->in_off, G,
+                         (const uint32_t *)c->rank_of, (const BatchGraph *)c->gr, c->idx[0], c->key[0], c->err,
+                         bad_pos));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                         (const BatchGraph *)c->gr, G, npos, c->pg));
+    }
+    if (need_validation) {
+        c->ctr_step = c->ctr;
+        GESMC_TRY(launch(c, s, KID_EMIT, npos, k_emit_sources, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                         (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
+        GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP));
+    }
+    // superstep s switches the ranks [0, active_s): those with r > s
+    uint32_t qa = nactive;
+    for (uint32_t st = 0; st < rmax; ++st) {
+        while (qa > 0 && r_eff(order[qa - 1]) <= st) --qa;
+        const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
+        const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
+        Plan p;
+        p.m = P;
+        p.ell = P / 2;
+        uint32_t B = 0;
+        while ((1ull << B) < NB) ++B;
+        p.bbits = B;
+        p.b1 = std::min<uint32_t>(B, 8);
+        p.b2 = B - p.b1;
+        p.ncoarse = 1u << p.b1;
+        p.nfine = 1u << B;
+        p.ntiles1 = std::max<uint32_t>(1, ceil_div(P, kScatterTile));
+        BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr};
+        c->ctr_step = c->ctr + st;
+        GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
+    }
+    if (total_m > 0)
+        GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_unpermute_batch, dim3(grid_stride_blocks(c, npos)), dim3(kBlock),
+                         0, (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0],
+                         (const uint32_t *)c->pg, (const BatchGraph *)c->gr, npos, (unsigned long long *)d_out,
+                         (const uint32_t *)c->err));
+    GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    if (rmax > 0)
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters) * rmax, hipMemcpyDeviceToHost, s),
+                            "hipMemcpyAsync"));
+    if (stats)
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, (size_t)G * 32, hipMemcpyDeviceToHost, s),
+                            "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    if (c->profile) collect_profile(c);
+    const uint32_t e = c->h_err[0];
+    if (e) {
+        const gesmc_status st = map_err(e);
+        const uint32_t bp = c->h_err[4];
+        if (bp && (e & (ERR_LOOP | ERR_RANGE))) {
+            const uint64_t pos = ~bp;
+            const uint32_t g = (uint32_t)(std::upper_bound(offsets, offsets + G + 1, pos) - offsets) - 1;
+            set_error("graph %u, edge %llu: %s", g, (unsigned long long)(pos - offsets[g]),
+                      st == GESMC_E_RANGE ? "vertex id out of range" : "input is not a simple graph (loop)");
+        } else if (e & ERR_DUP) {
+            set_error("a graph of the batch is not simple (duplicate edge)");
+        }
+        return st;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->call_a, c->call_b) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = 0.f;
+    }
+    if (stats) {
+        for (uint32_t g = 0; g < G; ++g) {
+            const uint32_t q = c->h_rank_of[g];
+            gesmc_stats &o = stats[g];
+            memset(&o, 0, sizeof(o));
+            const uint32_t rg = r_eff(g);
+            o.supersteps = rv[g];
+            o.attempts = (uint64_t)rg * (m_of(g) / 2);
+            o.legal = c->h_gacc[4 * (size_t)q + 0];
+            o.rej_loop = c->h_gacc[4 * (size_t)q + 1];
+            o.rej_exists = c->h_gacc[4 * (size_t)q + 2];
+            o.rej_pl = c->h_gacc[4 * (size_t)q + 3];
+            for (uint32_t st = 0; st < rg; ++st) {
+                o.rounds_sum += c->h_ctr[st].rounds;
+                o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)c->h_ctr[st].rounds);
+            }
+            o.ms_device = ms;
+        }
+    }
+    if (total) {
+        memset(total, 0, sizeof(*total));
+        total->supersteps = rmax;
+        for (uint32_t g = 0; g < G; ++g) total->attempts += (uint64_t)r_eff(g) * (m_of(g) / 2);
+        for (uint32_t st = 0; st < rmax; ++st) {
+            const StepCounters &h = c->h_ctr[st];
+            total->legal += h.legal;
+            total->rej_loop += h.rej_loop;
+            total->rej_exists += h.rej_exists;
+            total->rej_pl += h.rej_pl;
+            total->rounds_sum += h.rounds;
+            total->rounds_max = std::max<uint32_t>(total->rounds_max, (uint32_t)h.rounds);
+        }
+        total->ms_device = ms;
+    }
+    return GESMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -735,10 +1048,9 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sort_lds_bytes(kSortMaxItems * kBlock));
-    (void)hipFuncSetAttribute((const void *)k_scatter<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)scatter_lds_bytes(12));
-    (void)hipFuncSetAttribute((const void *)k_scatter<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)scatter_lds_bytes(12));
+    for (const void *f : {(const void *)k_scatter<kSrcPerm>, (const void *)k_scatter<kSrcHash>,
+                          (const void *)k_scatter<kSrcBatch>, (const void *)k_scatter<kSrcBucket>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds_bytes(12));
     (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)resolve_lds_bytes(kSortMaxItems * kBlock));
     (void)hipGetLastError();
@@ -762,6 +1074,10 @@ void gesmc_destroy(gesmc_ctx *c) {
     free_buffers(c);
     if (c->small) (void)hipFree(c->small);
     if (c->bslot) (void)hipFree(c->bslot);
+    for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
+                    (void *)c->bk})
+        if (q) (void)hipFree(q);
+    if (c->h_gacc) (void)hipHostFree(c->h_gacc);
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
@@ -769,6 +1085,16 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->call_a) (void)hipEventDestroy(c->call_a);
     if (c->call_b) (void)hipEventDestroy(c->call_b);
     delete c;
+}
+
+gesmc_status gesmc_run_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uint64_t *d_in, uint64_t *d_out,
+                             const uint64_t *offsets, const uint32_t *n, const uint64_t *seed, const uint32_t *t0,
+                             const uint32_t *r, uint32_t pl, uint32_t flags, gesmc_stats *stats, gesmc_stats *total) {
+    if (flags != 0) {
+        set_error("flags must be 0");
+        return GESMC_E_INVAL;
+    }
+    return run_batch_impl(ctx, stream, G, d_in, d_out, offsets, n, seed, t0, r, pl, stats, total);
 }
 
 gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,

@@ -113,15 +113,42 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
     return lo;
 }
 
-// Radix source of a record: kByKeyHash = false sorts edge records by the
-// Philox key of their index (the permutation); true sorts (tag, edge key)
-// tuples by a hash of the edge key (the dependency partitions), where an
-// empty key marks a tuple slot that carries nothing.
-template <bool kByKeyHash>
-__device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t t, uint32_t k0,
-                                               uint32_t k1) {
-    if (kByKeyHash) return slot_hash(key);
-    return perm_key(idx, t, k0, k1);
+// Radix source of a record.  kSrcPerm sorts edge records by the Philox key
+// of their index (the permutation); kSrcHash sorts (tag, edge key) tuples by
+// a hash of the edge key (the dependency partitions), where an empty key
+// marks a tuple slot that carries nothing.  A batch of graphs sorts by the
+// global bucket (graph, K range) of each record: kSrcBatch computes it from
+// the graph of the record's position (level 1) and writes it out beside the
+// record, kSrcBucket reads it back (level 2).  Bucket numbers are placed in
+// the top B bits of the radix word, so both levels use the same shifts.
+enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3 };
+
+struct BatchArgs {
+    const BatchGraph *gr;    // per graph (kSrcBatch)
+    const uint32_t *aux_in;  // kSrcBatch: graph of each position; kSrcBucket: bucket of each position
+    uint32_t *aux_out;       // kSrcBatch: bucket of each output position
+    uint32_t step;           // batch superstep
+    int bbits;               // bucket bits B (1 .. 32)
+};
+
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_reads_idx() { return kSrc == kSrcPerm || kSrc == kSrcBatch; }
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcBatch || kSrc == kSrcBucket; }
+
+// Radix word of one record; *bucket receives the global bucket (kSrcBatch).
+template <int kSrc>
+__device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t aux, uint32_t t,
+                                               uint32_t k0, uint32_t k1, const BatchArgs &ba, uint32_t *bucket) {
+    if (kSrc == kSrcHash) return slot_hash(key);
+    if (kSrc == kSrcPerm) return perm_key(idx, t, k0, k1);
+    uint32_t b = aux;
+    if (kSrc == kSrcBatch) {
+        const BatchGraph &g = ba.gr[aux];
+        b = batch_bucket(g, batch_perm_key(g, idx, ba.step));
+        *bucket = b;
+    }
+    return (uint64_t)b << (64 - ba.bbits);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,44 +182,40 @@ constexpr int kTileItems = kScatterTile / kBlock;
 
 // Tiles are processed by persistent workgroups; the records of the next
 // tile are loaded into registers while the current one is counted.
-template <bool kByKeyHash>
+template <int kSrc>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restrict__ src_idx,
                                                         const unsigned long long *__restrict__ src_key, uint32_t t,
                                                         uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
                                                         const uint32_t *__restrict__ seg_off,
                                                         const uint32_t *__restrict__ tile_first,
-                                                        uint32_t *__restrict__ counts) {
+                                                        uint32_t *__restrict__ counts, BatchArgs ba) {
     extern __shared__ uint32_t hs[];
     const uint32_t nt = tile_first[nseg];
     const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
     uint32_t w = blockIdx.x;
     if (w >= nt) return;
     TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
-    uint32_t cur_i[kTileItems];
+    uint32_t cur_i[kTileItems], cur_a[kTileItems];
     unsigned long long cur_k[kTileItems];
+    auto load = [&](const TileSpan &sp, uint32_t *ri, unsigned long long *rk, uint32_t *ra) {
 #pragma unroll
-    for (int q = 0; q < kTileItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        if (kByKeyHash)
-            cur_k[q] = p < ts.cnt ? src_key[ts.begin + p] : kEmptyKey;
-        else
-            cur_i[q] = p < ts.cnt ? src_idx[ts.begin + p] : 0u;
-    }
+        for (int q = 0; q < kTileItems; ++q) {
+            const uint32_t p = tid + q * kBlock;
+            const bool in = p < sp.cnt;
+            if (kSrc == kSrcHash) rk[q] = in ? src_key[sp.begin + p] : kEmptyKey;
+            if (src_reads_idx<kSrc>()) ri[q] = in ? src_idx[sp.begin + p] : 0u;
+            if (src_reads_aux<kSrc>()) ra[q] = in ? ba.aux_in[sp.begin + p] : 0u;
+        }
+    };
+    load(ts, cur_i, cur_k, cur_a);
     for (;;) {
         const uint32_t wn = w + gridDim.x;
         TileSpan tn = ts;
-        uint32_t nxt_i[kTileItems];
+        uint32_t nxt_i[kTileItems], nxt_a[kTileItems];
         unsigned long long nxt_k[kTileItems];
         if (wn < nt) {
             tn = tile_span(seg_off, tile_first, nseg, wn);
-#pragma unroll
-            for (int q = 0; q < kTileItems; ++q) {
-                const uint32_t p = tid + q * kBlock;
-                if (kByKeyHash)
-                    nxt_k[q] = p < tn.cnt ? src_key[tn.begin + p] : kEmptyKey;
-                else
-                    nxt_i[q] = p < tn.cnt ? src_idx[tn.begin + p] : 0u;
-            }
+            load(tn, nxt_i, nxt_k, nxt_a);
         }
         for (uint32_t d = tid; d < nd; d += kBlock) hs[d] = 0;
         lds_barrier();
@@ -200,12 +223,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         for (int q = 0; q < kTileItems; ++q) {
             const uint32_t p = tid + q * kBlock;
             if (p >= ts.cnt) continue;
-            if (kByKeyHash) {
-                if (cur_k[q] == kEmptyKey) continue;
-                atomicAdd(&hs[(uint32_t)(radix_word<true>(0, cur_k[q], t, k0, k1) >> shift) & dmask], 1u);
-            } else {
-                atomicAdd(&hs[(uint32_t)(radix_word<false>(cur_i[q], 0, t, k0, k1) >> shift) & dmask], 1u);
-            }
+            if (kSrc == kSrcHash && cur_k[q] == kEmptyKey) continue;
+            uint32_t bk = 0;
+            const uint64_t word = radix_word<kSrc>(cur_i[q], cur_k[q], cur_a[q], t, k0, k1, ba, &bk);
+            atomicAdd(&hs[(uint32_t)(word >> shift) & dmask], 1u);
         }
         lds_barrier();
         for (uint32_t d = tid; d < nd; d += kBlock) counts[(size_t)w * nd + d] = hs[d];
@@ -215,10 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         ts = tn;
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
-            if (kByKeyHash)
-                cur_k[q] = nxt_k[q];
-            else
-                cur_i[q] = nxt_i[q];
+            cur_i[q] = nxt_i[q];
+            cur_k[q] = nxt_k[q];
+            cur_a[q] = nxt_a[q];
         }
     }
 }
@@ -330,16 +350,17 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
     if (s == nseg - 1 && threadIdx.x == 0) fine_off[(size_t)nseg << dbits] = coarse_off[nseg];
 }
 
-// LDS-staged scatter of one tile of a segment by digit (K >> shift) & mask.
+// LDS-staged scatter of one tile of a segment by digit (word >> shift) & mask.
 // Records of one digit leave the workgroup as one contiguous run starting at
-// the run base offs[w][d].  With kByKeyHash, tuple slots whose key is empty
-// are dropped.  Persistent workgroups: the next tile's records and run bases
-// are loaded into registers while the current tile is staged in LDS.
-// Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then the staged
-// records.
+// the run base offs[w][d].  With kSrcHash, tuple slots whose key is empty
+// are dropped; with kSrcBatch the record's global bucket is written to
+// ba.aux_out beside it.  Persistent workgroups: the next tile's records and
+// run bases are loaded into registers while the current tile is staged in
+// LDS.  Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then the
+// staged records (scatter_lds_bytes on the host).
 constexpr int kScatterOffRegs = 4;  // run bases prefetched per thread (2^dbits <= 1024)
 
-template <bool kByKeyHash>
+template <int kSrc>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
                                                     uint32_t *__restrict__ dst_idx,
@@ -347,7 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     uint32_t k1, int shift, int dbits, uint32_t nseg,
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ tile_first,
-                                                    const uint32_t *__restrict__ offs, uint32_t *__restrict__ err) {
+                                                    const uint32_t *__restrict__ offs, uint32_t *__restrict__ err,
+                                                    BatchArgs ba) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_total;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
@@ -359,6 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
     unsigned long long *s_key =
         reinterpret_cast<unsigned long long *>(s_idx + kScatterTile + ((kBlock + 1 + 3 * nd + kScatterTile) & 1));
     uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kScatterTile);
+    uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kScatterTile);  // kSrcBatch only
 
     const uint32_t nt = tile_first[nseg];
     const uint32_t tid = threadIdx.x;
@@ -366,51 +389,48 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
     if (w >= nt) return;
 
     TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
-    uint32_t c_idx[kTileItems], c_off[kScatterOffRegs];
+    uint32_t c_idx[kTileItems], c_aux[kTileItems], c_off[kScatterOffRegs];
     unsigned long long c_key[kTileItems];
+    auto load = [&](const TileSpan &sp, uint32_t wt, uint32_t *ri, unsigned long long *rk, uint32_t *ra,
+                    uint32_t *ro) {
 #pragma unroll
-    for (int q = 0; q < kTileItems; ++q) {
-        const uint32_t p = tid + q * kBlock;
-        c_idx[q] = p < ts.cnt ? src_idx[ts.begin + p] : 0u;
-        c_key[q] = p < ts.cnt ? src_key[ts.begin + p] : kEmptyKey;
-    }
+        for (int q = 0; q < kTileItems; ++q) {
+            const uint32_t p = tid + q * kBlock;
+            const bool in = p < sp.cnt;
+            ri[q] = in ? src_idx[sp.begin + p] : 0u;
+            rk[q] = in ? src_key[sp.begin + p] : kEmptyKey;
+            if (src_reads_aux<kSrc>()) ra[q] = in ? ba.aux_in[sp.begin + p] : 0u;
+        }
 #pragma unroll
-    for (int j = 0; j < kScatterOffRegs; ++j) {
-        const uint32_t d = tid + j * kBlock;
-        c_off[j] = d < nd ? offs[(size_t)w * nd + d] : 0u;
-    }
+        for (int j = 0; j < kScatterOffRegs; ++j) {
+            const uint32_t d = tid + j * kBlock;
+            ro[j] = d < nd ? offs[(size_t)wt * nd + d] : 0u;
+        }
+    };
+    load(ts, w, c_idx, c_key, c_aux, c_off);
 
     for (;;) {
         const uint32_t wn = w + gridDim.x;
         TileSpan tn = ts;
-        uint32_t n_idx[kTileItems], n_off[kScatterOffRegs];
+        uint32_t n_idx[kTileItems], n_aux[kTileItems], n_off[kScatterOffRegs];
         unsigned long long n_key[kTileItems];
         if (wn < nt) {
             tn = tile_span(seg_off, tile_first, nseg, wn);
-#pragma unroll
-            for (int q = 0; q < kTileItems; ++q) {
-                const uint32_t p = tid + q * kBlock;
-                n_idx[q] = p < tn.cnt ? src_idx[tn.begin + p] : 0u;
-                n_key[q] = p < tn.cnt ? src_key[tn.begin + p] : kEmptyKey;
-            }
-#pragma unroll
-            for (int j = 0; j < kScatterOffRegs; ++j) {
-                const uint32_t d = tid + j * kBlock;
-                n_off[j] = d < nd ? offs[(size_t)wn * nd + d] : 0u;
-            }
+            load(tn, wn, n_idx, n_key, n_aux, n_off);
         }
 
         for (uint32_t d = tid; d < nd; d += kBlock) cnt[d] = 0;
         if (tid == 0) s_total = 0;
         lds_barrier();
-        uint32_t r_dig[kTileItems], r_rank[kTileItems];
+        uint32_t r_dig[kTileItems], r_rank[kTileItems], r_bkt[kTileItems];
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
             const uint32_t p = tid + q * kBlock;
             r_dig[q] = 0xFFFFFFFFu;
-            if (p < ts.cnt && (!kByKeyHash || c_key[q] != kEmptyKey)) {
-                const uint64_t K = radix_word<kByKeyHash>(c_idx[q], c_key[q], t, k0, k1);
-                r_dig[q] = (uint32_t)(K >> shift) & dmask;
+            r_bkt[q] = 0;
+            if (p < ts.cnt && (kSrc != kSrcHash || c_key[q] != kEmptyKey)) {
+                const uint64_t word = radix_word<kSrc>(c_idx[q], c_key[q], c_aux[q], t, k0, k1, ba, &r_bkt[q]);
+                r_dig[q] = (uint32_t)(word >> shift) & dmask;
                 r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
             }
         }
@@ -432,6 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                 s_idx[lp] = c_idx[q];
                 s_key[lp] = c_key[q];
                 s_dig[lp] = (uint16_t)r_dig[q];
+                if (kSrc == kSrcBatch) s_bkt[lp] = r_bkt[q];
                 ++mine;
             }
         }
@@ -444,6 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
             if (g >= ts.seg_begin && g < ts.seg_end) {
                 dst_idx[g] = s_idx[lp];
                 dst_key[g] = s_key[lp];
+                if (kSrc == kSrcBatch) ba.aux_out[g] = s_bkt[lp];
             } else {
                 atomicOr(err, ERR_INTERNAL);
             }
@@ -456,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         for (int q = 0; q < kTileItems; ++q) {
             c_idx[q] = n_idx[q];
             c_key[q] = n_key[q];
+            c_aux[q] = n_aux[q];
         }
 #pragma unroll
         for (int j = 0; j < kScatterOffRegs; ++j) c_off[j] = n_off[j];
@@ -476,7 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
                                                          unsigned long long *__restrict__ scratch_k, uint32_t t,
                                                          uint32_t k0, uint32_t k1, int bbits,
                                                          const uint32_t *__restrict__ fine_off, uint32_t nb,
-                                                         uint32_t m, uint32_t cap, StepCounters *__restrict__ ctr) {
+                                                         uint32_t m, uint32_t cap, StepCounters *__restrict__ ctr,
+                                                         const BatchGraph *__restrict__ gr, uint32_t ngraphs,
+                                                         uint32_t step) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t kCells = 1u << kSortSubBits;
     uint32_t *cell = lds;                    // kCells
@@ -514,9 +539,31 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
             }
         }
         const uint32_t c = end > begin ? end - begin : 0;
+        // batch: the graph owning bucket f (largest g with bbase <= f); its
+        // buckets split the high word of K by fast range reduction, so the
+        // cell is the top of the remainder of that reduction
+        BatchGraph bg{};
+        if (gr && c > 0) {
+            uint32_t lo = 0, hi = ngraphs - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (gr[mid].bbase <= f)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            bg = gr[lo];
+        }
+        auto key_of = [&](uint32_t idx) -> uint64_t {
+            return gr ? batch_perm_key(bg, idx, step) : perm_key(idx, t, k0, k1);
+        };
+        auto cell_of = [&](uint64_t K) -> uint32_t {
+            if (gr) return ((uint32_t)((K >> 32) * (uint64_t)bg.nb)) >> (32 - kSortSubBits);
+            return (uint32_t)((bbits >= 64 ? 0ull : (K << bbits)) >> sub_shift);
+        };
         if (c > lds_cap) {
             // exact slow path: rank_p = #{q : (K_q, i_q) < (K_p, i_p)}
-            for (uint32_t p = tid; p < c; p += kBlock) scratch_k[begin + p] = perm_key(src_idx[begin + p], t, k0, k1);
+            for (uint32_t p = tid; p < c; p += kBlock) scratch_k[begin + p] = key_of(src_idx[begin + p]);
             __threadfence_block();
             __syncthreads();
             for (uint32_t p = tid; p < c; p += kBlock) {
@@ -542,8 +589,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
             for (int q = 0; q < kSortMaxItems; ++q) {
                 const uint32_t p = tid + q * kBlock;
                 if (p < c) {
-                    r_K[q] = perm_key(c_idx[q], t, k0, k1);
-                    r_cell[q] = (uint32_t)((bbits >= 64 ? 0ull : (r_K[q] << bbits)) >> sub_shift);
+                    r_K[q] = key_of(c_idx[q]);
+                    r_cell[q] = cell_of(r_K[q]);
                     r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
                 }
             }

@@ -42,12 +42,15 @@ constexpr uint32_t kNoPred = 0xFFFFFFFFu;
 // get an empty key.  Also: records of locally rejected switches, the free
 // target records.
 // ---------------------------------------------------------------------------
+template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
                                                  const unsigned long long *__restrict__ s_key, uint32_t m, uint32_t t,
                                                  uint32_t k0, uint32_t k1, uint32_t pl, uint32_t *__restrict__ tu_tag,
                                                  unsigned long long *__restrict__ tu_key, uint2 *__restrict__ info,
                                                  uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
-                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot) {
+                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot,
+                                                 const BatchGraph *__restrict__ gr, const uint32_t *__restrict__ pg,
+                                                 uint32_t step) {
     __shared__ BlockCounts bc;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
@@ -68,7 +71,19 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         const unsigned long long e1 = ee.x, e2 = ee.y;
         uint8_t status = ST_UNDECIDED;
         Targets T{0, 0, false};
-        if (pl_skip(k, t, pl, k0, k1)) {
+        bool skip = false;
+        if (kBatch) {
+            if (i == kPadIdx || j == kPadIdx) {
+                status = ST_IDLE;
+            } else if (pl != 0) {
+                const BatchGraph &g = gr[pg[2 * (size_t)k]];
+                skip = pl_skip(k - (g.poff >> 1), g.t0 + step, pl, g.k0, g.k1);
+            }
+        } else {
+            skip = pl_skip(k, t, pl, k0, k1);
+        }
+        if (status == ST_IDLE) {
+        } else if (skip) {
             status = ST_PL;
         } else {
             T = switch_targets(e1, e2, i < j);
@@ -79,7 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         }
         const uint32_t etag = status == ST_UNDECIDED ? k : kTagStays;
         ulonglong2 *tk = reinterpret_cast<ulonglong2 *>(tu_key) + 2 * (size_t)k;
-        tk[0] = make_ulonglong2(e1, e2);
+        // a padding record carries no edge: its slot gets the empty key
+        tk[0] = make_ulonglong2(i == kPadIdx ? kEmptyKey : e1, j == kPadIdx ? kEmptyKey : e2);
         if (status == ST_UNDECIDED) {
             reinterpret_cast<uint4 *>(tu_tag)[k] =
                 make_uint4(etag, etag, kTagInsert | (k << 1), kTagInsert | (k << 1) | 1u);

@@ -1,0 +1,212 @@
+"""Batched form (gesmc_run_batch) through the C ABI against the oracle.
+
+A batch has no arithmetic of its own: every graph is an independent chain, so
+each graph's slice of the output must equal the oracle run on that graph
+alone, bit for bit, together with its outcome counts.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_03005_amd as gesmc
+    c = gesmc.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(E):
+    return torch.from_numpy(np.ascontiguousarray(E, dtype=np.uint64).view(np.int64).copy()).to("cuda")
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def key(a, b):
+    return (min(a, b) << 32) | max(a, b)
+
+
+def keys(pairs):
+    return np.array([key(a, b) for a, b in pairs], dtype=np.uint64).reshape(-1)
+
+
+def special_graphs():
+    """Degenerate members: empty, one edge, two disjoint edges, odd m, a star
+    (every switch shares a vertex), a complete graph (every target exists)."""
+    return [
+        (np.zeros(0, dtype=np.uint64), 3),
+        (keys([(0, 2)]), 3),
+        (keys([(0, 1), (2, 3)]), 4),
+        (keys([(0, 1), (2, 3), (4, 5)]), 6),
+        (keys([(0, v) for v in range(1, 60)]), 60),
+        (keys([(a, b) for a in range(12) for b in range(a + 1, 12)]), 12),
+    ]
+
+
+def run_batch(ctx, graphs, seeds, rs, t0s=None, pl=0):
+    E, offs, ns = graphgen.concat(graphs)
+    print("batch: G=%d total m=%d pl=%d" % (len(graphs), offs[-1], pl), flush=True)
+    out, stats, tot = ctx.run_batch(to_dev(E), offs, ns, seeds, rs, t0=t0s, pl=pl)
+    return to_host(out), offs, stats, tot
+
+
+def check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, pl, ids):
+    for g in ids:
+        E, n = graphs[g]
+        t0 = 0 if t0s is None else t0s[g]
+        rc, exp, counts, _ = oracle.run(E, n, seeds[g], t0, rs[g], pl)
+        assert rc == 0
+        sl = got[offs[g]:offs[g + 1]]
+        diff = np.flatnonzero(sl != exp)
+        assert diff.size == 0, "graph %d (m=%d n=%d r=%d): %d positions differ" % (g, len(E), n, rs[g], diff.size)
+        s = stats[g]
+        assert s["attempts"] == sum(c["attempts"] for c in counts), g
+        for k in ("legal", "rej_loop", "rej_exists", "rej_pl"):
+            assert s[k] == sum(c[k] for c in counts), (g, k, s)
+
+
+def mixed_batch(seed=7, G=40):
+    graphs = graphgen.batch_graphs(G, seed, 1e2, 3e3) + special_graphs()
+    rng = np.random.default_rng(seed)
+    seeds = [int(x) for x in rng.integers(0, 2**63, len(graphs))]
+    rs = [int(x) for x in rng.integers(0, 7, len(graphs))]
+    t0s = [int(x) for x in rng.integers(0, 1000, len(graphs))]
+    return graphs, seeds, rs, t0s
+
+
+@pytest.mark.parametrize("pl", [0, 1 << 30])
+def test_mixed_batch_exact(ctx, pl):
+    graphs, seeds, rs, t0s = mixed_batch()
+    got, offs, stats, tot = run_batch(ctx, graphs, seeds, rs, t0s, pl)
+    check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, pl, range(len(graphs)))
+    assert tot["attempts"] == sum(s["attempts"] for s in stats)
+    assert tot["legal"] == sum(s["legal"] for s in stats)
+
+
+def test_batch_equals_single_runs(ctx):
+    """Each graph's result is the same alone (gesmc_run) and in the mix."""
+    graphs, seeds, rs, t0s = mixed_batch(seed=11, G=24)
+    got, offs, _, _ = run_batch(ctx, graphs, seeds, rs, t0s)
+    for g, (E, n) in enumerate(graphs):
+        out, _ = ctx.run(to_dev(E), n, seeds[g], t0=t0s[g], r=rs[g])
+        assert np.array_equal(to_host(out), got[offs[g]:offs[g + 1]]), g
+
+
+def test_batch_order_and_company_do_not_matter(ctx):
+    """Reordering the batch and dropping members leaves every result unchanged."""
+    graphs, seeds, rs, t0s = mixed_batch(seed=13, G=30)
+    got, offs, _, _ = run_batch(ctx, graphs, seeds, rs, t0s)
+    perm = np.random.default_rng(5).permutation(len(graphs))[: len(graphs) // 2]
+    sub = [graphs[g] for g in perm]
+    got2, offs2, _, _ = run_batch(ctx, sub, [seeds[g] for g in perm], [rs[g] for g in perm],
+                                  [t0s[g] for g in perm])
+    for j, g in enumerate(perm):
+        assert np.array_equal(got2[offs2[j]:offs2[j + 1]], got[offs[g]:offs[g + 1]]), g
+
+
+def test_batch_schedule_independence(ctx):
+    """Bucket sizes, the LDS capacity (incl. the slow exact paths) and the
+    number of multi-workgroup rounds never change the result."""
+    import paper_2111_03005_amd as gesmc
+    graphs, seeds, rs, t0s = mixed_batch(seed=17, G=32)
+    ref = None
+    for avg, cap, fr in [(512, 1024, 2), (64, 1024, 0), (64, 64, 1), (768, 96, 4)]:
+        c = gesmc.Context(0)
+        try:
+            c.set_option(gesmc.OPT_BUCKET_AVG, avg)
+            c.set_option(gesmc.OPT_SORT_CAP, cap)
+            c.set_option(gesmc.OPT_FAST_ROUNDS, fr)
+            got, offs, stats, _ = run_batch(c, graphs, seeds, rs, t0s)
+            if ref is None:
+                ref = got
+                check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, 0, range(len(graphs)))
+            assert np.array_equal(got, ref), (avg, cap, fr)
+        finally:
+            c.close()
+
+
+def test_batch_invalid_inputs(ctx):
+    import paper_2111_03005_amd as gesmc
+    good = graphgen.batch_graphs(5, 3, 1e2, 1e3)
+    # (position in the batch, edges, n, r, status, message names the graph)
+    cases = [
+        (3, keys([(0, 1), (1, 2), (0, 1)]), 3, 2, gesmc.E_NOT_SIMPLE, False),   # duplicate, switched graph
+        (3, keys([(0, 1), (1, 2), (0, 1)]), 3, 0, gesmc.E_NOT_SIMPLE, False),   # duplicate, graph with r = 0
+        (1, np.array([(2 << 32) | 2, key(0, 1)], dtype=np.uint64), 3, 2, gesmc.E_NOT_SIMPLE, True),  # loop
+        (4, keys([(0, 1), (1, 7)]), 5, 1, gesmc.E_RANGE, True),                 # id >= n of its graph
+    ]
+    for pos, E, n, r, code, named in cases:
+        graphs = list(good)
+        graphs.insert(pos, (E, n))
+        E_all, offs, ns = graphgen.concat(graphs)
+        sentinel = torch.full((len(E_all),), 777, dtype=torch.int64, device="cuda")
+        with pytest.raises(gesmc.GesmcError) as ei:
+            ctx.run_batch(to_dev(E_all), offs, ns, [1] * len(graphs), [r if g == pos else 2 for g in
+                                                                       range(len(graphs))], out=sentinel)
+        assert ei.value.status == code, (pos, r, ei.value)
+        if named:
+            assert ("graph %d," % pos) in str(ei.value), str(ei.value)
+        assert (sentinel.cpu() == 777).all()
+    # the context stays usable
+    graphs, seeds, rs, t0s = mixed_batch(seed=19, G=8)
+    got, offs, stats, _ = run_batch(ctx, graphs, seeds, rs, t0s)
+    check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, 0, range(len(graphs)))
+
+
+def test_batch_argument_checks(ctx):
+    import paper_2111_03005_amd as gesmc
+    E, offs, ns = graphgen.concat(special_graphs())
+    d = to_dev(E)
+    with pytest.raises(gesmc.GesmcError) as ei:  # offsets must start at 0
+        ctx.run_batch(d, [1] + list(offs[1:]), ns, [1] * len(ns), [1] * len(ns))
+    assert ei.value.status == gesmc.E_INVAL
+    with pytest.raises(gesmc.GesmcError) as ei:  # decreasing offsets
+        bad = list(offs)
+        bad[2], bad[3] = bad[3], bad[2]
+        ctx.run_batch(d, bad, ns, [1] * len(ns), [1] * len(ns))
+    assert ei.value.status == gesmc.E_INVAL
+    c = gesmc.Context(0)
+    try:
+        c.set_option(gesmc.OPT_STRATEGY, gesmc.STRATEGY_HBM_TABLE)
+        with pytest.raises(gesmc.GesmcError) as ei:
+            c.run_batch(d, offs, ns, [1] * len(ns), [1] * len(ns))
+        assert ei.value.status == gesmc.E_INVAL
+    finally:
+        c.close()
+
+
+def test_full_batch_4096_sampled_exact(ctx):
+    """The 4096-graph workload at full size, 20 global switches each, in the
+    benchmark's configuration: a sample of graphs (smallest, largest and
+    random ones) exactly against the oracle, and every graph's degree
+    sequence, simplicity and counts."""
+    graphs = graphgen.workload_batch_4096()
+    G = len(graphs)
+    seeds = [42 + g for g in range(G)]
+    rs = [20] * G
+    got, offs, stats, tot = run_batch(ctx, graphs, seeds, rs)
+    sizes = np.diff(offs)
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} |
+                    {int(x) for x in np.random.default_rng(1).choice(G, 6, replace=False)})
+    check_against_oracle(graphs, got, offs, stats, seeds, rs, None, 0, sample)
+    for g, (E, n) in enumerate(graphs):
+        sl = got[offs[g]:offs[g + 1]]
+        u, v = graphgen.split(sl)
+        assert (u < v).all() and (v < n).all(), g
+        assert len(np.unique(sl)) == len(sl), g
+        assert np.array_equal(graphgen.degrees(sl, n), graphgen.degrees(E, n)), g
+        s = stats[g]
+        assert s["attempts"] == 20 * (len(E) // 2)
+        assert s["legal"] + s["rej_loop"] + s["rej_exists"] + s["rej_pl"] == s["attempts"], g
+    assert tot["attempts"] == sum(20 * (s // 2) for s in sizes)
