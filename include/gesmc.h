@@ -43,6 +43,8 @@ typedef int32_t gesmc_status;
 #define GESMC_E_RANGE (-3)      /* vertex id >= n or 0xFFFFFFFF, or m >= 2^30      */
 #define GESMC_E_NOMEM (-4)      /* device allocation failed                        */
 #define GESMC_E_DEVICE (-5)     /* HIP runtime error                               */
+#define GESMC_E_AGAIN (-6)      /* server: queue full (submit) / not done (poll)   */
+#define GESMC_E_CANCELED (-7)   /* server: the request was cancelled               */
 #define GESMC_E_INTERNAL (-9)   /* an internal consistency check failed            */
 
 typedef struct gesmc_ctx gesmc_ctx;
@@ -109,7 +111,7 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
  * below 2^32 - 1, G <= 2^20, and at most 2^20 permutation buckets (about
  * offsets[G] / GESMC_OPT_BUCKET_AVG + G).  Needs GESMC_OPT_STRATEGY 0.  Any
  * invalid graph fails the whole call with d_out untouched; the message names
- * the graph for loops and out-of-range ids.  flags: reserved, pass 0.
+ * the graph.  flags: reserved, pass 0.
  */
 gesmc_status gesmc_run_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uint64_t *d_in, uint64_t *d_out,
                              const uint64_t *offsets, const uint32_t *n, const uint64_t *seed, const uint32_t *t0,
@@ -131,6 +133,72 @@ gesmc_status gesmc_perm_keys(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t 
 /* The permutation pi of superstep t (Def. 3.2): d_pi[r] (device, m words) is
  * the edge index of rank r in (K_i, i) order. */
 gesmc_status gesmc_permutation(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint32_t *d_pi);
+
+/*
+ * Serving: a request loop with continuous batching.  A worker thread owns the
+ * context; every iteration it admits queued requests in arrival order while
+ * their device footprint fits the HBM budget and the resident-graph limit,
+ * runs one superstep of every resident graph together (the batched form,
+ * each graph at its own superstep), and hands back every graph that has
+ * finished its r supersteps.  Requests that arrive while others run join at
+ * the next iteration; a graph's records stay resident on the device between
+ * its supersteps.  Every result equals gesmc_run on that graph alone.
+ * While a server exists, its context must not be used by other calls.
+ */
+typedef struct gesmc_server gesmc_server;
+
+typedef struct gesmc_server_cfg {
+    uint64_t hbm_budget_bytes; /* device memory for resident graphs (0: 16 GiB); about 136 bytes per
+                                  edge, so at most budget / 136 edges are resident at once           */
+    uint32_t max_graphs;       /* resident graphs at most (0: 4096)                                   */
+    uint32_t max_queue;        /* queued requests at most; submit then returns GESMC_E_AGAIN (0: 2^16) */
+} gesmc_server_cfg;
+
+typedef struct gesmc_request {
+    const uint64_t *edges; /* host memory, m keys as for gesmc_run; copied by gesmc_submit */
+    uint64_t m;
+    uint32_t n;
+    uint32_t t0;
+    uint32_t r;
+    uint32_t pl;
+    uint64_t seed;
+} gesmc_request;
+
+typedef struct gesmc_result {
+    gesmc_status status; /* GESMC_OK, an input error, GESMC_E_CANCELED or GESMC_E_INTERNAL      */
+    uint64_t m;
+    uint64_t *edges;     /* host memory owned by the caller after poll / wait: m keys in position
+                            order (NULL unless status is GESMC_OK); release with gesmc_result_free */
+    gesmc_stats stats;   /* rounds_* are those of the shared supersteps                          */
+    double t_submit, t_admit, t_done; /* seconds on the server's steady clock                      */
+} gesmc_result;
+
+typedef struct gesmc_server_info {
+    uint64_t submitted, completed, iterations, attempts, legal;
+    uint64_t resident_edges;
+    uint32_t queued, resident;
+    double busy_s; /* wall time of the worker's iterations */
+    double now_s;  /* the server clock                      */
+} gesmc_server_info;
+
+/* Starts the worker (cfg nullable: defaults).  Fails with GESMC_E_NOMEM if
+ * the budget cannot be allocated.  *out receives the server. */
+gesmc_status gesmc_server_create(gesmc_ctx *ctx, const gesmc_server_cfg *cfg, gesmc_server **out);
+/* Stops the worker; requests still queued or resident are dropped. */
+void gesmc_server_destroy(gesmc_server *srv);
+/* Queues a request (edges copied; thread-safe).  GESMC_E_AGAIN if the queue is
+ * full, GESMC_E_RANGE if the graph can never fit the budget, GESMC_E_INVAL for
+ * bad arguments.  Input errors of the graph itself are reported in its result. */
+gesmc_status gesmc_submit(gesmc_server *srv, const gesmc_request *req, uint64_t *ticket);
+/* Non-blocking: fills *out and forgets the ticket if the request is done,
+ * else returns GESMC_E_AGAIN.  GESMC_E_INVAL for an unknown ticket. */
+gesmc_status gesmc_poll(gesmc_server *srv, uint64_t ticket, gesmc_result *out);
+/* As gesmc_poll, but blocks until the request is done. */
+gesmc_status gesmc_wait(gesmc_server *srv, uint64_t ticket, gesmc_result *out);
+/* Cancels a queued or resident request; its result then has GESMC_E_CANCELED. */
+gesmc_status gesmc_cancel(gesmc_server *srv, uint64_t ticket);
+void gesmc_result_free(gesmc_result *res);
+gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
 
 /* Tuning knobs (values are validated; results never depend on them). */
 #define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 768, default 512)    */

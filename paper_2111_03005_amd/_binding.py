@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgesmc.so")
 
 OK = 0
-E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_INTERNAL = -1, -2, -3, -4, -5, -9
+E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_AGAIN, E_CANCELED, E_INTERNAL = -1, -2, -3, -4, -5, -6, -7, -9
 OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST, OPT_PROFILE_ONLY = (
     1, 2, 3, 4, 5, 6, 7)
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
@@ -46,9 +46,37 @@ class StepStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_graphs", ctypes.c_uint32),
+                ("max_queue", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("edges", ctypes.c_void_p), ("m", ctypes.c_uint64), ("n", ctypes.c_uint32), ("t0", ctypes.c_uint32),
+                ("r", ctypes.c_uint32), ("pl", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("m", ctypes.c_uint64), ("edges", ctypes.POINTER(ctypes.c_uint64)),
+                ("stats", Stats), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
+                ("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("resident_edges", ctypes.c_uint64),
+                ("queued", ctypes.c_uint32), ("resident", ctypes.c_uint32), ("busy_s", ctypes.c_double),
+                ("now_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_batch",
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
-           "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset"]
+           "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
+           "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
+           "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get"]
 
 _lib = None
 _lock = threading.Lock()
@@ -96,6 +124,21 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_profile_get.restype = i32
         lib.gesmc_profile_reset.argtypes = [vp]
         lib.gesmc_profile_reset.restype = i32
+        lib.gesmc_server_create.argtypes = [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+        lib.gesmc_server_create.restype = i32
+        lib.gesmc_server_destroy.argtypes = [vp]
+        lib.gesmc_server_destroy.restype = None
+        lib.gesmc_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        lib.gesmc_submit.restype = i32
+        for f in (lib.gesmc_poll, lib.gesmc_wait):
+            f.argtypes = [vp, u64, ctypes.POINTER(Result)]
+            f.restype = i32
+        lib.gesmc_cancel.argtypes = [vp, u64]
+        lib.gesmc_cancel.restype = i32
+        lib.gesmc_result_free.argtypes = [ctypes.POINTER(Result)]
+        lib.gesmc_result_free.restype = None
+        lib.gesmc_server_info_get.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+        lib.gesmc_server_info_get.restype = i32
         _lib = lib
         return lib
 
@@ -227,6 +270,71 @@ class Context:
 
     def profile_reset(self):
         _check(_lib.gesmc_profile_reset(self._h))
+
+
+class Server:
+    """Request loop with continuous batching on one context (gesmc_server_*).
+    Requests carry host edge arrays; results come back as host arrays."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_graphs: int = 0, max_queue: int = 0):
+        self.ctx = ctx
+        cfg = ServerCfg(hbm_budget_bytes, max_graphs, max_queue)
+        h = ctypes.c_void_p()
+        _check(_lib.gesmc_server_create(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gesmc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, edges, n: int, seed: int, r: int, t0: int = 0, pl: int = 0) -> int:
+        """Queues a request (edges: numpy uint64 keys, copied).  Raises GesmcError
+        (status E_AGAIN when the queue is full)."""
+        import numpy as np
+        e = np.ascontiguousarray(edges, dtype=np.uint64)
+        req = Request(e.ctypes.data if e.size else None, e.size, n, t0, r, pl, seed & (2**64 - 1))
+        t = ctypes.c_uint64()
+        _check(_lib.gesmc_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _take(res: Result):
+        import numpy as np
+        edges = None
+        if res.status == OK:
+            edges = np.ctypeslib.as_array(res.edges, shape=(max(res.m, 1),))[: res.m].copy()
+            _lib.gesmc_result_free(ctypes.byref(res))
+        return {"status": res.status, "edges": edges, "stats": res.stats.as_dict(), "t_submit": res.t_submit,
+                "t_admit": res.t_admit, "t_done": res.t_done}
+
+    def poll(self, ticket: int):
+        """The result dict if the request is done, else None."""
+        res = Result()
+        st = _lib.gesmc_poll(self._h, ticket, ctypes.byref(res))
+        if st == E_AGAIN:
+            return None
+        _check(st)
+        return self._take(res)
+
+    def wait(self, ticket: int):
+        res = Result()
+        _check(_lib.gesmc_wait(self._h, ticket, ctypes.byref(res)))
+        return self._take(res)
+
+    def cancel(self, ticket: int):
+        _check(_lib.gesmc_cancel(self._h, ticket))
+
+    def info(self):
+        i = ServerInfo()
+        _check(_lib.gesmc_server_info_get(self._h, ctypes.byref(i)))
+        return i.as_dict()
 
 
 _default = {}

@@ -9,7 +9,7 @@ SRC = os.path.join(HERE, "csrc", "gesmc.hip")
 LIB = os.path.join(HERE, "libgesmc.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     # packed FP32 instructions disabled for every HIP code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -34,7 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_load_batch(const unsigned long long 
                                                        const uint32_t *__restrict__ rank_of,
                                                        const BatchGraph *__restrict__ gr, uint32_t *__restrict__ idx,
                                                        unsigned long long *__restrict__ key,
-                                                       uint32_t *__restrict__ err, uint32_t *__restrict__ bad_pos) {
+                                                       uint32_t *__restrict__ err, uint32_t *__restrict__ bad_pos,
+                                                       uint32_t *__restrict__ gerr) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint32_t f = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_load_batch(const unsigned long long 
         if (fe) {
             f |= fe;
             atomicMax(bad_pos, ~(uint32_t)i);
+            atomicOr(&gerr[rank_of[g]], fe);
         }
         if ((uint32_t)i == b.goff && b.mpad > b.m) {  // padding record of an odd switched graph
             idx[b.poff + b.m] = kPadIdx;
@@ -110,6 +112,53 @@ __global__ __launch_bounds__(kBlock) void k_unpermute_batch(const uint32_t *__re
         if (i == kPadIdx) continue;
         const uint64_t vb = gr[pg[p]].vbase;
         out[i] = key[p] - ((vb << 32) | vb);
+    }
+}
+
+// Serving: moves the records of the graphs that stay resident from their old
+// segments (src) into the new layout (dst), re-shifting vertex ids from the
+// old base mv[q].y to the new one.  mv[q].x = old first position, or ~0 for
+// a graph that is loaded into the new layout instead.
+__global__ __launch_bounds__(kBlock) void k_relayout(const BatchGraph *__restrict__ gr, const uint2 *__restrict__ mv,
+                                                     const uint32_t *__restrict__ pg, uint32_t total,
+                                                     const uint32_t *__restrict__ src_idx,
+                                                     const unsigned long long *__restrict__ src_key,
+                                                     uint32_t *__restrict__ dst_idx,
+                                                     unsigned long long *__restrict__ dst_key) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+        const uint32_t q = pg[p];
+        const uint2 m = mv[q];
+        if (m.x == 0xFFFFFFFFu) continue;
+        const uint32_t sp = m.x + ((uint32_t)p - gr[q].poff);
+        const uint32_t i = src_idx[sp];
+        unsigned long long e = src_key[sp];
+        if (i != kPadIdx) {
+            const uint64_t ob = m.y, nb = gr[q].vbase;
+            e = e - ((ob << 32) | ob) + ((nb << 32) | nb);
+        }
+        dst_idx[p] = i;
+        dst_key[p] = e;
+    }
+}
+
+// Serving: the records of every graph q with rb[q] != ~0 go to
+// out[rb[q] + local index] with the vertex shift removed.
+__global__ __launch_bounds__(kBlock) void k_extract(const uint32_t *__restrict__ idx,
+                                                    const unsigned long long *__restrict__ key,
+                                                    const uint32_t *__restrict__ pg,
+                                                    const BatchGraph *__restrict__ gr,
+                                                    const unsigned long long *__restrict__ rb, uint32_t total,
+                                                    unsigned long long *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+        const uint32_t q = pg[p];
+        const unsigned long long base = rb[q];
+        if (base == ~0ull) continue;
+        const uint32_t i = idx[p];
+        if (i == kPadIdx) continue;
+        const uint64_t vb = gr[q].vbase;
+        out[base + (i - gr[q].goff)] = key[p] - ((vb << 32) | vb);
     }
 }
 

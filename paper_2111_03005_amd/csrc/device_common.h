@@ -101,7 +101,7 @@ struct BatchGraph {
     uint32_t nb;     // permutation buckets of the graph
     uint32_t bbase;  // its first global bucket
     uint32_t m, n;   // edges, vertices
-    uint32_t pad;
+    uint32_t pl;     // P_L = pl / 2^32 of the graph
 };
 
 // Permutation key of record (input position idx) of graph g in batch superstep s.

@@ -132,6 +132,7 @@ struct gesmc_ctx {
     uint32_t *rank_of = nullptr;
     unsigned long long *gacc = nullptr;
     unsigned long long *h_gacc = nullptr;
+    uint32_t *gerr = nullptr, *h_gerr = nullptr;
     uint32_t *pg = nullptr, *bk = nullptr;
     std::vector<BatchGraph> h_gr;
     std::vector<uint32_t> h_rank_of, h_order;
@@ -447,6 +448,7 @@ struct BatchStep {
     const uint32_t *pg;        // device: rank of the graph holding each position
     uint32_t *bk;              // device: global bucket of each record between the radix levels
     unsigned long long *acc;   // device: per-rank outcome counts (nullable)
+    GraphErr ge;               // per-rank error attribution (gr = nullptr: none)
 };
 
 // Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t --
@@ -499,7 +501,8 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
 
 // Partitions the tuples in tuple buffer 0 (nslots slots, empty keys dropped)
 // by key hash and resolves every partition.
-gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit) {
+gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
+                                   GraphErr ge = GraphErr{nullptr, 0, nullptr}) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
@@ -511,7 +514,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
     const size_t rlds = resolve_lds_bytes(c->sort_cap);
     GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(persistent_blocks(c, k_resolve, rlds, np)),
                      dim3(kBlock), rlds, c->tu_tag[parts], c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch],
-                     (int)p.bbits, poff, np, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step));
+                     (int)p.bbits, poff, np, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step, ge));
     return GESMC_OK;
 }
 
@@ -533,7 +536,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
         GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit<false>, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
                          c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot,
                          (const BatchGraph *)nullptr, (const uint32_t *)nullptr, 0u));
-    GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit));
+    GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr}));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -738,21 +741,25 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
 // ---------------------------------------------------------------------------
 gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
     if (G > c->cap_g) {
-        for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc}) {
+        for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc,
+                         (void **)&c->gerr}) {
             if (*q) (void)hipFree(*q);
             *q = nullptr;
         }
         if (c->h_gacc) (void)hipHostFree(c->h_gacc);
+        if (c->h_gerr) (void)hipHostFree(c->h_gerr);
         c->h_gacc = nullptr;
+        c->h_gerr = nullptr;
         c->cap_g = 0;
         const uint64_t cap = std::max<uint64_t>(G, 64);
         GESMC_TRY(dev_alloc((void **)&c->gr, cap * sizeof(BatchGraph)));
         GESMC_TRY(dev_alloc((void **)&c->in_off, (cap + 1) * 8));
         GESMC_TRY(dev_alloc((void **)&c->rank_of, cap * 4));
         GESMC_TRY(dev_alloc((void **)&c->gacc, cap * 4 * 8));
-        if (hipHostMalloc((void **)&c->h_gacc, cap * 4 * 8, hipHostMallocDefault) != hipSuccess) {
+        GESMC_TRY(dev_alloc((void **)&c->gerr, cap * 4));
+        if (hipHostMalloc((void **)&c->h_gacc, cap * 4 * 8, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->h_gerr, cap * 4, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
-            c->h_gacc = nullptr;
             set_error("hipHostMalloc failed");
             return GESMC_E_NOMEM;
         }
@@ -857,6 +864,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         b.bbase = (uint32_t)bbase;
         b.m = (uint32_t)m;
         b.n = nv[g];
+        b.pl = pl;
         c->h_rank_of[g] = q;
         poff += b.mpad;
         vbase += nv[g];
@@ -890,12 +898,14 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     if (stats)
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
                          (uint64_t)G * 8));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
+    const GraphErr ge_all{c->gr, G, c->gerr};
     uint32_t *bad_pos = c->err + 4;
     if (total_m > 0) {
         GESMC_TRY(launch(c, s, KID_LOAD, total_m, k_load_batch, dim3(grid_stride_blocks(c, total_m)), dim3(kBlock), 0,
                          (const unsigned long long *)d_in, (uint32_t)total_m, (const uint64_t *)c->in_off, G,
                          (const uint32_t *)c->rank_of, (const BatchGraph *)c->gr, c->idx[0], c->key[0], c->err,
-                         bad_pos));
+                         bad_pos, c->gerr));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
                          (const BatchGraph *)c->gr, G, npos, c->pg));
     }
@@ -903,7 +913,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         c->ctr_step = c->ctr;
         GESMC_TRY(launch(c, s, KID_EMIT, npos, k_emit_sources, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
                          (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
-        GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP));
+        GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP, ge_all));
     }
     // superstep s switches the ranks [0, active_s): those with r > s
     uint32_t qa = nactive;
@@ -922,7 +932,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         p.ncoarse = 1u << p.b1;
         p.nfine = 1u << B;
         p.ntiles1 = std::max<uint32_t>(1, ceil_div(P, kScatterTile));
-        BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr};
+        BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all};
         c->ctr_step = c->ctr + st;
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
     }
@@ -939,6 +949,8 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     if (stats)
         GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, (size_t)G * 32, hipMemcpyDeviceToHost, s),
                             "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, (size_t)G * 4, hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
     if (c->profile) collect_profile(c);
     const uint32_t e = c->h_err[0];
@@ -951,7 +963,12 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             set_error("graph %u, edge %llu: %s", g, (unsigned long long)(pos - offsets[g]),
                       st == GESMC_E_RANGE ? "vertex id out of range" : "input is not a simple graph (loop)");
         } else if (e & ERR_DUP) {
-            set_error("a graph of the batch is not simple (duplicate edge)");
+            uint32_t g = 0;
+            while (g < G && !(c->h_gerr[c->h_rank_of[g]] & ERR_DUP)) ++g;
+            if (g < G)
+                set_error("graph %u: input is not a simple graph (duplicate edge)", g);
+            else
+                set_error("a graph of the batch is not simple (duplicate edge)");
         }
         return st;
     }
@@ -1075,9 +1092,10 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->small) (void)hipFree(c->small);
     if (c->bslot) (void)hipFree(c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
-                    (void *)c->bk})
+                    (void *)c->bk, (void *)c->gerr})
         if (q) (void)hipFree(q);
     if (c->h_gacc) (void)hipHostFree(c->h_gacc);
+    if (c->h_gerr) (void)hipHostFree(c->h_gerr);
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
@@ -1242,3 +1260,5 @@ gesmc_status gesmc_profile_reset(gesmc_ctx *c) {
 }
 
 }  // extern "C"
+
+#include "server_runtime.h"

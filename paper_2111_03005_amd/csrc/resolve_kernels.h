@@ -75,9 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         if (kBatch) {
             if (i == kPadIdx || j == kPadIdx) {
                 status = ST_IDLE;
-            } else if (pl != 0) {
+            } else if (pl != 0) {  // pl != 0: some graph of the batch has P_L > 0
                 const BatchGraph &g = gr[pg[2 * (size_t)k]];
-                skip = pl_skip(k - (g.poff >> 1), g.t0 + step, pl, g.k0, g.k1);
+                skip = pl_skip(k - (g.poff >> 1), g.t0 + step, g.pl, g.k0, g.k1);
             }
         } else {
             skip = pl_skip(k, t, pl, k0, k1);
@@ -127,13 +127,40 @@ __global__ __launch_bounds__(kBlock) void k_emit_sources(const unsigned long lon
     }
 }
 
+// Graph attribution of errors in a batch: the graph owning a key is the one
+// whose vertex range holds its smaller endpoint.
+struct GraphErr {
+    const BatchGraph *gr;  // nullptr: no attribution
+    uint32_t ngraphs;
+    uint32_t *gerr;        // per graph error bits
+};
+
+__device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t *err, uint32_t dup_bit,
+                                               const GraphErr &ge) {
+    if (dup_bit) atomicOr(err, dup_bit);
+    if (ge.gr) {
+        const uint32_t v = (uint32_t)(key >> 32);
+        uint32_t lo = 0, hi = ge.ngraphs - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (ge.gr[mid].vbase <= v)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        atomicOr(&ge.gerr[lo], ERR_DUP);
+    }
+}
+
 // Writes the records of the tuple at sorted position p, given the position
-// of the first tuple of its key.  Raises dup_bit on a second ERASE tuple.
+// of the first tuple of its key.  A second ERASE tuple means the edge occurs
+// twice: dup_bit is raised (and the graph flagged in a batch).
 __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, uint32_t p, uint32_t first,
-                                            uint32_t prev_tag, uint2 *info, uint32_t *err, uint32_t dup_bit) {
+                                            uint32_t prev_tag, unsigned long long key, uint2 *info, uint32_t *err,
+                                            uint32_t dup_bit, const GraphErr &ge) {
     const bool ins = (tag & kTagInsert) != 0;
     if (!ins) {
-        if (p != first) atomicOr(err, dup_bit);  // two ERASE tuples: the edge occurs twice
+        if (p != first) flag_duplicate(key, err, dup_bit, ge);
         return;
     }
     uint32_t eraser = kNoEraser;
@@ -153,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                                                     unsigned long long *__restrict__ sc_key, int pbits,
                                                     const uint32_t *__restrict__ part_off, uint32_t np, uint32_t cap,
                                                     uint2 *__restrict__ info, uint32_t *__restrict__ err,
-                                                    uint32_t dup_bit, StepCounters *ctr) {
+                                                    uint32_t dup_bit, StepCounters *ctr, GraphErr ge) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t kCells = 1u << kSortSubBits;
     uint32_t *cell = lds;
@@ -245,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                     else
                         b = x;
                 }
-                resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, info, err, dup_bit);
+                resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, kp, info, err, dup_bit, ge);
             }
             if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
             __syncthreads();
@@ -296,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 uint32_t first = a;
                 for (uint32_t x = a; x < b; ++x) {
                     if (x > a && sK[x] != sK[x - 1]) first = x;
-                    resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, info, err, dup_bit);
+                    resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, sK[x], info, err, dup_bit,
+                                ge);
                 }
             }
             lds_barrier();

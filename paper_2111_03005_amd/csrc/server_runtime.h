@@ -1,0 +1,600 @@
+// Serving runtime (gesmc_server_*): a worker thread with continuous batching
+// over the batched superstep.  Included at the end of gesmc.hip (it drives
+// the context's buffers and the superstep pipeline directly).
+//
+// Layout between iterations: buffer 0 of the context holds the records of
+// the resident graphs in rank order (segments as in a batch, BatchGraph);
+// every graph keeps its index labels (local index + a fixed base) and is
+// re-shifted to a new vertex base whenever the layout is rebuilt.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+constexpr uint64_t kServeBytesPerEdge = 136;  // context buffers per resident record (see ensure_capacity)
+
+struct ServeReq {
+    uint64_t ticket = 0;
+    std::vector<uint64_t> edges;
+    uint64_t m = 0;
+    uint32_t n = 0, t0 = 0, r = 0, pl = 0;
+    uint64_t seed = 0;
+    uint32_t done = 0;  // supersteps run
+    uint32_t goff = 0;  // index label base, fixed at admission
+    uint32_t poff = 0, vbase = 0;  // segment and vertex base in the current layout
+    bool cancel = false, finished = false;
+    gesmc_status status = GESMC_OK;
+    gesmc_stats stats{};
+    uint64_t *result = nullptr;
+    double t_submit = 0, t_admit = -1, t_done = 0;
+};
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct gesmc_server {
+    gesmc_ctx *c = nullptr;
+    hipStream_t s = nullptr;
+    uint64_t cap_edges = 0;
+    uint32_t max_graphs = 0, max_queue = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ServeReq *> queue;
+    std::unordered_map<uint64_t, ServeReq *> reqs;
+    std::vector<ServeReq *> resident;  // worker only: rank order of the layout in buffer 0
+    bool stop = false;
+    std::thread worker;
+    std::chrono::steady_clock::time_point t0;
+    uint64_t next_ticket = 1;
+    // info (under mu)
+    uint64_t submitted = 0, completed = 0, iterations = 0, attempts = 0, legal = 0, resident_edges = 0;
+    uint32_t resident_count = 0;
+    double busy_s = 0;
+    // worker-side staging
+    std::vector<BatchGraph> h_gr;
+    std::vector<uint2> h_mv;
+    std::vector<uint64_t> h_stage_off;
+    std::vector<uint32_t> h_stage_rank;
+    std::vector<unsigned long long> h_rb;
+    uint2 *d_mv = nullptr;
+    uint64_t *d_stage_off = nullptr;
+    uint32_t *d_stage_rank = nullptr;
+    unsigned long long *d_rb = nullptr;
+};
+
+namespace {
+
+void serve_finish_locked(gesmc_server *S, ServeReq *q, gesmc_status st) {
+    if (st != GESMC_OK && q->result) {
+        free(q->result);
+        q->result = nullptr;
+    }
+    q->status = st;
+    q->finished = true;
+    q->t_done = seconds_since(S->t0);
+    q->edges.clear();
+    q->edges.shrink_to_fit();
+    ++S->completed;
+    S->cv_done.notify_all();
+}
+
+// Requests without switches (r = 0 or m < 2): validated and canonicalised on
+// the host, with the checks and status precedence of gesmc_run.
+gesmc_status serve_trivial(ServeReq *q) {
+    bool loop = false, range = false;
+    std::vector<uint64_t> canon(q->m);
+    for (uint64_t i = 0; i < q->m; ++i) {
+        const uint32_t a = (uint32_t)(q->edges[i] >> 32), b = (uint32_t)q->edges[i];
+        loop |= a == b;
+        range |= a >= q->n || b >= q->n || a == 0xFFFFFFFFu || b == 0xFFFFFFFFu;
+        canon[i] = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+    }
+    std::vector<uint64_t> sorted = canon;
+    std::sort(sorted.begin(), sorted.end());
+    const bool dup = std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end();
+    if (loop || dup) return GESMC_E_NOT_SIMPLE;
+    if (range) return GESMC_E_RANGE;
+    q->result = (uint64_t *)malloc(std::max<uint64_t>(q->m, 1) * 8);
+    if (!q->result) return GESMC_E_NOMEM;
+    memcpy(q->result, canon.data(), q->m * 8);
+    return GESMC_OK;
+}
+
+gesmc_status serve_map_gerr(uint32_t e) {
+    if (e & (ERR_LOOP | ERR_DUP)) return GESMC_E_NOT_SIMPLE;
+    if (e & ERR_RANGE) return GESMC_E_RANGE;
+    return GESMC_E_INTERNAL;
+}
+
+// One iteration on the worker: new layout (survivors + admitted), one
+// superstep of every resident graph, results of the graphs that finish.
+gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, const std::vector<ServeReq *> &admit,
+                             bool relayout, std::vector<ServeReq *> &finishing) {
+    gesmc_ctx *c = S->c;
+    hipStream_t s = S->s;
+    const uint32_t nsurv = (uint32_t)next.size();
+    std::vector<ServeReq *> ranks = next;
+    ranks.insert(ranks.end(), admit.begin(), admit.end());
+    const uint32_t G = (uint32_t)ranks.size();
+    S->h_gr.assign(G, BatchGraph{});
+    S->h_mv.assign(G, make_uint2(0xFFFFFFFFu, 0));
+    uint64_t poff = 0, vbase = 0, bbase = 0, stage = 0;
+    uint32_t pl_any = 0;
+    S->h_stage_off.clear();
+    S->h_stage_rank.clear();
+    for (uint32_t q = 0; q < G; ++q) {
+        ServeReq *R = ranks[q];
+        BatchGraph &b = S->h_gr[q];
+        if (q >= nsurv) {  // admitted now: loaded from the staging buffer, labels = staging positions
+            R->goff = (uint32_t)stage;
+            S->h_stage_off.push_back(stage);
+            S->h_stage_rank.push_back(q);
+            stage += R->m;
+        } else if (relayout) {
+            S->h_mv[q] = make_uint2(R->poff, R->vbase);
+        }
+        b.poff = (uint32_t)poff;
+        b.mpad = (uint32_t)(R->m + (R->m & 1));
+        b.goff = R->goff;
+        b.vbase = (uint32_t)vbase;
+        b.k0 = (uint32_t)R->seed;
+        b.k1 = (uint32_t)(R->seed >> 32);
+        b.t0 = R->t0 + R->done;
+        b.nb = (uint32_t)std::max<uint64_t>(1, ceil_div(b.mpad, c->bucket_avg));
+        b.bbase = (uint32_t)bbase;
+        b.m = (uint32_t)R->m;
+        b.n = R->n;
+        b.pl = R->pl;
+        pl_any |= R->pl;
+        R->poff = b.poff;
+        R->vbase = b.vbase;
+        poff += b.mpad;
+        vbase += R->n;
+        bbase += b.nb;
+    }
+    S->h_stage_off.push_back(stage);
+    const uint32_t npos = (uint32_t)poff;
+    if (bbase > (1ull << kMaxFineBits) || npos > c->cap_pos) {
+        set_error("serving layout exceeds the context's capacity");
+        return GESMC_E_INTERNAL;
+    }
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, S->h_gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
+                     (uint64_t)(sizeof(StepCounters) / 4)));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
+                     (uint64_t)G * 8));
+    if (relayout) {
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                         (const BatchGraph *)c->gr, G, npos, c->pg));
+        if (nsurv > 0) {
+            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_mv, S->h_mv.data(), G * sizeof(uint2), hipMemcpyHostToDevice, s),
+                                "hipMemcpyAsync"));
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_relayout, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                             (const BatchGraph *)c->gr, (const uint2 *)S->d_mv, (const uint32_t *)c->pg, npos,
+                             (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], c->idx[1],
+                             c->key[1]));
+        }
+        if (!admit.empty()) {
+            // raw edges of the admitted requests -> staging (tuple key buffer 1), then load
+            unsigned long long *stg = c->tu_key[1];
+            for (size_t j = 0; j < admit.size(); ++j)
+                if (admit[j]->m)
+                    GESMC_TRY(check_hip(hipMemcpyAsync(stg + S->h_stage_off[j], admit[j]->edges.data(),
+                                                       admit[j]->m * 8, hipMemcpyHostToDevice, s),
+                                        "hipMemcpyAsync"));
+            const uint32_t nadm = (uint32_t)admit.size();
+            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage_off, S->h_stage_off.data(), (nadm + 1) * 8ull,
+                                               hipMemcpyHostToDevice, s),
+                                "hipMemcpyAsync"));
+            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage_rank, S->h_stage_rank.data(), nadm * 4ull,
+                                               hipMemcpyHostToDevice, s),
+                                "hipMemcpyAsync"));
+            if (stage > 0)
+                GESMC_TRY(launch(c, s, KID_LOAD, stage, k_load_batch, dim3(grid_stride_blocks(c, stage)),
+                                 dim3(kBlock), 0, (const unsigned long long *)stg, (uint32_t)stage,
+                                 (const uint64_t *)S->d_stage_off, nadm, (const uint32_t *)S->d_stage_rank,
+                                 (const BatchGraph *)c->gr, c->idx[1], c->key[1], c->err + 8, c->err + 9, c->gerr));
+        }
+        std::swap(c->idx[0], c->idx[1]);
+        std::swap(c->key[0], c->key[1]);
+    }
+    // one superstep of every resident graph (each at its own superstep t0 + done)
+    Plan p;
+    p.m = npos;
+    p.ell = npos / 2;
+    uint32_t B = 0;
+    while ((1ull << B) < bbase) ++B;
+    p.bbits = B;
+    p.b1 = std::min<uint32_t>(B, 8);
+    p.b2 = B - p.b1;
+    p.ncoarse = 1u << p.b1;
+    p.nfine = 1u << B;
+    p.ntiles1 = std::max<uint32_t>(1, ceil_div(npos, kScatterTile));
+    BatchStep bs{c->gr, G, 0u, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
+    c->ctr_step = c->ctr;
+    GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
+    // results of the graphs finishing now (discarded after the sync if flagged)
+    finishing.clear();
+    S->h_rb.assign(G, ~0ull);
+    uint64_t rpos = 0;
+    for (uint32_t q = 0; q < G; ++q) {
+        if (ranks[q]->done + 1 == ranks[q]->r) {
+            S->h_rb[q] = rpos;
+            rpos += ranks[q]->m;
+            finishing.push_back(ranks[q]);
+        }
+    }
+    unsigned long long *res = c->tu_key[2];
+    if (!finishing.empty()) {
+        GESMC_TRY(check_hip(hipMemcpyAsync(S->d_rb, S->h_rb.data(), G * 8ull, hipMemcpyHostToDevice, s),
+                            "hipMemcpyAsync"));
+        GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_extract, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                         (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], (const uint32_t *)c->pg,
+                         (const BatchGraph *)c->gr, (const unsigned long long *)S->d_rb, npos, res));
+        for (ServeReq *R : finishing) {
+            R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
+            if (!R->result) return GESMC_E_NOMEM;
+        }
+        for (uint32_t q = 0; q < G; ++q)
+            if (S->h_rb[q] != ~0ull)
+                GESMC_TRY(check_hip(hipMemcpyAsync(ranks[q]->result, res + S->h_rb[q], ranks[q]->m * 8,
+                                                   hipMemcpyDeviceToHost, s),
+                                    "hipMemcpyAsync"));
+    }
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, G * 32ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, G * 4ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    next = ranks;
+    return GESMC_OK;
+}
+
+void serve_loop(gesmc_server *S) {
+    gesmc_ctx *c = S->c;
+    (void)hipSetDevice(c->device);
+    std::vector<ServeReq *> admit, trivial, next, finishing;
+    bool dirty = true;  // the layout in buffer 0 differs from `resident`
+    for (;;) {
+        admit.clear();
+        trivial.clear();
+        next.clear();
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->resident.empty(); });
+            if (S->stop) return;
+            for (ServeReq *R : S->resident) {
+                if (R->cancel) {
+                    serve_finish_locked(S, R, GESMC_E_CANCELED);
+                    dirty = true;
+                } else {
+                    next.push_back(R);
+                }
+            }
+            uint64_t edges = 0, verts = 0;
+            for (ServeReq *R : next) {
+                edges += R->m + (R->m & 1);
+                verts += R->n;
+            }
+            while (!S->queue.empty()) {
+                ServeReq *R = S->queue.front();
+                if (R->cancel) {
+                    S->queue.pop_front();
+                    serve_finish_locked(S, R, GESMC_E_CANCELED);
+                    continue;
+                }
+                if (R->r == 0 || R->m < 2) {
+                    S->queue.pop_front();
+                    R->t_admit = seconds_since(S->t0);
+                    trivial.push_back(R);
+                    continue;
+                }
+                const uint64_t need = R->m + (R->m & 1);
+                if (next.size() + admit.size() >= S->max_graphs || edges + need > S->cap_edges ||
+                    verts + R->n > 0xFFFFFFFEull)
+                    break;
+                S->queue.pop_front();
+                R->t_admit = seconds_since(S->t0);
+                admit.push_back(R);
+                edges += need;
+                verts += R->n;
+            }
+            S->resident_edges = edges;
+            S->resident_count = (uint32_t)(next.size() + admit.size());
+        }
+        for (ServeReq *R : trivial) {
+            const gesmc_status st = serve_trivial(R);
+            std::lock_guard<std::mutex> lk(S->mu);
+            serve_finish_locked(S, R, st);
+        }
+        if (next.empty() && admit.empty()) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->resident.clear();
+            dirty = true;
+            continue;
+        }
+        const auto it0 = std::chrono::steady_clock::now();
+        const bool relayout = dirty || !admit.empty();
+        gesmc_status st = serve_iteration(S, next, admit, relayout, finishing);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->busy_s += seconds_since(it0);
+        if (st == GESMC_OK && c->h_err[0] != 0) {
+            set_error("internal consistency check failed (error bits 0x%x)", c->h_err[0]);
+            st = GESMC_E_INTERNAL;
+        }
+        if (st != GESMC_OK) {  // a failed iteration fails every graph in it
+            (void)hipStreamSynchronize(S->s);
+            (void)hipGetLastError();
+            std::vector<ServeReq *> all = next;  // survivors (unchanged on failure) and the admitted
+            all.insert(all.end(), admit.begin(), admit.end());
+            for (ServeReq *R : all)
+                if (!R->finished) serve_finish_locked(S, R, st);
+            S->resident.clear();
+            dirty = true;
+            continue;
+        }
+        ++S->iterations;
+        std::vector<ServeReq *> keep;
+        dirty = false;
+        const StepCounters &h = c->h_ctr[0];
+        for (uint32_t q = 0; q < (uint32_t)next.size(); ++q) {
+            ServeReq *R = next[q];
+            gesmc_stats &o = R->stats;
+            o.attempts += R->m / 2;
+            o.legal += c->h_gacc[4 * (size_t)q + 0];
+            o.rej_loop += c->h_gacc[4 * (size_t)q + 1];
+            o.rej_exists += c->h_gacc[4 * (size_t)q + 2];
+            o.rej_pl += c->h_gacc[4 * (size_t)q + 3];
+            o.rounds_sum += h.rounds;
+            o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)h.rounds);
+            S->attempts += R->m / 2;
+            S->legal += c->h_gacc[4 * (size_t)q + 0];
+            ++R->done;
+            const uint32_t ge = c->h_gerr[q];
+            if (ge) {
+                serve_finish_locked(S, R, R->done == 1 ? serve_map_gerr(ge) : GESMC_E_INTERNAL);
+                dirty = true;
+            } else if (R->done == R->r) {
+                o.supersteps = R->r;
+                o.ms_device = 0;
+                serve_finish_locked(S, R, GESMC_OK);
+                dirty = true;
+            } else {
+                keep.push_back(R);
+            }
+        }
+        S->resident = keep;
+        if (dirty) {
+            uint64_t edges = 0;
+            for (ServeReq *R : keep) edges += R->m + (R->m & 1);
+            S->resident_edges = edges;
+            S->resident_count = (uint32_t)keep.size();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesmc_server **out) {
+    if (!c || !out) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    *out = nullptr;
+    if (c->strategy != 0) {
+        set_error("serving needs the sorted-tuples strategy (GESMC_OPT_STRATEGY 0)");
+        return GESMC_E_INVAL;
+    }
+    const uint64_t budget = (cfg && cfg->hbm_budget_bytes) ? cfg->hbm_budget_bytes : (16ull << 30);
+    const uint32_t max_graphs = (cfg && cfg->max_graphs) ? cfg->max_graphs : 4096u;
+    const uint32_t max_queue = (cfg && cfg->max_queue) ? cfg->max_queue : 65536u;
+    const uint64_t cap_edges = std::min<uint64_t>(budget / kServeBytesPerEdge, kMaxEdges - 1 - max_graphs);
+    if (cap_edges < 16 || max_graphs > (1u << kMaxFineBits)) {
+        set_error("server budget too small or too many graphs");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    GESMC_TRY(ensure_capacity(c, cap_edges + 64));
+    GESMC_TRY(ensure_counters(c, 1));
+    GESMC_TRY(ensure_batch(c, max_graphs, cap_edges + 64));
+    gesmc_server *S = new gesmc_server();
+    S->c = c;
+    S->cap_edges = cap_edges;
+    S->max_graphs = max_graphs;
+    S->max_queue = max_queue;
+    S->t0 = std::chrono::steady_clock::now();
+    gesmc_status st = GESMC_OK;
+    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_mv, max_graphs * sizeof(uint2));
+    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
+    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_rank, max_graphs * 4ull);
+    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_rb, max_graphs * 8ull);
+    if (st == GESMC_OK && hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipStreamCreate failed");
+        st = GESMC_E_DEVICE;
+    }
+    if (st != GESMC_OK) {
+        gesmc_server_destroy(S);
+        return st;
+    }
+    S->worker = std::thread(serve_loop, S);
+    *out = S;
+    return GESMC_OK;
+}
+
+void gesmc_server_destroy(gesmc_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto &kv : S->reqs) {
+            if (!kv.second->finished) serve_finish_locked(S, kv.second, GESMC_E_CANCELED);
+            free(kv.second->result);
+            delete kv.second;
+        }
+        S->reqs.clear();
+    }
+    S->cv_done.notify_all();
+    if (S->s) {
+        (void)hipStreamSynchronize(S->s);
+        (void)hipStreamDestroy(S->s);
+    }
+    for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank, (void *)S->d_rb})
+        if (p) (void)hipFree(p);
+    delete S;
+}
+
+gesmc_status gesmc_submit(gesmc_server *S, const gesmc_request *req, uint64_t *ticket) {
+    if (!S || !req || !ticket || (req->m > 0 && !req->edges)) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    if (req->m >= kMaxEdges || req->m + (req->m & 1) > S->cap_edges || req->n > 0xFFFFFFFEu) {
+        set_error("request of m = %llu, n = %u can never fit the server", (unsigned long long)req->m, req->n);
+        return GESMC_E_RANGE;
+    }
+    if ((uint64_t)req->t0 + req->r > 0x100000000ull) {
+        set_error("superstep counter t0 + r overflows 32 bits");
+        return GESMC_E_INVAL;
+    }
+    ServeReq *R = new ServeReq();
+    R->edges.assign(req->edges, req->edges + req->m);
+    R->m = req->m;
+    R->n = req->n;
+    R->t0 = req->t0;
+    R->r = req->r;
+    R->pl = req->pl;
+    R->seed = req->seed;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->queue.size() >= S->max_queue) {
+            delete R;
+            set_error("queue full");
+            return GESMC_E_AGAIN;
+        }
+        R->ticket = S->next_ticket++;
+        R->t_submit = seconds_since(S->t0);
+        S->reqs[R->ticket] = R;
+        S->queue.push_back(R);
+        ++S->submitted;
+        *ticket = R->ticket;
+    }
+    S->cv_work.notify_one();
+    return GESMC_OK;
+}
+
+static gesmc_status serve_take_locked(gesmc_server *S, std::unordered_map<uint64_t, ServeReq *>::iterator it,
+                                      gesmc_result *out) {
+    ServeReq *R = it->second;
+    out->status = R->status;
+    out->m = R->m;
+    out->edges = R->status == GESMC_OK ? R->result : nullptr;
+    if (R->status != GESMC_OK) free(R->result);
+    out->stats = R->stats;
+    out->t_submit = R->t_submit;
+    out->t_admit = R->t_admit;
+    out->t_done = R->t_done;
+    S->reqs.erase(it);
+    delete R;
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_poll(gesmc_server *S, uint64_t ticket, gesmc_result *out) {
+    if (!S || !out) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("unknown ticket %llu", (unsigned long long)ticket);
+        return GESMC_E_INVAL;
+    }
+    if (!it->second->finished) return GESMC_E_AGAIN;
+    return serve_take_locked(S, it, out);
+}
+
+gesmc_status gesmc_wait(gesmc_server *S, uint64_t ticket, gesmc_result *out) {
+    if (!S || !out) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("unknown ticket %llu", (unsigned long long)ticket);
+        return GESMC_E_INVAL;
+    }
+    ServeReq *R = it->second;
+    S->cv_done.wait(lk, [&] { return R->finished || S->stop; });
+    if (!R->finished) {
+        set_error("server stopped");
+        return GESMC_E_CANCELED;
+    }
+    return serve_take_locked(S, S->reqs.find(ticket), out);
+}
+
+gesmc_status gesmc_cancel(gesmc_server *S, uint64_t ticket) {
+    if (!S) {
+        set_error("null server");
+        return GESMC_E_INVAL;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(ticket);
+        if (it == S->reqs.end()) {
+            set_error("unknown ticket %llu", (unsigned long long)ticket);
+            return GESMC_E_INVAL;
+        }
+        it->second->cancel = true;
+    }
+    S->cv_work.notify_one();
+    return GESMC_OK;
+}
+
+void gesmc_result_free(gesmc_result *res) {
+    if (!res) return;
+    free(res->edges);
+    res->edges = nullptr;
+}
+
+gesmc_status gesmc_server_info_get(gesmc_server *S, gesmc_server_info *out) {
+    if (!S || !out) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->iterations = S->iterations;
+    out->attempts = S->attempts;
+    out->legal = S->legal;
+    out->resident_edges = S->resident_edges;
+    out->queued = (uint32_t)S->queue.size();
+    out->resident = S->resident_count;
+    out->busy_s = S->busy_s;
+    out->now_s = seconds_since(S->t0);
+    return GESMC_OK;
+}
+
+}  // extern "C"

@@ -55,10 +55,56 @@ def test_binding_constants_match_header():
     import paper_2111_03005_amd as gesmc
     d = header_defines()
     assert d["GESMC_OK"] == gesmc.OK
-    for name in ["E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_INTERNAL"]:
+    for name in ["E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_AGAIN", "E_CANCELED", "E_INTERNAL"]:
         assert d["GESMC_" + name] == getattr(gesmc, name), name
     for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY"]:
         assert d["GESMC_OPT_" + name] == getattr(gesmc, "OPT_" + name), name
+
+
+C_LAYOUT_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "gesmc.h"
+#define F(T, f) printf("%s.%s %zu %zu\n", #T, #f, offsetof(T, f), sizeof(((T *)0)->f));
+#define S(T) printf("%s %zu\n", #T, sizeof(T));
+int main(void) {
+    S(gesmc_stats) F(gesmc_stats, rounds_max) F(gesmc_stats, ms_device)
+    S(gesmc_step_stats)
+    S(gesmc_server_cfg) F(gesmc_server_cfg, max_graphs) F(gesmc_server_cfg, max_queue)
+    S(gesmc_request) F(gesmc_request, m) F(gesmc_request, n) F(gesmc_request, t0) F(gesmc_request, r)
+    F(gesmc_request, pl) F(gesmc_request, seed)
+    S(gesmc_result) F(gesmc_result, m) F(gesmc_result, edges) F(gesmc_result, stats) F(gesmc_result, t_submit)
+    F(gesmc_result, t_done)
+    S(gesmc_server_info) F(gesmc_server_info, resident_edges) F(gesmc_server_info, queued)
+    F(gesmc_server_info, resident) F(gesmc_server_info, busy_s) F(gesmc_server_info, now_s)
+    return 0;
+}
+"""
+
+
+def test_ctypes_layouts_match_c_compiler(tmp_path):
+    """Every struct of the header, laid out by the C compiler, against the
+    binding's ctypes mirror (sizes and field offsets)."""
+    from paper_2111_03005_amd import _binding as b
+    src = tmp_path / "probe.c"
+    src.write_text(C_LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    mirror = {"gesmc_stats": b.Stats, "gesmc_step_stats": b.StepStats, "gesmc_server_cfg": b.ServerCfg,
+              "gesmc_request": b.Request, "gesmc_result": b.Result, "gesmc_server_info": b.ServerInfo}
+    checked = 0
+    for line in filter(None, out):
+        parts = line.split()
+        if "." in parts[0]:
+            sname, field = parts[0].split(".")
+            off, size = int(parts[1]), int(parts[2])
+            f = getattr(mirror[sname], field)
+            assert (f.offset, f.size) == (off, size), (sname, field)
+        else:
+            assert ctypes.sizeof(mirror[parts[0]]) == int(parts[1]), parts[0]
+        checked += 1
+    assert checked >= 20
 
 
 def test_struct_layouts_match_header():
@@ -83,3 +129,11 @@ def test_null_context_rejected_without_gpu(lib):
     assert lib.gesmc_set_option(None, gesmc.OPT_PROFILE, 1) == gesmc.E_INVAL
     assert lib.gesmc_run(None, None, None, None, 0, 0, 0, 0, 0, 0, 0, None, None) == gesmc.E_INVAL
     assert b"null" in lib.gesmc_last_error()
+    assert lib.gesmc_run_batch(None, None, 1, None, None, None, None, None, None, None, 0, 0, None,
+                               None) == gesmc.E_INVAL
+    assert lib.gesmc_server_create(None, None, None) == gesmc.E_INVAL
+    assert lib.gesmc_submit(None, None, None) == gesmc.E_INVAL
+    assert lib.gesmc_poll(None, 1, None) == gesmc.E_INVAL
+    assert lib.gesmc_cancel(None, 1) == gesmc.E_INVAL
+    lib.gesmc_server_destroy(None)
+    lib.gesmc_result_free(None)
