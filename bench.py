@@ -1,10 +1,14 @@
 """Benchmark of the G-ES-MC global switch on one MI355X.
 
-A step is one call of the library: input edges resident in HBM -> load and
-validation -> r global switches (permutation, dependency table, rounds of
-decisions) -> edges back in position order.  The value is switch attempts per
-second over the timed steps (floor(m/2) attempts per superstep, rejected ones
-included), the convention of the paper's runtime table (init + supersteps).
+Headline (value): the plain form on the power-law n=2^20 graph.  A step is
+one call of the library: input edges resident in HBM -> load and validation
+-> r global switches (permutation, dependency resolution, rounds of
+decisions) -> edges back in position order.  The value is switch attempts
+per second over the timed steps (floor(m/2) attempts per superstep, rejected
+ones included), the convention of the paper's runtime table (init +
+supersteps).  The same line carries the batched form (4096 graphs in one
+call, beside the plain form looping over the same graphs) and the served
+form (Poisson request streams: p50 / p99 latency and attempts/s).
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -90,6 +94,114 @@ def cpu_baseline(E, n, r_sample, seed):
     return att / dt, dt
 
 
+def bench_batched(gesmc, torch, args, plain_value):
+    """The 4096-graph batch: one gesmc_run_batch call (20 global switches of
+    every graph) per step, beside the plain path looping over the same graphs."""
+    import graphgen
+    t = time.perf_counter()
+    graphs = graphgen.workload_batch_4096()
+    E, offs, ns = graphgen.concat(graphs)
+    print("batched: %d graphs, %d edges generated in %.1f s" % (len(graphs), offs[-1], time.perf_counter() - t),
+          file=sys.stderr)
+    G = len(graphs)
+    seeds = [args.seed + g for g in range(G)]
+    rs = [20] * G
+    attempts = sum(20 * (int(m) // 2) for m in np.diff(offs))
+    ctx = gesmc.Context(0)
+    d_in = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
+    d_out = torch.empty_like(d_in)
+    ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)  # warm-up (allocation)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.batch_steps):
+        t = time.perf_counter()
+        ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    wall = sum(times)
+    value = attempts * len(times) / wall
+    # the plain path (one gesmc_run per graph) on a sample of the same graphs
+    sample = list(range(0, G, args.plain_sample_stride))
+    dev_graphs = [(torch.from_numpy(graphs[g][0].view(np.int64).copy()).to("cuda"), graphs[g][1]) for g in sample]
+    for d, n in dev_graphs[:4]:
+        ctx.run(d, n, 1, 0, 20)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    att_plain = 0
+    for g, (d, n) in zip(sample, dev_graphs):
+        ctx.run(d, n, seeds[g], 0, 20)
+        att_plain += 20 * (d.numel() // 2)
+    torch.cuda.synchronize()
+    plain_same = att_plain / (time.perf_counter() - t)
+    ctx.close()
+    print("batched: %.3e attempts/s (%.1f ms per batch); plain loop on every %dth graph: %.3e attempts/s" % (
+        value, 1e3 * wall / len(times), args.plain_sample_stride, plain_same), file=sys.stderr)
+    return {"value": round(value, 1), "unit": "attempts/s", "steps": len(times),
+            "ms_per_step": round(1e3 * wall / len(times), 3), "graphs": G, "edges": int(offs[-1]),
+            "supersteps_per_graph": 20, "attempts_per_step": attempts,
+            "workload": "4096 power-law graphs, n log-uniform [1e2,1e5], gamma U[2.1,3.0], d_min 2, "
+                        "d_max floor(sqrt(n)), Havel-Hakimi, generator seed 4, Philox seeds 42+g",
+            "plain_same_graphs": {"value": round(plain_same, 1), "unit": "attempts/s",
+                                  "sample": "gesmc_run per graph on every %dth graph (%d graphs)" % (
+                                      args.plain_sample_stride, len(sample))},
+            "vs_plain_same_graphs": round(value / plain_same, 2),
+            "vs_plain_headline": round(value / plain_value, 3) if plain_value else None}
+
+
+def bench_served(gesmc, torch, args):
+    """Open-loop Poisson request stream against the serving loop, per rate:
+    p50 / p99 latency (completion - submission, server clock) and attempts/s."""
+    import threading
+
+    import graphgen
+    t = time.perf_counter()
+    pool = graphgen.batch_graphs(args.serve_pool, 5, 1e3, 1e6)
+    print("served: pool of %d graphs generated in %.1f s" % (len(pool), time.perf_counter() - t), file=sys.stderr)
+    out = []
+    for rate, budget in [(x, args.serve_budget) for x in args.serve_rates] + [(args.serve_rates[-1], 1 << 30)]:
+        rng = np.random.default_rng(1000 + int(rate))
+        nreq = args.serve_requests
+        picks = rng.integers(0, len(pool), nreq)
+        rs = rng.integers(10, 51, nreq)
+        seeds = rng.integers(0, 2**63, nreq)
+        gaps = rng.exponential(1.0 / rate, nreq)
+        ctx = gesmc.Context(0)
+        srv = gesmc.Server(ctx, hbm_budget_bytes=budget)
+        tickets = [None] * nreq
+
+        def producer():
+            t_next = time.perf_counter()
+            for i in range(nreq):
+                t_next += gaps[i]
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                E, n = pool[picks[i]]
+                tickets[i] = srv.submit(E, n, int(seeds[i]), int(rs[i]))
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        res = [srv.wait(tk) for tk in tickets]
+        info = srv.info()
+        srv.close()
+        ctx.close()
+        bad = sum(1 for x in res if x["status"] != gesmc.OK)
+        lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+        att = sum(x["stats"]["attempts"] for x in res)
+        span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+        rec = {"rate_req_per_s": rate, "requests": nreq, "hbm_budget_bytes": budget, "failed": bad,
+               "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+               "attempts_per_s": round(att / span, 1), "iterations": info["iterations"],
+               "busy_fraction": round(info["busy_s"] / max(info["now_s"], 1e-9), 3)}
+        print("served: %s" % rec, file=sys.stderr)
+        out.append(rec)
+    return {"unit": "attempts/s", "per_rate": out,
+            "workload": "Poisson arrivals; requests drawn from a pool of %d power-law graphs (n log-uniform "
+                        "[1e3,1e6], gamma U[2.1,3.0], d_min 2, d_max floor(sqrt(n)), generator seed 5), "
+                        "r uniform in 10..50, own Philox seed" % len(pool)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +214,14 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no kernel events at all (no roofline)")
     ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
                     help="library option (e.g. PERSIST=2, STRATEGY=1); results never depend on options")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-graph batch")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--plain-sample-stride", type=int, default=8)
+    ap.add_argument("--no-served", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[100.0, 300.0, 1000.0])
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-pool", type=int, default=128)
+    ap.add_argument("--serve-budget", type=int, default=32 << 30, help="HBM budget of the server, bytes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
     args = ap.parse_args()
@@ -203,6 +323,10 @@ def main():
                "sample": "%s, first %d of %d supersteps incl. validation and set build (%.1f s)" % (
                    args.workload, rs, r, dt)}
 
+    ctx.close()
+    batched = None if args.no_batched else bench_batched(gesmc, torch, args, value)
+    served = None if args.no_served else bench_served(gesmc, torch, args)
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -224,6 +348,8 @@ def main():
                    "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(out))
 
