@@ -33,29 +33,40 @@ HBM_PEAK_GBS = 8000.0
 # counts for that kernel: edges m, switches ell, or table slots).  Random table
 # touches count the 16-byte slot read and written back; records are 12 bytes
 # (4-byte index + 8-byte key).
-def kernel_bytes(name: str, m: int, ell: int, tab_slots: int) -> float | None:
+def kernel_bytes(name: str, m: int, ell: int) -> float | None:
     return {
-        "k_hist_clear": 16.0 * tab_slots + ell,          # table reset + switch states (keys recomputed)
-        "k_scatter1": 24.0 * m,                          # read + write one record per edge
-        "k_hist_sub": 4.0 * m,                           # read the index of every record
+        "k_counts1": 4.0 * m,                            # index of every record (keys recomputed)
+        "k_scatter1": 24.0 * m,                          # read + write one 12-byte record per edge
+        "k_counts2": 4.0 * m,
         "k_scatter2": 24.0 * m,
         "k_sort_buckets": 24.0 * m,
-        "k_build": 24.0 * ell + 8.0 * ell + 4 * 32.0 * ell,  # pair records, slot ids, 4 slot RMWs
+        "k_build": 24.0 * ell + 8.0 * ell + 4 * 32.0 * ell,  # table strategy: pair records, slot ids, 4 slot RMWs
         "k_decide_first": 24.0 * ell + 8.0 * ell + 2 * 8.0 * ell + 24.0 * ell + 2.0 * ell,
         "k_unpermute": 12.0 * m + 8.0 * m,
         "k_load": 8.0 * m + 12.0 * m,
         # sorted-tuples dependency resolution: 4 tuples of 12 bytes per switch
         "k_emit": 24.0 * ell + 48.0 * ell + 16.0 * ell,  # pair records in, tuples + free target records out
+        "k_tcounts1": 32.0 * ell,                        # tuple keys
         "k_tscatter1": 48.0 * ell + 48.0 * ell,          # tuple slots in, partitioned tuples out
-        "k_thist_sub": 32.0 * ell,                       # tuple keys
+        "k_tcounts2": 32.0 * ell,
         "k_tscatter2": 48.0 * ell + 48.0 * ell,
         "k_resolve": 48.0 * ell,                         # tuples in (records out are rare)
         "k_decide_chain1": 16.0 * ell + 24.0 * ell + 24.0 * ell + 2.0 * ell,
     }.get(name)
 
 
-def table_slots(m: int) -> int:
-    return max(1024, (4 * m + 7) // 8 * 8)
+def switch_roofline(value: float, legal_fraction: float, G: int = 64):
+    """Attempts/s against the HBM bound of the method's own traffic: per
+    attempt 2 source reads and 2 target probes, and for an accepted switch 2
+    edge writes plus 2 erases and 2 inserts in the edge set (2 touches each),
+    every random touch one G-byte transaction, plus 16 streaming bytes of the
+    permutation: B_txn = G (4 + 10 a) + 16; B_alg = 48 + 48 a at byte level."""
+    a = legal_fraction
+    b_txn = G * (4 + 10 * a) + 16
+    b_alg = 48 + 48 * a
+    bound = HBM_PEAK_GBS * 1e9 / b_txn
+    return {"G_bytes": G, "bytes_per_attempt_txn": round(b_txn, 1), "bytes_per_attempt_alg": round(b_alg, 1),
+            "bound_attempts_per_s": round(bound, 1), "frac": round(value / bound, 4)}
 
 
 def source_digest() -> str:
@@ -263,7 +274,6 @@ def main():
     # Warm-up: the first pass times every kernel (events between all launches)
     # to find the dominant one; the timed steps then carry events around that
     # kernel only, so the clock around them is barely disturbed.
-    tslots = table_slots(m)
     ctx.set_option(gesmc.OPT_PROFILE, 0 if args.no_profile else 1)
     ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
     ctx.profile_reset()
@@ -277,7 +287,7 @@ def main():
     dominant = None
     for name, (ms, launches, items) in sorted(warm_prof.items(), key=lambda kv: -kv[1][0]):
         print("warm-up kernel %-16s total %9.3f ms  launches %5d" % (name, ms, launches), file=sys.stderr)
-        if dominant is None and kernel_bytes(name, m, ell, tslots) is not None:
+        if dominant is None and kernel_bytes(name, m, ell) is not None:
             dominant = name
 
     if dominant is not None:
@@ -304,7 +314,7 @@ def main():
     roofline = None
     if dominant is not None and dominant in prof:
         ms, launches, items = prof[dominant]
-        b = kernel_bytes(dominant, m, ell, tslots)
+        b = kernel_bytes(dominant, m, ell)
         avg_s = ms / launches / 1e3
         achieved = b / avg_s / 1e9
         print("timed kernel %s: %d launches, avg %.4f ms, %.0f GB/s" % (dominant, launches, avg_s * 1e3, achieved),
@@ -347,6 +357,7 @@ def main():
                    "step_ms_device_p50": round(float(np.median(step_ms)), 3) if step_ms else None,
                    "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
         "roofline": roofline,
+        "switch_roofline": switch_roofline(value, stats["legal"] / max(stats["attempts"], 1)) if stats else None,
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,

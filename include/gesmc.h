@@ -201,7 +201,7 @@ void gesmc_result_free(gesmc_result *res);
 gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
 
 /* Tuning knobs (values are validated; results never depend on them). */
-#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 768, default 512)    */
+#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 768, default 768)    */
 #define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1024, default 1024)     */
 #define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64) */
 #define GESMC_OPT_PROFILE 4     /* 1: time every kernel launch with HIP events                      */
@@ -210,6 +210,8 @@ gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
                                    rebuilt every superstep with device-scope atomics               */
 #define GESMC_OPT_PERSIST 6     /* workgroups of the tile/bucket kernels: resident count x value;
                                    0 = one workgroup per tile or bucket (default 0)                */
+#define GESMC_OPT_LEVEL1_BITS 8  /* digit bits of the first radix level (1 .. 10); 0 = half of the
+                                    bucket bits, rounded up (default)                              */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

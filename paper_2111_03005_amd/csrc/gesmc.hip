@@ -99,10 +99,11 @@ struct gesmc_ctx {
     int device = 0;
     int num_cus = 256;
     // options
-    uint32_t bucket_avg = (1u << kSortSubBits) / 2;
-    uint32_t sort_cap = 1u << kSortSubBits;
+    uint32_t bucket_avg = 3 * kLdsCap / 4;  // partition means fall in (avg / 2, avg]
+    uint32_t sort_cap = kLdsCap;
     int fast_rounds = 2;
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
+    uint32_t level1_cap = 0;  // first-level digit bits (0: even split)
     int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
     int profile_only = -1;  // kernel id timed while profiling (-1: every kernel)
@@ -312,11 +313,37 @@ gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern k
     } while (0)
 
 struct Plan {
-    uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1;
+    uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1, tile;
 };
 
+uint32_t tile_for(uint32_t n) { return n >= kLargeTileRecords ? (uint32_t)kTileLarge : (uint32_t)kTileSmall; }
+
+// Digit bits of the first level: an even split of B (so both levels write
+// runs of similar length), or at most `cap` bits if the option sets one.
+uint32_t level1_bits(uint32_t B, uint32_t cap) {
+    if (cap == 0) return std::min<uint32_t>(kMaxCoarseBits, (B + 1) / 2);
+    return std::min<uint32_t>(B, cap);
+}
+
+// Plan of a batch permutation: global buckets [0, nb) over m records.
+Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
+    Plan p;
+    p.m = m;
+    p.ell = m / 2;
+    uint32_t B = 0;
+    while ((1ull << B) < nb) ++B;
+    p.bbits = B;
+    p.b1 = level1_bits(B, c->level1_cap);
+    p.b2 = B - p.b1;
+    p.ncoarse = 1u << p.b1;
+    p.nfine = 1u << B;
+    p.tile = tile_for(m);
+    p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, p.tile));
+    return p;
+}
+
 // Radix plan for n records: B bucket bits (mean bucket <= bucket_avg), split
-// into a coarse level of <= 8 bits and a second level of the rest.
+// into a coarse level (level1_bits) and a second level of the rest.
 Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     Plan p;
     p.m = m;
@@ -324,28 +351,29 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     uint32_t B = 0;
     while (B < kMaxFineBits && ((uint64_t)c->bucket_avg << B) < m) ++B;
     p.bbits = B;
-    p.b1 = std::min<uint32_t>(B, 8);
+    p.b1 = level1_bits(B, c->level1_cap);
     p.b2 = B - p.b1;
     p.ncoarse = 1u << p.b1;
     p.nfine = 1u << B;
-    p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, kScatterTile));
+    p.tile = tile_for(m);
+    p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, p.tile));
     return p;
 }
 
-size_t scatter_lds_bytes(int dbits) {
+size_t scatter_lds_bytes(int dbits, uint32_t tile) {
     const size_t nd = (size_t)1 << dbits;
-    size_t words = 3 * nd + kBlock + 1 + kScatterTile;
+    size_t words = 3 * nd + kBlock + 1 + tile;
     words += words & 1;  // 8-byte alignment of the key stage
     // staged keys, digits and (batch level 1) global buckets
-    return words * 4 + (size_t)kScatterTile * 8 + (size_t)kScatterTile * 2 + (size_t)kScatterTile * 4;
+    return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (size_t)tile * 4;
 }
 
 size_t sort_lds_bytes(uint32_t cap) {
-    return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 20;
+    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 20;
 }
 
 size_t resolve_lds_bytes(uint32_t cap) {
-    return ((size_t)(1u << kSortSubBits) + kBlock + 2) * 4 + (size_t)cap * 12;
+    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 12;
 }
 
 // Workgroups of a persistent kernel: as many as can be resident at once
@@ -385,8 +413,8 @@ gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
 // batch arguments ba1 / ba2 of those levels.  Leaves c->coarse_off /
 // c->fine_off as the bucket boundaries; returns the buffer index holding the
 // result in *out.
-template <int kSrc1, int kSrc2>
-gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
+template <int kSrc1, int kSrc2, int kTile>
+gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
                               int kid_scatter1, int kid_counts2, int kid_scatter2, BatchArgs ba1, BatchArgs ba2) {
@@ -397,20 +425,20 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, n,
                      p.ntiles1));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;
-    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc1>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
+    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
                      (size_t)nd1 * 4, idx[src], key[src], t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
                      c->lvl1_tiles, c->counts1, ba1));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1, (int)p.b1,
                      c->partial));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kBlock), 0, c->partial, nchunks, (int)p.b1,
-                     c->coarse_off, c->tile_first));
+                     c->coarse_off, c->tile_first, (uint32_t)kTile));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1,
                      (int)p.b1, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
-    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc1>, scatter_lds_bytes(p.b1), p.ntiles1)),
-                     dim3(kBlock), scatter_lds_bytes(p.b1), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0,
+    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile>, scatter_lds_bytes(p.b1, kTile), p.ntiles1)),
+                     dim3(kBlock), scatter_lds_bytes(p.b1, kTile), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err,
                      ba1));
     if (p.b2 == 0) {
@@ -423,20 +451,34 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
     GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
     const int shift2 = 64 - (int)p.bbits;
-    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc2>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
+    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
                      (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, c->coarse_off,
                      c->tile_first, c->counts2, ba2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
-    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc2>, scatter_lds_bytes(p.b2), tiles2)), dim3(kBlock),
-                     scatter_lds_bytes(p.b2), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile>, scatter_lds_bytes(p.b2, kTile), tiles2)), dim3(kBlock),
+                     scatter_lds_bytes(p.b2, kTile), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
                      p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
     *bucket_off = c->fine_off;
     *nbuckets = p.nfine;
     return GESMC_OK;
+}
+
+template <int kSrc1, int kSrc2>
+gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
+                              uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
+                              int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
+                              int kid_scatter1, int kid_counts2, int kid_scatter2, BatchArgs ba1, BatchArgs ba2) {
+    if (p.tile == (uint32_t)kTileLarge)
+        return radix_distribute_t<kSrc1, kSrc2, kTileLarge>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
+                                                            bucket_off, nbuckets, kid_counts1, kid_scatter1,
+                                                            kid_counts2, kid_scatter2, ba1, ba2);
+    return radix_distribute_t<kSrc1, kSrc2, kTileSmall>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
+                                                        bucket_off, nbuckets, kid_counts1, kid_scatter1, kid_counts2,
+                                                        kid_scatter2, ba1, ba2);
 }
 
 // One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
@@ -921,17 +963,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         while (qa > 0 && r_eff(order[qa - 1]) <= st) --qa;
         const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
         const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
-        Plan p;
-        p.m = P;
-        p.ell = P / 2;
-        uint32_t B = 0;
-        while ((1ull << B) < NB) ++B;
-        p.bbits = B;
-        p.b1 = std::min<uint32_t>(B, 8);
-        p.b2 = B - p.b1;
-        p.ncoarse = 1u << p.b1;
-        p.nfine = 1u << B;
-        p.ntiles1 = std::max<uint32_t>(1, ceil_div(P, kScatterTile));
+        const Plan p = batch_plan(c, P, NB);
         BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all};
         c->ctr_step = c->ctr + st;
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
@@ -1040,7 +1072,8 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
         c->num_cus = prop.multiProcessorCount;
     // fixed-size area: err[16], ucount[16], coarse offsets / tile map, level-1 segment, fine offsets
     const size_t nf = (size_t)1 << kMaxFineBits;
-    const size_t words = 16 + 16 + 2 * 264 + 8 + (nf + 8);
+    const size_t nc = ((size_t)1 << kMaxCoarseBits) + 8;
+    const size_t words = 16 + 16 + 2 * nc + 8 + (nf + 8);
     if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK ||
         dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK ||
         dev_alloc((void **)&c->bslot, 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1) * sizeof(uint4)) != GESMC_OK) {
@@ -1054,9 +1087,9 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     c->ucount = w;
     w += 16;
     c->coarse_off = w;
-    w += 264;
+    w += nc;
     c->tile_first = w;
-    w += 264;
+    w += nc;
     c->lvl1_seg = w;
     w += 4;
     c->lvl1_tiles = w;
@@ -1064,12 +1097,19 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     c->fine_off = w;
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sort_lds_bytes(kSortMaxItems * kBlock));
-    for (const void *f : {(const void *)k_scatter<kSrcPerm>, (const void *)k_scatter<kSrcHash>,
-                          (const void *)k_scatter<kSrcBatch>, (const void *)k_scatter<kSrcBucket>})
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds_bytes(12));
+                              (int)sort_lds_bytes(kLdsCap));
+    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileSmall>, (const void *)k_scatter<kSrcHash, kTileSmall>,
+                          (const void *)k_scatter<kSrcBatch, kTileSmall>,
+                          (const void *)k_scatter<kSrcBucket, kTileSmall>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)scatter_lds_bytes(12, kTileSmall));
+    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileLarge>, (const void *)k_scatter<kSrcHash, kTileLarge>,
+                          (const void *)k_scatter<kSrcBatch, kTileLarge>,
+                          (const void *)k_scatter<kSrcBucket, kTileLarge>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)scatter_lds_bytes(12, kTileLarge));
     (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)resolve_lds_bytes(kSortMaxItems * kBlock));
+                              (int)resolve_lds_bytes(kLdsCap));
     (void)hipGetLastError();
     if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
         hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
@@ -1193,11 +1233,11 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
     }
     switch (option) {
         case GESMC_OPT_BUCKET_AVG:
-            if (v < 64 || v > (3 << kSortSubBits) / 4) break;
+            if (v < 64 || v > (int64_t)(3 * kLdsCap / 4)) break;
             c->bucket_avg = (uint32_t)v;
             return GESMC_OK;
         case GESMC_OPT_SORT_CAP:
-            if (v < 64 || v > kSortMaxItems * kBlock) break;
+            if (v < 64 || v > (int64_t)kLdsCap) break;
             c->sort_cap = (uint32_t)v;
             return GESMC_OK;
         case GESMC_OPT_FAST_ROUNDS:
@@ -1206,6 +1246,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_LEVEL1_BITS:
+            if (v < 0 || v > (int64_t)kMaxCoarseBits) break;
+            c->level1_cap = (uint32_t)v;
             return GESMC_OK;
         case GESMC_OPT_PROFILE_ONLY:
             if (v < -1 || v >= KID_COUNT) break;

@@ -4,13 +4,13 @@
 // Philox key of edge index i in superstep t.
 //
 // MSD radix layout for gfx950:
-//   level 1   : coarse digit = top b1 bits of K (b1 <= 8), LDS-staged scatter;
+//   level 1   : coarse digit = top b1 bits of K (b1 <= 10), LDS-staged scatter;
 //               run bases from per-tile digit counts and a column scan
 //   level 2   : sub digit    = next b2 bits, scattered inside each coarse
 //               bucket (its region is small enough to stay L2/MALL resident)
-//   bucket    : each fine bucket (~0.5-1k records) is counting-sorted in LDS
-//               on the next 11 bits of K, then ties inside a 12-bit cell are
-//               settled by insertion sort on (K, i).
+//   bucket    : each fine bucket (~400-770 records) is counting-sorted in
+//               LDS on the next kCellBits bits of K, then the records of a
+//               cell are settled by insertion sort on (K, i).
 // Keys are never stored: every pass recomputes K_i from the record's index.
 #pragma once
 
@@ -18,15 +18,19 @@
 
 namespace gesmc {
 
-#ifndef GESMC_SCATTER_TILE
-#define GESMC_SCATTER_TILE 2048
+// Records per scatter workgroup ("tile"): 2048, or 4096 for passes over at
+// least 2^25 records, where the longer runs per digit of the second level
+// pay off; on smaller passes the larger tile leaves CUs idle.
+constexpr int kTileSmall = 2048, kTileLarge = 4096;
+constexpr uint32_t kLargeTileRecords = 1u << 25;
+constexpr uint32_t kMaxCoarseBits = 10;  // digit bits of the first radix level
+#ifndef GESMC_CELL_BITS
+#define GESMC_CELL_BITS 8
 #endif
-#ifndef GESMC_SORT_SUB_BITS
-#define GESMC_SORT_SUB_BITS 10
-#endif
-constexpr int kScatterTile = GESMC_SCATTER_TILE;     // records per scatter workgroup
-constexpr int kSortSubBits = GESMC_SORT_SUB_BITS;    // counting-sort cells per bucket = 2^bits
-constexpr int kSortMaxItems = (1 << kSortSubBits) / kBlock;  // per-thread records (cap <= 2^bits)
+constexpr int kCellBits = GESMC_CELL_BITS;   // LDS counting-sort cells per bucket / partition = 2^bits
+constexpr int kSortMaxItems = 4;             // records per thread held in LDS
+constexpr uint32_t kLdsCap = kSortMaxItems * kBlock;  // records of one bucket sorted in LDS
+static_assert((1 << kCellBits) >= kBlock, "every thread owns at least one cell");
 
 // Inclusive prefix sum across one wave64 (shuffle-up ladder).
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
@@ -166,23 +170,22 @@ struct TileSpan {
     uint32_t seg, seg_begin, seg_end, begin, cnt;
 };
 
+template <int kTile>
 __device__ __forceinline__ TileSpan tile_span(const uint32_t *seg_off, const uint32_t *tile_first, uint32_t nseg,
                                               uint32_t w) {
     TileSpan ts;
     ts.seg = tile_segment(tile_first, nseg, w);
     ts.seg_begin = seg_off[ts.seg];
     ts.seg_end = seg_off[ts.seg + 1];
-    ts.begin = ts.seg_begin + (w - tile_first[ts.seg]) * kScatterTile;
-    const uint32_t end = min(ts.begin + kScatterTile, ts.seg_end);
+    ts.begin = ts.seg_begin + (w - tile_first[ts.seg]) * kTile;
+    const uint32_t end = min(ts.begin + kTile, ts.seg_end);
     ts.cnt = end > ts.begin ? end - ts.begin : 0;
     return ts;
 }
 
-constexpr int kTileItems = kScatterTile / kBlock;
-
 // Tiles are processed by persistent workgroups; the records of the next
 // tile are loaded into registers while the current one is counted.
-template <int kSrc>
+template <int kSrc, int kTile>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restrict__ src_idx,
                                                         const unsigned long long *__restrict__ src_key, uint32_t t,
                                                         uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
@@ -190,11 +193,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
                                                         const uint32_t *__restrict__ tile_first,
                                                         uint32_t *__restrict__ counts, BatchArgs ba) {
     extern __shared__ uint32_t hs[];
+    constexpr int kTileItems = kTile / kBlock;
     const uint32_t nt = tile_first[nseg];
     const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
     uint32_t w = blockIdx.x;
     if (w >= nt) return;
-    TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
+    TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
     uint32_t cur_i[kTileItems], cur_a[kTileItems];
     unsigned long long cur_k[kTileItems];
     auto load = [&](const TileSpan &sp, uint32_t *ri, unsigned long long *rk, uint32_t *ra) {
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         uint32_t nxt_i[kTileItems], nxt_a[kTileItems];
         unsigned long long nxt_k[kTileItems];
         if (wn < nt) {
-            tn = tile_span(seg_off, tile_first, nseg, wn);
+            tn = tile_span<kTile>(seg_off, tile_first, nseg, wn);
             load(tn, nxt_i, nxt_k, nxt_a);
         }
         for (uint32_t d = tid; d < nd; d += kBlock) hs[d] = 0;
@@ -260,8 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_colsum(const uint32_t *__restrict__ 
 // totals -> digit bases (the coarse offsets), and the level-2 tile map.
 __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ partial, uint32_t nchunks, int dbits,
                                                         uint32_t *__restrict__ coarse_off,
-                                                        uint32_t *__restrict__ tile_first) {
-    __shared__ uint32_t tot[257], tiles[257], tmp[kBlock + 1];
+                                                        uint32_t *__restrict__ tile_first, uint32_t tile) {
+    __shared__ uint32_t tot[(1u << kMaxCoarseBits) + 1], tiles[(1u << kMaxCoarseBits) + 1], tmp[kBlock + 1];
     const uint32_t nd = 1u << dbits;
     for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
         uint32_t run = 0;
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ p
             }
         }
         tot[d] = run;
-        tiles[d] = (run + kScatterTile - 1) / kScatterTile;
+        tiles[d] = (run + tile - 1) / tile;
     }
     __syncthreads();
     uint32_t total_tiles;
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
 // staged records (scatter_lds_bytes on the host).
 constexpr int kScatterOffRegs = 4;  // run bases prefetched per thread (2^dbits <= 1024)
 
-template <int kSrc>
+template <int kSrc, int kTile>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
                                                     uint32_t *__restrict__ dst_idx,
@@ -372,23 +376,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     BatchArgs ba) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_total;
+    constexpr int kTileItems = kTile / kBlock;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
     uint32_t *base = start + nd;         // nd (global run base)
     uint32_t *tmp = base + nd;           // kBlock + 1
-    uint32_t *s_idx = tmp + kBlock + 1;  // kScatterTile
+    uint32_t *s_idx = tmp + kBlock + 1;  // kTile
     unsigned long long *s_key =
-        reinterpret_cast<unsigned long long *>(s_idx + kScatterTile + ((kBlock + 1 + 3 * nd + kScatterTile) & 1));
-    uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kScatterTile);
-    uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kScatterTile);  // kSrcBatch only
+        reinterpret_cast<unsigned long long *>(s_idx + kTile + ((kBlock + 1 + 3 * nd + kTile) & 1));
+    uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kTile);
+    uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kTile);  // kSrcBatch only
 
     const uint32_t nt = tile_first[nseg];
     const uint32_t tid = threadIdx.x;
     uint32_t w = blockIdx.x;
     if (w >= nt) return;
 
-    TileSpan ts = tile_span(seg_off, tile_first, nseg, w);
+    TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
     uint32_t c_idx[kTileItems], c_aux[kTileItems], c_off[kScatterOffRegs];
     unsigned long long c_key[kTileItems];
     auto load = [&](const TileSpan &sp, uint32_t wt, uint32_t *ri, unsigned long long *rk, uint32_t *ra,
@@ -415,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         uint32_t n_idx[kTileItems], n_aux[kTileItems], n_off[kScatterOffRegs];
         unsigned long long n_key[kTileItems];
         if (wn < nt) {
-            tn = tile_span(seg_off, tile_first, nseg, wn);
+            tn = tile_span<kTile>(seg_off, tile_first, nseg, wn);
             load(tn, wn, n_idx, n_key, n_aux, n_off);
         }
 
@@ -485,12 +490,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
     }
 }
 
-// Sorts each fine bucket by (K, i): LDS counting sort on the kSortSubBits
+// Sorts each fine bucket by (K, i): LDS counting sort on the kCellBits
 // bits of K below the B bucket bits, then insertion sort inside each cell.
 // Persistent workgroups prefetch the next bucket into registers.  Buckets
 // larger than `cap` (not expected: the mean is cap / 2 and sizes are
 // binomial) take a slow exact path that ranks every record against the whole
-// bucket.  Dynamic LDS: 2^kSortSubBits cell counters + kBlock + 2 scan words
+// bucket.  Dynamic LDS: 2^kCellBits cell counters + kBlock + 2 scan words
 // + cap * 20 bytes.
 __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restrict__ src_idx,
                                                          const unsigned long long *__restrict__ src_key,
@@ -503,14 +508,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
                                                          const BatchGraph *__restrict__ gr, uint32_t ngraphs,
                                                          uint32_t step) {
     extern __shared__ uint32_t lds[];
-    constexpr uint32_t kCells = 1u << kSortSubBits;
+    constexpr uint32_t kCells = 1u << kCellBits;
     uint32_t *cell = lds;                    // kCells
     uint32_t *tmp = cell + kCells;           // kBlock + 1 (+1 pad for 8-byte alignment)
     unsigned long long *sK = reinterpret_cast<unsigned long long *>(tmp + kBlock + 2);
     unsigned long long *sE = sK + cap;
     uint32_t *sI = reinterpret_cast<uint32_t *>(sE + cap);
     const uint32_t tid = threadIdx.x;
-    const int sub_shift = 64 - kSortSubBits;
+    const int sub_shift = 64 - kCellBits;
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
 
     uint32_t f = blockIdx.x;
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
             return gr ? batch_perm_key(bg, idx, step) : perm_key(idx, t, k0, k1);
         };
         auto cell_of = [&](uint64_t K) -> uint32_t {
-            if (gr) return ((uint32_t)((K >> 32) * (uint64_t)bg.nb)) >> (32 - kSortSubBits);
+            if (gr) return ((uint32_t)((K >> 32) * (uint64_t)bg.nb)) >> (32 - kCellBits);
             return (uint32_t)((bbits >= 64 ? 0ull : (K << bbits)) >> sub_shift);
         };
         if (c > lds_cap) {

@@ -171,10 +171,10 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
 
 // Persistent workgroups over the fine partitions; the next partition's
 // tuples are prefetched into registers.  LDS path: counting sort on
-// kSortSubBits hash bits below the partition bits, then each thread sorts the
+// kCellBits hash bits below the partition bits, then each thread sorts the
 // cells it owns by (key, tag) and walks them.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
-// Dynamic LDS: 2^kSortSubBits cell words + kBlock + 2 words + cap * 12 bytes.
+// Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 12 bytes.
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
                                                     uint32_t *__restrict__ sc_tag,
                                                     unsigned long long *__restrict__ sc_key, int pbits,
@@ -182,13 +182,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                                                     uint2 *__restrict__ info, uint32_t *__restrict__ err,
                                                     uint32_t dup_bit, StepCounters *ctr, GraphErr ge) {
     extern __shared__ uint32_t lds[];
-    constexpr uint32_t kCells = 1u << kSortSubBits;
+    constexpr uint32_t kCells = 1u << kCellBits;
     uint32_t *cell = lds;
     uint32_t *tmp = cell + kCells;
     unsigned long long *sK = reinterpret_cast<unsigned long long *>(tmp + kBlock + 2);
     uint32_t *sT = reinterpret_cast<uint32_t *>(sK + cap);
     const uint32_t tid = threadIdx.x;
-    const int sub_shift = 64 - kSortSubBits;
+    const int sub_shift = 64 - kCellBits;
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
 
     uint32_t f = blockIdx.x;

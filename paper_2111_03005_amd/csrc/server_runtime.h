@@ -211,17 +211,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         std::swap(c->key[0], c->key[1]);
     }
     // one superstep of every resident graph (each at its own superstep t0 + done)
-    Plan p;
-    p.m = npos;
-    p.ell = npos / 2;
-    uint32_t B = 0;
-    while ((1ull << B) < bbase) ++B;
-    p.bbits = B;
-    p.b1 = std::min<uint32_t>(B, 8);
-    p.b2 = B - p.b1;
-    p.ncoarse = 1u << p.b1;
-    p.nfine = 1u << B;
-    p.ntiles1 = std::max<uint32_t>(1, ceil_div(npos, kScatterTile));
+    const Plan p = batch_plan(c, npos, bbase);
     BatchStep bs{c->gr, G, 0u, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
     c->ctr_step = c->ctr;
     GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
