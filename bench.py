@@ -45,9 +45,9 @@ def kernel_bytes(name: str, m: int, ell: int) -> float | None:
         "k_unpermute": 12.0 * m + 8.0 * m,
         "k_load": 8.0 * m + 12.0 * m,
         # sorted-tuples dependency resolution: 4 tuples of 12 bytes per switch
-        "k_emit": 24.0 * ell + 48.0 * ell + 16.0 * ell,  # pair records in, tuples + free target records out
-        "k_tcounts1": 32.0 * ell,                        # tuple keys
-        "k_tscatter1": 48.0 * ell + 48.0 * ell,          # tuple slots in, partitioned tuples out
+        "k_emit": 24.0 * ell + 16.0 * ell + 1.0 * ell,   # pair records in, free target records + statuses out
+        "k_tcounts1": 24.0 * ell,                        # pair records (tuples computed from them)
+        "k_tscatter1": 24.0 * ell + 48.0 * ell,          # pair records in, partitioned tuples out
         "k_tcounts2": 32.0 * ell,
         "k_tscatter2": 48.0 * ell + 48.0 * ell,
         "k_resolve": 48.0 * ell,                         # tuples in (records out are rare)

@@ -212,6 +212,8 @@ gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
                                    0 = one workgroup per tile or bucket (default 0)                */
 #define GESMC_OPT_LEVEL1_BITS 8  /* digit bits of the first radix level (1 .. 10); 0 = half of the
                                     bucket bits, rounded up (default)                              */
+#define GESMC_OPT_FUSE_EMIT 9      /* 1: the first tuple partition pass computes the switches' tuples from
+                                      their pair records (default); 0: they are written out first     */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

@@ -20,6 +20,7 @@ E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_AGAIN, E_CANCELED, E_INTERN
 OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST, OPT_PROFILE_ONLY = (
     1, 2, 3, 4, 5, 6, 7)
 OPT_LEVEL1_BITS = 8
+OPT_FUSE_EMIT = 9
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 

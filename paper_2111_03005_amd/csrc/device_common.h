@@ -104,6 +104,30 @@ struct BatchGraph {
     uint32_t pl;     // P_L = pl / 2^32 of the graph
 };
 
+// Switch k's targets from its sources (tau of Def. 2.1 on canonical edges).
+struct Targets {
+    uint64_t A, B;
+    bool loop;
+};
+
+__device__ __forceinline__ Targets switch_targets(uint64_t e1, uint64_t e2, bool g) {
+    const uint32_t u = ekey_lo_vertex(e1), v = ekey_hi_vertex(e1);
+    const uint32_t x = ekey_lo_vertex(e2), y = ekey_hi_vertex(e2);
+    // g = 0: (u,x),(v,y)     g = 1: (u,y),(v,x)
+    const uint32_t a1 = g ? y : x, b1 = g ? x : y;
+    Targets T;
+    T.loop = (u == a1) || (v == b1);
+    T.A = ekey(u, a1);
+    T.B = ekey(v, b1);
+    return T;
+}
+
+// Dependency tuples (tag, edge key): an ERASE tuple carries the switch that
+// erases its key (or kTagStays for an edge that survives the superstep), an
+// INSERT tuple kTagInsert | (k << 1 | h) for target h of switch k.
+constexpr uint32_t kTagInsert = 0x80000000u;
+constexpr uint32_t kTagStays = 0x7FFFFFFEu;
+
 // Permutation key of record (input position idx) of graph g in batch superstep s.
 __device__ __forceinline__ uint64_t batch_perm_key(const BatchGraph &g, uint32_t idx, uint32_t s) {
     if (idx == kPadIdx) return ~0ull;

@@ -104,6 +104,7 @@ struct gesmc_ctx {
     int fast_rounds = 2;
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     uint32_t level1_cap = 0;  // first-level digit bits (0: even split)
+    bool fuse_emit = true;    // tuples computed in the first partition pass (else stored flat)
     int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
     int profile_only = -1;  // kernel id timed while profiling (-1: every kernel)
@@ -360,12 +361,13 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     return p;
 }
 
-size_t scatter_lds_bytes(int dbits, uint32_t tile) {
+// LDS of k_scatter: counters, staged indices, keys and digits, and (batch
+// level 1 only) staged global buckets.  It bounds the workgroups per CU.
+size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true) {
     const size_t nd = (size_t)1 << dbits;
     size_t words = 3 * nd + kBlock + 1 + tile;
     words += words & 1;  // 8-byte alignment of the key stage
-    // staged keys, digits and (batch level 1) global buckets
-    return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (size_t)tile * 4;
+    return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (buckets ? (size_t)tile * 4 : 0);
 }
 
 size_t sort_lds_bytes(uint32_t cap) {
@@ -417,7 +419,11 @@ template <int kSrc1, int kSrc2, int kTile>
 gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
-                              int kid_scatter1, int kid_counts2, int kid_scatter2, BatchArgs ba1, BatchArgs ba2) {
+                              int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
+                              const uint32_t *in_idx, const unsigned long long *in_key) {
+    // level-1 input: buffer `src`, or the given arrays (the pair records of kSrcEmit)
+    const uint32_t *src_i = in_idx ? in_idx : idx[src];
+    const unsigned long long *src_k = in_key ? in_key : key[src];
     const uint32_t nd1 = 1u << p.b1;
     const uint32_t nchunks = ceil_div(p.ntiles1, kScanChunk);
     GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
@@ -427,7 +433,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;
     GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile>,
                      dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
-                     (size_t)nd1 * 4, idx[src], key[src], t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
+                     (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
                      c->lvl1_tiles, c->counts1, ba1));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1, (int)p.b1,
                      c->partial));
@@ -436,9 +442,10 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1,
                      (int)p.b1, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
+    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch);
+    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile>, scatter_lds_bytes(p.b1, kTile), p.ntiles1)),
-                     dim3(kBlock), scatter_lds_bytes(p.b1, kTile), idx[src], key[src], idx[lvl1_out], key[lvl1_out], t, k0,
+                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile>, lds1, p.ntiles1)), dim3(kBlock), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err,
                      ba1));
     if (p.b2 == 0) {
@@ -458,8 +465,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
     GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile>, scatter_lds_bytes(p.b2, kTile), tiles2)), dim3(kBlock),
-                     scatter_lds_bytes(p.b2, kTile), idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile>, lds2, tiles2)), dim3(kBlock), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
                      p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
     *bucket_off = c->fine_off;
@@ -471,14 +477,15 @@ template <int kSrc1, int kSrc2>
 gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
-                              int kid_scatter1, int kid_counts2, int kid_scatter2, BatchArgs ba1, BatchArgs ba2) {
+                              int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
+                              const uint32_t *in_idx = nullptr, const unsigned long long *in_key = nullptr) {
     if (p.tile == (uint32_t)kTileLarge)
         return radix_distribute_t<kSrc1, kSrc2, kTileLarge>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                             bucket_off, nbuckets, kid_counts1, kid_scatter1,
-                                                            kid_counts2, kid_scatter2, ba1, ba2);
+                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key);
     return radix_distribute_t<kSrc1, kSrc2, kTileSmall>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                         bucket_off, nbuckets, kid_counts1, kid_scatter1, kid_counts2,
-                                                        kid_scatter2, ba1, ba2);
+                                                        kid_scatter2, ba1, ba2, in_idx, in_key);
 }
 
 // One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
@@ -522,15 +529,15 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
     uint32_t nb = 0;
     const int mid = X, dst = p.b2 > 0 ? Y : X;
     if (bs) {
-        const BatchArgs ba1{bs->gr, bs->pg, bs->bk, bs->step, (int)p.bbits};
-        const BatchArgs ba2{bs->gr, bs->bk, nullptr, bs->step, (int)p.bbits};
+        const SrcArgs ba1{bs->gr, bs->pg, bs->bk, bs->step, (int)p.bbits};
+        const SrcArgs ba2{bs->gr, bs->bk, nullptr, bs->step, (int)p.bbits};
         GESMC_TRY((radix_distribute<kSrcBatch, kSrcBucket>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
                                                            &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
                                                            KID_SCATTER2, ba1, ba2)));
     } else {
         GESMC_TRY((radix_distribute<kSrcPerm, kSrcPerm>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
                                                         &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
-                                                        KID_SCATTER2, BatchArgs{}, BatchArgs{})));
+                                                        KID_SCATTER2, SrcArgs{}, SrcArgs{})));
     }
     const int sorted = (dist == X) ? Y : X;  // sort into the buffer not holding the buckets
     GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(persistent_blocks(c, k_sort_buckets, sort_lds, nb)),
@@ -543,15 +550,31 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
 
 // Partitions the tuples in tuple buffer 0 (nslots slots, empty keys dropped)
 // by key hash and resolves every partition.
+// Tuples come from tuple buffer 0 (validation), or -- with `emit` -- are
+// computed from the pair records si / sk of a superstep in the first pass.
+struct EmitSource {
+    const uint32_t *si;
+    const unsigned long long *sk;
+    uint32_t t, k0, k1;
+    SrcArgs sa;
+};
+
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
-                                   GraphErr ge = GraphErr{nullptr, 0, nullptr}) {
+                                   GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
-    GESMC_TRY((radix_distribute<kSrcHash, kSrcHash>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
-                                                    p.b2 > 0 ? 2 : 1, &parts, &poff, &np, KID_TCOUNTS1, KID_TSCATTER1,
-                                                    KID_TCOUNTS2, KID_TSCATTER2, BatchArgs{}, BatchArgs{})));
+    if (emit)
+        GESMC_TRY((radix_distribute<kSrcEmit, kSrcHash>(c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag,
+                                                        c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts, &poff, &np,
+                                                        KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2,
+                                                        emit->sa, SrcArgs{}, emit->si, emit->sk)));
+    else
+        GESMC_TRY((radix_distribute<kSrcHash, kSrcHash>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
+                                                        p.b2 > 0 ? 2 : 1, &parts, &poff, &np, KID_TCOUNTS1,
+                                                        KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, SrcArgs{},
+                                                        SrcArgs{})));
     const int scratch = parts == 2 ? 1 : 0;
     const size_t rlds = resolve_lds_bytes(c->sort_cap);
     GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(persistent_blocks(c, k_resolve, rlds, np)),
@@ -570,15 +593,20 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
     // per-block counts of emit and the first round go to slots [0, ge) and [ge, ge + gd)
     const uint32_t ge = grid_stride_blocks(c, (uint64_t)p.ell + 1), gd = grid_stride_blocks(c, p.ell);
-    if (bs)
-        GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit<true>, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
-                         c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot, bs->gr, bs->pg,
-                         bs->step));
-    else
-        GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit<false>, dim3(ge), dim3(kBlock), 0, si, sk, p.m, t, k0, k1, pl,
-                         c->tu_tag[0], c->tu_key[0], c->info, c->st, c->idx[0], c->key[0], c->bslot,
-                         (const BatchGraph *)nullptr, (const uint32_t *)nullptr, 0u));
-    GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr}));
+    SrcArgs sa{};
+    sa.gr = bs ? bs->gr : nullptr;
+    sa.pg = bs ? bs->pg : nullptr;
+    sa.step = bs ? bs->step : 0u;
+    sa.m = p.m;
+    sa.pl = pl;
+    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, t, k0, k1, sa, c->info, c->st,
+                     c->idx[0], c->key[0], c->bslot));
+    const EmitSource es{si, sk, t, k0, k1, sa};
+    if (!c->fuse_emit)
+        GESMC_TRY(launch(c, s, KID_EMIT, nslots, k_emit_tuples, dim3(grid_stride_blocks(c, nslots)), dim3(kBlock), 0,
+                         si, sk, t, k0, k1, sa, nslots, c->tu_tag[0], c->tu_key[0]));
+    GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr},
+                                    c->fuse_emit ? &es : nullptr));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -1246,6 +1274,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_FUSE_EMIT:
+            if (v < 0 || v > 1) break;
+            c->fuse_emit = v != 0;
             return GESMC_OK;
         case GESMC_OPT_LEVEL1_BITS:
             if (v < 0 || v > (int64_t)kMaxCoarseBits) break;

@@ -120,31 +120,115 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
 // Radix source of a record.  kSrcPerm sorts edge records by the Philox key
 // of their index (the permutation); kSrcHash sorts (tag, edge key) tuples by
 // a hash of the edge key (the dependency partitions), where an empty key
-// marks a tuple slot that carries nothing.  A batch of graphs sorts by the
-// global bucket (graph, K range) of each record: kSrcBatch computes it from
-// the graph of the record's position (level 1) and writes it out beside the
-// record, kSrcBucket reads it back (level 2).  Bucket numbers are placed in
-// the top B bits of the radix word, so both levels use the same shifts.
-enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3 };
+// marks a tuple slot that carries nothing; kSrcEmit is kSrcHash over the
+// tuples of the switches themselves, computed from the pair records while
+// they are read (slots 4k .. 4k+3 of switch k; see emit_switch), so the flat tuple
+// array is never stored.  A batch of graphs sorts by the global bucket
+// (graph, K range) of each record: kSrcBatch computes it from the graph of
+// the record's position (level 1) and writes it out beside the record,
+// kSrcBucket reads it back (level 2).  Bucket numbers are placed in the top
+// B bits of the radix word, so both levels use the same shifts.
+enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3, kSrcEmit = 4 };
 
-struct BatchArgs {
-    const BatchGraph *gr;    // per graph (kSrcBatch)
+struct SrcArgs {
+    const BatchGraph *gr;    // per graph (batches)
     const uint32_t *aux_in;  // kSrcBatch: graph of each position; kSrcBucket: bucket of each position
     uint32_t *aux_out;       // kSrcBatch: bucket of each output position
     uint32_t step;           // batch superstep
     int bbits;               // bucket bits B (1 .. 32)
+    // kSrcEmit
+    const uint32_t *pg;      // batch: graph of each position (nullptr: one graph)
+    uint32_t m;              // records (the pair records of ell = m / 2 switches)
+    uint32_t pl;             // P_L threshold (batch: nonzero if some graph has one)
 };
 
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_idx() { return kSrc == kSrcPerm || kSrc == kSrcBatch; }
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcBatch || kSrc == kSrcBucket; }
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_is_tuple() { return kSrc == kSrcHash || kSrc == kSrcEmit; }
+
+// Local outcome of switch k from its pair records (ij, ee): P_L skip, the
+// idle pair of a batch graph's padding record, a loop, or a target equal to
+// one of its own sources (Def. 2.1); ST_UNDECIDED if it depends on others.
+__device__ __forceinline__ uint8_t switch_local(uint32_t k, uint2 ij, ulonglong2 ee, uint32_t t, uint32_t k0,
+                                                uint32_t k1, const SrcArgs &sa, Targets *T) {
+    bool skip = false;
+    if (sa.pg) {
+        if (ij.x == kPadIdx || ij.y == kPadIdx) return ST_IDLE;
+        if (sa.pl != 0) {  // some graph of the batch has P_L > 0
+            const BatchGraph &g = sa.gr[sa.pg[2 * (size_t)k]];
+            skip = pl_skip(k - (g.poff >> 1), g.t0 + sa.step, g.pl, g.k0, g.k1);
+        }
+    } else {
+        skip = pl_skip(k, t, sa.pl, k0, k1);
+    }
+    if (skip) return ST_PL;
+    *T = switch_targets(ee.x, ee.y, ij.x < ij.y);
+    if (T->loop) return ST_LOOP;
+    if (T->A == ee.x || T->A == ee.y || T->B == ee.x || T->B == ee.y) return ST_EXISTS;
+    return ST_UNDECIDED;
+}
+
+struct Tuple {
+    uint32_t tag;
+    unsigned long long key;
+};
+
+// The four tuple slots 4k .. 4k+3 of switch k (Alg. 1's erase and insert
+// entries): j = 0, 1 the ERASE tuples of its sources, j = 2, 3 the INSERT
+// tuples of its targets.  A switch decided locally keeps its sources (STAYS)
+// and inserts nothing; slot 4 ell holds the idle record of odd m.
+__device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, const unsigned long long *sk, uint32_t t,
+                                            uint32_t k0, uint32_t k1, const SrcArgs &sa, Tuple *tp) {
+    const uint32_t ell = sa.m >> 1;
+    tp[1] = tp[2] = tp[3] = Tuple{0u, kEmptyKey};
+    if (k >= ell) {
+        tp[0] = (k == ell && (sa.m & 1u)) ? Tuple{kTagStays, sk[sa.m - 1]} : Tuple{0u, kEmptyKey};
+        return;
+    }
+    const uint2 ij = reinterpret_cast<const uint2 *>(si)[k];
+    const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(sk)[k];
+    Targets T{0, 0, false};
+    const uint8_t status = switch_local(k, ij, ee, t, k0, k1, sa, &T);
+    if (status == ST_UNDECIDED) {
+        tp[0] = Tuple{k, ee.x};
+        tp[1] = Tuple{k, ee.y};
+        tp[2] = Tuple{kTagInsert | (k << 1), T.A};
+        tp[3] = Tuple{kTagInsert | (k << 1) | 1u, T.B};
+    } else {
+        tp[0] = Tuple{kTagStays, ij.x == kPadIdx ? kEmptyKey : ee.x};
+        tp[1] = Tuple{kTagStays, ij.y == kPadIdx ? kEmptyKey : ee.y};
+    }
+}
+
+// kSrcEmit tiles: each thread takes whole switches, so the four slots of a
+// switch are items 4j .. 4j+3 of one thread (slot order inside a tile does
+// not matter: partitions are sorted later).
+template <int kTileItems>
+__device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const uint32_t *si,
+                                          const unsigned long long *sk, uint32_t t, uint32_t k0, uint32_t k1,
+                                          const SrcArgs &sa, uint32_t *tag, unsigned long long *key) {
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kTileItems / 4; ++j) {
+        const uint32_t sl = 4 * (tid + j * kBlock);  // first local slot of this thread's switch
+        Tuple tp[4] = {{0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}};
+        if (sl < cnt) emit_switch((begin + sl) >> 2, si, sk, t, k0, k1, sa, tp);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            tag[4 * j + h] = tp[h].tag;
+            key[4 * j + h] = sl + h < cnt ? tp[h].key : kEmptyKey;
+        }
+    }
+}
 
 // Radix word of one record; *bucket receives the global bucket (kSrcBatch).
 template <int kSrc>
 __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t aux, uint32_t t,
-                                               uint32_t k0, uint32_t k1, const BatchArgs &ba, uint32_t *bucket) {
-    if (kSrc == kSrcHash) return slot_hash(key);
+                                               uint32_t k0, uint32_t k1, const SrcArgs &ba, uint32_t *bucket) {
+    if (src_is_tuple<kSrc>()) return slot_hash(key);
     if (kSrc == kSrcPerm) return perm_key(idx, t, k0, k1);
     uint32_t b = aux;
     if (kSrc == kSrcBatch) {
@@ -183,51 +267,45 @@ __device__ __forceinline__ TileSpan tile_span(const uint32_t *seg_off, const uin
     return ts;
 }
 
-// Tiles are processed by persistent workgroups; the records of the next
-// tile are loaded into registers while the current one is counted.
+// One workgroup per tile (a grid smaller than the tile count walks the
+// tiles grid-stride).
 template <int kSrc, int kTile>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restrict__ src_idx,
                                                         const unsigned long long *__restrict__ src_key, uint32_t t,
                                                         uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
                                                         const uint32_t *__restrict__ seg_off,
                                                         const uint32_t *__restrict__ tile_first,
-                                                        uint32_t *__restrict__ counts, BatchArgs ba) {
+                                                        uint32_t *__restrict__ counts, SrcArgs ba) {
     extern __shared__ uint32_t hs[];
     constexpr int kTileItems = kTile / kBlock;
     const uint32_t nt = tile_first[nseg];
     const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
-    uint32_t w = blockIdx.x;
-    if (w >= nt) return;
-    TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
-    uint32_t cur_i[kTileItems], cur_a[kTileItems];
-    unsigned long long cur_k[kTileItems];
-    auto load = [&](const TileSpan &sp, uint32_t *ri, unsigned long long *rk, uint32_t *ra) {
+    for (uint32_t w = blockIdx.x; w < nt; w += gridDim.x) {
+        const TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
+        uint32_t cur_i[kTileItems], cur_a[kTileItems];
+        unsigned long long cur_k[kTileItems];
+        if (kSrc == kSrcEmit) {
+            emit_tile<kTileItems>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, cur_i, cur_k);
+        } else {
 #pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            const uint32_t p = tid + q * kBlock;
-            const bool in = p < sp.cnt;
-            if (kSrc == kSrcHash) rk[q] = in ? src_key[sp.begin + p] : kEmptyKey;
-            if (src_reads_idx<kSrc>()) ri[q] = in ? src_idx[sp.begin + p] : 0u;
-            if (src_reads_aux<kSrc>()) ra[q] = in ? ba.aux_in[sp.begin + p] : 0u;
-        }
-    };
-    load(ts, cur_i, cur_k, cur_a);
-    for (;;) {
-        const uint32_t wn = w + gridDim.x;
-        TileSpan tn = ts;
-        uint32_t nxt_i[kTileItems], nxt_a[kTileItems];
-        unsigned long long nxt_k[kTileItems];
-        if (wn < nt) {
-            tn = tile_span<kTile>(seg_off, tile_first, nseg, wn);
-            load(tn, nxt_i, nxt_k, nxt_a);
+            for (int q = 0; q < kTileItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                const bool in = p < ts.cnt;
+                cur_i[q] = 0u;
+                cur_a[q] = 0u;
+                cur_k[q] = kEmptyKey;
+                if (kSrc == kSrcHash && in) cur_k[q] = src_key[ts.begin + p];
+                if (src_reads_idx<kSrc>() && in) cur_i[q] = src_idx[ts.begin + p];
+                if (src_reads_aux<kSrc>() && in) cur_a[q] = ba.aux_in[ts.begin + p];
+            }
         }
         for (uint32_t d = tid; d < nd; d += kBlock) hs[d] = 0;
         lds_barrier();
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
             const uint32_t p = tid + q * kBlock;
-            if (p >= ts.cnt) continue;
-            if (kSrc == kSrcHash && cur_k[q] == kEmptyKey) continue;
+            if (kSrc != kSrcEmit && p >= ts.cnt) continue;  // (emit tiles mark missing slots empty)
+            if (src_is_tuple<kSrc>() && cur_k[q] == kEmptyKey) continue;
             uint32_t bk = 0;
             const uint64_t word = radix_word<kSrc>(cur_i[q], cur_k[q], cur_a[q], t, k0, k1, ba, &bk);
             atomicAdd(&hs[(uint32_t)(word >> shift) & dmask], 1u);
@@ -235,15 +313,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         lds_barrier();
         for (uint32_t d = tid; d < nd; d += kBlock) counts[(size_t)w * nd + d] = hs[d];
         lds_barrier();
-        if (wn >= nt) break;
-        w = wn;
-        ts = tn;
-#pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            cur_i[q] = nxt_i[q];
-            cur_k[q] = nxt_k[q];
-            cur_a[q] = nxt_a[q];
-        }
     }
 }
 
@@ -356,13 +425,11 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
 
 // LDS-staged scatter of one tile of a segment by digit (word >> shift) & mask.
 // Records of one digit leave the workgroup as one contiguous run starting at
-// the run base offs[w][d].  With kSrcHash, tuple slots whose key is empty
+// the run base offs[w][d].  With a tuple source, slots whose key is empty
 // are dropped; with kSrcBatch the record's global bucket is written to
-// ba.aux_out beside it.  Persistent workgroups: the next tile's records and
-// run bases are loaded into registers while the current tile is staged in
-// LDS.  Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then the
-// staged records (scatter_lds_bytes on the host).
-constexpr int kScatterOffRegs = 4;  // run bases prefetched per thread (2^dbits <= 1024)
+// ba.aux_out beside it.  One workgroup per tile (grid-stride if the grid is
+// smaller).  Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then
+// the staged records (scatter_lds_bytes on the host).
 
 template <int kSrc, int kTile>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
@@ -373,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ tile_first,
                                                     const uint32_t *__restrict__ offs, uint32_t *__restrict__ err,
-                                                    BatchArgs ba) {
+                                                    SrcArgs ba) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_total;
     constexpr int kTileItems = kTile / kBlock;
@@ -390,41 +457,26 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
 
     const uint32_t nt = tile_first[nseg];
     const uint32_t tid = threadIdx.x;
-    uint32_t w = blockIdx.x;
-    if (w >= nt) return;
-
-    TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
-    uint32_t c_idx[kTileItems], c_aux[kTileItems], c_off[kScatterOffRegs];
-    unsigned long long c_key[kTileItems];
-    auto load = [&](const TileSpan &sp, uint32_t wt, uint32_t *ri, unsigned long long *rk, uint32_t *ra,
-                    uint32_t *ro) {
+    for (uint32_t w = blockIdx.x; w < nt; w += gridDim.x) {
+        const TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
+        uint32_t c_idx[kTileItems], c_aux[kTileItems];
+        unsigned long long c_key[kTileItems];
+        if (kSrc == kSrcEmit) {
+            emit_tile<kTileItems>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, c_idx, c_key);
+        } else {
 #pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            const uint32_t p = tid + q * kBlock;
-            const bool in = p < sp.cnt;
-            ri[q] = in ? src_idx[sp.begin + p] : 0u;
-            rk[q] = in ? src_key[sp.begin + p] : kEmptyKey;
-            if (src_reads_aux<kSrc>()) ra[q] = in ? ba.aux_in[sp.begin + p] : 0u;
+            for (int q = 0; q < kTileItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                const bool in = p < ts.cnt;
+                c_idx[q] = in ? src_idx[ts.begin + p] : 0u;
+                c_key[q] = in ? src_key[ts.begin + p] : kEmptyKey;
+                c_aux[q] = (src_reads_aux<kSrc>() && in) ? ba.aux_in[ts.begin + p] : 0u;
+            }
         }
-#pragma unroll
-        for (int j = 0; j < kScatterOffRegs; ++j) {
-            const uint32_t d = tid + j * kBlock;
-            ro[j] = d < nd ? offs[(size_t)wt * nd + d] : 0u;
+        for (uint32_t d = tid; d < nd; d += kBlock) {
+            cnt[d] = 0;
+            base[d] = offs[(size_t)w * nd + d];
         }
-    };
-    load(ts, w, c_idx, c_key, c_aux, c_off);
-
-    for (;;) {
-        const uint32_t wn = w + gridDim.x;
-        TileSpan tn = ts;
-        uint32_t n_idx[kTileItems], n_aux[kTileItems], n_off[kScatterOffRegs];
-        unsigned long long n_key[kTileItems];
-        if (wn < nt) {
-            tn = tile_span<kTile>(seg_off, tile_first, nseg, wn);
-            load(tn, wn, n_idx, n_key, n_aux, n_off);
-        }
-
-        for (uint32_t d = tid; d < nd; d += kBlock) cnt[d] = 0;
         if (tid == 0) s_total = 0;
         lds_barrier();
         uint32_t r_dig[kTileItems], r_rank[kTileItems], r_bkt[kTileItems];
@@ -433,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
             const uint32_t p = tid + q * kBlock;
             r_dig[q] = 0xFFFFFFFFu;
             r_bkt[q] = 0;
-            if (p < ts.cnt && (kSrc != kSrcHash || c_key[q] != kEmptyKey)) {
+            if ((kSrc == kSrcEmit || p < ts.cnt) && (!src_is_tuple<kSrc>() || c_key[q] != kEmptyKey)) {
                 const uint64_t word = radix_word<kSrc>(c_idx[q], c_key[q], c_aux[q], t, k0, k1, ba, &r_bkt[q]);
                 r_dig[q] = (uint32_t)(word >> shift) & dmask;
                 r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
@@ -443,12 +495,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         for (uint32_t d = tid; d < nd; d += kBlock) start[d] = cnt[d];
         lds_barrier();
         block_exclusive_scan(start, nd, tmp);
-#pragma unroll
-        for (int j = 0; j < kScatterOffRegs; ++j) {
-            const uint32_t d = tid + j * kBlock;
-            if (d < nd) base[d] = c_off[j];
-        }
-        for (uint32_t d = tid + kScatterOffRegs * kBlock; d < nd; d += kBlock) base[d] = offs[(size_t)w * nd + d];
         uint32_t mine = 0;
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
@@ -476,23 +522,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
             }
         }
         lds_barrier();
-        if (wn >= nt) break;
-        w = wn;
-        ts = tn;
-#pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            c_idx[q] = n_idx[q];
-            c_key[q] = n_key[q];
-            c_aux[q] = n_aux[q];
-        }
-#pragma unroll
-        for (int j = 0; j < kScatterOffRegs; ++j) c_off[j] = n_off[j];
     }
 }
 
 // Sorts each fine bucket by (K, i): LDS counting sort on the kCellBits
 // bits of K below the B bucket bits, then insertion sort inside each cell.
-// Persistent workgroups prefetch the next bucket into registers.  Buckets
+// One workgroup per bucket (grid-stride if the grid is smaller).  Buckets
 // larger than `cap` (not expected: the mean is cap / 2 and sizes are
 // binomial) take a slow exact path that ranks every record against the whole
 // bucket.  Dynamic LDS: 2^kCellBits cell counters + kBlock + 2 scan words
@@ -518,30 +553,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
     const int sub_shift = 64 - kCellBits;
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
 
-    uint32_t f = blockIdx.x;
-    if (f >= nb) return;
-    uint32_t begin = min(fine_off[f], m), end = min(fine_off[f + 1], m);
-    uint32_t c_idx[kSortMaxItems];
-    unsigned long long c_key[kSortMaxItems];
+    for (uint32_t f = blockIdx.x; f < nb; f += gridDim.x) {
+        const uint32_t begin = min(fine_off[f], m), end = min(fine_off[f + 1], m);
+        uint32_t c_idx[kSortMaxItems];
+        unsigned long long c_key[kSortMaxItems];
 #pragma unroll
-    for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = begin + tid + q * kBlock;
-        c_idx[q] = p < end ? src_idx[p] : 0u;
-        c_key[q] = p < end ? src_key[p] : 0ull;
-    }
-    for (;;) {
-        const uint32_t fn = f + gridDim.x;
-        uint32_t nbegin = 0, nend = 0, n_idx[kSortMaxItems];
-        unsigned long long n_key[kSortMaxItems];
-        if (fn < nb) {
-            nbegin = min(fine_off[fn], m);
-            nend = min(fine_off[fn + 1], m);
-#pragma unroll
-            for (int q = 0; q < kSortMaxItems; ++q) {
-                const uint32_t p = nbegin + tid + q * kBlock;
-                n_idx[q] = p < nend ? src_idx[p] : 0u;
-                n_key[q] = p < nend ? src_key[p] : 0ull;
-            }
+        for (int q = 0; q < kSortMaxItems; ++q) {
+            const uint32_t p = begin + tid + q * kBlock;
+            c_idx[q] = p < end ? src_idx[p] : 0u;
+            c_key[q] = p < end ? src_key[p] : 0ull;
         }
         const uint32_t c = end > begin ? end - begin : 0;
         // batch: the graph owning bucket f (largest g with bbase <= f); its
@@ -637,15 +657,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
                 dst_key[begin + p] = sE[p];
             }
             lds_barrier();
-        }
-        if (fn >= nb) break;
-        f = fn;
-        begin = nbegin;
-        end = nend;
-#pragma unroll
-        for (int q = 0; q < kSortMaxItems; ++q) {
-            c_idx[q] = n_idx[q];
-            c_key[q] = n_key[q];
         }
     }
 }

@@ -7,7 +7,8 @@
 // equal to one of its own sources, P_L) and the idle position of odd m emit
 // ERASE tuples marked STAYS (those edges survive the superstep).  Tuples are
 // partitioned by a hash of the key with the same LDS-staged radix scatter as
-// the permutation, so all tuples of one key meet in one workgroup, which
+// the permutation (its first pass computes them from the pair records, see
+// emit_switch), so all tuples of one key meet in one workgroup, which
 // sorts its partition in LDS and derives for every INSERT tuple (k, X):
 //   eraser(X)  : the switch whose source X is (or STAYS / none)   -- lookup
 //   pred(k, X) : the next smaller inserter of X                    -- the
@@ -30,80 +31,43 @@
 
 namespace gesmc {
 
-// tuple tags
-constexpr uint32_t kTagInsert = 0x80000000u;  // | (k << 1 | h)
-constexpr uint32_t kTagStays = 0x7FFFFFFEu;   // ERASE tuple of a surviving edge
 // per-target record: x = eraser (kNoEraser / kStays / switch), y = predecessor (k' << 1 | h') or kNoPred
 constexpr uint32_t kNoPred = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
-// Emit: one thread per switch (+ one for the idle record).  Tuple slots
-// 4k .. 4k+3 belong to switch k, slot 4*ell to the idle record; unused slots
-// get an empty key.  Also: records of locally rejected switches, the free
-// target records.
+// Emit: one thread per switch (+ one for the idle record of odd m).  The
+// local outcome of every switch (switch_local): a switch decided locally gets
+// its status, its records (unchanged) and its count; an undecided one gets
+// its two target records initialised to "free".  The switches' tuples are
+// not stored: the first partition pass computes them from the same pair
+// records (emit_switch).
 // ---------------------------------------------------------------------------
-template <bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
-                                                 const unsigned long long *__restrict__ s_key, uint32_t m, uint32_t t,
-                                                 uint32_t k0, uint32_t k1, uint32_t pl, uint32_t *__restrict__ tu_tag,
-                                                 unsigned long long *__restrict__ tu_key, uint2 *__restrict__ info,
+                                                 const unsigned long long *__restrict__ s_key, uint32_t t, uint32_t k0,
+                                                 uint32_t k1, SrcArgs sa, uint2 *__restrict__ info,
                                                  uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
-                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot,
-                                                 const BatchGraph *__restrict__ gr, const uint32_t *__restrict__ pg,
-                                                 uint32_t step) {
+                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot) {
     __shared__ BlockCounts bc;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
     __syncthreads();
-    const uint32_t ell = m >> 1;
+    const uint32_t m = sa.m, ell = m >> 1;
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t k = blockIdx.x * kBlock + tid; k <= ell; k += stride) {
-    if (k == ell && (m & 1u)) {
-        const unsigned long long e = s_key[m - 1];
-        tu_tag[4 * (size_t)ell] = kTagStays;
-        tu_key[4 * (size_t)ell] = e;
-        out_idx[m - 1] = s_idx[m - 1];
-        out_key[m - 1] = e;
-    } else if (k < ell) {
+        if (k == ell) {
+            if (m & 1u) {
+                out_idx[m - 1] = s_idx[m - 1];
+                out_key[m - 1] = s_key[m - 1];
+            }
+            continue;
+        }
         const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
         const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
-        const uint32_t i = ij.x, j = ij.y;
-        const unsigned long long e1 = ee.x, e2 = ee.y;
-        uint8_t status = ST_UNDECIDED;
         Targets T{0, 0, false};
-        bool skip = false;
-        if (kBatch) {
-            if (i == kPadIdx || j == kPadIdx) {
-                status = ST_IDLE;
-            } else if (pl != 0) {  // pl != 0: some graph of the batch has P_L > 0
-                const BatchGraph &g = gr[pg[2 * (size_t)k]];
-                skip = pl_skip(k - (g.poff >> 1), g.t0 + step, g.pl, g.k0, g.k1);
-            }
-        } else {
-            skip = pl_skip(k, t, pl, k0, k1);
-        }
-        if (status == ST_IDLE) {
-        } else if (skip) {
-            status = ST_PL;
-        } else {
-            T = switch_targets(e1, e2, i < j);
-            if (T.loop)
-                status = ST_LOOP;
-            else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
-                status = ST_EXISTS;
-        }
-        const uint32_t etag = status == ST_UNDECIDED ? k : kTagStays;
-        ulonglong2 *tk = reinterpret_cast<ulonglong2 *>(tu_key) + 2 * (size_t)k;
-        // a padding record carries no edge: its slot gets the empty key
-        tk[0] = make_ulonglong2(i == kPadIdx ? kEmptyKey : e1, j == kPadIdx ? kEmptyKey : e2);
+        const uint8_t status = switch_local(k, ij, ee, t, k0, k1, sa, &T);
         if (status == ST_UNDECIDED) {
-            reinterpret_cast<uint4 *>(tu_tag)[k] =
-                make_uint4(etag, etag, kTagInsert | (k << 1), kTagInsert | (k << 1) | 1u);
-            tk[1] = make_ulonglong2(T.A, T.B);
             reinterpret_cast<uint4 *>(info)[k] = make_uint4(kNoEraser, kNoPred, kNoEraser, kNoPred);
         } else {
-            reinterpret_cast<uint4 *>(tu_tag)[k] = make_uint4(etag, etag, 0u, 0u);
-            tk[1] = make_ulonglong2(kEmptyKey, kEmptyKey);
             st[k] = status;
             reinterpret_cast<uint2 *>(out_idx)[k] = ij;
             reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
@@ -112,8 +76,25 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
             if (status == ST_EXISTS) atomicAdd(&bc.exists, 1u);
         }
     }
-    }
     store_counts(&bc, bslot + blockIdx.x);
+}
+
+// The tuples of every slot written out flat (tuple buffer 0), for the
+// unfused schedule (GESMC_OPT_FUSE_EMIT 0): one thread per switch.
+__global__ __launch_bounds__(kBlock) void k_emit_tuples(const uint32_t *__restrict__ s_idx,
+                                                        const unsigned long long *__restrict__ s_key, uint32_t t,
+                                                        uint32_t k0, uint32_t k1, SrcArgs sa, uint32_t nslots,
+                                                        uint32_t *__restrict__ tu_tag,
+                                                        unsigned long long *__restrict__ tu_key) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; 4 * (uint64_t)k < nslots; k += stride) {
+        Tuple tp[4];
+        emit_switch(k, s_idx, s_key, t, k0, k1, sa, tp);
+        for (uint32_t h = 0; h < 4 && 4 * k + h < nslots; ++h) {
+            tu_tag[4 * k + h] = tp[h].tag;
+            tu_key[4 * k + h] = tp[h].key;
+        }
+    }
 }
 
 // Validation only (no superstep): one STAYS tuple per input edge, so that a
@@ -169,8 +150,8 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
     if (eraser != kNoEraser || pred != kNoPred) info[tag & ~kTagInsert] = make_uint2(eraser, pred);
 }
 
-// Persistent workgroups over the fine partitions; the next partition's
-// tuples are prefetched into registers.  LDS path: counting sort on
+// One workgroup per fine partition (grid-stride if the grid is smaller).
+// LDS path: counting sort on
 // kCellBits hash bits below the partition bits, then each thread sorts the
 // cells it owns by (key, tag) and walks them.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
@@ -191,30 +172,15 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
     const int sub_shift = 64 - kCellBits;
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
 
-    uint32_t f = blockIdx.x;
-    if (f >= np) return;
-    uint32_t begin = part_off[f], end = part_off[f + 1];
-    uint32_t c_tag[kSortMaxItems];
-    unsigned long long c_key[kSortMaxItems];
+    for (uint32_t f = blockIdx.x; f < np; f += gridDim.x) {
+        const uint32_t begin = part_off[f], end = part_off[f + 1];
+        uint32_t c_tag[kSortMaxItems];
+        unsigned long long c_key[kSortMaxItems];
 #pragma unroll
-    for (int q = 0; q < kSortMaxItems; ++q) {
-        const uint32_t p = begin + tid + q * kBlock;
-        c_tag[q] = p < end ? tu_tag[p] : 0u;
-        c_key[q] = p < end ? tu_key[p] : 0ull;
-    }
-    for (;;) {
-        const uint32_t fn = f + gridDim.x;
-        uint32_t nbegin = 0, nend = 0, n_tag[kSortMaxItems];
-        unsigned long long n_key[kSortMaxItems];
-        if (fn < np) {
-            nbegin = part_off[fn];
-            nend = part_off[fn + 1];
-#pragma unroll
-            for (int q = 0; q < kSortMaxItems; ++q) {
-                const uint32_t p = nbegin + tid + q * kBlock;
-                n_tag[q] = p < nend ? tu_tag[p] : 0u;
-                n_key[q] = p < nend ? tu_key[p] : 0ull;
-            }
+        for (int q = 0; q < kSortMaxItems; ++q) {
+            const uint32_t p = begin + tid + q * kBlock;
+            c_tag[q] = p < end ? tu_tag[p] : 0u;
+            c_key[q] = p < end ? tu_key[p] : 0ull;
         }
         const uint32_t c = end > begin ? end - begin : 0;
         if (c > lds_cap) {
@@ -328,15 +294,6 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 }
             }
             lds_barrier();
-        }
-        if (fn >= np) break;
-        f = fn;
-        begin = nbegin;
-        end = nend;
-#pragma unroll
-        for (int q = 0; q < kSortMaxItems; ++q) {
-            c_tag[q] = n_tag[q];
-            c_key[q] = n_key[q];
         }
     }
 }

@@ -57,24 +57,6 @@ __global__ __launch_bounds__(kBlock) void k_validate(const unsigned long long *_
     }
 }
 
-// Switch k's targets from its sources (tau of Def. 2.1 on canonical edges).
-struct Targets {
-    uint64_t A, B;
-    bool loop;
-};
-
-__device__ __forceinline__ Targets switch_targets(uint64_t e1, uint64_t e2, bool g) {
-    const uint32_t u = ekey_lo_vertex(e1), v = ekey_hi_vertex(e1);
-    const uint32_t x = ekey_lo_vertex(e2), y = ekey_hi_vertex(e2);
-    // g = 0: (u,x),(v,y)     g = 1: (u,y),(v,x)
-    const uint32_t a1 = g ? y : x, b1 = g ? x : y;
-    Targets T;
-    T.loop = (u == a1) || (v == b1);
-    T.A = ekey(u, a1);
-    T.B = ekey(v, b1);
-    return T;
-}
-
 // Per-workgroup counter accumulation into the superstep's counters.
 struct BlockCounts {
     uint32_t legal, loop, exists, pl;

@@ -195,11 +195,13 @@ def test_schedule_independence(ctx):
     E = graphgen.powerlaw_graph(40000, 2.05, 1, 400, 21)
     n = 40000
     ref = None
-    for avg, cap, fr, strat in [(512, 1024, 4, 0), (64, 1024, 0, 0), (256, 64, 1, 0), (700, 512, 8, 0),
-                                (768, 1024, 0, 1), (64, 64, 3, 1), (128, 96, 2, 0)]:
+    for avg, cap, fr, strat, fuse in [(512, 1024, 4, 0, 1), (64, 1024, 0, 0, 1), (256, 64, 1, 0, 0),
+                                      (700, 512, 8, 0, 0), (768, 1024, 0, 1, 1), (64, 64, 3, 1, 1),
+                                      (128, 96, 2, 0, 1), (768, 1024, 2, 0, 0)]:
         c = gesmc.Context(0)
         try:
             c.set_option(gesmc.OPT_STRATEGY, strat)
+            c.set_option(gesmc.OPT_FUSE_EMIT, fuse)
             c.set_option(gesmc.OPT_BUCKET_AVG, avg)
             c.set_option(gesmc.OPT_SORT_CAP, cap)
             c.set_option(gesmc.OPT_FAST_ROUNDS, fr)
@@ -209,7 +211,7 @@ def test_schedule_independence(ctx):
                 ref = got
                 rc, exp, _, _ = oracle_run(E, n, 77, 2, 5)
                 assert np.array_equal(got, exp)
-            assert np.array_equal(got, ref), (avg, cap, fr, strat)
+            assert np.array_equal(got, ref), (avg, cap, fr, strat, fuse)
         finally:
             c.close()
 
