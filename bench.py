@@ -121,7 +121,9 @@ def bench_batched(gesmc, torch, args, plain_value):
     ctx = gesmc.Context(0)
     d_in = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
     d_out = torch.empty_like(d_in)
-    ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)  # warm-up (allocation)
+    tuning = ctx.autotune_batch(d_in, offs, ns, seeds, supersteps=2)  # options only; results never change
+    print("batched: autotuner chose %s" % tuning, file=sys.stderr)
+    ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)  # warm-up
     torch.cuda.synchronize()
     times = []
     for _ in range(args.batch_steps):
@@ -156,6 +158,7 @@ def bench_batched(gesmc, torch, args, plain_value):
                                   "sample": "gesmc_run per graph on every %dth graph (%d graphs)" % (
                                       args.plain_sample_stride, len(sample))},
             "vs_plain_same_graphs": round(value / plain_same, 2),
+            "autotuner": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in tuning.items()},
             "vs_plain_headline": round(value / plain_value, 3) if plain_value else None}
 
 
@@ -203,7 +206,9 @@ def bench_served(gesmc, torch, args):
         span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
         rec = {"rate_req_per_s": rate, "requests": nreq, "hbm_budget_bytes": budget, "failed": bad,
                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-               "attempts_per_s": round(att / span, 1), "iterations": info["iterations"],
+               "attempts_per_s": round(att / span, 1),
+               "attempts_per_busy_s": round(info["attempts"] / max(info["busy_s"], 1e-9), 1),
+               "iterations": info["iterations"],
                "busy_fraction": round(info["busy_s"] / max(info["now_s"], 1e-9), 3)}
         print("served: %s" % rec, file=sys.stderr)
         out.append(rec)

@@ -200,9 +200,38 @@ gesmc_status gesmc_cancel(gesmc_server *srv, uint64_t ticket);
 void gesmc_result_free(gesmc_result *res);
 gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
 
+/* Result of an autotuning run: the options chosen and the measured times. */
+typedef struct gesmc_tuning {
+    uint32_t bucket_avg;  /* GESMC_OPT_BUCKET_AVG chosen          */
+    uint32_t level1_bits; /* GESMC_OPT_LEVEL1_BITS chosen         */
+    uint32_t fuse_emit;   /* GESMC_OPT_FUSE_EMIT chosen           */
+    uint32_t candidates;  /* settings timed                       */
+    double best_ms;       /* device time of the chosen setting    */
+    double default_ms;    /* device time of the default setting   */
+} gesmc_tuning;
+
+/*
+ * Autotuner: times `supersteps` global switches (from superstep 0 with the
+ * given seed, results discarded) of the plain form on d_in (device, m keys,
+ * ids < n) under each candidate setting of the options above, and leaves the
+ * fastest set on the context.  Results never depend on the options, so a
+ * tuned context computes exactly what an untuned one does.  out (host,
+ * nullable) receives the choice.  Needs GESMC_OPT_STRATEGY 0.  Allocates a
+ * scratch output of m words for the duration of the call.
+ */
+gesmc_status gesmc_autotune(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t m, uint32_t n,
+                            uint64_t seed, uint32_t supersteps, gesmc_tuning *out);
+
+/* The same for batches: candidates are timed on gesmc_run_batch over the
+ * given graphs (arguments as for gesmc_run_batch; every graph runs
+ * `supersteps` switches from t0 = 0). */
+gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uint64_t *d_in,
+                                  const uint64_t *offsets, const uint32_t *n, const uint64_t *seed,
+                                  uint32_t supersteps, gesmc_tuning *out);
+
 /* Tuning knobs (values are validated; results never depend on them). */
-#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 768, default 768)    */
-#define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1024, default 1024)     */
+#define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 1152, default 1152)  */
+#define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1536, default 1536)     */
 #define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64) */
 #define GESMC_OPT_PROFILE 4     /* 1: time every kernel launch with HIP events                      */
 #define GESMC_OPT_STRATEGY 5    /* dependency resolution: 0 = tuples sorted by edge key per hash

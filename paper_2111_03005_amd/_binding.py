@@ -48,6 +48,14 @@ class StepStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("bucket_avg", ctypes.c_uint32), ("level1_bits", ctypes.c_uint32), ("fuse_emit", ctypes.c_uint32),
+                ("candidates", ctypes.c_uint32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_graphs", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32)]
@@ -78,7 +86,7 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
-           "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get"]
+           "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch"]
 
 _lib = None
 _lock = threading.Lock()
@@ -141,6 +149,11 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_result_free.restype = None
         lib.gesmc_server_info_get.argtypes = [vp, ctypes.POINTER(ServerInfo)]
         lib.gesmc_server_info_get.restype = i32
+        lib.gesmc_autotune.argtypes = [vp, vp, vp, u64, u32, u64, u32, ctypes.POINTER(Tuning)]
+        lib.gesmc_autotune.restype = i32
+        lib.gesmc_autotune_batch.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                             ctypes.POINTER(u64), u32, ctypes.POINTER(Tuning)]
+        lib.gesmc_autotune_batch.restype = i32
         _lib = lib
         return lib
 
@@ -228,6 +241,25 @@ class Context:
                                     _dev_ptr(out, 8, total_m, "out"), h_off, h_n, h_seed, h_t0, h_r, pl, 0,
                                     st, ctypes.byref(tot)))
         return out, ([st[g].as_dict() for g in range(G)] if stats else None), tot.as_dict()
+
+    def autotune(self, edges: torch.Tensor, n: int, seed: int = 1, supersteps: int = 2, stream=None):
+        """Times candidate option settings on these edges and keeps the fastest."""
+        tu = Tuning()
+        _check(_lib.gesmc_autotune(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, edges.numel(), "edges"),
+                                   edges.numel(), n, seed & (2**64 - 1), supersteps, ctypes.byref(tu)))
+        return tu.as_dict()
+
+    def autotune_batch(self, edges: torch.Tensor, offsets, n, seed, supersteps: int = 2, stream=None):
+        """The autotuner over a batch (arguments as run_batch)."""
+        G = len(offsets) - 1
+        h_off = (ctypes.c_uint64 * (G + 1))(*[int(x) for x in offsets])
+        h_n = (ctypes.c_uint32 * G)(*[int(x) for x in n])
+        h_seed = (ctypes.c_uint64 * G)(*[int(x) & (2**64 - 1) for x in seed])
+        tu = Tuning()
+        _check(_lib.gesmc_autotune_batch(self._h, _stream_ptr(stream), G,
+                                         _dev_ptr(edges, 8, int(offsets[-1]), "edges"), h_off, h_n, h_seed,
+                                         supersteps, ctypes.byref(tu)))
+        return tu.as_dict()
 
     def superstep_outcomes(self, edges: torch.Tensor, n: int, seed: int, t: int, pl: int = 0, stream=None):
         """One superstep; returns (edges after, outcome code per switch (uint8), step stats)."""

@@ -1183,6 +1183,118 @@ gesmc_status gesmc_run_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uin
     return run_batch_impl(ctx, stream, G, d_in, d_out, offsets, n, seed, t0, r, pl, stats, total);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Times every candidate setting with `trial` (device ms of one call; the
+// first call of a setting warms it up, the second is timed) and leaves the
+// fastest set.  Candidates: bucket mean 1/2 or 3/4 of the LDS capacity, an
+// even level split or an 8-bit first level, fused or unfused tuple pass.
+template <typename Trial>
+gesmc_status autotune_impl(gesmc_ctx *c, Trial trial, gesmc_tuning *out) {
+    if (c->strategy != 0) {
+        set_error("the autotuner needs the sorted-tuples strategy (GESMC_OPT_STRATEGY 0)");
+        return GESMC_E_INVAL;
+    }
+    const uint32_t avgs[2] = {3 * kLdsCap / 4, kLdsCap / 2};
+    const uint32_t l1s[2] = {0, 8};
+    const bool fuses[2] = {true, false};
+    const uint32_t save_avg = c->bucket_avg, save_l1 = c->level1_cap;
+    const bool save_fuse = c->fuse_emit, save_prof = c->profile;
+    c->profile = false;
+    double best = 1e300, dflt = 0;
+    uint32_t best_avg = save_avg, best_l1 = save_l1, ncand = 0;
+    bool best_fuse = save_fuse;
+    gesmc_status st = GESMC_OK;
+    for (uint32_t a : avgs)
+        for (uint32_t l : l1s)
+            for (bool f : fuses) {
+                c->bucket_avg = a;
+                c->level1_cap = l;
+                c->fuse_emit = f;
+                double ms = 0;
+                st = trial(&ms);  // warm-up
+                if (st == GESMC_OK) st = trial(&ms);
+                if (st != GESMC_OK) break;
+                ++ncand;
+                if (a == avgs[0] && l == 0 && f) dflt = ms;
+                if (ms < best) {
+                    best = ms;
+                    best_avg = a;
+                    best_l1 = l;
+                    best_fuse = f;
+                }
+            }
+    c->profile = save_prof;
+    if (st != GESMC_OK) {
+        c->bucket_avg = save_avg;
+        c->level1_cap = save_l1;
+        c->fuse_emit = save_fuse;
+        return st;
+    }
+    c->bucket_avg = best_avg;
+    c->level1_cap = best_l1;
+    c->fuse_emit = best_fuse;
+    if (out) *out = gesmc_tuning{best_avg, best_l1, best_fuse ? 1u : 0u, ncand, best, dflt};
+    return GESMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gesmc_status gesmc_autotune(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t m, uint32_t n, uint64_t seed,
+                            uint32_t supersteps, gesmc_tuning *out) {
+    if (!c || (m > 0 && !d_in)) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    uint64_t *tmp = nullptr;
+    GESMC_TRY(dev_alloc((void **)&tmp, std::max<uint64_t>(m, 1) * 8));
+    const gesmc_status st = autotune_impl(
+        c,
+        [&](double *ms) {
+            gesmc_stats stt{};
+            const gesmc_status s = run_impl(c, stream, d_in, tmp, m, n, seed, 0, std::max(supersteps, 1u), 0, &stt,
+                                            nullptr, nullptr);
+            *ms = stt.ms_device;
+            return s;
+        },
+        out);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(tmp);
+    return st;
+}
+
+gesmc_status gesmc_autotune_batch(gesmc_ctx *c, void *stream, uint32_t G, const uint64_t *d_in,
+                                  const uint64_t *offsets, const uint32_t *n, const uint64_t *seed,
+                                  uint32_t supersteps, gesmc_tuning *out) {
+    if (!c || !offsets || G == 0) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    const uint64_t total = offsets[G];
+    uint64_t *tmp = nullptr;
+    GESMC_TRY(dev_alloc((void **)&tmp, std::max<uint64_t>(total, 1) * 8));
+    std::vector<uint32_t> rs(G, std::max(supersteps, 1u));
+    const gesmc_status st = autotune_impl(
+        c,
+        [&](double *ms) {
+            gesmc_stats tot{};
+            const gesmc_status s = run_batch_impl(c, stream, G, d_in, tmp, offsets, n, seed, nullptr, rs.data(), 0,
+                                                  nullptr, &tot);
+            *ms = tot.ms_device;
+            return s;
+        },
+        out);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(tmp);
+    return st;
+}
+
 gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,
                        uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats,
                        gesmc_step_stats *steps) {

@@ -28,7 +28,10 @@ constexpr uint32_t kMaxCoarseBits = 10;  // digit bits of the first radix level
 #define GESMC_CELL_BITS 8
 #endif
 constexpr int kCellBits = GESMC_CELL_BITS;   // LDS counting-sort cells per bucket / partition = 2^bits
-constexpr int kSortMaxItems = 4;             // records per thread held in LDS
+#ifndef GESMC_LDS_ITEMS
+#define GESMC_LDS_ITEMS 6
+#endif
+constexpr int kSortMaxItems = GESMC_LDS_ITEMS;  // records per thread held in LDS
 constexpr uint32_t kLdsCap = kSortMaxItems * kBlock;  // records of one bucket sorted in LDS
 static_assert((1 << kCellBits) >= kBlock, "every thread owns at least one cell");
 

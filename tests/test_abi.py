@@ -77,6 +77,8 @@ int main(void) {
     F(gesmc_result, t_done)
     S(gesmc_server_info) F(gesmc_server_info, resident_edges) F(gesmc_server_info, queued)
     F(gesmc_server_info, resident) F(gesmc_server_info, busy_s) F(gesmc_server_info, now_s)
+    S(gesmc_tuning) F(gesmc_tuning, fuse_emit) F(gesmc_tuning, candidates) F(gesmc_tuning, best_ms)
+    F(gesmc_tuning, default_ms)
     return 0;
 }
 """
@@ -92,7 +94,8 @@ def test_ctypes_layouts_match_c_compiler(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     mirror = {"gesmc_stats": b.Stats, "gesmc_step_stats": b.StepStats, "gesmc_server_cfg": b.ServerCfg,
-              "gesmc_request": b.Request, "gesmc_result": b.Result, "gesmc_server_info": b.ServerInfo}
+              "gesmc_request": b.Request, "gesmc_result": b.Result, "gesmc_server_info": b.ServerInfo,
+              "gesmc_tuning": b.Tuning}
     checked = 0
     for line in filter(None, out):
         parts = line.split()
@@ -137,3 +140,5 @@ def test_null_context_rejected_without_gpu(lib):
     assert lib.gesmc_cancel(None, 1) == gesmc.E_INVAL
     lib.gesmc_server_destroy(None)
     lib.gesmc_result_free(None)
+    assert lib.gesmc_autotune(None, None, None, 0, 0, 0, 1, None) == gesmc.E_INVAL
+    assert lib.gesmc_autotune_batch(None, None, 0, None, None, None, None, 1, None) == gesmc.E_INVAL

@@ -210,3 +210,20 @@ def test_full_batch_4096_sampled_exact(ctx):
         assert s["attempts"] == 20 * (len(E) // 2)
         assert s["legal"] + s["rej_loop"] + s["rej_exists"] + s["rej_pl"] == s["attempts"], g
     assert tot["attempts"] == sum(20 * (s // 2) for s in sizes)
+
+
+def test_autotuned_batch_computes_the_same():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_03005_amd as gesmc
+    graphs, seeds, rs, t0s = mixed_batch(seed=23, G=20)
+    E, offs, ns = graphgen.concat(graphs)
+    c = gesmc.Context(0)
+    try:
+        tu = c.autotune_batch(to_dev(E), offs, ns, seeds, supersteps=2)
+        print("tuning:", tu, flush=True)
+        assert tu["candidates"] == 8
+        got, offs, stats, _ = run_batch(c, graphs, seeds, rs, t0s)
+        check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, 0, range(len(graphs)))
+    finally:
+        c.close()

@@ -261,3 +261,20 @@ def test_full_gnp_n2p22_ten_supersteps_properties(ctx):
     for s in steps:
         assert s["legal"] + s["rej_loop"] + s["rej_exists"] + s["rej_pl"] == s["attempts"] == len(E) // 2
         assert s["legal"] > 0.99 * s["attempts"]
+
+
+def test_autotuned_context_computes_the_same():
+    """The autotuner changes options only: the tuned context reproduces the oracle."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    E = graphgen.powerlaw_graph(60000, 2.3, 2, 244, 31)
+    n = 60000
+    c = gesmc.Context(0)
+    try:
+        tu = c.autotune(to_dev(E), n, seed=5, supersteps=2)
+        print("tuning:", tu, flush=True)
+        assert tu["candidates"] == 8 and tu["best_ms"] <= tu["default_ms"] + 1e-9
+        assert tu["fuse_emit"] in (0, 1) and tu["level1_bits"] in (0, 8)
+        check_run(c, E, n, 77, 1, 4, label="autotuned")
+    finally:
+        c.close()
