@@ -70,31 +70,52 @@ __global__ __launch_bounds__(kBlock) void k_fill_pg(const BatchGraph *__restrict
         pg[p] = upper_index(ngraphs, p, [&](uint32_t x) { return (uint64_t)gr[x].poff; });
 }
 
-// Outcomes of one superstep per graph: workgroup q counts graph q's switch
-// states into acc[4q .. 4q+3] = legal, loop, exists, P_L (one workgroup per
-// graph, so plain read-modify-writes).
+// Outcomes of one superstep per graph: acc[4q .. 4q+3] += legal, loop,
+// exists, P_L counts of graph q's switches.  Each workgroup takes a chunk of
+// kStatsChunk consecutive switches (graphs own contiguous switch ranges), so
+// a chunk spans a short run of graphs: counts go to LDS bins per graph of
+// the chunk and leave with one device atomic per (graph, outcome) and chunk;
+// graphs beyond the bins (many tiny graphs in one chunk) count directly.
+constexpr uint32_t kStatsPerThread = 16;
+constexpr uint32_t kStatsChunk = kStatsPerThread * kBlock;
+constexpr uint32_t kStatsBins = 64;
+
 __global__ __launch_bounds__(kBlock) void k_graph_stats(const uint8_t *__restrict__ st,
-                                                        const BatchGraph *__restrict__ gr,
-                                                        unsigned long long *__restrict__ acc) {
-    __shared__ uint32_t cnt[4];
-    const uint32_t q = blockIdx.x, tid = threadIdx.x;
-    if (tid < 4) cnt[tid] = 0;
+                                                        const BatchGraph *__restrict__ gr, uint32_t ngraphs,
+                                                        uint32_t ell, unsigned long long *__restrict__ acc) {
+    __shared__ uint32_t bins[kStatsBins * 4];
+    __shared__ uint32_t s_q0;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t kb = blockIdx.x * kStatsChunk;
+    auto first_switch = [&](uint32_t q) { return (uint64_t)(gr[q].poff >> 1); };
+    for (uint32_t j = tid; j < kStatsBins * 4; j += kBlock) bins[j] = 0;
+    if (tid == 0) s_q0 = upper_index(ngraphs, kb, first_switch);
     __syncthreads();
-    const BatchGraph b = gr[q];
-    const uint32_t k0 = b.poff >> 1, k1 = (b.poff + b.mpad) >> 1;
-    uint32_t c[4] = {0, 0, 0, 0};
-    for (uint32_t k = k0 + tid; k < k1; k += kBlock) {
-        const uint8_t s = st[k];
-        c[0] += s == ST_LEGAL;
-        c[1] += s == ST_LOOP;
-        c[2] += s == ST_EXISTS;
-        c[3] += s == ST_PL;
+    const uint32_t q0 = s_q0;
+    const uint32_t k0 = kb + tid * kStatsPerThread;
+    const uint32_t k1 = min(k0 + kStatsPerThread, ell);
+    if (k0 < k1) {
+        uint32_t q = upper_index(ngraphs, k0, first_switch);
+        uint32_t qend = (gr[q].poff + gr[q].mpad) >> 1;
+        for (uint32_t k = k0; k < k1; ++k) {
+            while (k >= qend && q + 1 < ngraphs) {
+                ++q;
+                qend = (gr[q].poff + gr[q].mpad) >> 1;
+            }
+            const uint8_t sv = st[k];
+            if (sv < ST_LEGAL || sv > ST_PL) continue;
+            const uint32_t j = sv - ST_LEGAL;  // legal, loop, exists, P_L
+            if (q - q0 < kStatsBins)
+                atomicAdd(&bins[(q - q0) * 4 + j], 1u);
+            else
+                atomicAdd(&acc[4 * (size_t)q + j], 1ull);
+        }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (c[j]) atomicAdd(&cnt[j], c[j]);
     __syncthreads();
-    if (tid < 4) acc[4 * (size_t)q + tid] += cnt[tid];
+    for (uint32_t j = tid; j < kStatsBins * 4; j += kBlock) {
+        const uint32_t q = q0 + j / 4;
+        if (bins[j] && q < ngraphs) atomicAdd(&acc[4 * (size_t)q + (j & 3)], (unsigned long long)bins[j]);
+    }
 }
 
 // Record at position p -> out[input position] = key with the graph's vertex

@@ -625,8 +625,8 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
                      c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
                      c->ctr_step, c->err));
     if (bs && bs->acc)
-        GESMC_TRY(launch(c, s, KID_MISC, 0, k_graph_stats, dim3(bs->ngraphs), dim3(kBlock), 0, (const uint8_t *)c->st,
-                         bs->gr, bs->acc));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_graph_stats, dim3(ceil_div(p.ell, kStatsChunk)), dim3(kBlock), 0,
+                         (const uint8_t *)c->st, bs->gr, bs->ngraphs, p.ell, bs->acc));
     return GESMC_OK;
 }
 

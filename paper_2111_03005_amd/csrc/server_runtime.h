@@ -65,6 +65,8 @@ struct gesmc_server {
     std::vector<uint64_t> h_stage_off;
     std::vector<uint32_t> h_stage_rank;
     std::vector<unsigned long long> h_rb;
+    uint64_t *h_pin = nullptr;  // pinned staging: admitted edges up, finished results down
+    uint64_t pin_cap = 0;       // words
     uint2 *d_mv = nullptr;
     uint64_t *d_stage_off = nullptr;
     uint32_t *d_stage_rank = nullptr;
@@ -115,6 +117,23 @@ gesmc_status serve_map_gerr(uint32_t e) {
     return GESMC_E_INTERNAL;
 }
 
+// Grows the pinned staging buffer to at least `words` words.
+gesmc_status serve_pin(gesmc_server *S, uint64_t words) {
+    if (words <= S->pin_cap) return GESMC_OK;
+    if (S->h_pin) (void)hipHostFree(S->h_pin);
+    S->h_pin = nullptr;
+    S->pin_cap = 0;
+    const uint64_t cap = std::max<uint64_t>(words, 8ull << 20);
+    if (hipHostMalloc((void **)&S->h_pin, cap * 8, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        S->h_pin = nullptr;
+        set_error("hipHostMalloc of the serving staging buffer failed");
+        return GESMC_E_NOMEM;
+    }
+    S->pin_cap = cap;
+    return GESMC_OK;
+}
+
 // One iteration on the worker: new layout (survivors + admitted), one
 // superstep of every resident graph, results of the graphs that finish.
 gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, const std::vector<ServeReq *> &admit,
@@ -163,6 +182,20 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     }
     S->h_stage_off.push_back(stage);
     const uint32_t npos = (uint32_t)poff;
+    // graphs that finish in this iteration, and their result offsets
+    finishing.clear();
+    S->h_rb.assign(G, ~0ull);
+    uint64_t rpos = 0;
+    for (uint32_t q = 0; q < G; ++q) {
+        if (ranks[q]->done + 1 == ranks[q]->r) {
+            S->h_rb[q] = rpos;
+            rpos += ranks[q]->m;
+            finishing.push_back(ranks[q]);
+        }
+    }
+    // the pinned staging holds this iteration's upload, then its results (same stream, in order);
+    // it is sized before any copy is queued
+    GESMC_TRY(serve_pin(S, std::max(stage, rpos)));
     if (bbase > (1ull << kMaxFineBits) || npos > c->cap_pos) {
         set_error("serving layout exceeds the context's capacity");
         return GESMC_E_INTERNAL;
@@ -187,13 +220,14 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
                              c->key[1]));
         }
         if (!admit.empty()) {
-            // raw edges of the admitted requests -> staging (tuple key buffer 1), then load
+            // raw edges of the admitted requests -> pinned staging -> one copy to the
+            // device staging area (tuple key buffer 1), then load
             unsigned long long *stg = c->tu_key[1];
             for (size_t j = 0; j < admit.size(); ++j)
-                if (admit[j]->m)
-                    GESMC_TRY(check_hip(hipMemcpyAsync(stg + S->h_stage_off[j], admit[j]->edges.data(),
-                                                       admit[j]->m * 8, hipMemcpyHostToDevice, s),
-                                        "hipMemcpyAsync"));
+                if (admit[j]->m) memcpy(S->h_pin + S->h_stage_off[j], admit[j]->edges.data(), admit[j]->m * 8);
+            if (stage)
+                GESMC_TRY(check_hip(hipMemcpyAsync(stg, S->h_pin, stage * 8, hipMemcpyHostToDevice, s),
+                                    "hipMemcpyAsync"));
             const uint32_t nadm = (uint32_t)admit.size();
             GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage_off, S->h_stage_off.data(), (nadm + 1) * 8ull,
                                                hipMemcpyHostToDevice, s),
@@ -216,16 +250,6 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     c->ctr_step = c->ctr;
     GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
     // results of the graphs finishing now (discarded after the sync if flagged)
-    finishing.clear();
-    S->h_rb.assign(G, ~0ull);
-    uint64_t rpos = 0;
-    for (uint32_t q = 0; q < G; ++q) {
-        if (ranks[q]->done + 1 == ranks[q]->r) {
-            S->h_rb[q] = rpos;
-            rpos += ranks[q]->m;
-            finishing.push_back(ranks[q]);
-        }
-    }
     unsigned long long *res = c->tu_key[2];
     if (!finishing.empty()) {
         GESMC_TRY(check_hip(hipMemcpyAsync(S->d_rb, S->h_rb.data(), G * 8ull, hipMemcpyHostToDevice, s),
@@ -233,15 +257,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_extract, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
                          (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], (const uint32_t *)c->pg,
                          (const BatchGraph *)c->gr, (const unsigned long long *)S->d_rb, npos, res));
-        for (ServeReq *R : finishing) {
-            R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
-            if (!R->result) return GESMC_E_NOMEM;
-        }
-        for (uint32_t q = 0; q < G; ++q)
-            if (S->h_rb[q] != ~0ull)
-                GESMC_TRY(check_hip(hipMemcpyAsync(ranks[q]->result, res + S->h_rb[q], ranks[q]->m * 8,
-                                                   hipMemcpyDeviceToHost, s),
-                                    "hipMemcpyAsync"));
+        GESMC_TRY(check_hip(hipMemcpyAsync(S->h_pin, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
@@ -249,6 +265,13 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, G * 32ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, G * 4ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    for (uint32_t q = 0; q < G; ++q) {
+        if (S->h_rb[q] == ~0ull) continue;
+        ServeReq *R = ranks[q];
+        R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
+        if (!R->result) return GESMC_E_NOMEM;
+        memcpy(R->result, S->h_pin + S->h_rb[q], R->m * 8);
+    }
     next = ranks;
     return GESMC_OK;
 }
@@ -451,6 +474,7 @@ void gesmc_server_destroy(gesmc_server *S) {
     }
     for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank, (void *)S->d_rb})
         if (p) (void)hipFree(p);
+    if (S->h_pin) (void)hipHostFree(S->h_pin);
     delete S;
 }
 
