@@ -149,6 +149,7 @@ def bench_batched(gesmc, torch, args, plain_value):
     ctx.close()
     print("batched: %.3e attempts/s (%.1f ms per batch); plain loop on every %dth graph: %.3e attempts/s" % (
         value, 1e3 * wall / len(times), args.plain_sample_stride, plain_same), file=sys.stderr)
+    small = bench_small_batches(gesmc, torch, args)
     return {"value": round(value, 1), "unit": "attempts/s", "steps": len(times),
             "ms_per_step": round(1e3 * wall / len(times), 3), "graphs": G, "edges": int(offs[-1]),
             "supersteps_per_graph": 20, "attempts_per_step": attempts,
@@ -159,7 +160,48 @@ def bench_batched(gesmc, torch, args, plain_value):
                                       args.plain_sample_stride, len(sample))},
             "vs_plain_same_graphs": round(value / plain_same, 2),
             "autotuner": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in tuning.items()},
-            "vs_plain_headline": round(value / plain_value, 3) if plain_value else None}
+            "vs_plain_headline": round(value / plain_value, 3) if plain_value else None,
+            "small_batches_hipgraph": small}
+
+
+def bench_small_batches(gesmc, torch, args):
+    """Launch-bound shapes, eager vs replayed from a hipGraph (GESMC_OPT_GRAPH):
+    64 small power-law graphs (n log-uniform [1e2, 1e3]) with 20 switches each,
+    and the G(1024, 10/1023) graph alone (a batch of one) with 10."""
+    import graphgen
+    out = {}
+    shapes = {"64 graphs n in [1e2,1e3], r=20": (graphgen.batch_graphs(64, 6, 1e2, 1e3), 20),
+              "gnp_n1024_d10 as a batch of one, r=10": ([graphgen.workload_gnp_small()], 10)}
+    stream = torch.cuda.Stream()
+    for name, (graphs, r) in shapes.items():
+        E, offs, ns = graphgen.concat(graphs)
+        G = len(graphs)
+        attempts = sum(r * (int(m) // 2) for m in np.diff(offs))
+        res = {}
+        for mode in (0, 1):
+            ctx = gesmc.Context(0)
+            ctx.set_option(gesmc.OPT_GRAPH, mode)
+            d_in = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
+            d_out = torch.empty_like(d_in)
+            with torch.cuda.stream(stream):
+                for w in range(3):  # eager, capture, first replay
+                    ctx.run_batch(d_in, offs, ns, [args.seed + g + w for g in range(G)], [r] * G, out=d_out,
+                                  stream=stream, stats=False)
+                stream.synchronize()
+                calls = 20
+                t = time.perf_counter()
+                for i in range(calls):
+                    ctx.run_batch(d_in, offs, ns, [args.seed + g + i for g in range(G)], [r] * G, out=d_out,
+                                  stream=stream, stats=False)
+                stream.synchronize()
+                dt = (time.perf_counter() - t) / calls
+            ctx.close()
+            res["graph" if mode else "eager"] = {"ms_per_call": round(1e3 * dt, 3),
+                                                "attempts_per_s": round(attempts / dt, 1)}
+        res["speedup"] = round(res["eager"]["ms_per_call"] / res["graph"]["ms_per_call"], 2)
+        print("small batch %s: %s" % (name, res), file=sys.stderr)
+        out[name] = res
+    return out
 
 
 def bench_served(gesmc, torch, args):

@@ -243,6 +243,10 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                     bucket bits, rounded up (default)                              */
 #define GESMC_OPT_FUSE_EMIT 9      /* 1: the first tuple partition pass computes the switches' tuples from
                                       their pair records (default); 0: they are written out first     */
+#define GESMC_OPT_GRAPH 10         /* 1: gesmc_run_batch captures its device work into a hipGraph on the
+                                      second call of the same shape (pointers, sizes, offsets, r, pl,
+                                      options) and replays it for later calls of that shape -- seeds,
+                                      t0 and n may change; needs a non-NULL stream (default 0)         */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

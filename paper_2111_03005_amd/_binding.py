@@ -21,6 +21,7 @@ OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PE
     1, 2, 3, 4, 5, 6, 7)
 OPT_LEVEL1_BITS = 8
 OPT_FUSE_EMIT = 9
+OPT_GRAPH = 10
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 

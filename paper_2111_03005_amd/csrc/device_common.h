@@ -174,6 +174,27 @@ __device__ __forceinline__ uint64_t slot_hash(uint64_t x) {
     return x;
 }
 
+// Tuples carry tuple_hash(key) instead of the key: slot_hash is a bijection
+// on 64-bit words (xor-shift by 32 is its own inverse, the multiplier is
+// odd), so equal hashes mean equal keys, and the partition passes and the
+// resolve read digits and cells straight from the word.  The constant makes
+// the empty key its own image, so no edge key hashes to it.
+constexpr unsigned long long kEmptyHashXor = 0x448E29CED4103459ull ^ ~0ull;  // slot_hash(~0) ^ ~0
+
+__device__ __forceinline__ uint64_t tuple_hash(uint64_t key) { return slot_hash(key) ^ kEmptyHashXor; }
+
+// The key of a tuple hash (error reporting only).
+__device__ __forceinline__ uint64_t tuple_key_of(uint64_t h) {
+    constexpr unsigned long long kInv = 0xCFEE444D8B59A89Bull;  // inverse of the multiplier mod 2^64
+    uint64_t x = h ^ kEmptyHashXor;
+    x ^= x >> 32;
+    x *= kInv;
+    x ^= x >> 32;
+    x *= kInv;
+    x ^= x >> 32;
+    return x;
+}
+
 // Finds or inserts `key`; returns its slot.  `nslots` need not be a power of
 // two: the home slot is the high word of hash * nslots (multiply-shift range
 // reduction).  The table is never more than half full, so the probe ends at

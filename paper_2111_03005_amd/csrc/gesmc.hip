@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -105,6 +106,10 @@ struct gesmc_ctx {
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     uint32_t level1_cap = 0;  // first-level digit bits (0: even split)
     bool fuse_emit = true;    // tuples computed in the first partition pass (else stored flat)
+    // hipGraph capture of batched calls (GESMC_OPT_GRAPH)
+    bool use_graph = false, capturing = false;
+    uint64_t graph_key = 0, graph_last_key = 0, graph_replays = 0;
+    hipGraphExec_t graph_exec = nullptr;
     int strategy = 0;  // 0: tuples partitioned by key and resolved in LDS; 1: HBM table
     bool profile = false;
     int profile_only = -1;  // kernel id timed while profiling (-1: every kernel)
@@ -203,7 +208,12 @@ void free_buffers(gesmc_ctx *c) {
     c->tab_slots = 0;
 }
 
+// Bumped by every device allocation: a captured graph holds buffer addresses,
+// so it is only replayed while no buffer has moved.
+std::atomic<uint64_t> g_alloc_epoch{0};
+
 gesmc_status dev_alloc(void **p, size_t bytes) {
+    ++g_alloc_epoch;
     if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
@@ -289,7 +299,7 @@ template <typename Kern, typename... Args>
 gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern kern, dim3 grid, dim3 block,
                     size_t lds, Args... args) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (c->profile && (c->profile_only < 0 || c->profile_only == kid)) {
+    if (c->profile && !c->capturing && (c->profile_only < 0 || c->profile_only == kid)) {
         a = take_event(c);
         b = take_event(c);
         if (a) (void)hipEventRecord(a, s);
@@ -566,12 +576,12 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
     if (emit)
-        GESMC_TRY((radix_distribute<kSrcEmit, kSrcHash>(c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag,
+        GESMC_TRY((radix_distribute<kSrcEmit, kSrcHashed>(c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag,
                                                         c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts, &poff, &np,
                                                         KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2,
                                                         emit->sa, SrcArgs{}, emit->si, emit->sk)));
     else
-        GESMC_TRY((radix_distribute<kSrcHash, kSrcHash>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
+        GESMC_TRY((radix_distribute<kSrcHash, kSrcHashed>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
                                                         p.b2 > 0 ? 2 : 1, &parts, &poff, &np, KID_TCOUNTS1,
                                                         KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, SrcArgs{},
                                                         SrcArgs{})));
@@ -961,46 +971,107 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                         "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->rank_of, c->h_rank_of.data(), G * 4ull, hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
+    // The device work of the call.  In graph mode (GESMC_OPT_GRAPH) it is captured
+    // into a hipGraph on the second call of a shape and replayed afterwards: the
+    // per-call data (seeds, t0, n) live in the per-graph records uploaded above,
+    // so a replay may use new seeds.  Uploads, events and result copies stay
+    // outside the graph; the first call of a shape runs eagerly, so every
+    // buffer is sized before a capture.
+    auto device_work = [&]() -> gesmc_status {
+        const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(rmax, 1) * (sizeof(StepCounters) / 4);
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr, zero_words - 64));
+        if (stats)
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
+                             (uint64_t)G * 8));
+        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
+        const GraphErr ge_all{c->gr, G, c->gerr};
+        uint32_t *bad_pos = c->err + 4;
+        if (total_m > 0) {
+            GESMC_TRY(launch(c, s, KID_LOAD, total_m, k_load_batch, dim3(grid_stride_blocks(c, total_m)), dim3(kBlock), 0,
+                             (const unsigned long long *)d_in, (uint32_t)total_m, (const uint64_t *)c->in_off, G,
+                             (const uint32_t *)c->rank_of, (const BatchGraph *)c->gr, c->idx[0], c->key[0], c->err,
+                             bad_pos, c->gerr));
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                             (const BatchGraph *)c->gr, G, npos, c->pg));
+        }
+        if (need_validation) {
+            c->ctr_step = c->ctr;
+            GESMC_TRY(launch(c, s, KID_EMIT, npos, k_emit_sources, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
+                             (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
+            GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP, ge_all));
+        }
+        // superstep s switches the ranks [0, active_s): those with r > s
+        uint32_t qa = nactive;
+        for (uint32_t st = 0; st < rmax; ++st) {
+            while (qa > 0 && r_eff(order[qa - 1]) <= st) --qa;
+            const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
+            const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
+            const Plan p = batch_plan(c, P, NB);
+            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all};
+            c->ctr_step = c->ctr + st;
+            GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
+        }
+        if (total_m > 0)
+            GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_unpermute_batch, dim3(grid_stride_blocks(c, npos)), dim3(kBlock),
+                             0, (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0],
+                             (const uint32_t *)c->pg, (const BatchGraph *)c->gr, npos, (unsigned long long *)d_out,
+                             (const uint32_t *)c->err));
+        return GESMC_OK;
+    };
     GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
-    const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(rmax, 1) * (sizeof(StepCounters) / 4);
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr, zero_words - 64));
-    if (stats)
-        GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
-                         (uint64_t)G * 8));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
-    const GraphErr ge_all{c->gr, G, c->gerr};
-    uint32_t *bad_pos = c->err + 4;
-    if (total_m > 0) {
-        GESMC_TRY(launch(c, s, KID_LOAD, total_m, k_load_batch, dim3(grid_stride_blocks(c, total_m)), dim3(kBlock), 0,
-                         (const unsigned long long *)d_in, (uint32_t)total_m, (const uint64_t *)c->in_off, G,
-                         (const uint32_t *)c->rank_of, (const BatchGraph *)c->gr, c->idx[0], c->key[0], c->err,
-                         bad_pos, c->gerr));
-        GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                         (const BatchGraph *)c->gr, G, npos, c->pg));
+    if (c->use_graph && s != nullptr) {
+        uint64_t key = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+        mix(G);
+        mix((uint64_t)(uintptr_t)d_in);
+        mix((uint64_t)(uintptr_t)d_out);
+        mix(stats != nullptr);
+        mix(pl);
+        for (uint32_t g = 0; g <= G; ++g) mix(offsets[g]);
+        for (uint32_t g = 0; g < G; ++g) mix(rv[g]);
+        mix(c->bucket_avg);
+        mix(c->sort_cap);
+        mix((uint64_t)c->fast_rounds);
+        mix(c->level1_cap);
+        mix(c->fuse_emit);
+        mix((uint64_t)c->persist_mult);
+        mix(g_alloc_epoch.load());
+        mix((uint64_t)(uintptr_t)s);
+        if (c->graph_exec && key == c->graph_key) {
+            GESMC_TRY(check_hip(hipGraphLaunch(c->graph_exec, s), "hipGraphLaunch"));
+            ++c->graph_replays;
+        } else if (key == c->graph_last_key) {
+            if (c->graph_exec) {
+                (void)hipGraphExecDestroy(c->graph_exec);
+                c->graph_exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            c->capturing = true;
+            gesmc_status st = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
+                                        "hipStreamBeginCapture");
+            if (st == GESMC_OK) {
+                st = device_work();
+                const hipError_t e = hipStreamEndCapture(s, &graph);
+                if (st == GESMC_OK) st = check_hip(e, "hipStreamEndCapture");
+            }
+            c->capturing = false;
+            if (st == GESMC_OK)
+                st = check_hip(hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            if (graph) (void)hipGraphDestroy(graph);
+            if (st != GESMC_OK) {
+                c->graph_exec = nullptr;
+                return st;
+            }
+            c->graph_key = key;
+            GESMC_TRY(check_hip(hipGraphLaunch(c->graph_exec, s), "hipGraphLaunch"));
+        } else {
+            c->graph_last_key = key;
+            GESMC_TRY(device_work());
+        }
+    } else {
+        GESMC_TRY(device_work());
     }
-    if (need_validation) {
-        c->ctr_step = c->ctr;
-        GESMC_TRY(launch(c, s, KID_EMIT, npos, k_emit_sources, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                         (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
-        GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP, ge_all));
-    }
-    // superstep s switches the ranks [0, active_s): those with r > s
-    uint32_t qa = nactive;
-    for (uint32_t st = 0; st < rmax; ++st) {
-        while (qa > 0 && r_eff(order[qa - 1]) <= st) --qa;
-        const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
-        const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
-        const Plan p = batch_plan(c, P, NB);
-        BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all};
-        c->ctr_step = c->ctr + st;
-        GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
-    }
-    if (total_m > 0)
-        GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_unpermute_batch, dim3(grid_stride_blocks(c, npos)), dim3(kBlock),
-                         0, (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0],
-                         (const uint32_t *)c->pg, (const BatchGraph *)c->gr, npos, (unsigned long long *)d_out,
-                         (const uint32_t *)c->err));
     GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     if (rmax > 0)
@@ -1128,12 +1199,14 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
                               (int)sort_lds_bytes(kLdsCap));
     for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileSmall>, (const void *)k_scatter<kSrcHash, kTileSmall>,
                           (const void *)k_scatter<kSrcBatch, kTileSmall>,
-                          (const void *)k_scatter<kSrcBucket, kTileSmall>})
+                          (const void *)k_scatter<kSrcBucket, kTileSmall>, (const void *)k_scatter<kSrcEmit, kTileSmall>,
+                          (const void *)k_scatter<kSrcHashed, kTileSmall>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(12, kTileSmall));
     for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileLarge>, (const void *)k_scatter<kSrcHash, kTileLarge>,
                           (const void *)k_scatter<kSrcBatch, kTileLarge>,
-                          (const void *)k_scatter<kSrcBucket, kTileLarge>})
+                          (const void *)k_scatter<kSrcBucket, kTileLarge>, (const void *)k_scatter<kSrcEmit, kTileLarge>,
+                          (const void *)k_scatter<kSrcHashed, kTileLarge>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(12, kTileLarge));
     (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1157,6 +1230,7 @@ void gesmc_destroy(gesmc_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     free_buffers(c);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->small) (void)hipFree(c->small);
     if (c->bslot) (void)hipFree(c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
@@ -1386,6 +1460,15 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_GRAPH:
+            if (v < 0 || v > 1) break;
+            c->use_graph = v != 0;
+            if (!c->use_graph && c->graph_exec) {
+                (void)hipGraphExecDestroy(c->graph_exec);
+                c->graph_exec = nullptr;
+            }
+            c->graph_key = c->graph_last_key = 0;
             return GESMC_OK;
         case GESMC_OPT_FUSE_EMIT:
             if (v < 0 || v > 1) break;

@@ -123,7 +123,9 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
 // Radix source of a record.  kSrcPerm sorts edge records by the Philox key
 // of their index (the permutation); kSrcHash sorts (tag, edge key) tuples by
 // a hash of the edge key (the dependency partitions), where an empty key
-// marks a tuple slot that carries nothing; kSrcEmit is kSrcHash over the
+// marks a tuple slot that carries nothing (the first pass turns keys into
+// tuple_hash words, which the second pass, kSrcHashed, and the resolve read
+// as they are); kSrcEmit is kSrcHash over the
 // tuples of the switches themselves, computed from the pair records while
 // they are read (slots 4k .. 4k+3 of switch k; see emit_switch), so the flat tuple
 // array is never stored.  A batch of graphs sorts by the global bucket
@@ -131,7 +133,7 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
 // the record's position (level 1) and writes it out beside the record,
 // kSrcBucket reads it back (level 2).  Bucket numbers are placed in the top
 // B bits of the radix word, so both levels use the same shifts.
-enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3, kSrcEmit = 4 };
+enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3, kSrcEmit = 4, kSrcHashed = 5 };
 
 struct SrcArgs {
     const BatchGraph *gr;    // per graph (batches)
@@ -150,7 +152,9 @@ __device__ __forceinline__ constexpr bool src_reads_idx() { return kSrc == kSrcP
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcBatch || kSrc == kSrcBucket; }
 template <int kSrc>
-__device__ __forceinline__ constexpr bool src_is_tuple() { return kSrc == kSrcHash || kSrc == kSrcEmit; }
+__device__ __forceinline__ constexpr bool src_is_tuple() {
+    return kSrc == kSrcHash || kSrc == kSrcEmit || kSrc == kSrcHashed;
+}
 
 // Local outcome of switch k from its pair records (ij, ee): P_L skip, the
 // idle pair of a batch graph's padding record, a loop, or a target equal to
@@ -222,7 +226,7 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             tag[4 * j + h] = tp[h].tag;
-            key[4 * j + h] = sl + h < cnt ? tp[h].key : kEmptyKey;
+            key[4 * j + h] = sl + h < cnt ? tuple_hash(tp[h].key) : kEmptyKey;
         }
     }
 }
@@ -231,7 +235,7 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
 template <int kSrc>
 __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t aux, uint32_t t,
                                                uint32_t k0, uint32_t k1, const SrcArgs &ba, uint32_t *bucket) {
-    if (src_is_tuple<kSrc>()) return slot_hash(key);
+    if (src_is_tuple<kSrc>()) return key;  // tuple words are tuple hashes (see the loads)
     if (kSrc == kSrcPerm) return perm_key(idx, t, k0, k1);
     uint32_t b = aux;
     if (kSrc == kSrcBatch) {
@@ -297,7 +301,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
                 cur_i[q] = 0u;
                 cur_a[q] = 0u;
                 cur_k[q] = kEmptyKey;
-                if (kSrc == kSrcHash && in) cur_k[q] = src_key[ts.begin + p];
+                if (kSrc == kSrcHash && in) cur_k[q] = tuple_hash(src_key[ts.begin + p]);
+                if (kSrc == kSrcHashed && in) cur_k[q] = src_key[ts.begin + p];
                 if (src_reads_idx<kSrc>() && in) cur_i[q] = src_idx[ts.begin + p];
                 if (src_reads_aux<kSrc>() && in) cur_a[q] = ba.aux_in[ts.begin + p];
             }
@@ -473,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                 const bool in = p < ts.cnt;
                 c_idx[q] = in ? src_idx[ts.begin + p] : 0u;
                 c_key[q] = in ? src_key[ts.begin + p] : kEmptyKey;
+                if (kSrc == kSrcHash) c_key[q] = tuple_hash(c_key[q]);  // empty stays empty
                 c_aux[q] = (src_reads_aux<kSrc>() && in) ? ba.aux_in[ts.begin + p] : 0u;
             }
         }

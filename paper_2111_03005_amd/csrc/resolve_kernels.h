@@ -120,7 +120,7 @@ __device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t 
                                                const GraphErr &ge) {
     if (dup_bit) atomicOr(err, dup_bit);
     if (ge.gr) {
-        const uint32_t v = (uint32_t)(key >> 32);
+        const uint32_t v = (uint32_t)(tuple_key_of(key) >> 32);
         uint32_t lo = 0, hi = ge.ngraphs - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             for (int q = 0; q < kSortMaxItems; ++q) {
                 const uint32_t p = tid + q * kBlock;
                 if (p < c) {
-                    const uint64_t hsh = slot_hash(c_key[q]);
+                    const uint64_t hsh = c_key[q];  // tuple words are tuple hashes
                     r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
                     r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
                 }

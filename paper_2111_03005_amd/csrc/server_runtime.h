@@ -243,6 +243,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         }
         std::swap(c->idx[0], c->idx[1]);
         std::swap(c->key[0], c->key[1]);
+        ++g_alloc_epoch;  // buffer roles moved: no captured graph may be replayed
     }
     // one superstep of every resident graph (each at its own superstep t0 + done)
     const Plan p = batch_plan(c, npos, bbase);
