@@ -254,7 +254,35 @@ def bench_served(gesmc, torch, args):
                "busy_fraction": round(info["busy_s"] / max(info["now_s"], 1e-9), 3)}
         print("served: %s" % rec, file=sys.stderr)
         out.append(rec)
+    # the plain form on the same kind of stream: gesmc_run on the requests one after
+    # another (a bounded sample of the highest rate's requests, no arrival gaps)
+    rng = np.random.default_rng(1000 + int(args.serve_rates[-1]))
+    picks = rng.integers(0, len(pool), args.serve_requests)
+    rs = rng.integers(10, 51, args.serve_requests)
+    seeds = rng.integers(0, 2**63, args.serve_requests)
+    ctx = gesmc.Context(0)
+    sample = list(range(0, args.serve_requests, 4))
+    devs = [torch.from_numpy(pool[picks[i]][0].view(np.int64).copy()).to("cuda") for i in sample]
+    for d, i in list(zip(devs, sample))[:4]:
+        ctx.run(d, pool[picks[i]][1], 1, 0, 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    att = 0
+    for d, i in zip(devs, sample):
+        ctx.run(d, pool[picks[i]][1], int(seeds[i]), 0, int(rs[i]))
+        att += int(rs[i]) * (d.numel() // 2)
+    torch.cuda.synchronize()
+    plain = att / (time.perf_counter() - t)
+    ctx.close()
+    del devs
+    best = max(x["attempts_per_s"] for x in out)
+    print("served: plain gesmc_run on every 4th request of the %g req/s stream: %.3e attempts/s" % (
+        args.serve_rates[-1], plain), file=sys.stderr)
     return {"unit": "attempts/s", "per_rate": out,
+            "plain_same_requests": {"value": round(plain, 1), "unit": "attempts/s",
+                                    "sample": "gesmc_run one request after another, every 4th request of the "
+                                              "%g req/s stream (%d requests)" % (args.serve_rates[-1], len(sample))},
+            "vs_plain_same_requests": round(best / plain, 3),
             "workload": "Poisson arrivals; requests drawn from a pool of %d power-law graphs (n log-uniform "
                         "[1e3,1e6], gamma U[2.1,3.0], d_min 2, d_max floor(sqrt(n)), generator seed 5), "
                         "r uniform in 10..50, own Philox seed" % len(pool)}
