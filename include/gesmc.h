@@ -247,6 +247,9 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                       second call of the same shape (pointers, sizes, offsets, r, pl,
                                       options) and replays it for later calls of that shape -- seeds,
                                       t0 and n may change; needs a non-NULL stream (default 0)         */
+#define GESMC_OPT_SMALL_GRAPHS 11  /* 1: in gesmc_run_batch, graphs of at most 1024 edges run all their
+                                      supersteps in one workgroup's LDS (one launch for all of them);
+                                      0: every graph takes the multi-kernel supersteps (default 1)   */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

@@ -22,6 +22,7 @@ OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PE
 OPT_LEVEL1_BITS = 8
 OPT_FUSE_EMIT = 9
 OPT_GRAPH = 10
+OPT_SMALL_GRAPHS = 11
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 

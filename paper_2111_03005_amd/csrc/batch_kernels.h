@@ -6,6 +6,8 @@
 #pragma once
 
 #include "device_common.h"
+#include "perm_kernels.h"
+#include "switch_kernels.h"
 
 namespace gesmc {
 
@@ -180,6 +182,270 @@ __global__ __launch_bounds__(kBlock) void k_extract(const uint32_t *__restrict__
         if (i == kPadIdx) continue;
         const uint64_t vb = gr[q].vbase;
         out[base + (i - gr[q].goff)] = key[p] - ((vb << 32) | vb);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small graphs of a batch: one workgroup runs all r global switches of one
+// graph inside LDS -- the permutation (LDS counting sort of (K_i, i) on the
+// top bits of K, insertion in cells), the switches' ERASE / INSERT tuples
+// sorted by (tuple hash, tag), the rounds of decisions of Alg. 1 and the
+// writes -- with the same definitions as the multi-kernel path, so the result
+// is the same chain.  The records stay in LDS across supersteps.  Two sizes:
+// m <= 1024 with 256 threads (36 KB of LDS, several workgroups per CU) and
+// m <= 4096 with 1024 threads (146 KB, one per CU); in both each thread holds
+// 4 permutation items, 2 switches (9 tuples) and owns one sort cell.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSmallMax = 1024, kSmallThreads = 256;  // edges, threads
+constexpr uint32_t kMidMax = 4096, kMidThreads = 1024;
+constexpr uint16_t kSmTagStays = 0x7FFF;  // ERASE tag of a surviving edge; erase tags are k < 0x7FFF
+constexpr uint16_t kSmTagInsert = 0x8000; // | (k << 1 | h)
+constexpr uint32_t kSmNone = 0xFFFFu, kSmStays = 0xFFFEu;
+
+template <uint32_t kMax, uint32_t kThreads>
+struct SmallLds {
+    unsigned long long E[kMax];       // edge keys by local index
+    unsigned long long sK[2 * kMax];  // sorted permutation keys, then sorted tuple hashes
+    uint32_t info[kMax];              // per target 2k+h: eraser << 16 | predecessor
+    uint16_t pi[kMax];                // the permutation of this superstep
+    uint16_t sT[2 * kMax];            // sorted local index, then sorted tuple tag
+    uint32_t cell[kThreads + 1];      // one sort cell per thread
+    uint32_t tmp[kThreads / 64 + 2];
+    uint8_t st[kMax / 2];
+    uint32_t undecided, flags;
+    uint32_t cnt[4];
+};
+static_assert(kMidMax / 2 < kSmTagStays && 2 * kMidMax <= 0x10000, "small-graph tags are 16 bits");
+static_assert(kSmallMax == 4 * kSmallThreads && kMidMax == 4 * kMidThreads, "4 edges per thread");
+
+template <uint32_t kThreads>
+constexpr int small_cell_bits() {
+    return kThreads == 256 ? 8 : kThreads == 512 ? 9 : 10;
+}
+
+// Sorts up to 2 kMax items by (word, tag): they sit in registers (w[q], g[q]
+// for q < kPer where present[q]); counting sort on the top cell bits into
+// sK / sT, then each thread settles the cell it owns by insertion.  Returns
+// with a barrier passed.
+template <int kPer, uint32_t kMax, uint32_t kThreads>
+__device__ __forceinline__ void small_sort(SmallLds<kMax, kThreads> &L, const unsigned long long *w,
+                                           const uint16_t *g, const bool *present) {
+    constexpr int kShift = 64 - small_cell_bits<kThreads>();
+    const uint32_t tid = threadIdx.x;
+    L.cell[tid] = 0;
+    __syncthreads();
+    uint32_t rank[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (present[q]) rank[q] = atomicAdd(&L.cell[(uint32_t)(w[q] >> kShift)], 1u);
+    __syncthreads();
+    uint32_t total;
+    const uint32_t base = block_exclusive_sum<kThreads>(L.cell[tid], L.tmp, &total);
+    L.cell[tid] = base;
+    if (tid == 0) L.cell[kThreads] = total;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (!present[q]) continue;
+        const uint32_t p = L.cell[(uint32_t)(w[q] >> kShift)] + rank[q];
+        L.sK[p] = w[q];
+        L.sT[p] = g[q];
+    }
+    __syncthreads();
+    const uint32_t a = L.cell[tid], b = L.cell[tid + 1];
+    for (uint32_t x = a + 1; x < b; ++x) {
+        const unsigned long long kx = L.sK[x];
+        const uint16_t tx = L.sT[x];
+        uint32_t y = x;
+        while (y > a && (L.sK[y - 1] > kx || (L.sK[y - 1] == kx && L.sT[y - 1] > tx))) {
+            L.sK[y] = L.sK[y - 1];
+            L.sT[y] = L.sT[y - 1];
+            --y;
+        }
+        L.sK[y] = kx;
+        L.sT[y] = tx;
+    }
+    __syncthreads();
+}
+
+// Alg. 1's rule for target 2k+h from its packed record (see judge_target_chain).
+template <uint32_t kMax, uint32_t kThreads>
+__device__ __forceinline__ int small_judge(const SmallLds<kMax, kThreads> &L, uint32_t rec, uint32_t k) {
+    int v = V_OK;
+    const uint32_t e = rec >> 16;
+    if (e != kSmNone) {
+        if (e == kSmStays || e >= k) return V_ILLEGAL;
+        const uint8_t se = L.st[e];
+        if (se == ST_UNDECIDED)
+            v = V_WAIT;
+        else if (se != ST_LEGAL)
+            return V_ILLEGAL;
+    }
+    uint32_t p = rec & 0xFFFFu, below = k;
+    while (p != kSmNone) {
+        const uint32_t pk = p >> 1;
+        if (pk >= below) return V_ILLEGAL;
+        const uint8_t sp = L.st[pk];
+        if (sp == ST_LEGAL) return V_ILLEGAL;
+        if (sp == ST_UNDECIDED) return V_WAIT;
+        below = pk;
+        p = L.info[p] & 0xFFFFu;
+    }
+    return v;
+}
+
+// One workgroup per listed graph (ranks `small[0 .. count)`, r of rank q in
+// rv[q], m of every listed graph <= kMax); records of graph q are at
+// positions poff + local index of `key`; its outcome counts go to
+// acc[4q .. 4q+3] (legal, loop, exists, P_L).
+template <uint32_t kMax, uint32_t kThreads>
+__global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__restrict__ small,
+                                                          const BatchGraph *__restrict__ gr,
+                                                          const uint32_t *__restrict__ rv,
+                                                          unsigned long long *__restrict__ key,
+                                                          unsigned long long *__restrict__ acc,
+                                                          uint32_t *__restrict__ gerr, uint32_t *__restrict__ err) {
+    __shared__ SmallLds<kMax, kThreads> L;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t q = small[blockIdx.x];
+    const BatchGraph b = gr[q];
+    const uint32_t m = b.m, ell = m >> 1, r = rv[q];
+    for (uint32_t li = tid; li < m; li += kThreads) L.E[li] = key[b.poff + li];
+    if (tid < 4) L.cnt[tid] = 0;
+    if (tid == 0) L.flags = 0;
+    uint32_t c_legal = 0, c_loop = 0, c_exists = 0, c_pl = 0;
+    __syncthreads();
+    for (uint32_t s = 0; s < r; ++s) {
+        const uint32_t t = b.t0 + s;
+        // permutation: sort local indices by (K_i, i)
+        {
+            unsigned long long w[4];
+            uint16_t g[4];
+            bool pr[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const uint32_t li = tid + x * kThreads;
+                pr[x] = li < m;
+                w[x] = pr[x] ? perm_key(li, t, b.k0, b.k1) : ~0ull;
+                g[x] = (uint16_t)li;
+            }
+            small_sort<4>(L, w, g, pr);
+            for (uint32_t p = tid; p < m; p += kThreads) L.pi[p] = L.sT[p];
+            __syncthreads();
+        }
+        // switches: local checks and tuples (4 per switch, + the idle record of odd m)
+        {
+            unsigned long long w[9];
+            uint16_t g[9];
+            bool pr[9];
+#pragma unroll
+            for (int x = 0; x < 9; ++x) pr[x] = false;
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const uint32_t k = tid + y * kThreads;
+                if (k >= ell) continue;
+                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+                const unsigned long long e1 = L.E[i], e2 = L.E[j];
+                uint8_t status = ST_UNDECIDED;
+                Targets T{0, 0, false};
+                if (pl_skip(k, t, b.pl, b.k0, b.k1)) {
+                    status = ST_PL;
+                } else {
+                    T = switch_targets(e1, e2, i < j);
+                    if (T.loop)
+                        status = ST_LOOP;
+                    else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
+                        status = ST_EXISTS;
+                }
+                L.st[k] = status;
+                L.info[2 * k] = L.info[2 * k + 1] = 0xFFFFFFFFu;
+                const uint16_t et = status == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
+                w[4 * y + 0] = tuple_hash(e1);
+                g[4 * y + 0] = et;
+                w[4 * y + 1] = tuple_hash(e2);
+                g[4 * y + 1] = et;
+                pr[4 * y + 0] = pr[4 * y + 1] = true;
+                if (status == ST_UNDECIDED) {
+                    w[4 * y + 2] = tuple_hash(T.A);
+                    g[4 * y + 2] = (uint16_t)(kSmTagInsert | (k << 1));
+                    w[4 * y + 3] = tuple_hash(T.B);
+                    g[4 * y + 3] = (uint16_t)(kSmTagInsert | (k << 1) | 1u);
+                    pr[4 * y + 2] = pr[4 * y + 3] = true;
+                }
+            }
+            if ((m & 1u) && tid == 0) {
+                w[8] = tuple_hash(L.E[L.pi[m - 1]]);
+                g[8] = kSmTagStays;
+                pr[8] = true;
+            }
+            small_sort<9>(L, w, g, pr);
+            // walk the cell this thread owns: eraser and predecessor of every INSERT tuple
+            const uint32_t a = L.cell[tid], bnd = L.cell[tid + 1];
+            uint32_t first = a;
+            for (uint32_t x = a; x < bnd; ++x) {
+                if (x > a && L.sK[x] != L.sK[x - 1]) first = x;
+                const uint16_t tg = L.sT[x];
+                if (!(tg & kSmTagInsert)) {
+                    if (x != first) atomicOr(&L.flags, 1u);  // a key erased twice: a duplicate edge
+                    continue;
+                }
+                const uint16_t ft = L.sT[first];
+                uint32_t eraser = kSmNone;
+                if (!(ft & kSmTagInsert)) eraser = ft == kSmTagStays ? kSmStays : ft;
+                const uint16_t prev = x > first ? L.sT[x - 1] : 0;
+                const uint32_t pred = (x > first && (prev & kSmTagInsert)) ? (uint32_t)(prev & ~kSmTagInsert) : kSmNone;
+                L.info[tg & ~kSmTagInsert] = (eraser << 16) | pred;
+            }
+            __syncthreads();
+        }
+        // rounds of decisions until every switch is decided
+        for (;;) {
+            if (tid == 0) L.undecided = 0;
+            __syncthreads();
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const uint32_t k = tid + y * kThreads;
+                if (k >= ell || L.st[k] != ST_UNDECIDED) continue;
+                const int v = max(small_judge(L, L.info[2 * k], k), small_judge(L, L.info[2 * k + 1], k));
+                if (v == V_WAIT)
+                    atomicAdd(&L.undecided, 1u);
+                else
+                    L.st[k] = v == V_OK ? ST_LEGAL : ST_EXISTS;
+            }
+            __syncthreads();
+            const uint32_t left = L.undecided;
+            __syncthreads();
+            if (left == 0) break;
+        }
+        // writes and counts
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const uint32_t k = tid + y * kThreads;
+            if (k >= ell) continue;
+            const uint8_t sv = L.st[k];
+            if (sv == ST_LEGAL) {
+                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+                const Targets T = switch_targets(L.E[i], L.E[j], i < j);
+                L.E[i] = T.A;
+                L.E[j] = T.B;
+                ++c_legal;
+            }
+            c_loop += sv == ST_LOOP;
+            c_exists += sv == ST_EXISTS;
+            c_pl += sv == ST_PL;
+        }
+        __syncthreads();
+    }
+    for (uint32_t li = tid; li < m; li += kThreads) key[b.poff + li] = L.E[li];
+    if (c_legal) atomicAdd(&L.cnt[0], c_legal);
+    if (c_loop) atomicAdd(&L.cnt[1], c_loop);
+    if (c_exists) atomicAdd(&L.cnt[2], c_exists);
+    if (c_pl) atomicAdd(&L.cnt[3], c_pl);
+    __syncthreads();
+    if (tid < 4) acc[4 * (size_t)q + tid] = L.cnt[tid];  // one workgroup per graph
+    if (tid == 0 && L.flags) {
+        atomicOr(&gerr[q], ERR_DUP);
+        atomicOr(err, ERR_DUP);
     }
 }
 

@@ -55,6 +55,8 @@ enum KernelId {
     KID_DECIDE_CHAIN1,
     KID_DECIDE_CHAIN,
     KID_FINISH_CHAIN,
+    KID_SMALL,
+    KID_SMALL_MID,
     KID_COUNT
 };
 
@@ -63,7 +65,7 @@ const char *kKernelNames[KID_COUNT] = {
     "k_scatter2",     "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
     "k_round_decide", "k_finish",       "k_unpermute",  "k_validate",      "k_misc",
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
-    "k_decide_chain1", "k_decide_chain", "k_finish_chain"};
+    "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -142,7 +144,9 @@ struct gesmc_ctx {
     uint32_t *gerr = nullptr, *h_gerr = nullptr;
     uint32_t *pg = nullptr, *bk = nullptr;
     std::vector<BatchGraph> h_gr;
-    std::vector<uint32_t> h_rank_of, h_order;
+    std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_rrank;
+    uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
+    bool small_graphs = true;                         // graphs with m <= kSmallMax run in LDS
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
     uint64_t ctr_cap = 0;
@@ -822,7 +826,7 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
 gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
     if (G > c->cap_g) {
         for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc,
-                         (void **)&c->gerr}) {
+                         (void **)&c->gerr, (void **)&c->small_list, (void **)&c->rrank}) {
             if (*q) (void)hipFree(*q);
             *q = nullptr;
         }
@@ -837,6 +841,8 @@ gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
         GESMC_TRY(dev_alloc((void **)&c->rank_of, cap * 4));
         GESMC_TRY(dev_alloc((void **)&c->gacc, cap * 4 * 8));
         GESMC_TRY(dev_alloc((void **)&c->gerr, cap * 4));
+        GESMC_TRY(dev_alloc((void **)&c->small_list, cap * 4));
+        GESMC_TRY(dev_alloc((void **)&c->rrank, cap * 4));
         if (hipHostMalloc((void **)&c->h_gacc, cap * 4 * 8, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&c->h_gerr, cap * 4, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
@@ -915,23 +921,35 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     }
     hipStream_t s = (hipStream_t)stream;
 
-    // rank order: switched graphs (m >= 2, r >= 1) by r descending, then the rest
+    // rank order: graphs switched by the multi-kernel supersteps (m >= 2, r >= 1,
+    // not small) by r descending, then the small ones (k_small_chain), then the rest
     auto m_of = [&](uint32_t g) { return offsets[g + 1] - offsets[g]; };
     auto r_eff = [&](uint32_t g) { return m_of(g) >= 2 ? rv[g] : 0u; };
+    auto is_small = [&](uint32_t g) { return c->small_graphs && r_eff(g) > 0 && m_of(g) <= kMidMax; };
+    auto r_pipe = [&](uint32_t g) { return is_small(g) ? 0u : r_eff(g); };
+    auto rank_class = [&](uint32_t g) { return r_pipe(g) > 0 ? 0 : (is_small(g) ? 1 : 2); };
     std::vector<uint32_t> &order = c->h_order;
     order.resize(G);
     for (uint32_t g = 0; g < G; ++g) order[g] = g;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return r_eff(a) > r_eff(b); });
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const int ca = rank_class(a), cb = rank_class(b);
+        return ca != cb ? ca < cb : r_pipe(a) > r_pipe(b);
+    });
     std::vector<BatchGraph> &gr = c->h_gr;
     gr.assign(G, BatchGraph{});
     c->h_rank_of.assign(G, 0);
+    c->h_small.clear();
+    c->h_mid.clear();
+    c->h_rrank.assign(G, 0);
     uint64_t poff = 0, vbase = 0, bbase = 0;
     uint32_t nactive = 0, rmax = 0;
     bool need_validation = false;
     for (uint32_t q = 0; q < G; ++q) {
         const uint32_t g = order[q];
         const uint64_t m = m_of(g);
-        const bool active = r_eff(g) > 0;
+        const bool active = r_pipe(g) > 0;
+        c->h_rrank[q] = r_eff(g);
+        if (is_small(g)) (m <= kSmallMax ? c->h_small : c->h_mid).push_back(q);
         BatchGraph &b = gr[q];
         b.poff = (uint32_t)poff;
         b.mpad = (uint32_t)(m + (active ? (m & 1) : 0));
@@ -952,7 +970,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         if (active) {
             ++nactive;
             rmax = std::max(rmax, rv[g]);
-        } else if (m >= 2) {
+        } else if (m >= 2 && !is_small(g)) {
             need_validation = true;  // never switched: duplicates are checked up front
         }
     }
@@ -969,6 +987,17 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                         "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->in_off, offsets, (G + 1) * 8ull, hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
+    const uint32_t nsm1 = (uint32_t)c->h_small.size(), nsm2 = (uint32_t)c->h_mid.size();
+    c->h_small.insert(c->h_small.end(), c->h_mid.begin(), c->h_mid.end());  // the m <= 1024 list, then the rest
+    const uint32_t nsmall = nsm1 + nsm2;
+    const bool need_acc = stats != nullptr || nsmall > 0;  // small graphs count per graph
+    if (nsmall) {
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->small_list, c->h_small.data(), nsmall * 4ull, hipMemcpyHostToDevice,
+                                           s),
+                            "hipMemcpyAsync"));
+        GESMC_TRY(check_hip(hipMemcpyAsync(c->rrank, c->h_rrank.data(), G * 4ull, hipMemcpyHostToDevice, s),
+                            "hipMemcpyAsync"));
+    }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->rank_of, c->h_rank_of.data(), G * 4ull, hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
     // The device work of the call.  In graph mode (GESMC_OPT_GRAPH) it is captured
@@ -981,7 +1010,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(rmax, 1) * (sizeof(StepCounters) / 4);
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr, zero_words - 64));
-        if (stats)
+        if (need_acc)
             GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
                              (uint64_t)G * 8));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
@@ -1001,10 +1030,19 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                              (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
             GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP, ge_all));
         }
+        // small graphs: every superstep of each in one workgroup, in LDS
+        if (nsm1)
+            GESMC_TRY(launch(c, s, KID_SMALL, nsm1, k_small_chain<kSmallMax, kSmallThreads>, dim3(nsm1),
+                             dim3(kSmallThreads), 0, (const uint32_t *)c->small_list, (const BatchGraph *)c->gr,
+                             (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
+        if (nsm2)
+            GESMC_TRY(launch(c, s, KID_SMALL_MID, nsm2, k_small_chain<kMidMax, kMidThreads>, dim3(nsm2),
+                             dim3(kMidThreads), 0, (const uint32_t *)c->small_list + nsm1, (const BatchGraph *)c->gr,
+                             (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
         // superstep s switches the ranks [0, active_s): those with r > s
         uint32_t qa = nactive;
         for (uint32_t st = 0; st < rmax; ++st) {
-            while (qa > 0 && r_eff(order[qa - 1]) <= st) --qa;
+            while (qa > 0 && r_pipe(order[qa - 1]) <= st) --qa;
             const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
             const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
             const Plan p = batch_plan(c, P, NB);
@@ -1035,6 +1073,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         mix((uint64_t)c->fast_rounds);
         mix(c->level1_cap);
         mix(c->fuse_emit);
+        mix(c->small_graphs);
         mix((uint64_t)c->persist_mult);
         mix(g_alloc_epoch.load());
         mix((uint64_t)(uintptr_t)s);
@@ -1077,7 +1116,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     if (rmax > 0)
         GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters) * rmax, hipMemcpyDeviceToHost, s),
                             "hipMemcpyAsync"));
-    if (stats)
+    if (need_acc)
         GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, (size_t)G * 32, hipMemcpyDeviceToHost, s),
                             "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, (size_t)G * 4, hipMemcpyDeviceToHost, s),
@@ -1120,7 +1159,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             o.rej_loop = c->h_gacc[4 * (size_t)q + 1];
             o.rej_exists = c->h_gacc[4 * (size_t)q + 2];
             o.rej_pl = c->h_gacc[4 * (size_t)q + 3];
-            for (uint32_t st = 0; st < rg; ++st) {
+            for (uint32_t st = 0; st < r_pipe(g); ++st) {  // rounds of the multi-kernel supersteps
                 o.rounds_sum += c->h_ctr[st].rounds;
                 o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)c->h_ctr[st].rounds);
             }
@@ -1139,6 +1178,13 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             total->rej_pl += h.rej_pl;
             total->rounds_sum += h.rounds;
             total->rounds_max = std::max<uint32_t>(total->rounds_max, (uint32_t)h.rounds);
+        }
+        for (uint32_t q : c->h_small) {  // small graphs count per graph only
+            total->legal += c->h_gacc[4 * (size_t)q + 0];
+            total->rej_loop += c->h_gacc[4 * (size_t)q + 1];
+            total->rej_exists += c->h_gacc[4 * (size_t)q + 2];
+            total->rej_pl += c->h_gacc[4 * (size_t)q + 3];
+            total->supersteps = std::max(total->supersteps, c->h_rrank[q]);
         }
         total->ms_device = ms;
     }
@@ -1234,7 +1280,7 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->small) (void)hipFree(c->small);
     if (c->bslot) (void)hipFree(c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
-                    (void *)c->bk, (void *)c->gerr})
+                    (void *)c->bk, (void *)c->gerr, (void *)c->small_list, (void *)c->rrank})
         if (q) (void)hipFree(q);
     if (c->h_gacc) (void)hipHostFree(c->h_gacc);
     if (c->h_gerr) (void)hipHostFree(c->h_gerr);
@@ -1460,6 +1506,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_SMALL_GRAPHS:
+            if (v < 0 || v > 1) break;
+            c->small_graphs = v != 0;
             return GESMC_OK;
         case GESMC_OPT_GRAPH:
             if (v < 0 || v > 1) break;

@@ -57,7 +57,7 @@ def test_binding_constants_match_header():
     assert d["GESMC_OK"] == gesmc.OK
     for name in ["E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_AGAIN", "E_CANCELED", "E_INTERNAL"]:
         assert d["GESMC_" + name] == getattr(gesmc, name), name
-    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH"]:
+    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH", "SMALL_GRAPHS"]:
         assert d["GESMC_OPT_" + name] == getattr(gesmc, "OPT_" + name), name
 
 

@@ -262,3 +262,51 @@ def test_batch_graph_capture_and_replay():
         assert loads <= 3, loads
     finally:
         c.close()
+
+
+def small_batch(seed=37):
+    """Graphs around the LDS-resident size limit (m <= 1024 edges): G(n,p)
+    graphs cut to exactly 1023, 1024 and 1025 edges, dense ones where most
+    targets exist, and small power-law graphs, with long chains (up to 40
+    global switches) so that many supersteps run inside one workgroup."""
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for m in (1023, 1024, 1025):
+        E = graphgen.gnp(300, 0.03, seed + m)
+        assert len(E) >= m
+        graphs.append((np.sort(E[:m]), 300))
+    graphs.append((graphgen.gnp(40, 0.9, seed + 1), 40))
+    graphs.append((graphgen.gnp(48, 0.85, seed + 2), 48))
+    graphs += graphgen.batch_graphs(24, seed, 20, 400)
+    graphs += special_graphs()
+    seeds = [int(x) for x in rng.integers(0, 2**63, len(graphs))]
+    rs = [int(x) for x in rng.integers(0, 41, len(graphs))]
+    t0s = [int(x) for x in rng.integers(0, 1 << 20, len(graphs))]
+    return graphs, seeds, rs, t0s
+
+
+@pytest.mark.parametrize("pl", [0, 1 << 31])
+def test_small_graph_path_exact(pl):
+    """GESMC_OPT_SMALL_GRAPHS: graphs of at most 1024 edges run every
+    superstep in one LDS-resident workgroup.  With the option on and off the
+    results and counts are identical and equal the oracle's."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2111_03005_amd as gesmc
+    graphs, seeds, rs, t0s = small_batch()
+    res = []
+    for on in (1, 0):
+        c = gesmc.Context(0)
+        try:
+            c.set_option(gesmc.OPT_SMALL_GRAPHS, on)
+            got, offs, stats, tot = run_batch(c, graphs, seeds, rs, t0s, pl)
+            res.append((got, stats, tot))
+        finally:
+            c.close()
+    check_against_oracle(graphs, res[0][0], offs, res[0][1], seeds, rs, t0s, pl, range(len(graphs)))
+    assert np.array_equal(res[0][0], res[1][0])
+    outcome = ("attempts", "legal", "rej_loop", "rej_exists", "rej_pl", "supersteps")
+    for g in range(len(graphs)):  # rounds and times depend on the schedule, outcomes do not
+        assert all(res[0][1][g][k] == res[1][1][g][k] for k in outcome), g
+    for k in outcome[:5]:
+        assert res[0][2][k] == res[1][2][k], k
