@@ -188,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_extract(const uint32_t *__restrict__
 // ---------------------------------------------------------------------------
 // Small graphs of a batch: one workgroup runs all r global switches of one
 // graph inside LDS -- the permutation (LDS counting sort of (K_i, i) on the
-// top bits of K, insertion in cells), the switches' ERASE / INSERT tuples
-// sorted by (tuple hash, tag), the rounds of decisions of Alg. 1 and the
+// top bits of K, then ranks within cells), the switches' ERASE / INSERT
+// tuples grouped by tuple hash, the rounds of decisions of Alg. 1 and the
 // writes -- with the same definitions as the multi-kernel path, so the result
 // is the same chain.  The records stay in LDS across supersteps.  Two sizes:
 // m <= 1024 with 256 threads (36 KB of LDS, several workgroups per CU) and
@@ -223,21 +223,25 @@ constexpr int small_cell_bits() {
     return kThreads == 256 ? 8 : kThreads == 512 ? 9 : 10;
 }
 
-// Sorts up to 2 kMax items by (word, tag): they sit in registers (w[q], g[q]
-// for q < kPer where present[q]); counting sort on the top cell bits into
-// sK / sT, then each thread settles the cell it owns by insertion.  Returns
-// with a barrier passed.
+// Groups up to 2 kMax items by the top cell bits of their word: they sit in
+// registers (w[q], g[q] for q < kPer where present[q]); a counting sort puts
+// them in cell order into sK / sT, item q at slot[q] of cell cl[q] (cell c
+// spans [L.cell[c], L.cell[c + 1])).  Within a cell the order is arbitrary;
+// callers read the whole cell.  Returns with a barrier passed.
 template <int kPer, uint32_t kMax, uint32_t kThreads>
-__device__ __forceinline__ void small_sort(SmallLds<kMax, kThreads> &L, const unsigned long long *w,
-                                           const uint16_t *g, const bool *present) {
+__device__ __forceinline__ void small_group(SmallLds<kMax, kThreads> &L, const unsigned long long *w,
+                                            const uint16_t *g, const bool *present, uint32_t *cl, uint32_t *slot) {
     constexpr int kShift = 64 - small_cell_bits<kThreads>();
     const uint32_t tid = threadIdx.x;
     L.cell[tid] = 0;
     __syncthreads();
     uint32_t rank[kPer];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q)
-        if (present[q]) rank[q] = atomicAdd(&L.cell[(uint32_t)(w[q] >> kShift)], 1u);
+    for (int q = 0; q < kPer; ++q) {
+        if (!present[q]) continue;
+        cl[q] = (uint32_t)(w[q] >> kShift);
+        rank[q] = atomicAdd(&L.cell[cl[q]], 1u);
+    }
     __syncthreads();
     uint32_t total;
     const uint32_t base = block_exclusive_sum<kThreads>(L.cell[tid], L.tmp, &total);
@@ -247,23 +251,9 @@ __device__ __forceinline__ void small_sort(SmallLds<kMax, kThreads> &L, const un
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
-        const uint32_t p = L.cell[(uint32_t)(w[q] >> kShift)] + rank[q];
-        L.sK[p] = w[q];
-        L.sT[p] = g[q];
-    }
-    __syncthreads();
-    const uint32_t a = L.cell[tid], b = L.cell[tid + 1];
-    for (uint32_t x = a + 1; x < b; ++x) {
-        const unsigned long long kx = L.sK[x];
-        const uint16_t tx = L.sT[x];
-        uint32_t y = x;
-        while (y > a && (L.sK[y - 1] > kx || (L.sK[y - 1] == kx && L.sT[y - 1] > tx))) {
-            L.sK[y] = L.sK[y - 1];
-            L.sT[y] = L.sT[y - 1];
-            --y;
-        }
-        L.sK[y] = kx;
-        L.sT[y] = tx;
+        slot[q] = L.cell[cl[q]] + rank[q];
+        L.sK[slot[q]] = w[q];
+        L.sT[slot[q]] = g[q];
     }
     __syncthreads();
 }
@@ -329,8 +319,20 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
                 w[x] = pr[x] ? perm_key(li, t, b.k0, b.k1) : ~0ull;
                 g[x] = (uint16_t)li;
             }
-            small_sort<4>(L, w, g, pr);
-            for (uint32_t p = tid; p < m; p += kThreads) L.pi[p] = L.sT[p];
+            uint32_t cl[4], slot[4];
+            small_group<4>(L, w, g, pr, cl, slot);
+            // keys (K_i, i) are distinct: an index's place is the number of smaller keys in its cell
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                if (!pr[x]) continue;
+                const uint32_t a = L.cell[cl[x]], e = L.cell[cl[x] + 1];
+                uint32_t rank = 0;
+                for (uint32_t y = a; y < e; ++y) {
+                    const unsigned long long ky = L.sK[y];
+                    rank += ky < w[x] || (ky == w[x] && L.sT[y] < g[x]);
+                }
+                L.pi[a + rank] = g[x];
+            }
             __syncthreads();
         }
         // switches: local checks and tuples (4 per switch, + the idle record of odd m)
@@ -378,23 +380,37 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
                 g[8] = kSmTagStays;
                 pr[8] = true;
             }
-            small_sort<9>(L, w, g, pr);
-            // walk the cell this thread owns: eraser and predecessor of every INSERT tuple
-            const uint32_t a = L.cell[tid], bnd = L.cell[tid + 1];
-            uint32_t first = a;
-            for (uint32_t x = a; x < bnd; ++x) {
-                if (x > a && L.sK[x] != L.sK[x - 1]) first = x;
-                const uint16_t tg = L.sT[x];
-                if (!(tg & kSmTagInsert)) {
-                    if (x != first) atomicOr(&L.flags, 1u);  // a key erased twice: a duplicate edge
+            uint32_t cl[9], slot[9];
+            small_group<9>(L, w, g, pr, cl, slot);
+            // all tuples of one key share a cell; each reads its cell for the
+            // group's smallest tag and the largest tag before it in (key, tag,
+            // slot) order: an ERASE tuple with one before it is a second
+            // eraser of its key (a duplicate edge); an INSERT tuple gets its
+            // eraser from the smallest tag and its predecessor from the one before
+#pragma unroll
+            for (int x = 0; x < 9; ++x) {
+                if (!pr[x]) continue;
+                const uint32_t a = L.cell[cl[x]], e = L.cell[cl[x] + 1];
+                const uint16_t tx = g[x];
+                uint32_t first = tx, prev = 0;
+                bool before = false;
+                for (uint32_t y = a; y < e; ++y) {
+                    if (y == slot[x] || L.sK[y] != w[x]) continue;
+                    const uint16_t ty = L.sT[y];
+                    first = min(first, (uint32_t)ty);
+                    if (ty < tx || (ty == tx && y < slot[x])) {
+                        prev = before ? max(prev, (uint32_t)ty) : ty;
+                        before = true;
+                    }
+                }
+                if (!(tx & kSmTagInsert)) {
+                    if (before) atomicOr(&L.flags, 1u);
                     continue;
                 }
-                const uint16_t ft = L.sT[first];
                 uint32_t eraser = kSmNone;
-                if (!(ft & kSmTagInsert)) eraser = ft == kSmTagStays ? kSmStays : ft;
-                const uint16_t prev = x > first ? L.sT[x - 1] : 0;
-                const uint32_t pred = (x > first && (prev & kSmTagInsert)) ? (uint32_t)(prev & ~kSmTagInsert) : kSmNone;
-                L.info[tg & ~kSmTagInsert] = (eraser << 16) | pred;
+                if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
+                const uint32_t pred = (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
+                L.info[tx & ~kSmTagInsert] = (eraser << 16) | pred;
             }
             __syncthreads();
         }

@@ -636,28 +636,36 @@ __global__ __launch_bounds__(kBlock) void k_sort_buckets(const uint32_t *__restr
                 if (p < c) {
                     const uint32_t lp = cell[r_cell[q]] + r_rank[q];
                     sK[lp] = r_K[q];
-                    sE[lp] = c_key[q];
                     sI[lp] = c_idx[q];
                 }
             }
             lds_barrier();
-            // settle ties of the counting sort: each thread owns kCells / kBlock consecutive cells
-            for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
-                const uint32_t a = cell[q];
-                const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
-                for (uint32_t x = a + 1; x < b; ++x) {
-                    const unsigned long long kx = sK[x], ex = sE[x];
-                    const uint32_t ix = sI[x];
-                    uint32_t y = x;
-                    while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sI[y - 1] > ix))) {
-                        sK[y] = sK[y - 1];
-                        sE[y] = sE[y - 1];
-                        sI[y] = sI[y - 1];
-                        --y;
-                    }
-                    sK[y] = kx;
-                    sE[y] = ex;
-                    sI[y] = ix;
+            // order within a cell: the keys (K_i, i) are distinct, so an item's
+            // place is the number of smaller ones in its cell (independent
+            // LDS loads, no insertion sort)
+            uint32_t r_pos[kSortMaxItems];
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p >= c) continue;
+                const uint32_t cl = r_cell[q];
+                const uint32_t a = cell[cl], b = (cl + 1 < kCells) ? cell[cl + 1] : c;
+                const unsigned long long kx = r_K[q];
+                const uint32_t ix = c_idx[q];
+                uint32_t rank = 0;
+                for (uint32_t y = a; y < b; ++y) {
+                    const unsigned long long ky = sK[y];
+                    rank += ky < kx || (ky == kx && sI[y] < ix);
+                }
+                r_pos[q] = a + rank;
+            }
+            lds_barrier();
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    sE[r_pos[q]] = c_key[q];
+                    sI[r_pos[q]] = c_idx[q];
                 }
             }
             lds_barrier();

@@ -151,9 +151,8 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
 }
 
 // One workgroup per fine partition (grid-stride if the grid is smaller).
-// LDS path: counting sort on
-// kCellBits hash bits below the partition bits, then each thread sorts the
-// cells it owns by (key, tag) and walks them.  Partitions above `cap` (hub
+// LDS path: counting sort on kCellBits hash bits below the partition bits;
+// each tuple then reads its own cell.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
 // Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 12 bytes.
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
@@ -267,31 +266,32 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 }
             }
             lds_barrier();
-            // Each thread owns kCells / kBlock consecutive cells.  All tuples of
-            // one key share a cell, so the owner sorts its cells by (key, tag)
-            // and walks them once.
-            for (uint32_t q = tid * (kCells / kBlock); q < (tid + 1) * (kCells / kBlock); ++q) {
-                const uint32_t a = cell[q];
-                const uint32_t b = (q + 1 < kCells) ? cell[q + 1] : c;
-                if (b - a < 2) continue;  // a lone tuple has neither eraser nor predecessor
-                for (uint32_t x = a + 1; x < b; ++x) {
-                    const unsigned long long kx = sK[x];
-                    const uint32_t tx = sT[x];
-                    uint32_t y = x;
-                    while (y > a && (sK[y - 1] > kx || (sK[y - 1] == kx && sT[y - 1] > tx))) {
-                        sK[y] = sK[y - 1];
-                        sT[y] = sT[y - 1];
-                        --y;
+            // All tuples of one key share a cell.  Each tuple reads its cell
+            // (independent LDS loads, no sorting) for what the walk over the
+            // sorted group would give: the group's smallest tag, whether a
+            // tuple precedes it in (key, tag, slot) order and the largest
+            // preceding tag.
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p >= c) continue;
+                const uint32_t cl = r_cell[q];
+                const uint32_t a = cell[cl], b = (cl + 1 < kCells) ? cell[cl + 1] : c;
+                const uint32_t me = a + r_rank[q];
+                const unsigned long long kx = c_key[q];
+                const uint32_t tx = c_tag[q];
+                uint32_t first_tag = tx, prev_tag = 0;
+                bool before = false;
+                for (uint32_t y = a; y < b; ++y) {
+                    if (y == me || sK[y] != kx) continue;
+                    const uint32_t ty = sT[y];
+                    first_tag = min(first_tag, ty);
+                    if (ty < tx || (ty == tx && y < me)) {
+                        prev_tag = before ? max(prev_tag, ty) : ty;
+                        before = true;
                     }
-                    sK[y] = kx;
-                    sT[y] = tx;
                 }
-                uint32_t first = a;
-                for (uint32_t x = a; x < b; ++x) {
-                    if (x > a && sK[x] != sK[x - 1]) first = x;
-                    resolve_one(sT[x], sT[first], x, first, x > a ? sT[x - 1] : 0u, sK[x], info, err, dup_bit,
-                                ge);
-                }
+                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, info, err, dup_bit, ge);
             }
             lds_barrier();
         }
