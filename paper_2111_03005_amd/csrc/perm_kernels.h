@@ -231,6 +231,22 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
     }
 }
 
+// Workgroups are dispatched round-robin over the chip's XCDs (workgroup b
+// runs on XCD b % kXcds), each with its own L2.  xcd_tile maps dispatch order
+// v in [0, n) to a tile so that XCD x works on the contiguous tiles
+// [x * n / kXcds, ...): the adjacent runs that neighbouring tiles write for
+// one digit then meet in the same L2.  A bijection on [0, n); with a
+// grid-stride loop the grid must be a multiple of kXcds.
+#ifndef GESMC_XCD_REMAP
+#define GESMC_XCD_REMAP 1
+#endif
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
+    if (!GESMC_XCD_REMAP) return v;
+    const uint32_t x = v % kXcds, i = v / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + min(x, r) + i;
+}
+
 // Radix word of one record; *bucket receives the global bucket (kSrcBatch).
 template <int kSrc>
 __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t aux, uint32_t t,
@@ -465,7 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
 
     const uint32_t nt = tile_first[nseg];
     const uint32_t tid = threadIdx.x;
-    for (uint32_t w = blockIdx.x; w < nt; w += gridDim.x) {
+    for (uint32_t v = blockIdx.x; v < nt; v += gridDim.x) {
+        const uint32_t w = xcd_tile(v, nt);
         const TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
         uint32_t c_idx[kTileItems], c_aux[kTileItems];
         unsigned long long c_key[kTileItems];
