@@ -379,7 +379,7 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
 // level 1 only) staged global buckets.  It bounds the workgroups per CU.
 size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true) {
     const size_t nd = (size_t)1 << dbits;
-    size_t words = 3 * nd + kBlock + 1 + tile;
+    size_t words = 3 * nd + scatter_threads((int)tile) / 64 + 1 + tile;
     words += words & 1;  // 8-byte alignment of the key stage
     return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (buckets ? (size_t)tile * 4 : 0);
 }
@@ -395,10 +395,10 @@ size_t resolve_lds_bytes(uint32_t cap) {
 // Workgroups of a persistent kernel: as many as can be resident at once
 // (occupancy query for its LDS size), never more than the work units.
 template <typename Kern>
-uint32_t persistent_blocks(const gesmc_ctx *c, Kern kern, size_t lds, uint64_t units) {
+uint32_t persistent_blocks(const gesmc_ctx *c, Kern kern, size_t lds, uint64_t units, int threads = kBlock) {
     if (c->persist_mult == 0) return (uint32_t)std::max<uint64_t>(1, units);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds) != hipSuccess || per_cu < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;
     }
@@ -458,8 +458,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const int lvl1_out = p.b2 > 0 ? mid : dst;
     const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch);
     const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch);
-    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile>, lds1, p.ntiles1)), dim3(kBlock), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
+    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile)>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile)>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err,
                      ba1));
     if (p.b2 == 0) {
@@ -478,8 +478,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
                      c->tile_first, c->counts2, ba2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
-    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile>, lds2, tiles2)), dim3(kBlock), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile, scatter_threads(kTile)>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile, scatter_threads(kTile)>, lds2, tiles2, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
                      p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
     *bucket_off = c->fine_off;
@@ -1243,16 +1243,16 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sort_lds_bytes(kLdsCap));
-    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileSmall>, (const void *)k_scatter<kSrcHash, kTileSmall>,
-                          (const void *)k_scatter<kSrcBatch, kTileSmall>,
-                          (const void *)k_scatter<kSrcBucket, kTileSmall>, (const void *)k_scatter<kSrcEmit, kTileSmall>,
-                          (const void *)k_scatter<kSrcHashed, kTileSmall>})
+    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileSmall, scatter_threads(kTileSmall)>, (const void *)k_scatter<kSrcHash, kTileSmall, scatter_threads(kTileSmall)>,
+                          (const void *)k_scatter<kSrcBatch, kTileSmall, scatter_threads(kTileSmall)>,
+                          (const void *)k_scatter<kSrcBucket, kTileSmall, scatter_threads(kTileSmall)>, (const void *)k_scatter<kSrcEmit, kTileSmall, scatter_threads(kTileSmall)>,
+                          (const void *)k_scatter<kSrcHashed, kTileSmall, scatter_threads(kTileSmall)>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(12, kTileSmall));
-    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileLarge>, (const void *)k_scatter<kSrcHash, kTileLarge>,
-                          (const void *)k_scatter<kSrcBatch, kTileLarge>,
-                          (const void *)k_scatter<kSrcBucket, kTileLarge>, (const void *)k_scatter<kSrcEmit, kTileLarge>,
-                          (const void *)k_scatter<kSrcHashed, kTileLarge>})
+    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileLarge, scatter_threads(kTileLarge)>, (const void *)k_scatter<kSrcHash, kTileLarge, scatter_threads(kTileLarge)>,
+                          (const void *)k_scatter<kSrcBatch, kTileLarge, scatter_threads(kTileLarge)>,
+                          (const void *)k_scatter<kSrcBucket, kTileLarge, scatter_threads(kTileLarge)>, (const void *)k_scatter<kSrcEmit, kTileLarge, scatter_threads(kTileLarge)>,
+                          (const void *)k_scatter<kSrcHashed, kTileLarge, scatter_threads(kTileLarge)>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(12, kTileLarge));
     (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -22,7 +22,10 @@ namespace gesmc {
 // least 2^25 records, where the longer runs per digit of the second level
 // pay off; on smaller passes the larger tile leaves CUs idle.
 constexpr int kTileSmall = 2048, kTileLarge = 4096;
-constexpr uint32_t kLargeTileRecords = 1u << 25;
+#ifndef GESMC_LARGE_TILE_RECORDS
+#define GESMC_LARGE_TILE_RECORDS (1u << 25)
+#endif
+constexpr uint32_t kLargeTileRecords = GESMC_LARGE_TILE_RECORDS;
 constexpr uint32_t kMaxCoarseBits = 10;  // digit bits of the first radix level
 #ifndef GESMC_CELL_BITS
 #define GESMC_CELL_BITS 8
@@ -32,6 +35,18 @@ constexpr int kCellBits = GESMC_CELL_BITS;   // LDS counting-sort cells per buck
 #define GESMC_LDS_ITEMS 6
 #endif
 constexpr int kSortMaxItems = GESMC_LDS_ITEMS;  // records per thread held in LDS
+// Threads of a scatter workgroup per tile size: the large tile's LDS stage
+// (~60 KB) allows two workgroups per CU, so it takes 512 threads to keep
+// enough waves in flight; the small tile fits more workgroups at 256.
+#ifndef GESMC_SCATTER_THREADS_LARGE
+#define GESMC_SCATTER_THREADS_LARGE 512
+#endif
+#ifndef GESMC_SCATTER_THREADS_SMALL
+#define GESMC_SCATTER_THREADS_SMALL 256
+#endif
+constexpr int scatter_threads(int tile) {
+    return tile >= kTileLarge ? GESMC_SCATTER_THREADS_LARGE : GESMC_SCATTER_THREADS_SMALL;
+}
 constexpr uint32_t kLdsCap = kSortMaxItems * kBlock;  // records of one bucket sorted in LDS
 static_assert((1 << kCellBits) >= kBlock, "every thread owns at least one cell");
 
@@ -68,18 +83,20 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t x, uint32_t *ws
     return before + incl - x;
 }
 
-// Workgroup-wide exclusive scan (in place) of n values in LDS; each thread
-// owns a contiguous run of ceil(n / kBlock).  `tmp` needs kBlock + 1 words.
+// Workgroup-wide exclusive scan (in place) of n values in LDS over NT
+// threads; each owns a contiguous run of ceil(n / NT).  `tmp` needs NT / 64 + 1
+// words.
 // Returns the total.
+template <int NT = kBlock>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *tmp) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t per = (n + kBlock - 1) / kBlock;
+    const uint32_t per = (n + NT - 1) / NT;
     const uint32_t b = min(tid * per, n);
     const uint32_t e = min(b + per, n);
     uint32_t s = 0;
     for (uint32_t q = b; q < e; ++q) s += v[q];
     uint32_t total;
-    uint32_t acc = block_exclusive_sum<kBlock>(s, tmp, &total);
+    uint32_t acc = block_exclusive_sum<NT>(s, tmp, &total);
     for (uint32_t q = b; q < e; ++q) {
         const uint32_t x = v[q];
         v[q] = acc;
@@ -213,14 +230,14 @@ __device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, cons
 // kSrcEmit tiles: each thread takes whole switches, so the four slots of a
 // switch are items 4j .. 4j+3 of one thread (slot order inside a tile does
 // not matter: partitions are sorted later).
-template <int kTileItems>
+template <int kTileItems, int kThreads>
 __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const uint32_t *si,
                                           const unsigned long long *sk, uint32_t t, uint32_t k0, uint32_t k1,
                                           const SrcArgs &sa, uint32_t *tag, unsigned long long *key) {
     const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < kTileItems / 4; ++j) {
-        const uint32_t sl = 4 * (tid + j * kBlock);  // first local slot of this thread's switch
+        const uint32_t sl = 4 * (tid + j * kThreads);  // first local slot of this thread's switch
         Tuple tp[4] = {{0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}};
         if (sl < cnt) emit_switch((begin + sl) >> 2, si, sk, t, k0, k1, sa, tp);
 #pragma unroll
@@ -308,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         uint32_t cur_i[kTileItems], cur_a[kTileItems];
         unsigned long long cur_k[kTileItems];
         if (kSrc == kSrcEmit) {
-            emit_tile<kTileItems>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, cur_i, cur_k);
+            emit_tile<kTileItems, kBlock>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, cur_i, cur_k);
         } else {
 #pragma unroll
             for (int q = 0; q < kTileItems; ++q) {
@@ -452,11 +469,11 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
 // the run base offs[w][d].  With a tuple source, slots whose key is empty
 // are dropped; with kSrcBatch the record's global bucket is written to
 // ba.aux_out beside it.  One workgroup per tile (grid-stride if the grid is
-// smaller).  Dynamic LDS: 3 * 2^dbits + kBlock + 1 words of counters, then
+// smaller).  Dynamic LDS: 3 * 2^dbits + kThreads / 64 + 1 words of counters, then
 // the staged records (scatter_lds_bytes on the host).
 
-template <int kSrc, int kTile>
-__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ src_idx,
+template <int kSrc, int kTile, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
                                                     uint32_t *__restrict__ dst_idx,
                                                     unsigned long long *__restrict__ dst_key, uint32_t t, uint32_t k0,
@@ -467,15 +484,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     SrcArgs ba) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_total;
-    constexpr int kTileItems = kTile / kBlock;
+    constexpr int kTileItems = kTile / kThreads;
+    constexpr uint32_t kScanWords = kThreads / 64 + 1;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
     uint32_t *base = start + nd;         // nd (global run base)
-    uint32_t *tmp = base + nd;           // kBlock + 1
-    uint32_t *s_idx = tmp + kBlock + 1;  // kTile
+    uint32_t *tmp = base + nd;           // kThreads / 64 + 1
+    uint32_t *s_idx = tmp + kScanWords;  // kTile
     unsigned long long *s_key =
-        reinterpret_cast<unsigned long long *>(s_idx + kTile + ((kBlock + 1 + 3 * nd + kTile) & 1));
+        reinterpret_cast<unsigned long long *>(s_idx + kTile + ((kScanWords + 3 * nd + kTile) & 1));
     uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kTile);
     uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kTile);  // kSrcBatch only
 
@@ -487,11 +505,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         uint32_t c_idx[kTileItems], c_aux[kTileItems];
         unsigned long long c_key[kTileItems];
         if (kSrc == kSrcEmit) {
-            emit_tile<kTileItems>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, c_idx, c_key);
+            emit_tile<kTileItems, kThreads>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, c_idx, c_key);
         } else {
 #pragma unroll
             for (int q = 0; q < kTileItems; ++q) {
-                const uint32_t p = tid + q * kBlock;
+                const uint32_t p = tid + q * kThreads;
                 const bool in = p < ts.cnt;
                 c_idx[q] = in ? src_idx[ts.begin + p] : 0u;
                 c_key[q] = in ? src_key[ts.begin + p] : kEmptyKey;
@@ -499,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                 c_aux[q] = (src_reads_aux<kSrc>() && in) ? ba.aux_in[ts.begin + p] : 0u;
             }
         }
-        for (uint32_t d = tid; d < nd; d += kBlock) {
+        for (uint32_t d = tid; d < nd; d += kThreads) {
             cnt[d] = 0;
             base[d] = offs[(size_t)w * nd + d];
         }
@@ -508,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         uint32_t r_dig[kTileItems], r_rank[kTileItems], r_bkt[kTileItems];
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
-            const uint32_t p = tid + q * kBlock;
+            const uint32_t p = tid + q * kThreads;
             r_dig[q] = 0xFFFFFFFFu;
             r_bkt[q] = 0;
             if ((kSrc == kSrcEmit || p < ts.cnt) && (!src_is_tuple<kSrc>() || c_key[q] != kEmptyKey)) {
@@ -518,9 +536,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
             }
         }
         lds_barrier();
-        for (uint32_t d = tid; d < nd; d += kBlock) start[d] = cnt[d];
+        for (uint32_t d = tid; d < nd; d += kThreads) start[d] = cnt[d];
         lds_barrier();
-        block_exclusive_scan(start, nd, tmp);
+        block_exclusive_scan<kThreads>(start, nd, tmp);
         uint32_t mine = 0;
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
@@ -536,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
         if (mine) atomicAdd(&s_total, mine);
         lds_barrier();
         const uint32_t staged = s_total;
-        for (uint32_t lp = tid; lp < staged; lp += kBlock) {
+        for (uint32_t lp = tid; lp < staged; lp += kThreads) {
             const uint32_t d = s_dig[lp];
             const uint32_t g = base[d] + (lp - start[d]);
             if (g >= ts.seg_begin && g < ts.seg_end) {
