@@ -192,9 +192,10 @@ __global__ __launch_bounds__(kBlock) void k_extract(const uint32_t *__restrict__
 // tuples grouped by tuple hash, the rounds of decisions of Alg. 1 and the
 // writes -- with the same definitions as the multi-kernel path, so the result
 // is the same chain.  The records stay in LDS across supersteps.  Two sizes:
-// m <= 1024 with 256 threads (36 KB of LDS, several workgroups per CU) and
-// m <= 4096 with 1024 threads (146 KB, one per CU); in both each thread holds
-// 4 permutation items, 2 switches (9 tuples) and owns one sort cell.
+// m <= 1024 with 256 threads (39 KB of LDS, several workgroups per CU) and
+// m <= 4096 with 1024 threads (158 KB, one per CU); in both each thread holds
+// 4 permutation items and 2 switches (9 tuples), and there are four sort
+// cells per thread.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSmallMax = 1024, kSmallThreads = 256;  // edges, threads
 constexpr uint32_t kMidMax = 4096, kMidThreads = 1024;
@@ -209,7 +210,7 @@ struct SmallLds {
     uint32_t info[kMax];              // per target 2k+h: eraser << 16 | predecessor
     uint16_t pi[kMax];                // the permutation of this superstep
     uint16_t sT[2 * kMax];            // sorted local index, then sorted tuple tag
-    uint32_t cell[kThreads + 1];      // one sort cell per thread
+    uint32_t cell[4 * kThreads + 1];  // sort cells, four per thread
     uint32_t tmp[kThreads / 64 + 2];
     uint8_t st[kMax / 2];
     uint32_t undecided, flags;
@@ -219,8 +220,8 @@ static_assert(kMidMax / 2 < kSmTagStays && 2 * kMidMax <= 0x10000, "small-graph 
 static_assert(kSmallMax == 4 * kSmallThreads && kMidMax == 4 * kMidThreads, "4 edges per thread");
 
 template <uint32_t kThreads>
-constexpr int small_cell_bits() {
-    return kThreads == 256 ? 8 : kThreads == 512 ? 9 : 10;
+constexpr int small_cell_bits() {  // 4 kThreads cells
+    return kThreads == 256 ? 10 : kThreads == 512 ? 11 : 12;
 }
 
 // Groups up to 2 kMax items by the top cell bits of their word: they sit in
@@ -232,8 +233,9 @@ template <int kPer, uint32_t kMax, uint32_t kThreads>
 __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads> &L, const unsigned long long *w,
                                             const uint16_t *g, const bool *present, uint32_t *cl, uint32_t *slot) {
     constexpr int kShift = 64 - small_cell_bits<kThreads>();
+    constexpr uint32_t kCells = 4 * kThreads;
     const uint32_t tid = threadIdx.x;
-    L.cell[tid] = 0;
+    for (uint32_t c = tid; c < kCells; c += kThreads) L.cell[c] = 0;
     __syncthreads();
     uint32_t rank[kPer];
 #pragma unroll
@@ -243,10 +245,8 @@ __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads> &L, const u
         rank[q] = atomicAdd(&L.cell[cl[q]], 1u);
     }
     __syncthreads();
-    uint32_t total;
-    const uint32_t base = block_exclusive_sum<kThreads>(L.cell[tid], L.tmp, &total);
-    L.cell[tid] = base;
-    if (tid == 0) L.cell[kThreads] = total;
+    const uint32_t total = block_exclusive_scan<kThreads>(L.cell, kCells, L.tmp);
+    if (tid == 0) L.cell[kCells] = total;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {

@@ -8,9 +8,10 @@
 //               run bases from per-tile digit counts and a column scan
 //   level 2   : sub digit    = next b2 bits, scattered inside each coarse
 //               bucket (its region is small enough to stay L2/MALL resident)
-//   bucket    : each fine bucket (~400-770 records) is counting-sorted in
-//               LDS on the next kCellBits bits of K, then the records of a
-//               cell are settled by insertion sort on (K, i).
+//   bucket    : each fine bucket (~400-1500 records) is counting-sorted in
+//               LDS on the next kCellBits bits of K (about one record per
+//               cell), then each record's place in its cell is the number of
+//               smaller (K, i) keys there.
 // Keys are never stored: every pass recomputes K_i from the record's index.
 #pragma once
 
@@ -28,9 +29,12 @@ constexpr int kTileSmall = 2048, kTileLarge = 4096;
 constexpr uint32_t kLargeTileRecords = GESMC_LARGE_TILE_RECORDS;
 constexpr uint32_t kMaxCoarseBits = 10;  // digit bits of the first radix level
 #ifndef GESMC_CELL_BITS
-#define GESMC_CELL_BITS 8
+#define GESMC_CELL_BITS 10
 #endif
-constexpr int kCellBits = GESMC_CELL_BITS;   // LDS counting-sort cells per bucket / partition = 2^bits
+// LDS counting-sort cells per bucket / partition = 2^bits.  Records then
+// read their whole cell, so the wave's cost follows its largest cell: 1024
+// cells (about one record each) beat 256 by ~15%; 2048 lose LDS occupancy.
+constexpr int kCellBits = GESMC_CELL_BITS;
 #ifndef GESMC_LDS_ITEMS
 #define GESMC_LDS_ITEMS 6
 #endif
@@ -570,9 +574,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
 }
 
 // Sorts each fine bucket by (K, i): LDS counting sort on the kCellBits
-// bits of K below the B bucket bits, then insertion sort inside each cell.
-// One workgroup per bucket (grid-stride if the grid is smaller).  Buckets
-// larger than `cap` (not expected: the mean is cap / 2 and sizes are
+// bits of K below the B bucket bits, then ranks within each cell.  One
+// workgroup per bucket (grid-stride if the grid is smaller).  Buckets larger
+// than `cap` (not expected: the default mean is 3/4 of cap and sizes are
 // binomial) take a slow exact path that ranks every record against the whole
 // bucket.  Dynamic LDS: 2^kCellBits cell counters + kBlock + 2 scan words
 // + cap * 20 bytes.
