@@ -170,6 +170,10 @@ struct gesmc_ctx {
     uint64_t prof_launch[KID_COUNT] = {0};
     uint64_t prof_items[KID_COUNT] = {0};
     hipEvent_t call_a = nullptr, call_b = nullptr;
+    // side streams of the batch's LDS small-graph kernels (default priority),
+    // forked from and joined back into the call's stream with these events
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -1030,15 +1034,32 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                              (const unsigned long long *)c->key[0], npos, c->tu_tag[0], c->tu_key[0]));
             GESMC_TRY(partition_and_resolve(c, s, npos, ERR_DUP, ge_all));
         }
-        // small graphs: every superstep of each in one workgroup, in LDS
+        // small graphs: every superstep of each in one workgroup, in LDS.  Each
+        // size class runs on a side stream beside the multi-kernel supersteps
+        // of the other graphs (their records, counts and error words are
+        // disjoint) and is joined back before the unpermute.  A lone class
+        // with nothing beside it stays on the call's stream.
+        const bool fork = (nsm1 > 0) + (nsm2 > 0) + (nactive > 0) > 1;
+        if (fork) GESMC_TRY(check_hip(hipEventRecord(c->fork_ev, s), "hipEventRecord"));
+        hipStream_t s1 = s, s2 = s;
+        if (fork && nsm1) {
+            s1 = c->side[0];
+            GESMC_TRY(check_hip(hipStreamWaitEvent(s1, c->fork_ev, 0), "hipStreamWaitEvent"));
+        }
+        if (fork && nsm2) {
+            s2 = c->side[1];
+            GESMC_TRY(check_hip(hipStreamWaitEvent(s2, c->fork_ev, 0), "hipStreamWaitEvent"));
+        }
         if (nsm1)
-            GESMC_TRY(launch(c, s, KID_SMALL, nsm1, k_small_chain<kSmallMax, kSmallThreads>, dim3(nsm1),
+            GESMC_TRY(launch(c, s1, KID_SMALL, nsm1, k_small_chain<kSmallMax, kSmallThreads>, dim3(nsm1),
                              dim3(kSmallThreads), 0, (const uint32_t *)c->small_list, (const BatchGraph *)c->gr,
                              (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
         if (nsm2)
-            GESMC_TRY(launch(c, s, KID_SMALL_MID, nsm2, k_small_chain<kMidMax, kMidThreads>, dim3(nsm2),
+            GESMC_TRY(launch(c, s2, KID_SMALL_MID, nsm2, k_small_chain<kMidMax, kMidThreads>, dim3(nsm2),
                              dim3(kMidThreads), 0, (const uint32_t *)c->small_list + nsm1, (const BatchGraph *)c->gr,
                              (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
+        if (s1 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[0], s1), "hipEventRecord"));
+        if (s2 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[1], s2), "hipEventRecord"));
         // superstep s switches the ranks [0, active_s): those with r > s
         uint32_t qa = nactive;
         for (uint32_t st = 0; st < rmax; ++st) {
@@ -1050,6 +1071,8 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             c->ctr_step = c->ctr + st;
             GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
         }
+        if (s1 != s) GESMC_TRY(check_hip(hipStreamWaitEvent(s, c->join_ev[0], 0), "hipStreamWaitEvent"));
+        if (s2 != s) GESMC_TRY(check_hip(hipStreamWaitEvent(s, c->join_ev[1], 0), "hipStreamWaitEvent"));
         if (total_m > 0)
             GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_unpermute_batch, dim3(grid_stride_blocks(c, npos)), dim3(kBlock),
                              0, (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0],
@@ -1261,6 +1284,11 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
         hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->call_a) != hipSuccess || hipEventCreate(&c->call_b) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side[1], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev[1], hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         set_error("context initialisation failed");
@@ -1290,6 +1318,10 @@ void gesmc_destroy(gesmc_ctx *c) {
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->call_a) (void)hipEventDestroy(c->call_a);
     if (c->call_b) (void)hipEventDestroy(c->call_b);
+    for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1]})
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t q : c->side)
+        if (q) (void)hipStreamDestroy(q);
     delete c;
 }
 
