@@ -177,8 +177,10 @@ typedef struct gesmc_server_info {
     uint64_t submitted, completed, iterations, attempts, legal;
     uint64_t resident_edges;
     uint32_t queued, resident;
-    double busy_s; /* wall time of the worker's iterations */
-    double now_s;  /* the server clock                      */
+    double busy_s; /* wall time of the worker's iterations             */
+    double now_s;  /* the server clock                                  */
+    double copy_s; /* of busy_s: host copies of edges in and results out */
+    double wait_s; /* of busy_s: waiting for the device                  */
 } gesmc_server_info;
 
 /* Starts the worker (cfg nullable: defaults).  Fails with GESMC_E_NOMEM if

@@ -78,7 +78,7 @@ class ServerInfo(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
                 ("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("resident_edges", ctypes.c_uint64),
                 ("queued", ctypes.c_uint32), ("resident", ctypes.c_uint32), ("busy_s", ctypes.c_double),
-                ("now_s", ctypes.c_double)]
+                ("now_s", ctypes.c_double), ("copy_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -10,14 +10,22 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <memory>
 #include <deque>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
 
+#include "copy_pool.h"
+
 namespace {
 
 constexpr uint64_t kServeBytesPerEdge = 136;  // context buffers per resident record (see ensure_capacity)
+// Supersteps per iteration (one host round trip): never beyond the next
+// completion; at most kServeBurstIdle while no request waits, so arrivals
+// are admitted within that many supersteps, and up to kServeBurstMax while
+// the queue is blocked (nothing can be admitted before a completion).
+constexpr uint32_t kServeBurstIdle = 4, kServeBurstMax = 64;
 
 struct ServeReq {
     uint64_t ticket = 0;
@@ -58,7 +66,8 @@ struct gesmc_server {
     // info (under mu)
     uint64_t submitted = 0, completed = 0, iterations = 0, attempts = 0, legal = 0, resident_edges = 0;
     uint32_t resident_count = 0;
-    double busy_s = 0;
+    double busy_s = 0, copy_s = 0, wait_s = 0;  // under mu
+    double w_copy = 0, w_wait = 0;              // the worker's, folded into the above under mu
     // worker-side staging
     std::vector<BatchGraph> h_gr;
     std::vector<uint2> h_mv;
@@ -71,6 +80,8 @@ struct gesmc_server {
     uint64_t *d_stage_off = nullptr;
     uint32_t *d_stage_rank = nullptr;
     unsigned long long *d_rb = nullptr;
+    std::unique_ptr<gesmc::CopyPool> copier;  // worker only
+    std::vector<gesmc::CopyPool::Seg> segs;
 };
 
 namespace {
@@ -137,7 +148,7 @@ gesmc_status serve_pin(gesmc_server *S, uint64_t words) {
 // One iteration on the worker: new layout (survivors + admitted), one
 // superstep of every resident graph, results of the graphs that finish.
 gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, const std::vector<ServeReq *> &admit,
-                             bool relayout, std::vector<ServeReq *> &finishing) {
+                             bool relayout, uint32_t k, std::vector<ServeReq *> &finishing) {
     gesmc_ctx *c = S->c;
     hipStream_t s = S->s;
     const uint32_t nsurv = (uint32_t)next.size();
@@ -187,7 +198,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     S->h_rb.assign(G, ~0ull);
     uint64_t rpos = 0;
     for (uint32_t q = 0; q < G; ++q) {
-        if (ranks[q]->done + 1 == ranks[q]->r) {
+        if (ranks[q]->done + k == ranks[q]->r) {
             S->h_rb[q] = rpos;
             rpos += ranks[q]->m;
             finishing.push_back(ranks[q]);
@@ -203,8 +214,9 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, S->h_gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+    GESMC_TRY(ensure_counters(c, k));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
-                     (uint64_t)(sizeof(StepCounters) / 4)));
+                     (uint64_t)k * (sizeof(StepCounters) / 4)));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
                      (uint64_t)G * 8));
@@ -223,8 +235,12 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
             // raw edges of the admitted requests -> pinned staging -> one copy to the
             // device staging area (tuple key buffer 1), then load
             unsigned long long *stg = c->tu_key[1];
+            const auto c0 = std::chrono::steady_clock::now();
+            S->segs.clear();
             for (size_t j = 0; j < admit.size(); ++j)
-                if (admit[j]->m) memcpy(S->h_pin + S->h_stage_off[j], admit[j]->edges.data(), admit[j]->m * 8);
+                if (admit[j]->m) S->segs.push_back({S->h_pin + S->h_stage_off[j], admit[j]->edges.data(), admit[j]->m * 8});
+            S->copier->copy(S->segs);
+            S->w_copy += seconds_since(c0);
             if (stage)
                 GESMC_TRY(check_hip(hipMemcpyAsync(stg, S->h_pin, stage * 8, hipMemcpyHostToDevice, s),
                                     "hipMemcpyAsync"));
@@ -245,11 +261,14 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         std::swap(c->key[0], c->key[1]);
         ++g_alloc_epoch;  // buffer roles moved: no captured graph may be replayed
     }
-    // one superstep of every resident graph (each at its own superstep t0 + done)
+    // k supersteps of every resident graph (each at its own superstep t0 + done + step);
+    // k never exceeds the remaining supersteps of any of them
     const Plan p = batch_plan(c, npos, bbase);
-    BatchStep bs{c->gr, G, 0u, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
-    c->ctr_step = c->ctr;
-    GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
+    for (uint32_t st = 0; st < k; ++st) {
+        BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
+        c->ctr_step = c->ctr + st;
+        GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
+    }
     // results of the graphs finishing now (discarded after the sync if flagged)
     unsigned long long *res = c->tu_key[2];
     if (!finishing.empty()) {
@@ -261,18 +280,24 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         GESMC_TRY(check_hip(hipMemcpyAsync(S->h_pin, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, k * sizeof(StepCounters), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, G * 32ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, G * 4ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    const auto w0 = std::chrono::steady_clock::now();
     GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    const auto c0 = std::chrono::steady_clock::now();
+    S->w_wait += std::chrono::duration<double>(c0 - w0).count();
+    S->segs.clear();
     for (uint32_t q = 0; q < G; ++q) {
         if (S->h_rb[q] == ~0ull) continue;
         ServeReq *R = ranks[q];
         R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
         if (!R->result) return GESMC_E_NOMEM;
-        memcpy(R->result, S->h_pin + S->h_rb[q], R->m * 8);
+        S->segs.push_back({R->result, S->h_pin + S->h_rb[q], R->m * 8});
     }
+    S->copier->copy(S->segs);
+    S->w_copy += seconds_since(c0);
     next = ranks;
     return GESMC_OK;
 }
@@ -282,6 +307,7 @@ void serve_loop(gesmc_server *S) {
     (void)hipSetDevice(c->device);
     std::vector<ServeReq *> admit, trivial, next, finishing;
     bool dirty = true;  // the layout in buffer 0 differs from `resident`
+    uint32_t burst = 1;
     for (;;) {
         admit.clear();
         trivial.clear();
@@ -328,6 +354,10 @@ void serve_loop(gesmc_server *S) {
             }
             S->resident_edges = edges;
             S->resident_count = (uint32_t)(next.size() + admit.size());
+            uint32_t rem = kServeBurstMax;
+            for (ServeReq *R : next) rem = std::min(rem, R->r - R->done);
+            for (ServeReq *R : admit) rem = std::min(rem, R->r - R->done);
+            burst = std::max(1u, std::min(rem, S->queue.empty() ? kServeBurstIdle : kServeBurstMax));
         }
         for (ServeReq *R : trivial) {
             const gesmc_status st = serve_trivial(R);
@@ -342,9 +372,12 @@ void serve_loop(gesmc_server *S) {
         }
         const auto it0 = std::chrono::steady_clock::now();
         const bool relayout = dirty || !admit.empty();
-        gesmc_status st = serve_iteration(S, next, admit, relayout, finishing);
+        gesmc_status st = serve_iteration(S, next, admit, relayout, burst, finishing);
         std::lock_guard<std::mutex> lk(S->mu);
         S->busy_s += seconds_since(it0);
+        S->copy_s += S->w_copy;
+        S->wait_s += S->w_wait;
+        S->w_copy = S->w_wait = 0;
         if (st == GESMC_OK && c->h_err[0] != 0) {
             set_error("internal consistency check failed (error bits 0x%x)", c->h_err[0]);
             st = GESMC_E_INTERNAL;
@@ -363,23 +396,28 @@ void serve_loop(gesmc_server *S) {
         ++S->iterations;
         std::vector<ServeReq *> keep;
         dirty = false;
-        const StepCounters &h = c->h_ctr[0];
+        uint64_t rounds = 0, rounds_max = 0;
+        for (uint32_t st = 0; st < burst; ++st) {
+            rounds += c->h_ctr[st].rounds;
+            rounds_max = std::max<uint64_t>(rounds_max, c->h_ctr[st].rounds);
+        }
         for (uint32_t q = 0; q < (uint32_t)next.size(); ++q) {
             ServeReq *R = next[q];
             gesmc_stats &o = R->stats;
-            o.attempts += R->m / 2;
+            const bool first = R->done == 0;
+            o.attempts += (uint64_t)burst * (R->m / 2);
             o.legal += c->h_gacc[4 * (size_t)q + 0];
             o.rej_loop += c->h_gacc[4 * (size_t)q + 1];
             o.rej_exists += c->h_gacc[4 * (size_t)q + 2];
             o.rej_pl += c->h_gacc[4 * (size_t)q + 3];
-            o.rounds_sum += h.rounds;
-            o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)h.rounds);
-            S->attempts += R->m / 2;
+            o.rounds_sum += rounds;
+            o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)rounds_max);
+            S->attempts += (uint64_t)burst * (R->m / 2);
             S->legal += c->h_gacc[4 * (size_t)q + 0];
-            ++R->done;
+            R->done += burst;
             const uint32_t ge = c->h_gerr[q];
             if (ge) {
-                serve_finish_locked(S, R, R->done == 1 ? serve_map_gerr(ge) : GESMC_E_INTERNAL);
+                serve_finish_locked(S, R, first ? serve_map_gerr(ge) : GESMC_E_INTERNAL);
                 dirty = true;
             } else if (R->done == R->r) {
                 o.supersteps = R->r;
@@ -424,7 +462,7 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
     }
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     GESMC_TRY(ensure_capacity(c, cap_edges + 64));
-    GESMC_TRY(ensure_counters(c, 1));
+    GESMC_TRY(ensure_counters(c, kServeBurstMax));
     GESMC_TRY(ensure_batch(c, max_graphs, cap_edges + 64));
     gesmc_server *S = new gesmc_server();
     S->c = c;
@@ -441,6 +479,15 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
         (void)hipGetLastError();
         set_error("hipStreamCreate failed");
         st = GESMC_E_DEVICE;
+    }
+    if (st == GESMC_OK) {
+        try {  // 7 copy threads beside the worker (the copies are memory-bound)
+            const unsigned hc = std::max(2u, std::thread::hardware_concurrency());
+            S->copier.reset(new gesmc::CopyPool(std::min(7u, hc - 1)));
+        } catch (...) {
+            set_error("cannot start the copy threads");
+            st = GESMC_E_NOMEM;
+        }
     }
     if (st != GESMC_OK) {
         gesmc_server_destroy(S);
@@ -608,6 +655,8 @@ gesmc_status gesmc_server_info_get(gesmc_server *S, gesmc_server_info *out) {
     out->queued = (uint32_t)S->queue.size();
     out->resident = S->resident_count;
     out->busy_s = S->busy_s;
+    out->copy_s = S->copy_s;
+    out->wait_s = S->wait_s;
     out->now_s = seconds_since(S->t0);
     return GESMC_OK;
 }

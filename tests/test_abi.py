@@ -76,7 +76,7 @@ int main(void) {
     S(gesmc_result) F(gesmc_result, m) F(gesmc_result, edges) F(gesmc_result, stats) F(gesmc_result, t_submit)
     F(gesmc_result, t_done)
     S(gesmc_server_info) F(gesmc_server_info, resident_edges) F(gesmc_server_info, queued)
-    F(gesmc_server_info, resident) F(gesmc_server_info, busy_s) F(gesmc_server_info, now_s)
+    F(gesmc_server_info, resident) F(gesmc_server_info, busy_s) F(gesmc_server_info, now_s) F(gesmc_server_info, copy_s) F(gesmc_server_info, wait_s)
     S(gesmc_tuning) F(gesmc_tuning, fuse_emit) F(gesmc_tuning, candidates) F(gesmc_tuning, best_ms)
     F(gesmc_tuning, default_ms)
     return 0;
