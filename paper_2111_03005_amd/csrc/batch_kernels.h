@@ -65,11 +65,16 @@ __global__ __launch_bounds__(kBlock) void k_load_batch(const unsigned long long 
 }
 
 // pg[p] = rank of the graph whose segment holds position p (p < total).
-__global__ __launch_bounds__(kBlock) void k_fill_pg(const BatchGraph *__restrict__ gr, uint32_t ngraphs,
-                                                    uint32_t total, uint32_t *__restrict__ pg) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride)
-        pg[p] = upper_index(ngraphs, p, [&](uint32_t x) { return (uint64_t)gr[x].poff; });
+// Position chunks {rank q, first position, end position, aux}: at most
+// kChunkPos positions of one rank's segment each, listed on the host, so a
+// workgroup knows its graph without a search.
+constexpr uint32_t kChunkPos = 8192;
+
+// pg[p] = rank owning position p, one workgroup per chunk (the chunks of all
+// ranks cover every position).
+__global__ __launch_bounds__(kBlock) void k_fill_pg(const uint4 *__restrict__ ch, uint32_t *__restrict__ pg) {
+    const uint4 c = ch[blockIdx.x];
+    for (uint32_t p = c.y + threadIdx.x; p < c.z; p += kBlock) pg[p] = c.x;
 }
 
 // Outcomes of one superstep per graph: acc[4q .. 4q+3] += legal, loop,
@@ -85,6 +90,7 @@ constexpr uint32_t kStatsBins = 64;
 __global__ __launch_bounds__(kBlock) void k_graph_stats(const uint8_t *__restrict__ st,
                                                         const BatchGraph *__restrict__ gr, uint32_t ngraphs,
                                                         uint32_t ell, unsigned long long *__restrict__ acc) {
+    static_assert(kStatsPerThread == 16, "one 16-byte load of statuses per thread");
     __shared__ uint32_t bins[kStatsBins * 4];
     __shared__ uint32_t s_q0;
     const uint32_t tid = threadIdx.x;
@@ -96,22 +102,45 @@ __global__ __launch_bounds__(kBlock) void k_graph_stats(const uint8_t *__restric
     const uint32_t q0 = s_q0;
     const uint32_t k0 = kb + tid * kStatsPerThread;
     const uint32_t k1 = min(k0 + kStatsPerThread, ell);
+    // counts of the run of switches of one graph, kept in registers and
+    // flushed when the graph changes (a thread's 16 switches rarely span two)
+    uint32_t cnt[4] = {0, 0, 0, 0};
+    auto flush = [&](uint32_t q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!cnt[j]) continue;
+            if (q - q0 < kStatsBins)
+                atomicAdd(&bins[(q - q0) * 4 + j], cnt[j]);
+            else
+                atomicAdd(&acc[4 * (size_t)q + j], (unsigned long long)cnt[j]);
+            cnt[j] = 0;
+        }
+    };
     if (k0 < k1) {
+        uint8_t sv[kStatsPerThread];
+        if (k1 - k0 == kStatsPerThread) {  // k0 is a multiple of 16
+            const uint4 v = *reinterpret_cast<const uint4 *>(st + k0);
+            __builtin_memcpy(sv, &v, sizeof(v));
+        } else {
+            for (uint32_t x = 0; x < k1 - k0; ++x) sv[x] = st[k0 + x];
+        }
         uint32_t q = upper_index(ngraphs, k0, first_switch);
         uint32_t qend = (gr[q].poff + gr[q].mpad) >> 1;
-        for (uint32_t k = k0; k < k1; ++k) {
-            while (k >= qend && q + 1 < ngraphs) {
-                ++q;
-                qend = (gr[q].poff + gr[q].mpad) >> 1;
+#pragma unroll
+        for (uint32_t x = 0; x < kStatsPerThread; ++x) {
+            const uint32_t k = k0 + x;
+            if (k >= k1) break;
+            if (k >= qend) {
+                flush(q);
+                while (k >= qend && q + 1 < ngraphs) {
+                    ++q;
+                    qend = (gr[q].poff + gr[q].mpad) >> 1;
+                }
             }
-            const uint8_t sv = st[k];
-            if (sv < ST_LEGAL || sv > ST_PL) continue;
-            const uint32_t j = sv - ST_LEGAL;  // legal, loop, exists, P_L
-            if (q - q0 < kStatsBins)
-                atomicAdd(&bins[(q - q0) * 4 + j], 1u);
-            else
-                atomicAdd(&acc[4 * (size_t)q + j], 1ull);
+            const uint8_t v = sv[x];
+            if (v >= ST_LEGAL && v <= ST_PL) ++cnt[v - ST_LEGAL];  // legal, loop, exists, P_L
         }
+        flush(q);
     }
     __syncthreads();
     for (uint32_t j = tid; j < kStatsBins * 4; j += kBlock) {
@@ -140,48 +169,42 @@ __global__ __launch_bounds__(kBlock) void k_unpermute_batch(const uint32_t *__re
 
 // Serving: moves the records of the graphs that stay resident from their old
 // segments (src) into the new layout (dst), re-shifting vertex ids from the
-// old base mv[q].y to the new one.  mv[q].x = old first position, or ~0 for
-// a graph that is loaded into the new layout instead.
-__global__ __launch_bounds__(kBlock) void k_relayout(const BatchGraph *__restrict__ gr, const uint2 *__restrict__ mv,
-                                                     const uint32_t *__restrict__ pg, uint32_t total,
+// old base mv[q].y to the new one; mv[q].x = old first position.  One
+// workgroup per chunk of a staying graph.
+__global__ __launch_bounds__(kBlock) void k_relayout(const uint4 *__restrict__ ch, const BatchGraph *__restrict__ gr,
+                                                     const uint2 *__restrict__ mv,
                                                      const uint32_t *__restrict__ src_idx,
                                                      const unsigned long long *__restrict__ src_key,
                                                      uint32_t *__restrict__ dst_idx,
                                                      unsigned long long *__restrict__ dst_key) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
-        const uint32_t q = pg[p];
-        const uint2 m = mv[q];
-        if (m.x == 0xFFFFFFFFu) continue;
-        const uint32_t sp = m.x + ((uint32_t)p - gr[q].poff);
+    const uint4 c = ch[blockIdx.x];
+    const uint2 m = mv[c.x];
+    const uint32_t poff = gr[c.x].poff;
+    const uint64_t ob = m.y, nb = gr[c.x].vbase;
+    const unsigned long long shift = ((nb << 32) | nb) - ((ob << 32) | ob);  // mod 2^64
+    for (uint32_t p = c.y + threadIdx.x; p < c.z; p += kBlock) {
+        const uint32_t sp = m.x + (p - poff);
         const uint32_t i = src_idx[sp];
-        unsigned long long e = src_key[sp];
-        if (i != kPadIdx) {
-            const uint64_t ob = m.y, nb = gr[q].vbase;
-            e = e - ((ob << 32) | ob) + ((nb << 32) | nb);
-        }
+        const unsigned long long e = src_key[sp];
         dst_idx[p] = i;
-        dst_key[p] = e;
+        dst_key[p] = i != kPadIdx ? e + shift : e;
     }
 }
 
-// Serving: the records of every graph q with rb[q] != ~0 go to
-// out[rb[q] + local index] with the vertex shift removed.
-__global__ __launch_bounds__(kBlock) void k_extract(const uint32_t *__restrict__ idx,
+// Serving: the records of a finishing graph go to out[base + local index]
+// with the vertex shift removed; one workgroup per chunk of such a graph,
+// base in the chunk's aux word.
+__global__ __launch_bounds__(kBlock) void k_extract(const uint4 *__restrict__ ch, const uint32_t *__restrict__ idx,
                                                     const unsigned long long *__restrict__ key,
-                                                    const uint32_t *__restrict__ pg,
                                                     const BatchGraph *__restrict__ gr,
-                                                    const unsigned long long *__restrict__ rb, uint32_t total,
                                                     unsigned long long *__restrict__ out) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
-        const uint32_t q = pg[p];
-        const unsigned long long base = rb[q];
-        if (base == ~0ull) continue;
+    const uint4 c = ch[blockIdx.x];
+    const uint64_t vb = gr[c.x].vbase;
+    const uint32_t goff = gr[c.x].goff;
+    for (uint32_t p = c.y + threadIdx.x; p < c.z; p += kBlock) {
         const uint32_t i = idx[p];
         if (i == kPadIdx) continue;
-        const uint64_t vb = gr[q].vbase;
-        out[base + (i - gr[q].goff)] = key[p] - ((vb << 32) | vb);
+        out[(uint64_t)c.w + (i - goff)] = key[p] - ((vb << 32) | vb);
     }
 }
 

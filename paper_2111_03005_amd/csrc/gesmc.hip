@@ -145,6 +145,9 @@ struct gesmc_ctx {
     uint32_t *pg = nullptr, *bk = nullptr;
     std::vector<BatchGraph> h_gr;
     std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_rrank;
+    std::vector<uint4> h_chunks;   // position chunks of the ranks' segments (k_fill_pg, serving kernels)
+    uint4 *chunks = nullptr;
+    uint64_t chunk_cap = 0;
     uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
     bool small_graphs = true;                         // graphs with m <= kSmallMax run in LDS
     StepCounters *ctr = nullptr;
@@ -827,6 +830,28 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
 // ---------------------------------------------------------------------------
 // Batches
 // ---------------------------------------------------------------------------
+// Appends the position chunks of rank q's segment [poff, poff + len).
+void add_chunks(std::vector<uint4> &v, uint32_t q, uint32_t poff, uint32_t len, uint32_t aux = 0) {
+    for (uint32_t b = 0; b < len; b += kChunkPos)
+        v.push_back(make_uint4(q, poff + b, poff + std::min<uint32_t>(len, b + kChunkPos), aux));
+}
+
+// Copies c->h_chunks to the device (growing the buffer if needed).
+gesmc_status upload_chunks(gesmc_ctx *c, hipStream_t s) {
+    const uint64_t n = c->h_chunks.size();
+    if (n == 0) return GESMC_OK;
+    if (n > c->chunk_cap) {
+        if (c->chunks) (void)hipFree(c->chunks);
+        c->chunks = nullptr;
+        c->chunk_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(n + n / 2, 1024);
+        GESMC_TRY(dev_alloc((void **)&c->chunks, cap * sizeof(uint4)));
+        c->chunk_cap = cap;
+    }
+    return check_hip(hipMemcpyAsync(c->chunks, c->h_chunks.data(), n * sizeof(uint4), hipMemcpyHostToDevice, s),
+                     "hipMemcpyAsync");
+}
+
 gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
     if (G > c->cap_g) {
         for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc,
@@ -1004,6 +1029,10 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->rank_of, c->h_rank_of.data(), G * 4ull, hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
+    c->h_chunks.clear();
+    for (uint32_t q = 0; q < G; ++q) add_chunks(c->h_chunks, q, gr[q].poff, gr[q].mpad);
+    const uint32_t nchunks = (uint32_t)c->h_chunks.size();
+    GESMC_TRY(upload_chunks(c, s));
     // The device work of the call.  In graph mode (GESMC_OPT_GRAPH) it is captured
     // into a hipGraph on the second call of a shape and replayed afterwards: the
     // per-call data (seeds, t0, n) live in the per-graph records uploaded above,
@@ -1025,8 +1054,8 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                              (const unsigned long long *)d_in, (uint32_t)total_m, (const uint64_t *)c->in_off, G,
                              (const uint32_t *)c->rank_of, (const BatchGraph *)c->gr, c->idx[0], c->key[0], c->err,
                              bad_pos, c->gerr));
-            GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                             (const BatchGraph *)c->gr, G, npos, c->pg));
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(nchunks), dim3(kBlock), 0, (const uint4 *)c->chunks,
+                             c->pg));
         }
         if (need_validation) {
             c->ctr_step = c->ctr;
@@ -1308,7 +1337,7 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->small) (void)hipFree(c->small);
     if (c->bslot) (void)hipFree(c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
-                    (void *)c->bk, (void *)c->gerr, (void *)c->small_list, (void *)c->rrank})
+                    (void *)c->bk, (void *)c->gerr, (void *)c->small_list, (void *)c->rrank, (void *)c->chunks})
         if (q) (void)hipFree(q);
     if (c->h_gacc) (void)hipHostFree(c->h_gacc);
     if (c->h_gerr) (void)hipHostFree(c->h_gerr);

@@ -79,7 +79,6 @@ struct gesmc_server {
     uint2 *d_mv = nullptr;
     uint64_t *d_stage_off = nullptr;
     uint32_t *d_stage_rank = nullptr;
-    unsigned long long *d_rb = nullptr;
     std::unique_ptr<gesmc::CopyPool> copier;  // worker only
     std::vector<gesmc::CopyPool::Seg> segs;
 };
@@ -204,6 +203,18 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
             finishing.push_back(ranks[q]);
         }
     }
+    // position chunks: every rank (pg) and the staying ranks (relayout) if the
+    // layout is rebuilt, then the finishing ranks with their result offsets
+    c->h_chunks.clear();
+    if (relayout)
+        for (uint32_t q = 0; q < G; ++q) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad);
+    const uint32_t n_fill = (uint32_t)c->h_chunks.size();
+    if (relayout)
+        for (uint32_t q = 0; q < nsurv; ++q) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad);
+    const uint32_t n_move = (uint32_t)c->h_chunks.size() - n_fill;
+    for (uint32_t q = 0; q < G; ++q)
+        if (S->h_rb[q] != ~0ull) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad, (uint32_t)S->h_rb[q]);
+    const uint32_t n_out = (uint32_t)c->h_chunks.size() - n_fill - n_move;
     // the pinned staging holds this iteration's upload, then its results (same stream, in order);
     // it is sized before any copy is queued
     GESMC_TRY(serve_pin(S, std::max(stage, rpos)));
@@ -213,6 +224,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, S->h_gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
                         "hipMemcpyAsync"));
+    GESMC_TRY(upload_chunks(c, s));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
     GESMC_TRY(ensure_counters(c, k));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
@@ -221,13 +233,14 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->gacc,
                      (uint64_t)G * 8));
     if (relayout) {
-        GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                         (const BatchGraph *)c->gr, G, npos, c->pg));
-        if (nsurv > 0) {
+        if (n_fill)
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(n_fill), dim3(kBlock), 0, (const uint4 *)c->chunks,
+                             c->pg));
+        if (n_move) {
             GESMC_TRY(check_hip(hipMemcpyAsync(S->d_mv, S->h_mv.data(), G * sizeof(uint2), hipMemcpyHostToDevice, s),
                                 "hipMemcpyAsync"));
-            GESMC_TRY(launch(c, s, KID_MISC, 0, k_relayout, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                             (const BatchGraph *)c->gr, (const uint2 *)S->d_mv, (const uint32_t *)c->pg, npos,
+            GESMC_TRY(launch(c, s, KID_MISC, 0, k_relayout, dim3(n_move), dim3(kBlock), 0,
+                             (const uint4 *)c->chunks + n_fill, (const BatchGraph *)c->gr, (const uint2 *)S->d_mv,
                              (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], c->idx[1],
                              c->key[1]));
         }
@@ -272,11 +285,10 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     // results of the graphs finishing now (discarded after the sync if flagged)
     unsigned long long *res = c->tu_key[2];
     if (!finishing.empty()) {
-        GESMC_TRY(check_hip(hipMemcpyAsync(S->d_rb, S->h_rb.data(), G * 8ull, hipMemcpyHostToDevice, s),
-                            "hipMemcpyAsync"));
-        GESMC_TRY(launch(c, s, KID_UNPERMUTE, npos, k_extract, dim3(grid_stride_blocks(c, npos)), dim3(kBlock), 0,
-                         (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], (const uint32_t *)c->pg,
-                         (const BatchGraph *)c->gr, (const unsigned long long *)S->d_rb, npos, res));
+        if (n_out)
+            GESMC_TRY(launch(c, s, KID_UNPERMUTE, rpos, k_extract, dim3(n_out), dim3(kBlock), 0,
+                             (const uint4 *)c->chunks + n_fill + n_move, (const uint32_t *)c->idx[0],
+                             (const unsigned long long *)c->key[0], (const BatchGraph *)c->gr, res));
         GESMC_TRY(check_hip(hipMemcpyAsync(S->h_pin, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
@@ -474,7 +486,6 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_mv, max_graphs * sizeof(uint2));
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_rank, max_graphs * 4ull);
-    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_rb, max_graphs * 8ull);
     if (st == GESMC_OK && hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         set_error("hipStreamCreate failed");
@@ -520,7 +531,7 @@ void gesmc_server_destroy(gesmc_server *S) {
         (void)hipStreamSynchronize(S->s);
         (void)hipStreamDestroy(S->s);
     }
-    for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank, (void *)S->d_rb})
+    for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank})
         if (p) (void)hipFree(p);
     if (S->h_pin) (void)hipHostFree(S->h_pin);
     delete S;
