@@ -182,6 +182,7 @@ struct gesmc_ctx {
 namespace {
 
 constexpr uint32_t kMaxFineBits = 20;
+constexpr uint32_t kMaxLevelBits = 12;  // digit bits of one radix level (first <= kMaxCoarseBits)
 constexpr uint64_t kMaxEdges = 1ull << 30;
 
 void free_buffers(gesmc_ctx *c) {
@@ -340,11 +341,23 @@ struct Plan {
 
 uint32_t tile_for(uint32_t n) { return n >= kLargeTileRecords ? (uint32_t)kTileLarge : (uint32_t)kTileSmall; }
 
+// Tiles per chunk of the level-1 column scan: a power of two in [8, 256]
+// giving about 192 chunks.
+#ifndef GESMC_SCAN_ROWS
+#define GESMC_SCAN_ROWS 192
+#endif
+uint32_t scan_chunk(uint32_t ntiles) {
+    uint32_t ch = 8;
+    while (ch < 256 && ceil_div(ntiles, ch) > GESMC_SCAN_ROWS) ch <<= 1;
+    return ch;
+}
+
 // Digit bits of the first level: an even split of B (so both levels write
 // runs of similar length), or at most `cap` bits if the option sets one.
 uint32_t level1_bits(uint32_t B, uint32_t cap) {
     if (cap == 0) return std::min<uint32_t>(kMaxCoarseBits, (B + 1) / 2);
-    return std::min<uint32_t>(B, cap);
+    // the second level keeps at most kMaxLevelBits (its LDS counters)
+    return std::min<uint32_t>(B, std::max<uint32_t>(cap, B > kMaxLevelBits ? B - kMaxLevelBits : 0));
 }
 
 // Plan of a batch permutation: global buckets [0, nb) over m records.
@@ -389,6 +402,26 @@ size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true) {
     size_t words = 3 * nd + scatter_threads((int)tile) / 64 + 1 + tile;
     words += words & 1;  // 8-byte alignment of the key stage
     return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (buckets ? (size_t)tile * 4 : 0);
+}
+
+// Every k_scatter instance may take more than 64 KiB of dynamic LDS (gfx950
+// has 160 KiB per CU); a level has at most kMaxLevelBits digit bits.
+template <int kTile, bool kOne>
+void set_scatter_lds_limits_one() {
+    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcHash, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcBatch, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcBucket, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcEmit, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcHashed, kTile, scatter_threads(kTile), kOne>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)scatter_lds_bytes(kMaxLevelBits, kTile));
+}
+
+template <int kTile>
+void set_scatter_lds_limits() {
+    set_scatter_lds_limits_one<kTile, true>();
+    set_scatter_lds_limits_one<kTile, false>();
 }
 
 size_t sort_lds_bytes(uint32_t cap) {
@@ -446,29 +479,29 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const uint32_t *src_i = in_idx ? in_idx : idx[src];
     const unsigned long long *src_k = in_key ? in_key : key[src];
     const uint32_t nd1 = 1u << p.b1;
-    const uint32_t nchunks = ceil_div(p.ntiles1, kScanChunk);
+    const uint32_t chunk = scan_chunk(p.ntiles1);
+    const uint32_t nchunks = ceil_div(p.ntiles1, chunk);
+    const uint32_t scan_threads = std::max<uint32_t>(64, std::min<uint32_t>(kBlock, nd1));
     GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
     GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, (uint64_t)nchunks * nd1));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_setup_level1, dim3(1), dim3(64), 0, c->lvl1_seg, c->lvl1_tiles, n,
-                     p.ntiles1));
-    const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;
-    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
-                     (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 1u, c->lvl1_seg,
-                     c->lvl1_tiles, c->counts1, ba1));
-    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1, (int)p.b1,
-                     c->partial));
+    const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;  // level 1: one segment [0, n), passed by value
+    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile, true>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile, true>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
+                     (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr,
+                     (const uint32_t *)nullptr, c->counts1, ba1));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
+                     (int)p.b1, chunk, c->partial));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kBlock), 0, c->partial, nchunks, (int)p.b1,
                      c->coarse_off, c->tile_first, (uint32_t)kTile));
-    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(kBlock), 0, c->counts1, p.ntiles1,
-                     (int)p.b1, c->partial, c->coarse_off));
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
+                     (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
     const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch);
     const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch);
-    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile)>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile)>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
-                     k1, shift1, (int)p.b1, 1u, c->lvl1_seg, c->lvl1_tiles, (const uint32_t *)c->counts1, c->err,
-                     ba1));
+    GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
+                     k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr, (const uint32_t *)nullptr,
+                     (const uint32_t *)c->counts1, c->err, ba1));
     if (p.b2 == 0) {
         *out = dst;
         *bucket_off = c->coarse_off;
@@ -479,15 +512,16 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
     GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
     const int shift2 = 64 - (int)p.bbits;
-    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
-                     (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, c->coarse_off,
-                     c->tile_first, c->counts2, ba2));
+    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile, false>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile, false>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
+                     (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, 0u,
+                     (const uint32_t *)c->coarse_off, (const uint32_t *)c->tile_first, c->counts2, ba2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
-    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile, scatter_threads(kTile)>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile, scatter_threads(kTile)>, lds2, tiles2, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
-                     p.ncoarse, c->coarse_off, c->tile_first, (const uint32_t *)c->counts2, c->err, ba2));
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile, scatter_threads(kTile), false>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile, scatter_threads(kTile), false>, lds2, tiles2, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+                     p.ncoarse, 0u, (const uint32_t *)c->coarse_off, (const uint32_t *)c->tile_first,
+                     (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
     *bucket_off = c->fine_off;
     *nbuckets = p.nfine;
@@ -1295,18 +1329,8 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     // kernels whose dynamic LDS can exceed 64 KiB (gfx950 has 160 KiB per CU)
     (void)hipFuncSetAttribute((const void *)k_sort_buckets, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sort_lds_bytes(kLdsCap));
-    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileSmall, scatter_threads(kTileSmall)>, (const void *)k_scatter<kSrcHash, kTileSmall, scatter_threads(kTileSmall)>,
-                          (const void *)k_scatter<kSrcBatch, kTileSmall, scatter_threads(kTileSmall)>,
-                          (const void *)k_scatter<kSrcBucket, kTileSmall, scatter_threads(kTileSmall)>, (const void *)k_scatter<kSrcEmit, kTileSmall, scatter_threads(kTileSmall)>,
-                          (const void *)k_scatter<kSrcHashed, kTileSmall, scatter_threads(kTileSmall)>})
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)scatter_lds_bytes(12, kTileSmall));
-    for (const void *f : {(const void *)k_scatter<kSrcPerm, kTileLarge, scatter_threads(kTileLarge)>, (const void *)k_scatter<kSrcHash, kTileLarge, scatter_threads(kTileLarge)>,
-                          (const void *)k_scatter<kSrcBatch, kTileLarge, scatter_threads(kTileLarge)>,
-                          (const void *)k_scatter<kSrcBucket, kTileLarge, scatter_threads(kTileLarge)>, (const void *)k_scatter<kSrcEmit, kTileLarge, scatter_threads(kTileLarge)>,
-                          (const void *)k_scatter<kSrcHashed, kTileLarge, scatter_threads(kTileLarge)>})
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)scatter_lds_bytes(12, kTileLarge));
+    set_scatter_lds_limits<kTileSmall>();
+    set_scatter_lds_limits<kTileLarge>();
     (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)resolve_lds_bytes(kLdsCap));
     (void)hipGetLastError();

@@ -292,16 +292,36 @@ __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long 
 // the same segment.  No global atomics are needed (device-scope atomics are
 // executed memory-side on gfx950).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kScanChunk = 256;  // tiles per chunk of the level-1 column scan
+// Tiles per chunk of the level-1 column scan: chosen per pass (scan_chunk on
+// the host) so that there are ~192 chunks, i.e. enough workgroups for the
+// column sums and applications and few rows for the one-workgroup top scan.
 
 struct TileSpan {
     uint32_t seg, seg_begin, seg_end, begin, cnt;
 };
 
-template <int kTile>
+// Segments of a radix pass: nseg segments with offsets seg_off[0..nseg] and
+// first tiles tile_first[0..nseg], or (kOne) the one segment [0, n1) passed
+// by value, with max(1, ceil(n1 / kTile)) tiles.
+// kOne selects the one-segment form at compile time (the first level of a
+// pass), so each level gets its own code.
+template <int kTile, bool kOne>
+__device__ __forceinline__ uint32_t pass_tiles(const uint32_t *tile_first, uint32_t nseg, uint32_t n1) {
+    return !kOne ? tile_first[nseg] : max(1u, (n1 + kTile - 1) / kTile);
+}
+
+template <int kTile, bool kOne>
 __device__ __forceinline__ TileSpan tile_span(const uint32_t *seg_off, const uint32_t *tile_first, uint32_t nseg,
-                                              uint32_t w) {
+                                              uint32_t n1, uint32_t w) {
     TileSpan ts;
+    if (kOne) {
+        ts.seg = 0;
+        ts.seg_begin = 0;
+        ts.seg_end = n1;
+        ts.begin = w * kTile;
+        ts.cnt = ts.begin < n1 ? min((uint32_t)kTile, n1 - ts.begin) : 0;
+        return ts;
+    }
     ts.seg = tile_segment(tile_first, nseg, w);
     ts.seg_begin = seg_off[ts.seg];
     ts.seg_end = seg_off[ts.seg + 1];
@@ -313,19 +333,19 @@ __device__ __forceinline__ TileSpan tile_span(const uint32_t *seg_off, const uin
 
 // One workgroup per tile (a grid smaller than the tile count walks the
 // tiles grid-stride).
-template <int kSrc, int kTile>
+template <int kSrc, int kTile, bool kOne>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restrict__ src_idx,
                                                         const unsigned long long *__restrict__ src_key, uint32_t t,
                                                         uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nseg,
-                                                        const uint32_t *__restrict__ seg_off,
+                                                        uint32_t n1, const uint32_t *__restrict__ seg_off,
                                                         const uint32_t *__restrict__ tile_first,
                                                         uint32_t *__restrict__ counts, SrcArgs ba) {
     extern __shared__ uint32_t hs[];
     constexpr int kTileItems = kTile / kBlock;
-    const uint32_t nt = tile_first[nseg];
+    const uint32_t nt = pass_tiles<kTile, kOne>(tile_first, nseg, n1);
     const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
     for (uint32_t w = blockIdx.x; w < nt; w += gridDim.x) {
-        const TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
+        const TileSpan ts = tile_span<kTile, kOne>(seg_off, tile_first, nseg, n1, w);
         uint32_t cur_i[kTileItems], cur_a[kTileItems];
         unsigned long long cur_k[kTileItems];
         if (kSrc == kSrcEmit) {
@@ -361,12 +381,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
     }
 }
 
-// Level-1 column scan, phase 1: per chunk of kScanChunk tiles, the column sums.
+// Level-1 column scan, phase 1: per chunk of `chunk` tiles, the column sums.
+// Workgroups of min(2^dbits, kBlock) threads.
 __global__ __launch_bounds__(kBlock) void k_colsum(const uint32_t *__restrict__ counts, uint32_t ntiles, int dbits,
-                                                   uint32_t *__restrict__ partial) {
+                                                   uint32_t chunk, uint32_t *__restrict__ partial) {
     const uint32_t nd = 1u << dbits, b = blockIdx.x;
-    const uint32_t w0 = b * kScanChunk, w1 = min(w0 + kScanChunk, ntiles);
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+    const uint32_t w0 = b * chunk, w1 = min(w0 + chunk, ntiles);
+    for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x) {
         uint32_t acc = 0;
 #pragma unroll 8
         for (uint32_t w = w0; w < w1; ++w) acc += counts[(size_t)w * nd + d];
@@ -375,30 +396,55 @@ __global__ __launch_bounds__(kBlock) void k_colsum(const uint32_t *__restrict__ 
 }
 
 // Phase 2 (one workgroup): exclusive scan of the chunk sums per digit, digit
-// totals -> digit bases (the coarse offsets), and the level-2 tile map.
+// totals -> digit bases (the coarse offsets), and the level-2 tile map.  With
+// fewer digits than threads, kBlock / nd threads share a digit's chunk rows
+// (contiguous runs, combined through LDS).
 __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ partial, uint32_t nchunks, int dbits,
                                                         uint32_t *__restrict__ coarse_off,
                                                         uint32_t *__restrict__ tile_first, uint32_t tile) {
     __shared__ uint32_t tot[(1u << kMaxCoarseBits) + 1], tiles[(1u << kMaxCoarseBits) + 1], tmp[kBlock + 1];
+    __shared__ uint32_t part[kBlock];
     const uint32_t nd = 1u << dbits;
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
-        uint32_t run = 0;
-        for (uint32_t b0 = 0; b0 < nchunks; b0 += 16) {
+    const uint32_t per_digit = nd >= kBlock ? 1u : kBlock / nd;  // threads per digit
+    const uint32_t rows = (nchunks + per_digit - 1) / per_digit;
+    auto scan_rows = [&](uint32_t d, uint32_t r0, uint32_t r1, uint32_t run, bool write) {
+        for (uint32_t b0 = r0; b0 < r1; b0 += 16) {
             uint32_t x[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = (b0 + j < nchunks) ? partial[(size_t)(b0 + j) * nd + d] : 0u;
+            for (int j = 0; j < 16; ++j) x[j] = (b0 + j < r1) ? partial[(size_t)(b0 + j) * nd + d] : 0u;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                if (b0 + j < nchunks) partial[(size_t)(b0 + j) * nd + d] = run;
+                if (write && b0 + j < r1) partial[(size_t)(b0 + j) * nd + d] = run;
                 run += x[j];
             }
         }
-        tot[d] = run;
-        tiles[d] = (run + tile - 1) / tile;
+        return run;
+    };
+    if (per_digit == 1) {
+        for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+            const uint32_t run = scan_rows(d, 0, nchunks, 0u, true);
+            tot[d] = run;
+            tiles[d] = (run + tile - 1) / tile;
+        }
+    } else {
+        const uint32_t d = threadIdx.x % nd, j = threadIdx.x / nd;
+        const uint32_t r0 = min(j * rows, nchunks), r1 = min(r0 + rows, nchunks);
+        part[threadIdx.x] = scan_rows(d, r0, r1, 0u, false);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (uint32_t q = 0; q < per_digit; ++q) {
+            const uint32_t v = part[q * nd + d];
+            before += q < j ? v : 0u;
+            all += v;
+        }
+        scan_rows(d, r0, r1, before, true);
+        if (j == 0) {
+            tot[d] = all;
+            tiles[d] = (all + tile - 1) / tile;
+        }
     }
     __syncthreads();
     uint32_t total_tiles;
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) tmp[d] = 0;
     const uint32_t total = block_exclusive_scan(tot, nd, tmp);
     total_tiles = block_exclusive_scan(tiles, nd, tmp);
     for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
@@ -411,13 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ p
     }
 }
 
-// Phase 3: run bases of every (tile, digit), in place of the counts.
+// Phase 3: run bases of every (tile, digit), in place of the counts
+// (workgroups as in phase 1).
 __global__ __launch_bounds__(kBlock) void k_colapply(uint32_t *__restrict__ counts, uint32_t ntiles, int dbits,
-                                                     const uint32_t *__restrict__ partial,
+                                                     uint32_t chunk, const uint32_t *__restrict__ partial,
                                                      const uint32_t *__restrict__ coarse_off) {
     const uint32_t nd = 1u << dbits, b = blockIdx.x;
-    const uint32_t w0 = b * kScanChunk, w1 = min(w0 + kScanChunk, ntiles);
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+    const uint32_t w0 = b * chunk, w1 = min(w0 + chunk, ntiles);
+    for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x) {
         uint32_t run = coarse_off[d] + partial[(size_t)b * nd + d];
         for (uint32_t wb = w0; wb < w1; wb += 16) {
             uint32_t x[16];
@@ -476,12 +523,12 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
 // smaller).  Dynamic LDS: 3 * 2^dbits + kThreads / 64 + 1 words of counters, then
 // the staged records (scatter_lds_bytes on the host).
 
-template <int kSrc, int kTile, int kThreads>
+template <int kSrc, int kTile, int kThreads, bool kOne>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict__ src_idx,
                                                     const unsigned long long *__restrict__ src_key,
                                                     uint32_t *__restrict__ dst_idx,
                                                     unsigned long long *__restrict__ dst_key, uint32_t t, uint32_t k0,
-                                                    uint32_t k1, int shift, int dbits, uint32_t nseg,
+                                                    uint32_t k1, int shift, int dbits, uint32_t nseg, uint32_t n1,
                                                     const uint32_t *__restrict__ seg_off,
                                                     const uint32_t *__restrict__ tile_first,
                                                     const uint32_t *__restrict__ offs, uint32_t *__restrict__ err,
@@ -501,11 +548,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
     uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kTile);
     uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kTile);  // kSrcBatch only
 
-    const uint32_t nt = tile_first[nseg];
+    const uint32_t nt = pass_tiles<kTile, kOne>(tile_first, nseg, n1);
     const uint32_t tid = threadIdx.x;
     for (uint32_t v = blockIdx.x; v < nt; v += gridDim.x) {
         const uint32_t w = xcd_tile(v, nt);
-        const TileSpan ts = tile_span<kTile>(seg_off, tile_first, nseg, w);
+        const TileSpan ts = tile_span<kTile, kOne>(seg_off, tile_first, nseg, n1, w);
         uint32_t c_idx[kTileItems], c_aux[kTileItems];
         unsigned long long c_key[kTileItems];
         if (kSrc == kSrcEmit) {

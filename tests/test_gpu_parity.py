@@ -216,6 +216,28 @@ def test_schedule_independence(ctx):
             c.close()
 
 
+def test_level_split_independence(ctx):
+    """The split of the bucket bits between the two radix levels (balanced,
+    or a first level of 1..10 bits, the second level then clamped to at most
+    12 bits) changes the schedule, never the result.  G(n,p) with about 1M
+    edges and 64-record buckets: 14 bucket bits, so small first levels hit
+    the clamp."""
+    import paper_2111_03005_amd as gesmc
+    n = 1 << 18
+    E = graphgen.gnp(n, 8.0 / (n - 1), 31)
+    rc, exp, _, _ = oracle_run(E, n, 123, 0, 2)
+    assert rc == 0
+    for l1 in (0, 1, 4, 10):
+        c = gesmc.Context(0)
+        try:
+            c.set_option(gesmc.OPT_BUCKET_AVG, 64)
+            c.set_option(gesmc.OPT_LEVEL1_BITS, l1)
+            out, _ = c.run(to_dev(E), n, 123, r=2)
+            assert np.array_equal(to_host(out), exp), l1
+        finally:
+            c.close()
+
+
 def test_resume_equals_single_call(ctx):
     E, n = graphgen.workload_gnp_small()
     a, _ = ctx.run(to_dev(E), n, 5, t0=0, r=7)
