@@ -491,7 +491,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
                      (const uint32_t *)nullptr, c->counts1, ba1));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial));
-    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kBlock), 0, c->partial, nchunks, (int)p.b1,
+    GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kTopThreads), 0, c->partial, nchunks, (int)p.b1,
                      c->coarse_off, c->tile_first, (uint32_t)kTile));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial, c->coarse_off));

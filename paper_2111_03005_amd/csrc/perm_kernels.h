@@ -397,15 +397,16 @@ __global__ __launch_bounds__(kBlock) void k_colsum(const uint32_t *__restrict__ 
 
 // Phase 2 (one workgroup): exclusive scan of the chunk sums per digit, digit
 // totals -> digit bases (the coarse offsets), and the level-2 tile map.  With
-// fewer digits than threads, kBlock / nd threads share a digit's chunk rows
-// (contiguous runs, combined through LDS).
-__global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ partial, uint32_t nchunks, int dbits,
+// fewer digits than threads, kTopThreads / nd threads share a digit's chunk
+// rows (contiguous runs, combined through LDS).
+constexpr uint32_t kTopThreads = 1024;
+__global__ __launch_bounds__(kTopThreads) void k_colscan_top(uint32_t *__restrict__ partial, uint32_t nchunks, int dbits,
                                                         uint32_t *__restrict__ coarse_off,
                                                         uint32_t *__restrict__ tile_first, uint32_t tile) {
-    __shared__ uint32_t tot[(1u << kMaxCoarseBits) + 1], tiles[(1u << kMaxCoarseBits) + 1], tmp[kBlock + 1];
-    __shared__ uint32_t part[kBlock];
+    __shared__ uint32_t tot[(1u << kMaxCoarseBits) + 1], tiles[(1u << kMaxCoarseBits) + 1], tmp[kTopThreads / 64 + 1];
+    __shared__ uint32_t part[kTopThreads];
     const uint32_t nd = 1u << dbits;
-    const uint32_t per_digit = nd >= kBlock ? 1u : kBlock / nd;  // threads per digit
+    const uint32_t per_digit = nd >= kTopThreads ? 1u : kTopThreads / nd;  // threads per digit
     const uint32_t rows = (nchunks + per_digit - 1) / per_digit;
     auto scan_rows = [&](uint32_t d, uint32_t r0, uint32_t r1, uint32_t run, bool write) {
         for (uint32_t b0 = r0; b0 < r1; b0 += 16) {
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ p
         return run;
     };
     if (per_digit == 1) {
-        for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+        for (uint32_t d = threadIdx.x; d < nd; d += kTopThreads) {
             const uint32_t run = scan_rows(d, 0, nchunks, 0u, true);
             tot[d] = run;
             tiles[d] = (run + tile - 1) / tile;
@@ -445,9 +446,9 @@ __global__ __launch_bounds__(kBlock) void k_colscan_top(uint32_t *__restrict__ p
     }
     __syncthreads();
     uint32_t total_tiles;
-    const uint32_t total = block_exclusive_scan(tot, nd, tmp);
-    total_tiles = block_exclusive_scan(tiles, nd, tmp);
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+    const uint32_t total = block_exclusive_scan<kTopThreads>(tot, nd, tmp);
+    total_tiles = block_exclusive_scan<kTopThreads>(tiles, nd, tmp);
+    for (uint32_t d = threadIdx.x; d < nd; d += kTopThreads) {
         coarse_off[d] = tot[d];
         tile_first[d] = tiles[d];
     }
