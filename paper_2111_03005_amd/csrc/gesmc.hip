@@ -563,10 +563,14 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
                      int *sorted_out, bool clear_table, const BatchStep *bs = nullptr) {
     const uint32_t m = p.m;
     const int X = (src + 1) % 3, Y = (src + 2) % 3;
-    const uint64_t tslots = clear_table ? c->tab_slots : 0;
-    GESMC_TRY(launch(c, s, KID_STEP_CLEAR, tslots, k_step_clear,
-                     dim3(grid_stride_blocks(c, std::max<uint64_t>(p.ell, tslots) + 1)), dim3(kBlock), 0, c->tab,
-                     tslots, c->st, p.ell, c->ucount));
+    // the table strategy resets its table, statuses and list counters here;
+    // the sorted-tuples emit writes every status and clears the counters itself
+    if (clear_table) {
+        const uint64_t tslots = c->tab_slots;
+        GESMC_TRY(launch(c, s, KID_STEP_CLEAR, tslots, k_step_clear,
+                         dim3(grid_stride_blocks(c, std::max<uint64_t>(p.ell, tslots) + 1)), dim3(kBlock), 0, c->tab,
+                         tslots, c->st, p.ell, c->ucount));
+    }
     const size_t sort_lds = sort_lds_bytes(c->sort_cap);
     if (p.bbits == 0) {
         // one bucket: sort src -> X (scratch keys in Y)
@@ -655,7 +659,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     sa.m = p.m;
     sa.pl = pl;
     GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, t, k0, k1, sa, c->info, c->st,
-                     c->idx[0], c->key[0], c->bslot));
+                     c->idx[0], c->key[0], c->bslot, c->ucount));
     const EmitSource es{si, sk, t, k0, k1, sa};
     if (!c->fuse_emit)
         GESMC_TRY(launch(c, s, KID_EMIT, nslots, k_emit_tuples, dim3(grid_stride_blocks(c, nslots)), dim3(kBlock), 0,

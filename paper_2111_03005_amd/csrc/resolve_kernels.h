@@ -36,20 +36,23 @@ constexpr uint32_t kNoPred = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
 // Emit: one thread per switch (+ one for the idle record of odd m).  The
-// local outcome of every switch (switch_local): a switch decided locally gets
-// its status, its records (unchanged) and its count; an undecided one gets
-// its two target records initialised to "free".  The switches' tuples are
-// not stored: the first partition pass computes them from the same pair
-// records (emit_switch).
+// local outcome of every switch (switch_local) goes to its status; a switch
+// decided locally also gets its records (unchanged) and its count, an
+// undecided one its two target records initialised to "free".  Workgroup 0
+// clears the undecided-list counters of the rounds that follow.  The
+// switches' tuples are not stored: the first partition pass computes them
+// from the same pair records (emit_switch).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
                                                  const unsigned long long *__restrict__ s_key, uint32_t t, uint32_t k0,
                                                  uint32_t k1, SrcArgs sa, uint2 *__restrict__ info,
                                                  uint8_t *__restrict__ st, uint32_t *__restrict__ out_idx,
-                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot) {
+                                                 unsigned long long *__restrict__ out_key, uint4 *__restrict__ bslot,
+                                                 uint32_t *__restrict__ ucount) {
     __shared__ BlockCounts bc;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
+    if (blockIdx.x == 0 && tid < 3) ucount[tid] = 0;  // the undecided-list counters of the rounds
     __syncthreads();
     const uint32_t m = sa.m, ell = m >> 1;
     const uint32_t stride = gridDim.x * kBlock;
@@ -65,10 +68,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
         const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
         Targets T{0, 0, false};
         const uint8_t status = switch_local(k, ij, ee, t, k0, k1, sa, &T);
+        st[k] = status;
         if (status == ST_UNDECIDED) {
             reinterpret_cast<uint4 *>(info)[k] = make_uint4(kNoEraser, kNoPred, kNoEraser, kNoPred);
         } else {
-            st[k] = status;
             reinterpret_cast<uint2 *>(out_idx)[k] = ij;
             reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
             if (status == ST_PL) atomicAdd(&bc.pl, 1u);
