@@ -146,6 +146,10 @@ struct gesmc_ctx {
     std::vector<BatchGraph> h_gr;
     std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_rrank;
     std::vector<uint4> h_chunks;   // position chunks of the ranks' segments (k_fill_pg, serving kernels)
+    unsigned char *h_up = nullptr;  // pinned staging of a call's small uploads (up_begin / up_copy)
+    uint64_t up_cap = 0, up_used = 0;
+    hipEvent_t up_ev = nullptr;     // recorded after a call's last upload
+    bool up_pending = false;
     uint4 *chunks = nullptr;
     uint64_t chunk_cap = 0;
     uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
@@ -874,10 +878,55 @@ void add_chunks(std::vector<uint4> &v, uint32_t q, uint32_t poff, uint32_t len, 
         v.push_back(make_uint4(q, poff + b, poff + std::min<uint32_t>(len, b + kChunkPos), aux));
 }
 
-// Copies c->h_chunks to the device (growing the buffer if needed).
-gesmc_status upload_chunks(gesmc_ctx *c, hipStream_t s) {
+// Pinned staging of a call's small host -> device uploads (graph records,
+// offsets, rank lists, chunks).  A copy from pageable memory may be carried
+// out before hipMemcpyAsync returns, which holds back the launches queued
+// after it; from pinned memory it is a DMA in stream order.  One arena per
+// context: up_begin sizes it for the call (after the previous call's uploads
+// have left it), up_copy stages and queues one upload, up_end marks the end.
+gesmc_status up_begin(gesmc_ctx *c, uint64_t bytes, uint32_t copies) {
+    if (c->up_pending) {
+        GESMC_TRY(check_hip(hipEventSynchronize(c->up_ev), "hipEventSynchronize"));
+        c->up_pending = false;
+    }
+    const uint64_t need = bytes + 64ull * copies;
+    if (need > c->up_cap) {
+        if (c->h_up) (void)hipHostFree(c->h_up);
+        c->h_up = nullptr;
+        c->up_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(need + need / 2, 1u << 16);
+        if (hipHostMalloc((void **)&c->h_up, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipHostMalloc of %llu bytes failed", (unsigned long long)cap);
+            return GESMC_E_NOMEM;
+        }
+        c->up_cap = cap;
+    }
+    c->up_used = 0;
+    return GESMC_OK;
+}
+
+gesmc_status up_copy(gesmc_ctx *c, hipStream_t s, void *dst, const void *src, uint64_t bytes) {
+    if (bytes == 0) return GESMC_OK;
+    const uint64_t off = (c->up_used + 63) & ~63ull;
+    if (off + bytes > c->up_cap) {
+        set_error("upload staging too small");
+        return GESMC_E_INTERNAL;
+    }
+    memcpy(c->h_up + off, src, bytes);
+    c->up_used = off + bytes;
+    return check_hip(hipMemcpyAsync(dst, c->h_up + off, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+}
+
+gesmc_status up_end(gesmc_ctx *c, hipStream_t s) {
+    GESMC_TRY(check_hip(hipEventRecord(c->up_ev, s), "hipEventRecord"));
+    c->up_pending = true;
+    return GESMC_OK;
+}
+
+// Device room for c->h_chunks (grown if needed; the copy goes through up_copy).
+gesmc_status ensure_chunks(gesmc_ctx *c) {
     const uint64_t n = c->h_chunks.size();
-    if (n == 0) return GESMC_OK;
     if (n > c->chunk_cap) {
         if (c->chunks) (void)hipFree(c->chunks);
         c->chunks = nullptr;
@@ -886,8 +935,7 @@ gesmc_status upload_chunks(gesmc_ctx *c, hipStream_t s) {
         GESMC_TRY(dev_alloc((void **)&c->chunks, cap * sizeof(uint4)));
         c->chunk_cap = cap;
     }
-    return check_hip(hipMemcpyAsync(c->chunks, c->h_chunks.data(), n * sizeof(uint4), hipMemcpyHostToDevice, s),
-                     "hipMemcpyAsync");
+    return GESMC_OK;
 }
 
 gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
@@ -1050,27 +1098,27 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     GESMC_TRY(ensure_capacity(c, npos));
     GESMC_TRY(ensure_counters(c, rmax));
     GESMC_TRY(ensure_batch(c, G, npos));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
-                        "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->in_off, offsets, (G + 1) * 8ull, hipMemcpyHostToDevice, s),
-                        "hipMemcpyAsync"));
+    c->h_chunks.clear();
+    for (uint32_t q = 0; q < G; ++q) add_chunks(c->h_chunks, q, gr[q].poff, gr[q].mpad);
+    const uint32_t nchunks = (uint32_t)c->h_chunks.size();
+    GESMC_TRY(ensure_chunks(c));
+    // uploads through the pinned arena: records, offsets, rank lists, chunks
+    const uint64_t up_bytes = G * (sizeof(BatchGraph) + 8 + 4 + 4) + 8 +
+                              (c->h_small.size() + c->h_mid.size()) * 4ull + (uint64_t)nchunks * sizeof(uint4);
+    GESMC_TRY(up_begin(c, up_bytes, 6));
+    GESMC_TRY(up_copy(c, s, c->gr, gr.data(), G * sizeof(BatchGraph)));
+    GESMC_TRY(up_copy(c, s, c->in_off, offsets, (G + 1) * 8ull));
     const uint32_t nsm1 = (uint32_t)c->h_small.size(), nsm2 = (uint32_t)c->h_mid.size();
     c->h_small.insert(c->h_small.end(), c->h_mid.begin(), c->h_mid.end());  // the m <= 1024 list, then the rest
     const uint32_t nsmall = nsm1 + nsm2;
     const bool need_acc = stats != nullptr || nsmall > 0;  // small graphs count per graph
     if (nsmall) {
-        GESMC_TRY(check_hip(hipMemcpyAsync(c->small_list, c->h_small.data(), nsmall * 4ull, hipMemcpyHostToDevice,
-                                           s),
-                            "hipMemcpyAsync"));
-        GESMC_TRY(check_hip(hipMemcpyAsync(c->rrank, c->h_rrank.data(), G * 4ull, hipMemcpyHostToDevice, s),
-                            "hipMemcpyAsync"));
+        GESMC_TRY(up_copy(c, s, c->small_list, c->h_small.data(), nsmall * 4ull));
+        GESMC_TRY(up_copy(c, s, c->rrank, c->h_rrank.data(), G * 4ull));
     }
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->rank_of, c->h_rank_of.data(), G * 4ull, hipMemcpyHostToDevice, s),
-                        "hipMemcpyAsync"));
-    c->h_chunks.clear();
-    for (uint32_t q = 0; q < G; ++q) add_chunks(c->h_chunks, q, gr[q].poff, gr[q].mpad);
-    const uint32_t nchunks = (uint32_t)c->h_chunks.size();
-    GESMC_TRY(upload_chunks(c, s));
+    GESMC_TRY(up_copy(c, s, c->rank_of, c->h_rank_of.data(), G * 4ull));
+    GESMC_TRY(up_copy(c, s, c->chunks, c->h_chunks.data(), (uint64_t)nchunks * sizeof(uint4)));
+    GESMC_TRY(up_end(c, s));
     // The device work of the call.  In graph mode (GESMC_OPT_GRAPH) it is captured
     // into a hipGraph on the second call of a shape and replayed afterwards: the
     // per-call data (seeds, t0, n) live in the per-graph records uploaded above,
@@ -1346,6 +1394,7 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
         hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->join_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->join_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->up_ev, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         set_error("context initialisation failed");
@@ -1375,7 +1424,8 @@ void gesmc_destroy(gesmc_ctx *c) {
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->call_a) (void)hipEventDestroy(c->call_a);
     if (c->call_b) (void)hipEventDestroy(c->call_b);
-    for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1]})
+    if (c->h_up) (void)hipHostFree(c->h_up);
+    for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1], c->up_ev})
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : c->side)
         if (q) (void)hipStreamDestroy(q);

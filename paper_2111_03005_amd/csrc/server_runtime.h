@@ -33,10 +33,13 @@ struct ServeReq {
     uint64_t m = 0;
     uint32_t n = 0, t0 = 0, r = 0, pl = 0;
     uint64_t seed = 0;
-    uint32_t done = 0;  // supersteps run
+    uint32_t done = 0;  // supersteps queued (the worker's view, ahead of the device)
     uint32_t goff = 0;  // index label base, fixed at admission
     uint32_t poff = 0, vbase = 0;  // segment and vertex base in the current layout
     bool cancel = false, finished = false;
+    uint32_t flights = 0;                   // queued iterations holding the graph (worker only)
+    bool leaving = false;                   // out of the resident set; finished when flights == 0
+    gesmc_status final_status = GESMC_OK;   // what it finishes with
     gesmc_status status = GESMC_OK;
     gesmc_stats stats{};
     uint64_t *result = nullptr;
@@ -46,6 +49,22 @@ struct ServeReq {
 double seconds_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
+
+// One queued iteration of the worker: its rank order, result offsets, and
+// the pinned host buffers its results and counts come back to.
+struct ServeFlight {
+    std::vector<ServeReq *> ranks;
+    std::vector<uint64_t> rb;  // result offset (words) per rank, ~0: not finishing
+    uint32_t nsurv = 0, k = 0;
+    bool live = false;
+    hipEvent_t done = nullptr;  // after the iteration's last copy
+    uint64_t *h_res = nullptr;  // results of the finishing graphs
+    uint64_t res_cap = 0;       // words
+    unsigned long long *h_gacc = nullptr;  // 4 per rank (max_graphs)
+    uint32_t *h_gerr = nullptr;            // per rank
+    StepCounters *h_ctr = nullptr;         // per superstep (kServeBurstMax)
+    uint32_t *h_err = nullptr;             // error words
+};
 
 }  // namespace
 
@@ -73,9 +92,11 @@ struct gesmc_server {
     std::vector<uint2> h_mv;
     std::vector<uint64_t> h_stage_off;
     std::vector<uint32_t> h_stage_rank;
-    std::vector<unsigned long long> h_rb;
-    uint64_t *h_pin = nullptr;  // pinned staging: admitted edges up, finished results down
+    uint64_t *h_pin = nullptr;  // pinned staging of admitted edges
     uint64_t pin_cap = 0;       // words
+    hipEvent_t stage_ev = nullptr;  // after the last upload from h_pin
+    bool stage_pending = false;
+    ServeFlight fl[2];          // two iterations in flight at most
     uint2 *d_mv = nullptr;
     uint64_t *d_stage_off = nullptr;
     uint32_t *d_stage_rank = nullptr;
@@ -127,13 +148,18 @@ gesmc_status serve_map_gerr(uint32_t e) {
     return GESMC_E_INTERNAL;
 }
 
-// Grows the pinned staging buffer to at least `words` words.
-gesmc_status serve_pin(gesmc_server *S, uint64_t words) {
+// Grows the pinned staging of admitted edges to at least `words` words
+// (after the previous upload from it has left).
+gesmc_status serve_stage(gesmc_server *S, uint64_t words) {
+    if (S->stage_pending) {
+        GESMC_TRY(check_hip(hipEventSynchronize(S->stage_ev), "hipEventSynchronize"));
+        S->stage_pending = false;
+    }
     if (words <= S->pin_cap) return GESMC_OK;
     if (S->h_pin) (void)hipHostFree(S->h_pin);
     S->h_pin = nullptr;
     S->pin_cap = 0;
-    const uint64_t cap = std::max<uint64_t>(words, 8ull << 20);
+    const uint64_t cap = std::max<uint64_t>(words + words / 4, 8ull << 20);
     if (hipHostMalloc((void **)&S->h_pin, cap * 8, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         S->h_pin = nullptr;
@@ -144,15 +170,39 @@ gesmc_status serve_pin(gesmc_server *S, uint64_t words) {
     return GESMC_OK;
 }
 
-// One iteration on the worker: new layout (survivors + admitted), one
-// superstep of every resident graph, results of the graphs that finish.
-gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, const std::vector<ServeReq *> &admit,
-                             bool relayout, uint32_t k, std::vector<ServeReq *> &finishing) {
+// Grows a flight's pinned result buffer (the flight is not in use).
+gesmc_status serve_flight_res(ServeFlight &F, uint64_t words) {
+    if (words <= F.res_cap) return GESMC_OK;
+    if (F.h_res) (void)hipHostFree(F.h_res);
+    F.h_res = nullptr;
+    F.res_cap = 0;
+    const uint64_t cap = std::max<uint64_t>(words + words / 4, 8ull << 20);
+    if (hipHostMalloc((void **)&F.h_res, cap * 8, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        F.h_res = nullptr;
+        set_error("hipHostMalloc of a serving result buffer failed");
+        return GESMC_E_NOMEM;
+    }
+    F.res_cap = cap;
+    return GESMC_OK;
+}
+
+// Queues one iteration into flight F: new layout (survivors `next` + the
+// admitted), k supersteps of every resident graph (each at its own superstep
+// t0 + done + step), the results of the graphs that finish, the outcome
+// counts; nothing waits for the device.  The requests' host state advances
+// as if the iteration had run (done += k); its outcome is read in
+// serve_complete.
+gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<ServeReq *> &next,
+                           const std::vector<ServeReq *> &admit, bool relayout, uint32_t k) {
     gesmc_ctx *c = S->c;
     hipStream_t s = S->s;
     const uint32_t nsurv = (uint32_t)next.size();
-    std::vector<ServeReq *> ranks = next;
-    ranks.insert(ranks.end(), admit.begin(), admit.end());
+    F.ranks = next;
+    F.ranks.insert(F.ranks.end(), admit.begin(), admit.end());
+    F.nsurv = nsurv;
+    F.k = k;
+    const std::vector<ServeReq *> &ranks = F.ranks;
     const uint32_t G = (uint32_t)ranks.size();
     S->h_gr.assign(G, BatchGraph{});
     S->h_mv.assign(G, make_uint2(0xFFFFFFFFu, 0));
@@ -193,14 +243,12 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
     S->h_stage_off.push_back(stage);
     const uint32_t npos = (uint32_t)poff;
     // graphs that finish in this iteration, and their result offsets
-    finishing.clear();
-    S->h_rb.assign(G, ~0ull);
+    F.rb.assign(G, ~0ull);
     uint64_t rpos = 0;
     for (uint32_t q = 0; q < G; ++q) {
         if (ranks[q]->done + k == ranks[q]->r) {
-            S->h_rb[q] = rpos;
+            F.rb[q] = rpos;
             rpos += ranks[q]->m;
-            finishing.push_back(ranks[q]);
         }
     }
     // position chunks: every rank (pg) and the staying ranks (relayout) if the
@@ -213,20 +261,29 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         for (uint32_t q = 0; q < nsurv; ++q) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad);
     const uint32_t n_move = (uint32_t)c->h_chunks.size() - n_fill;
     for (uint32_t q = 0; q < G; ++q)
-        if (S->h_rb[q] != ~0ull) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad, (uint32_t)S->h_rb[q]);
+        if (F.rb[q] != ~0ull) add_chunks(c->h_chunks, q, S->h_gr[q].poff, S->h_gr[q].mpad, (uint32_t)F.rb[q]);
     const uint32_t n_out = (uint32_t)c->h_chunks.size() - n_fill - n_move;
-    // the pinned staging holds this iteration's upload, then its results (same stream, in order);
-    // it is sized before any copy is queued
-    GESMC_TRY(serve_pin(S, std::max(stage, rpos)));
-    if (bbase > (1ull << kMaxFineBits) || npos > c->cap_pos) {
+    if (bbase > (1ull << kMaxFineBits) || npos > c->cap_pos || G > S->max_graphs || k > kServeBurstMax) {
         set_error("serving layout exceeds the context's capacity");
         return GESMC_E_INTERNAL;
     }
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->gr, S->h_gr.data(), G * sizeof(BatchGraph), hipMemcpyHostToDevice, s),
-                        "hipMemcpyAsync"));
-    GESMC_TRY(upload_chunks(c, s));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
+    {  // pinned buffers sized before any copy is queued (growing them is part of the copies' cost)
+        const auto a0 = std::chrono::steady_clock::now();
+        GESMC_TRY(serve_stage(S, stage));
+        GESMC_TRY(serve_flight_res(F, rpos));
+        S->w_copy += seconds_since(a0);
+    }
+    // small uploads through the context's pinned arena (records, chunks, moves, staging map)
+    const uint32_t nadm = (uint32_t)admit.size();
+    GESMC_TRY(ensure_chunks(c));
+    GESMC_TRY(up_begin(c,
+                       G * (sizeof(BatchGraph) + sizeof(uint2)) + (uint64_t)c->h_chunks.size() * sizeof(uint4) +
+                           (nadm + 1) * 8ull + nadm * 4ull,
+                       5));
+    GESMC_TRY(up_copy(c, s, c->gr, S->h_gr.data(), G * sizeof(BatchGraph)));
+    GESMC_TRY(up_copy(c, s, c->chunks, c->h_chunks.data(), (uint64_t)c->h_chunks.size() * sizeof(uint4)));
     GESMC_TRY(ensure_counters(c, k));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
                      (uint64_t)k * (sizeof(StepCounters) / 4)));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, c->gerr, (uint64_t)G));
@@ -237,8 +294,7 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
             GESMC_TRY(launch(c, s, KID_MISC, 0, k_fill_pg, dim3(n_fill), dim3(kBlock), 0, (const uint4 *)c->chunks,
                              c->pg));
         if (n_move) {
-            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_mv, S->h_mv.data(), G * sizeof(uint2), hipMemcpyHostToDevice, s),
-                                "hipMemcpyAsync"));
+            GESMC_TRY(up_copy(c, s, S->d_mv, S->h_mv.data(), G * sizeof(uint2)));
             GESMC_TRY(launch(c, s, KID_MISC, 0, k_relayout, dim3(n_move), dim3(kBlock), 0,
                              (const uint4 *)c->chunks + n_fill, (const BatchGraph *)c->gr, (const uint2 *)S->d_mv,
                              (const uint32_t *)c->idx[0], (const unsigned long long *)c->key[0], c->idx[1],
@@ -254,16 +310,14 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
                 if (admit[j]->m) S->segs.push_back({S->h_pin + S->h_stage_off[j], admit[j]->edges.data(), admit[j]->m * 8});
             S->copier->copy(S->segs);
             S->w_copy += seconds_since(c0);
-            if (stage)
+            if (stage) {
                 GESMC_TRY(check_hip(hipMemcpyAsync(stg, S->h_pin, stage * 8, hipMemcpyHostToDevice, s),
                                     "hipMemcpyAsync"));
-            const uint32_t nadm = (uint32_t)admit.size();
-            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage_off, S->h_stage_off.data(), (nadm + 1) * 8ull,
-                                               hipMemcpyHostToDevice, s),
-                                "hipMemcpyAsync"));
-            GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage_rank, S->h_stage_rank.data(), nadm * 4ull,
-                                               hipMemcpyHostToDevice, s),
-                                "hipMemcpyAsync"));
+                GESMC_TRY(check_hip(hipEventRecord(S->stage_ev, s), "hipEventRecord"));
+                S->stage_pending = true;
+            }
+            GESMC_TRY(up_copy(c, s, S->d_stage_off, S->h_stage_off.data(), (nadm + 1) * 8ull));
+            GESMC_TRY(up_copy(c, s, S->d_stage_rank, S->h_stage_rank.data(), nadm * 4ull));
             if (stage > 0)
                 GESMC_TRY(launch(c, s, KID_LOAD, stage, k_load_batch, dim3(grid_stride_blocks(c, stage)),
                                  dim3(kBlock), 0, (const unsigned long long *)stg, (uint32_t)stage,
@@ -274,64 +328,157 @@ gesmc_status serve_iteration(gesmc_server *S, std::vector<ServeReq *> &next, con
         std::swap(c->key[0], c->key[1]);
         ++g_alloc_epoch;  // buffer roles moved: no captured graph may be replayed
     }
-    // k supersteps of every resident graph (each at its own superstep t0 + done + step);
-    // k never exceeds the remaining supersteps of any of them
+    GESMC_TRY(up_end(c, s));
     const Plan p = batch_plan(c, npos, bbase);
     for (uint32_t st = 0; st < k; ++st) {
         BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
         c->ctr_step = c->ctr + st;
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
     }
-    // results of the graphs finishing now (discarded after the sync if flagged)
-    unsigned long long *res = c->tu_key[2];
-    if (!finishing.empty()) {
-        if (n_out)
-            GESMC_TRY(launch(c, s, KID_UNPERMUTE, rpos, k_extract, dim3(n_out), dim3(kBlock), 0,
-                             (const uint4 *)c->chunks + n_fill + n_move, (const uint32_t *)c->idx[0],
-                             (const unsigned long long *)c->key[0], (const BatchGraph *)c->gr, res));
-        GESMC_TRY(check_hip(hipMemcpyAsync(S->h_pin, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    // results of the graphs finishing now (discarded on the host if flagged)
+    if (n_out) {
+        unsigned long long *res = c->tu_key[2];
+        GESMC_TRY(launch(c, s, KID_UNPERMUTE, rpos, k_extract, dim3(n_out), dim3(kBlock), 0,
+                         (const uint4 *)c->chunks + n_fill + n_move, (const uint32_t *)c->idx[0],
+                         (const unsigned long long *)c->key[0], (const BatchGraph *)c->gr, res));
+        GESMC_TRY(check_hip(hipMemcpyAsync(F.h_res, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     }
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, k * sizeof(StepCounters), hipMemcpyDeviceToHost, s),
+    GESMC_TRY(check_hip(hipMemcpyAsync(F.h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(F.h_ctr, c->ctr, k * sizeof(StepCounters), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gacc, c->gacc, G * 32ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_gerr, c->gerr, G * 4ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
-    const auto w0 = std::chrono::steady_clock::now();
-    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
-    const auto c0 = std::chrono::steady_clock::now();
-    S->w_wait += std::chrono::duration<double>(c0 - w0).count();
-    S->segs.clear();
-    for (uint32_t q = 0; q < G; ++q) {
-        if (S->h_rb[q] == ~0ull) continue;
-        ServeReq *R = ranks[q];
-        R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
-        if (!R->result) return GESMC_E_NOMEM;
-        S->segs.push_back({R->result, S->h_pin + S->h_rb[q], R->m * 8});
+    GESMC_TRY(check_hip(hipMemcpyAsync(F.h_gacc, c->gacc, G * 32ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(F.h_gerr, c->gerr, G * 4ull, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipEventRecord(F.done, s), "hipEventRecord"));
+    F.live = true;
+    for (ServeReq *R : ranks) {
+        ++R->flights;
+        R->done += k;
+        if (R->done == R->r) {  // leaves the resident set; finished when this flight completes
+            R->leaving = true;
+            R->final_status = GESMC_OK;
+        }
     }
-    S->copier->copy(S->segs);
-    S->w_copy += seconds_since(c0);
-    next = ranks;
     return GESMC_OK;
 }
 
+// Releases flight F's hold on R and finishes R if it is leaving and no live
+// flight holds it any more.
+void serve_release_locked(gesmc_server *S, ServeReq *R) {
+    if (R->flights > 0) --R->flights;
+    if (R->leaving && R->flights == 0 && !R->finished) serve_finish_locked(S, R, R->final_status);
+}
+
+// Waits for flight F and takes its outcome: results of the finishing graphs,
+// outcome counts, input errors (a graph with one leaves the resident set and
+// fails once no live flight holds it).
+gesmc_status serve_complete(gesmc_server *S, ServeFlight &F) {
+    const auto w0 = std::chrono::steady_clock::now();
+    GESMC_TRY(check_hip(hipEventSynchronize(F.done), "hipEventSynchronize"));
+    const auto c0 = std::chrono::steady_clock::now();
+    S->w_wait += std::chrono::duration<double>(c0 - w0).count();
+    if (F.h_err[0] != 0) {
+        set_error("internal consistency check failed (error bits 0x%x)", F.h_err[0]);
+        return GESMC_E_INTERNAL;
+    }
+    const uint32_t G = (uint32_t)F.ranks.size();
+    S->segs.clear();
+    for (uint32_t q = 0; q < G; ++q) {
+        ServeReq *R = F.ranks[q];
+        if (F.rb[q] == ~0ull || F.h_gerr[q] || R->final_status != GESMC_OK) continue;
+        R->result = (uint64_t *)malloc(std::max<uint64_t>(R->m, 1) * 8);
+        if (!R->result) return GESMC_E_NOMEM;
+        S->segs.push_back({R->result, F.h_res + F.rb[q], R->m * 8});
+    }
+    S->copier->copy(S->segs);
+    S->w_copy += seconds_since(c0);
+    uint64_t rounds = 0, rounds_max = 0;
+    for (uint32_t st = 0; st < F.k; ++st) {
+        rounds += F.h_ctr[st].rounds;
+        rounds_max = std::max<uint64_t>(rounds_max, F.h_ctr[st].rounds);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    ++S->iterations;
+    for (uint32_t q = 0; q < G; ++q) {
+        ServeReq *R = F.ranks[q];
+        gesmc_stats &o = R->stats;
+        o.attempts += (uint64_t)F.k * (R->m / 2);
+        o.legal += F.h_gacc[4 * (size_t)q + 0];
+        o.rej_loop += F.h_gacc[4 * (size_t)q + 1];
+        o.rej_exists += F.h_gacc[4 * (size_t)q + 2];
+        o.rej_pl += F.h_gacc[4 * (size_t)q + 3];
+        o.rounds_sum += rounds;
+        o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)rounds_max);
+        S->attempts += (uint64_t)F.k * (R->m / 2);
+        S->legal += F.h_gacc[4 * (size_t)q + 0];
+        const uint32_t ge = F.h_gerr[q];
+        if (ge && R->final_status == GESMC_OK) {
+            R->leaving = true;  // excluded from the next layouts
+            R->final_status = q >= F.nsurv ? serve_map_gerr(ge) : GESMC_E_INTERNAL;
+        }
+        if (R->leaving && R->final_status == GESMC_OK) {
+            o.supersteps = R->r;
+            o.ms_device = 0;
+        }
+        serve_release_locked(S, R);
+    }
+    F.live = false;
+    F.ranks.clear();
+    return GESMC_OK;
+}
+
+// After a failed call: waits for the stream and fails every request that a
+// flight holds or that is resident.
+void serve_drain_locked(gesmc_server *S, gesmc_status st) {
+    (void)hipStreamSynchronize(S->s);
+    (void)hipGetLastError();
+    S->stage_pending = false;
+    for (ServeFlight &F : S->fl) {
+        for (ServeReq *R : F.ranks) R->flights = 0;
+        for (ServeReq *R : F.ranks)
+            if (!R->finished) serve_finish_locked(S, R, st);
+        F.ranks.clear();
+        F.live = false;
+    }
+    for (ServeReq *R : S->resident) {
+        R->flights = 0;
+        if (!R->finished) serve_finish_locked(S, R, st);
+    }
+    S->resident.clear();
+    S->resident_edges = 0;
+    S->resident_count = 0;
+}
+
+// The worker: a depth-one pipeline.  Each pass queues the next iteration
+// (the layout and the graphs that finish are known on the host in advance)
+// while the device still runs the previous one, then completes the previous
+// one.  A cancelled graph, or one whose input turns out to be bad, leaves
+// the resident set at the next pass and is finished once no queued
+// iteration holds it.
 void serve_loop(gesmc_server *S) {
     gesmc_ctx *c = S->c;
     (void)hipSetDevice(c->device);
-    std::vector<ServeReq *> admit, trivial, next, finishing;
+    std::vector<ServeReq *> admit, trivial, next;
     bool dirty = true;  // the layout in buffer 0 differs from `resident`
-    uint32_t burst = 1;
+    int cur = 0;        // flight slot of the next iteration; 1 - cur may be live
     for (;;) {
         admit.clear();
         trivial.clear();
         next.clear();
+        uint32_t burst = 1;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->resident.empty(); });
+            S->cv_work.wait(lk, [&] {
+                return S->stop || !S->queue.empty() || !S->resident.empty() || S->fl[1 - cur].live;
+            });
             if (S->stop) return;
             for (ServeReq *R : S->resident) {
-                if (R->cancel) {
-                    serve_finish_locked(S, R, GESMC_E_CANCELED);
+                if (R->cancel && !R->leaving) {
+                    R->leaving = true;
+                    R->final_status = GESMC_E_CANCELED;
+                }
+                if (R->leaving) {
                     dirty = true;
+                    if (R->flights == 0 && !R->finished) serve_finish_locked(S, R, R->final_status);
                 } else {
                     next.push_back(R);
                 }
@@ -364,89 +511,64 @@ void serve_loop(gesmc_server *S) {
                 edges += need;
                 verts += R->n;
             }
-            S->resident_edges = edges;
-            S->resident_count = (uint32_t)(next.size() + admit.size());
             uint32_t rem = kServeBurstMax;
             for (ServeReq *R : next) rem = std::min(rem, R->r - R->done);
             for (ServeReq *R : admit) rem = std::min(rem, R->r - R->done);
             burst = std::max(1u, std::min(rem, S->queue.empty() ? kServeBurstIdle : kServeBurstMax));
         }
+        const auto it0 = std::chrono::steady_clock::now();
         for (ServeReq *R : trivial) {
             const gesmc_status st = serve_trivial(R);
             std::lock_guard<std::mutex> lk(S->mu);
             serve_finish_locked(S, R, st);
         }
-        if (next.empty() && admit.empty()) {
+        bool queued = false;
+        if (!next.empty() || !admit.empty()) {
+            const bool relayout = dirty || !admit.empty();
+            const gesmc_status st = serve_enqueue(S, S->fl[cur], next, admit, relayout, burst);
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (st != GESMC_OK) {
+                for (ServeReq *R : admit) S->resident.push_back(R);  // fail them with the others
+                serve_drain_locked(S, st);
+                dirty = true;
+                S->busy_s += seconds_since(it0);
+                continue;
+            }
+            queued = true;
+            dirty = false;
+            S->resident.clear();
+            uint64_t edges = 0;
+            for (ServeReq *R : S->fl[cur].ranks) {
+                if (R->leaving) {
+                    dirty = true;  // finishes with this flight: the next layout differs
+                } else {
+                    S->resident.push_back(R);
+                    edges += R->m + (R->m & 1);
+                }
+            }
+            S->resident_edges = edges;
+            S->resident_count = (uint32_t)S->resident.size();
+        } else {
             std::lock_guard<std::mutex> lk(S->mu);
             S->resident.clear();
-            dirty = true;
-            continue;
+            S->resident_edges = 0;
+            S->resident_count = 0;
         }
-        const auto it0 = std::chrono::steady_clock::now();
-        const bool relayout = dirty || !admit.empty();
-        gesmc_status st = serve_iteration(S, next, admit, relayout, burst, finishing);
+        if (S->fl[1 - cur].live) {
+            const gesmc_status st = serve_complete(S, S->fl[1 - cur]);
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (st != GESMC_OK) {
+                serve_drain_locked(S, st);
+                dirty = true;
+                queued = false;
+            }
+        }
+        if (queued) cur = 1 - cur;
         std::lock_guard<std::mutex> lk(S->mu);
         S->busy_s += seconds_since(it0);
         S->copy_s += S->w_copy;
         S->wait_s += S->w_wait;
         S->w_copy = S->w_wait = 0;
-        if (st == GESMC_OK && c->h_err[0] != 0) {
-            set_error("internal consistency check failed (error bits 0x%x)", c->h_err[0]);
-            st = GESMC_E_INTERNAL;
-        }
-        if (st != GESMC_OK) {  // a failed iteration fails every graph in it
-            (void)hipStreamSynchronize(S->s);
-            (void)hipGetLastError();
-            std::vector<ServeReq *> all = next;  // survivors (unchanged on failure) and the admitted
-            all.insert(all.end(), admit.begin(), admit.end());
-            for (ServeReq *R : all)
-                if (!R->finished) serve_finish_locked(S, R, st);
-            S->resident.clear();
-            dirty = true;
-            continue;
-        }
-        ++S->iterations;
-        std::vector<ServeReq *> keep;
-        dirty = false;
-        uint64_t rounds = 0, rounds_max = 0;
-        for (uint32_t st = 0; st < burst; ++st) {
-            rounds += c->h_ctr[st].rounds;
-            rounds_max = std::max<uint64_t>(rounds_max, c->h_ctr[st].rounds);
-        }
-        for (uint32_t q = 0; q < (uint32_t)next.size(); ++q) {
-            ServeReq *R = next[q];
-            gesmc_stats &o = R->stats;
-            const bool first = R->done == 0;
-            o.attempts += (uint64_t)burst * (R->m / 2);
-            o.legal += c->h_gacc[4 * (size_t)q + 0];
-            o.rej_loop += c->h_gacc[4 * (size_t)q + 1];
-            o.rej_exists += c->h_gacc[4 * (size_t)q + 2];
-            o.rej_pl += c->h_gacc[4 * (size_t)q + 3];
-            o.rounds_sum += rounds;
-            o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)rounds_max);
-            S->attempts += (uint64_t)burst * (R->m / 2);
-            S->legal += c->h_gacc[4 * (size_t)q + 0];
-            R->done += burst;
-            const uint32_t ge = c->h_gerr[q];
-            if (ge) {
-                serve_finish_locked(S, R, first ? serve_map_gerr(ge) : GESMC_E_INTERNAL);
-                dirty = true;
-            } else if (R->done == R->r) {
-                o.supersteps = R->r;
-                o.ms_device = 0;
-                serve_finish_locked(S, R, GESMC_OK);
-                dirty = true;
-            } else {
-                keep.push_back(R);
-            }
-        }
-        S->resident = keep;
-        if (dirty) {
-            uint64_t edges = 0;
-            for (ServeReq *R : keep) edges += R->m + (R->m & 1);
-            S->resident_edges = edges;
-            S->resident_count = (uint32_t)keep.size();
-        }
     }
 }
 
@@ -486,6 +608,20 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_mv, max_graphs * sizeof(uint2));
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
     if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_rank, max_graphs * 4ull);
+    if (st == GESMC_OK && hipEventCreateWithFlags(&S->stage_ev, hipEventDisableTiming) != hipSuccess) st = GESMC_E_DEVICE;
+    for (ServeFlight &F : S->fl) {
+        if (st != GESMC_OK) break;
+        if (hipEventCreateWithFlags(&F.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void **)&F.h_gacc, max_graphs * 32ull, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&F.h_gerr, max_graphs * 4ull, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&F.h_ctr, kServeBurstMax * sizeof(StepCounters), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&F.h_err, 64, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("serving buffers could not be allocated");
+            st = GESMC_E_NOMEM;
+        }
+    }
     if (st == GESMC_OK && hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         set_error("hipStreamCreate failed");
@@ -534,6 +670,12 @@ void gesmc_server_destroy(gesmc_server *S) {
     for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank})
         if (p) (void)hipFree(p);
     if (S->h_pin) (void)hipHostFree(S->h_pin);
+    if (S->stage_ev) (void)hipEventDestroy(S->stage_ev);
+    for (ServeFlight &F : S->fl) {
+        for (void *p : {(void *)F.h_res, (void *)F.h_gacc, (void *)F.h_gerr, (void *)F.h_ctr, (void *)F.h_err})
+            if (p) (void)hipHostFree(p);
+        if (F.done) (void)hipEventDestroy(F.done);
+    }
     delete S;
 }
 
