@@ -173,3 +173,73 @@ def test_serve_cancel_and_poll():
     finally:
         srv.close()
         c.close()
+
+
+def test_serve_stream_with_cancels_bad_inputs_and_bursts():
+    """A budget and graph limit that keep the queue blocked (long bursts of
+    supersteps between completions), requests with 1..200 switches, bad
+    inputs among them, cancels at random moments (queued, resident, done)
+    and results taken by polling while others run.  Every request that was
+    not cancelled returns the oracle's result and counts; a cancelled one
+    returns E_CANCELED or, if it had already finished, its exact result."""
+    gesmc = _gesmc()
+    qs = requests(11, 48, 1e2, 5e3)
+    rng = np.random.default_rng(11)
+    for q in qs:
+        if rng.random() < 0.3:
+            q["r"] = int(rng.integers(40, 200))
+    bad = [(keys([(0, 1), (1, 2), (0, 1), (2, 3)]), 4), (keys([(0, 5), (1, 2), (2, 3), (1, 2), (3, 4)]), 6)]
+    c = gesmc.Context(0)
+    srv = gesmc.Server(c, hbm_budget_bytes=136 * 40000, max_graphs=10)
+    try:
+        entries = []  # (ticket, query or None, expected bad status)
+        early = set(int(x) for x in rng.choice(len(qs), 6, replace=False))  # cancelled right after submission
+        for i, q in enumerate(qs):
+            entries.append((srv.submit(q["E"], q["n"], q["seed"], q["r"], t0=q["t0"], pl=q["pl"]), q, None))
+            if i in early:
+                srv.cancel(entries[-1][0])
+            if i % 16 == 7:
+                E, n = bad[(i // 16) % len(bad)]
+                entries.append((srv.submit(E, n, 3, 5), None, gesmc.E_NOT_SIMPLE))
+            if i % 8 == 3:
+                time.sleep(0.002)
+        cancel = set(int(x) for x in rng.choice(len(qs), 12, replace=False))
+        results = {}
+        good_idx = [j for j, e in enumerate(entries) if e[1] is not None]
+        for step, j in enumerate(good_idx):
+            if step in cancel and j not in results:  # a taken ticket is unknown to the server
+                srv.cancel(entries[j][0])
+            if step % 5 == 0:  # take whatever is already done
+                for jj, (t, _, _) in enumerate(entries):
+                    if jj not in results:
+                        res = srv.poll(t)
+                        if res is not None:
+                            results[jj] = res
+            time.sleep(0.0005)
+        for jj, (t, _, _) in enumerate(entries):
+            if jj not in results:
+                results[jj] = srv.wait(t)
+        info = srv.info()
+        print("server info:", info, flush=True)
+        assert info["completed"] == len(entries)
+        cancelled_steps = {good_idx[s] for s in cancel} | {good_idx[i] for i in early}
+        n_cancelled = 0
+        for jj, (t, q, bad_status) in enumerate(entries):
+            res = results[jj]
+            if q is None:
+                assert res["status"] == bad_status and res["edges"] is None
+                continue
+            if jj in cancelled_steps and res["status"] == gesmc.E_CANCELED:
+                assert res["edges"] is None
+                n_cancelled += 1
+                continue
+            assert res["status"] == gesmc.OK, (jj, res["status"])
+            rc, exp, counts, _ = oracle.run(q["E"], q["n"], q["seed"], q["t0"], q["r"], q["pl"])
+            assert np.array_equal(res["edges"], exp), jj
+            s = res["stats"]
+            for k in ("attempts", "legal", "rej_loop", "rej_exists", "rej_pl"):
+                assert s[k] == sum(cn[k] for cn in counts), (jj, k)
+        print("cancelled before finishing:", n_cancelled, flush=True)
+    finally:
+        srv.close()
+        c.close()
