@@ -216,7 +216,8 @@ def bench_served(gesmc, torch, args):
     out = []
     for rate, budget in [(x, args.serve_budget) for x in args.serve_rates] + [(args.serve_rates[-1], 1 << 30)]:
         rng = np.random.default_rng(1000 + int(rate))
-        nreq = args.serve_requests
+        # at low rates, about serve_window seconds of arrivals (at least 40 requests)
+        nreq = min(args.serve_requests, max(40, int(rate * args.serve_window)))
         picks = rng.integers(0, len(pool), nreq)
         rs = rng.integers(10, 51, nreq)
         seeds = rng.integers(0, 2**63, nreq)
@@ -304,8 +305,10 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--plain-sample-stride", type=int, default=8)
     ap.add_argument("--no-served", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[100.0, 300.0, 1000.0])
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[10.0, 30.0, 100.0, 300.0, 1000.0])
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests per rate (at most)")
+    ap.add_argument("--serve-window", type=float, default=4.0,
+                    help="seconds of arrivals per rate at low rates (at least 40 requests)")
     ap.add_argument("--serve-pool", type=int, default=128)
     ap.add_argument("--serve-budget", type=int, default=32 << 30, help="HBM budget of the server, bytes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
