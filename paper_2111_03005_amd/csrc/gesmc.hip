@@ -432,8 +432,8 @@ size_t sort_lds_bytes(uint32_t cap) {
     return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 20;
 }
 
-size_t resolve_lds_bytes(uint32_t cap) {
-    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 12;
+size_t resolve_lds_bytes(uint32_t cap) {  // cells, scan words, keys, tags, list links
+    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 14;
 }
 
 // Workgroups of a persistent kernel: as many as can be resident at once

@@ -33,6 +33,11 @@ namespace gesmc {
 
 // per-target record: x = eraser (kNoEraser / kStays / switch), y = predecessor (k' << 1 | h') or kNoPred
 constexpr uint32_t kNoPred = 0xFFFFFFFFu;
+constexpr uint32_t kListEnd = 0xFFFFu;  // end of a cell list in k_resolve (slots are < 2^16)
+#ifndef GESMC_RESOLVE_LISTS
+#define GESMC_RESOLVE_LISTS 1
+#endif
+static_assert(kLdsCap < kListEnd, "k_resolve slots fit 16 bits");
 
 // ---------------------------------------------------------------------------
 // Emit: one thread per switch (+ one for the idle record of odd m).  The
@@ -157,7 +162,8 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
 // LDS path: counting sort on kCellBits hash bits below the partition bits;
 // each tuple then reads its own cell.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
-// Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 12 bytes.
+// Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 14 bytes
+// (keys, tags and the 16-bit cell-list links).
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
                                                     uint32_t *__restrict__ sc_tag,
                                                     unsigned long long *__restrict__ sc_key, int pbits,
@@ -244,7 +250,49 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             }
             if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
             __syncthreads();
-        } else if (c > 0) {
+        } else if (c > 0 && GESMC_RESOLVE_LISTS) {
+            // Tuples stay in their own slots p (contiguous writes); each cell
+            // keeps a list of its slots, linked by one LDS exchange per tuple.
+            uint16_t *nxt = reinterpret_cast<uint16_t *>(sT + cap);
+            for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = kListEnd;
+            lds_barrier();
+            uint32_t r_cell[kSortMaxItems];
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p < c) {
+                    const uint64_t hsh = c_key[q];  // tuple words are tuple hashes
+                    r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
+                    sK[p] = c_key[q];
+                    sT[p] = c_tag[q];
+                    nxt[p] = (uint16_t)atomicExch(&cell[r_cell[q]], p);
+                }
+            }
+            lds_barrier();
+            // All tuples of one key share a cell.  Each tuple walks its cell's
+            // list for what the walk over the sorted group would give: the
+            // group's smallest tag, whether a tuple precedes it in (key, tag,
+            // slot) order and the largest preceding tag.
+#pragma unroll
+            for (int q = 0; q < kSortMaxItems; ++q) {
+                const uint32_t p = tid + q * kBlock;
+                if (p >= c) continue;
+                const unsigned long long kx = c_key[q];
+                const uint32_t tx = c_tag[q];
+                uint32_t first_tag = tx, prev_tag = 0;
+                bool before = false;
+                for (uint32_t y = cell[r_cell[q]]; y != kListEnd; y = nxt[y]) {
+                    if (y == p || sK[y] != kx) continue;
+                    const uint32_t ty = sT[y];
+                    first_tag = min(first_tag, ty);
+                    if (ty < tx || (ty == tx && y < p)) {
+                        prev_tag = before ? max(prev_tag, ty) : ty;
+                        before = true;
+                    }
+                }
+                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, info, err, dup_bit, ge);
+            }
+        } else if (c > 0) {  // counting sort into cell order
             for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
             lds_barrier();
             uint32_t r_cell[kSortMaxItems], r_rank[kSortMaxItems];
