@@ -38,9 +38,11 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
                                                  uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        const uint32_t h0 = __umulhi(m0, c0), l0 = m0 * c0;
-        const uint32_t h1 = __umulhi(m1, c2), l1 = m1 * c2;
+        // each 32x32 -> 64 product in one instruction (v_mad_u64_u32) rather
+        // than separate high and low multiplies
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
         const uint32_t y0 = h1 ^ c1 ^ k0;
         const uint32_t y2 = h0 ^ c3 ^ k1;
         c0 = y0;
