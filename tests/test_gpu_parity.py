@@ -188,6 +188,42 @@ def test_invalid_inputs_rejected_output_untouched(ctx):
     check_run(ctx, E, n, 1, 0, 1, label="after_errors")
 
 
+def test_size_limits_rejected_on_the_host(ctx):
+    """The largest sizes the library takes: m < 2^30 edges per graph (and a
+    batch of G graphs below 2^30 - G positions), vertex ids below 2^32 - 1,
+    a 32-bit superstep counter.  Requests past them fail with a status before
+    any device work, so a one-element buffer stands in for the edges."""
+    import ctypes
+    import paper_2111_03005_amd as gesmc
+    from paper_2111_03005_amd import _binding as b
+    lib = b._lib
+    buf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    p_in, p_out = ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr())
+    st = b.Stats()
+    for m in (1 << 30, (1 << 30) + 1, 1 << 40):
+        assert lib.gesmc_run(ctx._h, None, p_in, p_out, m, 8, 1, 0, 1, 0, 0, ctypes.byref(st), None) == gesmc.E_RANGE
+        assert lib.gesmc_perm_keys(ctx._h, None, m, 1, 0, p_out) == gesmc.E_RANGE
+        assert lib.gesmc_permutation(ctx._h, None, m, 1, 0, p_out) == gesmc.E_RANGE
+    # superstep counter: t0 + r must fit 32 bits
+    assert lib.gesmc_run(ctx._h, None, p_in, p_out, 1, 8, 1, 0xFFFFFFFF, 2, 0, 0, ctypes.byref(st), None) == gesmc.E_INVAL
+    G = 2
+    u64s, u32s = ctypes.c_uint64 * (G + 1), ctypes.c_uint32 * G
+    seeds, t0s, rs = (ctypes.c_uint64 * G)(1, 2), u32s(0, 0), u32s(1, 1)
+    tot = b.Stats()
+    big = u64s(0, 1 << 29, (1 << 30) - 1)  # 2^30 - 1 positions + G padding records > limit
+    assert lib.gesmc_run_batch(ctx._h, None, G, p_in, p_out, big, u32s(8, 8), seeds, t0s, rs, 0, 0, None,
+                               ctypes.byref(tot)) == gesmc.E_RANGE
+    small = u64s(0, 1, 1)
+    wide = u32s(1 << 31, 1 << 31)  # 2^32 vertices in all
+    assert lib.gesmc_run_batch(ctx._h, None, G, p_in, p_out, small, wide, seeds, t0s, rs, 0, 0, None,
+                               ctypes.byref(tot)) == gesmc.E_RANGE
+    # nothing was touched, and the context stays usable
+    assert int(out.cpu()[0]) == 0
+    E, n = graphgen.workload_gnp_small()
+    check_run(ctx, E, n, 3, 0, 1, label="after_limits")
+
+
 def test_schedule_independence(ctx):
     """Bucket sizes, LDS sort capacity (incl. the slow exact path) and the
     number of multi-workgroup rounds change the schedule, never the result."""
