@@ -108,7 +108,7 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
  * counts of that graph; rounds_* count the batch's rounds of the supersteps
  * the graph took part in; ms_device is the whole call's).  total (host,
  * nullable): the batch's sums.  Limits: offsets[G] + G < 2^30, the sum of n
- * below 2^32 - 1, G <= 2^20, and at most 2^20 permutation buckets (about
+ * below 2^32 - 1, G <= 2^21, and at most 2^21 permutation buckets (about
  * offsets[G] / GESMC_OPT_BUCKET_AVG + G).  Needs GESMC_OPT_STRATEGY 0.  Any
  * invalid graph fails the whole call with d_out untouched; the message names
  * the graph.  flags: reserved, pass 0.

@@ -185,7 +185,9 @@ struct gesmc_ctx {
 
 namespace {
 
-constexpr uint32_t kMaxFineBits = 20;
+// Bucket bits of a radix pass: 21 keeps the mean tuple partition within the
+// LDS capacity up to the largest input (2^31 tuple slots at m < 2^30).
+constexpr uint32_t kMaxFineBits = 21;
 constexpr uint32_t kMaxLevelBits = 12;  // digit bits of one radix level (first <= kMaxCoarseBits)
 constexpr uint64_t kMaxEdges = 1ull << 30;
 

@@ -321,6 +321,47 @@ def test_full_gnp_n2p22_ten_supersteps_properties(ctx):
         assert s["legal"] > 0.99 * s["attempts"]
 
 
+def test_largest_size_gnp_one_superstep():
+    """Close to the largest input (m < 2^30): G(n,p) with n = 2^25 and about
+    6.5e8 edges, where the tuple pass has 2^30 slots and 21 partition bits.
+    One global switch, checked on the device by what holds at any size (the
+    oracle takes minutes here): degrees kept, every edge canonical and in
+    range, no edge twice, outcome counts that add up, and a legal fraction
+    near one for a graph this sparse."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    n = 1 << 25
+    E = graphgen.gnp(n, 38.7 / (n - 1), 41)
+    m = len(E)
+    print("largest-size case: n=%d m=%d" % (n, m), flush=True)
+    assert (1 << 29) < m < (1 << 30)
+    d_in = torch.from_numpy(E.view(np.int64)).to("cuda")
+    del E
+
+    def degrees(d):
+        return (torch.bincount(d >> 32, minlength=n) + torch.bincount(d & 0xFFFFFFFF, minlength=n))
+
+    deg_in = degrees(d_in)
+    c = gesmc.Context(0)
+    try:
+        out, st = c.run(d_in, n, 7, r=1)
+        torch.cuda.synchronize()
+        print("largest-size case: stats", st, flush=True)
+        assert torch.equal(degrees(out), deg_in)
+        u, v = out >> 32, out & 0xFFFFFFFF
+        assert bool((u < v).all()) and bool((v < n).all())
+        del u, v
+        srt, _ = torch.sort(out)
+        assert bool((srt[1:] != srt[:-1]).all())
+        del srt
+        ell = m // 2
+        assert st["attempts"] == ell
+        assert st["legal"] + st["rej_loop"] + st["rej_exists"] + st["rej_pl"] == ell
+        assert st["legal"] > 0.999 * ell
+    finally:
+        c.close()
+
+
 def test_autotuned_context_computes_the_same():
     """The autotuner changes options only: the tuned context reproduces the oracle."""
     _require_gpu()
