@@ -65,8 +65,10 @@ def switch_roofline(value: float, legal_fraction: float, G: int = 64):
     b_txn = G * (4 + 10 * a) + 16
     b_alg = 48 + 48 * a
     bound = HBM_PEAK_GBS * 1e9 / b_txn
+    bound_alg = HBM_PEAK_GBS * 1e9 / b_alg  # byte-level lower bound on the traffic: an upper bound on attempts/s
     return {"G_bytes": G, "bytes_per_attempt_txn": round(b_txn, 1), "bytes_per_attempt_alg": round(b_alg, 1),
-            "bound_attempts_per_s": round(bound, 1), "frac": round(value / bound, 4)}
+            "bound_attempts_per_s": round(bound, 1), "frac": round(value / bound, 4),
+            "bound_attempts_per_s_alg": round(bound_alg, 1), "frac_alg": round(value / bound_alg, 4)}
 
 
 def source_digest() -> str:
@@ -93,6 +95,41 @@ def load_traffic(kernel: str, workload: str):
     if not rec:
         return None
     return rec.get("bytes_per_launch")
+
+
+def host_cpu():
+    """(CPU model, logical CPUs) of the host running the bench."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline_batch(graphs, seeds, r, stride, threads):
+    """The oracle on every stride-th graph of a batch, one graph per task on
+    a thread pool (the oracle's C calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    oracle._load()
+    sample = list(range(0, len(graphs), stride))
+
+    def one(g):
+        E, n = graphs[g]
+        rc, _, counts, _ = oracle.run(E, n, seeds[g], 0, r, 0)
+        return sum(c["attempts"] for c in counts)
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        att = sum(ex.map(one, sample))
+    dt = time.perf_counter() - t
+    return att / dt, dt, len(sample)
 
 
 def cpu_baseline(E, n, r_sample, seed):
@@ -149,6 +186,14 @@ def bench_batched(gesmc, torch, args, plain_value):
     ctx.close()
     print("batched: %.3e attempts/s (%.1f ms per batch); plain loop on every %dth graph: %.3e attempts/s" % (
         value, 1e3 * wall / len(times), args.plain_sample_stride, plain_same), file=sys.stderr)
+    cpu_b = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)  # the machine's CPU share per GPU
+        v, dt, ns_ = cpu_baseline_batch(graphs, seeds, 20, 16, threads)
+        cpu_b = {"value": round(v, 1), "unit": "attempts/s", "cores": threads, "kind": "oracle",
+                 "sample": "every 16th graph (%d graphs), 20 supersteps each, one graph per task on %d threads "
+                           "(%.1f s)" % (ns_, threads, dt)}
+        print("batched: oracle %s" % cpu_b, file=sys.stderr)
     small = bench_small_batches(gesmc, torch, args)
     return {"value": round(value, 1), "unit": "attempts/s", "steps": len(times),
             "ms_per_step": round(1e3 * wall / len(times), 3), "graphs": G, "edges": int(offs[-1]),
@@ -161,6 +206,7 @@ def bench_batched(gesmc, torch, args, plain_value):
             "vs_plain_same_graphs": round(value / plain_same, 2),
             "autotuner": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in tuning.items()},
             "vs_plain_headline": round(value / plain_value, 3) if plain_value else None,
+            "cpu_baseline": cpu_b,
             "small_batches_hipgraph": small}
 
 
@@ -403,13 +449,24 @@ def main():
                     "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 4),
                     "share_of_step": round(ms / (wall * 1e3), 3)}
 
+    # the host entry point on the same workload: edges in and out of host
+    # memory, so both PCIe copies are inside the time (never the headline)
+    uv = np.stack([(E >> np.uint64(32)).astype(np.uint32), (E & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1)
+    ctx.run_host(uv, n, args.seed, 0, r)  # sizes its staging
+    t = time.perf_counter()
+    ctx.run_host(uv, n, args.seed, 0, r)
+    dt_host = time.perf_counter() - t
+    host_api = {"value": round(r * ell / dt_host, 1), "unit": "attempts/s", "ms_per_call": round(1e3 * dt_host, 3),
+                "note": "gesmc_run_host, %d supersteps per call, incl. host->device and device->host copies" % r}
+
     cpu = None
     if not args.no_cpu_baseline:
         rs = min(args.cpu_sample_supersteps, r)
         v, dt = cpu_baseline(E, n, rs, args.seed)
+        model, nproc = host_cpu()
         cpu = {"value": round(v, 1), "unit": "attempts/s", "cores": 1, "kind": "oracle",
                "sample": "%s, first %d of %d supersteps incl. validation and set build (%.1f s)" % (
-                   args.workload, rs, r, dt)}
+                   args.workload, rs, r, dt), "host_cpu": model, "host_logical_cpus": nproc}
 
     ctx.close()
     batched = None if args.no_batched else bench_batched(gesmc, torch, args, value)
@@ -436,6 +493,7 @@ def main():
                    "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
         "roofline": roofline,
         "switch_roofline": switch_roofline(value, stats["legal"] / max(stats["attempts"], 1)) if stats else None,
+        "host_api": host_api,
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,

@@ -96,6 +96,19 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
                        gesmc_step_stats *steps);
 
 /*
+ * Host convenience form of gesmc_run (Alg. 3 on an edge list in host memory):
+ * uv holds the m input edges as 2m vertex ids (u0, v0, u1, v1, ...; either
+ * orientation), uv_out (host, 2m ids, may equal uv) receives the result as
+ * (min, max) pairs in position order.  Runs on the default stream of the
+ * context's device and returns when the result is in uv_out; the edges go
+ * through pinned staging and device buffers owned by the context, so the
+ * time includes both PCIe copies.  Limits, flags, pl, stats and errors as in
+ * gesmc_run; on error uv_out is left untouched.
+ */
+gesmc_status gesmc_run_host(gesmc_ctx *ctx, const uint32_t *uv, uint32_t *uv_out, uint64_t m, uint32_t n,
+                            uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats);
+
+/*
  * G independent graphs in one call: the batched form of gesmc_run.  Graph g
  * is d_in[offsets[g] .. offsets[g+1]) (device memory, uint64 keys of local
  * vertex ids < n[g]); it runs r[g] global switches from superstep t0[g] with

@@ -84,7 +84,7 @@ class ServerInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_batch",
+EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_host", "gesmc_run_batch",
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_run.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
                                   ctypes.POINTER(StepStats)]
         lib.gesmc_run.restype = i32
+        lib.gesmc_run_host.argtypes = [vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats)]
+        lib.gesmc_run_host.restype = i32
         lib.gesmc_run_batch.argtypes = [vp, vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
                                         ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32), u32, u32,
                                         ctypes.POINTER(Stats), ctypes.POINTER(Stats)]
@@ -220,6 +222,20 @@ class Context:
         if steps:
             return out, st.as_dict(), [ss[q].as_dict() for q in range(r)]
         return out, st.as_dict()
+
+    def run_host(self, uv, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0):
+        """gesmc_run_host: edges as host vertex-id pairs (numpy, shape (m, 2) or 2m flat,
+        any orientation) -> (result as an (m, 2) uint32 array of (min, max) pairs, stats)."""
+        import numpy as np
+        a = np.ascontiguousarray(uv, dtype=np.uint32).reshape(-1)
+        if a.size % 2:
+            raise ValueError("uv must hold an even number of vertex ids")
+        m = a.size // 2
+        out = np.empty(2 * m, dtype=np.uint32)
+        st = Stats()
+        _check(_lib.gesmc_run_host(self._h, a.ctypes.data if m else None, out.ctypes.data if m else None, m, n,
+                                   seed & (2**64 - 1), t0, r, pl, 0, ctypes.byref(st)))
+        return out.reshape(m, 2), st.as_dict()
 
     def run_batch(self, edges: torch.Tensor, offsets, n, seed, r, t0=None, pl: int = 0,
                   out: torch.Tensor | None = None, stream=None, stats: bool = True):

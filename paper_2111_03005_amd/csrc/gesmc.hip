@@ -146,6 +146,8 @@ struct gesmc_ctx {
     std::vector<BatchGraph> h_gr;
     std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_rrank;
     std::vector<uint4> h_chunks;   // position chunks of the ranks' segments (k_fill_pg, serving kernels)
+    uint64_t *hr_dev = nullptr, *h_hr = nullptr;  // gesmc_run_host: device in/out (2 x cap), pinned staging
+    uint64_t hr_cap = 0, h_hr_cap = 0;              // words
     unsigned char *h_up = nullptr;  // pinned staging of a call's small uploads (up_begin / up_copy)
     uint64_t up_cap = 0, up_used = 0;
     hipEvent_t up_ev = nullptr;     // recorded after a call's last upload
@@ -1427,6 +1429,8 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->call_a) (void)hipEventDestroy(c->call_a);
     if (c->call_b) (void)hipEventDestroy(c->call_b);
     if (c->h_up) (void)hipHostFree(c->h_up);
+    if (c->h_hr) (void)hipHostFree(c->h_hr);
+    if (c->hr_dev) (void)hipFree(c->hr_dev);
     for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1], c->up_ev})
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : c->side)
@@ -1564,6 +1568,57 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
         return GESMC_E_INVAL;
     }
     return run_impl(ctx, stream, d_in, d_out, m, n, seed, t0, r, pl, stats, steps, nullptr);
+}
+
+gesmc_status gesmc_run_host(gesmc_ctx *c, const uint32_t *uv, uint32_t *uv_out, uint64_t m, uint32_t n,
+                            uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats) {
+    if (!c || (m > 0 && (!uv || !uv_out))) {
+        set_error("null argument");
+        return GESMC_E_INVAL;
+    }
+    if (flags != 0) {
+        set_error("flags must be 0");
+        return GESMC_E_INVAL;
+    }
+    if (m >= kMaxEdges) {
+        set_error("m = %llu exceeds the limit 2^30 - 1", (unsigned long long)m);
+        return GESMC_E_RANGE;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    const uint64_t words = std::max<uint64_t>(m, 1);
+    if (words > c->hr_cap) {
+        if (c->hr_dev) (void)hipFree(c->hr_dev);
+        c->hr_dev = nullptr;
+        c->hr_cap = 0;
+        GESMC_TRY(dev_alloc((void **)&c->hr_dev, 2 * words * 8));
+        c->hr_cap = words;
+    }
+    if (words > c->h_hr_cap) {
+        if (c->h_hr) (void)hipHostFree(c->h_hr);
+        c->h_hr = nullptr;
+        c->h_hr_cap = 0;
+        if (hipHostMalloc((void **)&c->h_hr, words * 8, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipHostMalloc of %llu bytes failed", (unsigned long long)(words * 8));
+            return GESMC_E_NOMEM;
+        }
+        c->h_hr_cap = words;
+    }
+    uint64_t *d_in = c->hr_dev, *d_out = c->hr_dev + c->hr_cap;
+    for (uint64_t i = 0; i < m; ++i) c->h_hr[i] = ((uint64_t)uv[2 * i] << 32) | uv[2 * i + 1];
+    hipStream_t s = nullptr;
+    gesmc_status st = check_hip(hipMemcpyAsync(d_in, c->h_hr, m * 8, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    if (st == GESMC_OK) st = run_impl(c, s, d_in, d_out, m, n, seed, t0, r, pl, stats, nullptr, nullptr);
+    if (st == GESMC_OK)
+        st = check_hip(hipMemcpyAsync(c->h_hr, d_out, m * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    const gesmc_status sy = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");  // staging free again
+    if (st != GESMC_OK) return st;
+    if (sy != GESMC_OK) return sy;
+    for (uint64_t i = 0; i < m; ++i) {
+        uv_out[2 * i] = (uint32_t)(c->h_hr[i] >> 32);
+        uv_out[2 * i + 1] = (uint32_t)c->h_hr[i];
+    }
+    return GESMC_OK;
 }
 
 gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,

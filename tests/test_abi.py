@@ -131,6 +131,7 @@ def test_null_context_rejected_without_gpu(lib):
     import paper_2111_03005_amd as gesmc
     assert lib.gesmc_set_option(None, gesmc.OPT_PROFILE, 1) == gesmc.E_INVAL
     assert lib.gesmc_run(None, None, None, None, 0, 0, 0, 0, 0, 0, 0, None, None) == gesmc.E_INVAL
+    assert lib.gesmc_run_host(None, None, None, 0, 0, 0, 0, 0, 0, 0, None) == gesmc.E_INVAL
     assert b"null" in lib.gesmc_last_error()
     assert lib.gesmc_run_batch(None, None, 1, None, None, None, None, None, None, None, 0, 0, None,
                                None) == gesmc.E_INVAL

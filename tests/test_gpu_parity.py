@@ -224,6 +224,49 @@ def test_size_limits_rejected_on_the_host(ctx):
     check_run(ctx, E, n, 3, 0, 1, label="after_limits")
 
 
+def test_host_entry_point(ctx):
+    """gesmc_run_host (host vertex-id pairs in any orientation) equals
+    gesmc_run on the device and the oracle; the output may alias the input;
+    invalid input leaves the output untouched."""
+    import ctypes
+    import paper_2111_03005_amd as gesmc
+    from paper_2111_03005_amd import _binding as b
+    rng = np.random.default_rng(3)
+    cases = [graphgen.workload_gnp_small(), (graphgen.powerlaw_graph(20000, 2.2, 2, 141, 5), 20000),
+             (keys([(0, 3)]), 4), (keys([(0, 1), (2, 3)]), 4), (keys([(0, 1), (2, 3), (4, 5)]), 6),
+             (np.zeros(0, dtype=np.uint64), 3)]
+    for E, n in cases:
+        uv = np.stack([(E >> np.uint64(32)).astype(np.uint32), (E & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1)
+        flip = rng.random(len(E)) < 0.5
+        uv[flip] = uv[flip][:, ::-1]  # either orientation is accepted
+        got, st = ctx.run_host(uv, n, 17, t0=3, r=4, pl=1 << 29)
+        keys_got = (got[:, 0].astype(np.uint64) << np.uint64(32)) | got[:, 1].astype(np.uint64)
+        rc, exp, counts, _ = oracle_run(E, n, 17, 3, 4, 1 << 29)
+        assert rc == 0
+        assert np.array_equal(keys_got, exp), len(E)
+        dev, _ = ctx.run(to_dev(E), n, 17, t0=3, r=4, pl=1 << 29) if len(E) else (None, None)
+        if len(E):
+            assert np.array_equal(to_host(dev), exp)
+        assert st["attempts"] == sum(c["attempts"] for c in counts)
+        assert st["legal"] == sum(c["legal"] for c in counts)
+    # in place (uv_out == uv)
+    E, n = graphgen.workload_gnp_small()
+    buf = np.stack([(E >> np.uint64(32)).astype(np.uint32), (E & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1).copy()
+    p = ctypes.c_void_p(buf.ctypes.data)
+    st = b.Stats()
+    assert b._lib.gesmc_run_host(ctx._h, p, p, len(E), n, 9, 0, 2, 0, 0, ctypes.byref(st)) == gesmc.OK
+    rc, exp, _, _ = oracle_run(E, n, 9, 0, 2)
+    assert np.array_equal((buf[:, 0].astype(np.uint64) << np.uint64(32)) | buf[:, 1].astype(np.uint64), exp)
+    # invalid input: status, output untouched
+    for pairs, n, code in [([(0, 1), (1, 2), (1, 0)], 3, gesmc.E_NOT_SIMPLE), ([(2, 2), (0, 1)], 3, gesmc.E_NOT_SIMPLE),
+                           ([(0, 1), (1, 7)], 5, gesmc.E_RANGE)]:
+        uv = np.array(pairs, dtype=np.uint32)
+        out = np.full_like(uv, 12345)
+        assert b._lib.gesmc_run_host(ctx._h, ctypes.c_void_p(uv.ctypes.data), ctypes.c_void_p(out.ctypes.data),
+                                     len(uv), n, 1, 0, 2, 0, 0, None) == code
+        assert (out == 12345).all()
+
+
 def test_schedule_independence(ctx):
     """Bucket sizes, LDS sort capacity (incl. the slow exact path) and the
     number of multi-workgroup rounds change the schedule, never the result."""
