@@ -21,7 +21,7 @@
 //   * Alg. 3 (ParGlobalES driver): r global switches in a row.
 //
 // Random choices (the paper uses MT19937-64 + Lemire, Sec. 5.3; that is not
-// reproducible across implementations).  This build fixes them with the
+// reproducible across implementations).  Here they are fixed by the
 // counter-based Philox4x32-10 generator of Salmon, Moraes, Dror and Shaw
 // ("Parallel random numbers: as easy as 1, 2, 3", SC'11):
 //   K_i   = (x0 << 32) | x1 of Philox(ctr = (i, 0, t, 0), key = (seed_lo, seed_hi))
