@@ -33,7 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # counts for that kernel: edges m, switches ell, or table slots).  Random table
 # touches count the 16-byte slot read and written back; records are 12 bytes
 # (4-byte index + 8-byte key).
-def kernel_bytes(name: str, m: int, ell: int) -> float | None:
+def kernel_bytes(name: str, m: int, ell: int, tb: int = 12) -> float | None:
+    """Algorithmic HBM bytes of one launch over m records / ell switches;
+    tb is the dependency tuple size the call reported (12, or 8 packed)."""
     return {
         "k_counts1": 4.0 * m,                            # index of every record (keys recomputed)
         "k_scatter1": 24.0 * m,                          # read + write one 12-byte record per edge
@@ -44,13 +46,13 @@ def kernel_bytes(name: str, m: int, ell: int) -> float | None:
         "k_decide_first": 24.0 * ell + 8.0 * ell + 2 * 8.0 * ell + 24.0 * ell + 2.0 * ell,
         "k_unpermute": 12.0 * m + 8.0 * m,
         "k_load": 8.0 * m + 12.0 * m,
-        # sorted-tuples dependency resolution: 4 tuples of 12 bytes per switch
+        # sorted-tuples dependency resolution: 4 tuples of tb bytes per switch
         "k_emit": 24.0 * ell + 16.0 * ell + 1.0 * ell,   # pair records in, free target records + statuses out
         "k_tcounts1": 24.0 * ell,                        # pair records (tuples computed from them)
-        "k_tscatter1": 24.0 * ell + 48.0 * ell,          # pair records in, partitioned tuples out
-        "k_tcounts2": 32.0 * ell,
-        "k_tscatter2": 48.0 * ell + 48.0 * ell,
-        "k_resolve": 48.0 * ell,                         # tuples in (records out are rare)
+        "k_tscatter1": 24.0 * ell + 4.0 * tb * ell,      # pair records in, partitioned tuples out
+        "k_tcounts2": 32.0 * ell,                        # the 8-byte key (or packed) word of each tuple
+        "k_tscatter2": 8.0 * tb * ell,
+        "k_resolve": 4.0 * tb * ell,                     # tuples in (records out are rare)
         "k_decide_chain1": 16.0 * ell + 24.0 * ell + 24.0 * ell + 2.0 * ell,
     }.get(name)
 
@@ -402,16 +404,17 @@ def main():
     ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
     ctx.profile_reset()
     for w in range(max(args.warmup, 1)):
-        ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
+        _, wst = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
         if w == 0:
             torch.cuda.synchronize()
             ctx.set_option(gesmc.OPT_PROFILE, 0)
     torch.cuda.synchronize()
     warm_prof = ctx.profile()
+    tb = int(wst["tuple_bytes"]) or 12
     dominant = None
     for name, (ms, launches, items) in sorted(warm_prof.items(), key=lambda kv: -kv[1][0]):
         print("warm-up kernel %-16s total %9.3f ms  launches %5d" % (name, ms, launches), file=sys.stderr)
-        if dominant is None and kernel_bytes(name, m, ell) is not None:
+        if dominant is None and kernel_bytes(name, m, ell, tb) is not None:
             dominant = name
 
     if dominant is not None:
@@ -438,7 +441,7 @@ def main():
     roofline = None
     if dominant is not None and dominant in prof:
         ms, launches, items = prof[dominant]
-        b = kernel_bytes(dominant, m, ell)
+        b = kernel_bytes(dominant, m, ell, tb)
         avg_s = ms / launches / 1e3
         achieved = b / avg_s / 1e9
         print("timed kernel %s: %d launches, avg %.4f ms, %.0f GB/s" % (dominant, launches, avg_s * 1e3, achieved),
@@ -489,6 +492,7 @@ def main():
                    "attempts_per_step": r * ell, "seed": args.seed, "pl": 0, "mode": "plain",
                    "legal_fraction": round(stats["legal"] / max(stats["attempts"], 1), 5) if stats else None,
                    "rounds_max": stats["rounds_max"] if stats else None,
+                   "tuple_bytes": int(stats["tuple_bytes"]) if stats else None,
                    "step_ms_device_p50": round(float(np.median(step_ms)), 3) if step_ms else None,
                    "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
         "roofline": roofline,

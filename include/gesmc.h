@@ -60,6 +60,10 @@ typedef struct gesmc_stats {
     uint32_t rounds_max; /* most rounds in one superstep                        */
     uint32_t supersteps; /* r                                                   */
     double ms_device;    /* device time of the whole call (HIP events)          */
+    uint32_t tuple_bytes; /* bytes per dependency tuple in the call's last
+                             superstep: 8 (packed words, GESMC_OPT_PACK_TUPLES),
+                             12, or 0 if no superstep ran the tuple passes     */
+    uint32_t reserved;   /* 0                                                   */
 } gesmc_stats;
 
 /* Per superstep (same meaning as above; `rounds` counts the decision rounds of
@@ -265,6 +269,10 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
 #define GESMC_OPT_SMALL_GRAPHS 11  /* 1: in gesmc_run_batch, graphs of at most 1024 edges run all their
                                       supersteps in one workgroup's LDS (one launch for all of them);
                                       0: every graph takes the multi-kernel supersteps (default 1)   */
+#define GESMC_OPT_PACK_TUPLES 12   /* 1: dependency tuples travel as one 8-byte word (a bijective hash of
+                                      the edge key on 2 x the vertex id bits, minus the bits the first
+                                      partition pass implies, over a coded tag) wherever those bits and
+                                      the tag fit 64; 0: always (tag u32, key hash u64) (default 1)    */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

@@ -23,6 +23,7 @@ OPT_LEVEL1_BITS = 8
 OPT_FUSE_EMIT = 9
 OPT_GRAPH = 10
 OPT_SMALL_GRAPHS = 11
+OPT_PACK_TUPLES = 12
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 
@@ -35,7 +36,8 @@ class GesmcError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("rej_loop", ctypes.c_uint64),
                 ("rej_exists", ctypes.c_uint64), ("rej_pl", ctypes.c_uint64), ("rounds_sum", ctypes.c_uint64),
-                ("rounds_max", ctypes.c_uint32), ("supersteps", ctypes.c_uint32), ("ms_device", ctypes.c_double)]
+                ("rounds_max", ctypes.c_uint32), ("supersteps", ctypes.c_uint32), ("ms_device", ctypes.c_double),
+                ("tuple_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: (float(getattr(self, f)) if f == "ms_device" else int(getattr(self, f))) for f, _ in self._fields_}

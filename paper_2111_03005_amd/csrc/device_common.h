@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tuple_pack.h"
+
 namespace gesmc {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
@@ -123,12 +125,6 @@ __device__ __forceinline__ Targets switch_targets(uint64_t e1, uint64_t e2, bool
     T.B = ekey(v, b1);
     return T;
 }
-
-// Dependency tuples (tag, edge key): an ERASE tuple carries the switch that
-// erases its key (or kTagStays for an edge that survives the superstep), an
-// INSERT tuple kTagInsert | (k << 1 | h) for target h of switch k.
-constexpr uint32_t kTagInsert = 0x80000000u;
-constexpr uint32_t kTagStays = 0x7FFFFFFEu;
 
 // Permutation key of record (input position idx) of graph g in batch superstep s.
 __device__ __forceinline__ uint64_t batch_perm_key(const BatchGraph &g, uint32_t idx, uint32_t s) {

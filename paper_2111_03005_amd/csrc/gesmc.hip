@@ -156,6 +156,8 @@ struct gesmc_ctx {
     uint64_t chunk_cap = 0;
     uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
     bool small_graphs = true;                         // graphs with m <= kSmallMax run in LDS
+    bool pack_tuples = true;                          // 8-byte tuple words where the bits allow
+    uint32_t tuple_bytes = 0;                         // tuple size of the call's last superstep
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
     uint64_t ctr_cap = 0;
@@ -403,11 +405,12 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
     return p;
 }
 
-// LDS of k_scatter: counters, staged indices, keys and digits, and (batch
-// level 1 only) staged global buckets.  It bounds the workgroups per CU.
-size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true) {
+// LDS of k_scatter: counters, staged indices (none for packed tuple
+// words), keys and digits, and (batch level 1 only) staged global buckets.
+// It bounds the workgroups per CU.
+size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true, bool idx = true) {
     const size_t nd = (size_t)1 << dbits;
-    size_t words = 3 * nd + scatter_threads((int)tile) / 64 + 1 + tile;
+    size_t words = 3 * nd + scatter_threads((int)tile) / 64 + 1 + (idx ? tile : 0);
     words += words & 1;  // 8-byte alignment of the key stage
     return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (buckets ? (size_t)tile * 4 : 0);
 }
@@ -421,7 +424,9 @@ void set_scatter_lds_limits_one() {
                           (const void *)k_scatter<kSrcBatch, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcBucket, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcEmit, kTile, scatter_threads(kTile), kOne>,
-                          (const void *)k_scatter<kSrcHashed, kTile, scatter_threads(kTile), kOne>})
+                          (const void *)k_scatter<kSrcHashed, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcEmitPacked, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcPacked, kTile, scatter_threads(kTile), kOne>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(kMaxLevelBits, kTile));
 }
@@ -504,8 +509,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
-    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch);
-    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch);
+    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, kSrc1 != kSrcEmitPacked);
+    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
                      dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr, (const uint32_t *)nullptr,
@@ -519,7 +524,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const uint32_t nd2 = 1u << p.b2;
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
     GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
-    const int shift2 = 64 - (int)p.bbits;
+    // packed words lost the first level's bits: the second level's are on top
+    const int shift2 = kSrc2 == kSrcPacked ? 64 - (int)p.b2 : 64 - (int)p.bbits;
     GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile, false>,
                      dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile, false>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
                      (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, 0u,
@@ -561,6 +567,7 @@ struct BatchStep {
     uint32_t *bk;              // device: global bucket of each record between the radix levels
     unsigned long long *acc;   // device: per-rank outcome counts (nullable)
     GraphErr ge;               // per-rank error attribution (gr = nullptr: none)
+    uint64_t vend;             // vertex ids of the switched ranks are below this
 };
 
 // Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t --
@@ -626,12 +633,55 @@ struct EmitSource {
     SrcArgs sa;
 };
 
+// Bits of x - 1 (x >= 1): the width of the values [0, x).
+int width_below(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x - 1) >> b) ++b;
+    return b;
+}
+
+// Packed 8-byte tuple words (TuplePack) for nslots tuple slots of keys with
+// vertex ids below vend, if the bits allow: the hash bits left after the
+// first level plus the tag code fit 64 bits, and at least kCellBits hash bits
+// remain below both levels for the resolve's cells.  w = 0: 12-byte tuples.
+TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_t vend) {
+    TuplePack pk{0, 0, 0, 0, 0};
+    if (!c->pack_tuples || vend < 2) return pk;
+    const int vb = width_below(vend), w = 2 * vb;
+    const int kb = std::max(1, width_below(2ull * (nslots / 4) + 1));  // 2 ell <= 2^kb, ell < 2^kb - 1
+    if (w > 62 || w - (int)p.b1 + kb + 1 > 64 || w - (int)p.bbits < kCellBits) return pk;
+    pk.w = w;
+    pk.vb = vb;
+    pk.kb = kb;
+    pk.b1 = (int)p.b1;
+    pk.b2 = (int)p.b2;
+    return pk;
+}
+
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
-                                   GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr) {
+                                   GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr,
+                                   uint64_t vend = 0) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
+    const TuplePack pk = emit ? tuple_pack(c, p, nslots, vend) : TuplePack{0, 0, 0, 0, 0};
+    c->tuple_bytes = pk.w ? 8u : 12u;
+    if (pk.w) {
+        SrcArgs sa = emit->sa;
+        sa.pk = pk;
+        GESMC_TRY((radix_distribute<kSrcEmitPacked, kSrcPacked>(
+            c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts,
+            &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
+            emit->sk)));
+        const int scratch = parts == 2 ? 1 : 0;
+        const size_t rlds = resolve_lds_bytes(c->sort_cap);
+        GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<true>,
+                         dim3(persistent_blocks(c, k_resolve<true>, rlds, np)), dim3(kBlock), rlds, c->tu_tag[parts],
+                         c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.b2, poff, np, c->sort_cap,
+                         c->info, c->err, dup_bit, c->ctr_step, ge, pk));
+        return GESMC_OK;
+    }
     if (emit)
         GESMC_TRY((radix_distribute<kSrcEmit, kSrcHashed>(c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag,
                                                         c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts, &poff, &np,
@@ -644,15 +694,17 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
                                                         SrcArgs{})));
     const int scratch = parts == 2 ? 1 : 0;
     const size_t rlds = resolve_lds_bytes(c->sort_cap);
-    GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve, dim3(persistent_blocks(c, k_resolve, rlds, np)),
-                     dim3(kBlock), rlds, c->tu_tag[parts], c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch],
-                     (int)p.bbits, poff, np, c->sort_cap, c->info, c->err, dup_bit, c->ctr_step, ge));
+    GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<false>,
+                     dim3(persistent_blocks(c, k_resolve<false>, rlds, np)), dim3(kBlock), rlds, c->tu_tag[parts],
+                     c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.bbits, poff, np, c->sort_cap,
+                     c->info, c->err, dup_bit, c->ctr_step, ge, TuplePack{0, 0, 0, 0, 0}));
     return GESMC_OK;
 }
 
 // One superstep with the partitioned resolution (state in buffer 0).
+// vend bounds the vertex ids of the keys (a batch: bs->vend).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
-                                   uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr) {
+                                   uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0) {
     int sorted = 0;
     GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs));
     const uint32_t *si = c->idx[sorted];
@@ -673,7 +725,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
         GESMC_TRY(launch(c, s, KID_EMIT, nslots, k_emit_tuples, dim3(grid_stride_blocks(c, nslots)), dim3(kBlock), 0,
                          si, sk, t, k0, k1, sa, nslots, c->tu_tag[0], c->tu_key[0]));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr},
-                                    c->fuse_emit ? &es : nullptr));
+                                    c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -794,6 +846,7 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     GESMC_TRY(ensure_capacity(c, m));
     GESMC_TRY(ensure_counters(c, r));
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    c->tuple_bytes = 0;
     GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
     const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(r, 1) * (sizeof(StepCounters) / 4);
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
@@ -825,7 +878,7 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
             if (c->strategy == 1)
                 GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, dup));
             else
-                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup));
+                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup, nullptr, n));
         }
     }
     if (d_outcome && p.ell > 0)
@@ -869,6 +922,7 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
             stats->ms_device = ms;
         else
             (void)hipGetLastError();
+        stats->tuple_bytes = c->tuple_bytes;
     }
     return GESMC_OK;
 }
@@ -1130,6 +1184,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     // outside the graph; the first call of a shape runs eagerly, so every
     // buffer is sized before a capture.
     auto device_work = [&]() -> gesmc_status {
+        c->tuple_bytes = 0;
         const uint64_t zero_words = 64 + (uint64_t)std::max<uint32_t>(rmax, 1) * (sizeof(StepCounters) / 4);
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(16), dim3(256), 0, (uint32_t *)c->ctr, zero_words - 64));
@@ -1186,7 +1241,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
             const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
             const Plan p = batch_plan(c, P, NB);
-            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all};
+            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase};
             c->ctr_step = c->ctr + st;
             GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
         }
@@ -1216,6 +1271,8 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         mix(c->level1_cap);
         mix(c->fuse_emit);
         mix(c->small_graphs);
+        mix(c->pack_tuples);
+        mix(vbase);  // the tuple layout depends on the vertex id width (n may change between replays)
         mix((uint64_t)c->persist_mult);
         mix(g_alloc_epoch.load());
         mix((uint64_t)(uintptr_t)s);
@@ -1306,6 +1363,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
                 o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)c->h_ctr[st].rounds);
             }
             o.ms_device = ms;
+            o.tuple_bytes = r_pipe(g) > 0 ? c->tuple_bytes : 0u;
         }
     }
     if (total) {
@@ -1329,6 +1387,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             total->supersteps = std::max(total->supersteps, c->h_rrank[q]);
         }
         total->ms_device = ms;
+        total->tuple_bytes = c->tuple_bytes;
     }
     return GESMC_OK;
 }
@@ -1387,8 +1446,8 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
                               (int)sort_lds_bytes(kLdsCap));
     set_scatter_lds_limits<kTileSmall>();
     set_scatter_lds_limits<kTileLarge>();
-    (void)hipFuncSetAttribute((const void *)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)resolve_lds_bytes(kLdsCap));
+    for (const void *f : {(const void *)k_resolve<false>, (const void *)k_resolve<true>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)resolve_lds_bytes(kLdsCap));
     (void)hipGetLastError();
     if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
         hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
@@ -1706,6 +1765,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
         case GESMC_OPT_SMALL_GRAPHS:
             if (v < 0 || v > 1) break;
             c->small_graphs = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_PACK_TUPLES:
+            if (v < 0 || v > 1) break;
+            c->pack_tuples = v != 0;
             return GESMC_OK;
         case GESMC_OPT_GRAPH:
             if (v < 0 || v > 1) break;

@@ -154,7 +154,18 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
 // the record's position (level 1) and writes it out beside the record,
 // kSrcBucket reads it back (level 2).  Bucket numbers are placed in the top
 // B bits of the radix word, so both levels use the same shifts.
-enum RadixSrc : int { kSrcPerm = 0, kSrcHash = 1, kSrcBatch = 2, kSrcBucket = 3, kSrcEmit = 4, kSrcHashed = 5 };
+// kSrcEmitPacked is kSrcEmit writing packed 8-byte tuple words (TuplePack)
+// and kSrcPacked the second level over them: no tag array is read or written.
+enum RadixSrc : int {
+    kSrcPerm = 0,
+    kSrcHash = 1,
+    kSrcBatch = 2,
+    kSrcBucket = 3,
+    kSrcEmit = 4,
+    kSrcHashed = 5,
+    kSrcEmitPacked = 6,
+    kSrcPacked = 7
+};
 
 struct SrcArgs {
     const BatchGraph *gr;    // per graph (batches)
@@ -166,16 +177,23 @@ struct SrcArgs {
     const uint32_t *pg;      // batch: graph of each position (nullptr: one graph)
     uint32_t m;              // records (the pair records of ell = m / 2 switches)
     uint32_t pl;             // P_L threshold (batch: nonzero if some graph has one)
+    TuplePack pk;            // kSrcEmitPacked: hash width, vertex and tag code bits
 };
 
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_idx() { return kSrc == kSrcPerm || kSrc == kSrcBatch; }
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcBatch || kSrc == kSrcBucket; }
+// Tuple sources whose slots may be empty (kEmptyKey); the second level over
+// packed words has none (every word is a tuple, and any word value occurs).
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_is_tuple() {
-    return kSrc == kSrcHash || kSrc == kSrcEmit || kSrc == kSrcHashed;
+    return kSrc == kSrcHash || kSrc == kSrcEmit || kSrc == kSrcHashed || kSrc == kSrcEmitPacked;
 }
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_emits() { return kSrc == kSrcEmit || kSrc == kSrcEmitPacked; }
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_packed() { return kSrc == kSrcEmitPacked || kSrc == kSrcPacked; }
 
 // Local outcome of switch k from its pair records (ij, ee): P_L skip, the
 // idle pair of a batch graph's padding record, a loop, or a target equal to
@@ -233,8 +251,10 @@ __device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, cons
 
 // kSrcEmit tiles: each thread takes whole switches, so the four slots of a
 // switch are items 4j .. 4j+3 of one thread (slot order inside a tile does
-// not matter: partitions are sorted later).
-template <int kTileItems, int kThreads>
+// not matter: partitions are sorted later).  kPacked: tag codes and the
+// w-bit key hash aligned to the top of the word (the radix word); the
+// scatter packs them.
+template <int kTileItems, int kThreads, bool kPacked>
 __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const uint32_t *si,
                                           const unsigned long long *sk, uint32_t t, uint32_t k0, uint32_t k1,
                                           const SrcArgs &sa, uint32_t *tag, unsigned long long *key) {
@@ -246,8 +266,15 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
         if (sl < cnt) emit_switch((begin + sl) >> 2, si, sk, t, k0, k1, sa, tp);
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            tag[4 * j + h] = tp[h].tag;
-            key[4 * j + h] = sl + h < cnt ? tuple_hash(tp[h].key) : kEmptyKey;
+            if (kPacked) {
+                tag[4 * j + h] = tag_code(tp[h].tag, sa.pk.kb);
+                key[4 * j + h] = (sl + h < cnt && tp[h].key != kEmptyKey)
+                                     ? key_hash_w(tp[h].key, sa.pk.vb, sa.pk.w) << (64 - sa.pk.w)
+                                     : kEmptyKey;
+            } else {
+                tag[4 * j + h] = tp[h].tag;
+                key[4 * j + h] = sl + h < cnt ? tuple_hash(tp[h].key) : kEmptyKey;
+            }
         }
     }
 }
@@ -272,7 +299,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
 template <int kSrc>
 __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long key, uint32_t aux, uint32_t t,
                                                uint32_t k0, uint32_t k1, const SrcArgs &ba, uint32_t *bucket) {
-    if (src_is_tuple<kSrc>()) return key;  // tuple words are tuple hashes (see the loads)
+    if (src_is_tuple<kSrc>() || kSrc == kSrcPacked) return key;  // tuple hashes or packed words (see the loads)
     if (kSrc == kSrcPerm) return perm_key(idx, t, k0, k1);
     uint32_t b = aux;
     if (kSrc == kSrcBatch) {
@@ -348,8 +375,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         const TileSpan ts = tile_span<kTile, kOne>(seg_off, tile_first, nseg, n1, w);
         uint32_t cur_i[kTileItems], cur_a[kTileItems];
         unsigned long long cur_k[kTileItems];
-        if (kSrc == kSrcEmit) {
-            emit_tile<kTileItems, kBlock>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, cur_i, cur_k);
+        if (src_emits<kSrc>()) {
+            emit_tile<kTileItems, kBlock, kSrc == kSrcEmitPacked>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba,
+                                                                  cur_i, cur_k);
         } else {
 #pragma unroll
             for (int q = 0; q < kTileItems; ++q) {
@@ -359,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
                 cur_a[q] = 0u;
                 cur_k[q] = kEmptyKey;
                 if (kSrc == kSrcHash && in) cur_k[q] = tuple_hash(src_key[ts.begin + p]);
-                if (kSrc == kSrcHashed && in) cur_k[q] = src_key[ts.begin + p];
+                if ((kSrc == kSrcHashed || kSrc == kSrcPacked) && in) cur_k[q] = src_key[ts.begin + p];
                 if (src_reads_idx<kSrc>() && in) cur_i[q] = src_idx[ts.begin + p];
                 if (src_reads_aux<kSrc>() && in) cur_a[q] = ba.aux_in[ts.begin + p];
             }
@@ -369,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
 #pragma unroll
         for (int q = 0; q < kTileItems; ++q) {
             const uint32_t p = tid + q * kBlock;
-            if (kSrc != kSrcEmit && p >= ts.cnt) continue;  // (emit tiles mark missing slots empty)
+            if (!src_emits<kSrc>() && p >= ts.cnt) continue;  // (emit tiles mark missing slots empty)
             if (src_is_tuple<kSrc>() && cur_k[q] == kEmptyKey) continue;
             uint32_t bk = 0;
             const uint64_t word = radix_word<kSrc>(cur_i[q], cur_k[q], cur_a[q], t, k0, k1, ba, &bk);
@@ -520,9 +548,11 @@ __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ count
 // Records of one digit leave the workgroup as one contiguous run starting at
 // the run base offs[w][d].  With a tuple source, slots whose key is empty
 // are dropped; with kSrcBatch the record's global bucket is written to
-// ba.aux_out beside it.  One workgroup per tile (grid-stride if the grid is
-// smaller).  Dynamic LDS: 3 * 2^dbits + kThreads / 64 + 1 words of counters, then
-// the staged records (scatter_lds_bytes on the host).
+// ba.aux_out beside it.  Packed sources move key words only; kSrcEmitPacked
+// packs each tuple as it is staged, dropping the dbits digit bits.  One
+// workgroup per tile (grid-stride if the grid is smaller).  Dynamic LDS:
+// 3 * 2^dbits + kThreads / 64 + 1 words of counters, then the staged records
+// (scatter_lds_bytes on the host).
 
 template <int kSrc, int kTile, int kThreads, bool kOne>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict__ src_idx,
@@ -538,14 +568,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
     __shared__ uint32_t s_total;
     constexpr int kTileItems = kTile / kThreads;
     constexpr uint32_t kScanWords = kThreads / 64 + 1;
+    constexpr uint32_t kIdxWords = src_packed<kSrc>() ? 0u : (uint32_t)kTile;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
     uint32_t *base = start + nd;         // nd (global run base)
     uint32_t *tmp = base + nd;           // kThreads / 64 + 1
-    uint32_t *s_idx = tmp + kScanWords;  // kTile
+    uint32_t *s_idx = tmp + kScanWords;  // kTile (none for packed words)
     unsigned long long *s_key =
-        reinterpret_cast<unsigned long long *>(s_idx + kTile + ((kScanWords + 3 * nd + kTile) & 1));
+        reinterpret_cast<unsigned long long *>(s_idx + kIdxWords + ((kScanWords + 3 * nd + kIdxWords) & 1));
     uint16_t *s_dig = reinterpret_cast<uint16_t *>(s_key + kTile);
     uint32_t *s_bkt = reinterpret_cast<uint32_t *>(s_dig + kTile);  // kSrcBatch only
 
@@ -556,14 +587,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
         const TileSpan ts = tile_span<kTile, kOne>(seg_off, tile_first, nseg, n1, w);
         uint32_t c_idx[kTileItems], c_aux[kTileItems];
         unsigned long long c_key[kTileItems];
-        if (kSrc == kSrcEmit) {
-            emit_tile<kTileItems, kThreads>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba, c_idx, c_key);
+        if (src_emits<kSrc>()) {
+            emit_tile<kTileItems, kThreads, kSrc == kSrcEmitPacked>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1,
+                                                                    ba, c_idx, c_key);
         } else {
 #pragma unroll
             for (int q = 0; q < kTileItems; ++q) {
                 const uint32_t p = tid + q * kThreads;
                 const bool in = p < ts.cnt;
-                c_idx[q] = in ? src_idx[ts.begin + p] : 0u;
+                c_idx[q] = (!src_packed<kSrc>() && in) ? src_idx[ts.begin + p] : 0u;
                 c_key[q] = in ? src_key[ts.begin + p] : kEmptyKey;
                 if (kSrc == kSrcHash) c_key[q] = tuple_hash(c_key[q]);  // empty stays empty
                 c_aux[q] = (src_reads_aux<kSrc>() && in) ? ba.aux_in[ts.begin + p] : 0u;
@@ -581,7 +613,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
             const uint32_t p = tid + q * kThreads;
             r_dig[q] = 0xFFFFFFFFu;
             r_bkt[q] = 0;
-            if ((kSrc == kSrcEmit || p < ts.cnt) && (!src_is_tuple<kSrc>() || c_key[q] != kEmptyKey)) {
+            if ((src_emits<kSrc>() || p < ts.cnt) && (!src_is_tuple<kSrc>() || c_key[q] != kEmptyKey)) {
                 const uint64_t word = radix_word<kSrc>(c_idx[q], c_key[q], c_aux[q], t, k0, k1, ba, &r_bkt[q]);
                 r_dig[q] = (uint32_t)(word >> shift) & dmask;
                 r_rank[q] = atomicAdd(&cnt[r_dig[q]], 1u);
@@ -596,8 +628,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
         for (int q = 0; q < kTileItems; ++q) {
             if (r_dig[q] != 0xFFFFFFFFu) {
                 const uint32_t lp = start[r_dig[q]] + r_rank[q];
-                s_idx[lp] = c_idx[q];
-                s_key[lp] = c_key[q];
+                if (!src_packed<kSrc>()) s_idx[lp] = c_idx[q];
+                // kSrcEmitPacked: the tag code goes below the hash bits left after this level's digit
+                s_key[lp] = kSrc == kSrcEmitPacked ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
                 s_dig[lp] = (uint16_t)r_dig[q];
                 if (kSrc == kSrcBatch) s_bkt[lp] = r_bkt[q];
                 ++mine;
@@ -610,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
             const uint32_t d = s_dig[lp];
             const uint32_t g = base[d] + (lp - start[d]);
             if (g >= ts.seg_begin && g < ts.seg_end) {
-                dst_idx[g] = s_idx[lp];
+                if (!src_packed<kSrc>()) dst_idx[g] = s_idx[lp];
                 dst_key[g] = s_key[lp];
                 if (kSrc == kSrcBatch) ba.aux_out[g] = s_bkt[lp];
             } else {

@@ -124,11 +124,20 @@ struct GraphErr {
     uint32_t *gerr;        // per graph error bits
 };
 
-__device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t *err, uint32_t dup_bit,
-                                               const GraphErr &ge) {
+// `key` is a tuple hash, or (pk.w > 0) a packed word with its tag code
+// cleared; f is the tuple's partition, whose first-level digit restores the
+// hash bits the packed word dropped.
+__device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t f, const TuplePack &pk, uint32_t *err,
+                                               uint32_t dup_bit, const GraphErr &ge) {
     if (dup_bit) atomicOr(err, dup_bit);
     if (ge.gr) {
-        const uint32_t v = (uint32_t)(tuple_key_of(key) >> 32);
+        uint32_t v;
+        if (pk.w) {
+            const uint64_t h = ((uint64_t)(f >> pk.b2) << (pk.w - pk.b1)) | (key >> (64 - pk.w + pk.b1));
+            v = key_hash_w_vertex(h, pk.vb, pk.w);
+        } else {
+            v = (uint32_t)(tuple_key_of(key) >> 32);
+        }
         uint32_t lo = 0, hi = ge.ngraphs - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
@@ -145,11 +154,12 @@ __device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t 
 // of the first tuple of its key.  A second ERASE tuple means the edge occurs
 // twice: dup_bit is raised (and the graph flagged in a batch).
 __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, uint32_t p, uint32_t first,
-                                            uint32_t prev_tag, unsigned long long key, uint2 *info, uint32_t *err,
-                                            uint32_t dup_bit, const GraphErr &ge) {
+                                            uint32_t prev_tag, unsigned long long key, uint32_t f,
+                                            const TuplePack &pk, uint2 *info, uint32_t *err, uint32_t dup_bit,
+                                            const GraphErr &ge) {
     const bool ins = (tag & kTagInsert) != 0;
     if (!ins) {
-        if (p != first) flag_duplicate(key, err, dup_bit, ge);
+        if (p != first) flag_duplicate(key, f, pk, err, dup_bit, ge);
         return;
     }
     uint32_t eraser = kNoEraser;
@@ -163,13 +173,16 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
 // each tuple then reads its own cell.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
 // Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 14 bytes
-// (keys, tags and the 16-bit cell-list links).
+// (keys, tags and the 16-bit cell-list links).  kPacked: the tuples are
+// packed words (no tag array); pbits is then the second level's bits only,
+// the first level's having been dropped from the words.
+template <bool kPacked>
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_tag, unsigned long long *__restrict__ tu_key,
                                                     uint32_t *__restrict__ sc_tag,
                                                     unsigned long long *__restrict__ sc_key, int pbits,
                                                     const uint32_t *__restrict__ part_off, uint32_t np, uint32_t cap,
                                                     uint2 *__restrict__ info, uint32_t *__restrict__ err,
-                                                    uint32_t dup_bit, StepCounters *ctr, GraphErr ge) {
+                                                    uint32_t dup_bit, StepCounters *ctr, GraphErr ge, TuplePack pk) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t kCells = 1u << kCellBits;
     uint32_t *cell = lds;
@@ -179,6 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
     const uint32_t tid = threadIdx.x;
     const int sub_shift = 64 - kCellBits;
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
+    const uint64_t code_mask = kPacked ? low_mask(pk.kb + 1) : 0ull;
 
     for (uint32_t f = blockIdx.x; f < np; f += gridDim.x) {
         const uint32_t begin = part_off[f], end = part_off[f + 1];
@@ -187,11 +201,73 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
 #pragma unroll
         for (int q = 0; q < kSortMaxItems; ++q) {
             const uint32_t p = begin + tid + q * kBlock;
-            c_tag[q] = p < end ? tu_tag[p] : 0u;
-            c_key[q] = p < end ? tu_key[p] : 0ull;
+            if (kPacked) {
+                // raw words, decoded at their first use below: the loads stay in
+                // flight across the cell initialisation and its barrier
+                c_tag[q] = 0u;
+                c_key[q] = p < end ? tu_key[p] : 0ull;
+            } else {
+                c_tag[q] = p < end ? tu_tag[p] : 0u;
+                c_key[q] = p < end ? tu_key[p] : 0ull;
+            }
         }
         const uint32_t c = end > begin ? end - begin : 0;
-        if (c > lds_cap) {
+        if (kPacked && c > lds_cap) {
+            // exact slow path over packed words: their order is (key, tag)
+            // order, so a merge sort of the words is the sort by (key, tag)
+            unsigned long long *ak = tu_key + begin, *bk = sc_key + begin;
+            for (uint32_t width = 1; width < c; width <<= 1) {
+                for (uint32_t p = tid; p < c; p += kBlock) {
+                    const uint32_t run = p / (2 * width);
+                    const uint32_t lo = run * 2 * width, mid = min(lo + width, c), hi = min(lo + 2 * width, c);
+                    const unsigned long long kp = ak[p];
+                    uint32_t pos;
+                    if (p < mid) {  // rank among the right run: words strictly smaller
+                        uint32_t a = mid, b = hi;
+                        while (a < b) {
+                            const uint32_t x = (a + b) >> 1;
+                            if (ak[x] < kp)
+                                a = x + 1;
+                            else
+                                b = x;
+                        }
+                        pos = lo + (p - lo) + (a - mid);
+                    } else {  // rank among the left run: words smaller or equal
+                        uint32_t a = lo, b = mid;
+                        while (a < b) {
+                            const uint32_t x = (a + b) >> 1;
+                            if (ak[x] <= kp)
+                                a = x + 1;
+                            else
+                                b = x;
+                        }
+                        pos = lo + (p - mid) + (a - lo);
+                    }
+                    bk[pos] = kp;
+                }
+                __threadfence_block();
+                __syncthreads();
+                unsigned long long *xk = ak;
+                ak = bk;
+                bk = xk;
+            }
+            for (uint32_t p = tid; p < c; p += kBlock) {
+                const unsigned long long kp = ak[p] & ~code_mask;
+                uint32_t a = 0, b = p;
+                while (a < b) {
+                    const uint32_t x = (a + b) >> 1;
+                    if ((ak[x] & ~code_mask) < kp)
+                        a = x + 1;
+                    else
+                        b = x;
+                }
+                const auto tag_at = [&](uint32_t x) { return tag_of_code((uint32_t)(ak[x] & code_mask), pk.kb); };
+                resolve_one(tag_at(p), tag_at(a), p, a, p > 0 ? tag_at(p - 1) : 0u, kp, f, pk, info, err, dup_bit,
+                            ge);
+            }
+            if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
+            __syncthreads();
+        } else if (c > lds_cap) {
             // exact slow path: bottom-up merge sort by (key, tag) between the
             // partition's range and the scratch range, then binary searches.
             uint32_t *at = tu_tag + begin, *bt = sc_tag + begin;
@@ -246,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                     else
                         b = x;
                 }
-                resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, kp, info, err, dup_bit, ge);
+                resolve_one(at[p], at[a], p, a, p > 0 ? at[p - 1] : 0u, kp, f, pk, info, err, dup_bit, ge);
             }
             if (tid == 0) atomicAdd(&ctr->fallback_buckets, 1ull);
             __syncthreads();
@@ -261,6 +337,10 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             for (int q = 0; q < kSortMaxItems; ++q) {
                 const uint32_t p = tid + q * kBlock;
                 if (p < c) {
+                    if (kPacked) {  // the key bits stay in place (cells, equality); the code is the tag
+                        c_tag[q] = tag_of_code((uint32_t)(c_key[q] & code_mask), pk.kb);
+                        c_key[q] &= ~code_mask;
+                    }
                     const uint64_t hsh = c_key[q];  // tuple words are tuple hashes
                     r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
                     sK[p] = c_key[q];
@@ -290,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                         before = true;
                     }
                 }
-                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, info, err, dup_bit, ge);
+                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, f, pk, info, err, dup_bit, ge);
             }
         } else if (c > 0) {  // counting sort into cell order
             for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0;
@@ -300,6 +380,10 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             for (int q = 0; q < kSortMaxItems; ++q) {
                 const uint32_t p = tid + q * kBlock;
                 if (p < c) {
+                    if (kPacked) {
+                        c_tag[q] = tag_of_code((uint32_t)(c_key[q] & code_mask), pk.kb);
+                        c_key[q] &= ~code_mask;
+                    }
                     const uint64_t hsh = c_key[q];  // tuple words are tuple hashes
                     r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
                     r_rank[q] = atomicAdd(&cell[r_cell[q]], 1u);
@@ -342,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                         before = true;
                     }
                 }
-                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, info, err, dup_bit, ge);
+                resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, f, pk, info, err, dup_bit, ge);
             }
             lds_barrier();
         }

@@ -56,6 +56,7 @@ struct ServeFlight {
     std::vector<ServeReq *> ranks;
     std::vector<uint64_t> rb;  // result offset (words) per rank, ~0: not finishing
     uint32_t nsurv = 0, k = 0;
+    uint32_t tuple_bytes = 0;  // tuple size of the iteration's supersteps
     bool live = false;
     hipEvent_t done = nullptr;  // after the iteration's last copy
     uint64_t *h_res = nullptr;  // results of the finishing graphs
@@ -331,10 +332,11 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
     GESMC_TRY(up_end(c, s));
     const Plan p = batch_plan(c, npos, bbase);
     for (uint32_t st = 0; st < k; ++st) {
-        BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}};
+        BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}, vbase};
         c->ctr_step = c->ctr + st;
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
     }
+    F.tuple_bytes = c->tuple_bytes;
     // results of the graphs finishing now (discarded on the host if flagged)
     if (n_out) {
         unsigned long long *res = c->tu_key[2];
@@ -408,6 +410,7 @@ gesmc_status serve_complete(gesmc_server *S, ServeFlight &F) {
         o.rej_pl += F.h_gacc[4 * (size_t)q + 3];
         o.rounds_sum += rounds;
         o.rounds_max = std::max<uint32_t>(o.rounds_max, (uint32_t)rounds_max);
+        if (F.k) o.tuple_bytes = F.tuple_bytes;
         S->attempts += (uint64_t)F.k * (R->m / 2);
         S->legal += F.h_gacc[4 * (size_t)q + 0];
         const uint32_t ge = F.h_gerr[q];

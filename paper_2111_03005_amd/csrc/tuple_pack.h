@@ -1,0 +1,79 @@
+// Tuple tags and the packed 8-byte tuple word of the dependency partitions
+// (host and device: the host test of the packing includes this file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gesmc {
+
+// Dependency tuples (tag, edge key): an ERASE tuple carries the switch that
+// erases its key (or kTagStays for an edge that survives the superstep), an
+// INSERT tuple kTagInsert | (k << 1 | h) for target h of switch k.
+constexpr uint32_t kTagInsert = 0x80000000u;
+constexpr uint32_t kTagStays = 0x7FFFFFFEu;
+
+// Packed tuples: one 8-byte word per tuple when the bits allow it.  With
+// vertex ids below 2^vb an edge key has w = 2 vb significant bits; key_hash_w
+// is a bijection on w-bit words (xor-shift by at least w/2 is its own
+// inverse, odd multipliers are invertible mod 2^w), so equal hashes still
+// mean equal keys.  A tag is coded on tb = kb + 1 bits in the order of the
+// 32-bit tags: ERASE k -> k, STAYS -> 2^kb - 1, INSERT (k, h) -> 2^kb | 2k+h
+// (2 ell <= 2^kb).  The first partition pass writes
+// (H << (64 - w + b1)) | code: the b1 hash bits it partitioned by are implied
+// by the partition and dropped, the rest stays on top for the second level's
+// digits and the resolve's cells.
+struct TuplePack {
+    int w;   // hash bits (0: 12-byte tuples)
+    int vb;  // vertex id bits
+    int kb;  // tag code bits below the INSERT flag
+    int b1;  // hash bits dropped by the first partition pass
+    int b2;  // hash bits of the second partition pass
+};
+
+__host__ __device__ __forceinline__ uint64_t low_mask(int w) { return w >= 64 ? ~0ull : ((1ull << w) - 1); }
+
+constexpr unsigned long long kMixMul1 = 0xD6E8FEB86659FD93ull, kMixMul2 = 0x9E3779B97F4A7C15ull;
+constexpr unsigned long long inverse_mod_2_64(unsigned long long a) {  // Newton: x <- x (2 - a x)
+    unsigned long long x = a;
+    for (int i = 0; i < 6; ++i) x *= 2ull - a * x;
+    return x;
+}
+
+__host__ __device__ __forceinline__ uint64_t key_hash_w(uint64_t key, int vb, int w) {
+    const uint64_t mask = low_mask(w);
+    const int s = (w + 1) >> 1;
+    uint64_t x = ((key >> 32) << vb) | (key & 0xFFFFFFFFull);
+    x ^= x >> s;
+    x = (x * kMixMul1) & mask;
+    x ^= x >> s;
+    x = (x * kMixMul2) & mask;
+    x ^= x >> s;
+    return x;
+}
+
+// The smaller endpoint of the key with w-bit hash h (error reporting only).
+__host__ __device__ __forceinline__ uint32_t key_hash_w_vertex(uint64_t h, int vb, int w) {
+    constexpr unsigned long long kInv1 = inverse_mod_2_64(kMixMul1), kInv2 = inverse_mod_2_64(kMixMul2);
+    const uint64_t mask = low_mask(w);
+    const int s = (w + 1) >> 1;
+    uint64_t x = h;
+    x ^= x >> s;
+    x = (x * kInv2) & mask;
+    x ^= x >> s;
+    x = (x * kInv1) & mask;
+    x ^= x >> s;
+    return (uint32_t)(x >> vb);
+}
+
+__host__ __device__ __forceinline__ uint32_t tag_code(uint32_t tag, int kb) {
+    if (tag & kTagInsert) return (1u << kb) | (tag & ~kTagInsert);
+    return tag == kTagStays ? (1u << kb) - 1u : tag;
+}
+
+__host__ __device__ __forceinline__ uint32_t tag_of_code(uint32_t code, int kb) {
+    if (code >> kb) return kTagInsert | (code & ((1u << kb) - 1u));
+    return code == (1u << kb) - 1u ? kTagStays : code;
+}
+
+}  // namespace gesmc

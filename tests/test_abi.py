@@ -57,7 +57,7 @@ def test_binding_constants_match_header():
     assert d["GESMC_OK"] == gesmc.OK
     for name in ["E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_AGAIN", "E_CANCELED", "E_INTERNAL"]:
         assert d["GESMC_" + name] == getattr(gesmc, name), name
-    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH", "SMALL_GRAPHS"]:
+    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH", "SMALL_GRAPHS", "PACK_TUPLES"]:
         assert d["GESMC_OPT_" + name] == getattr(gesmc, "OPT_" + name), name
 
 
@@ -68,7 +68,7 @@ C_LAYOUT_PROBE = r"""
 #define F(T, f) printf("%s.%s %zu %zu\n", #T, #f, offsetof(T, f), sizeof(((T *)0)->f));
 #define S(T) printf("%s %zu\n", #T, sizeof(T));
 int main(void) {
-    S(gesmc_stats) F(gesmc_stats, rounds_max) F(gesmc_stats, ms_device)
+    S(gesmc_stats) F(gesmc_stats, rounds_max) F(gesmc_stats, ms_device) F(gesmc_stats, tuple_bytes)
     S(gesmc_step_stats)
     S(gesmc_server_cfg) F(gesmc_server_cfg, max_graphs) F(gesmc_server_cfg, max_queue)
     S(gesmc_request) F(gesmc_request, m) F(gesmc_request, n) F(gesmc_request, t0) F(gesmc_request, r)
@@ -112,8 +112,8 @@ def test_ctypes_layouts_match_c_compiler(tmp_path):
 
 def test_struct_layouts_match_header():
     from paper_2111_03005_amd import _binding as b
-    # gesmc_stats: 6 x u64, 2 x u32, 1 x double; gesmc_step_stats: 8 x u64
-    assert ctypes.sizeof(b.Stats) == 6 * 8 + 2 * 4 + 8
+    # gesmc_stats: 6 x u64, 2 x u32, 1 x double, 2 x u32; gesmc_step_stats: 8 x u64
+    assert ctypes.sizeof(b.Stats) == 6 * 8 + 2 * 4 + 8 + 2 * 4
     assert ctypes.sizeof(b.StepStats) == 8 * 8
     txt = header_text()
     assert "uint64_t attempts, legal, rej_loop, rej_exists, rej_pl;" in txt
