@@ -568,6 +568,7 @@ struct BatchStep {
     unsigned long long *acc;   // device: per-rank outcome counts (nullable)
     GraphErr ge;               // per-rank error attribution (gr = nullptr: none)
     uint64_t vend;             // vertex ids of the switched ranks are below this
+    uint64_t dend;             // and so are the id offsets v - u of their edges (the largest n)
 };
 
 // Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t --
@@ -640,18 +641,19 @@ int width_below(uint64_t x) {
     return b;
 }
 
-// Packed 8-byte tuple words (TuplePack) for nslots tuple slots of keys with
-// vertex ids below vend, if the bits allow: the hash bits left after the
-// first level plus the tag code fit 64 bits, and at least kCellBits hash bits
-// remain below both levels for the resolve's cells.  w = 0: 12-byte tuples.
-TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_t vend) {
+// Packed 8-byte tuple words (TuplePack) for nslots tuple slots of keys (u, v)
+// with v below vend and v - u below dend, if the bits allow: the hash bits
+// left after the first level plus the tag code fit 64 bits, and at least
+// kCellBits hash bits remain below both levels for the resolve's cells.
+// w = 0: 12-byte tuples.
+TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_t vend, uint64_t dend) {
     TuplePack pk{0, 0, 0, 0, 0};
-    if (!c->pack_tuples || vend < 2) return pk;
-    const int vb = width_below(vend), w = 2 * vb;
-    const int kb = std::max(1, width_below(2ull * (nslots / 4) + 1));  // 2 ell <= 2^kb, ell < 2^kb - 1
+    if (!c->pack_tuples || vend < 2 || dend < 2) return pk;
+    const int vb = width_below(vend), db = width_below(std::min(dend, vend)), w = vb + db;
+    const int kb = std::max(1, width_below(2ull * (nslots / 4) + 1));  // 2 ell < 2^kb, so ell < 2^kb - 1
     if (w > 62 || w - (int)p.b1 + kb + 1 > 64 || w - (int)p.bbits < kCellBits) return pk;
     pk.w = w;
-    pk.vb = vb;
+    pk.db = db;
     pk.kb = kb;
     pk.b1 = (int)p.b1;
     pk.b2 = (int)p.b2;
@@ -660,12 +662,12 @@ TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_
 
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
                                    GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr,
-                                   uint64_t vend = 0) {
+                                   uint64_t vend = 0, uint64_t dend = 0) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
-    const TuplePack pk = emit ? tuple_pack(c, p, nslots, vend) : TuplePack{0, 0, 0, 0, 0};
+    const TuplePack pk = emit ? tuple_pack(c, p, nslots, vend, dend) : TuplePack{0, 0, 0, 0, 0};
     c->tuple_bytes = pk.w ? 8u : 12u;
     if (pk.w) {
         SrcArgs sa = emit->sa;
@@ -702,7 +704,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
 }
 
 // One superstep with the partitioned resolution (state in buffer 0).
-// vend bounds the vertex ids of the keys (a batch: bs->vend).
+// vend bounds the vertex ids of the keys (a batch: bs->vend, bs->dend).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
                                    uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0) {
     int sorted = 0;
@@ -725,7 +727,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
         GESMC_TRY(launch(c, s, KID_EMIT, nslots, k_emit_tuples, dim3(grid_stride_blocks(c, nslots)), dim3(kBlock), 0,
                          si, sk, t, k0, k1, sa, nslots, c->tu_tag[0], c->tu_key[0]));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr},
-                                    c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend));
+                                    c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend, bs ? bs->dend : vend));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -1114,7 +1116,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     c->h_small.clear();
     c->h_mid.clear();
     c->h_rrank.assign(G, 0);
-    uint64_t poff = 0, vbase = 0, bbase = 0;
+    uint64_t poff = 0, vbase = 0, bbase = 0, nmax = 0;
     uint32_t nactive = 0, rmax = 0;
     bool need_validation = false;
     for (uint32_t q = 0; q < G; ++q) {
@@ -1139,6 +1141,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         c->h_rank_of[g] = q;
         poff += b.mpad;
         vbase += nv[g];
+        nmax = std::max<uint64_t>(nmax, nv[g]);
         bbase += b.nb;
         if (active) {
             ++nactive;
@@ -1241,7 +1244,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
             const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
             const Plan p = batch_plan(c, P, NB);
-            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase};
+            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase, nmax};
             c->ctr_step = c->ctr + st;
             GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
         }
@@ -1272,7 +1275,8 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         mix(c->fuse_emit);
         mix(c->small_graphs);
         mix(c->pack_tuples);
-        mix(vbase);  // the tuple layout depends on the vertex id width (n may change between replays)
+        mix(vbase);  // the tuple layout depends on the vertex id widths (n may change between replays)
+        mix(nmax);
         mix((uint64_t)c->persist_mult);
         mix(g_alloc_epoch.load());
         mix((uint64_t)(uintptr_t)s);

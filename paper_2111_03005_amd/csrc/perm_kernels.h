@@ -177,7 +177,7 @@ struct SrcArgs {
     const uint32_t *pg;      // batch: graph of each position (nullptr: one graph)
     uint32_t m;              // records (the pair records of ell = m / 2 switches)
     uint32_t pl;             // P_L threshold (batch: nonzero if some graph has one)
-    TuplePack pk;            // kSrcEmitPacked: hash width, vertex and tag code bits
+    TuplePack pk;            // kSrcEmitPacked: hash width, offset and tag code bits
 };
 
 template <int kSrc>
@@ -269,7 +269,7 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
             if (kPacked) {
                 tag[4 * j + h] = tag_code(tp[h].tag, sa.pk.kb);
                 key[4 * j + h] = (sl + h < cnt && tp[h].key != kEmptyKey)
-                                     ? key_hash_w(tp[h].key, sa.pk.vb, sa.pk.w) << (64 - sa.pk.w)
+                                     ? key_hash_w(tp[h].key, sa.pk.db, sa.pk.w) << (64 - sa.pk.w)
                                      : kEmptyKey;
             } else {
                 tag[4 * j + h] = tp[h].tag;

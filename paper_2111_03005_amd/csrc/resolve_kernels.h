@@ -134,7 +134,7 @@ __device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t 
         uint32_t v;
         if (pk.w) {
             const uint64_t h = ((uint64_t)(f >> pk.b2) << (pk.w - pk.b1)) | (key >> (64 - pk.w + pk.b1));
-            v = key_hash_w_vertex(h, pk.vb, pk.w);
+            v = key_hash_w_vertex(h, pk.db, pk.w);
         } else {
             v = (uint32_t)(tuple_key_of(key) >> 32);
         }

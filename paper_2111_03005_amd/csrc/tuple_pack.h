@@ -13,19 +13,21 @@ namespace gesmc {
 constexpr uint32_t kTagInsert = 0x80000000u;
 constexpr uint32_t kTagStays = 0x7FFFFFFEu;
 
-// Packed tuples: one 8-byte word per tuple when the bits allow it.  With
-// vertex ids below 2^vb an edge key has w = 2 vb significant bits; key_hash_w
-// is a bijection on w-bit words (xor-shift by at least w/2 is its own
-// inverse, odd multipliers are invertible mod 2^w), so equal hashes still
-// mean equal keys.  A tag is coded on tb = kb + 1 bits in the order of the
-// 32-bit tags: ERASE k -> k, STAYS -> 2^kb - 1, INSERT (k, h) -> 2^kb | 2k+h
-// (2 ell <= 2^kb).  The first partition pass writes
-// (H << (64 - w + b1)) | code: the b1 hash bits it partitioned by are implied
-// by the partition and dropped, the rest stays on top for the second level's
-// digits and the resolve's cells.
+// Packed tuples: one 8-byte word per tuple when the bits allow it.  An edge
+// key (u, v), u < v, with u below 2^vb and v - u below 2^db is coded on
+// w = vb + db bits as (u << db) | (v - u): one graph has db = vb, and in a
+// batch, whose graphs' vertex ranges are disjoint, db covers the largest
+// graph while vb covers them all.  mix_w is a bijection on w-bit words
+// (xor-shift by at least w/2 is its own inverse, odd multipliers are
+// invertible mod 2^w), so equal hashes still mean equal keys.  A tag is coded
+// on tb = kb + 1 bits in the order of the 32-bit tags: ERASE k -> k,
+// STAYS -> 2^kb - 1, INSERT (k, h) -> 2^kb | 2k+h (2 ell < 2^kb).  The first
+// partition pass writes (H << (64 - w + b1)) | code: the b1 hash bits it
+// partitioned by are implied by the partition and dropped, the rest stays on
+// top for the second level's digits and the resolve's cells.
 struct TuplePack {
-    int w;   // hash bits (0: 12-byte tuples)
-    int vb;  // vertex id bits
+    int w;   // hash bits vb + db (0: 12-byte tuples)
+    int db;  // bits of the larger endpoint's offset v - u
     int kb;  // tag code bits below the INSERT flag
     int b1;  // hash bits dropped by the first partition pass
     int b2;  // hash bits of the second partition pass
@@ -40,10 +42,9 @@ constexpr unsigned long long inverse_mod_2_64(unsigned long long a) {  // Newton
     return x;
 }
 
-__host__ __device__ __forceinline__ uint64_t key_hash_w(uint64_t key, int vb, int w) {
+__host__ __device__ __forceinline__ uint64_t mix_w(uint64_t x, int w) {
     const uint64_t mask = low_mask(w);
     const int s = (w + 1) >> 1;
-    uint64_t x = ((key >> 32) << vb) | (key & 0xFFFFFFFFull);
     x ^= x >> s;
     x = (x * kMixMul1) & mask;
     x ^= x >> s;
@@ -52,18 +53,27 @@ __host__ __device__ __forceinline__ uint64_t key_hash_w(uint64_t key, int vb, in
     return x;
 }
 
-// The smaller endpoint of the key with w-bit hash h (error reporting only).
-__host__ __device__ __forceinline__ uint32_t key_hash_w_vertex(uint64_t h, int vb, int w) {
+__host__ __device__ __forceinline__ uint64_t unmix_w(uint64_t x, int w) {
     constexpr unsigned long long kInv1 = inverse_mod_2_64(kMixMul1), kInv2 = inverse_mod_2_64(kMixMul2);
     const uint64_t mask = low_mask(w);
     const int s = (w + 1) >> 1;
-    uint64_t x = h;
     x ^= x >> s;
     x = (x * kInv2) & mask;
     x ^= x >> s;
     x = (x * kInv1) & mask;
     x ^= x >> s;
-    return (uint32_t)(x >> vb);
+    return x;
+}
+
+// The w-bit hash of a canonical edge key (u << 32) | v.
+__host__ __device__ __forceinline__ uint64_t key_hash_w(uint64_t key, int db, int w) {
+    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;  // u < v
+    return mix_w(((uint64_t)u << db) | (uint32_t)(v - u), w);
+}
+
+// The smaller endpoint of the key with w-bit hash h (error reporting only).
+__host__ __device__ __forceinline__ uint32_t key_hash_w_vertex(uint64_t h, int db, int w) {
+    return (uint32_t)(unmix_w(h, w) >> db);
 }
 
 __host__ __device__ __forceinline__ uint32_t tag_code(uint32_t tag, int kb) {

@@ -1,11 +1,11 @@
 // Host checks of the packed tuple word (paper_2111_03005_amd/csrc/tuple_pack.h),
 // the functions the kernels use, run on the CPU:
-//   1. key_hash_w is a bijection on w-bit words (exhaustive for w <= 20) and
-//      key_hash_w_vertex inverts it (exhaustive, then 2^20 random keys per w);
+//   1. mix_w is a bijection on w-bit words (exhaustive for w <= 20) with
+//      inverse unmix_w, and the (u, v - u) coding of edge keys returns u;
 //   2. tag codes round-trip and keep the order of the 32-bit tags;
 //   3. the packed word (H' << (64 - w + b1)) | code orders as (H', tag);
-//   4. the top hash bits spread structured key sets (banded and star graphs)
-//      evenly over partitions and cells.
+//   4. the top hash bits spread structured key sets (banded, star and
+//      batched graphs) evenly over partitions and cells.
 // Prints "ok" or the first failure.
 #include <stdio.h>
 #include <stdlib.h>
@@ -37,10 +37,10 @@ static uint64_t splitmix() {
 static uint64_t key_of(uint64_t u, uint64_t v) { return (u << 32) | v; }
 
 // Largest bucket of the top `bits` bits of H over a key set, and the mean.
-static int spread(const std::vector<uint64_t> &keys, int vb, int bits, double *ratio) {
-    const int w = 2 * vb;
+static int spread(const std::vector<uint64_t> &keys, int vb, int db, int bits, double *ratio) {
+    const int w = vb + db;
     std::vector<uint32_t> cnt((size_t)1 << bits, 0);
-    for (uint64_t k : keys) ++cnt[key_hash_w(k, vb, w) >> (w - bits)];
+    for (uint64_t k : keys) ++cnt[key_hash_w(k, db, w) >> (w - bits)];
     const double mean = (double)keys.size() / cnt.size();
     const uint32_t mx = *std::max_element(cnt.begin(), cnt.end());
     *ratio = mx / mean;
@@ -48,27 +48,41 @@ static int spread(const std::vector<uint64_t> &keys, int vb, int bits, double *r
 }
 
 int main() {
-    // 1. bijection and inverse, exhaustive for small widths
-    for (int vb = 1; vb <= 10; ++vb) {
-        const int w = 2 * vb;
+    // 1. mix_w is a bijection with inverse unmix_w: exhaustive for w <= 20,
+    //    2^18 random words for every wider w up to 62
+    for (int w = 1; w <= 20; ++w) {
         std::vector<uint8_t> seen((size_t)1 << w, 0);
         for (uint64_t x = 0; x < (1ull << w); ++x) {
-            const uint64_t u = x >> vb, v = x & ((1ull << vb) - 1);
-            const uint64_t h = key_hash_w(key_of(u, v), vb, w);
-            CHECK(h < (1ull << w), "hash out of range vb=%d", vb);
-            CHECK(!seen[h], "hash collision vb=%d x=%llu", vb, (unsigned long long)x);
+            const uint64_t h = mix_w(x, w);
+            CHECK(h < (1ull << w), "mix out of range w=%d", w);
+            CHECK(!seen[h], "mix collision w=%d x=%llu", w, (unsigned long long)x);
             seen[h] = 1;
-            CHECK(key_hash_w_vertex(h, vb, w) == u, "inverse vb=%d x=%llu", vb, (unsigned long long)x);
+            CHECK(unmix_w(h, w) == x, "inverse w=%d x=%llu", w, (unsigned long long)x);
         }
     }
-    for (int vb = 11; vb <= 31; ++vb) {
-        const int w = 2 * vb;
-        for (int i = 0; i < (1 << 20); ++i) {
-            const uint64_t r = splitmix();
-            const uint64_t u = r & ((1ull << vb) - 1), v = (r >> 32) & ((1ull << vb) - 1);
-            const uint64_t h = key_hash_w(key_of(u, v), vb, w);
-            CHECK(h <= low_mask(w), "hash out of range vb=%d", vb);
-            CHECK(key_hash_w_vertex(h, vb, w) == u, "inverse vb=%d", vb);
+    for (int w = 21; w <= 62; ++w) {
+        for (int i = 0; i < (1 << 18); ++i) {
+            const uint64_t x = splitmix() & low_mask(w);
+            const uint64_t h = mix_w(x, w);
+            CHECK(h <= low_mask(w), "mix out of range w=%d", w);
+            CHECK(unmix_w(h, w) == x, "inverse w=%d", w);
+        }
+    }
+    //    edge keys (u, v), u < v, coded as (u, v - u) on vb + db bits: the
+    //    coding comes back through unmix_w (so distinct keys get distinct
+    //    hashes) and so does the vertex
+    const int widths[][2] = {{20, 20}, {22, 22}, {26, 17}, {31, 31}, {26, 1}, {5, 3}};
+    for (const auto &vd : widths) {
+        const int vb = vd[0], db = vd[1], w = vb + db;
+        for (int i = 0; i < 200000; ++i) {
+            const uint64_t d = 1 + splitmix() % ((1ull << db) - 1 + (db == 0));
+            const uint64_t u = splitmix() % ((1ull << vb) - d > 0 ? (1ull << vb) - d : 1);
+            if (u + d >= (1ull << vb) || d >= (1ull << db)) continue;
+            const uint64_t k = key_of(u, u + d);
+            const uint64_t h = key_hash_w(k, db, w);
+            CHECK(h <= low_mask(w), "key hash out of range vb=%d db=%d", vb, db);
+            CHECK(key_hash_w_vertex(h, db, w) == u, "vertex vb=%d db=%d", vb, db);
+            CHECK(unmix_w(h, w) == ((u << db) | d), "coding vb=%d db=%d", vb, db);
         }
     }
     // 2. tag codes
@@ -124,21 +138,30 @@ int main() {
         }
         (void)vb;
     }
-    // 4. spread of structured key sets over partitions (top 11 bits) and cells (next 10)
+    // 4. spread of structured key sets over partitions (top 11 bits) and cells
+    //    (the next 10): a banded and a star graph on 2^18 vertices, and a batch
+    //    of 4096 disjoint small graphs (ids up to 2^22, offsets below 2^10)
     {
-        const int vb = 18;
-        std::vector<uint64_t> band, star;
+        std::vector<uint64_t> band, star, batch;
         for (uint64_t u = 0; u < (1u << 17); ++u)
             for (uint64_t d = 1; d <= 16; ++d) band.push_back(key_of(u, u + d));
         for (uint64_t hub = 0; hub < 64; ++hub)
             for (uint64_t v = 64; v < 64 + 32768; ++v) star.push_back(key_of(hub, v));
-        double r1, r2;
-        const int m1 = spread(band, vb, 11, &r1), m2 = spread(star, vb, 11, &r2);
-        CHECK(r1 < 1.25 && r2 < 1.25, "partition spread band %d (%.3f) star %d (%.3f)", m1, r1, m2, r2);
-        double c1, c2;
-        spread(band, vb, 21, &c1);
-        spread(star, vb, 21, &c2);
-        CHECK(c1 < 16 && c2 < 16, "cell spread band %.2f star %.2f", c1, c2);
+        for (uint64_t g = 0; g < 4096; ++g)
+            for (uint64_t a = 0; a < 32; ++a)
+                for (uint64_t b = a + 1; b < a + 17; ++b) batch.push_back(key_of(g * 1024 + a, g * 1024 + b));
+        const struct {
+            const std::vector<uint64_t> *keys;
+            int vb, db;
+            const char *name;
+        } sets[] = {{&band, 18, 18, "band"}, {&star, 18, 18, "star"}, {&batch, 22, 10, "batch"}};
+        for (const auto &st : sets) {
+            double r, rc;
+            const int mx = spread(*st.keys, st.vb, st.db, 11, &r);
+            spread(*st.keys, st.vb, st.db, 21, &rc);
+            CHECK(r < 1.25, "partition spread %s: largest %d (%.3f x mean)", st.name, mx, r);
+            CHECK(rc < 16, "cell spread %s: %.2f x mean", st.name, rc);
+        }
     }
     printf("ok\n");
     return 0;

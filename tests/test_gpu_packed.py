@@ -200,3 +200,31 @@ def test_packed_batch_graph_replay_with_wider_ids():
                 assert np.array_equal(got[offs[g]:offs[g + 1]], exp), (rep, g)
     finally:
         c.close()
+
+
+def test_packed_batch_wide_vertex_range():
+    """600 sparse graphs of 10^5 vertices: ids need 26 bits, offsets v - u
+    only 17, so the (u, v - u) coding packs (57 bits) where two 26-bit ids
+    would not (66).  Every graph equals the oracle."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    graphs = [(random_simple(100000, 200, 100 + g), 100000) for g in range(600)]
+    rng = np.random.default_rng(11)
+    seeds = [int(x) for x in rng.integers(0, 2**63, len(graphs))]
+    rs = [int(x) for x in rng.integers(1, 5, len(graphs))]
+    E_all, offs, ns = graphgen.concat(graphs)
+    c = gesmc.Context(0)
+    try:
+        c.set_option(gesmc.OPT_SMALL_GRAPHS, 0)
+        print("wide batch: G=%d total m=%d" % (len(graphs), offs[-1]), flush=True)
+        out, stats, tot = c.run_batch(to_dev(E_all), offs, ns, seeds, rs)
+        assert tot["tuple_bytes"] == 8, tot
+        got = to_host(out)
+        for g, (E, n) in enumerate(graphs):
+            rc, exp, counts, _ = oracle.run(E, n, seeds[g], 0, rs[g])
+            assert rc == 0
+            assert np.array_equal(got[offs[g]:offs[g + 1]], exp), g
+            for k in ("legal", "rej_loop", "rej_exists"):
+                assert stats[g][k] == sum(x[k] for x in counts), (g, k)
+    finally:
+        c.close()
