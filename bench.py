@@ -48,7 +48,7 @@ def kernel_bytes(name: str, m: int, ell: int, tb: int = 12) -> float | None:
         "k_load": 8.0 * m + 12.0 * m,
         # sorted-tuples dependency resolution: 4 tuples of tb bytes per switch
         "k_emit": 24.0 * ell + 16.0 * ell + 1.0 * ell,   # pair records in, free target records + statuses out
-        "k_tcounts1": 24.0 * ell,                        # pair records (tuples computed from them)
+        "k_tcounts1": 24.0 * ell + 16.0 * ell + 1.0 * ell,  # the emit fused in: as k_emit
         "k_tscatter1": 24.0 * ell + 4.0 * tb * ell,      # pair records in, partitioned tuples out
         "k_tcounts2": 32.0 * ell,                        # the 8-byte key (or packed) word of each tuple
         "k_tscatter2": 8.0 * tb * ell,

@@ -476,6 +476,25 @@ gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
     return GESMC_OK;
 }
 
+// 1: with fused tuple passes, the emit runs inside the first tuple count pass
+#ifndef GESMC_FUSE_EMIT_COUNTS
+#define GESMC_FUSE_EMIT_COUNTS 1
+#endif
+
+// The emit's per-switch outputs, written by the first tuple count pass
+// (k_emit_counts) when the tuples are computed from the pair records; its
+// `grid` workgroups store their outcome counts in bslot[0, grid).
+struct EmitOut {
+    uint2 *info;
+    uint8_t *st;
+    uint32_t *out_idx;
+    unsigned long long *out_key;
+    uint4 *bslot;
+    uint32_t *ucount;
+    uint32_t grid;
+};
+constexpr uint32_t kEmitSlotsMax = 8192;  // workgroups of k_emit_counts (count slots)
+
 // Two-level MSD radix distribution of the n records (idx/tag, key) in buffer
 // set `src` into `dst` (one level) or via `mid` into `dst` (two levels), by
 // the radix word of source kSrc1 (level 1) and kSrc2 (level 2), with the
@@ -487,7 +506,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
                               int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
-                              const uint32_t *in_idx, const unsigned long long *in_key) {
+                              const uint32_t *in_idx, const unsigned long long *in_key, const EmitOut *eo) {
     // level-1 input: buffer `src`, or the given arrays (the pair records of kSrcEmit)
     const uint32_t *src_i = in_idx ? in_idx : idx[src];
     const unsigned long long *src_k = in_key ? in_key : key[src];
@@ -498,10 +517,24 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
     GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, (uint64_t)nchunks * nd1));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;  // level 1: one segment [0, n), passed by value
-    GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile, true>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile, true>, (size_t)nd1 * 4, p.ntiles1)), dim3(kBlock),
-                     (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr,
-                     (const uint32_t *)nullptr, c->counts1, ba1));
+    bool fused_emit = false;
+    if constexpr (kSrc1 == kSrcEmit || kSrc1 == kSrcEmitPacked) {
+        if (eo) {  // the emit's outputs in the same pass
+            GESMC_TRY(launch(c, s, kid_counts1, n, k_emit_counts<kSrc1, kTile>, dim3(eo->grid), dim3(kBlock),
+                             (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, n, c->counts1, ba1,
+                             eo->info, eo->st, eo->out_idx, eo->out_key, eo->bslot, eo->ucount));
+            fused_emit = true;
+        }
+    }
+    if (eo && !fused_emit) {
+        set_error("internal: emit outputs need a tuple source computed from the pair records");
+        return GESMC_E_INTERNAL;
+    }
+    if (!fused_emit)
+        GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile, true>,
+                         dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile, true>, (size_t)nd1 * 4, p.ntiles1)),
+                         dim3(kBlock), (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 0u, n,
+                         (const uint32_t *)nullptr, (const uint32_t *)nullptr, c->counts1, ba1));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kTopThreads), 0, c->partial, nchunks, (int)p.b1,
@@ -547,14 +580,15 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
                               int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
-                              const uint32_t *in_idx = nullptr, const unsigned long long *in_key = nullptr) {
+                              const uint32_t *in_idx = nullptr, const unsigned long long *in_key = nullptr,
+                              const EmitOut *eo = nullptr) {
     if (p.tile == (uint32_t)kTileLarge)
         return radix_distribute_t<kSrc1, kSrc2, kTileLarge>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                             bucket_off, nbuckets, kid_counts1, kid_scatter1,
-                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key);
+                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key, eo);
     return radix_distribute_t<kSrc1, kSrc2, kTileSmall>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                         bucket_off, nbuckets, kid_counts1, kid_scatter1, kid_counts2,
-                                                        kid_scatter2, ba1, ba2, in_idx, in_key);
+                                                        kid_scatter2, ba1, ba2, in_idx, in_key, eo);
 }
 
 // One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
@@ -662,7 +696,7 @@ TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_
 
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
                                    GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr,
-                                   uint64_t vend = 0, uint64_t dend = 0) {
+                                   uint64_t vend = 0, uint64_t dend = 0, const EmitOut *eo = nullptr) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
@@ -675,7 +709,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
         GESMC_TRY((radix_distribute<kSrcEmitPacked, kSrcPacked>(
             c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts,
             &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
-            emit->sk)));
+            emit->sk, eo)));
         const int scratch = parts == 2 ? 1 : 0;
         const size_t rlds = resolve_lds_bytes(c->sort_cap);
         GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<true>,
@@ -688,7 +722,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
         GESMC_TRY((radix_distribute<kSrcEmit, kSrcHashed>(c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag,
                                                         c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts, &poff, &np,
                                                         KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2,
-                                                        emit->sa, SrcArgs{}, emit->si, emit->sk)));
+                                                        emit->sa, SrcArgs{}, emit->si, emit->sk, eo)));
     else
         GESMC_TRY((radix_distribute<kSrcHash, kSrcHashed>(c, s, p, nslots, 0u, 0u, 0u, c->tu_tag, c->tu_key, 0, 1,
                                                         p.b2 > 0 ? 2 : 1, &parts, &poff, &np, KID_TCOUNTS1,
@@ -712,22 +746,31 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
-    // per-block counts of emit and the first round go to slots [0, ge) and [ge, ge + gd)
-    const uint32_t ge = grid_stride_blocks(c, (uint64_t)p.ell + 1), gd = grid_stride_blocks(c, p.ell);
+    // per-block counts of emit and the first round go to slots [0, ge) and [ge, ge + gd);
+    // with the tuples computed from the pair records, the emit runs inside the
+    // first tuple count pass (k_emit_counts), one workgroup per tile up to
+    // kEmitSlotsMax
+    const bool fused = c->fuse_emit && GESMC_FUSE_EMIT_COUNTS;
+    const uint32_t ge = fused ? std::min<uint32_t>(kEmitSlotsMax, make_plan(c, nslots).ntiles1)
+                              : grid_stride_blocks(c, (uint64_t)p.ell + 1);
+    const uint32_t gd = grid_stride_blocks(c, p.ell);
     SrcArgs sa{};
     sa.gr = bs ? bs->gr : nullptr;
     sa.pg = bs ? bs->pg : nullptr;
     sa.step = bs ? bs->step : 0u;
     sa.m = p.m;
     sa.pl = pl;
-    GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, t, k0, k1, sa, c->info, c->st,
-                     c->idx[0], c->key[0], c->bslot, c->ucount));
+    if (!fused)
+        GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, t, k0, k1, sa, c->info,
+                         c->st, c->idx[0], c->key[0], c->bslot, c->ucount));
     const EmitSource es{si, sk, t, k0, k1, sa};
+    const EmitOut eo{c->info, c->st, c->idx[0], c->key[0], c->bslot, c->ucount, ge};
     if (!c->fuse_emit)
         GESMC_TRY(launch(c, s, KID_EMIT, nslots, k_emit_tuples, dim3(grid_stride_blocks(c, nslots)), dim3(kBlock), 0,
                          si, sk, t, k0, k1, sa, nslots, c->tu_tag[0], c->tu_key[0]));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr},
-                                    c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend, bs ? bs->dend : vend));
+                                    c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend, bs ? bs->dend : vend,
+                                    fused ? &eo : nullptr));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -1426,7 +1469,8 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     const size_t words = 16 + 16 + 2 * nc + 8 + (nf + 8);
     if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK ||
         dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK ||
-        dev_alloc((void **)&c->bslot, 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1) * sizeof(uint4)) != GESMC_OK) {
+        dev_alloc((void **)&c->bslot, (kEmitSlotsMax + 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1)) * sizeof(uint4)) !=
+            GESMC_OK) {
         gesmc_destroy(c);
         return GESMC_E_NOMEM;
     }

@@ -226,6 +226,22 @@ struct Tuple {
 // entries): j = 0, 1 the ERASE tuples of its sources, j = 2, 3 the INSERT
 // tuples of its targets.  A switch decided locally keeps its sources (STAYS)
 // and inserts nothing; slot 4 ell holds the idle record of odd m.
+// The four tuples of switch k < ell with pair records (ij, ee), local
+// outcome `status` and targets T.
+__device__ __forceinline__ void switch_tuples(uint32_t k, uint2 ij, ulonglong2 ee, uint8_t status, Targets T,
+                                              Tuple *tp) {
+    tp[1] = tp[2] = tp[3] = Tuple{0u, kEmptyKey};
+    if (status == ST_UNDECIDED) {
+        tp[0] = Tuple{k, ee.x};
+        tp[1] = Tuple{k, ee.y};
+        tp[2] = Tuple{kTagInsert | (k << 1), T.A};
+        tp[3] = Tuple{kTagInsert | (k << 1) | 1u, T.B};
+    } else {
+        tp[0] = Tuple{kTagStays, ij.x == kPadIdx ? kEmptyKey : ee.x};
+        tp[1] = Tuple{kTagStays, ij.y == kPadIdx ? kEmptyKey : ee.y};
+    }
+}
+
 __device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, const unsigned long long *sk, uint32_t t,
                                             uint32_t k0, uint32_t k1, const SrcArgs &sa, Tuple *tp) {
     const uint32_t ell = sa.m >> 1;
@@ -238,6 +254,8 @@ __device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, cons
     const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(sk)[k];
     Targets T{0, 0, false};
     const uint8_t status = switch_local(k, ij, ee, t, k0, k1, sa, &T);
+    // the tuples of switch_tuples, written out here: calling it from this
+    // function made the compiler keep T in scratch memory
     if (status == ST_UNDECIDED) {
         tp[0] = Tuple{k, ee.x};
         tp[1] = Tuple{k, ee.y};
@@ -247,6 +265,13 @@ __device__ __forceinline__ void emit_switch(uint32_t k, const uint32_t *si, cons
         tp[0] = Tuple{kTagStays, ij.x == kPadIdx ? kEmptyKey : ee.x};
         tp[1] = Tuple{kTagStays, ij.y == kPadIdx ? kEmptyKey : ee.y};
     }
+}
+
+// The radix word of a tuple key emitted by kSrcEmit / kSrcEmitPacked.
+template <bool kPacked>
+__device__ __forceinline__ unsigned long long emitted_word(unsigned long long key, const SrcArgs &sa) {
+    if (key == kEmptyKey) return kEmptyKey;
+    return kPacked ? key_hash_w(key, sa.pk.db, sa.pk.w) << (64 - sa.pk.w) : tuple_hash(key);
 }
 
 // kSrcEmit tiles: each thread takes whole switches, so the four slots of a
@@ -266,15 +291,8 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
         if (sl < cnt) emit_switch((begin + sl) >> 2, si, sk, t, k0, k1, sa, tp);
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            if (kPacked) {
-                tag[4 * j + h] = tag_code(tp[h].tag, sa.pk.kb);
-                key[4 * j + h] = (sl + h < cnt && tp[h].key != kEmptyKey)
-                                     ? key_hash_w(tp[h].key, sa.pk.db, sa.pk.w) << (64 - sa.pk.w)
-                                     : kEmptyKey;
-            } else {
-                tag[4 * j + h] = tp[h].tag;
-                key[4 * j + h] = sl + h < cnt ? tuple_hash(tp[h].key) : kEmptyKey;
-            }
+            tag[4 * j + h] = kPacked ? tag_code(tp[h].tag, sa.pk.kb) : tp[h].tag;
+            key[4 * j + h] = sl + h < cnt ? emitted_word<kPacked>(tp[h].key, sa) : kEmptyKey;
         }
     }
 }

@@ -87,6 +87,79 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
     store_counts(&bc, bslot + blockIdx.x);
 }
 
+// k_emit fused into the first tuple partition pass's counts (kSrcEmit or
+// kSrcEmitPacked, one segment [0, nslots) of kTile-slot tiles): the pair
+// records of a switch are read once, for its status, its records and
+// counts (as k_emit) and for its four tuples' digit counts (as
+// k_tile_counts).  Tiles are taken grid-stride; each workgroup stores its
+// outcome counts in bslot[blockIdx.x].  The per-tile digit counts equal
+// k_tile_counts' (the same tiles, tuples and radix words).
+template <int kSrc, int kTile>
+__global__ __launch_bounds__(kBlock) void k_emit_counts(const uint32_t *__restrict__ s_idx,
+                                                        const unsigned long long *__restrict__ s_key, uint32_t t,
+                                                        uint32_t k0, uint32_t k1, int shift, int dbits, uint32_t nslots,
+                                                        uint32_t *__restrict__ counts, SrcArgs sa,
+                                                        uint2 *__restrict__ info, uint8_t *__restrict__ st,
+                                                        uint32_t *__restrict__ out_idx,
+                                                        unsigned long long *__restrict__ out_key,
+                                                        uint4 *__restrict__ bslot, uint32_t *__restrict__ ucount) {
+    static_assert(src_emits<kSrc>(), "tuples emitted from the pair records");
+    extern __shared__ uint32_t hs[];
+    __shared__ BlockCounts bc;
+    constexpr int kSwitches = kTile / kBlock / 4;  // switches per thread and tile
+    constexpr bool kPacked = kSrc == kSrcEmitPacked;
+    const uint32_t nt = max(1u, (nslots + kTile - 1) / kTile);
+    const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
+    const uint32_t m = sa.m, ell = m >> 1;
+    if (tid == 0) bc = BlockCounts{0, 0, 0, 0};
+    if (blockIdx.x == 0 && tid < 3) ucount[tid] = 0;  // the undecided-list counters of the rounds
+    for (uint32_t w = blockIdx.x; w < nt; w += gridDim.x) {
+        const uint32_t begin = w * kTile;
+        const uint32_t cnt = begin < nslots ? min((uint32_t)kTile, nslots - begin) : 0u;
+        for (uint32_t d = tid; d < nd; d += kBlock) hs[d] = 0;
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < kSwitches; ++j) {
+            const uint32_t sl = 4 * (tid + j * kBlock);  // first local slot of this thread's switch
+            Tuple tp[4] = {{0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}};
+            if (sl < cnt) {
+                const uint32_t k = (begin + sl) >> 2;
+                if (k < ell) {
+                    const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+                    const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+                    Targets T{0, 0, false};
+                    const uint8_t status = switch_local(k, ij, ee, t, k0, k1, sa, &T);
+                    st[k] = status;
+                    if (status == ST_UNDECIDED) {
+                        reinterpret_cast<uint4 *>(info)[k] = make_uint4(kNoEraser, kNoPred, kNoEraser, kNoPred);
+                    } else {
+                        reinterpret_cast<uint2 *>(out_idx)[k] = ij;
+                        reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
+                        if (status == ST_PL) atomicAdd(&bc.pl, 1u);
+                        if (status == ST_LOOP) atomicAdd(&bc.loop, 1u);
+                        if (status == ST_EXISTS) atomicAdd(&bc.exists, 1u);
+                    }
+                    switch_tuples(k, ij, ee, status, T, tp);
+                } else if (k == ell && (m & 1u)) {  // the idle record of odd m stays
+                    out_idx[m - 1] = s_idx[m - 1];
+                    out_key[m - 1] = s_key[m - 1];
+                    tp[0] = Tuple{kTagStays, s_key[m - 1]};
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                if (sl + h >= cnt) continue;
+                const unsigned long long word = emitted_word<kPacked>(tp[h].key, sa);
+                if (word != kEmptyKey) atomicAdd(&hs[(uint32_t)(word >> shift) & dmask], 1u);
+            }
+        }
+        lds_barrier();
+        for (uint32_t d = tid; d < nd; d += kBlock) counts[(size_t)w * nd + d] = hs[d];
+        lds_barrier();
+    }
+    store_counts(&bc, bslot + blockIdx.x);
+}
+
 // The tuples of every slot written out flat (tuple buffer 0), for the
 // unfused schedule (GESMC_OPT_FUSE_EMIT 0): one thread per switch.
 __global__ __launch_bounds__(kBlock) void k_emit_tuples(const uint32_t *__restrict__ s_idx,
