@@ -528,38 +528,66 @@ __global__ __launch_bounds__(kBlock) void k_colapply(uint32_t *__restrict__ coun
 
 // Level-2 scan, one workgroup per coarse segment: sub-bucket totals -> fine
 // offsets, then run bases of the segment's tiles (in place of the counts).
+// With fewer digits than threads, kBlock / 2^dbits threads share a digit's
+// tiles (contiguous runs, combined through LDS).
 __global__ __launch_bounds__(kBlock) void k_segscan(uint32_t *__restrict__ counts, int dbits, uint32_t nseg,
                                                     const uint32_t *__restrict__ coarse_off,
                                                     const uint32_t *__restrict__ tile_first,
                                                     uint32_t *__restrict__ fine_off) {
     extern __shared__ uint32_t v[];  // 2^dbits + kBlock + 1
+    __shared__ uint32_t part[kBlock];
     uint32_t *tmp = v + (1u << dbits);
-    const uint32_t s = blockIdx.x, nd = 1u << dbits;
+    const uint32_t s = blockIdx.x, nd = 1u << dbits, tid = threadIdx.x;
     const uint32_t w0 = tile_first[s], w1 = tile_first[s + 1];
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
+    const uint32_t per_digit = nd >= kBlock ? 1u : kBlock / nd;  // threads per digit
+    // thread tid takes digits d = tid % nd (+ kBlock ...) over its share of the tiles
+    const uint32_t jrow = tid / nd < per_digit ? tid / nd : 0u;
+    const uint32_t rows = w1 - w0, share = (rows + per_digit - 1) / per_digit;
+    const uint32_t r0 = w0 + min(jrow * share, rows), r1 = w0 + min(jrow * share + share, rows);
+    auto tile_sum = [&](uint32_t d, uint32_t a, uint32_t b) {
         uint32_t acc = 0;
 #pragma unroll 8
-        for (uint32_t w = w0; w < w1; ++w) acc += counts[(size_t)w * nd + d];
-        v[d] = acc;
-    }
-    __syncthreads();
-    block_exclusive_scan(v, nd, tmp);
-    const uint32_t off = coarse_off[s];
-    for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
-        uint32_t run = off + v[d];
-        fine_off[((size_t)s << dbits) + d] = run;
-        for (uint32_t wb = w0; wb < w1; wb += 16) {
+        for (uint32_t w = a; w < b; ++w) acc += counts[(size_t)w * nd + d];
+        return acc;
+    };
+    auto apply = [&](uint32_t d, uint32_t a, uint32_t b, uint32_t run) {
+        for (uint32_t wb = a; wb < b; wb += 16) {
             uint32_t x[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = (wb + j < w1) ? counts[(size_t)(wb + j) * nd + d] : 0u;
+            for (int j = 0; j < 16; ++j) x[j] = (wb + j < b) ? counts[(size_t)(wb + j) * nd + d] : 0u;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                if (wb + j < w1) counts[(size_t)(wb + j) * nd + d] = run;
+                if (wb + j < b) counts[(size_t)(wb + j) * nd + d] = run;
                 run += x[j];
             }
         }
+    };
+    const uint32_t off = coarse_off[s];
+    if (per_digit == 1) {
+        for (uint32_t d = tid; d < nd; d += kBlock) v[d] = tile_sum(d, w0, w1);
+        __syncthreads();
+        block_exclusive_scan(v, nd, tmp);
+        for (uint32_t d = tid; d < nd; d += kBlock) {
+            fine_off[((size_t)s << dbits) + d] = off + v[d];
+            apply(d, w0, w1, off + v[d]);
+        }
+    } else {
+        const uint32_t d = tid % nd;
+        part[tid] = tile_sum(d, r0, r1);
+        __syncthreads();
+        uint32_t before = 0, all = 0;  // this thread's share starts after `before` records of digit d
+        for (uint32_t q = 0; q < per_digit; ++q) {
+            const uint32_t x = part[q * nd + d];
+            before += q < jrow ? x : 0u;
+            all += x;
+        }
+        if (jrow == 0) v[d] = all;
+        __syncthreads();
+        block_exclusive_scan(v, nd, tmp);
+        if (jrow == 0) fine_off[((size_t)s << dbits) + d] = off + v[d];
+        apply(d, r0, r1, off + v[d] + before);
     }
-    if (s == nseg - 1 && threadIdx.x == 0) fine_off[(size_t)nseg << dbits] = coarse_off[nseg];
+    if (s == nseg - 1 && tid == 0) fine_off[(size_t)nseg << dbits] = coarse_off[nseg];
 }
 
 // LDS-staged scatter of one tile of a segment by digit (word >> shift) & mask.

@@ -619,14 +619,23 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
         s_n = min(*count_a, ell);
     }
     __syncthreads();
-    {  // fold the per-block counts of the emit and first-round kernels
+    {  // fold the per-block counts of the emit and first-round kernels (eight loads in flight)
+        constexpr uint32_t kFold = 8;
         uint4 acc = make_uint4(0, 0, 0, 0);
-        for (uint32_t q = tid; q < nbslot; q += kFinishBlock) {
-            const uint4 v = bslot[q];
-            acc.x += v.x;
-            acc.y += v.y;
-            acc.z += v.z;
-            acc.w += v.w;
+        for (uint32_t q0 = tid; q0 < nbslot; q0 += kFold * kFinishBlock) {
+            uint4 v[kFold];
+#pragma unroll
+            for (uint32_t j = 0; j < kFold; ++j) {
+                const uint32_t q = q0 + j * kFinishBlock;
+                v[j] = q < nbslot ? bslot[q] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kFold; ++j) {
+                acc.x += v[j].x;
+                acc.y += v[j].y;
+                acc.z += v[j].z;
+                acc.w += v[j].w;
+            }
         }
         if (acc.x) atomicAdd(&bc.legal, acc.x);
         if (acc.y) atomicAdd(&bc.loop, acc.y);
