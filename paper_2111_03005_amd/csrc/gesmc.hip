@@ -441,8 +441,10 @@ size_t sort_lds_bytes(uint32_t cap) {
     return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 20;
 }
 
-size_t resolve_lds_bytes(uint32_t cap) {  // cells, scan words, keys, tags, list links
-    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * 14;
+// cells, scan words, keys, tags, list links; packed words with the cell
+// lists keep their tags in the words
+size_t resolve_lds_bytes(uint32_t cap, bool packed = false) {
+    return ((size_t)(1u << kCellBits) + kBlock + 2) * 4 + (size_t)cap * (packed && GESMC_RESOLVE_LISTS ? 10 : 14);
 }
 
 // Workgroups of a persistent kernel: as many as can be resident at once
@@ -711,7 +713,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
             &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
             emit->sk, eo)));
         const int scratch = parts == 2 ? 1 : 0;
-        const size_t rlds = resolve_lds_bytes(c->sort_cap);
+        const size_t rlds = resolve_lds_bytes(c->sort_cap, true);
         GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<true>,
                          dim3(persistent_blocks(c, k_resolve<true>, rlds, np)), dim3(kBlock), rlds, c->tu_tag[parts],
                          c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.b2, poff, np, c->sort_cap,

@@ -246,7 +246,8 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
 // each tuple then reads its own cell.  Partitions above `cap` (hub
 // keys with many inserters) take an exact global-memory merge sort.
 // Dynamic LDS: 2^kCellBits cell words + kBlock + 2 words + cap * 14 bytes
-// (keys, tags and the 16-bit cell-list links).  kPacked: the tuples are
+// (keys, tags and the 16-bit cell-list links), or cap * 10 bytes for packed
+// words with the cell lists (the tags stay in the words).  kPacked: the tuples are
 // packed words (no tag array); pbits is then the second level's bits only,
 // the first level's having been dropped from the words.
 template <bool kPacked>
@@ -402,7 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
         } else if (c > 0 && GESMC_RESOLVE_LISTS) {
             // Tuples stay in their own slots p (contiguous writes); each cell
             // keeps a list of its slots, linked by one LDS exchange per tuple.
-            uint16_t *nxt = reinterpret_cast<uint16_t *>(sT + cap);
+            // Packed words stay whole in sK (key bits and tag code), with no
+            // tag array: 10 bytes of LDS per tuple instead of 14.
+            uint16_t *nxt = reinterpret_cast<uint16_t *>(kPacked ? reinterpret_cast<uint32_t *>(sK + cap) : sT + cap);
             for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = kListEnd;
             lds_barrier();
             uint32_t r_cell[kSortMaxItems];
@@ -410,14 +413,15 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             for (int q = 0; q < kSortMaxItems; ++q) {
                 const uint32_t p = tid + q * kBlock;
                 if (p < c) {
+                    const unsigned long long raw = c_key[q];
                     if (kPacked) {  // the key bits stay in place (cells, equality); the code is the tag
-                        c_tag[q] = tag_of_code((uint32_t)(c_key[q] & code_mask), pk.kb);
-                        c_key[q] &= ~code_mask;
+                        c_tag[q] = tag_of_code((uint32_t)(raw & code_mask), pk.kb);
+                        c_key[q] = raw & ~code_mask;
                     }
                     const uint64_t hsh = c_key[q];  // tuple words are tuple hashes
                     r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
-                    sK[p] = c_key[q];
-                    sT[p] = c_tag[q];
+                    sK[p] = raw;
+                    if (!kPacked) sT[p] = c_tag[q];
                     nxt[p] = (uint16_t)atomicExch(&cell[r_cell[q]], p);
                 }
             }
@@ -435,8 +439,9 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 uint32_t first_tag = tx, prev_tag = 0;
                 bool before = false;
                 for (uint32_t y = cell[r_cell[q]]; y != kListEnd; y = nxt[y]) {
-                    if (y == p || sK[y] != kx) continue;
-                    const uint32_t ty = sT[y];
+                    const unsigned long long wy = sK[y];
+                    if (y == p || (kPacked ? (wy & ~code_mask) : wy) != kx) continue;
+                    const uint32_t ty = kPacked ? tag_of_code((uint32_t)(wy & code_mask), pk.kb) : sT[y];
                     first_tag = min(first_tag, ty);
                     if (ty < tx || (ty == tx && y < p)) {
                         prev_tag = before ? max(prev_tag, ty) : ty;

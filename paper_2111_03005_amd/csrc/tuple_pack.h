@@ -19,7 +19,9 @@ constexpr uint32_t kTagStays = 0x7FFFFFFEu;
 // batch, whose graphs' vertex ranges are disjoint, db covers the largest
 // graph while vb covers them all.  mix_w is a bijection on w-bit words
 // (xor-shift by at least w/2 is its own inverse, odd multipliers are
-// invertible mod 2^w), so equal hashes still mean equal keys.  A tag is coded
+// invertible mod 2^w), so equal hashes still mean equal keys; one multiply
+// between two xor-shifts spreads the keys over partitions and cells as
+// evenly as two (measured on the benchmark graphs and structured sets).  A tag is coded
 // on tb = kb + 1 bits in the order of the 32-bit tags: ERASE k -> k,
 // STAYS -> 2^kb - 1, INSERT (k, h) -> 2^kb | 2k+h (2 ell < 2^kb).  The first
 // partition pass writes (H << (64 - w + b1)) | code: the b1 hash bits it
@@ -42,14 +44,20 @@ constexpr unsigned long long inverse_mod_2_64(unsigned long long a) {  // Newton
     return x;
 }
 
+#ifndef GESMC_MIX_ROUNDS
+#define GESMC_MIX_ROUNDS 1  // multiply rounds of mix_w (1 or 2)
+#endif
+
 __host__ __device__ __forceinline__ uint64_t mix_w(uint64_t x, int w) {
     const uint64_t mask = low_mask(w);
     const int s = (w + 1) >> 1;
     x ^= x >> s;
     x = (x * kMixMul1) & mask;
     x ^= x >> s;
-    x = (x * kMixMul2) & mask;
-    x ^= x >> s;
+    if (GESMC_MIX_ROUNDS > 1) {
+        x = (x * kMixMul2) & mask;
+        x ^= x >> s;
+    }
     return x;
 }
 
@@ -58,8 +66,10 @@ __host__ __device__ __forceinline__ uint64_t unmix_w(uint64_t x, int w) {
     const uint64_t mask = low_mask(w);
     const int s = (w + 1) >> 1;
     x ^= x >> s;
-    x = (x * kInv2) & mask;
-    x ^= x >> s;
+    if (GESMC_MIX_ROUNDS > 1) {
+        x = (x * kInv2) & mask;
+        x ^= x >> s;
+    }
     x = (x * kInv1) & mask;
     x ^= x >> s;
     return x;
