@@ -408,11 +408,11 @@ Plan make_plan(const gesmc_ctx *c, uint32_t m) {
 // LDS of k_scatter: counters, staged indices (none for packed tuple
 // words), keys and digits, and (batch level 1 only) staged global buckets.
 // It bounds the workgroups per CU.
-size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true, bool idx = true) {
+size_t scatter_lds_bytes(int dbits, uint32_t tile, bool buckets = true, bool idx = true, bool digits = true) {
     const size_t nd = (size_t)1 << dbits;
     size_t words = 3 * nd + scatter_threads((int)tile) / 64 + 1 + (idx ? tile : 0);
     words += words & 1;  // 8-byte alignment of the key stage
-    return words * 4 + (size_t)tile * 8 + (size_t)tile * 2 + (buckets ? (size_t)tile * 4 : 0);
+    return words * 4 + (size_t)tile * 8 + (digits ? (size_t)tile * 2 : 0) + (buckets ? (size_t)tile * 4 : 0);
 }
 
 // Every k_scatter instance may take more than 64 KiB of dynamic LDS (gfx950
@@ -545,7 +545,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
                      (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
     const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, kSrc1 != kSrcEmitPacked);
-    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked);
+    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked,
+                                          kSrc2 != kSrcPacked && kSrc2 != kSrcHashed);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
                      dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr, (const uint32_t *)nullptr,

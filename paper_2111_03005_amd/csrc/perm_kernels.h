@@ -615,6 +615,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
     constexpr int kTileItems = kTile / kThreads;
     constexpr uint32_t kScanWords = kThreads / 64 + 1;
     constexpr uint32_t kIdxWords = src_packed<kSrc>() ? 0u : (uint32_t)kTile;
+    // second tuple level: a staged word (packed word or tuple hash, moved
+    // unchanged) holds its own digit, so none is staged
+    constexpr bool kDigitOfWord = kSrc == kSrcPacked || kSrc == kSrcHashed;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
@@ -677,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
                 if (!src_packed<kSrc>()) s_idx[lp] = c_idx[q];
                 // kSrcEmitPacked: the tag code goes below the hash bits left after this level's digit
                 s_key[lp] = kSrc == kSrcEmitPacked ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
-                s_dig[lp] = (uint16_t)r_dig[q];
+                if (!kDigitOfWord) s_dig[lp] = (uint16_t)r_dig[q];
                 if (kSrc == kSrcBatch) s_bkt[lp] = r_bkt[q];
                 ++mine;
             }
@@ -686,11 +689,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
         lds_barrier();
         const uint32_t staged = s_total;
         for (uint32_t lp = tid; lp < staged; lp += kThreads) {
-            const uint32_t d = s_dig[lp];
+            const unsigned long long word = s_key[lp];
+            const uint32_t d = kDigitOfWord ? (uint32_t)(word >> shift) & dmask : s_dig[lp];
             const uint32_t g = base[d] + (lp - start[d]);
             if (g >= ts.seg_begin && g < ts.seg_end) {
                 if (!src_packed<kSrc>()) dst_idx[g] = s_idx[lp];
-                dst_key[g] = s_key[lp];
+                dst_key[g] = word;
                 if (kSrc == kSrcBatch) ba.aux_out[g] = s_bkt[lp];
             } else {
                 atomicOr(err, ERR_INTERNAL);
