@@ -261,7 +261,9 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
 #define GESMC_OPT_LEVEL1_BITS 8  /* digit bits of the first radix level (1 .. 10); 0 = half of the
                                     bucket bits, rounded up (default)                              */
 #define GESMC_OPT_FUSE_EMIT 9      /* 1: the first tuple partition pass computes the switches' tuples from
-                                      their pair records (default); 0: they are written out first     */
+                                      their pair records, and its count kernel also writes each
+                                      switch's status and records (default); 0: a separate emit
+                                      kernel, and the tuples are written out first                   */
 #define GESMC_OPT_GRAPH 10         /* 1: gesmc_run_batch captures its device work into a hipGraph on the
                                       second call of the same shape (pointers, sizes, offsets, r, pl,
                                       options) and replays it for later calls of that shape -- seeds,
