@@ -14,7 +14,8 @@
 //   pred(k, X) : the next smaller inserter of X                    -- the
 //                chain behind lookup_min over non-illegal inserters.
 // Only tuples with an eraser or a predecessor write their record (rare); all
-// other records keep the "free" value written by the emit kernel.
+// other records keep the "free" value written by the emit (k_emit or
+// k_emit_counts).
 //
 // Decision of switch k (same rule as Alg. 1): illegal if a target is erased
 // by a later switch / stays / is erased by an illegal switch, or if an
@@ -44,9 +45,11 @@ static_assert(kLdsCap < kListEnd, "k_resolve slots fit 16 bits");
 // local outcome of every switch (switch_local) goes to its status; a switch
 // decided locally also gets its records (unchanged) and its count, an
 // undecided one its two target records initialised to "free".  Workgroup 0
-// clears the undecided-list counters of the rounds that follow.  The
-// switches' tuples are not stored: the first partition pass computes them
-// from the same pair records (emit_switch).
+// clears the undecided-list counters of the rounds that follow.  This kernel
+// serves the unfused schedule; by default the same work runs inside the
+// first tuple count pass (k_emit_counts below), and the switches' tuples are
+// never stored: the first partition pass computes them from the same pair
+// records (emit_switch).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_idx,
                                                  const unsigned long long *__restrict__ s_key, uint32_t t, uint32_t k0,
