@@ -29,6 +29,9 @@ MUT_WRITE_SWAP = 16
 MUT_NO_ERASE = 32
 MUT_PAIR_SHIFT = 64
 MUT_KEY_SWAP = 128
+MUT_ES_J_ANY = 1 << 16
+MUT_ES_G_HIGH = 1 << 17
+MUT_ES_NO_SKIP = 1 << 18
 
 
 class Counts(ctypes.Structure):
@@ -73,6 +76,12 @@ def _load():
     lib.oracle_global_switch.restype = ctypes.c_int
     lib.oracle_run.argtypes = [vp, u64, u32, u64, u32, u32, u32, vp, vp, u32]
     lib.oracle_run.restype = ctypes.c_int
+    lib.oracle_es_draws.argtypes = [u64, u64, u64, u64, vp, vp, vp, u32]
+    lib.oracle_es_draws.restype = None
+    lib.oracle_edge_switch.argtypes = [vp, u64, u64, u64, ctypes.c_int]
+    lib.oracle_edge_switch.restype = ctypes.c_int
+    lib.oracle_es_run.argtypes = [vp, u64, u32, u64, u64, u64, vp, vp, u32]
+    lib.oracle_es_run.restype = ctypes.c_int
     lib.oracle_selftest_edgeset.argtypes = [u64, u64]
     lib.oracle_selftest_edgeset.restype = u64
     _lib = lib
@@ -145,6 +154,32 @@ def run_batch(graphs, seeds, rs, t0s=None, pl: int = 0):
         rc, E2, counts, _ = run(E, n, seeds[g], 0 if t0s is None else t0s[g], rs[g], pl)
         out.append((rc, E2, counts))
     return out
+
+
+def es_draws(seed: int, k0: int, count: int, m: int, mutate: int = 0):
+    """ES-MC draws of switches k0 .. k0+count-1 on m edges: (i, j, g) arrays."""
+    i = np.empty(max(count, 1), dtype=np.uint64)
+    j = np.empty(max(count, 1), dtype=np.uint64)
+    g = np.empty(max(count, 1), dtype=np.uint8)
+    _load().oracle_es_draws(seed & (2**64 - 1), k0, count, m, _p(i), _p(j), _p(g), mutate)
+    return i[:count], j[:count], g[:count]
+
+
+def edge_switch(E: np.ndarray, i: int, j: int, g: int):
+    """One edge switch (Def. 2.1) on a copy of E: (E', outcome code)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    oc = _load().oracle_edge_switch(_p(E), len(E), i, j, g)
+    return E, oc
+
+
+def es_run(E: np.ndarray, n: int, seed: int, k0: int, r: int, mutate: int = 0, outcomes: bool = False):
+    """ES-MC (Def. 2.1; the chain Alg. 2 parallelises): r switches from switch
+    counter k0.  Returns (status, E', counts, per-switch outcomes or None)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    c = Counts()
+    oc = np.zeros(max(r, 1), dtype=np.uint8) if outcomes else None
+    rc = _load().oracle_es_run(_p(E), len(E), n, seed & (2**64 - 1), k0, r, ctypes.byref(c), _p(oc), mutate)
+    return rc, E, c.as_dict(), (oc[:r] if outcomes else None)
 
 
 def selftest_edgeset(ops: int = 200000, seed: int = 1) -> int:

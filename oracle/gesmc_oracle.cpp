@@ -31,6 +31,17 @@
 // A uniform random key per element, sorted, is a uniform random permutation
 // (up to key ties, broken by index) -- the random-keys permutation the
 // paper's parallel shuffling builds on (Sec. 5.3).
+//
+// ES-MC (Def. 2.1, the chain that Alg. 2, ParES, parallelises): r edge
+// switches in sequence, switch k (a 64-bit counter, k0 .. k0+r-1) drawn as
+//   (x0, x1, x2, x3) = Philox(ctr = (k_lo, k_hi, 0, 2), key = (seed_lo, seed_hi))
+//   i = floor(((x0 << 32) | x1) * m / 2^64)            uniform on [0, m)
+//   j' = floor(((x2 << 32) | x3) * (m - 1) / 2^64),  j = j' + [j' >= i]
+//                                                       uniform on [0, m) \ {i}
+//   g = x1 & 1
+// (i != j as Alg. 2 samples them; the biases of the 64-bit products are
+// below m / 2^64).  Tags 0 and 1 of the Philox counter are the permutation
+// and P_L draws of G-ES-MC, so the streams never meet.
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
@@ -275,6 +286,32 @@ static void global_switch(uint64_t *E, uint64_t m, EdgeSet &S, const uint32_t *p
     }
 }
 
+// ---- ES-MC (Def. 2.1; the sequential chain of Alg. 2) -------------------
+static uint64_t mulhi64(uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) >> 64); }
+
+// Planted mistakes of the ES-MC draws (for the pin tests).
+enum {
+    MUT_ES_J_ANY = 1u << 16,    // j drawn from all of [0, m) (may equal i)
+    MUT_ES_G_HIGH = 1u << 17,   // g taken from bit 0 of x0 instead of x1
+    MUT_ES_NO_SKIP = 1u << 18,  // j = j' (no skip of i): j never reaches m - 1
+};
+
+static void es_draw(uint64_t seed, uint64_t k, uint64_t m, uint32_t mutate, uint64_t *i, uint64_t *j, int *g) {
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), 0u, 2u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    philox10(ctr, key, x);
+    const uint64_t w0 = ((uint64_t)x[0] << 32) | x[1], w1 = ((uint64_t)x[2] << 32) | x[3];
+    *i = mulhi64(w0, m);
+    if (mutate & MUT_ES_J_ANY) {
+        *j = mulhi64(w1, m);
+    } else {
+        const uint64_t jp = mulhi64(w1, m - 1);
+        *j = (mutate & MUT_ES_NO_SKIP) ? jp : jp + (jp >= *i ? 1 : 0);
+    }
+    *g = (mutate & MUT_ES_G_HIGH) ? (int)(x[0] & 1u) : (int)(x[1] & 1u);
+}
+
 // Checks that E is a simple graph on [0, n): every key has min < max < n.
 // Returns 0 if simple, -2 for a loop or duplicate, -3 for an id out of range.
 int oracle_validate(const uint64_t *E, uint64_t m, uint32_t n) {
@@ -319,6 +356,53 @@ int oracle_run(uint64_t *E, uint64_t m, uint32_t n, uint64_t seed, uint32_t t0, 
         for (uint64_t k = 0; k < m / 2; ++k) skip[k] = pl_skip(seed, t, k, pl) ? 1 : 0;
         global_switch(E, m, S, pi.data(), skip.data(), (s + 1 == r) ? last_outcome : nullptr,
                       per_step ? &per_step[s] : nullptr, mutate);
+    }
+    return 0;
+}
+
+// The draws (i, j, g) of ES-MC switches k0 .. k0+count-1 on m edges.
+void oracle_es_draws(uint64_t seed, uint64_t k0, uint64_t count, uint64_t m, uint64_t *i, uint64_t *j, uint8_t *g,
+                     uint32_t mutate) {
+    for (uint64_t q = 0; q < count; ++q) {
+        int gg = 0;
+        es_draw(seed, k0 + q, m, mutate, &i[q], &j[q], &gg);
+        g[q] = (uint8_t)gg;
+    }
+}
+
+// One edge switch (i, j, g) of Def. 2.1 on E and its edge set (built here):
+// for exhaustive tests.  Returns the outcome code.
+int oracle_edge_switch(uint64_t *E, uint64_t m, uint64_t i, uint64_t j, int g) {
+    EdgeSet S(m);
+    for (uint64_t e = 0; e < m; ++e) S.insert(E[e]);
+    return edge_switch(E, S, i, j, g, 0);
+}
+
+// ES-MC: switches k = k0 .. k0+r-1 with the draws above, applied one after
+// another by Def. 2.1 (validated and canonicalised first, as oracle_run).
+// counts (nullable): totals; outcome (nullable, r bytes): per switch.
+// m < 2 leaves E as it is (no pair of distinct indices exists).
+int oracle_es_run(uint64_t *E, uint64_t m, uint32_t n, uint64_t seed, uint64_t k0, uint64_t r, oracle_counts *counts,
+                  uint8_t *outcome, uint32_t mutate) {
+    int rc = oracle_validate(E, m, n);
+    if (rc) return rc;
+    for (uint64_t e = 0; e < m; ++e) E[e] = make_key(key_u(E[e]), key_v(E[e]));
+    if (counts) memset(counts, 0, sizeof(*counts));
+    if (m < 2) return 0;
+    EdgeSet S(m);
+    for (uint64_t e = 0; e < m; ++e) S.insert(E[e]);
+    for (uint64_t q = 0; q < r; ++q) {
+        uint64_t i, j;
+        int g;
+        es_draw(seed, k0 + q, m, mutate, &i, &j, &g);
+        const int oc = edge_switch(E, S, i, j, g, mutate & 0xFFFFu);
+        if (outcome) outcome[q] = (uint8_t)oc;
+        if (counts) {
+            counts->attempts++;
+            if (oc == OR_LEGAL) counts->legal++;
+            if (oc == OR_LOOP) counts->rej_loop++;
+            if (oc == OR_EXISTS) counts->rej_exists++;
+        }
     }
     return 0;
 }

@@ -102,3 +102,44 @@ def run(E, seed: int, t0: int, r: int, pl: int = 0):
         counts.append(dict(attempts=m // 2, legal=last.count(LEGAL), rej_loop=last.count(LOOP),
                            rej_exists=last.count(EXISTS), rej_pl=last.count(PL)))
     return E, counts, last
+
+
+# ---------------------------------------------------------------------------
+# ES-MC (Def. 2.1, the chain Alg. 2 parallelises), written out separately
+# ---------------------------------------------------------------------------
+
+def es_draw(seed: int, k: int, m: int):
+    """Switch k's (i, j, g): Philox at counter (k_lo, k_hi, 0, 2); i uniform on
+    [0, m) from the first 64-bit word, j uniform on [0, m) without i from the
+    second (the value j' on [0, m-1) moved up past i), g the lowest bit of x1."""
+    x = philox4x32_10((k & M32, k >> 32, 0, 2), (seed & M32, seed >> 32))
+    w0 = (x[0] << 32) | x[1]
+    w1 = (x[2] << 32) | x[3]
+    i = (w0 * m) >> 64
+    jp = (w1 * (m - 1)) >> 64
+    j = jp + 1 if jp >= i else jp
+    return i, j, x[1] & 1
+
+
+def es_run(E, seed: int, k0: int, r: int):
+    """r ES-MC switches from counter k0, one at a time: (E, outcome codes)."""
+    E = [_key(*_split(e)) for e in E]
+    m = len(E)
+    out = []
+    if m < 2:
+        return E, out
+    for k in range(k0, k0 + r):
+        i, j, g = es_draw(seed, k, m)
+        u, v = _split(E[i])
+        x, y = _split(E[j])
+        a, b = ((u, x), (v, y)) if g == 0 else ((u, y), (v, x))
+        if a[0] == a[1] or b[0] == b[1]:
+            out.append(LOOP)
+            continue
+        e3, e4 = _key(*a), _key(*b)
+        if e3 in E or e4 in E:
+            out.append(EXISTS)
+            continue
+        E[i], E[j] = e3, e4
+        out.append(LEGAL)
+    return E, out

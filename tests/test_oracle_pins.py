@@ -289,6 +289,31 @@ def test_naive_equals_oracle():
     assert pin_naive()
 
 
+def test_oracle_resumes_exactly():
+    """Alg. 3 is r global switches in a row, each a function of the edge list
+    and its superstep t only: oracle.run(E, t0, a + b) equals oracle.run on
+    the output of oracle.run(E, t0, a), from t0 + a, for b more.  (The
+    largest GPU parity check splits the oracle's run at superstep boundaries
+    on this identity.)  Checked against the naive replay's single run too."""
+    for E, n, seed, pl in [(graphgen.powerlaw_graph(3000, 2.2, 2, 54, 5), 3000, 9, 0),
+                           (graphgen.gnp(400, 0.05, 4), 400, 1 << 40, 1 << 30)]:
+        rc, full, cf, _ = oracle.run(E, n, seed, 3, 6, pl)
+        assert rc == 0
+        cur, cs = E, []
+        for a, b in [(3, 2), (5, 3), (8, 1)]:
+            rc, cur, c, _ = oracle.run(cur, n, seed, a, b, pl)
+            assert rc == 0
+            cs += c
+        assert np.array_equal(cur, full)
+        assert cs == cf
+    E = graphgen.gnp(60, 0.2, 2)
+    En, cn, _ = naive.run([int(x) for x in E], 5, 2, 3, 0)
+    cur = E
+    for t in (2, 3, 4):
+        _, cur, _, _ = oracle.run(cur, 60, 5, t, 1, 0)
+    assert [int(x) for x in cur] == En
+
+
 # ---------------------------------------------------------------------------
 # Thm. 3.3: exact transition matrix; chi-square uniformity over G(d)
 # ---------------------------------------------------------------------------
