@@ -1,14 +1,16 @@
 """Benchmark of the G-ES-MC global switch on one MI355X.
 
-Headline (value): the plain form on the power-law n=2^20 graph.  A step is
-one call of the library: input edges resident in HBM -> load and validation
--> r global switches (permutation, dependency resolution, rounds of
-decisions) -> edges back in position order.  The value is switch attempts
+Headline (value): the plain form on G(n,p) with n=2^22 and average degree 32
+(m = 67,125,011, 10 global switches per step), the HBM-bound instance.  A
+step is one call of the library: input edges resident in HBM -> load and
+validation -> r global switches (permutation, dependency resolution, rounds
+of decisions) -> edges back in position order.  The value is switch attempts
 per second over the timed steps (floor(m/2) attempts per superstep, rejected
 ones included), the convention of the paper's runtime table (init +
-supersteps).  The same line carries the batched form (4096 graphs in one
-call, beside the plain form looping over the same graphs) and the served
-form (Poisson request streams: p50 / p99 latency and attempts/s).
+supersteps).  The same line carries the other plain workloads (power-law
+n=2^20, G(1024, 10/1023)) under plain_<name>, the batched form (4096 graphs
+in one call, beside the plain form looping over the same graphs) and the
+served form (Poisson request streams: p50 / p99 latency and attempts/s).
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -57,46 +59,65 @@ def kernel_bytes(name: str, m: int, ell: int, tb: int = 12) -> float | None:
     }.get(name)
 
 
-def switch_roofline(value: float, legal_fraction: float, G: int = 64):
+def switch_roofline(value: float, legal_fraction: float, G: float | None):
     """Attempts/s against the HBM bound of the method's own traffic: per
     attempt 2 source reads and 2 target probes, and for an accepted switch 2
     edge writes plus 2 erases and 2 inserts in the edge set (2 touches each),
-    every random touch one G-byte transaction, plus 16 streaming bytes of the
-    permutation: B_txn = G (4 + 10 a) + 16; B_alg = 48 + 48 a at byte level."""
+    every random touch one G-byte DRAM transaction, plus 16 streaming bytes of
+    the permutation: B_txn = G (4 + 10 a) + 16; B_alg = 48 + 48 a at byte
+    level.  G is the transaction size measured for isolated random 8-byte
+    reads (profiles/gather_calibration.json); None if it was never measured."""
     a = legal_fraction
-    b_txn = G * (4 + 10 * a) + 16
     b_alg = 48 + 48 * a
-    bound = HBM_PEAK_GBS * 1e9 / b_txn
     bound_alg = HBM_PEAK_GBS * 1e9 / b_alg  # byte-level lower bound on the traffic: an upper bound on attempts/s
-    return {"G_bytes": G, "bytes_per_attempt_txn": round(b_txn, 1), "bytes_per_attempt_alg": round(b_alg, 1),
-            "bound_attempts_per_s": round(bound, 1), "frac": round(value / bound, 4),
-            "bound_attempts_per_s_alg": round(bound_alg, 1), "frac_alg": round(value / bound_alg, 4)}
+    out = {"bytes_per_attempt_alg": round(b_alg, 1), "bound_attempts_per_s_alg": round(bound_alg, 1),
+           "frac_alg": round(value / bound_alg, 4), "G_bytes": None}
+    if G:
+        b_txn = G * (4 + 10 * a) + 16
+        bound = HBM_PEAK_GBS * 1e9 / b_txn
+        out.update({"G_bytes": round(G, 1), "G_source": "profiles/gather_calibration.json",
+                    "bytes_per_attempt_txn": round(b_txn, 1), "bound_attempts_per_s": round(bound, 1),
+                    "frac": round(value / bound, 4)})
+    return out
+
+
+# The kernel sources of the plain path's supersteps: HBM counters taken on
+# them stay valid while these files are unchanged.
+PLAIN_KERNEL_SOURCES = ("device_common.h", "perm_kernels.h", "resolve_kernels.h", "switch_kernels.h", "tuple_pack.h")
 
 
 def source_digest() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2111_03005_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in PLAIN_KERNEL_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources; else None."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+def _profile_json(name: str):
     try:
-        with open(p) as fh:
-            d = json.load(fh)
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            return json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("source_digest") != source_digest():
+
+
+def load_traffic(workload: str):
+    """Per-kernel HBM bytes per launch from committed rocprofv3 counter runs
+    (read and write request counts by size), if they were taken on the
+    current kernel sources; else None."""
+    d = _profile_json("traffic.json")
+    if not d or d.get("source_digest") != source_digest():
         return None
-    rec = d.get("kernels", {}).get(workload, {}).get(kernel)
-    if not rec:
-        return None
-    return rec.get("bytes_per_launch")
+    return d.get("kernels", {}).get(workload)
+
+
+def measured_G():
+    """DRAM transaction bytes per isolated random 8-byte read, measured with
+    the request-size counters on a random gather (bench.py --gather-calibration)."""
+    d = _profile_json("gather_calibration.json")
+    return d.get("G_bytes") if d else None
 
 
 def host_cpu():
@@ -337,15 +358,152 @@ def bench_served(gesmc, torch, args):
                         "r uniform in 10..50, own Philox seed" % len(pool)}
 
 
+def bench_plain(gesmc, torch, args, workload: str, steps: int, warmup: int, host_api: bool = False):
+    """The plain form on one named workload: whole gesmc_run calls (r global
+    switches each) with the input resident in HBM.  Returns the record and
+    the input (for the CPU baseline)."""
+    import graphgen
+    make, r = graphgen.WORKLOADS[workload]
+    E, n = make()
+    m = len(E)
+    ell = m // 2
+    dev = torch.device("cuda", 0)
+    ctx = gesmc.Context(0)
+    for opt in args.option:
+        name, val = opt.split("=")
+        ctx.set_option(getattr(gesmc, "OPT_" + name.upper()), int(val))
+    d_in = torch.from_numpy(E.view(np.int64).copy()).to(dev)
+    d_out = torch.empty_like(d_in)
+    stream = torch.cuda.current_stream()
+
+    # Warm-up: the first pass times every kernel (events between all launches)
+    # to find the dominant one; the timed steps then carry events around that
+    # kernel only, on the launch stream, so the clock around them is barely
+    # disturbed.
+    ctx.set_option(gesmc.OPT_PROFILE, 0 if args.no_profile else 1)
+    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
+    ctx.profile_reset()
+    wst = None
+    for w in range(max(warmup, 1)):
+        _, wst = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream)
+        if w == 0:
+            torch.cuda.synchronize()
+            ctx.set_option(gesmc.OPT_PROFILE, 0)
+    torch.cuda.synchronize()
+    warm_prof = ctx.profile()
+    tb = int(wst["tuple_bytes"]) or 12
+    dominant = None
+    for name, (ms, launches, items) in sorted(warm_prof.items(), key=lambda kv: -kv[1][0]):
+        print("%s warm-up kernel %-16s total %9.3f ms  launches %5d" % (workload, name, ms, launches),
+              file=sys.stderr)
+        if dominant is None and kernel_bytes(name, m, ell, tb) is not None:
+            dominant = name
+    warm_total = sum(v[0] for v in warm_prof.values())
+
+    if dominant is not None:
+        ctx.set_option(gesmc.OPT_PROFILE, 1)
+        ctx.set_option(gesmc.OPT_PROFILE_ONLY, gesmc.Context.kernel_names().index(dominant))
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    step_ms = []
+    for _ in range(steps):
+        _, stats = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream)
+        step_ms.append(stats["ms_device"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_option(gesmc.OPT_PROFILE, 0)
+    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
+    prof = ctx.profile()
+
+    value = steps * r * ell / wall
+    a = stats["legal"] / max(stats["attempts"], 1)
+    traffic = load_traffic(workload) or {}
+    roofline = None
+    if dominant is not None and dominant in prof:
+        ms, launches, items = prof[dominant]
+        b = kernel_bytes(dominant, m, ell, tb)
+        avg_s = ms / launches / 1e3
+        achieved = b / avg_s / 1e9
+        print("%s timed kernel %s: %d launches, avg %.4f ms, %.0f GB/s" % (
+            workload, dominant, launches, avg_s * 1e3, achieved), file=sys.stderr)
+        tr = traffic.get(dominant)
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": tr["bytes_per_launch"] if tr else None,
+                    "traffic_over_alg": round(tr["bytes_per_launch"] / b, 3) if tr else None,
+                    "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 4),
+                    "share_of_step": round(ms / (wall * 1e3), 3)}
+    # whole-superstep HBM traffic from the counter runs (every kernel of a
+    # superstep), over the measured time per superstep
+    step_traffic = None
+    if traffic:
+        per_step = sum(v["bytes_per_launch"] * v.get("launches_per_superstep", 1) for v in traffic.values())
+        s_per_superstep = wall / (steps * r)
+        step_traffic = {"bytes_per_superstep": round(per_step), "bytes_per_attempt": round(per_step / ell, 1),
+                        "achieved_GBs": round(per_step / s_per_superstep / 1e9, 1),
+                        "frac": round(per_step / s_per_superstep / 1e9 / HBM_PEAK_GBS, 4)}
+    rec = {"workload": workload, "value": round(value, 1), "unit": "attempts/s", "n": n, "m": m,
+           "supersteps_per_step": r, "attempts_per_step": r * ell, "steps": steps,
+           "ms_per_step": round(1000.0 * wall / steps, 3),
+           "step_ms_device_p50": round(float(np.median(step_ms)), 3) if step_ms else None,
+           "legal_fraction": round(a, 5), "rounds_max": stats["rounds_max"],
+           "tuple_bytes": int(stats["tuple_bytes"]), "timed_kernel_events": dominant,
+           "kernel_share_warmup": {k: round(v[0] / warm_total, 3) for k, v in warm_prof.items()} if warm_total else None,
+           "roofline": roofline, "superstep_traffic": step_traffic,
+           "switch_roofline": switch_roofline(value, a, measured_G())}
+    if host_api:
+        # the host entry point on the same workload: edges in and out of host
+        # memory, so both PCIe copies are inside the time (never the headline)
+        uv = np.stack([(E >> np.uint64(32)).astype(np.uint32), (E & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1)
+        ctx.run_host(uv, n, args.seed, 0, r)  # sizes its staging
+        t = time.perf_counter()
+        ctx.run_host(uv, n, args.seed, 0, r)
+        dt_host = time.perf_counter() - t
+        rec["host_api"] = {"value": round(r * ell / dt_host, 1), "unit": "attempts/s",
+                           "ms_per_call": round(1e3 * dt_host, 3),
+                           "note": "gesmc_run_host, %d supersteps per call, incl. host->device and device->host "
+                                   "copies" % r}
+    ctx.close()
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    print("%s: %.3e attempts/s (%.3f ms per %d-superstep call)" % (workload, value, rec["ms_per_step"], r),
+          file=sys.stderr)
+    return rec, E, n, r
+
+
+def gather_calibration(mib: int, count: int):
+    """Isolated random 8-byte reads: index_select of `count` random int64
+    words from a `mib` MiB buffer, three times.  Under rocprofv3's read
+    request-size counters this gives the DRAM bytes moved per random 8-byte
+    read (the gather kernel also streams its index array and output)."""
+    import torch
+    words = (mib << 20) // 8
+    src = torch.arange(words, dtype=torch.int64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    idx = torch.randint(0, words, (count,), dtype=torch.int64, device="cuda", generator=g)
+    out = None
+    for _ in range(3):
+        out = torch.index_select(src, 0, idx)
+    torch.cuda.synchronize()
+    assert int(out[0]) == int(idx[0])
+    print(json.dumps({"gather_calibration_buffer_bytes": words * 8, "gathers": count, "repeats": 3,
+                      "streamed_bytes_per_gather": 16}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pld_n2^20_g2.5")
+    ap.add_argument("--workload", default="gnp_n2^22_d32", help="the headline workload (plain form)")
+    ap.add_argument("--extra-workloads", nargs="*", default=["pld_n2^20_g2.5", "gnp_n1024_d10"],
+                    help="further plain workloads reported under plain_<name>")
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-supersteps", type=int, default=3)
+    ap.add_argument("--cpu-sample-supersteps", type=int, default=1)
     ap.add_argument("--no-profile", action="store_true", help="no kernel events at all (no roofline)")
     ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
                     help="library option (e.g. PERSIST=2, STRATEGY=1); results never depend on options")
@@ -361,6 +519,9 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=32 << 30, help="HBM budget of the server, bytes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
+    ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 2^26 random 8-byte gathers from a MIB MiB buffer (3 times): the DRAM "
+                         "transaction size of isolated random reads, from the request-size counters")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -373,6 +534,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}))
         return
+    if args.gather_calibration:
+        gather_calibration(args.gather_calibration, 1 << 26)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -381,86 +545,14 @@ def main():
 
     import torch
 
-    import graphgen
     import paper_2111_03005_amd as gesmc
 
-    make, r = graphgen.WORKLOADS[args.workload]
-    E, n = make()
-    m = len(E)
-    ell = m // 2
-    dev = torch.device("cuda", 0)
-    ctx = gesmc.Context(0)
-    for opt in args.option:
-        name, val = opt.split("=")
-        ctx.set_option(getattr(gesmc, "OPT_" + name.upper()), int(val))
-    d_in = torch.from_numpy(E.view(np.int64).copy()).to(dev)
-    d_out = torch.empty_like(d_in)
-    stream = torch.cuda.current_stream()
-
-    # Warm-up: the first pass times every kernel (events between all launches)
-    # to find the dominant one; the timed steps then carry events around that
-    # kernel only, so the clock around them is barely disturbed.
-    ctx.set_option(gesmc.OPT_PROFILE, 0 if args.no_profile else 1)
-    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
-    ctx.profile_reset()
-    for w in range(max(args.warmup, 1)):
-        _, wst = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out)
-        if w == 0:
-            torch.cuda.synchronize()
-            ctx.set_option(gesmc.OPT_PROFILE, 0)
-    torch.cuda.synchronize()
-    warm_prof = ctx.profile()
-    tb = int(wst["tuple_bytes"]) or 12
-    dominant = None
-    for name, (ms, launches, items) in sorted(warm_prof.items(), key=lambda kv: -kv[1][0]):
-        print("warm-up kernel %-16s total %9.3f ms  launches %5d" % (name, ms, launches), file=sys.stderr)
-        if dominant is None and kernel_bytes(name, m, ell, tb) is not None:
-            dominant = name
-
-    if dominant is not None:
-        ctx.set_option(gesmc.OPT_PROFILE, 1)
-        ctx.set_option(gesmc.OPT_PROFILE_ONLY, gesmc.Context.kernel_names().index(dominant))
-    ctx.profile_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = None
-    step_ms = []
-    for _ in range(args.steps):
-        _, stats = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream)
-        step_ms.append(stats["ms_device"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.set_option(gesmc.OPT_PROFILE, 0)
-    ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
-    prof = ctx.profile()
-
-    attempts = args.steps * r * ell
-    value = attempts / wall
-    ms_per_step = 1000.0 * wall / args.steps
-
-    roofline = None
-    if dominant is not None and dominant in prof:
-        ms, launches, items = prof[dominant]
-        b = kernel_bytes(dominant, m, ell, tb)
-        avg_s = ms / launches / 1e3
-        achieved = b / avg_s / 1e9
-        print("timed kernel %s: %d launches, avg %.4f ms, %.0f GB/s" % (dominant, launches, avg_s * 1e3, achieved),
-              file=sys.stderr)
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(dominant, args.workload),
-                    "bytes_per_launch": b, "avg_launch_ms": round(avg_s * 1e3, 4),
-                    "share_of_step": round(ms / (wall * 1e3), 3)}
-
-    # the host entry point on the same workload: edges in and out of host
-    # memory, so both PCIe copies are inside the time (never the headline)
-    uv = np.stack([(E >> np.uint64(32)).astype(np.uint32), (E & np.uint64(0xFFFFFFFF)).astype(np.uint32)], 1)
-    ctx.run_host(uv, n, args.seed, 0, r)  # sizes its staging
-    t = time.perf_counter()
-    ctx.run_host(uv, n, args.seed, 0, r)
-    dt_host = time.perf_counter() - t
-    host_api = {"value": round(r * ell / dt_host, 1), "unit": "attempts/s", "ms_per_call": round(1e3 * dt_host, 3),
-                "note": "gesmc_run_host, %d supersteps per call, incl. host->device and device->host copies" % r}
+    head, E, n, r = bench_plain(gesmc, torch, args, args.workload, args.steps, args.warmup, host_api=True)
+    extra = {}
+    for w in args.extra_workloads:
+        if w != args.workload:
+            rec, _, _, _ = bench_plain(gesmc, torch, args, w, args.steps, args.warmup)
+            extra["plain_" + w] = rec
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -470,38 +562,42 @@ def main():
         cpu = {"value": round(v, 1), "unit": "attempts/s", "cores": 1, "kind": "oracle",
                "sample": "%s, first %d of %d supersteps incl. validation and set build (%.1f s)" % (
                    args.workload, rs, r, dt), "host_cpu": model, "host_logical_cpus": nproc}
+        print("oracle: %s" % cpu, file=sys.stderr)
+    del E
 
-    ctx.close()
-    batched = None if args.no_batched else bench_batched(gesmc, torch, args, value)
+    batched = None if args.no_batched else bench_batched(gesmc, torch, args, head["value"])
     served = None if args.no_served else bench_served(gesmc, torch, args)
 
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": head["value"],
         "unit": "attempts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": max(args.warmup, 1),
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "supersteps_per_step": r,
-                   "attempts_per_step": r * ell, "seed": args.seed, "pl": 0, "mode": "plain",
-                   "legal_fraction": round(stats["legal"] / max(stats["attempts"], 1), 5) if stats else None,
-                   "rounds_max": stats["rounds_max"] if stats else None,
-                   "tuple_bytes": int(stats["tuple_bytes"]) if stats else None,
-                   "step_ms_device_p50": round(float(np.median(step_ms)), 3) if step_ms else None,
-                   "timed_kernel_events": dominant if not args.no_profile else None, "options": args.option},
-        "roofline": roofline,
-        "switch_roofline": switch_roofline(value, stats["legal"] / max(stats["attempts"], 1)) if stats else None,
-        "host_api": host_api,
+        "config": {"workload": args.workload, "n": head["n"], "m": head["m"],
+                   "supersteps_per_step": head["supersteps_per_step"],
+                   "attempts_per_step": head["attempts_per_step"], "seed": args.seed, "pl": 0, "mode": "plain",
+                   "legal_fraction": head["legal_fraction"], "rounds_max": head["rounds_max"],
+                   "tuple_bytes": head["tuple_bytes"], "step_ms_device_p50": head["step_ms_device_p50"],
+                   "timed_kernel_events": head["timed_kernel_events"] if not args.no_profile else None,
+                   "options": args.option},
+        "roofline": head["roofline"],
+        "superstep_traffic": head["superstep_traffic"],
+        "switch_roofline": head["switch_roofline"],
+        "kernel_share_warmup": head["kernel_share_warmup"],
+        "host_api": head.get("host_api"),
         "cpu_baseline": cpu,
-        "batched": batched,
-        "served": served,
     }
+    out.update(extra)
+    out["batched"] = batched
+    out["served"] = served
     print(json.dumps(out))
 
 

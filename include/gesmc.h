@@ -45,6 +45,7 @@ typedef int32_t gesmc_status;
 #define GESMC_E_DEVICE (-5)     /* HIP runtime error                               */
 #define GESMC_E_AGAIN (-6)      /* server: queue full (submit) / not done (poll)   */
 #define GESMC_E_CANCELED (-7)   /* server: the request was cancelled               */
+#define GESMC_E_ROUNDS (-8)     /* a superstep exceeded GESMC_OPT_ROUND_LIMIT      */
 #define GESMC_E_INTERNAL (-9)   /* an internal consistency check failed            */
 
 typedef struct gesmc_ctx gesmc_ctx;
@@ -76,7 +77,7 @@ typedef struct gesmc_step_stats {
 } gesmc_step_stats;
 
 /* Creates a context on HIP device `hip_device`.  Device memory is allocated
- * lazily and kept for later calls (about 110 bytes per edge).  *out receives
+ * lazily and kept for later calls (about 136 bytes per edge).  *out receives
  * the context; release it with gesmc_destroy. */
 gesmc_status gesmc_create(int hip_device, gesmc_ctx **out);
 void gesmc_destroy(gesmc_ctx *ctx);
@@ -203,14 +204,19 @@ typedef struct gesmc_server_info {
 /* Starts the worker (cfg nullable: defaults).  Fails with GESMC_E_NOMEM if
  * the budget cannot be allocated.  *out receives the server. */
 gesmc_status gesmc_server_create(gesmc_ctx *ctx, const gesmc_server_cfg *cfg, gesmc_server **out);
-/* Stops the worker; requests still queued or resident are dropped. */
+/* Stops the worker; requests still queued or resident are dropped.  Threads
+ * blocked in gesmc_wait on this server return first, with a result whose
+ * status is GESMC_E_CANCELED (unless their request had finished); destroy
+ * waits for them to leave before it frees anything.  No other call on the
+ * server may start once destroy has been entered. */
 void gesmc_server_destroy(gesmc_server *srv);
 /* Queues a request (edges copied; thread-safe).  GESMC_E_AGAIN if the queue is
  * full, GESMC_E_RANGE if the graph can never fit the budget, GESMC_E_INVAL for
  * bad arguments.  Input errors of the graph itself are reported in its result. */
 gesmc_status gesmc_submit(gesmc_server *srv, const gesmc_request *req, uint64_t *ticket);
 /* Non-blocking: fills *out and forgets the ticket if the request is done,
- * else returns GESMC_E_AGAIN.  GESMC_E_INVAL for an unknown ticket. */
+ * else returns GESMC_E_AGAIN.  GESMC_E_INVAL for an unknown ticket.  A ticket
+ * is taken by one thread: two threads must not poll or wait on the same one. */
 gesmc_status gesmc_poll(gesmc_server *srv, uint64_t ticket, gesmc_result *out);
 /* As gesmc_poll, but blocks until the request is done. */
 gesmc_status gesmc_wait(gesmc_server *srv, uint64_t ticket, gesmc_result *out);
@@ -248,7 +254,8 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                   const uint64_t *offsets, const uint32_t *n, const uint64_t *seed,
                                   uint32_t supersteps, gesmc_tuning *out);
 
-/* Tuning knobs (values are validated; results never depend on them). */
+/* Tuning knobs (values are validated; results never depend on them, except
+ * that GESMC_OPT_ROUND_LIMIT can make a call fail). */
 #define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 1152, default 1152)  */
 #define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1536, default 1536)     */
 #define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64) */
@@ -268,8 +275,9 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                       second call of the same shape (pointers, sizes, offsets, r, pl,
                                       options) and replays it for later calls of that shape -- seeds,
                                       t0 and n may change; needs a non-NULL stream (default 0)         */
-#define GESMC_OPT_SMALL_GRAPHS 11  /* 1: in gesmc_run_batch, graphs of at most 1024 edges run all their
-                                      supersteps in one workgroup's LDS (one launch for all of them);
+#define GESMC_OPT_SMALL_GRAPHS 11  /* 1: in gesmc_run_batch, graphs of at most 4096 edges run all their
+                                      supersteps in one workgroup's LDS (one launch per size class:
+                                      up to 1024 edges on 256 threads, up to 4096 on 1024);
                                       0: every graph takes the multi-kernel supersteps (default 1)   */
 #define GESMC_OPT_PACK_TUPLES 12   /* 1: dependency tuples travel as one 8-byte word (a bijective hash of
                                       the edge key on 2 x the vertex id bits, minus the bits the first
@@ -278,6 +286,13 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */
+#define GESMC_OPT_ROUND_LIMIT 13  /* decision rounds a superstep may take (Alg. 1's loop, counted as in
+                                     gesmc_step_stats.rounds) before the call fails with GESMC_E_ROUNDS
+                                     and d_out untouched; 0 = no limit (default).  A debugging cap for
+                                     the multi-kernel supersteps of GESMC_OPT_STRATEGY 0 (plain and
+                                     batched); the LDS small-graph kernels do not count against it,
+                                     and a context serving a gesmc_server must keep it 0.  The only
+                                     option that can change a call's outcome                        */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgesmc.so")
 
 OK = 0
 E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_AGAIN, E_CANCELED, E_INTERNAL = -1, -2, -3, -4, -5, -6, -7, -9
+E_ROUNDS = -8
 OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST, OPT_PROFILE_ONLY = (
     1, 2, 3, 4, 5, 6, 7)
 OPT_LEVEL1_BITS = 8
@@ -24,6 +25,7 @@ OPT_FUSE_EMIT = 9
 OPT_GRAPH = 10
 OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
+OPT_ROUND_LIMIT = 13
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 
@@ -86,7 +88,8 @@ class ServerInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_host", "gesmc_run_batch",
+EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_host",
+           "gesmc_run_batch",
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",

@@ -224,6 +224,7 @@ enum : uint32_t {
     ERR_RANGE = 2u,      // vertex id >= n (or 0xFFFFFFFF)
     ERR_DUP = 4u,        // input contains a duplicate edge
     ERR_INTERNAL = 8u,   // an internal consistency check failed
+    ERR_ROUNDS = 16u,    // a superstep needed more decision rounds than the caller's limit
 };
 
 // Per-superstep statistics kept on the device.

@@ -17,6 +17,7 @@
 
 using namespace gesmc;
 
+
 namespace {
 
 thread_local char g_last_error[512] = "";
@@ -27,6 +28,7 @@ void set_error(const char *fmt, ...) {
     vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
     va_end(ap);
 }
+
 
 enum KernelId {
     KID_LOAD,
@@ -105,6 +107,7 @@ struct gesmc_ctx {
     uint32_t bucket_avg = 3 * kLdsCap / 4;  // partition means fall in (avg / 2, avg]
     uint32_t sort_cap = kLdsCap;
     int fast_rounds = 2;
+    uint32_t round_limit = 0;  // decision rounds per superstep before GESMC_E_ROUNDS (0: none)
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     uint32_t level1_cap = 0;  // first-level digit bits (0: even split)
     bool fuse_emit = true;    // tuples computed in the first partition pass (else stored flat)
@@ -478,6 +481,19 @@ gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
     return GESMC_OK;
 }
 
+// Words of the radix bookkeeping of one two-level distribution with plan p:
+// per-tile digit counts of both levels and the level-1 chunk sums.
+struct RadixWords {
+    uint64_t counts1, partial, counts2;
+};
+
+RadixWords radix_words(const Plan &p) {
+    const uint64_t nd1 = 1ull << p.b1, nd2 = 1ull << p.b2;
+    const uint64_t nchunks = ceil_div(p.ntiles1, scan_chunk(p.ntiles1));
+    return RadixWords{(uint64_t)p.ntiles1 * nd1, nchunks * nd1,
+                      p.b2 > 0 ? ((uint64_t)p.ntiles1 + p.ncoarse) * nd2 : 0};
+}
+
 // 1: with fused tuple passes, the emit runs inside the first tuple count pass
 #ifndef GESMC_FUSE_EMIT_COUNTS
 #define GESMC_FUSE_EMIT_COUNTS 1
@@ -516,8 +532,9 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const uint32_t chunk = scan_chunk(p.ntiles1);
     const uint32_t nchunks = ceil_div(p.ntiles1, chunk);
     const uint32_t scan_threads = std::max<uint32_t>(64, std::min<uint32_t>(kBlock, nd1));
-    GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, (uint64_t)p.ntiles1 * nd1));
-    GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, (uint64_t)nchunks * nd1));
+    const RadixWords rw = radix_words(p);
+    GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, rw.counts1));
+    GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, rw.partial));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;  // level 1: one segment [0, n), passed by value
     bool fused_emit = false;
     if constexpr (kSrc1 == kSrcEmit || kSrc1 == kSrcEmitPacked) {
@@ -559,7 +576,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     }
     const uint32_t nd2 = 1u << p.b2;
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
-    GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, (uint64_t)tiles2 * nd2));
+    GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, rw.counts2));
     // packed words lost the first level's bits: the second level's are on top
     const int shift2 = kSrc2 == kSrcPacked ? 64 - (int)p.b2 : 64 - (int)p.bbits;
     GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile, false>,
@@ -790,7 +807,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
                      c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
-                     c->ctr_step, c->err));
+                     c->ctr_step, c->err, c->round_limit));
     if (bs && bs->acc)
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_graph_stats, dim3(ceil_div(p.ell, kStatsChunk)), dim3(kBlock), 0,
                          (const uint8_t *)c->st, bs->gr, bs->ngraphs, p.ell, bs->acc));
@@ -861,6 +878,10 @@ gesmc_status map_err(uint32_t e) {
     if (e & ERR_RANGE) {
         set_error("vertex id out of range");
         return GESMC_E_RANGE;
+    }
+    if (e & ERR_ROUNDS) {
+        set_error("a superstep needed more decision rounds than GESMC_OPT_ROUND_LIMIT allows");
+        return GESMC_E_ROUNDS;
     }
     if (e) {
         set_error("internal consistency check failed (error bits 0x%x)", e);
@@ -1812,6 +1833,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_ROUND_LIMIT:
+            if (v < 0 || v > 0xFFFFFFFFll) break;
+            c->round_limit = (uint32_t)v;
             return GESMC_OK;
         case GESMC_OPT_SMALL_GRAPHS:
             if (v < 0 || v > 1) break;

@@ -618,13 +618,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
                                                                uint32_t *list_a, uint32_t *count_a, uint32_t *list_b,
                                                                uint32_t *count_b, const uint4 *__restrict__ bslot,
                                                                uint32_t nbslot, StepCounters *ctr,
-                                                               uint32_t *__restrict__ err) {
+                                                               uint32_t *__restrict__ err, uint32_t round_limit) {
     __shared__ BlockCounts bc;
     __shared__ uint32_t s_n;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) {
         bc = BlockCounts{0, 0, 0, 0};
         s_n = min(*count_a, ell);
+        // a caller's round budget (0: none), counted over the superstep's rounds so
+        // far (the multi-workgroup rounds before this kernel included)
+        const unsigned long long so_far = round_limit ? atomicAdd(&ctr->rounds, 0ull) : 0ull;
+        if (round_limit && (so_far > round_limit || (so_far == round_limit && s_n > 0))) {
+            atomicOr(err, ERR_ROUNDS);
+            s_n = 0;
+        }
     }
     __syncthreads();
     {  // fold the per-block counts of the emit and first-round kernels (eight loads in flight)
@@ -677,7 +684,11 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
             const uint32_t nn = min(*cnxt, ell);
             if (nn >= n) atomicOr(err, ERR_INTERNAL);  // the smallest undecided switch always decides
             s_n = nn >= n ? 0 : nn;
-            atomicAdd(&ctr->rounds, 1ull);
+            const unsigned long long done = atomicAdd(&ctr->rounds, 1ull) + 1;
+            if (round_limit && s_n > 0 && done >= round_limit) {
+                atomicOr(err, ERR_ROUNDS);
+                s_n = 0;
+            }
         }
         __syncthreads();
         n = s_n;

@@ -80,6 +80,7 @@ struct gesmc_server {
     std::unordered_map<uint64_t, ServeReq *> reqs;
     std::vector<ServeReq *> resident;  // worker only: rank order of the layout in buffer 0
     bool stop = false;
+    uint32_t waiters = 0;  // threads blocked in gesmc_wait (under mu); destroy waits for them to leave
     std::thread worker;
     std::chrono::steady_clock::time_point t0;
     uint64_t next_ticket = 1;
@@ -658,15 +659,19 @@ void gesmc_server_destroy(gesmc_server *S) {
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
     {
-        std::lock_guard<std::mutex> lk(S->mu);
-        for (auto &kv : S->reqs) {
+        std::unique_lock<std::mutex> lk(S->mu);
+        for (auto &kv : S->reqs)
             if (!kv.second->finished) serve_finish_locked(S, kv.second, GESMC_E_CANCELED);
+        S->cv_done.notify_all();
+        // threads blocked in gesmc_wait take their (cancelled) results and
+        // leave before any request or the server itself is freed
+        S->cv_done.wait(lk, [&] { return S->waiters == 0; });
+        for (auto &kv : S->reqs) {
             free(kv.second->result);
             delete kv.second;
         }
         S->reqs.clear();
     }
-    S->cv_done.notify_all();
     if (S->s) {
         (void)hipStreamSynchronize(S->s);
         (void)hipStreamDestroy(S->s);
@@ -765,12 +770,12 @@ gesmc_status gesmc_wait(gesmc_server *S, uint64_t ticket, gesmc_result *out) {
         return GESMC_E_INVAL;
     }
     ServeReq *R = it->second;
-    S->cv_done.wait(lk, [&] { return R->finished || S->stop; });
-    if (!R->finished) {
-        set_error("server stopped");
-        return GESMC_E_CANCELED;
-    }
-    return serve_take_locked(S, S->reqs.find(ticket), out);
+    ++S->waiters;
+    S->cv_done.wait(lk, [&] { return R->finished; });  // destroy finishes every request before it frees them
+    --S->waiters;
+    const gesmc_status st = serve_take_locked(S, S->reqs.find(ticket), out);
+    if (S->stop) S->cv_done.notify_all();  // a destroy in progress waits for the last waiter
+    return st;
 }
 
 gesmc_status gesmc_cancel(gesmc_server *S, uint64_t ticket) {

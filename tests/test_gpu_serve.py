@@ -243,3 +243,97 @@ def test_serve_stream_with_cancels_bad_inputs_and_bursts():
     finally:
         srv.close()
         c.close()
+
+
+def test_serve_recipe_stream_exact():
+    """Requests drawn as the benchmark's served stream draws them: power-law
+    graphs with n log-uniform in [1e3, 1e6] (gamma in [2.1, 3.0], d_min 2,
+    d_max floor(sqrt(n))), r uniform in 10..50, own seeds, Poisson arrivals
+    at 300 requests/s.  Every result is checked exactly against the oracle
+    (run on a thread pool), and a sample against gesmc_run alone."""
+    import os
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    gesmc = _gesmc()
+    pool = graphgen.batch_graphs(32, 5, 1e3, 1e6)
+    rng = np.random.default_rng(1300)
+    nreq = 40
+    picks = rng.integers(0, len(pool), nreq)
+    rs = rng.integers(10, 51, nreq)
+    seeds = rng.integers(0, 2**63, nreq)
+    gaps = rng.exponential(1.0 / 300.0, nreq)
+    print("served recipe: %d requests, m up to %d" % (nreq, max(len(pool[p][0]) for p in picks)), flush=True)
+    c = gesmc.Context(0)
+    srv = gesmc.Server(c)
+    tickets = [None] * nreq
+    try:
+        def producer():
+            t_next = time.perf_counter()
+            for i in range(nreq):
+                t_next += gaps[i]
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                E, n = pool[picks[i]]
+                tickets[i] = srv.submit(E, n, int(seeds[i]), int(rs[i]))
+
+        th = threading.Thread(target=producer)
+        th.start()
+        oracle._load()
+
+        def one(i):
+            E, n = pool[picks[i]]
+            return oracle.run(E, n, int(seeds[i]), 0, int(rs[i]), 0)
+
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            exp = list(ex.map(one, range(nreq)))
+        th.join()
+        results = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+        c.close()
+    ref = gesmc.Context(0)
+    try:
+        for i, (res, (rc, e, counts, _)) in enumerate(zip(results, exp)):
+            assert rc == 0 and res["status"] == gesmc.OK, i
+            assert np.array_equal(res["edges"], e), "request %d (m=%d, r=%d)" % (i, len(e), rs[i])
+            for k in ("attempts", "legal", "rej_loop", "rej_exists", "rej_pl"):
+                assert res["stats"][k] == sum(cn[k] for cn in counts), (i, k)
+        for i in range(0, nreq, 8):
+            E, n = pool[picks[i]]
+            q = dict(E=E, n=n, seed=int(seeds[i]), t0=0, r=int(rs[i]), pl=0)
+            assert np.array_equal(results[i]["edges"], alone(ref, q)), i
+    finally:
+        ref.close()
+
+
+def test_serve_destroy_while_a_thread_waits():
+    """gesmc_server_destroy with threads blocked in gesmc_wait: they return
+    (their requests cancelled, or finished if they got that far) before the
+    server is freed, and destroy returns."""
+    import threading
+    gesmc = _gesmc()
+    E = graphgen.powerlaw_graph(400000, 2.3, 2, 632, 9)
+    c = gesmc.Context(0)
+    srv = gesmc.Server(c)
+    got = {}
+    try:
+        tickets = [srv.submit(E, 400000, s, 2000) for s in range(4)]  # about a second of work
+
+        def waiter(t):
+            got[t] = srv.wait(t)
+
+        ths = [threading.Thread(target=waiter, args=(t,)) for t in tickets]
+        for th in ths:
+            th.start()
+        time.sleep(0.2)  # the waiters are blocked inside gesmc_wait by now
+        srv.close()  # destroy while they block
+        for th in ths:
+            th.join(timeout=60)
+            assert not th.is_alive()
+    finally:
+        srv.close()
+        c.close()
+    assert sorted(got) == sorted(tickets)
+    for t, res in got.items():
+        assert res["status"] in (gesmc.OK, gesmc.E_CANCELED), res["status"]
