@@ -473,6 +473,47 @@ def bench_plain(gesmc, torch, args, workload: str, steps: int, warmup: int, host
     return rec, E, n, r
 
 
+def bench_es(gesmc, torch, args):
+    """ParES (Alg. 2): the ES-MC chain on the power-law n=2^20 graph, r = m
+    switches per call (input resident in HBM), beside the ES-MC oracle on a
+    bounded sample of the same chain."""
+    import graphgen
+    E, n = graphgen.workload_powerlaw_1m()
+    m = len(E)
+    r = m
+    ctx = gesmc.Context(0)
+    d_in = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
+    d_out = torch.empty_like(d_in)
+    ctx.run_es(d_in, n, args.seed, 0, r, out=d_out)  # warm-up (sizes the buffers)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(args.es_steps):
+        t = time.perf_counter()
+        _, st = ctx.run_es(d_in, n, args.seed, 0, r, out=d_out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    ctx.close()
+    wall = sum(times)
+    value = r * len(times) / wall
+    rec = {"value": round(value, 1), "unit": "attempts/s", "workload": "pld_n2^20_g2.5", "m": m,
+           "switches_per_step": r, "steps": len(times), "ms_per_step": round(1e3 * wall / len(times), 3),
+           "supersteps": st["supersteps"], "mean_superstep": round(r / max(st["supersteps"], 1), 1),
+           "rounds_max": st["rounds_max"], "legal_fraction": round(st["legal"] / max(st["attempts"], 1), 5),
+           "epochs": st["epochs"]}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle._load()
+        sample = min(r, 4000000)
+        t = time.perf_counter()
+        oracle.es_run(E, n, args.seed, 0, sample)
+        dt = time.perf_counter() - t
+        rec["cpu_baseline"] = {"value": round(sample / dt, 1), "unit": "attempts/s", "cores": 1, "kind": "oracle",
+                               "sample": "ES-MC oracle, first %d of the %d switches incl. validation and set build "
+                                         "(%.1f s)" % (sample, r, dt)}
+    print("ParES: %s" % rec, file=sys.stderr)
+    return rec
+
+
 def gather_calibration(mib: int, count: int):
     """Isolated random 8-byte reads: index_select of `count` random int64
     words from a `mib` MiB buffer, three times.  Under rocprofv3's read
@@ -517,6 +558,8 @@ def main():
                     help="seconds of arrivals per rate at low rates (at least 40 requests)")
     ap.add_argument("--serve-pool", type=int, default=128)
     ap.add_argument("--serve-budget", type=int, default=32 << 30, help="HBM budget of the server, bytes")
+    ap.add_argument("--no-es", action="store_true", help="skip ParES (the ES-MC chain)")
+    ap.add_argument("--es-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
     ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
@@ -565,6 +608,7 @@ def main():
         print("oracle: %s" % cpu, file=sys.stderr)
     del E
 
+    es = None if args.no_es else bench_es(gesmc, torch, args)
     batched = None if args.no_batched else bench_batched(gesmc, torch, args, head["value"])
     served = None if args.no_served else bench_served(gesmc, torch, args)
 
@@ -596,6 +640,7 @@ def main():
         "cpu_baseline": cpu,
     }
     out.update(extra)
+    out["es_pares"] = es
     out["batched"] = batched
     out["served"] = served
     print(json.dumps(out))

@@ -225,6 +225,47 @@ gesmc_status gesmc_cancel(gesmc_server *srv, uint64_t ticket);
 void gesmc_result_free(gesmc_result *res);
 gesmc_status gesmc_server_info_get(gesmc_server *srv, gesmc_server_info *out);
 
+/*
+ * ParES (Alg. 2, Sec. 4): the Edge Switching Markov Chain of Def. 2.1, run
+ * exactly in supersteps without source dependencies.  r edge switches with
+ * switch counters k0 .. k0+r-1 are applied in sequence to the m edges at d_in
+ * (device memory, uint64 keys as for gesmc_run); the result, in position
+ * order, goes to d_out (device, m words, may equal d_in).  Switch k draws,
+ * with (x0, x1, x2, x3) = Philox4x32-10 at counter (k_lo, k_hi, 0, 2) and key
+ * (seed_lo, seed_hi):
+ *   i = floor(((x0 << 32) | x1) * m / 2^64),
+ *   j = j' + [j' >= i] with j' = floor(((x2 << 32) | x3) * (m - 1) / 2^64),
+ *   g = x1 & 1,
+ * so i != j (as Alg. 2 samples them) and the triple is uniform up to a bias
+ * below m / 2^64; the switch is rejected on a loop or a present target, else
+ * E[i] <- canon(e3), E[j] <- canon(e4).  run_es(r1) then run_es(r2, k0 + r1)
+ * equals run_es(r1 + r2).  d_outcome (device, nullable, r bytes): the outcome
+ * code of switch k0 + q at d_outcome[q] (1 accepted, 2 loop, 3 target
+ * present).  stats (host, nullable).  m < 2 copies the canonicalised input
+ * (no two distinct indices exist).  Errors as for gesmc_run, d_out untouched.
+ * Runs on one workgroup of the device per call: ES-MC has supersteps of
+ * about sqrt(m) switches (Sec. 3), a latency-bound chain.
+ */
+typedef struct gesmc_es_stats {
+    uint64_t attempts, legal, rej_loop, rej_exists;
+    uint64_t supersteps;  /* ParES supersteps: runs of switches without a shared edge index, at
+                             most 1024 switches each                                          */
+    uint64_t rounds_sum;  /* decision rounds over all supersteps                              */
+    uint32_t rounds_max;  /* most rounds in one superstep                                     */
+    uint32_t epochs;      /* launches (the edge set is rebuilt between them)                  */
+    double ms_device;
+} gesmc_es_stats;
+
+gesmc_status gesmc_run_es(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,
+                          uint64_t seed, uint64_t k0, uint64_t r, uint32_t flags, uint8_t *d_outcome,
+                          gesmc_es_stats *stats);
+
+/* The draws (i, j, g) of ES-MC switches k0 .. k0+count-1 on m edges (2 <= m
+ * < 2^30), defined as for gesmc_run_es: d_i, d_j (device, count uint64 each),
+ * d_g (device, count bytes).  Parity hook for the random choices of ParES. */
+gesmc_status gesmc_es_draws(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint64_t k0, uint64_t count,
+                            uint64_t *d_i, uint64_t *d_j, uint8_t *d_g);
+
 /* Result of an autotuning run: the options chosen and the measured times. */
 typedef struct gesmc_tuning {
     uint32_t bucket_avg;  /* GESMC_OPT_BUCKET_AVG chosen          */

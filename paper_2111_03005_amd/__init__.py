@@ -5,7 +5,9 @@ resolution and the rounds of decisions of each global switch -- runs in the HIP
 kernels of ``libgesmc.so`` (C ABI in ``include/gesmc.h``); this package is its
 thin ctypes binding.  PyTorch supplies device memory and streams only.
 Forms: ``Context.run`` (one graph), ``Context.run_batch`` (many graphs in one
-call) and ``Server`` (a request loop with continuous batching).
+call), ``Server`` (a request loop with continuous batching) and
+``Context.run_es`` (ParES: the ES-MC chain in supersteps without source
+dependencies).
 """
 from . import _binding
 from ._binding import Context, GesmcError, Server, default_context, load_library, run

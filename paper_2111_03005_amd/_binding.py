@@ -62,6 +62,15 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class EsStats(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("legal", ctypes.c_uint64), ("rej_loop", ctypes.c_uint64),
+                ("rej_exists", ctypes.c_uint64), ("supersteps", ctypes.c_uint64), ("rounds_sum", ctypes.c_uint64),
+                ("rounds_max", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("ms_device", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: (float(getattr(self, f)) if f == "ms_device" else int(getattr(self, f))) for f, _ in self._fields_}
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_graphs", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32)]
@@ -93,7 +102,8 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
-           "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch"]
+           "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
+           "gesmc_run_es", "gesmc_es_draws"]
 
 _lib = None
 _lock = threading.Lock()
@@ -163,6 +173,10 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_autotune_batch.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
                                              ctypes.POINTER(u64), u32, ctypes.POINTER(Tuning)]
         lib.gesmc_autotune_batch.restype = i32
+        lib.gesmc_run_es.argtypes = [vp, vp, vp, vp, u64, u32, u64, u64, u64, u32, vp, ctypes.POINTER(EsStats)]
+        lib.gesmc_run_es.restype = i32
+        lib.gesmc_es_draws.argtypes = [vp, vp, u64, u64, u64, u64, vp, vp, vp]
+        lib.gesmc_es_draws.restype = i32
         _lib = lib
         return lib
 
@@ -294,6 +308,34 @@ class Context:
                                              _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), t, pl,
                                              ctypes.c_void_p(oc.data_ptr()), ctypes.byref(ss)))
         return out, oc[: m // 2], ss.as_dict()
+
+    # ---- ParES: the ES-MC chain (Alg. 2) --------------------------------
+    def run_es(self, edges: torch.Tensor, n: int, seed: int, k0: int = 0, r: int = 1, out: torch.Tensor | None = None,
+               stream=None, outcomes: bool = False):
+        """r ES-MC switches (counters k0 .. k0+r-1) on `edges` (device uint64/int64
+        keys).  Returns (out, stats[, per-switch outcome codes (uint8 device tensor)])."""
+        m = edges.numel()
+        if out is None:
+            out = torch.empty_like(edges)
+        oc = torch.empty(max(r, 1), dtype=torch.uint8, device=edges.device) if outcomes else None
+        st = EsStats()
+        _check(_lib.gesmc_run_es(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges"),
+                                 _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), k0, r, 0,
+                                 ctypes.c_void_p(oc.data_ptr()) if outcomes else None, ctypes.byref(st)))
+        if outcomes:
+            return out, st.as_dict(), oc[:r]
+        return out, st.as_dict()
+
+    def es_draws(self, m: int, seed: int, k0: int, count: int, stream=None, device=None):
+        """The (i, j, g) draws of ES-MC switches k0 .. k0+count-1 on m edges (device tensors)."""
+        dev = device or torch.device("cuda", self.device)
+        di = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+        dj = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+        dg = torch.empty(max(count, 1), dtype=torch.uint8, device=dev)
+        _check(_lib.gesmc_es_draws(self._h, _stream_ptr(stream), m, seed & (2**64 - 1), k0, count,
+                                   ctypes.c_void_p(di.data_ptr()), ctypes.c_void_p(dj.data_ptr()),
+                                   ctypes.c_void_p(dg.data_ptr())))
+        return di[:count], dj[:count], dg[:count]
 
     def perm_keys(self, m: int, seed: int, t: int, stream=None, device=None):
         out = torch.empty(max(m, 1), dtype=torch.int64, device=device or torch.device("cuda", self.device))

@@ -14,6 +14,7 @@
 #include "switch_kernels.h"
 #include "resolve_kernels.h"
 #include "batch_kernels.h"
+#include "es_kernels.h"
 
 using namespace gesmc;
 
@@ -59,6 +60,8 @@ enum KernelId {
     KID_FINISH_CHAIN,
     KID_SMALL,
     KID_SMALL_MID,
+    KID_ES_BUILD,
+    KID_ES_CHAIN,
     KID_COUNT
 };
 
@@ -67,7 +70,8 @@ const char *kKernelNames[KID_COUNT] = {
     "k_scatter2",     "k_sort_buckets", "k_build",      "k_decide_first",  "k_round_reset", "k_round_claim",
     "k_round_decide", "k_finish",       "k_unpermute",  "k_validate",      "k_misc",
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
-    "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096"};
+    "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
+    "k_es_build",     "k_es_chain"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -184,6 +188,11 @@ struct gesmc_ctx {
     uint64_t prof_launch[KID_COUNT] = {0};
     uint64_t prof_items[KID_COUNT] = {0};
     hipEvent_t call_a = nullptr, call_b = nullptr;
+    // ParES (gesmc_run_es): edge list, slot of each edge, edge set, counters
+    unsigned long long *es_E = nullptr, *es_H = nullptr;
+    uint32_t *es_slot = nullptr;
+    uint64_t es_cap_m = 0, es_cap_T = 0;
+    EsCounters *es_ctr = nullptr, *h_es_ctr = nullptr;
     // side streams of the batch's LDS small-graph kernels (default priority),
     // forked from and joined back into the call's stream with these events
     hipStream_t side[2] = {nullptr, nullptr};
@@ -1561,6 +1570,9 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->call_b) (void)hipEventDestroy(c->call_b);
     if (c->h_up) (void)hipHostFree(c->h_up);
     if (c->h_hr) (void)hipHostFree(c->h_hr);
+    for (void *q : {(void *)c->es_E, (void *)c->es_H, (void *)c->es_slot, (void *)c->es_ctr})
+        if (q) (void)hipFree(q);
+    if (c->h_es_ctr) (void)hipHostFree(c->h_es_ctr);
     if (c->hr_dev) (void)hipFree(c->hr_dev);
     for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1], c->up_ev})
         if (e) (void)hipEventDestroy(e);
@@ -1918,3 +1930,4 @@ gesmc_status gesmc_profile_reset(gesmc_ctx *c) {
 }  // extern "C"
 
 #include "server_runtime.h"
+#include "es_runtime.h"
