@@ -114,6 +114,31 @@ gesmc_status gesmc_run_host(gesmc_ctx *ctx, const uint32_t *uv, uint32_t *uv_out
                             uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags, gesmc_stats *stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): gesmc_run
+ * with every per-call device buffer -- state records, dependency tuples,
+ * radix counts, statuses, undecided lists, error words and counters -- taken
+ * from one fixed device array of GESMC_NOALLOC_SCRATCH_MIB MiB that the
+ * library holds on each device from the first gesmc_create on it until the
+ * process ends.  This call allocates nothing (no hipMalloc, hipFree or
+ * pinned host memory); the context's own buffers are left as they are.
+ * Arguments, result, stats and errors as in gesmc_run (no per-superstep
+ * records); m at most GESMC_NOALLOC_MAX_EDGES (else GESMC_E_RANGE and d_out
+ * untouched); needs GESMC_OPT_STRATEGY 0.  Runs of more than 64 supersteps
+ * go in pieces of 64 that resume one another (run(r1) then run(r2, t0 = r1)
+ * equals run(r1 + r2)), so only an internal error or GESMC_E_ROUNDS in a
+ * later piece can leave d_out holding the earlier pieces' result; input
+ * errors leave it untouched.  Every call on a device shares that device's
+ * array and keeps nothing in it between calls: calls that overlap on one
+ * device (from any context or thread) race and must not be made.
+ */
+#define GESMC_NOALLOC_SCRATCH_MIB 256u
+#define GESMC_NOALLOC_MAX_EDGES 2000000ull
+gesmc_status gesmc_run_noalloc(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                               uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags,
+                               gesmc_stats *stats);
+
+/*
  * G independent graphs in one call: the batched form of gesmc_run.  Graph g
  * is d_in[offsets[g] .. offsets[g+1]) (device memory, uint64 keys of local
  * vertex ids < n[g]); it runs r[g] global switches from superstep t0[g] with

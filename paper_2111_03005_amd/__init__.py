@@ -5,7 +5,8 @@ resolution and the rounds of decisions of each global switch -- runs in the HIP
 kernels of ``libgesmc.so`` (C ABI in ``include/gesmc.h``); this package is its
 thin ctypes binding.  PyTorch supplies device memory and streams only.
 Forms: ``Context.run`` (one graph), ``Context.run_batch`` (many graphs in one
-call), ``Server`` (a request loop with continuous batching) and
+call), ``Server`` (a request loop with continuous batching),
+``Context.run_noalloc`` (one graph, nothing allocated inside the call) and
 ``Context.run_es`` (ParES: the ES-MC chain in supersteps without source
 dependencies).
 """

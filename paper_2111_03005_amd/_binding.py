@@ -26,6 +26,7 @@ OPT_GRAPH = 10
 OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
 OPT_ROUND_LIMIT = 13
+NOALLOC_MAX_EDGES = 2000000
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
 
@@ -97,7 +98,7 @@ class ServerInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_host",
+EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "gesmc_run_noalloc", "gesmc_run_host",
            "gesmc_run_batch",
            "gesmc_superstep_outcomes", "gesmc_perm_keys", "gesmc_permutation", "gesmc_set_option",
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
@@ -129,6 +130,8 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_run.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
                                   ctypes.POINTER(StepStats)]
         lib.gesmc_run.restype = i32
+        lib.gesmc_run_noalloc.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats)]
+        lib.gesmc_run_noalloc.restype = i32
         lib.gesmc_run_host.argtypes = [vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats)]
         lib.gesmc_run_host.restype = i32
         lib.gesmc_run_batch.argtypes = [vp, vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(u32),
@@ -240,6 +243,19 @@ class Context:
                               ctypes.byref(st), ss))
         if steps:
             return out, st.as_dict(), [ss[q].as_dict() for q in range(r)]
+        return out, st.as_dict()
+
+    def run_noalloc(self, edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0,
+                    out: torch.Tensor | None = None, stream=None):
+        """gesmc_run_noalloc: as run, with the library's fixed device array as
+        its only scratch (no allocation inside the call).  Returns (out, stats)."""
+        m = edges.numel()
+        if out is None:
+            out = torch.empty_like(edges)
+        st = Stats()
+        _check(_lib.gesmc_run_noalloc(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges"),
+                                      _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), t0, r, pl, 0,
+                                      ctypes.byref(st)))
         return out, st.as_dict()
 
     def run_host(self, uv, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0):

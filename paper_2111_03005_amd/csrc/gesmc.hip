@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gesmc.h"
@@ -18,6 +19,11 @@
 
 using namespace gesmc;
 
+// Device memory of gesmc_run_noalloc: one fixed array per device, held for
+// the whole process.  In host code its name is a host-side stand-in: host
+// code uses only the device address that hipGetSymbolAddress returns for it
+// (noalloc_scratch_ptr), never the name itself.
+static __device__ __align__(256) unsigned char scratch[(size_t)GESMC_NOALLOC_SCRATCH_MIB << 20];
 
 namespace {
 
@@ -30,6 +36,15 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
 }
 
+// Set on the calling thread for the duration of gesmc_run_noalloc: every
+// path that would allocate or free device or pinned memory fails instead.
+thread_local bool t_no_alloc = false;
+
+bool alloc_forbidden() {
+    if (!t_no_alloc) return false;
+    set_error("internal: gesmc_run_noalloc reached an allocation");
+    return true;
+}
 
 enum KernelId {
     KID_LOAD,
@@ -247,6 +262,7 @@ void free_buffers(gesmc_ctx *c) {
 std::atomic<uint64_t> g_alloc_epoch{0};
 
 gesmc_status dev_alloc(void **p, size_t bytes) {
+    if (alloc_forbidden()) return GESMC_E_INTERNAL;
     ++g_alloc_epoch;
     if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
         (void)hipGetLastError();
@@ -267,6 +283,7 @@ gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
     const bool need_tab = c->strategy == 1;
     const bool need_tu = c->strategy == 0;
     if (m <= c->cap_m && (!need_tab || c->tab) && (!need_tu || c->info)) return GESMC_OK;
+    if (alloc_forbidden()) return GESMC_E_INTERNAL;
     free_buffers(c);
     const uint64_t cap = std::max<uint64_t>(m, 1024);
     gesmc_status s = GESMC_OK;
@@ -297,6 +314,7 @@ gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
 
 gesmc_status ensure_counters(gesmc_ctx *c, uint64_t r) {
     const uint64_t want = std::max<uint64_t>(r, 1);
+    if ((want > c->ctr_cap || want > c->h_ctr_cap) && alloc_forbidden()) return GESMC_E_INTERNAL;
     if (want > c->ctr_cap) {
         if (c->ctr) (void)hipFree(c->ctr);
         c->ctr = nullptr;
@@ -482,6 +500,7 @@ uint32_t grid_stride_blocks(const gesmc_ctx *c, uint64_t work) {
 // Grows a word buffer of the radix bookkeeping.
 gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
     if (want <= *cap && *p) return GESMC_OK;
+    if (alloc_forbidden()) return GESMC_E_INTERNAL;
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
@@ -1002,6 +1021,269 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
             (void)hipGetLastError();
         stats->tuple_bytes = c->tuple_bytes;
     }
+    return GESMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// gesmc_run_noalloc: gesmc_run with every per-call device buffer carved from
+// `scratch` instead of the context's own allocations.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)GESMC_NOALLOC_SCRATCH_MIB << 20;
+constexpr int kMaxDevices = 64;
+constexpr uint32_t kNoAllocChunk = 64;  // supersteps per internal run: the context's counter records
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current), looked
+// up once per device with hipGetSymbolAddress: each device holds its own copy
+// of the array.  *out may be null (look-up only).
+gesmc_status noalloc_scratch_ptr(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d devices the no-allocation entry point supports", dev, kMaxDevices);
+        return GESMC_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the no-allocation scratch failed: %s", hipGetErrorString(e));
+            return GESMC_E_DEVICE;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    if (out) *out = g_scratch_dev[dev];
+    return GESMC_OK;
+}
+
+// Every per-call device buffer of a plain sorted-tuples run, with its capacity.
+struct RunBuffers {
+    uint32_t *idx[3];
+    unsigned long long *key[3];
+    uint32_t *tu_tag[3];
+    unsigned long long *tu_key[3];
+    uint2 *info;
+    uint32_t *sw_slot;
+    uint8_t *st;
+    uint32_t *ulist[2];
+    Slot *tab;
+    uint64_t cap_m, cap_tu, tab_slots;
+    uint32_t *counts1, *counts2, *partial;
+    uint64_t cap_counts1, cap_counts2, cap_partial;
+    uint32_t *small;
+    uint4 *bslot;
+    StepCounters *ctr;
+    uint64_t ctr_cap;
+    uint32_t *err, *ucount, *coarse_off, *tile_first, *lvl1_seg, *lvl1_tiles, *fine_off;
+};
+
+RunBuffers take_buffers(const gesmc_ctx *c) {
+    RunBuffers b;
+    for (int q = 0; q < 3; ++q) {
+        b.idx[q] = c->idx[q];
+        b.key[q] = c->key[q];
+        b.tu_tag[q] = c->tu_tag[q];
+        b.tu_key[q] = c->tu_key[q];
+    }
+    b.info = c->info;
+    b.sw_slot = c->sw_slot;
+    b.st = c->st;
+    b.ulist[0] = c->ulist[0];
+    b.ulist[1] = c->ulist[1];
+    b.tab = c->tab;
+    b.cap_m = c->cap_m;
+    b.cap_tu = c->cap_tu;
+    b.tab_slots = c->tab_slots;
+    b.counts1 = c->counts1;
+    b.counts2 = c->counts2;
+    b.partial = c->partial;
+    b.cap_counts1 = c->cap_counts1;
+    b.cap_counts2 = c->cap_counts2;
+    b.cap_partial = c->cap_partial;
+    b.small = c->small;
+    b.bslot = c->bslot;
+    b.ctr = c->ctr;
+    b.ctr_cap = c->ctr_cap;
+    b.err = c->err;
+    b.ucount = c->ucount;
+    b.coarse_off = c->coarse_off;
+    b.tile_first = c->tile_first;
+    b.lvl1_seg = c->lvl1_seg;
+    b.lvl1_tiles = c->lvl1_tiles;
+    b.fine_off = c->fine_off;
+    return b;
+}
+
+void put_buffers(gesmc_ctx *c, const RunBuffers &b) {
+    for (int q = 0; q < 3; ++q) {
+        c->idx[q] = b.idx[q];
+        c->key[q] = b.key[q];
+        c->tu_tag[q] = b.tu_tag[q];
+        c->tu_key[q] = b.tu_key[q];
+    }
+    c->info = b.info;
+    c->sw_slot = b.sw_slot;
+    c->st = b.st;
+    c->ulist[0] = b.ulist[0];
+    c->ulist[1] = b.ulist[1];
+    c->tab = b.tab;
+    c->cap_m = b.cap_m;
+    c->cap_tu = b.cap_tu;
+    c->tab_slots = b.tab_slots;
+    c->counts1 = b.counts1;
+    c->counts2 = b.counts2;
+    c->partial = b.partial;
+    c->cap_counts1 = b.cap_counts1;
+    c->cap_counts2 = b.cap_counts2;
+    c->cap_partial = b.cap_partial;
+    c->small = b.small;
+    c->bslot = b.bslot;
+    c->ctr = b.ctr;
+    c->ctr_cap = b.ctr_cap;
+    c->err = b.err;
+    c->ucount = b.ucount;
+    c->coarse_off = b.coarse_off;
+    c->tile_first = b.tile_first;
+    c->lvl1_seg = b.lvl1_seg;
+    c->lvl1_tiles = b.lvl1_tiles;
+    c->fine_off = b.fine_off;
+}
+
+// Lays out the buffers of a run over m edges from `base` (256-byte aligned
+// pieces) and returns the bytes they take; base = nullptr only measures.
+// Sizes follow ensure_capacity, the radix plans of the permutation (m
+// records) and of the tuple partition (4 floor(m/2) + (m & 1) slots, or m
+// for a validation-only call), and the fixed areas of gesmc_create.
+uint64_t carve_buffers(const gesmc_ctx *c, unsigned char *base, uint64_t m, RunBuffers *out) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> void * {
+        off = (off + 255) & ~255ull;
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    RunBuffers b{};
+    const uint64_t cap = std::max<uint64_t>(m, 1024), ntu = 2 * cap + 8;
+    for (int q = 0; q < 3; ++q) {
+        b.idx[q] = (uint32_t *)take(cap * 4);
+        b.key[q] = (unsigned long long *)take(cap * 8);
+    }
+    for (int q = 0; q < 3; ++q) {
+        b.tu_tag[q] = (uint32_t *)take(ntu * 4);
+        b.tu_key[q] = (unsigned long long *)take(ntu * 8);
+    }
+    b.info = (uint2 *)take((cap + 8) * sizeof(uint2));
+    b.st = (uint8_t *)take(cap / 2 + 64);
+    for (int q = 0; q < 2; ++q) b.ulist[q] = (uint32_t *)take((cap / 2 + 64) * 4);
+    b.sw_slot = nullptr;  // the table strategy only
+    b.tab = nullptr;
+    b.cap_m = cap;
+    b.cap_tu = ntu;
+    b.tab_slots = 0;
+    uint64_t w1 = 1024, wp = 1024, w2 = 1024, nfine = 1;
+    const uint64_t nslots = 4 * (m / 2) + (m & 1);
+    for (uint64_t nrec : {m, nslots}) {
+        if (nrec == 0) continue;
+        const Plan p = make_plan(c, (uint32_t)nrec);
+        const RadixWords rw = radix_words(p);
+        w1 = std::max(w1, rw.counts1);
+        wp = std::max(wp, rw.partial);
+        w2 = std::max(w2, rw.counts2);
+        nfine = std::max<uint64_t>(nfine, p.nfine);
+    }
+    b.counts1 = (uint32_t *)take(w1 * 4);
+    b.partial = (uint32_t *)take(wp * 4);
+    b.counts2 = (uint32_t *)take(w2 * 4);
+    b.cap_counts1 = w1;
+    b.cap_partial = wp;
+    b.cap_counts2 = w2;
+    const uint64_t nc = ((uint64_t)1 << kMaxCoarseBits) + 8;
+    b.small = (uint32_t *)take((16 + 16 + 2 * nc + 8 + nfine + 8) * 4);
+    b.bslot = (uint4 *)take((kEmitSlotsMax + 2 * (uint64_t)grid_stride_blocks(c, ~0ull >> 1)) * sizeof(uint4));
+    b.ctr = (StepCounters *)take(kNoAllocChunk * sizeof(StepCounters));
+    b.ctr_cap = kNoAllocChunk;
+    if (base) {
+        uint32_t *w = b.small;
+        b.err = w;
+        b.ucount = w + 16;
+        b.coarse_off = w + 32;
+        b.tile_first = w + 32 + nc;
+        b.lvl1_seg = w + 32 + 2 * nc;
+        b.lvl1_tiles = w + 32 + 2 * nc + 4;
+        b.fine_off = w + 32 + 2 * nc + 8;
+    }
+    if (out) *out = b;
+    return off;
+}
+
+gesmc_status run_noalloc_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                              uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats) {
+    if (!c) {
+        set_error("null context");
+        return GESMC_E_INVAL;
+    }
+    if (c->strategy != 0) {
+        set_error("gesmc_run_noalloc needs the sorted-tuples strategy (GESMC_OPT_STRATEGY 0)");
+        return GESMC_E_INVAL;
+    }
+    if (m > GESMC_NOALLOC_MAX_EDGES) {
+        set_error("m = %llu exceeds the no-allocation limit of %llu edges (a %u MiB device array)",
+                  (unsigned long long)m, (unsigned long long)GESMC_NOALLOC_MAX_EDGES, (unsigned)GESMC_NOALLOC_SCRATCH_MIB);
+        return GESMC_E_RANGE;
+    }
+    if (m > 0 && (!d_in || !d_out)) {
+        set_error("null edge pointer");
+        return GESMC_E_INVAL;
+    }
+    if ((uint64_t)t0 + r > 0x100000000ull) {
+        set_error("superstep counter t0 + r overflows 32 bits");
+        return GESMC_E_INVAL;
+    }
+    GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
+    void *base = nullptr;
+    GESMC_TRY(noalloc_scratch_ptr(c->device, &base));
+    const uint64_t need = carve_buffers(c, nullptr, m, nullptr);
+    if (need > kScratchBytes) {
+        set_error("internal: %llu scratch bytes needed for m = %llu, %llu held", (unsigned long long)need,
+                  (unsigned long long)m, (unsigned long long)kScratchBytes);
+        return GESMC_E_INTERNAL;
+    }
+    RunBuffers carved;
+    carve_buffers(c, (unsigned char *)base, m, &carved);
+    const RunBuffers saved = take_buffers(c);
+    const bool prof = c->profile;
+    c->profile = false;
+    put_buffers(c, carved);
+    t_no_alloc = true;
+    gesmc_stats tot{};
+    gesmc_status st = GESMC_OK;
+    const uint64_t *src = d_in;
+    uint32_t done = 0;
+    do {  // pieces of at most kNoAllocChunk supersteps, each resuming where the last ended
+        const uint32_t rr = std::min<uint32_t>(r - done, kNoAllocChunk);
+        gesmc_stats part{};
+        st = run_impl(c, stream, src, d_out, m, n, seed, t0 + done, rr, pl, &part, nullptr, nullptr);
+        if (st != GESMC_OK) break;
+        tot.attempts += part.attempts;
+        tot.legal += part.legal;
+        tot.rej_loop += part.rej_loop;
+        tot.rej_exists += part.rej_exists;
+        tot.rej_pl += part.rej_pl;
+        tot.rounds_sum += part.rounds_sum;
+        tot.rounds_max = std::max(tot.rounds_max, part.rounds_max);
+        tot.ms_device += part.ms_device;
+        tot.tuple_bytes = part.tuple_bytes;
+        src = d_out;
+        done += rr;
+    } while (done < r);
+    t_no_alloc = false;
+    put_buffers(c, saved);
+    c->profile = prof;
+    if (st != GESMC_OK) return st;
+    tot.supersteps = r;
+    if (stats) *stats = tot;
     return GESMC_OK;
 }
 
@@ -1532,6 +1814,7 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     (void)hipGetLastError();
     if (hipMemset(c->small, 0, words * 4) != hipSuccess ||
         hipHostMalloc((void **)&c->h_err, 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_ctr, 64 * sizeof(StepCounters), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->call_a) != hipSuccess || hipEventCreate(&c->call_b) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side[1], hipStreamNonBlocking) != hipSuccess ||
@@ -1544,6 +1827,12 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
         set_error("context initialisation failed");
         gesmc_destroy(c);
         return GESMC_E_DEVICE;
+    }
+    c->h_ctr_cap = 64;
+    const gesmc_status sc = noalloc_scratch_ptr(hip_device, nullptr);
+    if (sc != GESMC_OK) {
+        gesmc_destroy(c);
+        return sc;
     }
     *out = c;
     return GESMC_OK;
@@ -1762,6 +2051,16 @@ gesmc_status gesmc_run_host(gesmc_ctx *c, const uint32_t *uv, uint32_t *uv_out, 
         uv_out[2 * i + 1] = (uint32_t)c->h_hr[i];
     }
     return GESMC_OK;
+}
+
+gesmc_status gesmc_run_noalloc(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                               uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t flags,
+                               gesmc_stats *stats) {
+    if (flags != 0) {
+        set_error("flags must be 0");
+        return GESMC_E_INVAL;
+    }
+    return run_noalloc_impl(ctx, stream, d_in, d_out, m, n, seed, t0, r, pl, stats);
 }
 
 gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
