@@ -209,27 +209,66 @@ __global__ __launch_bounds__(kBlock) void k_extract(const uint4 *__restrict__ ch
 }
 
 // ---------------------------------------------------------------------------
-// Small graphs of a batch: one workgroup runs all r global switches of one
-// graph inside LDS -- the permutation (LDS counting sort of (K_i, i) on the
-// top bits of K, then ranks within cells), the switches' ERASE / INSERT
-// tuples grouped by tuple hash, the rounds of decisions of Alg. 1 and the
-// writes -- with the same definitions as the multi-kernel path, so the result
-// is the same chain.  The records stay in LDS across supersteps.  Two sizes:
-// m <= 1024 with 256 threads (39 KB of LDS, several workgroups per CU) and
-// m <= 4096 with 1024 threads (158 KB, one per CU); in both each thread holds
-// 4 permutation items and 2 switches (9 tuples), and there are four sort
-// cells per thread.
+// Small graphs: one workgroup runs all r global switches of one graph inside
+// LDS -- the permutation (LDS counting sort of (K_i, i) on the top bits of K,
+// then ranks within cells), the switches' ERASE / INSERT tuples grouped by
+// tuple hash, the rounds of decisions of Alg. 1 and the writes -- with the
+// same definitions as the multi-kernel path, so the result is the same chain.
+// The records stay in LDS across supersteps.  Size classes:
+//   m <= 1024 on 256 threads (39 KB of LDS, several workgroups per CU),
+//   m <= 4096 on 1024 threads (158 KB, one per CU),
+//   m <= 6144 on 1024 threads with every vertex id below 2^16 ("compact":
+//   edge keys (min << 16) | max and 32-bit sort words, 151 KB).
+// Each thread holds kMax / kThreads permutation items and half as many
+// switches; there are four sort cells per thread.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSmallMax = 1024, kSmallThreads = 256;  // edges, threads
 constexpr uint32_t kMidMax = 4096, kMidThreads = 1024;
+constexpr uint32_t kCmpMax = 6144, kCmpThreads = 1024;     // compact keys: vertex ids < 2^16
+constexpr uint32_t kCmpMaxN = 1u << 16;
 constexpr uint16_t kSmTagStays = 0x7FFF;  // ERASE tag of a surviving edge; erase tags are k < 0x7FFF
 constexpr uint16_t kSmTagInsert = 0x8000; // | (k << 1 | h)
 constexpr uint32_t kSmNone = 0xFFFFu, kSmStays = 0xFFFEu;
 
-template <uint32_t kMax, uint32_t kThreads>
+// Edge keys and sort words of the LDS chain: 64-bit keys and tuple hashes, or
+// (compact) 32-bit keys (min << 16) | max and a 32-bit bijective mix of them.
+template <bool kCompact>
+struct SmallKeys {
+    using Key = unsigned long long;
+    using Word = unsigned long long;
+    static __device__ __forceinline__ Key pack(unsigned long long e) { return e; }
+    static __device__ __forceinline__ unsigned long long unpack(Key e) { return e; }
+    static __device__ __forceinline__ Word word(Key e) { return tuple_hash(e); }
+};
+
+template <>
+struct SmallKeys<true> {
+    using Key = uint32_t;
+    using Word = uint32_t;
+    static __device__ __forceinline__ Key pack(unsigned long long e) {
+        return ((uint32_t)(e >> 32) << 16) | ((uint32_t)e & 0xFFFFu);
+    }
+    static __device__ __forceinline__ unsigned long long unpack(Key e) {
+        return ((unsigned long long)(e >> 16) << 32) | (e & 0xFFFFu);
+    }
+    // xor-shifts and odd multipliers: a bijection on 32-bit words, so equal
+    // words mean equal keys
+    static __device__ __forceinline__ Word word(Key x) {
+        x ^= x >> 16;
+        x *= 0x7FEB352Du;
+        x ^= x >> 15;
+        x *= 0x846CA68Bu;
+        x ^= x >> 16;
+        return x;
+    }
+};
+
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
 struct SmallLds {
-    unsigned long long E[kMax];       // edge keys by local index
-    unsigned long long sK[2 * kMax];  // sorted permutation keys, then sorted tuple hashes
+    using Key = typename SmallKeys<kCompact>::Key;
+    using Word = typename SmallKeys<kCompact>::Word;
+    Key E[kMax];                      // edge keys by local index
+    Word sK[2 * kMax];                // sorted permutation words, then sorted tuple words
     uint32_t info[kMax];              // per target 2k+h: eraser << 16 | predecessor
     uint16_t pi[kMax];                // the permutation of this superstep
     uint16_t sT[2 * kMax];            // sorted local index, then sorted tuple tag
@@ -239,8 +278,9 @@ struct SmallLds {
     uint32_t undecided, flags;
     uint32_t cnt[4];
 };
-static_assert(kMidMax / 2 < kSmTagStays && 2 * kMidMax <= 0x10000, "small-graph tags are 16 bits");
-static_assert(kSmallMax == 4 * kSmallThreads && kMidMax == 4 * kMidThreads, "4 edges per thread");
+static_assert(kCmpMax / 2 < kSmTagStays && 2 * kCmpMax <= 0x10000, "small-graph tags are 16 bits");
+static_assert(kSmallMax % (2 * kSmallThreads) == 0 && kMidMax % (2 * kMidThreads) == 0 &&
+                  kCmpMax % (2 * kCmpThreads) == 0, "whole switches per thread");
 
 template <uint32_t kThreads>
 constexpr int small_cell_bits() {  // 4 kThreads cells
@@ -249,18 +289,20 @@ constexpr int small_cell_bits() {  // 4 kThreads cells
 
 // Groups up to 2 kMax items by the top cell bits of their word: they sit in
 // registers (w[q], g[q] for q < kPer where present[q]); a counting sort puts
-// them in cell order into sK / sT, item q at slot[q] of cell cl[q] (cell c
-// spans [L.cell[c], L.cell[c + 1])).  Within a cell the order is arbitrary;
-// callers read the whole cell.  Returns with a barrier passed.
-template <int kPer, uint32_t kMax, uint32_t kThreads>
-__device__ __forceinline__ void small_group(SmallLds<kMax, kThreads> &L, const unsigned long long *w,
-                                            const uint16_t *g, const bool *present, uint32_t *cl, uint32_t *slot) {
-    constexpr int kShift = 64 - small_cell_bits<kThreads>();
+// them in cell order into sK / sT (cell c spans [L.cell[c], L.cell[c + 1])).
+// Within a cell the order is arbitrary; callers then walk whole cells, four
+// per thread, so no per-item state outlives the grouping.  Returns with a
+// barrier passed.
+template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ void small_group(SmallLds<kMax, kThreads, kCompact> &L,
+                                            const typename SmallKeys<kCompact>::Word *w, const uint16_t *g,
+                                            const bool *present) {
+    constexpr int kShift = 8 * (int)sizeof(typename SmallKeys<kCompact>::Word) - small_cell_bits<kThreads>();
     constexpr uint32_t kCells = 4 * kThreads;
     const uint32_t tid = threadIdx.x;
     for (uint32_t c = tid; c < kCells; c += kThreads) L.cell[c] = 0;
     __syncthreads();
-    uint32_t rank[kPer];
+    uint32_t cl[kPer], rank[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
@@ -274,16 +316,52 @@ __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads> &L, const u
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
-        slot[q] = L.cell[cl[q]] + rank[q];
-        L.sK[slot[q]] = w[q];
-        L.sT[slot[q]] = g[q];
+        const uint32_t slot = L.cell[cl[q]] + rank[q];
+        L.sK[slot] = w[q];
+        L.sT[slot] = g[q];
+    }
+    __syncthreads();
+}
+
+// small_group with items produced on demand: item(q, &w, &g) returns whether
+// item q is present and sets its word and tag.  It is called twice per item
+// (count, then place), so only the cells and ranks stay in registers.
+template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact, typename Item>
+__device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact> &L, Item item) {
+    using Word = typename SmallKeys<kCompact>::Word;
+    constexpr int kShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
+    constexpr uint32_t kCells = 4 * kThreads;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t c = tid; c < kCells; c += kThreads) L.cell[c] = 0;
+    __syncthreads();
+    uint32_t cr[kPer];  // cell << 16 | rank within the cell (cells and ranks are below 2^16)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        Word w;
+        uint16_t g;
+        if (!item(q, &w, &g)) continue;
+        const uint32_t cl = (uint32_t)(w >> kShift);
+        cr[q] = (cl << 16) | atomicAdd(&L.cell[cl], 1u);
+    }
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan<kThreads>(L.cell, kCells, L.tmp);
+    if (tid == 0) L.cell[kCells] = total;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        Word w;
+        uint16_t g;
+        if (!item(q, &w, &g)) continue;
+        const uint32_t slot = L.cell[cr[q] >> 16] + (cr[q] & 0xFFFFu);
+        L.sK[slot] = w;
+        L.sT[slot] = g;
     }
     __syncthreads();
 }
 
 // Alg. 1's rule for target 2k+h from its packed record (see judge_target_chain).
-template <uint32_t kMax, uint32_t kThreads>
-__device__ __forceinline__ int small_judge(const SmallLds<kMax, kThreads> &L, uint32_t rec, uint32_t k) {
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ int small_judge(const SmallLds<kMax, kThreads, kCompact> &L, uint32_t rec, uint32_t k) {
     int v = V_OK;
     const uint32_t e = rec >> 16;
     if (e != kSmNone) {
@@ -307,133 +385,147 @@ __device__ __forceinline__ int small_judge(const SmallLds<kMax, kThreads> &L, ui
     return v;
 }
 
-// One workgroup per listed graph (ranks `small[0 .. count)`, r of rank q in
-// rv[q], m of every listed graph <= kMax); records of graph q are at
-// positions poff + local index of `key`; its outcome counts go to
-// acc[4q .. 4q+3] (legal, loop, exists, P_L).
-template <uint32_t kMax, uint32_t kThreads>
-__global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__restrict__ small,
-                                                          const BatchGraph *__restrict__ gr,
-                                                          const uint32_t *__restrict__ rv,
-                                                          unsigned long long *__restrict__ key,
-                                                          unsigned long long *__restrict__ acc,
-                                                          uint32_t *__restrict__ gerr, uint32_t *__restrict__ err) {
-    __shared__ SmallLds<kMax, kThreads> L;
+// All r supersteps of one graph in LDS.  L.E holds its m edge keys (local
+// ids) on entry and the result on exit; counts go to c[4] (legal, loop,
+// exists, P_L, per thread).  A duplicate edge (two ERASE tuples of one key
+// in the first superstep) sets L.flags.
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompact> &L, uint32_t m, uint32_t r,
+                                                 uint32_t t0, uint32_t pl, uint32_t k0, uint32_t k1, uint32_t *c) {
+    using K = SmallKeys<kCompact>;
+    using Word = typename K::Word;
+    constexpr int kPer = (int)(kMax / kThreads);  // permutation items per thread
+    constexpr int kSw = kPer / 2;                 // switches per thread
+    constexpr int kTu = 4 * kSw + 1;              // tuples per thread (+ the idle record of odd m)
+    // compact permutation words are K's high 32 bits (so their top bits are
+    // K's cell bits); equal words fall back to the full keys
+    constexpr int kCellShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
     const uint32_t tid = threadIdx.x;
-    const uint32_t q = small[blockIdx.x];
-    const BatchGraph b = gr[q];
-    const uint32_t m = b.m, ell = m >> 1, r = rv[q];
-    for (uint32_t li = tid; li < m; li += kThreads) L.E[li] = key[b.poff + li];
-    if (tid < 4) L.cnt[tid] = 0;
-    if (tid == 0) L.flags = 0;
-    uint32_t c_legal = 0, c_loop = 0, c_exists = 0, c_pl = 0;
-    __syncthreads();
+    const uint32_t ell = m >> 1;
     for (uint32_t s = 0; s < r; ++s) {
-        const uint32_t t = b.t0 + s;
+        const uint32_t t = t0 + s;
         // permutation: sort local indices by (K_i, i)
         {
-            unsigned long long w[4];
-            uint16_t g[4];
-            bool pr[4];
+            Word w[kPer];
+            uint16_t g[kPer];
+            bool pr[kPer];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
+            for (int x = 0; x < kPer; ++x) {
                 const uint32_t li = tid + x * kThreads;
                 pr[x] = li < m;
-                w[x] = pr[x] ? perm_key(li, t, b.k0, b.k1) : ~0ull;
+                const unsigned long long kf = pr[x] ? perm_key(li, t, k0, k1) : ~0ull;
+                w[x] = kCompact ? (Word)(kf >> 32) : (Word)kf;
                 g[x] = (uint16_t)li;
             }
-            uint32_t cl[4], slot[4];
-            small_group<4>(L, w, g, pr, cl, slot);
-            // keys (K_i, i) are distinct: an index's place is the number of smaller keys in its cell
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                if (!pr[x]) continue;
-                const uint32_t a = L.cell[cl[x]], e = L.cell[cl[x] + 1];
-                uint32_t rank = 0;
-                for (uint32_t y = a; y < e; ++y) {
-                    const unsigned long long ky = L.sK[y];
-                    rank += ky < w[x] || (ky == w[x] && L.sT[y] < g[x]);
+            small_group<kPer>(L, w, g, pr);
+            // keys (K_i, i) are distinct: an index's place is the number of
+            // smaller keys in its cell (one grouped item per thread at a time;
+            // its word's top bits give its cell)
+            for (uint32_t y = tid; y < m; y += kThreads) {
+                {
+                    const Word wy = L.sK[y];
+                    const uint16_t gy = L.sT[y];
+                    const uint32_t cc = (uint32_t)(wy >> kCellShift);
+                    const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                    uint32_t rank = 0;
+                    for (uint32_t z = a; z < e; ++z) {
+                        const Word wz = L.sK[z];
+                        const uint16_t gz = L.sT[z];
+                        bool less = wz < wy;
+                        if (wz == wy && gz != gy) {
+                            if (kCompact) {  // equal high words (rare): compare the full keys
+                                const unsigned long long fz = perm_key(gz, t, k0, k1), fy = perm_key(gy, t, k0, k1);
+                                less = fz < fy || (fz == fy && gz < gy);
+                            } else {
+                                less = gz < gy;
+                            }
+                        }
+                        rank += less;
+                    }
+                    L.pi[a + rank] = gy;
                 }
-                L.pi[a + rank] = g[x];
             }
             __syncthreads();
         }
-        // switches: local checks and tuples (4 per switch, + the idle record of odd m)
+        // switches: local checks, then their tuples (4 per switch, + the idle
+        // record of odd m) grouped by word; a tuple's word is recomputed from
+        // the switch's records whenever the grouping needs it
         {
-            unsigned long long w[9];
-            uint16_t g[9];
-            bool pr[9];
 #pragma unroll
-            for (int x = 0; x < 9; ++x) pr[x] = false;
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
+            for (int y = 0; y < kSw; ++y) {
                 const uint32_t k = tid + y * kThreads;
                 if (k >= ell) continue;
                 const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
-                const unsigned long long e1 = L.E[i], e2 = L.E[j];
+                const unsigned long long e1 = K::unpack(L.E[i]), e2 = K::unpack(L.E[j]);
                 uint8_t status = ST_UNDECIDED;
-                Targets T{0, 0, false};
-                if (pl_skip(k, t, b.pl, b.k0, b.k1)) {
+                if (pl_skip(k, t, pl, k0, k1)) {
                     status = ST_PL;
                 } else {
-                    T = switch_targets(e1, e2, i < j);
+                    const Targets T = switch_targets(e1, e2, i < j);
                     if (T.loop)
                         status = ST_LOOP;
                     else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
                         status = ST_EXISTS;
                 }
-                L.st[k] = status;
+                L.st[k] = status;  // read back below by this thread only
                 L.info[2 * k] = L.info[2 * k + 1] = 0xFFFFFFFFu;
-                const uint16_t et = status == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
-                w[4 * y + 0] = tuple_hash(e1);
-                g[4 * y + 0] = et;
-                w[4 * y + 1] = tuple_hash(e2);
-                g[4 * y + 1] = et;
-                pr[4 * y + 0] = pr[4 * y + 1] = true;
-                if (status == ST_UNDECIDED) {
-                    w[4 * y + 2] = tuple_hash(T.A);
-                    g[4 * y + 2] = (uint16_t)(kSmTagInsert | (k << 1));
-                    w[4 * y + 3] = tuple_hash(T.B);
-                    g[4 * y + 3] = (uint16_t)(kSmTagInsert | (k << 1) | 1u);
-                    pr[4 * y + 2] = pr[4 * y + 3] = true;
+            }
+            auto tuple = [&](int q, Word *w, uint16_t *g) -> bool {
+                if (q == kTu - 1) {  // the idle record of odd m survives the superstep
+                    if (!((m & 1u) && tid == 0)) return false;
+                    *w = K::word(L.E[L.pi[m - 1]]);
+                    *g = kSmTagStays;
+                    return true;
                 }
-            }
-            if ((m & 1u) && tid == 0) {
-                w[8] = tuple_hash(L.E[L.pi[m - 1]]);
-                g[8] = kSmTagStays;
-                pr[8] = true;
-            }
-            uint32_t cl[9], slot[9];
-            small_group<9>(L, w, g, pr, cl, slot);
-            // all tuples of one key share a cell; each reads its cell for the
+                const uint32_t k = tid + (uint32_t)(q >> 2) * kThreads, h = (uint32_t)q & 3u;
+                if (k >= ell) return false;
+                const uint8_t status = L.st[k];
+                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+                if (h < 2) {
+                    *w = K::word(L.E[h ? j : i]);
+                    *g = status == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
+                    return true;
+                }
+                if (status != ST_UNDECIDED) return false;
+                const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
+                *w = K::word(K::pack(h == 2 ? T.A : T.B));
+                *g = (uint16_t)(kSmTagInsert | (k << 1) | (h - 2));
+                return true;
+            };
+            small_group_fn<kTu>(L, tuple);
+            // all tuples of one key share a cell; each finds in its cell the
             // group's smallest tag and the largest tag before it in (key, tag,
             // slot) order: an ERASE tuple with one before it is a second
             // eraser of its key (a duplicate edge); an INSERT tuple gets its
             // eraser from the smallest tag and its predecessor from the one before
-#pragma unroll
-            for (int x = 0; x < 9; ++x) {
-                if (!pr[x]) continue;
-                const uint32_t a = L.cell[cl[x]], e = L.cell[cl[x] + 1];
-                const uint16_t tx = g[x];
-                uint32_t first = tx, prev = 0;
-                bool before = false;
-                for (uint32_t y = a; y < e; ++y) {
-                    if (y == slot[x] || L.sK[y] != w[x]) continue;
+            const uint32_t ntu = L.cell[4 * kThreads];
+            for (uint32_t y = tid; y < ntu; y += kThreads) {
+                {
+                    const Word wy = L.sK[y];
                     const uint16_t ty = L.sT[y];
-                    first = min(first, (uint32_t)ty);
-                    if (ty < tx || (ty == tx && y < slot[x])) {
-                        prev = before ? max(prev, (uint32_t)ty) : ty;
-                        before = true;
+                    const uint32_t cc = (uint32_t)(wy >> kCellShift);
+                    const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                    uint32_t first = ty, prev = 0;
+                    bool before = false;
+                    for (uint32_t z = a; z < e; ++z) {
+                        if (z == y || L.sK[z] != wy) continue;
+                        const uint16_t tz = L.sT[z];
+                        first = min(first, (uint32_t)tz);
+                        if (tz < ty || (tz == ty && z < y)) {
+                            prev = before ? max(prev, (uint32_t)tz) : tz;
+                            before = true;
+                        }
                     }
+                    if (!(ty & kSmTagInsert)) {
+                        if (before) atomicOr(&L.flags, 1u);
+                        continue;
+                    }
+                    uint32_t eraser = kSmNone;
+                    if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
+                    const uint32_t pred =
+                        (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
+                    L.info[ty & ~kSmTagInsert] = (eraser << 16) | pred;
                 }
-                if (!(tx & kSmTagInsert)) {
-                    if (before) atomicOr(&L.flags, 1u);
-                    continue;
-                }
-                uint32_t eraser = kSmNone;
-                if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
-                const uint32_t pred = (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
-                L.info[tx & ~kSmTagInsert] = (eraser << 16) | pred;
             }
             __syncthreads();
         }
@@ -442,7 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
             if (tid == 0) L.undecided = 0;
             __syncthreads();
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
+            for (int y = 0; y < kSw; ++y) {
                 const uint32_t k = tid + y * kThreads;
                 if (k >= ell || L.st[k] != ST_UNDECIDED) continue;
                 const int v = max(small_judge(L, L.info[2 * k], k), small_judge(L, L.info[2 * k + 1], k));
@@ -458,34 +550,105 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
         }
         // writes and counts
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int y = 0; y < kSw; ++y) {
             const uint32_t k = tid + y * kThreads;
             if (k >= ell) continue;
             const uint8_t sv = L.st[k];
             if (sv == ST_LEGAL) {
                 const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
-                const Targets T = switch_targets(L.E[i], L.E[j], i < j);
-                L.E[i] = T.A;
-                L.E[j] = T.B;
-                ++c_legal;
+                const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
+                L.E[i] = K::pack(T.A);
+                L.E[j] = K::pack(T.B);
+                ++c[0];
             }
-            c_loop += sv == ST_LOOP;
-            c_exists += sv == ST_EXISTS;
-            c_pl += sv == ST_PL;
+            c[1] += sv == ST_LOOP;
+            c[2] += sv == ST_EXISTS;
+            c[3] += sv == ST_PL;
         }
         __syncthreads();
     }
-    for (uint32_t li = tid; li < m; li += kThreads) key[b.poff + li] = L.E[li];
-    if (c_legal) atomicAdd(&L.cnt[0], c_legal);
-    if (c_loop) atomicAdd(&L.cnt[1], c_loop);
-    if (c_exists) atomicAdd(&L.cnt[2], c_exists);
-    if (c_pl) atomicAdd(&L.cnt[3], c_pl);
+}
+
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ void small_flush_counts(SmallLds<kMax, kThreads, kCompact> &L, const uint32_t *c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (c[q]) atomicAdd(&L.cnt[q], c[q]);
     __syncthreads();
+}
+
+// One workgroup per listed graph of a batch (ranks `small[0 .. count)`, r of
+// rank q in rv[q], m of every listed graph <= kMax, and n < 2^16 if
+// kCompact); records of graph q are at positions poff + local index of
+// `key` (vertex ids shifted by the graph's vbase); its outcome counts go to
+// acc[4q .. 4q+3] (legal, loop, exists, P_L).
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__restrict__ small,
+                                                          const BatchGraph *__restrict__ gr,
+                                                          const uint32_t *__restrict__ rv,
+                                                          unsigned long long *__restrict__ key,
+                                                          unsigned long long *__restrict__ acc,
+                                                          uint32_t *__restrict__ gerr, uint32_t *__restrict__ err) {
+    using K = SmallKeys<kCompact>;
+    __shared__ SmallLds<kMax, kThreads, kCompact> L;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t q = small[blockIdx.x];
+    const BatchGraph b = gr[q];
+    const unsigned long long shift = ((unsigned long long)b.vbase << 32) | b.vbase;
+    for (uint32_t li = tid; li < b.m; li += kThreads) L.E[li] = K::pack(key[b.poff + li] - shift);
+    if (tid < 4) L.cnt[tid] = 0;
+    if (tid == 0) L.flags = 0;
+    uint32_t c[4] = {0, 0, 0, 0};
+    __syncthreads();
+    small_chain_body(L, b.m, rv[q], b.t0, b.pl, b.k0, b.k1, c);
+    for (uint32_t li = tid; li < b.m; li += kThreads) key[b.poff + li] = K::unpack(L.E[li]) + shift;
+    small_flush_counts(L, c);
     if (tid < 4) acc[4 * (size_t)q + tid] = L.cnt[tid];  // one workgroup per graph
     if (tid == 0 && L.flags) {
         atomicOr(&gerr[q], ERR_DUP);
         atomicOr(err, ERR_DUP);
     }
+}
+
+// The plain form on one small graph (m <= kMax, n < 2^16 if kCompact), in
+// one launch: loads and checks the input (canonical keys, ids < n, no loop),
+// runs every superstep in LDS, and writes d_out only if no error was found
+// (a duplicate shows in the first superstep).  Counts: acc[0 .. 3].
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__global__ __launch_bounds__(kThreads) void k_small_plain(const unsigned long long *__restrict__ in,
+                                                          unsigned long long *__restrict__ out, uint32_t m,
+                                                          uint32_t n, uint32_t t0, uint32_t r, uint32_t pl,
+                                                          uint32_t k0, uint32_t k1,
+                                                          unsigned long long *__restrict__ acc,
+                                                          uint32_t *__restrict__ err) {
+    using K = SmallKeys<kCompact>;
+    __shared__ SmallLds<kMax, kThreads, kCompact> L;
+    const uint32_t tid = threadIdx.x;
+    if (tid < 4) L.cnt[tid] = 0;
+    if (tid == 0) L.flags = 0;
+    __syncthreads();
+    uint32_t f = 0;
+    for (uint32_t li = tid; li < m; li += kThreads) {
+        const unsigned long long e = in[li];
+        const uint32_t a = (uint32_t)(e >> 32), b = (uint32_t)e;
+        if (a == b) f |= ERR_LOOP;
+        if (a >= n || b >= n || a == 0xFFFFFFFFu || b == 0xFFFFFFFFu) f |= ERR_RANGE;
+        L.E[li] = K::pack(ekey(a, b));
+    }
+    if (f) atomicOr(&L.flags, f << 1);
+    __syncthreads();
+    const uint32_t bad = L.flags;
+    __syncthreads();
+    uint32_t c[4] = {0, 0, 0, 0};
+    if (!bad) small_chain_body(L, m, r, t0, pl, k0, k1, c);  // uniform: every thread read the same flags
+    small_flush_counts(L, c);
+    const uint32_t fl = L.flags;
+    if (fl) {
+        if (tid == 0) atomicOr(err, (fl & 1u ? ERR_DUP : 0u) | (fl >> 1));
+        return;
+    }
+    for (uint32_t li = tid; li < m; li += kThreads) out[li] = K::unpack(L.E[li]);
+    if (tid < 4) acc[tid] = L.cnt[tid];
 }
 
 }  // namespace gesmc

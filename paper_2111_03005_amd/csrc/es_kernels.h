@@ -70,41 +70,91 @@ __device__ __forceinline__ uint32_t es_home(unsigned long long key, uint32_t mas
     return (uint32_t)slot_hash(key) & mask;
 }
 
-// Loads that bypass the vector L1: the edge list and the edge set are
-// rewritten by other threads between supersteps.
+// Accesses of the chain kernel to the edge list, slots and edge set.  One
+// workgroup owns a graph for a whole launch, so workgroup scope suffices:
+// loads and compare-and-swaps are served by the CU's own caches and its
+// XCD's L2 instead of going memory-side, and the workgroup barrier between
+// supersteps orders them.  (Kernel boundaries order them with the build
+// kernels, which use device-scope atomics across workgroups.)
 __device__ __forceinline__ unsigned long long es_load64(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ uint32_t es_load32(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned long long es_cas(unsigned long long *p, unsigned long long expected,
+                                                     unsigned long long desired) {
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;  // the value found (equal to the expected one on success)
 }
 
-// Is `key` in the edge set?  Linear probing ends at an empty slot; the probe
-// count is bounded by the slot count (never reached at load <= 1/2).
-__device__ __forceinline__ bool es_contains(const unsigned long long *H, uint32_t mask, unsigned long long key,
-                                            uint32_t *err) {
-    uint32_t s = es_home(key, mask);
-    for (uint32_t p = 0; p <= mask; ++p) {
-        const unsigned long long cur = es_load64(H + s);
-        if (cur == key) return true;
-        if (cur == kEsEmpty) return false;
-        s = (s + 1) & mask;
+// Probes the edge set for two keys at once (their linear-probing chains
+// interleaved, so the loads of both are in flight together).  For each key:
+// whether it is present, and the first free slot of its chain (a retired
+// slot before the end, else the empty slot that ends the chain) with the
+// value seen there -- where an insert of the key may go.  The chains end at
+// an empty slot (load <= 1/2); their length is bounded by the slot count.
+struct EsProbe {
+    bool found;
+    uint32_t free_slot;
+    unsigned long long free_seen;
+};
+
+__device__ __forceinline__ void es_probe2(const unsigned long long *H, uint32_t mask, unsigned long long ka,
+                                          unsigned long long kb, EsProbe *pa, EsProbe *pb, uint32_t *err) {
+    uint32_t sa = es_home(ka, mask), sb = es_home(kb, mask);
+    bool da = false, db = false;
+    pa->found = pb->found = false;
+    pa->free_slot = pb->free_slot = kEsNone;
+    pa->free_seen = pb->free_seen = kEsEmpty;
+    // one slot of each chain per step: a single workgroup is bound by the
+    // random lines it keeps in flight, so wider steps (measured: four slots)
+    // only add loads
+    for (uint32_t p = 0; p <= mask && !(da && db); ++p) {
+        const unsigned long long ca = da ? 0 : es_load64(H + sa);
+        const unsigned long long cb = db ? 0 : es_load64(H + sb);
+        if (!da) {
+            if (ca == ka) {
+                pa->found = true;
+                da = true;
+            } else if (ca == kEsEmpty || ca == kEsTomb) {
+                if (pa->free_slot == kEsNone) {
+                    pa->free_slot = sa;
+                    pa->free_seen = ca;
+                }
+                da = ca == kEsEmpty;
+            }
+            sa = (sa + 1) & mask;
+        }
+        if (!db) {
+            if (cb == kb) {
+                pb->found = true;
+                db = true;
+            } else if (cb == kEsEmpty || cb == kEsTomb) {
+                if (pb->free_slot == kEsNone) {
+                    pb->free_slot = sb;
+                    pb->free_seen = cb;
+                }
+                db = cb == kEsEmpty;
+            }
+            sb = (sb + 1) & mask;
+        }
     }
-    atomicOr(err, ERR_INTERNAL);
-    return false;
+    if (!(da && db)) atomicOr(err, ERR_INTERNAL);
 }
 
-// Inserts `key` (known to be absent) into the first empty or retired slot of
-// its probe sequence; returns the slot.  *fresh is set if it took an empty one.
-__device__ __forceinline__ uint32_t es_insert(unsigned long long *H, uint32_t mask, unsigned long long key,
-                                              bool *fresh, uint32_t *err) {
-    uint32_t s = es_home(key, mask);
+// Inserts `key` (absent once its superstep's erases are done) at the first
+// empty or retired slot of its chain from slot s on; returns the slot.
+// *fresh is set if it took an empty one.
+__device__ __forceinline__ uint32_t es_insert_from(unsigned long long *H, uint32_t mask, uint32_t s,
+                                                   unsigned long long key, bool *fresh, uint32_t *err) {
     // a slot changes at most twice in a superstep (retired once, taken once),
     // so the lost races are bounded too
     for (uint32_t p = 0, tries = 0; p <= mask && tries < 2 * mask + 64; ++tries) {
         const unsigned long long cur = es_load64(H + s);
         if (cur == kEsEmpty || cur == kEsTomb) {
-            const unsigned long long prev = atomicCAS(H + s, cur, key);
+            const unsigned long long prev = es_cas(H + s, cur, key);
             if (prev == cur) {
                 *fresh = cur == kEsEmpty;
                 return s;
@@ -215,7 +265,7 @@ __global__ __launch_bounds__(kEsThreads) void k_es_chain(unsigned long long *__r
     }
     __syncthreads();
     // nothing to do, or the input failed its checks (the edge set may then be incomplete)
-    if (m < 2 || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    if (m < 2 || *err != 0) return;
     for (;;) {
         const uint64_t s = s_start;  // uniform: written by thread 0 before the barrier that ends a superstep
         if (s >= kend) break;
@@ -257,18 +307,17 @@ __global__ __launch_bounds__(kEsThreads) void k_es_chain(unsigned long long *__r
         unsigned long long e1 = 0, e2 = 0;
         uint32_t so1 = 0, so2 = 0;
         Targets T{0, 0, true};
-        bool ex[2] = {false, false};
+        EsProbe pr[2];
+        pr[0].found = pr[1].found = false;
         if (act) {
             e1 = es_load64(E + d.i);
             e2 = es_load64(E + d.j);
             so1 = es_load32(slot_of + d.i);
             so2 = es_load32(slot_of + d.j);
             T = switch_targets(e1, e2, d.g);
-            if (!T.loop) {
-                ex[0] = es_contains(H, mask, T.A, err);
-                ex[1] = es_contains(H, mask, T.B, err);
-            }
+            if (!T.loop) es_probe2(H, mask, T.A, T.B, &pr[0], &pr[1], err);
         }
+        const bool ex[2] = {pr[0].found, pr[1].found};
         // ---- C: tuples in LDS cells (the boundary table is no longer needed)
         __syncthreads();
         for (uint32_t q = tid; q < kEsCells; q += kEsThreads) sh.t.head[q] = kEsNone;
@@ -365,9 +414,23 @@ __global__ __launch_bounds__(kEsThreads) void k_es_chain(unsigned long long *__r
                 E[d.j] = T.B;
                 H[so1] = kEsTomb;
                 H[so2] = kEsTomb;
-                bool f1 = false, f2 = false;
-                slot_of[d.i] = es_insert(H, mask, T.A, &f1, err);
-                slot_of[d.j] = es_insert(H, mask, T.B, &f2, err);
+                // A target its probe did not find goes to the free slot the probe
+                // saw, if that is still free (both compare-and-swaps in flight
+                // together), else further along its chain.  A target that was
+                // present (its eraser runs earlier in this superstep) is
+                // inserted from its home slot.
+                const bool qa = !pr[0].found && pr[0].free_slot != kEsNone;
+                const bool qb = !pr[1].found && pr[1].free_slot != kEsNone;
+                const unsigned long long ga = qa ? es_cas(H + pr[0].free_slot, pr[0].free_seen, T.A) : 0;
+                const unsigned long long gb = qb ? es_cas(H + pr[1].free_slot, pr[1].free_seen, T.B) : 0;
+                bool f1 = pr[0].free_seen == kEsEmpty, f2 = pr[1].free_seen == kEsEmpty;
+                uint32_t sa = pr[0].free_slot, sb = pr[1].free_slot;
+                if (!qa || ga != pr[0].free_seen)
+                    sa = es_insert_from(H, mask, qa ? sa : es_home(T.A, mask), T.A, &f1, err);
+                if (!qb || gb != pr[1].free_seen)
+                    sb = es_insert_from(H, mask, qb ? sb : es_home(T.B, mask), T.B, &f2, err);
+                slot_of[d.i] = sa;
+                slot_of[d.j] = sb;
                 atomicAdd(&c_legal, 1u);
                 if (f1 || f2) atomicAdd(&c_fresh, (uint32_t)f1 + (uint32_t)f2);
             } else if (sk == ST_LOOP) {
@@ -377,7 +440,9 @@ __global__ __launch_bounds__(kEsThreads) void k_es_chain(unsigned long long *__r
             }
             if (outcome) outcome[s + tid - kbase] = sk == ST_UNDECIDED ? ST_EXISTS : sk;
         }
-        __threadfence();
+        // every access to the graph's arrays in this launch comes from this
+        // workgroup (one CU, one L2), so the barrier orders the writes above
+        // before the next superstep's loads; no device-wide fence is needed
         if (tid == 0) {
             s_start = s + L;
             ++c_steps;

@@ -75,6 +75,7 @@ enum KernelId {
     KID_FINISH_CHAIN,
     KID_SMALL,
     KID_SMALL_MID,
+    KID_SMALL_CMP,
     KID_ES_BUILD,
     KID_ES_CHAIN,
     KID_COUNT
@@ -86,6 +87,7 @@ const char *kKernelNames[KID_COUNT] = {
     "k_round_decide", "k_finish",       "k_unpermute",  "k_validate",      "k_misc",
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
     "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
+    "k_small_chain_compact",
     "k_es_build",     "k_es_chain"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
@@ -166,7 +168,7 @@ struct gesmc_ctx {
     uint32_t *gerr = nullptr, *h_gerr = nullptr;
     uint32_t *pg = nullptr, *bk = nullptr;
     std::vector<BatchGraph> h_gr;
-    std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_rrank;
+    std::vector<uint32_t> h_rank_of, h_order, h_small, h_mid, h_cmp, h_rrank;
     std::vector<uint4> h_chunks;   // position chunks of the ranks' segments (k_fill_pg, serving kernels)
     uint64_t *hr_dev = nullptr, *h_hr = nullptr;  // gesmc_run_host: device in/out (2 x cap), pinned staging
     uint64_t hr_cap = 0, h_hr_cap = 0;              // words
@@ -918,6 +920,50 @@ gesmc_status map_err(uint32_t e) {
     return GESMC_OK;
 }
 
+// The plain form on a graph that fits one workgroup's LDS (k_small_plain):
+// one launch, counts in the first counter record, no rounds recorded.
+gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, uint64_t *d_out, uint32_t m,
+                            uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    unsigned long long *acc = (unsigned long long *)c->ctr;  // legal, loop, exists, P_L
+    const auto *in = (const unsigned long long *)d_in;
+    auto *out = (unsigned long long *)d_out;
+    GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, c->err, (uint64_t)64));
+    if (m <= kSmallMax)
+        GESMC_TRY(launch(c, s, KID_SMALL, m, k_small_plain<kSmallMax, kSmallThreads, false>, dim3(1),
+                         dim3(kSmallThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+    else if (m <= kMidMax)
+        GESMC_TRY(launch(c, s, KID_SMALL_MID, m, k_small_plain<kMidMax, kMidThreads, false>, dim3(1),
+                         dim3(kMidThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+    else
+        GESMC_TRY(launch(c, s, KID_SMALL_CMP, m, k_small_plain<kCmpMax, kCmpThreads, true>, dim3(1),
+                         dim3(kCmpThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+    GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
+    if (c->profile) collect_profile(c);
+    GESMC_TRY(map_err(*c->h_err));
+    if (stats) {
+        const StepCounters &h = c->h_ctr[0];
+        memset(stats, 0, sizeof(*stats));
+        stats->supersteps = r;
+        stats->attempts = (uint64_t)r * (m / 2);
+        stats->legal = h.legal;
+        stats->rej_loop = h.rej_loop;
+        stats->rej_exists = h.rej_exists;
+        stats->rej_pl = h.rej_pl;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->call_a, c->call_b) == hipSuccess)
+            stats->ms_device = ms;
+        else
+            (void)hipGetLastError();
+    }
+    return GESMC_OK;
+}
+
 gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m64, uint32_t n,
                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats,
                       gesmc_step_stats *steps, uint8_t *d_outcome) {
@@ -940,6 +986,11 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     const uint32_t m = (uint32_t)m64;
+    // small graphs (Sec. 7's base case): every superstep in one workgroup's LDS,
+    // one launch, when no per-superstep records or outcome codes are asked for
+    if (c->small_graphs && c->strategy == 0 && m >= 2 && r > 0 && !steps && !d_outcome &&
+        (m <= kMidMax || (m <= kCmpMax && n <= kCmpMaxN)))
+        return run_small_impl(c, s, d_in, d_out, m, n, seed, t0, r, pl, stats);
     GESMC_TRY(ensure_capacity(c, m));
     GESMC_TRY(ensure_counters(c, r));
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -1458,7 +1509,11 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     // not small) by r descending, then the small ones (k_small_chain), then the rest
     auto m_of = [&](uint32_t g) { return offsets[g + 1] - offsets[g]; };
     auto r_eff = [&](uint32_t g) { return m_of(g) >= 2 ? rv[g] : 0u; };
-    auto is_small = [&](uint32_t g) { return c->small_graphs && r_eff(g) > 0 && m_of(g) <= kMidMax; };
+    // LDS classes: m <= 4096, or m <= 6144 with vertex ids below 2^16 (compact keys)
+    auto is_cmp = [&](uint32_t g) { return m_of(g) > kMidMax && m_of(g) <= kCmpMax && nv[g] <= kCmpMaxN; };
+    auto is_small = [&](uint32_t g) {
+        return c->small_graphs && r_eff(g) > 0 && (m_of(g) <= kMidMax || is_cmp(g));
+    };
     auto r_pipe = [&](uint32_t g) { return is_small(g) ? 0u : r_eff(g); };
     auto rank_class = [&](uint32_t g) { return r_pipe(g) > 0 ? 0 : (is_small(g) ? 1 : 2); };
     std::vector<uint32_t> &order = c->h_order;
@@ -1473,6 +1528,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     c->h_rank_of.assign(G, 0);
     c->h_small.clear();
     c->h_mid.clear();
+    c->h_cmp.clear();
     c->h_rrank.assign(G, 0);
     uint64_t poff = 0, vbase = 0, bbase = 0, nmax = 0;
     uint32_t nactive = 0, rmax = 0;
@@ -1482,7 +1538,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         const uint64_t m = m_of(g);
         const bool active = r_pipe(g) > 0;
         c->h_rrank[q] = r_eff(g);
-        if (is_small(g)) (m <= kSmallMax ? c->h_small : c->h_mid).push_back(q);
+        if (is_small(g)) (m <= kSmallMax ? c->h_small : m <= kMidMax ? c->h_mid : c->h_cmp).push_back(q);
         BatchGraph &b = gr[q];
         b.poff = (uint32_t)poff;
         b.mpad = (uint32_t)(m + (active ? (m & 1) : 0));
@@ -1523,13 +1579,17 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     GESMC_TRY(ensure_chunks(c));
     // uploads through the pinned arena: records, offsets, rank lists, chunks
     const uint64_t up_bytes = G * (sizeof(BatchGraph) + 8 + 4 + 4) + 8 +
-                              (c->h_small.size() + c->h_mid.size()) * 4ull + (uint64_t)nchunks * sizeof(uint4);
+                              (c->h_small.size() + c->h_mid.size() + c->h_cmp.size()) * 4ull +
+                              (uint64_t)nchunks * sizeof(uint4);
     GESMC_TRY(up_begin(c, up_bytes, 6));
     GESMC_TRY(up_copy(c, s, c->gr, gr.data(), G * sizeof(BatchGraph)));
     GESMC_TRY(up_copy(c, s, c->in_off, offsets, (G + 1) * 8ull));
-    const uint32_t nsm1 = (uint32_t)c->h_small.size(), nsm2 = (uint32_t)c->h_mid.size();
-    c->h_small.insert(c->h_small.end(), c->h_mid.begin(), c->h_mid.end());  // the m <= 1024 list, then the rest
-    const uint32_t nsmall = nsm1 + nsm2;
+    const uint32_t nsm1 = (uint32_t)c->h_small.size(), nsm2 = (uint32_t)c->h_mid.size(),
+                   nsm3 = (uint32_t)c->h_cmp.size();
+    // the m <= 1024 list, then m <= 4096, then the compact class
+    c->h_small.insert(c->h_small.end(), c->h_mid.begin(), c->h_mid.end());
+    c->h_small.insert(c->h_small.end(), c->h_cmp.begin(), c->h_cmp.end());
+    const uint32_t nsmall = nsm1 + nsm2 + nsm3;
     const bool need_acc = stats != nullptr || nsmall > 0;  // small graphs count per graph
     if (nsmall) {
         GESMC_TRY(up_copy(c, s, c->small_list, c->h_small.data(), nsmall * 4ull));
@@ -1574,25 +1634,30 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         // of the other graphs (their records, counts and error words are
         // disjoint) and is joined back before the unpermute.  A lone class
         // with nothing beside it stays on the call's stream.
-        const bool fork = (nsm1 > 0) + (nsm2 > 0) + (nactive > 0) > 1;
+        const bool fork = (nsm1 > 0) + (nsm2 + nsm3 > 0) + (nactive > 0) > 1;
         if (fork) GESMC_TRY(check_hip(hipEventRecord(c->fork_ev, s), "hipEventRecord"));
         hipStream_t s1 = s, s2 = s;
         if (fork && nsm1) {
             s1 = c->side[0];
             GESMC_TRY(check_hip(hipStreamWaitEvent(s1, c->fork_ev, 0), "hipStreamWaitEvent"));
         }
-        if (fork && nsm2) {
+        if (fork && nsm2 + nsm3) {
             s2 = c->side[1];
             GESMC_TRY(check_hip(hipStreamWaitEvent(s2, c->fork_ev, 0), "hipStreamWaitEvent"));
         }
         if (nsm1)
-            GESMC_TRY(launch(c, s1, KID_SMALL, nsm1, k_small_chain<kSmallMax, kSmallThreads>, dim3(nsm1),
+            GESMC_TRY(launch(c, s1, KID_SMALL, nsm1, k_small_chain<kSmallMax, kSmallThreads, false>, dim3(nsm1),
                              dim3(kSmallThreads), 0, (const uint32_t *)c->small_list, (const BatchGraph *)c->gr,
                              (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
         if (nsm2)
-            GESMC_TRY(launch(c, s2, KID_SMALL_MID, nsm2, k_small_chain<kMidMax, kMidThreads>, dim3(nsm2),
+            GESMC_TRY(launch(c, s2, KID_SMALL_MID, nsm2, k_small_chain<kMidMax, kMidThreads, false>, dim3(nsm2),
                              dim3(kMidThreads), 0, (const uint32_t *)c->small_list + nsm1, (const BatchGraph *)c->gr,
                              (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr, c->err));
+        if (nsm3)  // after the 4096-edge class on the same stream (one workgroup per CU either way)
+            GESMC_TRY(launch(c, s2, KID_SMALL_CMP, nsm3, k_small_chain<kCmpMax, kCmpThreads, true>, dim3(nsm3),
+                             dim3(kCmpThreads), 0, (const uint32_t *)c->small_list + nsm1 + nsm2,
+                             (const BatchGraph *)c->gr, (const uint32_t *)c->rrank, c->key[0], c->gacc, c->gerr,
+                             c->err));
         if (s1 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[0], s1), "hipEventRecord"));
         if (s2 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[1], s2), "hipEventRecord"));
         // superstep s switches the ranks [0, active_s): those with r > s

@@ -282,21 +282,25 @@ def test_batch_graph_capture_and_replay():
 
 
 def small_batch(seed=37):
-    """Graphs around the two LDS-resident size limits (1024 edges on 256
-    threads, 4096 on 1024): G(n,p) graphs cut to exactly 1023, 1024, 1025,
-    4095, 4096 and 4097 edges, dense ones where most targets exist, and small
-    power-law graphs, with long chains (up to 40 global switches) so that
-    many supersteps run inside one workgroup."""
+    """Graphs around the LDS-resident size limits (1024 edges on 256 threads,
+    4096 on 1024, 6144 on 1024 with vertex ids below 2^16): G(n,p) graphs
+    cut to exactly 1023, 1024, 1025, 4095, 4096, 4097, 6143, 6144 and 6145
+    edges, one of 5000 edges whose ids exceed 2^16, dense ones where most
+    targets exist, and small power-law graphs, with long chains (up to 40
+    global switches) so that many supersteps run inside one workgroup."""
     rng = np.random.default_rng(seed)
     graphs = []
     for m in (1023, 1024, 1025):
         E = graphgen.gnp(300, 0.03, seed + m)
         assert len(E) >= m
         graphs.append((np.sort(E[:m]), 300))
-    for m in (4095, 4096, 4097):
-        E = graphgen.gnp(700, 0.02, seed + m)
+    for m in (4095, 4096, 4097, 6143, 6144, 6145):
+        E = graphgen.gnp(900, 0.02, seed + m)
         assert len(E) >= m
-        graphs.append((np.sort(E[:m]), 700))
+        graphs.append((np.sort(E[:m]), 900))
+    # ids above 2^16: the compact class does not apply, the multi-kernel path runs
+    E = graphgen.gnp(900, 0.02, seed + 9)[:5000]
+    graphs.append(((E + np.uint64((70000 << 32) | 70000)).astype(np.uint64), 71000))
     graphs.append((graphgen.gnp(40, 0.9, seed + 1), 40))
     graphs.append((graphgen.gnp(48, 0.85, seed + 2), 48))
     graphs += graphgen.batch_graphs(24, seed, 20, 400)
@@ -309,8 +313,8 @@ def small_batch(seed=37):
 
 @pytest.mark.parametrize("pl", [0, 1 << 31])
 def test_small_graph_path_exact(pl):
-    """GESMC_OPT_SMALL_GRAPHS: graphs of at most 4096 edges run every
-    superstep in one LDS-resident workgroup.  With the option on and off the
+    """GESMC_OPT_SMALL_GRAPHS: graphs of at most 4096 edges (6144 with ids
+    below 2^16) run every superstep in one LDS-resident workgroup.  With the option on and off the
     results and counts are identical and equal the oracle's."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -471,3 +471,67 @@ def test_round_limit_fails_the_call_and_leaves_output_untouched():
         c.set_option(gesmc.OPT_ROUND_LIMIT, 0)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("pl", [0, 1 << 31])
+def test_small_plain_path_exact(pl):
+    """gesmc_run on graphs that fit one workgroup's LDS (at most 4096 edges,
+    6144 with ids below 2^16) runs every superstep in one launch: equal to
+    the oracle and to the multi-kernel supersteps (GESMC_OPT_SMALL_GRAPHS 0)
+    at every size limit, for long chains and with P_L."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    cases = []
+    for m in (2, 3, 1023, 1024, 1025, 4095, 4096, 4097, 6143, 6144, 6145):
+        E = graphgen.gnp(900, 0.02, 100 + m)
+        cases.append((np.sort(E[:m]), 900, "G(900, .02) cut to %d" % m))
+    E, n = graphgen.workload_gnp_small()
+    cases.append((E, n, "gnp_n1024_d10"))
+    cases.append((graphgen.gnp(40, 0.9, 5), 40, "dense"))
+    cases.append((keys([(0, v) for v in range(1, 300)]), 300, "star"))
+    E = graphgen.gnp(900, 0.02, 7)[:5000]  # ids beyond 2^16: the compact class does not apply
+    cases.append(((E + np.uint64((70000 << 32) | 70000)).astype(np.uint64), 71000, "ids above 2^16"))
+    c_on, c_off = gesmc.Context(0), gesmc.Context(0)
+    try:
+        c_off.set_option(gesmc.OPT_SMALL_GRAPHS, 0)
+        for q, (E, n, label) in enumerate(cases):
+            st_on = check_run_plain(c_on, E, n, 11 + q, 5 * q, 30, pl, label)
+            st_off = check_run_plain(c_off, E, n, 11 + q, 5 * q, 30, pl, label + " (multi-kernel)")
+            for k in COUNT_KEYS:
+                assert st_on[k] == st_off[k], (label, k)
+    finally:
+        c_on.close()
+        c_off.close()
+
+
+def check_run_plain(ctx, E, n, seed, t0, r, pl, label):
+    """gesmc_run without per-superstep records (the small-graph path applies)."""
+    print("case %s: m=%d n=%d r=%d pl=%d" % (label, len(E), n, r, pl), flush=True)
+    out, st = ctx.run(to_dev(E), n, seed, t0=t0, r=r, pl=pl)
+    rc, exp, counts, _ = oracle_run(E, n, seed, t0, r, pl)
+    assert rc == 0
+    got = to_host(out)
+    assert np.array_equal(got, exp), "%s: %d positions differ" % (label, int((got != exp).sum()))
+    for k in COUNT_KEYS:
+        assert st[k] == sum(c[k] for c in counts), (label, k, st)
+    return st
+
+
+def test_small_plain_path_invalid_inputs():
+    """The one-launch small path checks its input as the multi-kernel path
+    does (loop, id out of range, duplicate) and leaves d_out untouched."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    c = gesmc.Context(0)
+    try:
+        good = graphgen.gnp(900, 0.02, 3)[:5000]
+        for bad, status in [(np.concatenate([good, good[:1]]), gesmc.E_NOT_SIMPLE),
+                            (np.concatenate([good[:100], keys([(5, 5)])]), gesmc.E_NOT_SIMPLE),
+                            (np.concatenate([good[:3000], keys([(1, 900)])]), gesmc.E_RANGE)]:
+            sentinel = torch.full((len(bad),), 3, dtype=torch.int64, device="cuda")
+            with pytest.raises(gesmc.GesmcError) as ei:
+                c.run(to_dev(bad), 900, 1, r=4, out=sentinel)
+            assert ei.value.status == status
+            assert bool((sentinel == 3).all())
+    finally:
+        c.close()
