@@ -514,6 +514,44 @@ def bench_es(gesmc, torch, args):
     return rec
 
 
+def bench_mixing(gesmc, torch, args):
+    """The mixing diagnostic of Sec. 6.1 on a point of its SynPld grid: a
+    power-law graph with n = 2^13, gamma = 2.2, degrees in [1, n^(1/(gamma-1))],
+    Havel-Hakimi; K supersteps of each chain with the thinned series of
+    k = 1, 2, 4, ..., 64 aggregated on the device; beside the oracle (every
+    state kept) on a bounded sample of the same run."""
+    import graphgen
+    n, gamma = 1 << 13, 2.2
+    E = graphgen.powerlaw_graph(n, gamma, 1, int(n ** (1.0 / (gamma - 1.0))), 7)
+    m = len(E)
+    thin = [1, 2, 4, 8, 16, 32, 64]
+    K = args.mixing_supersteps
+    ctx = gesmc.Context(0)
+    d = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
+    rec = {"workload": "SynPld n=2^13 gamma=2.2 d in [1, n^(1/(gamma-1))], Havel-Hakimi, generator seed 7",
+           "m": m, "supersteps": K, "thinning": thin}
+    for chain, name in ((0, "G-ES-MC"), (1, "ES-MC")):
+        ctx.mixing(d, n, args.seed, 2, [1], chain=chain)  # warm-up
+        t = time.perf_counter()
+        res, ms = ctx.mixing(d, n, args.seed, K, thin, chain=chain)
+        dt = time.perf_counter() - t
+        rec[name] = {"ms": round(1e3 * dt, 1), "attempts_per_s": round(K * (m // 2) / dt, 1),
+                     "fraction_not_independent": {r["k"]: round(r["non_independent"] / max(r["tracked"], 1), 5)
+                                                  for r in res}}
+    ctx.close()
+    if not args.no_cpu_baseline:
+        from oracle import mixing
+        Ks = min(K, 50)
+        t = time.perf_counter()
+        mixing.diagnostic(E, n, args.seed, Ks, thin, chain="global")
+        dt = time.perf_counter() - t
+        rec["cpu_baseline"] = {"value": round(Ks * (m // 2) / dt, 1), "unit": "attempts/s", "cores": 1,
+                               "kind": "oracle", "sample": "G-ES-MC, first %d of the %d supersteps with every state "
+                                                           "kept and the same thinning values (%.1f s)" % (Ks, K, dt)}
+    print("mixing: %s" % rec, file=sys.stderr)
+    return rec
+
+
 def gather_calibration(mib: int, count: int):
     """Isolated random 8-byte reads: index_select of `count` random int64
     words from a `mib` MiB buffer, three times.  Under rocprofv3's read
@@ -559,6 +597,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=128)
     ap.add_argument("--serve-budget", type=int, default=32 << 30, help="HBM budget of the server, bytes")
     ap.add_argument("--no-es", action="store_true", help="skip ParES (the ES-MC chain)")
+    ap.add_argument("--no-mixing", action="store_true", help="skip the mixing diagnostic")
+    ap.add_argument("--mixing-supersteps", type=int, default=400)
     ap.add_argument("--es-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
@@ -609,6 +649,7 @@ def main():
     del E
 
     es = None if args.no_es else bench_es(gesmc, torch, args)
+    mix = None if args.no_mixing else bench_mixing(gesmc, torch, args)
     batched = None if args.no_batched else bench_batched(gesmc, torch, args, head["value"])
     served = None if args.no_served else bench_served(gesmc, torch, args)
 
@@ -641,6 +682,7 @@ def main():
     }
     out.update(extra)
     out["es_pares"] = es
+    out["mixing"] = mix
     out["batched"] = batched
     out["served"] = served
     print(json.dumps(out))

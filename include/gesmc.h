@@ -295,6 +295,40 @@ gesmc_status gesmc_run_es(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, ui
 gesmc_status gesmc_es_draws(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint64_t k0, uint64_t count,
                             uint64_t *d_i, uint64_t *d_j, uint8_t *d_g);
 
+/*
+ * Mixing diagnostic (Sec. 6.1): the autocorrelation analysis of a chain's
+ * edge series, aggregated on the device while the chain runs.  The chain
+ * runs K supersteps from the m edges at d_in (device, keys as for gesmc_run,
+ * left unchanged): chain 0 = G-ES-MC (superstep t is gesmc_run's superstep t
+ * with this seed and pl), chain 1 = ES-MC (superstep t is floor(m/2) edge
+ * switches of gesmc_run_es, counters t*floor(m/2) ..).  For each thinning
+ * value k = thin[q] the k-thinned series samples the states X_0, X_k, ...,
+ * X_{Nk}, N = floor(K / k); every edge present in some sample is tracked
+ * with the counts n_ab of its transitions a -> b between consecutive
+ * samples; G^2 = 2 sum n_ab ln(n_ab N / (n_a. n_.b)) (float64) and the
+ * Bayesian information criterion (the Markov model has one parameter more)
+ * deem it not independent iff G^2 > ln N.  out[q] (host, nthin records)
+ * receives k, N, the edges tracked, those not independent and the counts
+ * summed over tracked edges (exact integers).  ms_chain (host, nullable):
+ * wall time of the chain and its sampling.  Limits: 2 <= n <= 2^14 (dense
+ * pair counters: 12 bytes per vertex pair and thinning value), 1 <= nthin
+ * <= 16, every k >= 1.  Device memory is allocated for the call and freed.
+ */
+typedef struct gesmc_mixing_result {
+    uint32_t k;            /* thinning value                                */
+    uint32_t transitions;  /* N = floor(K / k)                              */
+    uint64_t tracked;      /* edges present in at least one sample          */
+    uint64_t non_independent;
+    uint64_t n00, n01, n10, n11; /* transitions summed over tracked edges   */
+} gesmc_mixing_result;
+
+#define GESMC_CHAIN_GLOBAL 0u
+#define GESMC_CHAIN_ES 1u
+
+gesmc_status gesmc_mixing(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t m, uint32_t n, uint64_t seed,
+                          uint32_t chain, uint32_t pl, uint32_t K, const uint32_t *thin, uint32_t nthin,
+                          gesmc_mixing_result *out, double *ms_chain);
+
 /* Result of an autotuning run: the options chosen and the measured times. */
 typedef struct gesmc_tuning {
     uint32_t bucket_avg;  /* GESMC_OPT_BUCKET_AVG chosen          */

@@ -26,6 +26,7 @@ OPT_GRAPH = 10
 OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
 OPT_ROUND_LIMIT = 13
+CHAIN_GLOBAL, CHAIN_ES = 0, 1
 NOALLOC_MAX_EDGES = 2000000
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
@@ -72,6 +73,15 @@ class EsStats(ctypes.Structure):
         return {f: (float(getattr(self, f)) if f == "ms_device" else int(getattr(self, f))) for f, _ in self._fields_}
 
 
+class MixingResult(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("transitions", ctypes.c_uint32), ("tracked", ctypes.c_uint64),
+                ("non_independent", ctypes.c_uint64), ("n00", ctypes.c_uint64), ("n01", ctypes.c_uint64),
+                ("n10", ctypes.c_uint64), ("n11", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_graphs", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32)]
@@ -104,7 +114,7 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
            "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
-           "gesmc_run_es", "gesmc_es_draws"]
+           "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing"]
 
 _lib = None
 _lock = threading.Lock()
@@ -180,6 +190,9 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_run_es.restype = i32
         lib.gesmc_es_draws.argtypes = [vp, vp, u64, u64, u64, u64, vp, vp, vp]
         lib.gesmc_es_draws.restype = i32
+        lib.gesmc_mixing.argtypes = [vp, vp, vp, u64, u32, u64, u32, u32, u32, ctypes.POINTER(u32), u32,
+                                     ctypes.POINTER(MixingResult), ctypes.POINTER(ctypes.c_double)]
+        lib.gesmc_mixing.restype = i32
         _lib = lib
         return lib
 
@@ -352,6 +365,20 @@ class Context:
                                    ctypes.c_void_p(di.data_ptr()), ctypes.c_void_p(dj.data_ptr()),
                                    ctypes.c_void_p(dg.data_ptr())))
         return di[:count], dj[:count], dg[:count]
+
+    # ---- mixing diagnostic (Sec. 6.1) -------------------------------------
+    def mixing(self, edges: torch.Tensor, n: int, seed: int, K: int, thin, chain: int = 0, pl: int = 0,
+               stream=None):
+        """Autocorrelation diagnostic of K supersteps of G-ES-MC (chain 0) or ES-MC
+        (chain 1) from `edges` (device keys, unchanged).  Returns (list of per-k
+        dicts, wall ms of the chain and its sampling)."""
+        m = edges.numel()
+        th = (ctypes.c_uint32 * len(thin))(*[int(x) for x in thin])
+        res = (MixingResult * len(thin))()
+        ms = ctypes.c_double()
+        _check(_lib.gesmc_mixing(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges") if m else None, m, n,
+                                 seed & (2**64 - 1), chain, pl, K, th, len(thin), res, ctypes.byref(ms)))
+        return [res[q].as_dict() for q in range(len(thin))], ms.value
 
     def perm_keys(self, m: int, seed: int, t: int, stream=None, device=None):
         out = torch.empty(max(m, 1), dtype=torch.int64, device=device or torch.device("cuda", self.device))

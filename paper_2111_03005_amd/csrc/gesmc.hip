@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -16,6 +17,7 @@
 #include "resolve_kernels.h"
 #include "batch_kernels.h"
 #include "es_kernels.h"
+#include "mixing_kernels.h"
 
 using namespace gesmc;
 
@@ -78,6 +80,7 @@ enum KernelId {
     KID_SMALL_CMP,
     KID_ES_BUILD,
     KID_ES_CHAIN,
+    KID_MIX,
     KID_COUNT
 };
 
@@ -88,7 +91,7 @@ const char *kKernelNames[KID_COUNT] = {
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
     "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
     "k_small_chain_compact",
-    "k_es_build",     "k_es_chain"};
+    "k_es_build",     "k_es_chain",     "k_mixing"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -2295,3 +2298,4 @@ gesmc_status gesmc_profile_reset(gesmc_ctx *c) {
 
 #include "server_runtime.h"
 #include "es_runtime.h"
+#include "mixing_runtime.h"
