@@ -82,6 +82,12 @@ def _load():
     lib.oracle_edge_switch.restype = ctypes.c_int
     lib.oracle_es_run.argtypes = [vp, u64, u32, u64, u64, u64, vp, vp, u32]
     lib.oracle_es_run.restype = ctypes.c_int
+    lib.oracle_validate_class.argtypes = [vp, u64, u32, u32]
+    lib.oracle_validate_class.restype = ctypes.c_int
+    lib.oracle_run_class.argtypes = [vp, u64, u32, u64, u32, u32, u32, u32, vp, vp, u32]
+    lib.oracle_run_class.restype = ctypes.c_int
+    lib.oracle_edge_switch_class.argtypes = [vp, u64, u64, u64, ctypes.c_int, u32, u32]
+    lib.oracle_edge_switch_class.restype = ctypes.c_int
     lib.oracle_selftest_edgeset.argtypes = [u64, u64]
     lib.oracle_selftest_edgeset.restype = u64
     _lib = lib
@@ -180,6 +186,34 @@ def es_run(E: np.ndarray, n: int, seed: int, k0: int, r: int, mutate: int = 0, o
     oc = np.zeros(max(r, 1), dtype=np.uint8) if outcomes else None
     rc = _load().oracle_es_run(_p(E), len(E), n, seed & (2**64 - 1), k0, r, ctypes.byref(c), _p(oc), mutate)
     return rc, E, c.as_dict(), (oc[:r] if outcomes else None)
+
+
+CLS_LOOPS, CLS_MULTI, CLS_DIRECTED = 1, 2, 4
+CMUT_DIR_TAILS, CMUT_NO_SAME, CMUT_LOOPS_ALWAYS, CMUT_LOOP_BOTH_G = 1, 2, 4, 8
+
+
+def run_class(E: np.ndarray, n: int, seed: int, t0: int, r: int, pl: int = 0, cls: int = 0, outcomes: bool = False,
+              mutate: int = 0):
+    """Alg. 3 for a graph class (bits CLS_LOOPS, CLS_MULTI, CLS_DIRECTED): r
+    global switches.  Returns (status, E', [per-superstep counts], last outcomes)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    m = len(E)
+    per = (Counts * max(r, 1))()
+    oc = np.zeros(max(m // 2, 1), dtype=np.uint8) if outcomes else None
+    rc = _load().oracle_run_class(_p(E), m, n, seed & (2**64 - 1), t0, r, pl, cls, per, _p(oc), mutate)
+    return rc, E, [per[s].as_dict() for s in range(r)], (oc[: m // 2] if outcomes else None)
+
+
+def validate_class(E: np.ndarray, n: int, cls: int) -> int:
+    E = np.ascontiguousarray(E, dtype=np.uint64)
+    return _load().oracle_validate_class(_p(E), len(E), n, cls)
+
+
+def edge_switch_class(E: np.ndarray, i: int, j: int, g: int, cls: int, mutate: int = 0):
+    """One switch of a graph class on a copy of E: (E', outcome code)."""
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    oc = _load().oracle_edge_switch_class(_p(E), len(E), i, j, g, cls, mutate)
+    return E, oc
 
 
 def selftest_edgeset(ops: int = 200000, seed: int = 1) -> int:

@@ -46,6 +46,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <unordered_map>
 #include <unordered_set>
 #include <utility>
 #include <vector>
@@ -405,6 +406,119 @@ int oracle_es_run(uint64_t *E, uint64_t m, uint32_t n, uint64_t seed, uint64_t k
         }
     }
     return 0;
+}
+
+// ---- graph classes (Sec. 1: directed graphs, graphs with loops, with
+// multi-edges) -----------------------------------------------------------
+// cls bits: 1 = loops allowed, 2 = multi-edges allowed, 4 = directed.
+//   undirected: edges stored (min, max); tau of Def. 2.1 with g;
+//   directed:   edges stored (tail, head) as given; the switch exchanges the
+//               heads, (u->v), (x->y) -> (u->y), (x->v), whatever g is (out-
+//               and in-degrees are kept);
+//   a loop target is rejected unless loops are allowed; a present target is
+//   rejected unless multi-edges are allowed, and so is a switch whose two
+//   targets coincide (it would double an edge);
+//   undirected with loops and no multi-edges: a switch with a loop among its
+//   sources gives the same targets for g = 0 and g = 1, while its reverse
+//   move has one g, so it runs for g = 0 only and is rejected (as a loop) for
+//   g = 1 -- this keeps the chain symmetric (Thm. 3.3's argument), hence
+//   uniform over the class.  With multi-edges the plain switch is kept: the
+//   chain then balances the configuration model's weight 1 / (prod over
+//   edges of multiplicity! * 2^loops) (directed: 1 / prod multiplicity!).
+// The edge multiset is a count per key.
+enum { CLS_LOOPS = 1, CLS_MULTI = 2, CLS_DIRECTED = 4 };
+
+static uint64_t cls_key(uint32_t a, uint32_t b, uint32_t cls) {
+    return (cls & CLS_DIRECTED) ? (((uint64_t)a << 32) | b) : make_key(a, b);
+}
+
+// Planted mistakes of the class switch (for the pin tests).
+enum { CMUT_DIR_TAILS = 1, CMUT_NO_SAME = 2, CMUT_LOOPS_ALWAYS = 4, CMUT_LOOP_BOTH_G = 8 };
+
+static int edge_switch_cls(uint64_t *E, std::unordered_map<uint64_t, uint32_t> &S, uint64_t i, uint64_t j, int g,
+                           uint32_t cls, uint32_t mutate) {
+    const uint64_t e1 = E[i], e2 = E[j];
+    const uint32_t u = key_u(e1), v = key_v(e1), x = key_u(e2), y = key_v(e2);
+    uint32_t a0, a1, b0, b1;
+    if ((cls & CLS_DIRECTED) && (mutate & CMUT_DIR_TAILS)) {
+        a0 = u; a1 = x; b0 = v; b1 = y;
+    } else if (cls & CLS_DIRECTED) {
+        a0 = u; a1 = y; b0 = x; b1 = v;
+    } else if (g == 0) {
+        a0 = u; a1 = x; b0 = v; b1 = y;
+    } else {
+        a0 = u; a1 = y; b0 = v; b1 = x;
+    }
+    if (!(cls & CLS_LOOPS) && !(mutate & CMUT_LOOPS_ALWAYS) && (a0 == a1 || b0 == b1)) return OR_LOOP;
+    if ((cls & (CLS_LOOPS | CLS_MULTI | CLS_DIRECTED)) == CLS_LOOPS && g == 1 && (u == v || x == y) &&
+        !(mutate & CMUT_LOOP_BOTH_G))
+        return OR_LOOP;
+    const uint64_t e3 = cls_key(a0, a1, cls), e4 = cls_key(b0, b1, cls);
+    if (!(cls & CLS_MULTI)) {
+        if ((e3 == e4 && !(mutate & CMUT_NO_SAME)) || S.count(e3) || S.count(e4)) return OR_EXISTS;
+    }
+    for (uint64_t e : {e1, e2}) {
+        auto it = S.find(e);
+        if (--it->second == 0) S.erase(it);
+    }
+    ++S[e3];
+    ++S[e4];
+    E[i] = e3;
+    E[j] = e4;
+    return OR_LEGAL;
+}
+
+// Input check of a graph of class cls on [0, n): ids in range, loops only if
+// allowed, duplicates only if multi-edges are allowed.  Returns 0, -2 or -3.
+int oracle_validate_class(const uint64_t *E, uint64_t m, uint32_t n, uint32_t cls) {
+    std::unordered_map<uint64_t, uint32_t> S;
+    for (uint64_t e = 0; e < m; ++e) {
+        const uint32_t a = key_u(E[e]), b = key_v(E[e]);
+        if (a >= n || b >= n || a == 0xFFFFFFFFu || b == 0xFFFFFFFFu) return -3;
+        if (a == b && !(cls & CLS_LOOPS)) return -2;
+        if (S[cls_key(a, b, cls)]++ && !(cls & CLS_MULTI)) return -2;
+    }
+    return 0;
+}
+
+// Alg. 3 for a graph class: r global switches from superstep t0 (pi and the
+// P_L skips as in oracle_run) with the class's switch.  Undirected inputs
+// given as (max, min) are canonicalised; directed ones are kept as given.
+int oracle_run_class(uint64_t *E, uint64_t m, uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl,
+                     uint32_t cls, oracle_counts *per_step, uint8_t *last_outcome, uint32_t mutate) {
+    int rc = oracle_validate_class(E, m, n, cls);
+    if (rc) return rc;
+    for (uint64_t e = 0; e < m; ++e) E[e] = cls_key(key_u(E[e]), key_v(E[e]), cls);
+    if (per_step) memset(per_step, 0, sizeof(oracle_counts) * r);
+    if (m < 2) return 0;
+    std::unordered_map<uint64_t, uint32_t> S;
+    for (uint64_t e = 0; e < m; ++e) ++S[E[e]];
+    std::vector<uint32_t> pi(m);
+    for (uint32_t s = 0; s < r; ++s) {
+        const uint32_t t = t0 + s;
+        oracle_permutation_mut(m, seed, t, pi.data(), 0);
+        for (uint64_t k = 0; k < m / 2; ++k) {
+            const uint64_t i = pi[2 * k], j = pi[2 * k + 1];
+            const int oc = pl_skip(seed, t, k, pl) ? OR_PL : edge_switch_cls(E, S, i, j, i < j, cls, mutate);
+            if (s + 1 == r && last_outcome) last_outcome[k] = (uint8_t)oc;
+            if (per_step) {
+                oracle_counts &c = per_step[s];
+                c.attempts++;
+                c.legal += oc == OR_LEGAL;
+                c.rej_loop += oc == OR_LOOP;
+                c.rej_exists += oc == OR_EXISTS;
+                c.rej_pl += oc == OR_PL;
+            }
+        }
+    }
+    return 0;
+}
+
+// One switch of class cls with explicit (i, j, g) on E (for exhaustive tests).
+int oracle_edge_switch_class(uint64_t *E, uint64_t m, uint64_t i, uint64_t j, int g, uint32_t cls, uint32_t mutate) {
+    std::unordered_map<uint64_t, uint32_t> S;
+    for (uint64_t e = 0; e < m; ++e) ++S[E[e]];
+    return edge_switch_cls(E, S, i, j, g, cls, mutate);
 }
 
 // Self-check of the edge set against std::unordered_set on a seeded random

@@ -143,3 +143,52 @@ def es_run(E, seed: int, k0: int, r: int):
         E[i], E[j] = e3, e4
         out.append(LEGAL)
     return E, out
+
+
+# ---------------------------------------------------------------------------
+# Graph classes (Sec. 1): loops allowed (1), multi-edges allowed (2),
+# directed (4), written out separately
+# ---------------------------------------------------------------------------
+
+def _ckey(a, b, cls):
+    return (a << 32) | b if cls & 4 else _key(a, b)
+
+
+def run_class(E, seed: int, t0: int, r: int, pl: int, cls: int):
+    """r global switches of class cls, one at a time: (E, per-superstep counts)."""
+    E = [_ckey(*_split(e), cls) for e in E]
+    m = len(E)
+    counts = []
+    for s in range(r):
+        t = t0 + s
+        c = dict(attempts=0, legal=0, rej_loop=0, rej_exists=0, rej_pl=0)
+        if m >= 2:
+            pi = permutation(m, seed, t)
+            for k in range(m // 2):
+                c["attempts"] += 1
+                if pl_skip(seed, t, k, pl):
+                    c["rej_pl"] += 1
+                    continue
+                i, j = pi[2 * k], pi[2 * k + 1]
+                u, v = _split(E[i])
+                x, y = _split(E[j])
+                if cls & 4:
+                    a, b = (u, y), (x, v)
+                elif i < j:
+                    a, b = (u, y), (v, x)
+                else:
+                    a, b = (u, x), (v, y)
+                if not (cls & 1) and (a[0] == a[1] or b[0] == b[1]):
+                    c["rej_loop"] += 1
+                    continue
+                if cls & 7 == 1 and i < j and (u == v or x == y):
+                    c["rej_loop"] += 1  # a loop source: g = 1 gives g = 0's targets again
+                    continue
+                e3, e4 = _ckey(*a, cls), _ckey(*b, cls)
+                if not (cls & 2) and (e3 == e4 or e3 in E or e4 in E):
+                    c["rej_exists"] += 1
+                    continue
+                E[i], E[j] = e3, e4
+                c["legal"] += 1
+        counts.append(c)
+    return E, counts
