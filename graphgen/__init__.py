@@ -1,9 +1,10 @@
 """Seeded synthetic starting graphs shared by the HIP path's tests/bench and the oracle.
 
-This module holds no part of the edge-switching method: it only builds simple
-undirected graphs (as packed 64-bit keys ``(min << 32) | max``) whose shape
-follows the paper's synthetic families (Sec. 6: SynGnp and SynPld), and the
-named workloads used for parity tests and the benchmark.
+This module holds no part of the edge-switching method: it only builds graphs
+(as packed 64-bit keys ``(min << 32) | max``, directed ``(tail << 32) | head``)
+whose shape follows the paper's synthetic families (Sec. 6: SynGnp and
+SynPld), graphs of the other classes Sec. 1 names, and the named workloads
+used for parity tests and the benchmark.
 
 The C source ``graphgen.c`` is compiled with gcc into ``libgraphgen.so`` next to
 it (``build()``); loading compiles it if the library is missing.
@@ -139,6 +140,57 @@ def pack(u, v) -> np.ndarray:
 def degrees(keys: np.ndarray, n: int) -> np.ndarray:
     u, v = split(keys)
     return (np.bincount(u, minlength=n) + np.bincount(v, minlength=n)).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Graphs of the other classes (directed, with loops, with multi-edges).  Keys:
+# undirected (min << 32) | max, directed (tail << 32) | head.  cls bits:
+# 1 loops allowed, 2 multi-edges allowed, 4 directed.
+# ---------------------------------------------------------------------------
+
+def class_graph(n: int, m: int, cls: int, seed: int) -> np.ndarray:
+    """m edges with uniform endpoints on [0, n), in random order: a loop is
+    redrawn unless the class allows loops, a repeated key unless it allows
+    multi-edges."""
+    loops, multi, directed = bool(cls & 1), bool(cls & 2), bool(cls & 4)
+    cap = n * (n - 1) // (1 if directed else 2) + (n if loops else 0)
+    if not multi and m > cap:
+        raise ValueError("class %d on %d vertices holds at most %d edges" % (cls, n, cap))
+    rng = np.random.default_rng(seed)
+    have = np.zeros(0, dtype=np.uint64)
+    while len(have) < m:
+        want = m - len(have)
+        a = rng.integers(0, n, 2 * want + 16, dtype=np.uint64)
+        b = rng.integers(0, n, 2 * want + 16, dtype=np.uint64)
+        if not loops:
+            keep = a != b
+            a, b = a[keep], b[keep]
+        k = (a << np.uint64(32)) | b if directed else pack(a, b)
+        if multi:
+            have = np.concatenate([have, k[:want]])
+        else:
+            allk = np.concatenate([have, k])
+            _, first = np.unique(allk, return_index=True)
+            first.sort()
+            have = allk[first][:m]
+    return have[:m].astype(np.uint64)
+
+
+def config_model_graph(n: int, gamma: float, dmin: int, dmax: int, seed: int, directed: bool = False) -> np.ndarray:
+    """The configuration model's loopy multigraph of a Pld([dmin..dmax], gamma)
+    degree sequence: stubs paired uniformly at random.  Directed: out-degrees
+    from the draw, in-degrees a seeded permutation of them, out-stubs paired
+    with in-stubs."""
+    deg = powerlaw_degrees(n, gamma, dmin, dmax, seed).astype(np.int64)
+    rng = np.random.default_rng(seed ^ 0x9E3779B97F4A7C15)
+    stubs = np.repeat(np.arange(n, dtype=np.uint64), deg)
+    if directed:
+        heads = np.repeat(np.arange(n, dtype=np.uint64), deg[rng.permutation(n)])
+        rng.shuffle(heads)
+        rng.shuffle(stubs)
+        return (stubs << np.uint64(32)) | heads
+    rng.shuffle(stubs)
+    return pack(stubs[0::2], stubs[1::2])
 
 
 # ---------------------------------------------------------------------------

@@ -174,6 +174,43 @@ gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64
                                       uint32_t n, uint64_t seed, uint32_t t, uint32_t pl, uint8_t *d_outcome,
                                       gesmc_step_stats *step);
 
+/*
+ * G-ES-MC on another graph class (Sec. 1 names directed graphs and graphs
+ * with loops or multi-edges as classes the switch carries over to).  cls is
+ * a set of bits: GESMC_CLASS_LOOPS (loops allowed), GESMC_CLASS_MULTI
+ * (multi-edges allowed), GESMC_CLASS_DIRECTED; 0 is gesmc_run's simple
+ * undirected graph.  The permutation, the pairs, P_L and g = [i < j] are as
+ * for gesmc_run; the switch of a pair is:
+ *   undirected: tau of Def. 2.1 on the canonical keys (smaller id high);
+ *   directed: keys stay (tail << 32) | head as given and the switch
+ *     exchanges the heads, (u->v), (x->y) -> (u->y), (x->v), for either g,
+ *     keeping every out- and in-degree;
+ *   rejected as a loop (code 2): a loop target where loops are not allowed;
+ *     and, undirected with loops but no multi-edges, a switch with g = 1
+ *     and a loop among its sources (its two g give the same targets, its
+ *     reverse move only one; rejecting one keeps the chain symmetric, so
+ *     the class's uniform distribution is stationary);
+ *   rejected as present (code 3), without multi-edges only: a target that
+ *     is an edge (Def. 2.1's rule, the switch's own sources included), or
+ *     two equal targets.
+ * With multi-edges every switch is decided from its own two edges, and the
+ * chain balances the configuration model's weights (1 / the product of the
+ * multiplicities' factorials, times 2^-loops undirected).  Input: ids < n,
+ * loops only with GESMC_CLASS_LOOPS (else GESMC_E_NOT_SIMPLE), duplicates
+ * (equal keys; directed (a,b) and (b,a) differ) only with GESMC_CLASS_MULTI
+ * (else GESMC_E_NOT_SIMPLE).  Output: undirected canonical, directed as
+ * stored, at the input positions.  d_outcome (device, nullable, floor(m/2)
+ * bytes): the last superstep's codes as for gesmc_superstep_outcomes.
+ * Other arguments, statistics and errors as for gesmc_run (no LDS small-
+ * graph path; GESMC_E_INVAL for cls > 7).
+ */
+#define GESMC_CLASS_LOOPS 1u
+#define GESMC_CLASS_MULTI 2u
+#define GESMC_CLASS_DIRECTED 4u
+gesmc_status gesmc_run_class(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                             uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t cls,
+                             gesmc_stats *stats, gesmc_step_stats *steps, uint8_t *d_outcome);
+
 /* Permutation keys K_i (see above) for i < m, to d_keys (device, m words). */
 gesmc_status gesmc_perm_keys(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint64_t *d_keys);
 

@@ -27,6 +27,7 @@ OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
 OPT_ROUND_LIMIT = 13
 CHAIN_GLOBAL, CHAIN_ES = 0, 1
+CLASS_LOOPS, CLASS_MULTI, CLASS_DIRECTED = 1, 2, 4
 NOALLOC_MAX_EDGES = 2000000
 STRATEGY_SORTED_TUPLES, STRATEGY_HBM_TABLE = 0, 1
 
@@ -114,7 +115,7 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
            "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
-           "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing"]
+           "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing", "gesmc_run_class"]
 
 _lib = None
 _lock = threading.Lock()
@@ -193,6 +194,9 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_mixing.argtypes = [vp, vp, vp, u64, u32, u64, u32, u32, u32, ctypes.POINTER(u32), u32,
                                      ctypes.POINTER(MixingResult), ctypes.POINTER(ctypes.c_double)]
         lib.gesmc_mixing.restype = i32
+        lib.gesmc_run_class.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
+                                        ctypes.POINTER(StepStats), vp]
+        lib.gesmc_run_class.restype = i32
         _lib = lib
         return lib
 
@@ -257,6 +261,22 @@ class Context:
         if steps:
             return out, st.as_dict(), [ss[q].as_dict() for q in range(r)]
         return out, st.as_dict()
+
+    def run_class(self, edges: torch.Tensor, n: int, seed: int, cls: int, t0: int = 0, r: int = 1, pl: int = 0,
+                  out: torch.Tensor | None = None, stream=None, steps: bool = False, outcomes: bool = False):
+        """gesmc_run_class: r global switches of graph class `cls` (CLASS_* bits).
+        Returns (out, stats, step list or None, last superstep's outcome codes or None)."""
+        m = edges.numel()
+        if out is None:
+            out = torch.empty_like(edges)
+        st = Stats()
+        ss = (StepStats * max(r, 1))() if steps else None
+        oc = torch.zeros(max(m // 2, 1), dtype=torch.uint8, device=edges.device) if outcomes else None
+        _check(_lib.gesmc_run_class(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges"),
+                                    _dev_ptr(out, 8, m, "out"), m, n, seed & (2**64 - 1), t0, r, pl, cls,
+                                    ctypes.byref(st), ss, None if oc is None else ctypes.c_void_p(oc.data_ptr())))
+        return (out, st.as_dict(), [ss[q].as_dict() for q in range(r)] if steps else None,
+                oc[: m // 2] if outcomes else None)
 
     def run_noalloc(self, edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0,
                     out: torch.Tensor | None = None, stream=None):

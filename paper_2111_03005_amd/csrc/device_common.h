@@ -126,6 +126,37 @@ __device__ __forceinline__ Targets switch_targets(uint64_t e1, uint64_t e2, bool
     return T;
 }
 
+// Graph classes (Sec. 1): bit 1 loops allowed, bit 2 multi-edges allowed,
+// bit 4 directed.  Class 0 is the simple undirected graph of Def. 2.1.
+enum : uint32_t { CLS_LOOPS = 1u, CLS_MULTI = 2u, CLS_DIRECTED = 4u, CLS_ALL = 7u };
+
+// Targets of a switch in class cls.  Directed edges are stored (tail, head)
+// in the key's (high, low) word and the switch exchanges the heads whatever
+// g is, which keeps every out- and in-degree.  Undirected edges are stored
+// canonically and tau of Def. 2.1 applies.  `loop` asks for rejection as a
+// loop: a loop target where loops are not allowed, and, for undirected
+// graphs with loops and no multi-edges, a switch with g = 1 that has a loop
+// among its sources -- such a switch gives the same targets for both g while
+// its reverse move has only one, so only g = 0 runs and the chain stays
+// symmetric (Thm. 3.3).
+__device__ __forceinline__ Targets switch_targets_cls(uint64_t e1, uint64_t e2, bool g, uint32_t cls) {
+    if (cls == 0) return switch_targets(e1, e2, g);
+    const uint32_t u = ekey_lo_vertex(e1), v = ekey_hi_vertex(e1);
+    const uint32_t x = ekey_lo_vertex(e2), y = ekey_hi_vertex(e2);
+    Targets T;
+    if (cls & CLS_DIRECTED) {
+        T.A = ((uint64_t)u << 32) | y;
+        T.B = ((uint64_t)x << 32) | v;
+        T.loop = !(cls & CLS_LOOPS) && (u == y || x == v);
+    } else {
+        const uint32_t a1 = g ? y : x, b1 = g ? x : y;
+        T.A = ekey(u, a1);
+        T.B = ekey(v, b1);
+        T.loop = (cls & CLS_LOOPS) ? (cls == CLS_LOOPS && g && (u == v || x == y)) : (u == a1 || v == b1);
+    }
+    return T;
+}
+
 // Permutation key of record (input position idx) of graph g in batch superstep s.
 __device__ __forceinline__ uint64_t batch_perm_key(const BatchGraph &g, uint32_t idx, uint32_t s) {
     if (idx == kPadIdx) return ~0ull;

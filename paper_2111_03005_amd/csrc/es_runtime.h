@@ -79,7 +79,7 @@ gesmc_status run_es_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint6
                      (uint64_t)(sizeof(EsCounters) / 4)));
     if (m > 0)
         GESMC_TRY(launch(c, s, KID_LOAD, m, k_load, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
-                         (const unsigned long long *)d_in, m, n, c->es_slot, c->es_E, c->err));
+                         (const unsigned long long *)d_in, m, n, c->es_slot, c->es_E, c->err, 0u));
     uint64_t launches = 0;
     if (m >= 2) {
         for (uint64_t kb = k0; kb == k0 || kb - k0 < r; kb += epoch) {

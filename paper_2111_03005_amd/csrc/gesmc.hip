@@ -81,6 +81,7 @@ enum KernelId {
     KID_ES_BUILD,
     KID_ES_CHAIN,
     KID_MIX,
+    KID_DECIDE_LOCAL,
     KID_COUNT
 };
 
@@ -91,7 +92,7 @@ const char *kKernelNames[KID_COUNT] = {
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
     "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
     "k_small_chain_compact",
-    "k_es_build",     "k_es_chain",     "k_mixing"};
+    "k_es_build",     "k_es_chain",     "k_mixing",     "k_decide_local"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -284,9 +285,9 @@ uint64_t table_slots_for(uint64_t m) {
     return std::max<uint64_t>(1024, (4 * m + 7) / 8 * 8);
 }
 
-gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m) {
+gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m, bool tuples = false) {
     const bool need_tab = c->strategy == 1;
-    const bool need_tu = c->strategy == 0;
+    const bool need_tu = c->strategy == 0 || tuples;
     if (m <= c->cap_m && (!need_tab || c->tab) && (!need_tu || c->info)) return GESMC_OK;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
     free_buffers(c);
@@ -793,7 +794,8 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
 // One superstep with the partitioned resolution (state in buffer 0).
 // vend bounds the vertex ids of the keys (a batch: bs->vend, bs->dend).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
-                                   uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0) {
+                                   uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0,
+                                   uint32_t cls = 0) {
     int sorted = 0;
     GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs));
     const uint32_t *si = c->idx[sorted];
@@ -813,6 +815,9 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     sa.step = bs ? bs->step : 0u;
     sa.m = p.m;
     sa.pl = pl;
+    sa.cls = cls;
+    // directed keys (tail, head) do not fit the packed (u, v - u) coding
+    if (cls & CLS_DIRECTED) vend = 0;
     if (!fused)
         GESMC_TRY(launch(c, s, KID_EMIT, p.ell, k_emit, dim3(ge), dim3(kBlock), 0, si, sk, t, k0, k1, sa, c->info,
                          c->st, c->idx[0], c->key[0], c->bslot, c->ucount));
@@ -828,22 +833,34 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
                      (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->bslot + ge,
-                     c->ctr_step));
+                     c->ctr_step, cls));
     const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
     int j = 0;
     for (; j < c->fast_rounds; ++j) {
         GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN, 0, k_decide_chain, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
                          (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
                          (const uint32_t *)&c->ucount[j % 3], c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3],
-                         &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step));
+                         &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step, cls));
     }
     GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
                      (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
                      c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
-                     c->ctr_step, c->err, c->round_limit));
+                     c->ctr_step, c->err, c->round_limit, cls));
     if (bs && bs->acc)
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_graph_stats, dim3(ceil_div(p.ell, kStatsChunk)), dim3(kBlock), 0,
                          (const uint8_t *)c->st, bs->gr, bs->ngraphs, p.ell, bs->acc));
+    return GESMC_OK;
+}
+
+// One superstep of a multi-edge class (state in buffer 0): the permutation,
+// then every switch decided from its own pair records (k_decide_local).
+gesmc_status superstep_local(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
+                             uint32_t pl, uint32_t cls) {
+    int sorted = 0;
+    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false));
+    GESMC_TRY(launch(c, s, KID_DECIDE_LOCAL, p.ell, k_decide_local, dim3(grid_stride_blocks(c, (uint64_t)p.ell + 1)),
+                     dim3(kBlock), 0, c->idx[sorted], c->key[sorted], p.m, t, k0, k1, pl, cls, c->st, c->idx[0],
+                     c->key[0], c->ctr_step));
     return GESMC_OK;
 }
 
@@ -905,7 +922,7 @@ gesmc_status collect_profile(gesmc_ctx *c) {
 
 gesmc_status map_err(uint32_t e) {
     if (e & (ERR_LOOP | ERR_DUP)) {
-        set_error("input is not a simple graph (%s)", (e & ERR_LOOP) ? "loop" : "duplicate edge");
+        set_error("input is not a graph of the requested class (%s)", (e & ERR_LOOP) ? "loop" : "duplicate edge");
         return GESMC_E_NOT_SIMPLE;
     }
     if (e & ERR_RANGE) {
@@ -969,7 +986,7 @@ gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, u
 
 gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m64, uint32_t n,
                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats,
-                      gesmc_step_stats *steps, uint8_t *d_outcome) {
+                      gesmc_step_stats *steps, uint8_t *d_outcome, uint32_t cls = 0) {
     if (!c) {
         set_error("null context");
         return GESMC_E_INVAL;
@@ -991,10 +1008,14 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     const uint32_t m = (uint32_t)m64;
     // small graphs (Sec. 7's base case): every superstep in one workgroup's LDS,
     // one launch, when no per-superstep records or outcome codes are asked for
-    if (c->small_graphs && c->strategy == 0 && m >= 2 && r > 0 && !steps && !d_outcome &&
+    if (cls > CLS_ALL) {
+        set_error("graph class %u has bits other than loops (1), multi-edges (2) and directed (4)", cls);
+        return GESMC_E_INVAL;
+    }
+    if (cls == 0 && c->small_graphs && c->strategy == 0 && m >= 2 && r > 0 && !steps && !d_outcome &&
         (m <= kMidMax || (m <= kCmpMax && n <= kCmpMaxN)))
         return run_small_impl(c, s, d_in, d_out, m, n, seed, t0, r, pl, stats);
-    GESMC_TRY(ensure_capacity(c, m));
+    GESMC_TRY(ensure_capacity(c, m, cls != 0 && !(cls & CLS_MULTI)));
     GESMC_TRY(ensure_counters(c, r));
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     c->tuple_bytes = 0;
@@ -1005,12 +1026,15 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
                      zero_words - 64));
     if (m > 0)
         GESMC_TRY(launch(c, s, KID_LOAD, m, k_load, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
-                         (const unsigned long long *)d_in, m, n, c->idx[0], c->key[0], c->err));
+                         (const unsigned long long *)d_in, m, n, c->idx[0], c->key[0], c->err, cls));
     const Plan p = make_plan(c, m);
     const uint32_t nslots = (uint32_t)c->tab_slots;
-    if (m >= 2 && r == 0) {
+    // the graph classes run on the sorted tuples only (multi-edge classes
+    // have no dependencies at all)
+    const bool table = c->strategy == 1 && cls == 0;
+    if (m >= 2 && r == 0 && !(cls & CLS_MULTI)) {
         c->ctr_step = c->ctr;
-        if (c->strategy == 1) {
+        if (table) {
             GESMC_TRY(launch(c, s, KID_STEP_CLEAR, c->tab_slots, k_step_clear,
                              dim3(grid_stride_blocks(c, c->tab_slots)), dim3(kBlock), 0, c->tab, c->tab_slots, c->st,
                              0u, c->ucount));
@@ -1026,10 +1050,12 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
         for (uint32_t q = 0; q < r; ++q) {
             c->ctr_step = c->ctr + q;
             const uint32_t dup = q == 0 ? ERR_DUP : ERR_INTERNAL;
-            if (c->strategy == 1)
+            if (cls & CLS_MULTI)
+                GESMC_TRY(superstep_local(c, s, p, t0 + q, k0, k1, pl, cls));
+            else if (table)
                 GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, dup));
             else
-                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup, nullptr, n));
+                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup, nullptr, n, cls));
         }
     }
     if (d_outcome && p.ell > 0)
@@ -2068,6 +2094,12 @@ gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint6
         return GESMC_E_INVAL;
     }
     return run_impl(ctx, stream, d_in, d_out, m, n, seed, t0, r, pl, stats, steps, nullptr);
+}
+
+gesmc_status gesmc_run_class(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
+                             uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t cls,
+                             gesmc_stats *stats, gesmc_step_stats *steps, uint8_t *d_outcome) {
+    return run_impl(ctx, stream, d_in, d_out, m, n, seed, t0, r, pl, stats, steps, d_outcome, cls);
 }
 
 gesmc_status gesmc_run_host(gesmc_ctx *c, const uint32_t *uv, uint32_t *uv_out, uint64_t m, uint32_t n,

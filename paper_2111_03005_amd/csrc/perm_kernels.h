@@ -178,6 +178,7 @@ struct SrcArgs {
     uint32_t m;              // records (the pair records of ell = m / 2 switches)
     uint32_t pl;             // P_L threshold (batch: nonzero if some graph has one)
     TuplePack pk;            // kSrcEmitPacked: hash width, offset and tag code bits
+    uint32_t cls;            // graph class (CLS_* bits; multi-edge classes never come here)
 };
 
 template <int kSrc>
@@ -197,7 +198,8 @@ __device__ __forceinline__ constexpr bool src_packed() { return kSrc == kSrcEmit
 
 // Local outcome of switch k from its pair records (ij, ee): P_L skip, the
 // idle pair of a batch graph's padding record, a loop, or a target equal to
-// one of its own sources (Def. 2.1); ST_UNDECIDED if it depends on others.
+// one of its own sources or to its other target (Def. 2.1; the last occurs
+// only with loops, as two loop sources); ST_UNDECIDED if it depends on others.
 __device__ __forceinline__ uint8_t switch_local(uint32_t k, uint2 ij, ulonglong2 ee, uint32_t t, uint32_t k0,
                                                 uint32_t k1, const SrcArgs &sa, Targets *T) {
     bool skip = false;
@@ -211,9 +213,9 @@ __device__ __forceinline__ uint8_t switch_local(uint32_t k, uint2 ij, ulonglong2
         skip = pl_skip(k, t, sa.pl, k0, k1);
     }
     if (skip) return ST_PL;
-    *T = switch_targets(ee.x, ee.y, ij.x < ij.y);
+    *T = switch_targets_cls(ee.x, ee.y, ij.x < ij.y, sa.cls);
     if (T->loop) return ST_LOOP;
-    if (T->A == ee.x || T->A == ee.y || T->B == ee.x || T->B == ee.y) return ST_EXISTS;
+    if (T->A == ee.x || T->A == ee.y || T->B == ee.x || T->B == ee.y || T->A == T->B) return ST_EXISTS;
     return ST_UNDECIDED;
 }
 

@@ -90,6 +90,55 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t *__restrict__ s_
     store_counts(&bc, bslot + blockIdx.x);
 }
 
+// A superstep of a multi-edge class (Sec. 1): no target is rejected for
+// being present, so each switch's outcome follows from its own pair records
+// alone (P_L skip, else a loop where loops are not allowed, else legal) and
+// the whole superstep is decided here, one thread per switch plus one for
+// the idle record of odd m.  Writes every record of buffer 0, the status
+// array and the superstep's counts.
+__global__ __launch_bounds__(kBlock) void k_decide_local(const uint32_t *__restrict__ s_idx,
+                                                         const unsigned long long *__restrict__ s_key, uint32_t m,
+                                                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t pl,
+                                                         uint32_t cls, uint8_t *__restrict__ st,
+                                                         uint32_t *__restrict__ out_idx,
+                                                         unsigned long long *__restrict__ out_key,
+                                                         StepCounters *ctr) {
+    __shared__ BlockCounts bc;
+    if (threadIdx.x == 0) bc = BlockCounts{0, 0, 0, 0};
+    __syncthreads();
+    const uint32_t ell = m >> 1;
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= ell; k += stride) {
+        if (k == ell) {
+            if (m & 1u) {
+                out_idx[m - 1] = s_idx[m - 1];
+                out_key[m - 1] = s_key[m - 1];
+            }
+            continue;
+        }
+        const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+        const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+        uint8_t status = ST_LEGAL;
+        ulonglong2 out = ee;
+        if (pl_skip(k, t, pl, k0, k1)) {
+            status = ST_PL;
+        } else {
+            const Targets T = switch_targets_cls(ee.x, ee.y, ij.x < ij.y, cls);
+            if (T.loop)
+                status = ST_LOOP;
+            else
+                out = make_ulonglong2(T.A, T.B);
+        }
+        st[k] = status;
+        reinterpret_cast<uint2 *>(out_idx)[k] = ij;
+        reinterpret_cast<ulonglong2 *>(out_key)[k] = out;
+        if (status == ST_LEGAL) atomicAdd(&bc.legal, 1u);
+        if (status == ST_LOOP) atomicAdd(&bc.loop, 1u);
+        if (status == ST_PL) atomicAdd(&bc.pl, 1u);
+    }
+    flush_counts(&bc, ctr);
+}
+
 // k_emit fused into the first tuple partition pass's counts (kSrcEmit or
 // kSrcEmitPacked, one segment [0, nslots) of kTile-slot tiles): the pair
 // records of a switch are read once, for its status, its records and
@@ -547,13 +596,13 @@ __device__ __forceinline__ int judge_target_chain(const uint2 *info, uint2 rec, 
 // are passed in so that callers can issue every load of the switch at once.
 __device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint2 ij, ulonglong2 ee, const uint2 *info,
                                                     uint8_t *st, uint32_t *out_idx, unsigned long long *out_key,
-                                                    BlockCounts *bc) {
+                                                    BlockCounts *bc, uint32_t cls) {
     const int v = max(judge_target_chain(info, make_uint2(recs.x, recs.y), k, st),
                       judge_target_chain(info, make_uint2(recs.z, recs.w), k, st));
     if (v == V_WAIT) return true;
     reinterpret_cast<uint2 *>(out_idx)[k] = ij;
     if (v == V_OK) {
-        const Targets T = switch_targets(ee.x, ee.y, ij.x < ij.y);
+        const Targets T = switch_targets_cls(ee.x, ee.y, ij.x < ij.y, cls);
         reinterpret_cast<ulonglong2 *>(out_key)[k] = make_ulonglong2(T.A, T.B);
         st[k] = ST_LEGAL;
         atomicAdd(&bc->legal, 1u);
@@ -576,7 +625,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
                                                          uint32_t *__restrict__ next_list,
                                                          uint32_t *__restrict__ next_count,
                                                          uint32_t *__restrict__ zero_count,
-                                                         uint4 *__restrict__ bslot, StepCounters *ctr) {
+                                                         uint4 *__restrict__ bslot, StepCounters *ctr,
+                                                         uint32_t cls) {
     __shared__ BlockCounts bc;
     if (threadIdx.x == 0) bc = BlockCounts{0, 0, 0, 0};
     __syncthreads();
@@ -596,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
                 const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
                 const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
                 const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
-                if (sk == ST_UNDECIDED) wait = decide_switch_chain(k, recs, ij, ee, info, st, out_idx, out_key, &bc);
+                if (sk == ST_UNDECIDED) wait = decide_switch_chain(k, recs, ij, ee, info, st, out_idx, out_key, &bc, cls);
             }
         }
         append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
@@ -618,7 +668,8 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
                                                                uint32_t *list_a, uint32_t *count_a, uint32_t *list_b,
                                                                uint32_t *count_b, const uint4 *__restrict__ bslot,
                                                                uint32_t nbslot, StepCounters *ctr,
-                                                               uint32_t *__restrict__ err, uint32_t round_limit) {
+                                                               uint32_t *__restrict__ err, uint32_t round_limit,
+                                                               uint32_t cls) {
     __shared__ BlockCounts bc;
     __shared__ uint32_t s_n;
     const uint32_t tid = threadIdx.x;
@@ -674,7 +725,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
                     wait = decide_switch_chain(k, reinterpret_cast<const uint4 *>(info)[k],
                                                reinterpret_cast<const uint2 *>(s_idx)[k],
                                                reinterpret_cast<const ulonglong2 *>(s_key)[k], info, st, out_idx,
-                                               out_key, &bc);
+                                               out_key, &bc, cls);
             }
             append_undecided(wait, k, nxt, cnxt);
         }

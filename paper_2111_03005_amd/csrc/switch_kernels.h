@@ -26,20 +26,22 @@
 namespace gesmc {
 
 // ---------------------------------------------------------------------------
-// Input load: records (i, canonical E[i]); loops and out-of-range ids flagged.
+// Input load: records (i, E[i]), undirected keys made canonical; loops
+// (unless the class allows them) and out-of-range ids flagged.  Class 0 is
+// the simple undirected graph; directed keys are kept as (tail, head).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_load(const unsigned long long *__restrict__ in, uint32_t m, uint32_t n,
                                                  uint32_t *__restrict__ idx, unsigned long long *__restrict__ key,
-                                                 uint32_t *__restrict__ err) {
+                                                 uint32_t *__restrict__ err, uint32_t cls) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint32_t f = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
         const unsigned long long e = in[i];
         const uint32_t a = (uint32_t)(e >> 32), b = (uint32_t)e;
-        if (a == b) f |= ERR_LOOP;
+        if (a == b && !(cls & CLS_LOOPS)) f |= ERR_LOOP;
         if (a >= n || b >= n || a == 0xFFFFFFFFu || b == 0xFFFFFFFFu) f |= ERR_RANGE;
         idx[i] = (uint32_t)i;
-        key[i] = ekey(a, b);
+        key[i] = (cls & CLS_DIRECTED) ? e : ekey(a, b);
     }
     if (f) atomicOr(err, f);
 }
