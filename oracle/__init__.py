@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gesmc_oracle.cpp")
+_SRC_GEN = os.path.join(_HERE, "gen_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -45,7 +46,9 @@ class Counts(ctypes.Structure):
 def build() -> str:
     """Compile the oracle with g++ (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+    # no fused multiply-adds: the portable ln / exp must round every step
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC,
+                           _SRC_GEN])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -88,6 +91,25 @@ def _load():
     lib.oracle_run_class.restype = ctypes.c_int
     lib.oracle_edge_switch_class.argtypes = [vp, u64, u64, u64, ctypes.c_int, u32, u32]
     lib.oracle_edge_switch_class.restype = ctypes.c_int
+    f64, i64 = ctypes.c_double, ctypes.c_int64
+    lib.oracle_gen_set_mutate.argtypes = [u32]
+    lib.oracle_gen_set_mutate.restype = None
+    lib.oracle_ln_p.argtypes = [f64]
+    lib.oracle_ln_p.restype = f64
+    lib.oracle_exp_p.argtypes = [f64]
+    lib.oracle_exp_p.restype = f64
+    lib.oracle_pair_of.argtypes = [u64, vp, vp]
+    lib.oracle_pair_of.restype = None
+    lib.oracle_gnp_chunk.argtypes = [f64]
+    lib.oracle_gnp_chunk.restype = u64
+    lib.oracle_gen_gnp.argtypes = [u32, f64, u64, vp, i64]
+    lib.oracle_gen_gnp.restype = i64
+    lib.oracle_gen_pld.argtypes = [u32, f64, u32, u32, u64, vp, vp]
+    lib.oracle_gen_pld.restype = i64
+    lib.oracle_gen_havel_hakimi.argtypes = [u32, vp, vp, i64]
+    lib.oracle_gen_havel_hakimi.restype = i64
+    lib.oracle_gen_relabel.argtypes = [vp, u64, u32, u64]
+    lib.oracle_gen_relabel.restype = None
     lib.oracle_selftest_edgeset.argtypes = [u64, u64]
     lib.oracle_selftest_edgeset.restype = u64
     _lib = lib
@@ -214,6 +236,83 @@ def edge_switch_class(E: np.ndarray, i: int, j: int, g: int, cls: int, mutate: i
     E = np.ascontiguousarray(E, dtype=np.uint64).copy()
     oc = _load().oracle_edge_switch_class(_p(E), len(E), i, j, g, cls, mutate)
     return E, oc
+
+
+# ---- input realisation (gen_oracle.cpp) -----------------------------------
+
+GMUT_LN_TERMS, GMUT_GNP_NO_ADVANCE, GMUT_GNP_CEIL, GMUT_GNP_CHUNK_SKIP = 1, 2, 4, 8
+GMUT_PLD_SIGN, GMUT_PLD_OFF1, GMUT_HH_TIE, GMUT_HH_PICK, GMUT_RELABEL_INV, GMUT_EXP_TERMS = 16, 32, 64, 128, 256, 512
+
+
+class gen_mutation:
+    """Context manager planting a mistake in the input-realisation oracle."""
+
+    def __init__(self, mutate: int):
+        self.mutate = mutate
+
+    def __enter__(self):
+        _load().oracle_gen_set_mutate(self.mutate)
+        return self
+
+    def __exit__(self, *exc):
+        _load().oracle_gen_set_mutate(0)
+        return False
+
+
+def ln_p(x: float) -> float:
+    return _load().oracle_ln_p(float(x))
+
+
+def exp_p(x: float) -> float:
+    return _load().oracle_exp_p(float(x))
+
+
+def pair_of(q: int):
+    w, v = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().oracle_pair_of(q, ctypes.byref(w), ctypes.byref(v))
+    return w.value, v.value
+
+
+def gnp_chunk(p: float) -> int:
+    return int(_load().oracle_gnp_chunk(float(p)))
+
+
+def gen_gnp(n: int, p: float, seed: int) -> np.ndarray:
+    """G(n,p) edge keys in pair order (see gen_oracle.cpp)."""
+    lib = _load()
+    m = lib.oracle_gen_gnp(n, float(p), seed & (2**64 - 1), None, 0)
+    out = np.empty(max(m, 1), dtype=np.uint64)
+    m2 = lib.oracle_gen_gnp(n, float(p), seed & (2**64 - 1), _p(out), m)
+    assert m2 == m
+    return out[:m]
+
+
+def gen_pld(n: int, gamma: float, dmin: int, dmax: int, seed: int):
+    """(degrees uint32[n], degree sum, redraws of vertex 0), or None on failure."""
+    deg = np.empty(max(n, 1), dtype=np.uint32)
+    rd = ctypes.c_uint32(0)
+    s = _load().oracle_gen_pld(n, float(gamma), dmin, dmax, seed & (2**64 - 1), _p(deg), ctypes.byref(rd))
+    if s < 0:
+        return None
+    return deg[:n], int(s), rd.value
+
+
+def gen_havel_hakimi(deg) -> np.ndarray | None:
+    """Havel-Hakimi realisation (edge keys), or None if not graphical."""
+    d = np.ascontiguousarray(deg, dtype=np.uint32)
+    half = int(d.astype(np.int64).sum()) // 2
+    out = np.empty(max(half, 1), dtype=np.uint64)
+    m = _load().oracle_gen_havel_hakimi(len(d), _p(d), _p(out), half)
+    if m < 0:
+        return None
+    assert m == half
+    return out[:m]
+
+
+def gen_relabel(E, n: int, seed: int) -> np.ndarray:
+    E = np.ascontiguousarray(E, dtype=np.uint64).copy()
+    _load().oracle_gen_relabel(_p(E), len(E), n, seed & (2**64 - 1))
+    return E
 
 
 def selftest_edgeset(ops: int = 200000, seed: int = 1) -> int:

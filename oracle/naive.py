@@ -192,3 +192,138 @@ def run_class(E, seed: int, t0: int, r: int, pl: int, cls: int):
                 c["legal"] += 1
         counts.append(c)
     return E, counts
+
+
+# ---------------------------------------------------------------------------
+# Input realisation (the definitions in gen_oracle.cpp), written out again in
+# plain Python for small cases: Python floats are IEEE doubles whose +, -, *,
+# / round correctly and never fuse, so the portable ln / exp give the same
+# bits here as there.
+# ---------------------------------------------------------------------------
+import math as _math
+import struct as _struct
+
+_LN2_HI = 6.93147180369123816490e-01
+_LN2_LO = 1.90821492927058770002e-10
+
+
+def ln_p(x: float) -> float:
+    b = _struct.unpack("<Q", _struct.pack("<d", x))[0]
+    e = ((b >> 52) & 0x7FF) - 1023
+    m = _struct.unpack("<d", _struct.pack("<Q", (b & ((1 << 52) - 1)) | (1023 << 52)))[0]
+    if m > 1.4142135623730951:
+        m *= 0.5
+        e += 1
+    f = m - 1.0
+    s = f / (2.0 + f)
+    z = s * s
+    P = 1.0 / 23.0
+    for j in range(10, 0, -1):
+        P = P * z + 1.0 / (2 * j + 1)
+    t = 2.0 * s
+    return e * _LN2_HI + (e * _LN2_LO + (t + t * (z * P)))
+
+
+def exp_p(x: float) -> float:
+    kd = _math.floor(x * 1.4426950408889634 + 0.5)
+    r = (x - kd * _LN2_HI) - kd * _LN2_LO
+    p = 1.0 / _math.factorial(13)
+    for j in range(12, -1, -1):
+        p = p * r + 1.0 / _math.factorial(j)
+    return p * 2.0 ** kd
+
+
+def gnp(n: int, p: float, seed: int):
+    """G(n,p) by the chunked geometric skips, pair index decoded by search."""
+    if n < 2 or not p > 0:
+        return []
+    N = n * (n - 1) // 2
+    rows = [(v * (v - 1) // 2, v) for v in range(1, n)]
+
+    def pair(q):
+        base, v = max(r for r in rows if r[0] <= q)
+        return ((q - base) << 32) | v
+
+    if p >= 1:
+        return [pair(q) for q in range(N)]
+    L = 64
+    while L * p < 64 and L < 2 ** 40:
+        L *= 2
+    lq = ln_p(1.0 - p)
+    out = []
+    j = 0
+    while j * L < N:
+        end, c, t = min(j * L + L, N), j * L, 0
+        while True:
+            x = philox4x32_10((j & M32, j >> 32, t, 3), (seed & M32, (seed >> 32) & M32))
+            U = (((x[0] << 32 | x[1]) >> 11) + 1) / 2.0 ** 53
+            G = ln_p(U) / lq
+            t += 1
+            if not G < end - c:
+                break
+            q = c + int(G)
+            out.append(pair(q))
+            c = q + 1
+            if c >= end:
+                break
+        j += 1
+    return out
+
+
+def pld(n: int, gamma: float, dmin: int, dmax: int, seed: int):
+    """Degrees by the integer-weight inverse CDF; None if no even sum."""
+    W = [int(exp_p(-(gamma * (ln_p(float(k)) - ln_p(float(dmin))))) * 2.0 ** 43) for k in range(dmin, dmax + 1)]
+    C, acc = [], 0
+    for w in W:
+        acc += w
+        C.append(acc)
+
+    def draw(v, r):
+        x = philox4x32_10((v, r, 0, 4), (seed & M32, (seed >> 32) & M32))
+        u = ((x[0] << 32 | x[1]) * acc) >> 64
+        return dmin + next(i for i, c in enumerate(C) if c > u)
+
+    deg = [draw(v, 0) for v in range(n)]
+    r = 0
+    while sum(deg) % 2:
+        if dmin == dmax or r == 65535:
+            return None
+        r += 1
+        deg[0] = draw(0, r)
+    return deg
+
+
+def havel_hakimi(deg):
+    """The Havel-Hakimi construction by exhaustive scans: positions by
+    (degree desc, id asc); v = largest residual, smallest position; partners
+    the d others of positive residual with the largest (residual, position).
+    Returns the edge keys, or None if not graphical."""
+    n = len(deg)
+    order = sorted(range(n), key=lambda v: (-deg[v], v))
+    res = [deg[v] for v in order]
+    out = []
+    while any(res):
+        top = max(res)
+        s = min(p for p in range(n) if res[p] == top)
+        d = res[s]
+        res[s] = 0
+        cand = sorted((p for p in range(n) if res[p] > 0), key=lambda p: (res[p], p), reverse=True)
+        if len(cand) < d:
+            return None
+        for p in sorted(cand[:d]):
+            res[p] -= 1
+            a, b = order[s], order[p]
+            out.append((min(a, b) << 32) | max(a, b))
+    return out
+
+
+def erdos_gallai(deg) -> bool:
+    """Graphicality by the Erdos-Gallai inequalities."""
+    d = sorted(deg, reverse=True)
+    if sum(d) % 2:
+        return False
+    n = len(d)
+    for k in range(1, n + 1):
+        if sum(d[:k]) > k * (k - 1) + sum(min(x, k) for x in d[k:]):
+            return False
+    return True
