@@ -47,6 +47,7 @@ typedef int32_t gesmc_status;
 #define GESMC_E_CANCELED (-7)   /* server: the request was cancelled               */
 #define GESMC_E_ROUNDS (-8)     /* a superstep exceeded GESMC_OPT_ROUND_LIMIT      */
 #define GESMC_E_INTERNAL (-9)   /* an internal consistency check failed            */
+#define GESMC_E_NOT_GRAPHICAL (-10) /* a degree sequence no simple graph realises  */
 
 typedef struct gesmc_ctx gesmc_ctx;
 
@@ -210,6 +211,75 @@ gesmc_status gesmc_superstep_outcomes(gesmc_ctx *ctx, void *stream, const uint64
 gesmc_status gesmc_run_class(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m,
                              uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, uint32_t cls,
                              gesmc_stats *stats, gesmc_step_stats *steps, uint8_t *d_outcome);
+
+/*
+ * Input realisation on the device: the steps before the chain that build the
+ * synthetic inputs of Sec. 6, G(n,p) graphs (SynGnp) and Havel-Hakimi
+ * realisations of i.i.d. Pld([a..b], gamma) degree sequences (SynPld, Sec.
+ * 2.1's notation), plus a random relabelling.  Each result is a function of
+ * the arguments alone (any device, any launch shape):
+ *
+ *   Draws: Philox4x32-10 with key (seed_lo, seed_hi), counter tag 3 for
+ *   G(n,p) and 4 for degrees (tags 0 .. 2 belong to the chain).  Where
+ *   floating point decides an integer it goes through ln_p / exp_p, made of
+ *   correctly rounded IEEE double steps in a fixed order, never fused:
+ *     ln_p(x): x = 2^e m, m in [1, 2), if m > sqrt(2) then m /= 2, e += 1;
+ *       f = m - 1, s = f / (2 + f), z = s s, P = 1/23 then P = P z + 1/(2j+1)
+ *       for j = 10 .. 1, t = 2 s; ln_p = e LN2_HI + (e LN2_LO + (t + t (z P)))
+ *       with fdlibm's LN2_HI = 6.93147180369123816490e-01 and LN2_LO =
+ *       1.90821492927058770002e-10 (2 atanh(s) by its power series);
+ *     exp_p(x), -700 <= x <= 0: k = floor(x 1.4426950408889634 + 0.5),
+ *       r = (x - k LN2_HI) - k LN2_LO, p = 1/13! then p = p r + 1/j! for
+ *       j = 12 .. 0; exp_p = p 2^k.
+ *
+ *   gesmc_gen_gnp: each pair w < v < n an edge with probability p.  Pairs
+ *   are indexed q = v(v-1)/2 + w; [0, N) is cut into chunks of L pairs, L
+ *   the smallest power of two >= 64 with L p >= 64 (at most 2^40).  Chunk
+ *   j = [jL, min(jL+L, N)) walks a cursor c from jL: draw t takes (x0, x1)
+ *   of Philox(ctr = (j_lo, j_hi, t, 3)), U = (((x0 << 32 | x1) >> 11) + 1)
+ *   / 2^53, G = ln_p(U) / ln_p(1 - p); if G >= end - c the chunk ends, else
+ *   pair c + floor(G) is an edge and c moves past it (geometric skipping,
+ *   Batagelj and Brandes 2005; restarting at chunk starts is exact).  p >= 1:
+ *   every pair; p <= 0 or n < 2: none.  Output (w << 32) | v in q order.
+ *   *m = the edge count; d_out (device, cap keys) NULL only counts, and a
+ *   count above cap is GESMC_E_RANGE (d_out untouched).
+ *
+ *   gesmc_gen_pld_degrees: W_i = floor(exp_p(-(gamma (ln_p(a+i) - ln_p(a))))
+ *   2^43) for i = 0 .. b-a, C_i = W_0 + .. + W_i, T = C_{b-a}; vertex v's
+ *   draw r takes R = x0 << 32 | x1 of Philox(ctr = (v, r, 0, 4)), u =
+ *   floor(R T / 2^64), degree a + min{i : C_i > u}.  All vertices take draw
+ *   0; while the sum is odd vertex 0 takes draws 1, 2, ... (at most 65535).
+ *   d_deg (device, n words); *sum the even degree sum.  GESMC_E_INVAL for
+ *   n = 0, a < 1, b < a, b - a >= 2^20, gamma < 0, (b/a)^gamma >= e^690, or
+ *   no even sum (a = b odd with n odd).
+ *
+ *   gesmc_gen_havel_hakimi: vertices placed at positions 0 .. n-1 by (degree
+ *   descending, id ascending), residuals starting at the degrees; while a
+ *   residual is positive, the position v of largest residual d (smallest
+ *   position among ties) is joined to the d other positions of positive
+ *   residual with the largest (residual, position), v's residual becomes 0
+ *   and theirs drop by one; edges (v, partner) by ascending partner
+ *   position (Havel 1955, Hakimi 1962: this succeeds iff the sequence is
+ *   graphical).  d_deg (device, n words); d_out (device, cap keys, (min <<
+ *   32) | max); *m = sum / 2 (NULL d_out: only *m).  GESMC_E_NOT_GRAPHICAL
+ *   for an odd sum, a degree >= n, or a sequence that runs out of partners
+ *   (d_out then holds nothing defined); GESMC_E_RANGE for a degree above
+ *   16000, m >= 2^32 or m > cap.  The steps run in one wavefront (the
+ *   construction is sequential); the placement and edge writing are parallel.
+ *
+ *   gesmc_gen_relabel: pi = gesmc_permutation(n, seed ^ 0x9E3779B97F4A7C15,
+ *   t = 0); vertex pi[r] becomes r; each of the m keys of d_edges (device,
+ *   in place) is rewritten and made canonical.  1 <= n < 2^30;
+ *   GESMC_E_RANGE for an id >= n (keys then partly rewritten).
+ */
+gesmc_status gesmc_gen_gnp(gesmc_ctx *ctx, void *stream, uint32_t n, double p, uint64_t seed, uint64_t *d_out,
+                           uint64_t cap, uint64_t *m);
+gesmc_status gesmc_gen_pld_degrees(gesmc_ctx *ctx, void *stream, uint32_t n, double gamma, uint32_t dmin,
+                                   uint32_t dmax, uint64_t seed, uint32_t *d_deg, uint64_t *sum);
+gesmc_status gesmc_gen_havel_hakimi(gesmc_ctx *ctx, void *stream, uint32_t n, const uint32_t *d_deg,
+                                    uint64_t *d_out, uint64_t cap, uint64_t *m);
+gesmc_status gesmc_gen_relabel(gesmc_ctx *ctx, void *stream, uint64_t *d_edges, uint64_t m, uint32_t n,
+                               uint64_t seed);
 
 /* Permutation keys K_i (see above) for i < m, to d_keys (device, m words). */
 gesmc_status gesmc_perm_keys(gesmc_ctx *ctx, void *stream, uint64_t m, uint64_t seed, uint32_t t, uint64_t *d_keys);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgesmc.so")
 OK = 0
 E_INVAL, E_NOT_SIMPLE, E_RANGE, E_NOMEM, E_DEVICE, E_AGAIN, E_CANCELED, E_INTERNAL = -1, -2, -3, -4, -5, -6, -7, -9
 E_ROUNDS = -8
+E_NOT_GRAPHICAL = -10
 OPT_BUCKET_AVG, OPT_SORT_CAP, OPT_FAST_ROUNDS, OPT_PROFILE, OPT_STRATEGY, OPT_PERSIST, OPT_PROFILE_ONLY = (
     1, 2, 3, 4, 5, 6, 7)
 OPT_LEVEL1_BITS = 8
@@ -115,7 +116,8 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_kernel_count", "gesmc_kernel_name", "gesmc_profile_get", "gesmc_profile_reset",
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
            "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
-           "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing", "gesmc_run_class"]
+           "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing", "gesmc_run_class", "gesmc_gen_gnp",
+           "gesmc_gen_pld_degrees", "gesmc_gen_havel_hakimi", "gesmc_gen_relabel"]
 
 _lib = None
 _lock = threading.Lock()
@@ -197,6 +199,15 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_run_class.argtypes = [vp, vp, vp, vp, u64, u32, u64, u32, u32, u32, u32, ctypes.POINTER(Stats),
                                         ctypes.POINTER(StepStats), vp]
         lib.gesmc_run_class.restype = i32
+        f64 = ctypes.c_double
+        lib.gesmc_gen_gnp.argtypes = [vp, vp, u32, f64, u64, vp, u64, ctypes.POINTER(u64)]
+        lib.gesmc_gen_gnp.restype = i32
+        lib.gesmc_gen_pld_degrees.argtypes = [vp, vp, u32, f64, u32, u32, u64, vp, ctypes.POINTER(u64)]
+        lib.gesmc_gen_pld_degrees.restype = i32
+        lib.gesmc_gen_havel_hakimi.argtypes = [vp, vp, u32, vp, vp, u64, ctypes.POINTER(u64)]
+        lib.gesmc_gen_havel_hakimi.restype = i32
+        lib.gesmc_gen_relabel.argtypes = [vp, vp, vp, u64, u32, u64]
+        lib.gesmc_gen_relabel.restype = i32
         _lib = lib
         return lib
 
@@ -277,6 +288,49 @@ class Context:
                                     ctypes.byref(st), ss, None if oc is None else ctypes.c_void_p(oc.data_ptr())))
         return (out, st.as_dict(), [ss[q].as_dict() for q in range(r)] if steps else None,
                 oc[: m // 2] if outcomes else None)
+
+    # ---- input realisation ------------------------------------------------
+    def gen_gnp(self, n: int, p: float, seed: int, stream=None) -> torch.Tensor:
+        """G(n,p) on the device (gesmc_gen_gnp): a count call, then the edges."""
+        m = ctypes.c_uint64(0)
+        _check(_lib.gesmc_gen_gnp(self._h, _stream_ptr(stream), n, float(p), seed & (2**64 - 1), None, 0,
+                                  ctypes.byref(m)))
+        out = torch.empty(max(m.value, 1), dtype=torch.int64, device="cuda:%d" % self.device)
+        _check(_lib.gesmc_gen_gnp(self._h, _stream_ptr(stream), n, float(p), seed & (2**64 - 1),
+                                  ctypes.c_void_p(out.data_ptr()), m.value, ctypes.byref(m)))
+        return out[: m.value]
+
+    def gen_pld_degrees(self, n: int, gamma: float, dmin: int, dmax: int, seed: int, stream=None):
+        """Pld([dmin..dmax], gamma) degrees on the device -> (uint32-valued int32 tensor, sum)."""
+        deg = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:%d" % self.device)
+        s = ctypes.c_uint64(0)
+        _check(_lib.gesmc_gen_pld_degrees(self._h, _stream_ptr(stream), n, float(gamma), dmin, dmax,
+                                          seed & (2**64 - 1), ctypes.c_void_p(deg.data_ptr()), ctypes.byref(s)))
+        return deg[:n], s.value
+
+    def gen_havel_hakimi(self, deg: torch.Tensor, stream=None) -> torch.Tensor:
+        """Havel-Hakimi realisation of a device degree sequence (4-byte ints)."""
+        n = deg.numel()
+        dp = _dev_ptr(deg, 4, n, "deg")
+        m = ctypes.c_uint64(0)
+        _check(_lib.gesmc_gen_havel_hakimi(self._h, _stream_ptr(stream), n, dp, None, 0, ctypes.byref(m)))
+        out = torch.empty(max(m.value, 1), dtype=torch.int64, device=deg.device)
+        _check(_lib.gesmc_gen_havel_hakimi(self._h, _stream_ptr(stream), n, dp, ctypes.c_void_p(out.data_ptr()),
+                                           m.value, ctypes.byref(m)))
+        return out[: m.value]
+
+    def gen_relabel(self, edges: torch.Tensor, n: int, seed: int, stream=None) -> torch.Tensor:
+        """Relabels the vertices of `edges` in place (gesmc_gen_relabel); returns it."""
+        m = edges.numel()
+        _check(_lib.gesmc_gen_relabel(self._h, _stream_ptr(stream), _dev_ptr(edges, 8, m, "edges") if m else None,
+                                      m, n, seed & (2**64 - 1)))
+        return edges
+
+    def gen_powerlaw_graph(self, n: int, gamma: float, dmin: int, dmax: int, seed: int, stream=None):
+        """Degrees, Havel-Hakimi and relabelling, all on the device: the SynPld input."""
+        deg, _ = self.gen_pld_degrees(n, gamma, dmin, dmax, seed, stream)
+        E = self.gen_havel_hakimi(deg, stream)
+        return self.gen_relabel(E, n, seed, stream)
 
     def run_noalloc(self, edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0,
                     out: torch.Tensor | None = None, stream=None):

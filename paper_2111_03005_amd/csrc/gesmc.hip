@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -18,6 +19,7 @@
 #include "batch_kernels.h"
 #include "es_kernels.h"
 #include "mixing_kernels.h"
+#include "gen_kernels.h"
 
 using namespace gesmc;
 
@@ -82,6 +84,8 @@ enum KernelId {
     KID_ES_CHAIN,
     KID_MIX,
     KID_DECIDE_LOCAL,
+    KID_GEN,
+    KID_GEN_HH_STEPS,
     KID_COUNT
 };
 
@@ -92,7 +96,8 @@ const char *kKernelNames[KID_COUNT] = {
     "k_emit",         "k_tcounts1",     "k_tscatter1",  "k_tcounts2",      "k_tscatter2",   "k_resolve",
     "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
     "k_small_chain_compact",
-    "k_es_build",     "k_es_chain",     "k_mixing",     "k_decide_local"};
+    "k_es_build",     "k_es_chain",     "k_mixing",     "k_decide_local", "k_gen",
+    "k_hh_steps"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -2331,3 +2336,4 @@ gesmc_status gesmc_profile_reset(gesmc_ctx *c) {
 #include "server_runtime.h"
 #include "es_runtime.h"
 #include "mixing_runtime.h"
+#include "gen_runtime.h"
