@@ -416,6 +416,10 @@ def bench_plain(gesmc, torch, args, workload: str, steps: int, warmup: int, host
     ctx.set_option(gesmc.OPT_PROFILE, 0)
     ctx.set_option(gesmc.OPT_PROFILE_ONLY, -1)
     prof = ctx.profile()
+    # per-superstep records of one more call (outside the timed region): the
+    # exact slow paths taken (partitions over the LDS capacity) and the rounds
+    _, _, step_recs = ctx.run(d_in, n, args.seed, 0, r, 0, out=d_out, stream=stream, steps=True)
+    torch.cuda.synchronize()
 
     value = steps * r * ell / wall
     a = stats["legal"] / max(stats["attempts"], 1)
@@ -451,6 +455,8 @@ def bench_plain(gesmc, torch, args, workload: str, steps: int, warmup: int, host
            "legal_fraction": round(a, 5), "rounds_max": stats["rounds_max"],
            "tuple_bytes": int(stats["tuple_bytes"]), "timed_kernel_events": dominant,
            "kernel_share_warmup": {k: round(v[0] / warm_total, 3) for k, v in warm_prof.items()} if warm_total else None,
+           "fallback_buckets_per_superstep": round(sum(q["fallback_buckets"] for q in step_recs) / max(r, 1), 2),
+           "rounds_mean": round(sum(q["rounds"] for q in step_recs) / max(r, 1), 2),
            "roofline": roofline, "superstep_traffic": step_traffic,
            "switch_roofline": switch_roofline(value, a, measured_G())}
     if host_api:
@@ -552,6 +558,105 @@ def bench_mixing(gesmc, torch, args):
     return rec
 
 
+def bench_generation(gesmc, torch, args):
+    """Input realisation on the device (Sec. 6's synthetic families): G(n,p)
+    at n = 2^22, p = 32/(n-1) (the G(n,p) benchmark input), and the power-law
+    pipeline -- degrees, Havel-Hakimi, relabelling -- at n = 2^20, gamma =
+    2.5, degrees in [5..1024]; beside the oracle's definitions on the CPU."""
+    ctx = gesmc.Context(0)
+    n, p, seed = 1 << 22, 32.0 / ((1 << 22) - 1), 3
+    E = ctx.gen_gnp(n, p, seed)  # warm-up; sizes the output
+    out = torch.empty(E.numel() + 1024, dtype=torch.int64, device="cuda")
+    del E
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        E = ctx.gen_gnp(n, p, seed, out=out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    m = E.numel()
+    dt = float(np.median(times))
+    rec = {"gnp": {"workload": "G(n=2^22, p=32/(2^22-1)), seed 3", "m": m, "ms": round(1e3 * dt, 3),
+                   "edges_per_s": round(m / dt, 1), "written_GBs": round(8 * m / dt / 1e9, 1),
+                   "note": "counting pass, scan and writing pass; Philox and a portable ln per draw"}}
+    del out, E
+    pn, gamma, dmin, dmax, pseed = 1 << 20, 2.5, 5, 1024, 2
+    ctx.gen_powerlaw_graph(pn, gamma, dmin, dmax, pseed)  # warm-up
+    torch.cuda.synchronize()
+    ph = {}
+    t = time.perf_counter()
+    deg, _ = ctx.gen_pld_degrees(pn, gamma, dmin, dmax, pseed)
+    torch.cuda.synchronize()
+    ph["degrees_ms"] = 1e3 * (time.perf_counter() - t)
+    ctx.set_option(gesmc.OPT_PROFILE, 1)
+    ctx.profile_reset()
+    t = time.perf_counter()
+    H = ctx.gen_havel_hakimi(deg)
+    torch.cuda.synchronize()
+    ph["havel_hakimi_ms"] = 1e3 * (time.perf_counter() - t)
+    prof = ctx.profile()
+    ctx.set_option(gesmc.OPT_PROFILE, 0)
+    t = time.perf_counter()
+    ctx.gen_relabel(H, pn, pseed)
+    torch.cuda.synchronize()
+    ph["relabel_ms"] = 1e3 * (time.perf_counter() - t)
+    pm = H.numel()
+    total = sum(ph.values())
+    rec["powerlaw"] = {"workload": "Pld([5..1024], 2.5) on n=2^20, Havel-Hakimi, relabelled, seed 2", "m": pm,
+                       **{k: round(v, 3) for k, v in ph.items()}, "ms": round(total, 3),
+                       "edges_per_s": round(pm / total * 1e3, 1),
+                       "hh_steps_kernel_ms": round(prof.get("k_hh_steps", (0.0,))[0], 3)}
+    del H, deg
+    ctx.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle._load()
+        t = time.perf_counter()
+        Eo = oracle.gen_gnp(1 << 20, 32.0 / ((1 << 20) - 1), seed)
+        dg = time.perf_counter() - t
+        t = time.perf_counter()
+        d0 = oracle.gen_pld(pn, gamma, dmin, dmax, pseed)[0]
+        Ho = oracle.gen_havel_hakimi(d0)
+        oracle.gen_relabel(Ho, pn, pseed)
+        dp = time.perf_counter() - t
+        rec["cpu_baseline"] = {"gnp_edges_per_s": round(len(Eo) / dg, 1), "powerlaw_edges_per_s": round(len(Ho) / dp, 1),
+                               "cores": 1, "kind": "oracle",
+                               "sample": "G(n=2^20, p=32/(2^20-1)) (%.1f s); the whole power-law pipeline (%.1f s)"
+                                         % (dg, dp)}
+    print("generation: %s" % rec, file=sys.stderr)
+    return rec
+
+
+def bench_classes(gesmc, torch, args):
+    """G-ES-MC on other graph classes (Sec. 1): random graphs with n = 2^20
+    and m = 2^22 of the classes with loops, directed, and with loops and
+    multi-edges, 5 supersteps per call with the input resident in HBM."""
+    import graphgen
+    ctx = gesmc.Context(0)
+    n, m, r = 1 << 20, 1 << 22, 5
+    rec = {"workload": "class_graph(n=2^20, m=2^22), 5 supersteps per call", "n": n, "m": m}
+    for cls, name in ((1, "loops"), (4, "directed"), (3, "loops_multi")):
+        E = graphgen.class_graph(n, m, cls, 60 + cls)
+        d_in = torch.from_numpy(E.view(np.int64).copy()).to("cuda")
+        d_out = torch.empty_like(d_in)
+        ctx.run_class(d_in, n, args.seed, cls, r=r, out=d_out)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        steps = 3
+        st = None
+        for _ in range(steps):
+            _, st, _, _ = ctx.run_class(d_in, n, args.seed, cls, r=r, out=d_out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rec[name] = {"cls": cls, "value": round(steps * r * (m // 2) / dt, 1), "unit": "attempts/s",
+                     "legal_fraction": round(st["legal"] / max(st["attempts"], 1), 5)}
+        del d_in, d_out
+    ctx.close()
+    print("classes: %s" % rec, file=sys.stderr)
+    return rec
+
+
 def gather_calibration(mib: int, count: int):
     """Isolated random 8-byte reads: index_select of `count` random int64
     words from a `mib` MiB buffer, three times.  Under rocprofv3's read
@@ -578,7 +683,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gnp_n2^22_d32", help="the headline workload (plain form)")
-    ap.add_argument("--extra-workloads", nargs="*", default=["pld_n2^20_g2.5", "gnp_n1024_d10"],
+    ap.add_argument("--extra-workloads", nargs="*", default=["pld_n2^20_g2.5", "gnp_n1024_d10", "pld_n2^20_g2.01"],
                     help="further plain workloads reported under plain_<name>")
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -600,6 +705,8 @@ def main():
     ap.add_argument("--no-mixing", action="store_true", help="skip the mixing diagnostic")
     ap.add_argument("--mixing-supersteps", type=int, default=400)
     ap.add_argument("--es-steps", type=int, default=3)
+    ap.add_argument("--no-generation", action="store_true", help="skip the input realisation on the device")
+    ap.add_argument("--no-classes", action="store_true", help="skip the graph classes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for HBM counters")
     ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
@@ -650,6 +757,8 @@ def main():
 
     es = None if args.no_es else bench_es(gesmc, torch, args)
     mix = None if args.no_mixing else bench_mixing(gesmc, torch, args)
+    gen = None if args.no_generation else bench_generation(gesmc, torch, args)
+    classes = None if args.no_classes else bench_classes(gesmc, torch, args)
     batched = None if args.no_batched else bench_batched(gesmc, torch, args, head["value"])
     served = None if args.no_served else bench_served(gesmc, torch, args)
 
@@ -683,6 +792,8 @@ def main():
     out.update(extra)
     out["es_pares"] = es
     out["mixing"] = mix
+    out["generation"] = gen
+    out["classes"] = classes
     out["batched"] = batched
     out["served"] = served
     print(json.dumps(out))

@@ -247,8 +247,17 @@ def workload_batch_4096():
     return batch_graphs(4096, 4, 1e2, 1e5)
 
 
+def workload_powerlaw_hubs():
+    """Pld([1..n^(1/(gamma-1))], 2.01) on n=2^20 (SynPld's degree range at
+    gamma near 2: hubs adjacent to half the vertices), Havel-Hakimi, ids
+    shuffled; generator seed 11."""
+    n, gamma = 1 << 20, 2.01
+    return powerlaw_graph(n, gamma, 1, int(n ** (1.0 / (gamma - 1.0))), 11), n
+
+
 WORKLOADS = {
     "gnp_n1024_d10": (workload_gnp_small, 10),
     "pld_n2^20_g2.5": (workload_powerlaw_1m, 20),
     "gnp_n2^22_d32": (workload_gnp_large, 10),
+    "pld_n2^20_g2.01": (workload_powerlaw_hubs, 10),
 }

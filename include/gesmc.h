@@ -506,6 +506,10 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                      batched); the LDS small-graph kernels do not count against it,
                                      and a context serving a gesmc_server must keep it 0.  The only
                                      option that can change a call's outcome                        */
+#define GESMC_OPT_UNPERMUTE_BUCKETS 14 /* 1 (default): from 2^20 edges on, the final write-back to input
+                                          order first gathers the records into buckets of consecutive
+                                          indices, then writes each bucket's window of d_out XCD by XCD
+                                          (whole lines reach HBM); 0: one scattered write per edge   */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

@@ -27,6 +27,7 @@ OPT_GRAPH = 10
 OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
 OPT_ROUND_LIMIT = 13
+OPT_UNPERMUTE_BUCKETS = 14
 CHAIN_GLOBAL, CHAIN_ES = 0, 1
 CLASS_LOOPS, CLASS_MULTI, CLASS_DIRECTED = 1, 2, 4
 NOALLOC_MAX_EDGES = 2000000
@@ -290,12 +291,18 @@ class Context:
                 oc[: m // 2] if outcomes else None)
 
     # ---- input realisation ------------------------------------------------
-    def gen_gnp(self, n: int, p: float, seed: int, stream=None) -> torch.Tensor:
-        """G(n,p) on the device (gesmc_gen_gnp): a count call, then the edges."""
+    def gen_gnp(self, n: int, p: float, seed: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """G(n,p) on the device (gesmc_gen_gnp) into `out` (int64, its size the
+        capacity), or into a new tensor sized by a count call first."""
         m = ctypes.c_uint64(0)
-        _check(_lib.gesmc_gen_gnp(self._h, _stream_ptr(stream), n, float(p), seed & (2**64 - 1), None, 0,
-                                  ctypes.byref(m)))
-        out = torch.empty(max(m.value, 1), dtype=torch.int64, device="cuda:%d" % self.device)
+        if out is None:
+            _check(_lib.gesmc_gen_gnp(self._h, _stream_ptr(stream), n, float(p), seed & (2**64 - 1), None, 0,
+                                      ctypes.byref(m)))
+            out = torch.empty(max(m.value, 1), dtype=torch.int64, device="cuda:%d" % self.device)
+            m.value = out.numel() if m.value else 0
+        else:
+            m.value = out.numel()
+            _dev_ptr(out, 8, 0, "out")
         _check(_lib.gesmc_gen_gnp(self._h, _stream_ptr(stream), n, float(p), seed & (2**64 - 1),
                                   ctypes.c_void_p(out.data_ptr()), m.value, ctypes.byref(m)))
         return out[: m.value]

@@ -514,12 +514,13 @@ __global__ __launch_bounds__(64) void k_hh_steps(const uint32_t *__restrict__ E0
                 fail = 1;
                 break;
             }
-            const uint32_t ex1 = x < 64 ? (uint32_t)__shfl(e, x, 64) : 0u;  // E[x + 1]
-            const uint32_t b = (uint32_t)__shfl(e, x - 1, 64);              // E[x]
+            // x and d are uniform: single-lane reads; E[x + 1] is lane x's
+            const uint32_t ex1 = x < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)e, (int)x) : 0u;
+            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)e, (int)(x - 1));  // E[x]
             const uint32_t a = max(ex1, s + 1), k = s + d + 1 - a;
-            // every lane takes part in the shuffle (a lane left out of it
-            // hands its neighbour no value), then lane 63 drops E[65]
-            const uint32_t down = (uint32_t)__shfl_down(e, 1, 64);
+            // E[y + 1] from the next lane: DPP wave_shl:1 (lane i reads lane
+            // i + 1; every lane active), lane 63 takes E[65] = empty
+            const uint32_t down = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)e, 0x130, 0xF, 0xF, false);
             const uint32_t nxt = lane < 63 ? down : 0u;
             const uint32_t y = lane + 1;
             if (y > x && y <= d)

@@ -189,6 +189,7 @@ struct gesmc_ctx {
     uint64_t chunk_cap = 0;
     uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
     bool small_graphs = true;                         // graphs with m <= kSmallMax run in LDS
+    bool unpermute_buckets = true;                    // large write-backs by index buckets
     bool pack_tuples = true;                          // 8-byte tuple words where the bits allow
     uint32_t tuple_bytes = 0;                         // tuple size of the call's last superstep
     StepCounters *ctr = nullptr;
@@ -467,7 +468,8 @@ void set_scatter_lds_limits_one() {
                           (const void *)k_scatter<kSrcEmit, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcHashed, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcEmitPacked, kTile, scatter_threads(kTile), kOne>,
-                          (const void *)k_scatter<kSrcPacked, kTile, scatter_threads(kTile), kOne>})
+                          (const void *)k_scatter<kSrcPacked, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcIdx, kTile, scatter_threads(kTile), kOne>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)scatter_lds_bytes(kMaxLevelBits, kTile));
 }
@@ -836,19 +838,19 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
                                     fused ? &eo : nullptr));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
-                     (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
+                     c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
                      (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->bslot + ge,
                      c->ctr_step, cls));
     const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
     int j = 0;
     for (; j < c->fast_rounds; ++j) {
         GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN, 0, k_decide_chain, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
-                         (const uint2 *)c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
+                         c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
                          (const uint32_t *)&c->ucount[j % 3], c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3],
                          &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step, cls));
     }
     GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
-                     (const uint2 *)c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
+                     c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
                      c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3], (const uint4 *)c->bslot, ge + gd,
                      c->ctr_step, c->err, c->round_limit, cls));
     if (bs && bs->acc)
@@ -901,6 +903,40 @@ gesmc_status superstep(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, u
                      c->sw_slot, c->st, c->idx[0], c->key[0], c->ulist[cur], &c->ucount[cur], c->ulist[1 - cur],
                      &c->ucount[1 - cur], c->ctr_step, c->err));
     return GESMC_OK;
+}
+
+// Writes the state records of buffer 0 (idx, key) to out[idx].  From
+// 2^20 records on, a one-level distribution by the index's top bits
+// (kSrcIdx, buffer 0 -> 1) first gathers consecutive indices into buckets
+// of at most 2^17 records, which k_unpermute_buckets writes back XCD by XCD.
+constexpr uint32_t kUnpermuteBuckets = 1u << 20;  // records from which the buckets pay
+gesmc_status unpermute(gesmc_ctx *c, hipStream_t s, uint32_t m, unsigned long long *out) {
+    if (m < kUnpermuteBuckets || !c->unpermute_buckets || alloc_forbidden()) {
+        return launch(c, s, KID_UNPERMUTE, m, k_unpermute, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
+                      c->idx[0], c->key[0], m, out, c->err);
+    }
+    const int W = width_below(m);  // every index < 2^W
+    Plan p;
+    p.m = m;
+    p.ell = m / 2;
+    p.bbits = (uint32_t)std::min<int>((int)kMaxCoarseBits, std::max(1, W - 17));
+    p.b1 = p.bbits;
+    p.b2 = 0;
+    p.ncoarse = p.nfine = 1u << p.bbits;
+    p.tile = tile_for(m);
+    p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, p.tile));
+    SrcArgs sa{};
+    sa.ishift = 64u - (uint32_t)W;
+    int dist = 0;
+    const uint32_t *boff = nullptr;
+    uint32_t nb = 0;
+    GESMC_TRY((radix_distribute<kSrcIdx, kSrcIdx>(c, s, p, m, 0u, 0u, 0u, c->idx, c->key, 0, 1, 1, &dist, &boff, &nb,
+                                                  KID_UNPERMUTE, KID_UNPERMUTE, KID_UNPERMUTE, KID_UNPERMUTE, sa,
+                                                  SrcArgs{})));
+    const uint32_t per_xcd = std::max<uint32_t>(1, c->num_cus / 8) * 4;
+    return launch(c, s, KID_UNPERMUTE, m, k_unpermute_buckets, dim3(8 * per_xcd), dim3(kBlock), 0,
+                  (const uint32_t *)c->idx[dist], (const unsigned long long *)c->key[dist], boff, nb, m, out,
+                  (const uint32_t *)c->err);
 }
 
 gesmc_status check_hip(hipError_t e, const char *what) {
@@ -1067,8 +1103,7 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_copy_bytes, dim3(grid_stride_blocks(c, p.ell)), dim3(kBlock), 0,
                          (const uint8_t *)c->st, d_outcome, (uint64_t)p.ell));
     if (m > 0)
-        GESMC_TRY(launch(c, s, KID_UNPERMUTE, m, k_unpermute, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
-                         c->idx[0], c->key[0], m, (unsigned long long *)d_out, c->err));
+        GESMC_TRY(unpermute(c, s, m, (unsigned long long *)d_out));
     GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     if (r > 0)
@@ -2257,6 +2292,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
         case GESMC_OPT_SMALL_GRAPHS:
             if (v < 0 || v > 1) break;
             c->small_graphs = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_UNPERMUTE_BUCKETS:
+            if (v < 0 || v > 1) break;
+            c->unpermute_buckets = v != 0;
             return GESMC_OK;
         case GESMC_OPT_PACK_TUPLES:
             if (v < 0 || v > 1) break;

@@ -156,6 +156,8 @@ __device__ __forceinline__ uint32_t tile_segment(const uint32_t *tile_first, uin
 // B bits of the radix word, so both levels use the same shifts.
 // kSrcEmitPacked is kSrcEmit writing packed 8-byte tuple words (TuplePack)
 // and kSrcPacked the second level over them: no tag array is read or written.
+// kSrcIdx sorts records by their own index (idx << ishift puts its top bits
+// on top): the buckets of the final write-back to input order.
 enum RadixSrc : int {
     kSrcPerm = 0,
     kSrcHash = 1,
@@ -164,7 +166,8 @@ enum RadixSrc : int {
     kSrcEmit = 4,
     kSrcHashed = 5,
     kSrcEmitPacked = 6,
-    kSrcPacked = 7
+    kSrcPacked = 7,
+    kSrcIdx = 8
 };
 
 struct SrcArgs {
@@ -179,10 +182,13 @@ struct SrcArgs {
     uint32_t pl;             // P_L threshold (batch: nonzero if some graph has one)
     TuplePack pk;            // kSrcEmitPacked: hash width, offset and tag code bits
     uint32_t cls;            // graph class (CLS_* bits; multi-edge classes never come here)
+    uint32_t ishift;         // kSrcIdx: 64 - (bits of the largest index)
 };
 
 template <int kSrc>
-__device__ __forceinline__ constexpr bool src_reads_idx() { return kSrc == kSrcPerm || kSrc == kSrcBatch; }
+__device__ __forceinline__ constexpr bool src_reads_idx() {
+    return kSrc == kSrcPerm || kSrc == kSrcBatch || kSrc == kSrcIdx;
+}
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcBatch || kSrc == kSrcBucket; }
 // Tuple sources whose slots may be empty (kEmptyKey); the second level over
@@ -321,6 +327,7 @@ __device__ __forceinline__ uint64_t radix_word(uint32_t idx, unsigned long long 
                                                uint32_t k0, uint32_t k1, const SrcArgs &ba, uint32_t *bucket) {
     if (src_is_tuple<kSrc>() || kSrc == kSrcPacked) return key;  // tuple hashes or packed words (see the loads)
     if (kSrc == kSrcPerm) return perm_key(idx, t, k0, k1);
+    if (kSrc == kSrcIdx) return (uint64_t)idx << ba.ishift;
     uint32_t b = aux;
     if (kSrc == kSrcBatch) {
         const BatchGraph &g = ba.gr[aux];

@@ -34,6 +34,7 @@ namespace gesmc {
 
 // per-target record: x = eraser (kNoEraser / kStays / switch), y = predecessor (k' << 1 | h') or kNoPred
 constexpr uint32_t kNoPred = 0xFFFFFFFFu;
+constexpr uint32_t kWalked = 0xFFFFFFFEu;  // a resumed walk that reached the chain's end
 constexpr uint32_t kListEnd = 0xFFFFu;  // end of a cell list in k_resolve (slots are < 2^16)
 #ifndef GESMC_RESOLVE_LISTS
 #define GESMC_RESOLVE_LISTS 1
@@ -566,7 +567,15 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
 // ---------------------------------------------------------------------------
 // Decisions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int judge_target_chain(const uint2 *info, uint2 rec, uint32_t k, const uint8_t *st) {
+// Two shortcuts keep long chains (many switches inserting one hub edge)
+// linear: inserters older than the target's eraser saw the target present,
+// so they were rejected and the walk stops there; and a walk that passed
+// decided-rejected inserters stores the first one it stopped at in its own
+// record's predecessor link (`self`), so later walks through this switch
+// skip them.  Any value so written skips only decided-rejected inserters of
+// the same target, so concurrent writers are harmless.
+__device__ __forceinline__ int judge_target_chain(uint2 *info, uint2 rec, uint32_t self, uint32_t k,
+                                                  const uint8_t *st) {
     int v = V_OK;
     const uint32_t e = rec.x;
     if (e != kNoEraser) {
@@ -580,25 +589,87 @@ __device__ __forceinline__ int judge_target_chain(const uint2 *info, uint2 rec, 
     // earlier inserters of the same target, nearest first; switch ids strictly
     // decrease along the chain (checked, so a corrupt record cannot loop)
     uint32_t p = rec.y, below = k;
+    int out = v;
     while (p != kNoPred) {
         const uint32_t pk = p >> 1;
         if (pk >= below) return V_ILLEGAL;
+        if (e != kNoEraser && pk < e) {  // inserted while the target was still there
+            p = kNoPred;
+            break;
+        }
         const uint8_t sp = load_status(st, pk);
-        if (sp == ST_LEGAL) return V_ILLEGAL;
-        if (sp == ST_UNDECIDED) return V_WAIT;
+        if (sp == ST_LEGAL) {
+            out = V_ILLEGAL;
+            break;
+        }
+        if (sp == ST_UNDECIDED) {
+            out = V_WAIT;
+            break;
+        }
         below = pk;
         p = info[p].y;
     }
-    return v;
+    if (p != rec.y) info[self].y = p;
+    return out;
+}
+
+// judge_target_chain that resumes its predecessor walk at *from (kNoPred:
+// the first predecessor, rec.y) and leaves there the predecessor it waits
+// for: decided predecessors never change, so a repeated judgement of the
+// same switch walks each link once.
+__device__ __forceinline__ int judge_target_resume(uint2 *info, uint2 rec, uint32_t self, uint32_t k,
+                                                   const uint8_t *st, uint32_t *from) {
+    int v = V_OK;
+    const uint32_t e = rec.x;
+    if (e != kNoEraser) {
+        if (e == kStays || e >= k) return V_ILLEGAL;
+        const uint8_t se = load_status(st, e);
+        if (se == ST_UNDECIDED)
+            v = V_WAIT;
+        else if (se != ST_LEGAL)
+            return V_ILLEGAL;
+    }
+    // *from: kNoPred (not started), kWalked (nothing left) or a predecessor
+    uint32_t p = rec.y, below = k;
+    if (*from == kWalked) {
+        p = kNoPred;
+    } else if (*from != kNoPred) {
+        p = *from;
+        below = (p >> 1) + 1;
+    }
+    const uint32_t p0 = p;
+    int out = v;
+    while (p != kNoPred) {
+        const uint32_t pk = p >> 1;
+        if (pk >= below) return V_ILLEGAL;
+        if (e != kNoEraser && pk < e) {  // inserted while the target was still there
+            p = kNoPred;
+            break;
+        }
+        const uint8_t sp = load_status(st, pk);
+        if (sp == ST_LEGAL) {
+            out = V_ILLEGAL;
+            break;
+        }
+        if (sp == ST_UNDECIDED) {
+            out = V_WAIT;
+            break;
+        }
+        below = pk;
+        p = info[p].y;
+    }
+    if (p != p0) info[self].y = p;  // the shortcut of judge_target_chain
+    *from = p == kNoPred ? kWalked : p;
+    return out;
 }
 
 // Decides switch k from its two target records; the pair's records (ij, ee)
 // are passed in so that callers can issue every load of the switch at once.
-__device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint2 ij, ulonglong2 ee, const uint2 *info,
+__device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint2 ij, ulonglong2 ee, uint2 *info,
                                                     uint8_t *st, uint32_t *out_idx, unsigned long long *out_key,
                                                     BlockCounts *bc, uint32_t cls) {
-    const int v = max(judge_target_chain(info, make_uint2(recs.x, recs.y), k, st),
-                      judge_target_chain(info, make_uint2(recs.z, recs.w), k, st));
+    const int v = max(judge_target_chain(info, make_uint2(recs.x, recs.y), 2 * k, k, st),
+                      judge_target_chain(info, make_uint2(recs.z, recs.w), 2 * k + 1, k, st));
     if (v == V_WAIT) return true;
     reinterpret_cast<uint2 *>(out_idx)[k] = ij;
     if (v == V_OK) {
@@ -617,7 +688,7 @@ __device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint
 // Round 1 (list == nullptr: every switch) or a later round over a list.
 __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restrict__ s_idx,
                                                          const unsigned long long *__restrict__ s_key, uint32_t ell,
-                                                         const uint2 *__restrict__ info, uint8_t *st,
+                                                         uint2 *info, uint8_t *st,
                                                          uint32_t *__restrict__ out_idx,
                                                          unsigned long long *__restrict__ out_key,
                                                          const uint32_t *__restrict__ list,
@@ -659,10 +730,20 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
 }
 
 // Remaining rounds in one workgroup; the next round's list counter is cleared
-// by the round that fills it.
+// by the round that fills it.  After kSweepAfter rounds with switches still
+// undecided (long dependency chains: hub edges that many switches erase and
+// insert), the rest is decided by a sweep in ascending switch id: a switch
+// depends on smaller ids only, so chunks of kSweepChunk ids are taken in
+// order, each repeated until it holds no undecided switch; earlier chunks
+// are then final and only chains inside a chunk cost repeats.  Each repeat
+// counts as a round.
+constexpr uint32_t kSweepAfter = 8;
+constexpr uint32_t kSweepChunk = 1024;
+constexpr uint32_t kSweepWords = 16384;  // chunk marks: ids below 2^29 (m < 2^30)
+
 __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *__restrict__ s_idx,
                                                                const unsigned long long *__restrict__ s_key,
-                                                               uint32_t ell, const uint2 *__restrict__ info,
+                                                               uint32_t ell, uint2 *info,
                                                                uint8_t *st, uint32_t *__restrict__ out_idx,
                                                                unsigned long long *__restrict__ out_key,
                                                                uint32_t *list_a, uint32_t *count_a, uint32_t *list_b,
@@ -710,7 +791,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
     }
     uint32_t *cur = list_a, *nxt = list_b, *ccur = count_a, *cnxt = count_b;
     uint32_t n = s_n;
-    while (n > 0) {
+    for (uint32_t here = 0; n > 0 && here < kSweepAfter; ++here) {
         if (tid == 0) *cnxt = 0;
         __threadfence();
         __syncthreads();
@@ -749,6 +830,89 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chain(const uint32_t *_
         uint32_t *tc = ccur;
         ccur = cnxt;
         cnxt = tc;
+    }
+    if (n > 0) {
+        __shared__ uint32_t s_chunks[kSweepWords];
+        __shared__ uint32_t s_wait, s_done, s_stop;
+        __shared__ unsigned long long s_rounds;
+        const uint32_t nwords = ((ell + kSweepChunk - 1) / kSweepChunk + 31) / 32;
+        for (uint32_t w = tid; w < nwords; w += kFinishBlock) s_chunks[w] = 0;
+        if (tid == 0) {
+            s_rounds = atomicAdd(&ctr->rounds, 0ull);
+            s_stop = 0;
+        }
+        __syncthreads();
+        for (uint32_t q = tid; q < n; q += kFinishBlock) {
+            const uint32_t k = cur[q];
+            if (k < ell) atomicOr(&s_chunks[(k / kSweepChunk) >> 5], 1u << ((k / kSweepChunk) & 31));
+        }
+        __syncthreads();
+        unsigned long long added = 0;
+        for (uint32_t w = 0; w < nwords && !s_stop; ++w) {
+            uint32_t bits = s_chunks[w];
+            while (bits && !s_stop) {
+                const uint32_t c = w * 32 + (uint32_t)(__ffs(bits) - 1);
+                bits &= bits - 1;
+                const uint32_t kb = c * kSweepChunk, ke = min(kb + kSweepChunk, ell);
+                constexpr uint32_t kPer = kSweepChunk / kFinishBlock;
+                uint2 from[kPer];  // resume points of the two predecessor walks
+#pragma unroll
+                for (uint32_t j = 0; j < kPer; ++j) from[j] = make_uint2(kNoPred, kNoPred);
+                for (;;) {
+                    if (tid == 0) {
+                        s_wait = 0;
+                        s_done = 0;
+                    }
+                    __syncthreads();
+                    uint32_t waits = 0, dones = 0;
+#pragma unroll
+                    for (uint32_t j = 0; j < kPer; ++j) {
+                        const uint32_t k = kb + tid + j * kFinishBlock;
+                        if (k >= ke || load_status(st, k) != ST_UNDECIDED) continue;
+                        const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
+                        const int v =
+                            max(judge_target_resume(info, make_uint2(recs.x, recs.y), 2 * k, k, st, &from[j].x),
+                                judge_target_resume(info, make_uint2(recs.z, recs.w), 2 * k + 1, k, st, &from[j].y));
+                        if (v == V_WAIT) {
+                            ++waits;
+                            continue;
+                        }
+                        ++dones;
+                        const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+                        const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+                        reinterpret_cast<uint2 *>(out_idx)[k] = ij;
+                        if (v == V_OK) {
+                            const Targets T = switch_targets_cls(ee.x, ee.y, ij.x < ij.y, cls);
+                            reinterpret_cast<ulonglong2 *>(out_key)[k] = make_ulonglong2(T.A, T.B);
+                            st[k] = ST_LEGAL;
+                            atomicAdd(&bc.legal, 1u);
+                        } else {
+                            reinterpret_cast<ulonglong2 *>(out_key)[k] = ee;
+                            st[k] = ST_EXISTS;
+                            atomicAdd(&bc.exists, 1u);
+                        }
+                    }
+                    if (waits) atomicAdd(&s_wait, waits);
+                    if (dones) atomicAdd(&s_done, dones);
+                    __syncthreads();
+                    const uint32_t W = s_wait, D = s_done;
+                    if (tid == 0) {
+                        ++added;
+                        // the smallest undecided switch of the chunk always decides
+                        if (W > 0 && D == 0) {
+                            atomicOr(err, ERR_INTERNAL);
+                            s_stop = 1;
+                        } else if (W > 0 && round_limit && s_rounds + added >= round_limit) {
+                            atomicOr(err, ERR_ROUNDS);
+                            s_stop = 1;
+                        }
+                    }
+                    __syncthreads();
+                    if (W == 0 || s_stop) break;
+                }
+            }
+        }
+        if (tid == 0 && added) atomicAdd(&ctr->rounds, added);
     }
     flush_counts(&bc, ctr);
 }

@@ -441,6 +441,30 @@ __global__ __launch_bounds__(kBlock) void k_unpermute(const uint32_t *__restrict
     }
 }
 
+// The write-back of large states after their records were distributed into
+// buckets of consecutive input indices (bucket b = records [boff[b],
+// boff[b+1]), indices below 2^20 apart): workgroup w runs on XCD w % 8 and
+// the workgroups of one XCD take its buckets b = x, x + 8, ... together, so
+// each bucket's window of `out` (at most 8 MB, 1 MB at 2^26 edges) fills in
+// that XCD's L2 and reaches HBM as whole lines.  The grid is a multiple of
+// 8.  Skipped entirely if an error flag is set (output untouched).
+__global__ __launch_bounds__(kBlock) void k_unpermute_buckets(const uint32_t *__restrict__ idx,
+                                                              const unsigned long long *__restrict__ key,
+                                                              const uint32_t *__restrict__ boff, uint32_t nb,
+                                                              uint32_t m, unsigned long long *__restrict__ out,
+                                                              const uint32_t *__restrict__ err) {
+    if (*err) return;
+    constexpr uint32_t kXcd = 8;
+    const uint32_t x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, per = gridDim.x / kXcd;
+    for (uint32_t b = x; b < nb; b += kXcd) {
+        const uint32_t lo = boff[b], hi = boff[b + 1];
+        for (uint32_t r = lo + j * kBlock + threadIdx.x; r < hi; r += per * kBlock) {
+            const uint32_t i = idx[r];
+            if (i < m) out[i] = key[r];
+        }
+    }
+}
+
 // pi[r] = index of sorted record r (building block exposed for checks).
 __global__ __launch_bounds__(kBlock) void k_extract_pi(const uint32_t *__restrict__ idx, uint32_t m,
                                                        uint32_t *__restrict__ pi) {

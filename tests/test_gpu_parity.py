@@ -325,6 +325,24 @@ def test_resume_equals_single_call(ctx):
     assert torch.equal(a, b2)
 
 
+def test_unpermute_buckets_exact(ctx):
+    """From 2^20 edges on, the write-back to input order goes through index
+    buckets; sizes around the switch-over, an odd count and several bucket
+    widths, against the oracle and against the one-pass write-back."""
+    import paper_2111_03005_amd as gesmc
+    for q, (n, m) in enumerate([(300000, (1 << 20) - 1), (300000, 1 << 20), (400000, (1 << 20) + 4097),
+                                (1 << 21, 3000001)]):
+        E = graphgen.class_graph(n, m, 0, 900 + q)
+        check_run(ctx, E, n, 13 + q, q, 1, label="unpermute buckets m=%d" % m)
+        ctx.set_option(gesmc.OPT_UNPERMUTE_BUCKETS, 0)
+        try:
+            one, _ = ctx.run(to_dev(E), n, 13 + q, t0=q, r=1)
+        finally:
+            ctx.set_option(gesmc.OPT_UNPERMUTE_BUCKETS, 1)
+        two, _ = ctx.run(to_dev(E), n, 13 + q, t0=q, r=1)
+        assert torch.equal(one, two)
+
+
 def test_repeat_determinism(ctx):
     E = graphgen.powerlaw_graph(100000, 2.3, 2, 316, 4)
     outs = [to_host(ctx.run(to_dev(E), 100000, 8, r=3)[0]) for _ in range(3)]
@@ -338,6 +356,20 @@ def test_repeat_determinism(ctx):
 def test_full_powerlaw_n2p20_20_supersteps(ctx):
     E, n = graphgen.workload_powerlaw_1m()
     st, steps = check_run(ctx, E, n, 42, 0, 20, label="pld_n2^20_g2.5")
+    print("rounds per superstep:", [s["rounds"] for s in steps], flush=True)
+
+
+def test_hub_heavy_powerlaw_exact(ctx):
+    """gamma = 2.01 with degrees up to n^(1/(gamma-1)): hubs adjacent to a
+    large share of the vertices make dependency chains hundreds of rounds
+    long, which the finisher's in-order sweep decides.  Exact against the
+    oracle, also at n = 2^20 (the hub benchmark workload)."""
+    for n, seed in [(20000, 3), (100000, 4)]:
+        E = graphgen.powerlaw_graph(n, 2.01, 1, int(n ** (1 / 1.01)), seed)
+        st, steps = check_run(ctx, E, n, 7 + seed, 0, 3, label="hubs n=%d" % n)
+        print("rounds per superstep:", [s["rounds"] for s in steps], flush=True)
+    E, n = graphgen.workload_powerlaw_hubs()
+    st, steps = check_run(ctx, E, n, 42, 0, 2, label="pld_n2^20_g2.01")
     print("rounds per superstep:", [s["rounds"] for s in steps], flush=True)
 
 
