@@ -508,8 +508,8 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                      option that can change a call's outcome                        */
 #define GESMC_OPT_UNPERMUTE_BUCKETS 14 /* 1 (default): from 2^20 edges on, the final write-back to input
                                           order first gathers the records into buckets of consecutive
-                                          indices, then writes each bucket's window of d_out XCD by XCD
-                                          (whole lines reach HBM); 0: one scattered write per edge   */
+                                          indices, then writes each bucket's window of d_out XCD by XCD;
+                                          0: one scattered write per edge over all of d_out          */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0

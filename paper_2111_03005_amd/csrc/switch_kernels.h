@@ -445,9 +445,11 @@ __global__ __launch_bounds__(kBlock) void k_unpermute(const uint32_t *__restrict
 // buckets of consecutive input indices (bucket b = records [boff[b],
 // boff[b+1]), indices below 2^20 apart): workgroup w runs on XCD w % 8 and
 // the workgroups of one XCD take its buckets b = x, x + 8, ... together, so
-// each bucket's window of `out` (at most 8 MB, 1 MB at 2^26 edges) fills in
-// that XCD's L2 and reaches HBM as whole lines.  The grid is a multiple of
-// 8.  Skipped entirely if an error flag is set (output untouched).
+// at any time each XCD writes into one window of `out` (at most 8 MB, 1 MB at
+// 2^26 edges) instead of all of it.  The stores still leave L2 as 32-byte
+// partial writes (the request-size counters show no merging), so the gain is
+// locality, not fewer bytes.  The grid is a multiple of 8.  Skipped entirely
+// if an error flag is set (output untouched).
 __global__ __launch_bounds__(kBlock) void k_unpermute_buckets(const uint32_t *__restrict__ idx,
                                                               const unsigned long long *__restrict__ key,
                                                               const uint32_t *__restrict__ boff, uint32_t nb,
