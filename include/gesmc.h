@@ -29,6 +29,7 @@
 #ifndef GESMC_H
 #define GESMC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -511,6 +512,26 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                           indices, then writes each bucket's window of d_out XCD by XCD;
                                           0: one scattered write per edge over all of d_out          */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
+
+/*
+ * Caller-supplied device memory (for instance PyTorch's caching allocator).
+ * After the call the context takes every device buffer it allocates from
+ * alloc(bytes, user), which must return memory of the context's device,
+ * aligned to 256 bytes, or NULL (the call that needed it then fails with
+ * GESMC_E_NOMEM and leaves its output untouched; the context stays usable).
+ * Each buffer goes back to the allocator that made it: free_fn(ptr, user) of
+ * the pair in force when it was allocated, called only after the device has
+ * finished all queued work (hipMalloc buffers from before stay hipMalloc
+ * buffers).  Both NULL: back to hipMalloc.  The functions run on the thread
+ * of the library call that allocates (a context's buffers grow on demand)
+ * and must not call into the library.  GESMC_E_INVAL for one function given
+ * without the other, or while a gesmc_server uses the context.  The small
+ * fixed area of gesmc_create and gesmc_run_noalloc's array are never taken
+ * from it.
+ */
+typedef void *(*gesmc_alloc_fn)(size_t bytes, void *user);
+typedef void (*gesmc_free_fn)(void *ptr, void *user);
+gesmc_status gesmc_set_allocator(gesmc_ctx *ctx, gesmc_alloc_fn alloc, gesmc_free_fn free_fn, void *user);
 
 /* Kernel timing collected while GESMC_OPT_PROFILE is on.  Kernel ids run from 0
  * to gesmc_kernel_count() - 1; gesmc_kernel_name gives the name.  *ms is the

@@ -118,7 +118,10 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
            "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
            "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing", "gesmc_run_class", "gesmc_gen_gnp",
-           "gesmc_gen_pld_degrees", "gesmc_gen_havel_hakimi", "gesmc_gen_relabel"]
+           "gesmc_gen_pld_degrees", "gesmc_gen_havel_hakimi", "gesmc_gen_relabel", "gesmc_set_allocator"]
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 _lib = None
 _lock = threading.Lock()
@@ -209,6 +212,8 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_gen_havel_hakimi.restype = i32
         lib.gesmc_gen_relabel.argtypes = [vp, vp, vp, u64, u32, u64]
         lib.gesmc_gen_relabel.restype = i32
+        lib.gesmc_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
+        lib.gesmc_set_allocator.restype = i32
         _lib = lib
         return lib
 
@@ -257,6 +262,29 @@ class Context:
 
     def set_option(self, option: int, value: int):
         _check(_lib.gesmc_set_option(self._h, option, int(value)))
+
+    def set_allocator(self, alloc=None, free=None):
+        """gesmc_set_allocator: alloc(nbytes) -> device address (int, 0 = none)
+        and free(address) for the context's device buffers; both None restores
+        hipMalloc.  The Python callables are kept alive by the context."""
+        if (alloc is None) != (free is None):
+            raise ValueError("give both alloc and free, or neither")
+        if alloc is None:
+            _check(_lib.gesmc_set_allocator(self._h, ALLOC_FN(), FREE_FN(), None))
+            self._alloc_cbs = None
+            return
+        a = ALLOC_FN(lambda nbytes, user: int(alloc(int(nbytes))) or None)
+        f = FREE_FN(lambda ptr, user: free(int(ptr)))
+        _check(_lib.gesmc_set_allocator(self._h, a, f, None))
+        # buffers made by earlier pairs still hold their functions: keep them all
+        self._alloc_keep = getattr(self, "_alloc_keep", []) + [(a, f)]
+        self._alloc_cbs = (a, f)
+
+    def use_torch_allocator(self):
+        """Backs the context's device buffers with PyTorch's caching allocator."""
+        dev = self.device
+        self.set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device=dev),
+                           lambda p: torch.cuda.caching_allocator_delete(p))
 
     # ---- the global switch chain -----------------------------------------
     def run(self, edges: torch.Tensor, n: int, seed: int, t0: int = 0, r: int = 1, pl: int = 0,

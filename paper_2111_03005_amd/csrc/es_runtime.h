@@ -20,7 +20,7 @@ uint64_t es_slots(uint32_t m) {
 gesmc_status es_ensure(gesmc_ctx *c, uint32_t m) {
     const uint64_t cap = std::max<uint64_t>(m, 1024), T = es_slots(m);
     if (!c->es_ctr) {
-        GESMC_TRY(dev_alloc((void **)&c->es_ctr, sizeof(EsCounters)));
+        GESMC_TRY(dev_alloc(c, (void **)&c->es_ctr, sizeof(EsCounters)));
         if (hipHostMalloc((void **)&c->h_es_ctr, sizeof(EsCounters), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             c->h_es_ctr = nullptr;
@@ -30,19 +30,19 @@ gesmc_status es_ensure(gesmc_ctx *c, uint32_t m) {
     }
     if (cap > c->es_cap_m) {
         for (void **q : {(void **)&c->es_E, (void **)&c->es_slot}) {
-            if (*q) (void)hipFree(*q);
+            if (*q) dev_free(c, *q);
             *q = nullptr;
         }
         c->es_cap_m = 0;
-        GESMC_TRY(dev_alloc((void **)&c->es_E, cap * 8));
-        GESMC_TRY(dev_alloc((void **)&c->es_slot, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->es_E, cap * 8));
+        GESMC_TRY(dev_alloc(c, (void **)&c->es_slot, cap * 4));
         c->es_cap_m = cap;
     }
     if (T > c->es_cap_T) {
-        if (c->es_H) (void)hipFree(c->es_H);
+        if (c->es_H) dev_free(c, c->es_H);
         c->es_H = nullptr;
         c->es_cap_T = 0;
-        GESMC_TRY(dev_alloc((void **)&c->es_H, T * 8));
+        GESMC_TRY(dev_alloc(c, (void **)&c->es_H, T * 8));
         c->es_cap_T = T;
     }
     return GESMC_OK;

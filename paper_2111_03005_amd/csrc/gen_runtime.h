@@ -10,10 +10,12 @@ namespace {
 
 // A block of device memory carved into aligned pieces, freed at scope exit.
 struct GenBlock {
+    gesmc_ctx *c;
     unsigned char *base = nullptr;
     uint64_t off = 0;
+    explicit GenBlock(gesmc_ctx *ctx) : c(ctx) {}
     ~GenBlock() {
-        if (base) (void)hipFree(base);
+        if (base) dev_free(c, base);
     }
     template <typename T>
     T *take(uint64_t count) {
@@ -86,9 +88,9 @@ gesmc_status gen_gnp_impl(gesmc_ctx *c, void *stream, uint32_t n, double p, uint
     const uint64_t L = gnp_chunk_length(p);
     const uint64_t nchunks = (N + L - 1) / L;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
-    GenBlock blk;
+    GenBlock blk(c);
     const uint64_t nsum = gen_scan_sums(nchunks);
-    GESMC_TRY(dev_alloc((void **)&blk.base, gen_bytes_with_align({nchunks * 4, nchunks * 8, nsum * 8, 64})));
+    GESMC_TRY(dev_alloc(c, (void **)&blk.base, gen_bytes_with_align({nchunks * 4, nchunks * 8, nsum * 8, 64})));
     uint32_t *counts = blk.take<uint32_t>(nchunks);
     unsigned long long *offs = blk.take<unsigned long long>(nchunks);
     unsigned long long *sums = blk.take<unsigned long long>(nsum);
@@ -131,9 +133,9 @@ gesmc_status gen_pld_impl(gesmc_ctx *c, void *stream, uint32_t n, double gamma, 
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t nv = dmax - dmin + 1;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
-    GenBlock blk;
+    GenBlock blk(c);
     const uint64_t nsum = gen_scan_sums(nv);
-    GESMC_TRY(dev_alloc((void **)&blk.base, gen_bytes_with_align({(uint64_t)nv * 8, (uint64_t)nv * 8, nsum * 8, 64})));
+    GESMC_TRY(dev_alloc(c, (void **)&blk.base, gen_bytes_with_align({(uint64_t)nv * 8, (uint64_t)nv * 8, nsum * 8, 64})));
     unsigned long long *W = blk.take<unsigned long long>(nv);
     unsigned long long *C = blk.take<unsigned long long>(nv);
     unsigned long long *sums = blk.take<unsigned long long>(nsum);
@@ -172,8 +174,8 @@ gesmc_status gen_hh_impl(gesmc_ctx *c, void *stream, uint32_t n, const uint32_t 
     hipStream_t s = (hipStream_t)stream;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
     // degree statistics first: the largest degree sizes the state
-    GenBlock sblk;
-    GESMC_TRY(dev_alloc((void **)&sblk.base, 256));
+    GenBlock sblk(c);
+    GESMC_TRY(dev_alloc(c, (void **)&sblk.base, 256));
     uint32_t *w = (uint32_t *)sblk.base;  // [0] max degree, [2..3] sum
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(64), 0, w, (uint64_t)8));
     GESMC_TRY(launch(c, s, KID_GEN, n, k_hh_stats, dim3(grid_stride_blocks(c, n)), dim3(kBlock), 0, d_deg, n, w,
@@ -205,8 +207,8 @@ gesmc_status gen_hh_impl(gesmc_ctx *c, void *stream, uint32_t n, const uint32_t 
     const uint32_t nb = ceil_div(n, T);
     const uint64_t nM = (uint64_t)(D + 1) * nb;
     const uint64_t nsum = gen_scan_sums(nM);
-    GenBlock blk;
-    GESMC_TRY(dev_alloc((void **)&blk.base,
+    GenBlock blk(c);
+    GESMC_TRY(dev_alloc(c, (void **)&blk.base,
                         gen_bytes_with_align({nM * 4, nM * 8, nsum * 8, 64, (uint64_t)n * 4, (uint64_t)(D + 2) * 4,
                                               (uint64_t)n * sizeof(HhStep), 64})));
     uint32_t *M = blk.take<uint32_t>(nM);
@@ -261,8 +263,8 @@ gesmc_status gen_relabel_impl(gesmc_ctx *c, void *stream, uint64_t *d_edges, uin
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
-    GenBlock blk;
-    GESMC_TRY(dev_alloc((void **)&blk.base, gen_bytes_with_align({(uint64_t)n * 4, (uint64_t)n * 4})));
+    GenBlock blk(c);
+    GESMC_TRY(dev_alloc(c, (void **)&blk.base, gen_bytes_with_align({(uint64_t)n * 4, (uint64_t)n * 4})));
     uint32_t *pi = blk.take<uint32_t>(n);
     uint32_t *sigma = blk.take<uint32_t>(n);
     GESMC_TRY(gesmc_permutation(c, stream, n, seed ^ 0x9E3779B97F4A7C15ull, 0u, pi));

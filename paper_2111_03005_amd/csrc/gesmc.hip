@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "gesmc.h"
@@ -130,6 +131,12 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1)
 
 }  // namespace
 
+// A buffer from the caller's allocator and the free function that returns it.
+struct HookedBuffer {
+    gesmc_free_fn free_fn;
+    void *user;
+};
+
 struct gesmc_ctx {
     int device = 0;
     int num_cus = 256;
@@ -190,6 +197,11 @@ struct gesmc_ctx {
     uint32_t *small_list = nullptr, *rrank = nullptr;  // small graphs' ranks; r per rank
     bool small_graphs = true;                         // graphs with m <= kSmallMax run in LDS
     bool unpermute_buckets = true;                    // large write-backs by index buckets
+    gesmc_alloc_fn alloc_fn = nullptr;                // the caller's allocator (gesmc_set_allocator)
+    gesmc_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
+    std::unordered_map<void *, HookedBuffer> hooked;  // live buffers of caller allocators
+    bool serving = false;                             // a gesmc_server owns the context
     bool pack_tuples = true;                          // 8-byte tuple words where the bits allow
     uint32_t tuple_bytes = 0;                         // tuple size of the call's last superstep
     StepCounters *ctr = nullptr;
@@ -234,30 +246,32 @@ constexpr uint32_t kMaxFineBits = 21;
 constexpr uint32_t kMaxLevelBits = 12;  // digit bits of one radix level (first <= kMaxCoarseBits)
 constexpr uint64_t kMaxEdges = 1ull << 30;
 
+void dev_free(gesmc_ctx *c, void *p);
+
 void free_buffers(gesmc_ctx *c) {
     for (int q = 0; q < 3; ++q) {
-        if (c->idx[q]) (void)hipFree(c->idx[q]);
-        if (c->key[q]) (void)hipFree(c->key[q]);
+        if (c->idx[q]) dev_free(c, c->idx[q]);
+        if (c->key[q]) dev_free(c, c->key[q]);
         c->idx[q] = nullptr;
         c->key[q] = nullptr;
     }
-    if (c->tab) (void)hipFree(c->tab);
-    if (c->sw_slot) (void)hipFree(c->sw_slot);
-    if (c->st) (void)hipFree(c->st);
+    if (c->tab) dev_free(c, c->tab);
+    if (c->sw_slot) dev_free(c, c->sw_slot);
+    if (c->st) dev_free(c, c->st);
     for (int q = 0; q < 2; ++q) {
-        if (c->ulist[q]) (void)hipFree(c->ulist[q]);
+        if (c->ulist[q]) dev_free(c, c->ulist[q]);
         c->ulist[q] = nullptr;
     }
     for (int q = 0; q < 3; ++q) {
-        if (c->tu_tag[q]) (void)hipFree(c->tu_tag[q]);
-        if (c->tu_key[q]) (void)hipFree(c->tu_key[q]);
+        if (c->tu_tag[q]) dev_free(c, c->tu_tag[q]);
+        if (c->tu_key[q]) dev_free(c, c->tu_key[q]);
         c->tu_tag[q] = nullptr;
         c->tu_key[q] = nullptr;
     }
-    if (c->info) (void)hipFree(c->info);
+    if (c->info) dev_free(c, c->info);
     c->info = nullptr;
     for (uint32_t **pp : {&c->counts1, &c->counts2, &c->partial}) {
-        if (*pp) (void)hipFree(*pp);
+        if (*pp) dev_free(c, *pp);
         *pp = nullptr;
     }
     c->cap_counts1 = c->cap_counts2 = c->cap_partial = 0;
@@ -273,16 +287,53 @@ void free_buffers(gesmc_ctx *c) {
 // so it is only replayed while no buffer has moved.
 std::atomic<uint64_t> g_alloc_epoch{0};
 
-gesmc_status dev_alloc(void **p, size_t bytes) {
+// Device memory of a context: from the caller's allocator once one is set
+// (gesmc_set_allocator), else hipMalloc.  Each buffer remembers the free
+// function of the allocator that made it, so buffers from before and after a
+// change are each returned to their own allocator.
+gesmc_status dev_alloc(gesmc_ctx *c, void **p, size_t bytes) {
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
     ++g_alloc_epoch;
-    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+    const size_t b = bytes ? bytes : 16;
+    if (c && c->alloc_fn) {
+        void *q = c->alloc_fn(b, c->alloc_user);
+        *p = q;
+        if (!q || ((uintptr_t)q & 255u)) {
+            if (q) c->free_fn(q, c->alloc_user);
+            *p = nullptr;
+            set_error(q ? "the caller's allocator returned memory aligned below 256 bytes"
+                        : "the caller's allocator returned no memory for %zu bytes",
+                      b);
+            return GESMC_E_NOMEM;
+        }
+        c->hooked[q] = HookedBuffer{c->free_fn, c->alloc_user};
+        return GESMC_OK;
+    }
+    if (hipMalloc(p, b) != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
         set_error("hipMalloc of %zu bytes failed", bytes);
         return GESMC_E_NOMEM;
     }
     return GESMC_OK;
+}
+
+// Returns a device buffer to the allocator that made it.  The caller's free
+// function runs only once the device has finished all queued work, since it
+// may hand the memory to other work at once; hipFree waits by itself.
+void dev_free(gesmc_ctx *c, void *p) {
+    if (!p) return;
+    if (c) {
+        const auto it = c->hooked.find(p);
+        if (it != c->hooked.end()) {
+            const HookedBuffer h = it->second;
+            c->hooked.erase(it);
+            (void)hipDeviceSynchronize();
+            h.free_fn(p, h.user);
+            return;
+        }
+    }
+    (void)hipFree(p);
 }
 
 uint64_t table_slots_for(uint64_t m) {
@@ -300,21 +351,21 @@ gesmc_status ensure_capacity(gesmc_ctx *c, uint64_t m, bool tuples = false) {
     const uint64_t cap = std::max<uint64_t>(m, 1024);
     gesmc_status s = GESMC_OK;
     for (int q = 0; q < 3 && s == GESMC_OK; ++q) {
-        s = dev_alloc((void **)&c->idx[q], cap * 4);
-        if (s == GESMC_OK) s = dev_alloc((void **)&c->key[q], cap * 8);
+        s = dev_alloc(c, (void **)&c->idx[q], cap * 4);
+        if (s == GESMC_OK) s = dev_alloc(c, (void **)&c->key[q], cap * 8);
     }
     const uint64_t ts = need_tab ? table_slots_for(cap) : 0;
-    if (s == GESMC_OK && need_tab) s = dev_alloc((void **)&c->tab, ts * sizeof(Slot));
+    if (s == GESMC_OK && need_tab) s = dev_alloc(c, (void **)&c->tab, ts * sizeof(Slot));
     const uint64_t ntu = 2 * cap + 8;  // 4 * floor(m/2) + 1 tuple slots
     for (int q = 0; q < 3 && s == GESMC_OK && need_tu; ++q) {
-        s = dev_alloc((void **)&c->tu_tag[q], ntu * 4);
-        if (s == GESMC_OK) s = dev_alloc((void **)&c->tu_key[q], ntu * 8);
+        s = dev_alloc(c, (void **)&c->tu_tag[q], ntu * 4);
+        if (s == GESMC_OK) s = dev_alloc(c, (void **)&c->tu_key[q], ntu * 8);
     }
-    if (s == GESMC_OK && need_tu) s = dev_alloc((void **)&c->info, (cap + 8) * sizeof(uint2));
+    if (s == GESMC_OK && need_tu) s = dev_alloc(c, (void **)&c->info, (cap + 8) * sizeof(uint2));
     if (s == GESMC_OK) c->cap_tu = need_tu ? ntu : 0;
-    if (s == GESMC_OK) s = dev_alloc((void **)&c->sw_slot, (cap / 2 + 1) * 8);
-    if (s == GESMC_OK) s = dev_alloc((void **)&c->st, cap / 2 + 64);
-    for (int q = 0; q < 2 && s == GESMC_OK; ++q) s = dev_alloc((void **)&c->ulist[q], (cap / 2 + 64) * 4);
+    if (s == GESMC_OK) s = dev_alloc(c, (void **)&c->sw_slot, (cap / 2 + 1) * 8);
+    if (s == GESMC_OK) s = dev_alloc(c, (void **)&c->st, cap / 2 + 64);
+    for (int q = 0; q < 2 && s == GESMC_OK; ++q) s = dev_alloc(c, (void **)&c->ulist[q], (cap / 2 + 64) * 4);
     if (s != GESMC_OK) {
         free_buffers(c);
         return s;
@@ -328,10 +379,10 @@ gesmc_status ensure_counters(gesmc_ctx *c, uint64_t r) {
     const uint64_t want = std::max<uint64_t>(r, 1);
     if ((want > c->ctr_cap || want > c->h_ctr_cap) && alloc_forbidden()) return GESMC_E_INTERNAL;
     if (want > c->ctr_cap) {
-        if (c->ctr) (void)hipFree(c->ctr);
+        if (c->ctr) dev_free(c, c->ctr);
         c->ctr = nullptr;
         c->ctr_cap = 0;
-        gesmc_status s = dev_alloc((void **)&c->ctr, want * sizeof(StepCounters));
+        gesmc_status s = dev_alloc(c, (void **)&c->ctr, want * sizeof(StepCounters));
         if (s != GESMC_OK) return s;
         c->ctr_cap = want;
     }
@@ -511,13 +562,13 @@ uint32_t grid_stride_blocks(const gesmc_ctx *c, uint64_t work) {
 }
 
 // Grows a word buffer of the radix bookkeeping.
-gesmc_status ensure_words(uint32_t **p, uint64_t *cap, uint64_t want) {
+gesmc_status ensure_words(gesmc_ctx *c, uint32_t **p, uint64_t *cap, uint64_t want) {
     if (want <= *cap && *p) return GESMC_OK;
     if (alloc_forbidden()) return GESMC_E_INTERNAL;
-    if (*p) (void)hipFree(*p);
+    if (*p) dev_free(c, *p);
     *p = nullptr;
     *cap = 0;
-    GESMC_TRY(dev_alloc((void **)p, std::max<uint64_t>(want, 1024) * 4));
+    GESMC_TRY(dev_alloc(c, (void **)p, std::max<uint64_t>(want, 1024) * 4));
     *cap = std::max<uint64_t>(want, 1024);
     return GESMC_OK;
 }
@@ -574,8 +625,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     const uint32_t nchunks = ceil_div(p.ntiles1, chunk);
     const uint32_t scan_threads = std::max<uint32_t>(64, std::min<uint32_t>(kBlock, nd1));
     const RadixWords rw = radix_words(p);
-    GESMC_TRY(ensure_words(&c->counts1, &c->cap_counts1, rw.counts1));
-    GESMC_TRY(ensure_words(&c->partial, &c->cap_partial, rw.partial));
+    GESMC_TRY(ensure_words(c, &c->counts1, &c->cap_counts1, rw.counts1));
+    GESMC_TRY(ensure_words(c, &c->partial, &c->cap_partial, rw.partial));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;  // level 1: one segment [0, n), passed by value
     bool fused_emit = false;
     if constexpr (kSrc1 == kSrcEmit || kSrc1 == kSrcEmitPacked) {
@@ -617,7 +668,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     }
     const uint32_t nd2 = 1u << p.b2;
     const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
-    GESMC_TRY(ensure_words(&c->counts2, &c->cap_counts2, rw.counts2));
+    GESMC_TRY(ensure_words(c, &c->counts2, &c->cap_counts2, rw.counts2));
     // packed words lost the first level's bits: the second level's are on top
     const int shift2 = kSrc2 == kSrcPacked ? 64 - (int)p.b2 : 64 - (int)p.bbits;
     GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile, false>,
@@ -1468,11 +1519,11 @@ gesmc_status up_end(gesmc_ctx *c, hipStream_t s) {
 gesmc_status ensure_chunks(gesmc_ctx *c) {
     const uint64_t n = c->h_chunks.size();
     if (n > c->chunk_cap) {
-        if (c->chunks) (void)hipFree(c->chunks);
+        if (c->chunks) dev_free(c, c->chunks);
         c->chunks = nullptr;
         c->chunk_cap = 0;
         const uint64_t cap = std::max<uint64_t>(n + n / 2, 1024);
-        GESMC_TRY(dev_alloc((void **)&c->chunks, cap * sizeof(uint4)));
+        GESMC_TRY(dev_alloc(c, (void **)&c->chunks, cap * sizeof(uint4)));
         c->chunk_cap = cap;
     }
     return GESMC_OK;
@@ -1482,7 +1533,7 @@ gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
     if (G > c->cap_g) {
         for (void **q : {(void **)&c->gr, (void **)&c->in_off, (void **)&c->rank_of, (void **)&c->gacc,
                          (void **)&c->gerr, (void **)&c->small_list, (void **)&c->rrank}) {
-            if (*q) (void)hipFree(*q);
+            if (*q) dev_free(c, *q);
             *q = nullptr;
         }
         if (c->h_gacc) (void)hipHostFree(c->h_gacc);
@@ -1491,13 +1542,13 @@ gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
         c->h_gerr = nullptr;
         c->cap_g = 0;
         const uint64_t cap = std::max<uint64_t>(G, 64);
-        GESMC_TRY(dev_alloc((void **)&c->gr, cap * sizeof(BatchGraph)));
-        GESMC_TRY(dev_alloc((void **)&c->in_off, (cap + 1) * 8));
-        GESMC_TRY(dev_alloc((void **)&c->rank_of, cap * 4));
-        GESMC_TRY(dev_alloc((void **)&c->gacc, cap * 4 * 8));
-        GESMC_TRY(dev_alloc((void **)&c->gerr, cap * 4));
-        GESMC_TRY(dev_alloc((void **)&c->small_list, cap * 4));
-        GESMC_TRY(dev_alloc((void **)&c->rrank, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->gr, cap * sizeof(BatchGraph)));
+        GESMC_TRY(dev_alloc(c, (void **)&c->in_off, (cap + 1) * 8));
+        GESMC_TRY(dev_alloc(c, (void **)&c->rank_of, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->gacc, cap * 4 * 8));
+        GESMC_TRY(dev_alloc(c, (void **)&c->gerr, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->small_list, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->rrank, cap * 4));
         if (hipHostMalloc((void **)&c->h_gacc, cap * 4 * 8, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&c->h_gerr, cap * 4, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
@@ -1508,13 +1559,13 @@ gesmc_status ensure_batch(gesmc_ctx *c, uint64_t G, uint64_t npos) {
     }
     if (npos > c->cap_pos) {
         for (void **q : {(void **)&c->pg, (void **)&c->bk}) {
-            if (*q) (void)hipFree(*q);
+            if (*q) dev_free(c, *q);
             *q = nullptr;
         }
         c->cap_pos = 0;
         const uint64_t cap = std::max<uint64_t>(npos, 1024);
-        GESMC_TRY(dev_alloc((void **)&c->pg, cap * 4));
-        GESMC_TRY(dev_alloc((void **)&c->bk, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->pg, cap * 4));
+        GESMC_TRY(dev_alloc(c, (void **)&c->bk, cap * 4));
         c->cap_pos = cap;
     }
     return GESMC_OK;
@@ -1918,9 +1969,9 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     const size_t nf = (size_t)1 << kMaxFineBits;
     const size_t nc = ((size_t)1 << kMaxCoarseBits) + 8;
     const size_t words = 16 + 16 + 2 * nc + 8 + (nf + 8);
-    if (dev_alloc((void **)&c->small, words * 4) != GESMC_OK ||
-        dev_alloc((void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK ||
-        dev_alloc((void **)&c->bslot, (kEmitSlotsMax + 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1)) * sizeof(uint4)) !=
+    if (dev_alloc(c, (void **)&c->small, words * 4) != GESMC_OK ||
+        dev_alloc(c, (void **)&c->ctr, 64 * sizeof(StepCounters)) != GESMC_OK ||
+        dev_alloc(c, (void **)&c->bslot, (kEmitSlotsMax + 2 * (size_t)grid_stride_blocks(c, ~0ull >> 1)) * sizeof(uint4)) !=
             GESMC_OK) {
         gesmc_destroy(c);
         return GESMC_E_NOMEM;
@@ -1980,14 +2031,14 @@ void gesmc_destroy(gesmc_ctx *c) {
     (void)hipDeviceSynchronize();
     free_buffers(c);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->small) (void)hipFree(c->small);
-    if (c->bslot) (void)hipFree(c->bslot);
+    if (c->small) dev_free(c, c->small);
+    if (c->bslot) dev_free(c, c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
                     (void *)c->bk, (void *)c->gerr, (void *)c->small_list, (void *)c->rrank, (void *)c->chunks})
-        if (q) (void)hipFree(q);
+        if (q) dev_free(c, q);
     if (c->h_gacc) (void)hipHostFree(c->h_gacc);
     if (c->h_gerr) (void)hipHostFree(c->h_gerr);
-    if (c->ctr) (void)hipFree(c->ctr);
+    if (c->ctr) dev_free(c, c->ctr);
     if (c->h_err) (void)hipHostFree(c->h_err);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1996,9 +2047,9 @@ void gesmc_destroy(gesmc_ctx *c) {
     if (c->h_up) (void)hipHostFree(c->h_up);
     if (c->h_hr) (void)hipHostFree(c->h_hr);
     for (void *q : {(void *)c->es_E, (void *)c->es_H, (void *)c->es_slot, (void *)c->es_ctr})
-        if (q) (void)hipFree(q);
+        if (q) dev_free(c, q);
     if (c->h_es_ctr) (void)hipHostFree(c->h_es_ctr);
-    if (c->hr_dev) (void)hipFree(c->hr_dev);
+    if (c->hr_dev) dev_free(c, c->hr_dev);
     for (hipEvent_t e : {c->fork_ev, c->join_ev[0], c->join_ev[1], c->up_ev})
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : c->side)
@@ -2085,7 +2136,7 @@ gesmc_status gesmc_autotune(gesmc_ctx *c, void *stream, const uint64_t *d_in, ui
     }
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     uint64_t *tmp = nullptr;
-    GESMC_TRY(dev_alloc((void **)&tmp, std::max<uint64_t>(m, 1) * 8));
+    GESMC_TRY(dev_alloc(c, (void **)&tmp, std::max<uint64_t>(m, 1) * 8));
     const gesmc_status st = autotune_impl(
         c,
         [&](double *ms) {
@@ -2097,7 +2148,7 @@ gesmc_status gesmc_autotune(gesmc_ctx *c, void *stream, const uint64_t *d_in, ui
         },
         out);
     (void)hipStreamSynchronize((hipStream_t)stream);
-    (void)hipFree(tmp);
+    dev_free(c, tmp);
     return st;
 }
 
@@ -2111,7 +2162,7 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *c, void *stream, uint32_t G, const 
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     const uint64_t total = offsets[G];
     uint64_t *tmp = nullptr;
-    GESMC_TRY(dev_alloc((void **)&tmp, std::max<uint64_t>(total, 1) * 8));
+    GESMC_TRY(dev_alloc(c, (void **)&tmp, std::max<uint64_t>(total, 1) * 8));
     std::vector<uint32_t> rs(G, std::max(supersteps, 1u));
     const gesmc_status st = autotune_impl(
         c,
@@ -2124,7 +2175,7 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *c, void *stream, uint32_t G, const 
         },
         out);
     (void)hipStreamSynchronize((hipStream_t)stream);
-    (void)hipFree(tmp);
+    dev_free(c, tmp);
     return st;
 }
 
@@ -2161,10 +2212,10 @@ gesmc_status gesmc_run_host(gesmc_ctx *c, const uint32_t *uv, uint32_t *uv_out, 
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     const uint64_t words = std::max<uint64_t>(m, 1);
     if (words > c->hr_cap) {
-        if (c->hr_dev) (void)hipFree(c->hr_dev);
+        if (c->hr_dev) dev_free(c, c->hr_dev);
         c->hr_dev = nullptr;
         c->hr_cap = 0;
-        GESMC_TRY(dev_alloc((void **)&c->hr_dev, 2 * words * 8));
+        GESMC_TRY(dev_alloc(c, (void **)&c->hr_dev, 2 * words * 8));
         c->hr_cap = words;
     }
     if (words > c->h_hr_cap) {
@@ -2263,6 +2314,21 @@ gesmc_status gesmc_permutation(gesmc_ctx *c, void *stream, uint64_t m64, uint64_
     GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
     if (c->profile) collect_profile(c);
     if (m > 0) return map_err(*c->h_err);
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_set_allocator(gesmc_ctx *c, gesmc_alloc_fn alloc, gesmc_free_fn free_fn, void *user) {
+    if (!c || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("null context, or only one of the allocate and free functions given");
+        return GESMC_E_INVAL;
+    }
+    if (c->serving) {
+        set_error("the context serves a gesmc_server; destroy the server first");
+        return GESMC_E_INVAL;
+    }
+    c->alloc_fn = alloc;
+    c->free_fn = free_fn;
+    c->alloc_user = user;
     return GESMC_OK;
 }
 

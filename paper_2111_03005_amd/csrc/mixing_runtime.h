@@ -41,13 +41,14 @@ gesmc_status mixing_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint6
     const uint64_t per_q = mm * 8 + words * 8 + npairs * sizeof(MixCount) + 256 * 3;
     const uint64_t bytes = mm * 8 + words * 4 + 64 + nthin * per_q + 256;
     unsigned char *blk = nullptr;
-    GESMC_TRY(dev_alloc((void **)&blk, bytes));
+    GESMC_TRY(dev_alloc(c, (void **)&blk, bytes));
     struct Free {
+        gesmc_ctx *c;
         unsigned char *p;
         ~Free() {
-            if (p) (void)hipFree(p);
+            if (p) dev_free(c, p);
         }
-    } guard{blk};
+    } guard{c, blk};
     uint64_t off = 0;
     auto take = [&](uint64_t b) {
         off = (off + 255) & ~255ull;

@@ -605,14 +605,15 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
     GESMC_TRY(ensure_batch(c, max_graphs, cap_edges + 64));
     gesmc_server *S = new gesmc_server();
     S->c = c;
+    c->serving = true;
     S->cap_edges = cap_edges;
     S->max_graphs = max_graphs;
     S->max_queue = max_queue;
     S->t0 = std::chrono::steady_clock::now();
     gesmc_status st = GESMC_OK;
-    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_mv, max_graphs * sizeof(uint2));
-    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
-    if (st == GESMC_OK) st = dev_alloc((void **)&S->d_stage_rank, max_graphs * 4ull);
+    if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_mv, max_graphs * sizeof(uint2));
+    if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
+    if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_stage_rank, max_graphs * 4ull);
     if (st == GESMC_OK && hipEventCreateWithFlags(&S->stage_ev, hipEventDisableTiming) != hipSuccess) st = GESMC_E_DEVICE;
     for (ServeFlight &F : S->fl) {
         if (st != GESMC_OK) break;
@@ -677,7 +678,8 @@ void gesmc_server_destroy(gesmc_server *S) {
         (void)hipStreamDestroy(S->s);
     }
     for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank})
-        if (p) (void)hipFree(p);
+        if (p) dev_free(S->c, p);
+    S->c->serving = false;
     if (S->h_pin) (void)hipHostFree(S->h_pin);
     if (S->stage_ev) (void)hipEventDestroy(S->stage_ev);
     for (ServeFlight &F : S->fl) {
