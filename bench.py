@@ -193,6 +193,20 @@ def bench_batched(gesmc, torch, args, plain_value):
         times.append(time.perf_counter() - t)
     wall = sum(times)
     value = attempts * len(times) / wall
+    # the same calls replayed from a hipGraph (captured on the second call of this shape)
+    ctx.set_option(gesmc.OPT_GRAPH, 1)
+    for _ in range(2):
+        ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_steps):
+        ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=False)
+    torch.cuda.synchronize()
+    gwall = time.perf_counter() - t
+    ctx.set_option(gesmc.OPT_GRAPH, 0)
+    graph_rec = {"value": round(attempts * args.batch_steps / gwall, 1), "unit": "attempts/s",
+                 "ms_per_step": round(1e3 * gwall / args.batch_steps, 3), "vs_eager": round(wall / gwall, 3)}
+    print("batched: hipGraph replay %s" % graph_rec, file=sys.stderr)
     # the plain path (one gesmc_run per graph) on a sample of the same graphs
     sample = list(range(0, G, args.plain_sample_stride))
     dev_graphs = [(torch.from_numpy(graphs[g][0].view(np.int64).copy()).to("cuda"), graphs[g][1]) for g in sample]
@@ -230,6 +244,7 @@ def bench_batched(gesmc, torch, args, plain_value):
             "autotuner": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in tuning.items()},
             "vs_plain_headline": round(value / plain_value, 3) if plain_value else None,
             "cpu_baseline": cpu_b,
+            "hipgraph_replay": graph_rec,
             "small_batches_hipgraph": small}
 
 
