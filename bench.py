@@ -336,7 +336,9 @@ def bench_served(gesmc, torch, args):
                "attempts_per_s": round(att / span, 1),
                "attempts_per_busy_s": round(info["attempts"] / max(info["busy_s"], 1e-9), 1),
                "iterations": info["iterations"],
-               "busy_fraction": round(info["busy_s"] / max(info["now_s"], 1e-9), 3)}
+               "busy_fraction": round(info["busy_s"] / max(info["now_s"], 1e-9), 3),
+               "host_copy_fraction": round(info["copy_s"] / max(info["busy_s"], 1e-9), 3),
+               "device_wait_fraction": round(info["wait_s"] / max(info["busy_s"], 1e-9), 3)}
         print("served: %s" % rec, file=sys.stderr)
         out.append(rec)
     # the plain form on the same kind of stream: gesmc_run on the requests one after

@@ -304,7 +304,9 @@ typedef struct gesmc_server gesmc_server;
 
 typedef struct gesmc_server_cfg {
     uint64_t hbm_budget_bytes; /* device memory for resident graphs (0: 16 GiB); about 136 bytes per
-                                  edge, so at most budget / 136 edges are resident at once           */
+                                  edge, so at most budget / 136 edges are resident at once; copy
+                                  buffers beside it grow to the largest admission and completion
+                                  (8 bytes per edge each, three of them)                              */
     uint32_t max_graphs;       /* resident graphs at most (0: 4096)                                   */
     uint32_t max_queue;        /* queued requests at most; submit then returns GESMC_E_AGAIN (0: 2^16) */
 } gesmc_server_cfg;

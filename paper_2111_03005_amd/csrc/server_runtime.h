@@ -58,9 +58,14 @@ struct ServeFlight {
     uint32_t nsurv = 0, k = 0;
     uint32_t tuple_bytes = 0;  // tuple size of the iteration's supersteps
     bool live = false;
-    hipEvent_t done = nullptr;  // after the iteration's last copy
+    hipEvent_t done = nullptr;  // on the compute stream, after the iteration's last copy
     uint64_t *h_res = nullptr;  // results of the finishing graphs
     uint64_t res_cap = 0;       // words
+    uint64_t *d_res = nullptr;  // the same on the device (filled by the compute stream)
+    uint64_t d_res_cap = 0;     // words
+    hipEvent_t ext = nullptr;     // on the compute stream, after the results are extracted
+    hipEvent_t res_ev = nullptr;  // on the download stream, after the results' copy
+    bool res_pending = false;
     unsigned long long *h_gacc = nullptr;  // 4 per rank (max_graphs)
     uint32_t *h_gerr = nullptr;            // per rank
     StepCounters *h_ctr = nullptr;         // per superstep (kServeBurstMax)
@@ -96,8 +101,16 @@ struct gesmc_server {
     std::vector<uint32_t> h_stage_rank;
     uint64_t *h_pin = nullptr;  // pinned staging of admitted edges
     uint64_t pin_cap = 0;       // words
-    hipEvent_t stage_ev = nullptr;  // after the last upload from h_pin
+    uint64_t *d_stage = nullptr;  // device staging of admitted edges (the upload's target)
+    uint64_t d_stage_cap = 0;     // words
+    // Copies of edges and results run on streams of their own, so that they
+    // overlap the supersteps of the neighbouring iteration.  Every wait below
+    // is on an event recorded earlier in host order.
+    hipStream_t up = nullptr, down = nullptr;
+    hipEvent_t stage_ev = nullptr;  // on `up`, after the last upload from h_pin into d_stage
     bool stage_pending = false;
+    hipEvent_t load_ev = nullptr;   // on the compute stream, after the last load from d_stage
+    bool load_recorded = false;
     ServeFlight fl[2];          // two iterations in flight at most
     uint2 *d_mv = nullptr;
     uint64_t *d_stage_off = nullptr;
@@ -169,6 +182,38 @@ gesmc_status serve_stage(gesmc_server *S, uint64_t words) {
         return GESMC_E_NOMEM;
     }
     S->pin_cap = cap;
+    return GESMC_OK;
+}
+
+// Grows the device staging of admitted edges to at least `words` words,
+// once no upload into it and no load from it is queued any more.
+gesmc_status serve_dev_stage(gesmc_server *S, uint64_t words) {
+    if (words <= S->d_stage_cap) return GESMC_OK;
+    if (S->d_stage) {
+        if (S->stage_pending) GESMC_TRY(check_hip(hipEventSynchronize(S->stage_ev), "hipEventSynchronize"));
+        if (S->load_recorded) GESMC_TRY(check_hip(hipEventSynchronize(S->load_ev), "hipEventSynchronize"));
+        dev_free(S->c, S->d_stage);
+    }
+    S->d_stage = nullptr;
+    S->d_stage_cap = 0;
+    const uint64_t cap = std::max(words, std::min<uint64_t>(std::max<uint64_t>(words + words / 4, 1ull << 20),
+                                                            S->cap_edges + 64));
+    GESMC_TRY(dev_alloc(S->c, (void **)&S->d_stage, cap * 8));
+    S->d_stage_cap = cap;
+    return GESMC_OK;
+}
+
+// Grows a flight's device result buffer (the flight is not in use: its last
+// download was waited for when it completed).
+gesmc_status serve_flight_dres(gesmc_server *S, ServeFlight &F, uint64_t words) {
+    if (words <= F.d_res_cap) return GESMC_OK;
+    if (F.d_res) dev_free(S->c, F.d_res);
+    F.d_res = nullptr;
+    F.d_res_cap = 0;
+    const uint64_t cap = std::max(words, std::min<uint64_t>(std::max<uint64_t>(words + words / 4, 1ull << 20),
+                                                            S->cap_edges + 64));
+    GESMC_TRY(dev_alloc(S->c, (void **)&F.d_res, cap * 8));
+    F.d_res_cap = cap;
     return GESMC_OK;
 }
 
@@ -274,6 +319,8 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
         const auto a0 = std::chrono::steady_clock::now();
         GESMC_TRY(serve_stage(S, stage));
         GESMC_TRY(serve_flight_res(F, rpos));
+        GESMC_TRY(serve_dev_stage(S, stage));
+        GESMC_TRY(serve_flight_dres(S, F, rpos));
         S->w_copy += seconds_since(a0);
     }
     // small uploads through the context's pinned arena (records, chunks, moves, staging map)
@@ -305,8 +352,9 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
         }
         if (!admit.empty()) {
             // raw edges of the admitted requests -> pinned staging -> one copy to the
-            // device staging area (tuple key buffer 1), then load
-            unsigned long long *stg = c->tu_key[1];
+            // device staging (on the upload stream, once the previous load from it
+            // is done), then load on the compute stream after that copy
+            const unsigned long long *stg = (const unsigned long long *)S->d_stage;
             const auto c0 = std::chrono::steady_clock::now();
             S->segs.clear();
             for (size_t j = 0; j < admit.size(); ++j)
@@ -314,18 +362,25 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
             S->copier->copy(S->segs);
             S->w_copy += seconds_since(c0);
             if (stage) {
-                GESMC_TRY(check_hip(hipMemcpyAsync(stg, S->h_pin, stage * 8, hipMemcpyHostToDevice, s),
+                if (S->load_recorded)
+                    GESMC_TRY(check_hip(hipStreamWaitEvent(S->up, S->load_ev, 0), "hipStreamWaitEvent"));
+                GESMC_TRY(check_hip(hipMemcpyAsync(S->d_stage, S->h_pin, stage * 8, hipMemcpyHostToDevice, S->up),
                                     "hipMemcpyAsync"));
-                GESMC_TRY(check_hip(hipEventRecord(S->stage_ev, s), "hipEventRecord"));
+                GESMC_TRY(check_hip(hipEventRecord(S->stage_ev, S->up), "hipEventRecord"));
                 S->stage_pending = true;
+                GESMC_TRY(check_hip(hipStreamWaitEvent(s, S->stage_ev, 0), "hipStreamWaitEvent"));
             }
             GESMC_TRY(up_copy(c, s, S->d_stage_off, S->h_stage_off.data(), (nadm + 1) * 8ull));
             GESMC_TRY(up_copy(c, s, S->d_stage_rank, S->h_stage_rank.data(), nadm * 4ull));
             if (stage > 0)
                 GESMC_TRY(launch(c, s, KID_LOAD, stage, k_load_batch, dim3(grid_stride_blocks(c, stage)),
-                                 dim3(kBlock), 0, (const unsigned long long *)stg, (uint32_t)stage,
+                                 dim3(kBlock), 0, stg, (uint32_t)stage,
                                  (const uint64_t *)S->d_stage_off, nadm, (const uint32_t *)S->d_stage_rank,
                                  (const BatchGraph *)c->gr, c->idx[1], c->key[1], c->err + 8, c->err + 9, c->gerr));
+            if (stage) {
+                GESMC_TRY(check_hip(hipEventRecord(S->load_ev, s), "hipEventRecord"));
+                S->load_recorded = true;
+            }
         }
         std::swap(c->idx[0], c->idx[1]);
         std::swap(c->key[0], c->key[1]);
@@ -339,13 +394,19 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
     }
     F.tuple_bytes = c->tuple_bytes;
-    // results of the graphs finishing now (discarded on the host if flagged)
+    // results of the graphs finishing now (discarded on the host if flagged),
+    // downloaded on the download stream while the next iteration computes
     if (n_out) {
-        unsigned long long *res = c->tu_key[2];
         GESMC_TRY(launch(c, s, KID_UNPERMUTE, rpos, k_extract, dim3(n_out), dim3(kBlock), 0,
                          (const uint4 *)c->chunks + n_fill + n_move, (const uint32_t *)c->idx[0],
-                         (const unsigned long long *)c->key[0], (const BatchGraph *)c->gr, res));
-        GESMC_TRY(check_hip(hipMemcpyAsync(F.h_res, res, rpos * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
+                         (const unsigned long long *)c->key[0], (const BatchGraph *)c->gr,
+                         (unsigned long long *)F.d_res));
+        GESMC_TRY(check_hip(hipEventRecord(F.ext, s), "hipEventRecord"));
+        GESMC_TRY(check_hip(hipStreamWaitEvent(S->down, F.ext, 0), "hipStreamWaitEvent"));
+        GESMC_TRY(check_hip(hipMemcpyAsync(F.h_res, F.d_res, rpos * 8, hipMemcpyDeviceToHost, S->down),
+                            "hipMemcpyAsync"));
+        GESMC_TRY(check_hip(hipEventRecord(F.res_ev, S->down), "hipEventRecord"));
+        F.res_pending = true;
     }
     GESMC_TRY(check_hip(hipMemcpyAsync(F.h_err, c->err, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(F.h_ctr, c->ctr, k * sizeof(StepCounters), hipMemcpyDeviceToHost, s),
@@ -378,6 +439,10 @@ void serve_release_locked(gesmc_server *S, ServeReq *R) {
 gesmc_status serve_complete(gesmc_server *S, ServeFlight &F) {
     const auto w0 = std::chrono::steady_clock::now();
     GESMC_TRY(check_hip(hipEventSynchronize(F.done), "hipEventSynchronize"));
+    if (F.res_pending) {
+        GESMC_TRY(check_hip(hipEventSynchronize(F.res_ev), "hipEventSynchronize"));
+        F.res_pending = false;
+    }
     const auto c0 = std::chrono::steady_clock::now();
     S->w_wait += std::chrono::duration<double>(c0 - w0).count();
     if (F.h_err[0] != 0) {
@@ -435,9 +500,13 @@ gesmc_status serve_complete(gesmc_server *S, ServeFlight &F) {
 // flight holds or that is resident.
 void serve_drain_locked(gesmc_server *S, gesmc_status st) {
     (void)hipStreamSynchronize(S->s);
+    (void)hipStreamSynchronize(S->up);
+    (void)hipStreamSynchronize(S->down);
     (void)hipGetLastError();
     S->stage_pending = false;
+    S->load_recorded = false;
     for (ServeFlight &F : S->fl) {
+        F.res_pending = false;
         for (ServeReq *R : F.ranks) R->flights = 0;
         for (ServeReq *R : F.ranks)
             if (!R->finished) serve_finish_locked(S, R, st);
@@ -614,10 +683,17 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
     if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_mv, max_graphs * sizeof(uint2));
     if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_stage_off, (max_graphs + 1) * 8ull);
     if (st == GESMC_OK) st = dev_alloc(c, (void **)&S->d_stage_rank, max_graphs * 4ull);
-    if (st == GESMC_OK && hipEventCreateWithFlags(&S->stage_ev, hipEventDisableTiming) != hipSuccess) st = GESMC_E_DEVICE;
+    if (st == GESMC_OK && (hipEventCreateWithFlags(&S->stage_ev, hipEventDisableTiming) != hipSuccess ||
+                           hipEventCreateWithFlags(&S->load_ev, hipEventDisableTiming) != hipSuccess)) {
+        (void)hipGetLastError();
+        set_error("hipEventCreate failed");
+        st = GESMC_E_DEVICE;
+    }
     for (ServeFlight &F : S->fl) {
         if (st != GESMC_OK) break;
         if (hipEventCreateWithFlags(&F.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&F.ext, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&F.res_ev, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc((void **)&F.h_gacc, max_graphs * 32ull, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&F.h_gerr, max_graphs * 4ull, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&F.h_ctr, kServeBurstMax * sizeof(StepCounters), hipHostMallocDefault) !=
@@ -628,7 +704,9 @@ gesmc_status gesmc_server_create(gesmc_ctx *c, const gesmc_server_cfg *cfg, gesm
             st = GESMC_E_NOMEM;
         }
     }
-    if (st == GESMC_OK && hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) {
+    if (st == GESMC_OK && (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess ||
+                           hipStreamCreateWithFlags(&S->up, hipStreamNonBlocking) != hipSuccess ||
+                           hipStreamCreateWithFlags(&S->down, hipStreamNonBlocking) != hipSuccess)) {
         (void)hipGetLastError();
         set_error("hipStreamCreate failed");
         st = GESMC_E_DEVICE;
@@ -673,19 +751,23 @@ void gesmc_server_destroy(gesmc_server *S) {
         }
         S->reqs.clear();
     }
-    if (S->s) {
-        (void)hipStreamSynchronize(S->s);
-        (void)hipStreamDestroy(S->s);
-    }
-    for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank})
+    for (hipStream_t q : {S->s, S->up, S->down})
+        if (q) {
+            (void)hipStreamSynchronize(q);
+            (void)hipStreamDestroy(q);
+        }
+    for (void *p : {(void *)S->d_mv, (void *)S->d_stage_off, (void *)S->d_stage_rank, (void *)S->d_stage,
+                    (void *)S->fl[0].d_res, (void *)S->fl[1].d_res})
         if (p) dev_free(S->c, p);
     S->c->serving = false;
     if (S->h_pin) (void)hipHostFree(S->h_pin);
-    if (S->stage_ev) (void)hipEventDestroy(S->stage_ev);
+    for (hipEvent_t e : {S->stage_ev, S->load_ev})
+        if (e) (void)hipEventDestroy(e);
     for (ServeFlight &F : S->fl) {
         for (void *p : {(void *)F.h_res, (void *)F.h_gacc, (void *)F.h_gerr, (void *)F.h_ctr, (void *)F.h_err})
             if (p) (void)hipHostFree(p);
-        if (F.done) (void)hipEventDestroy(F.done);
+        for (hipEvent_t e : {F.done, F.ext, F.res_ev})
+            if (e) (void)hipEventDestroy(e);
     }
     delete S;
 }
