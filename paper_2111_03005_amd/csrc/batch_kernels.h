@@ -325,9 +325,10 @@ __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads, kCompact> &
 
 // small_group with items produced on demand: item(q, &w, &g) returns whether
 // item q is present and sets its word and tag.  It is called twice per item
-// (count, then place), so only the cells and ranks stay in registers.
-template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact, typename Item>
-__device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact> &L, Item item) {
+// (count, then place), so only the cells and ranks stay in registers;
+// placed(q, slot) is told where each present item went.
+template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact, typename Item, typename Placed>
+__device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact> &L, Item item, Placed placed) {
     using Word = typename SmallKeys<kCompact>::Word;
     constexpr int kShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
     constexpr uint32_t kCells = 4 * kThreads;
@@ -355,6 +356,7 @@ __device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact
         const uint32_t slot = L.cell[cr[q] >> 16] + (cr[q] & 0xFFFFu);
         L.sK[slot] = w;
         L.sT[slot] = g;
+        placed(q, slot);
     }
     __syncthreads();
 }
@@ -385,91 +387,156 @@ __device__ __forceinline__ int small_judge(const SmallLds<kMax, kThreads, kCompa
     return v;
 }
 
+// The permutation of superstep t: L.pi[x] = the local index at position x of
+// the order by (K_i, i).  Returns with a barrier passed.
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ void small_permute(SmallLds<kMax, kThreads, kCompact> &L, uint32_t m, uint32_t t,
+                                              uint32_t k0, uint32_t k1) {
+    using Word = typename SmallKeys<kCompact>::Word;
+    constexpr int kPer = (int)(kMax / kThreads);
+    // compact permutation words are K's high 32 bits (so their top bits are
+    // K's cell bits); equal words fall back to the full keys
+    constexpr int kCellShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
+    const uint32_t tid = threadIdx.x;
+    Word w[kPer];
+    uint16_t g[kPer];
+    bool pr[kPer];
+#pragma unroll
+    for (int x = 0; x < kPer; ++x) {
+        const uint32_t li = tid + x * kThreads;
+        pr[x] = li < m;
+        const unsigned long long kf = pr[x] ? perm_key(li, t, k0, k1) : ~0ull;
+        w[x] = kCompact ? (Word)(kf >> 32) : (Word)kf;
+        g[x] = (uint16_t)li;
+    }
+    small_group<kPer>(L, w, g, pr);
+    // keys (K_i, i) are distinct: an index's place is the number of smaller
+    // keys in its cell (one grouped item per thread at a time; its word's top
+    // bits give its cell)
+    for (uint32_t y = tid; y < m; y += kThreads) {
+        const Word wy = L.sK[y];
+        const uint16_t gy = L.sT[y];
+        const uint32_t cc = (uint32_t)(wy >> kCellShift);
+        const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+        uint32_t rank = 0;
+        for (uint32_t z = a; z < e; ++z) {
+            const Word wz = L.sK[z];
+            const uint16_t gz = L.sT[z];
+            bool less = wz < wy;
+            if (wz == wy && gz != gy) {
+                if (kCompact) {  // equal high words (rare): compare the full keys
+                    const unsigned long long fz = perm_key(gz, t, k0, k1), fy = perm_key(gy, t, k0, k1);
+                    less = fz < fy || (fz == fy && gz < gy);
+                } else {
+                    less = gz < gy;
+                }
+            }
+            rank += less;
+        }
+        L.pi[a + rank] = gy;
+    }
+    __syncthreads();
+}
+
+// Permutations of supersteps t0 .. t0 + gridDim.x - 1 of an m-edge graph,
+// one workgroup each: row s of pi (kMax entries, the first m used) is the
+// permutation of superstep t0 + s.  They depend on nothing but (m, t, seed),
+// so k_small_plain takes them from here instead of computing them on its one
+// workgroup between supersteps.
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__global__ __launch_bounds__(kThreads) void k_small_perm(uint32_t m, uint32_t t0, uint32_t k0, uint32_t k1,
+                                                         uint16_t *__restrict__ pi) {
+    __shared__ SmallLds<kMax, kThreads, kCompact> L;
+    small_permute(L, m, t0 + blockIdx.x, k0, k1);
+    uint16_t *row = pi + (size_t)blockIdx.x * kMax;
+    for (uint32_t x = threadIdx.x; x < m; x += kThreads) row[x] = L.pi[x];
+}
+
 // All r supersteps of one graph in LDS.  L.E holds its m edge keys (local
 // ids) on entry and the result on exit; counts go to c[4] (legal, loop,
 // exists, P_L, per thread).  A duplicate edge (two ERASE tuples of one key
-// in the first superstep) sets L.flags.
-template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+// in the first superstep) sets L.flags.  kPre: the permutations of the r
+// supersteps are read from pre (k_small_perm rows), else computed here.
+template <bool kPre, uint32_t kMax, uint32_t kThreads, bool kCompact>
 __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompact> &L, uint32_t m, uint32_t r,
-                                                 uint32_t t0, uint32_t pl, uint32_t k0, uint32_t k1, uint32_t *c) {
+                                                 uint32_t t0, uint32_t pl, uint32_t k0, uint32_t k1, uint32_t *c,
+                                                 const uint16_t *__restrict__ pre) {
     using K = SmallKeys<kCompact>;
     using Word = typename K::Word;
     constexpr int kPer = (int)(kMax / kThreads);  // permutation items per thread
     constexpr int kSw = kPer / 2;                 // switches per thread
     constexpr int kTu = 4 * kSw + 1;              // tuples per thread (+ the idle record of odd m)
-    // compact permutation words are K's high 32 bits (so their top bits are
-    // K's cell bits); equal words fall back to the full keys
+    constexpr int kPiW = kPer / 2;                // 32-bit words of a permutation row per thread
+    constexpr uint8_t kAbsent = 0xFF;             // a switch index at or beyond ell
     constexpr int kCellShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
     const uint32_t tid = threadIdx.x;
-    const uint32_t ell = m >> 1;
+    const uint32_t ell = m >> 1, mw = (m + 1) >> 1;
+    uint32_t pw[kPiW];  // the next superstep's permutation row (kPre), loaded one superstep ahead
+    if (kPre) {
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(pre);
+#pragma unroll
+        for (int q = 0; q < kPiW; ++q) {
+            const uint32_t x = tid + q * kThreads;
+            pw[q] = x < mw ? row[x] : 0u;
+        }
+    }
     for (uint32_t s = 0; s < r; ++s) {
         const uint32_t t = t0 + s;
-        // permutation: sort local indices by (K_i, i)
-        {
-            Word w[kPer];
-            uint16_t g[kPer];
-            bool pr[kPer];
+        if (kPre) {
+            uint32_t *lp = reinterpret_cast<uint32_t *>(L.pi);
 #pragma unroll
-            for (int x = 0; x < kPer; ++x) {
-                const uint32_t li = tid + x * kThreads;
-                pr[x] = li < m;
-                const unsigned long long kf = pr[x] ? perm_key(li, t, k0, k1) : ~0ull;
-                w[x] = kCompact ? (Word)(kf >> 32) : (Word)kf;
-                g[x] = (uint16_t)li;
+            for (int q = 0; q < kPiW; ++q) {
+                const uint32_t x = tid + q * kThreads;
+                if (x < mw) lp[x] = pw[q];
             }
-            small_group<kPer>(L, w, g, pr);
-            // keys (K_i, i) are distinct: an index's place is the number of
-            // smaller keys in its cell (one grouped item per thread at a time;
-            // its word's top bits give its cell)
-            for (uint32_t y = tid; y < m; y += kThreads) {
-                {
-                    const Word wy = L.sK[y];
-                    const uint16_t gy = L.sT[y];
-                    const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                    const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
-                    uint32_t rank = 0;
-                    for (uint32_t z = a; z < e; ++z) {
-                        const Word wz = L.sK[z];
-                        const uint16_t gz = L.sT[z];
-                        bool less = wz < wy;
-                        if (wz == wy && gz != gy) {
-                            if (kCompact) {  // equal high words (rare): compare the full keys
-                                const unsigned long long fz = perm_key(gz, t, k0, k1), fy = perm_key(gy, t, k0, k1);
-                                less = fz < fy || (fz == fy && gz < gy);
-                            } else {
-                                less = gz < gy;
-                            }
-                        }
-                        rank += less;
-                    }
-                    L.pi[a + rank] = gy;
+            if (s + 1 < r) {
+                const uint32_t *row = reinterpret_cast<const uint32_t *>(pre + (size_t)(s + 1) * kMax);
+#pragma unroll
+                for (int q = 0; q < kPiW; ++q) {
+                    const uint32_t x = tid + q * kThreads;
+                    pw[q] = x < mw ? row[x] : 0u;
                 }
             }
             __syncthreads();
+        } else {
+            small_permute(L, m, t, k0, k1);
         }
-        // switches: local checks, then their tuples (4 per switch, + the idle
-        // record of odd m) grouped by word; a tuple's word is recomputed from
-        // the switch's records whenever the grouping needs it
-        {
+        // switches: local checks; this thread's switches (k = tid + y kThreads)
+        // keep their indices and status (byte y of sst) in registers
+        uint32_t sij[kSw];
+        uint32_t sst = 0;
+        auto st_of = [&](int y) -> uint32_t { return (sst >> (8 * y)) & 0xFFu; };
+        auto set_st = [&](int y, uint32_t v) { sst = (sst & ~(0xFFu << (8 * y))) | (v << (8 * y)); };
 #pragma unroll
-            for (int y = 0; y < kSw; ++y) {
-                const uint32_t k = tid + y * kThreads;
-                if (k >= ell) continue;
-                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
-                const unsigned long long e1 = K::unpack(L.E[i]), e2 = K::unpack(L.E[j]);
-                uint8_t status = ST_UNDECIDED;
-                if (pl_skip(k, t, pl, k0, k1)) {
-                    status = ST_PL;
-                } else {
-                    const Targets T = switch_targets(e1, e2, i < j);
-                    if (T.loop)
-                        status = ST_LOOP;
-                    else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
-                        status = ST_EXISTS;
-                }
-                L.st[k] = status;  // read back below by this thread only
-                L.info[2 * k] = L.info[2 * k + 1] = 0xFFFFFFFFu;
+        for (int y = 0; y < kSw; ++y) {
+            const uint32_t k = tid + y * kThreads;
+            set_st(y, kAbsent);
+            sij[y] = 0;
+            if (k >= ell) continue;
+            const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+            sij[y] = i | (j << 16);
+            const unsigned long long e1 = K::unpack(L.E[i]), e2 = K::unpack(L.E[j]);
+            uint8_t status = ST_UNDECIDED;
+            if (pl_skip(k, t, pl, k0, k1)) {
+                status = ST_PL;
+            } else {
+                const Targets T = switch_targets(e1, e2, i < j);
+                if (T.loop)
+                    status = ST_LOOP;
+                else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
+                    status = ST_EXISTS;
             }
+            set_st(y, status);
+            L.st[k] = status;
+            L.info[2 * k] = L.info[2 * k + 1] = 0xFFFFFFFFu;
+        }
+        // tuples (4 per switch, + the idle record of odd m) grouped by word,
+        // computed from the registers whenever the grouping needs them; the
+        // slots of this thread's INSERT tuples are kept
+        uint32_t islot[kSw];  // slots of the two INSERT tuples, 16 bits each
+#pragma unroll
+        for (int y = 0; y < kSw; ++y) islot[y] = 0;
+        {
             auto tuple = [&](int q, Word *w, uint16_t *g) -> bool {
                 if (q == kTu - 1) {  // the idle record of odd m survives the superstep
                     if (!((m & 1u) && tid == 0)) return false;
@@ -477,71 +544,95 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                     *g = kSmTagStays;
                     return true;
                 }
-                const uint32_t k = tid + (uint32_t)(q >> 2) * kThreads, h = (uint32_t)q & 3u;
-                if (k >= ell) return false;
-                const uint8_t status = L.st[k];
-                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+                const int y = q >> 2;
+                const uint32_t h = (uint32_t)q & 3u, k = tid + (uint32_t)y * kThreads;
+                if (st_of(y) == kAbsent) return false;
+                const uint32_t i = sij[y] & 0xFFFFu, j = sij[y] >> 16;
                 if (h < 2) {
                     *w = K::word(L.E[h ? j : i]);
-                    *g = status == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
+                    *g = st_of(y) == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
                     return true;
                 }
-                if (status != ST_UNDECIDED) return false;
+                if (st_of(y) != ST_UNDECIDED) return false;
                 const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
                 *w = K::word(K::pack(h == 2 ? T.A : T.B));
                 *g = (uint16_t)(kSmTagInsert | (k << 1) | (h - 2));
                 return true;
             };
-            small_group_fn<kTu>(L, tuple);
-            // all tuples of one key share a cell; each finds in its cell the
-            // group's smallest tag and the largest tag before it in (key, tag,
-            // slot) order: an ERASE tuple with one before it is a second
-            // eraser of its key (a duplicate edge); an INSERT tuple gets its
-            // eraser from the smallest tag and its predecessor from the one before
+            auto placed = [&](int q, uint32_t slot) {
+                if (q < kTu - 1 && (q & 3) == 2) islot[q >> 2] = slot;
+                if (q < kTu - 1 && (q & 3) == 3) islot[q >> 2] |= slot << 16;
+            };
+            small_group_fn<kTu>(L, tuple, placed);
+        }
+        // all tuples of one key share a cell.  Input duplicates (first
+        // superstep only: every later state is simple): an ERASE tuple with
+        // another ERASE tuple of its key before it in (key, tag, slot) order.
+        if (s == 0) {
             const uint32_t ntu = L.cell[4 * kThreads];
             for (uint32_t y = tid; y < ntu; y += kThreads) {
-                {
-                    const Word wy = L.sK[y];
-                    const uint16_t ty = L.sT[y];
-                    const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                    const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
-                    uint32_t first = ty, prev = 0;
-                    bool before = false;
-                    for (uint32_t z = a; z < e; ++z) {
-                        if (z == y || L.sK[z] != wy) continue;
-                        const uint16_t tz = L.sT[z];
-                        first = min(first, (uint32_t)tz);
-                        if (tz < ty || (tz == ty && z < y)) {
-                            prev = before ? max(prev, (uint32_t)tz) : tz;
-                            before = true;
-                        }
-                    }
-                    if (!(ty & kSmTagInsert)) {
-                        if (before) atomicOr(&L.flags, 1u);
-                        continue;
-                    }
-                    uint32_t eraser = kSmNone;
-                    if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
-                    const uint32_t pred =
-                        (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
-                    L.info[ty & ~kSmTagInsert] = (eraser << 16) | pred;
+                const uint16_t ty = L.sT[y];
+                if (ty & kSmTagInsert) continue;
+                const Word wy = L.sK[y];
+                const uint32_t cc = (uint32_t)(wy >> kCellShift);
+                const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                bool before = false;
+                for (uint32_t z = a; z < e; ++z) {
+                    if (z == y || L.sK[z] != wy) continue;
+                    const uint16_t tz = L.sT[z];
+                    before |= tz < ty || (tz == ty && z < y);
                 }
+                if (before) atomicOr(&L.flags, 1u);
             }
-            __syncthreads();
         }
+        // each INSERT tuple of an undecided switch finds in its cell its
+        // key group's smallest tag (-> eraser) and the largest tag before its
+        // own (-> predecessor inserter)
+#pragma unroll
+        for (int y = 0; y < kSw; ++y) {
+            if (st_of(y) != ST_UNDECIDED) continue;
+            const uint32_t k = tid + (uint32_t)y * kThreads;
+#pragma unroll 1
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint32_t sl = (islot[y] >> (16 * h)) & 0xFFFFu;
+                const Word wy = L.sK[sl];
+                const uint32_t ty = kSmTagInsert | (k << 1) | h;
+                const uint32_t cc = (uint32_t)(wy >> kCellShift);
+                const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                uint32_t first = ty, prev = 0;
+                bool before = false;
+                for (uint32_t z = a; z < e; ++z) {
+                    if (z == sl || L.sK[z] != wy) continue;
+                    const uint32_t tz = L.sT[z];
+                    first = min(first, tz);
+                    if (tz < ty) {  // INSERT tags are distinct
+                        prev = before ? max(prev, tz) : tz;
+                        before = true;
+                    }
+                }
+                uint32_t eraser = kSmNone;
+                if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
+                const uint32_t pred = (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
+                L.info[2 * k + h] = (eraser << 16) | pred;
+            }
+        }
+        __syncthreads();
         // rounds of decisions until every switch is decided
         for (;;) {
             if (tid == 0) L.undecided = 0;
             __syncthreads();
 #pragma unroll
             for (int y = 0; y < kSw; ++y) {
-                const uint32_t k = tid + y * kThreads;
-                if (k >= ell || L.st[k] != ST_UNDECIDED) continue;
+                if (st_of(y) != ST_UNDECIDED) continue;
+                const uint32_t k = tid + (uint32_t)y * kThreads;
                 const int v = max(small_judge(L, L.info[2 * k], k), small_judge(L, L.info[2 * k + 1], k));
-                if (v == V_WAIT)
+                if (v == V_WAIT) {
                     atomicAdd(&L.undecided, 1u);
-                else
-                    L.st[k] = v == V_OK ? ST_LEGAL : ST_EXISTS;
+                } else {
+                    const uint32_t d = v == V_OK ? ST_LEGAL : ST_EXISTS;
+                    set_st(y, d);
+                    L.st[k] = (uint8_t)d;
+                }
             }
             __syncthreads();
             const uint32_t left = L.undecided;
@@ -551,11 +642,9 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
         // writes and counts
 #pragma unroll
         for (int y = 0; y < kSw; ++y) {
-            const uint32_t k = tid + y * kThreads;
-            if (k >= ell) continue;
-            const uint8_t sv = L.st[k];
+            const uint32_t sv = st_of(y);
             if (sv == ST_LEGAL) {
-                const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
+                const uint32_t i = sij[y] & 0xFFFFu, j = sij[y] >> 16;
                 const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
                 L.E[i] = K::pack(T.A);
                 L.E[j] = K::pack(T.B);
@@ -600,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
     if (tid == 0) L.flags = 0;
     uint32_t c[4] = {0, 0, 0, 0};
     __syncthreads();
-    small_chain_body(L, b.m, rv[q], b.t0, b.pl, b.k0, b.k1, c);
+    small_chain_body<false>(L, b.m, rv[q], b.t0, b.pl, b.k0, b.k1, c, nullptr);
     for (uint32_t li = tid; li < b.m; li += kThreads) key[b.poff + li] = K::unpack(L.E[li]) + shift;
     small_flush_counts(L, c);
     if (tid < 4) acc[4 * (size_t)q + tid] = L.cnt[tid];  // one workgroup per graph
@@ -610,20 +699,25 @@ __global__ __launch_bounds__(kThreads) void k_small_chain(const uint32_t *__rest
     }
 }
 
-// The plain form on one small graph (m <= kMax, n < 2^16 if kCompact), in
-// one launch: loads and checks the input (canonical keys, ids < n, no loop),
-// runs every superstep in LDS, and writes d_out only if no error was found
-// (a duplicate shows in the first superstep).  Counts: acc[0 .. 3].
+// The plain form on one small graph (m <= kMax, n < 2^16 if kCompact), for
+// r supersteps in one launch: loads and checks the input (canonical keys,
+// ids < n, no loop), runs every superstep in LDS, and writes `out` only if no
+// error was found (a duplicate shows in the first superstep).  Counts are
+// added to acc[0 .. 3].  A call's supersteps may come in several launches,
+// each resuming from the last one's output (in may equal out); a launch
+// does nothing once an earlier one has set err[0].  pre: the r supersteps'
+// permutations (k_small_perm).
 template <uint32_t kMax, uint32_t kThreads, bool kCompact>
-__global__ __launch_bounds__(kThreads) void k_small_plain(const unsigned long long *__restrict__ in,
-                                                          unsigned long long *__restrict__ out, uint32_t m,
-                                                          uint32_t n, uint32_t t0, uint32_t r, uint32_t pl,
-                                                          uint32_t k0, uint32_t k1,
+__global__ __launch_bounds__(kThreads) void k_small_plain(const unsigned long long *in, unsigned long long *out,
+                                                          uint32_t m, uint32_t n, uint32_t t0, uint32_t r,
+                                                          uint32_t pl, uint32_t k0, uint32_t k1,
                                                           unsigned long long *__restrict__ acc,
-                                                          uint32_t *__restrict__ err) {
+                                                          uint32_t *__restrict__ err,
+                                                          const uint16_t *__restrict__ pre) {
     using K = SmallKeys<kCompact>;
     __shared__ SmallLds<kMax, kThreads, kCompact> L;
     const uint32_t tid = threadIdx.x;
+    if (err[0] != 0) return;  // uniform: written by an earlier launch
     if (tid < 4) L.cnt[tid] = 0;
     if (tid == 0) L.flags = 0;
     __syncthreads();
@@ -640,7 +734,7 @@ __global__ __launch_bounds__(kThreads) void k_small_plain(const unsigned long lo
     const uint32_t bad = L.flags;
     __syncthreads();
     uint32_t c[4] = {0, 0, 0, 0};
-    if (!bad) small_chain_body(L, m, r, t0, pl, k0, k1, c);  // uniform: every thread read the same flags
+    if (!bad) small_chain_body<true>(L, m, r, t0, pl, k0, k1, c, pre);  // uniform: every thread read the same flags
     small_flush_counts(L, c);
     const uint32_t fl = L.flags;
     if (fl) {
@@ -648,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_small_plain(const unsigned long lo
         return;
     }
     for (uint32_t li = tid; li < m; li += kThreads) out[li] = K::unpack(L.E[li]);
-    if (tid < 4) acc[tid] = L.cnt[tid];
+    if (tid < 4) acc[tid] += L.cnt[tid];
 }
 
 }  // namespace gesmc

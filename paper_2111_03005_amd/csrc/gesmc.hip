@@ -51,6 +51,11 @@ bool alloc_forbidden() {
     return true;
 }
 
+// Supersteps per piece of the small-graph path, and the bytes of its
+// permutation rows (one row of kCmpMax 16-bit entries per superstep).
+constexpr uint32_t kSmallPiSteps = 32;
+constexpr size_t kSmallPiBytes = (size_t)kSmallPiSteps * kCmpMax * sizeof(uint16_t);
+
 enum KernelId {
     KID_LOAD,
     KID_STEP_CLEAR,
@@ -87,6 +92,7 @@ enum KernelId {
     KID_DECIDE_LOCAL,
     KID_GEN,
     KID_GEN_HH_STEPS,
+    KID_SMALL_PERM,
     KID_COUNT
 };
 
@@ -98,7 +104,7 @@ const char *kKernelNames[KID_COUNT] = {
     "k_decide_chain1", "k_decide_chain", "k_finish_chain", "k_small_chain", "k_small_chain_4096",
     "k_small_chain_compact",
     "k_es_build",     "k_es_chain",     "k_mixing",     "k_decide_local", "k_gen",
-    "k_hh_steps"};
+    "k_hh_steps",     "k_small_perm"};
 
 __global__ void k_setup_level1(uint32_t *seg_off, uint32_t *tile_first, uint32_t m, uint32_t ntiles) {
     if (threadIdx.x == 0) {
@@ -173,6 +179,7 @@ struct gesmc_ctx {
     uint64_t cap_counts1 = 0, cap_counts2 = 0, cap_partial = 0;
     uint32_t *counts1 = nullptr, *counts2 = nullptr, *partial = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
+    uint16_t *small_pi = nullptr;  // permutations of the small-graph path (kSmallPiSteps rows of kCmpMax)
     uint4 *bslot = nullptr;     // per-block counts of the grid-stride kernels (2 grids)
     // batches: per graph (rank order) and per position
     uint64_t cap_g = 0, cap_pos = 0;
@@ -1034,25 +1041,48 @@ gesmc_status map_err(uint32_t e) {
     return GESMC_OK;
 }
 
-// The plain form on a graph that fits one workgroup's LDS (k_small_plain):
-// one launch, counts in the first counter record, no rounds recorded.
+// The plain form on a graph that fits one workgroup's LDS: per piece of at
+// most kSmallPiSteps supersteps, their permutations in parallel
+// (k_small_perm, one workgroup each), then the chain itself on one
+// workgroup (k_small_plain), which resumes from the previous piece's output.
+// Counts in the first counter record, no rounds recorded.
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+gesmc_status run_small_pieces(gesmc_ctx *c, hipStream_t s, int kid, const unsigned long long *in,
+                              unsigned long long *out, uint32_t m, uint32_t n, uint32_t t0, uint32_t r, uint32_t pl,
+                              uint32_t k0, uint32_t k1, unsigned long long *acc) {
+    static_assert(kMax <= kCmpMax, "permutation rows of the small-graph path hold kCmpMax entries");
+    for (uint32_t done = 0; done < r;) {
+        const uint32_t rr = std::min<uint32_t>(r - done, kSmallPiSteps);
+        GESMC_TRY(launch(c, s, KID_SMALL_PERM, (uint64_t)rr * m, k_small_perm<kMax, kThreads, kCompact>, dim3(rr),
+                         dim3(kThreads), 0, m, t0 + done, k0, k1, c->small_pi));
+        GESMC_TRY(launch(c, s, kid, m, k_small_plain<kMax, kThreads, kCompact>, dim3(1), dim3(kThreads), 0,
+                         done ? (const unsigned long long *)out : in, out, m, n, t0 + done, rr, pl, k0, k1, acc,
+                         c->err, (const uint16_t *)c->small_pi));
+        done += rr;
+    }
+    return GESMC_OK;
+}
+
 gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, uint64_t *d_out, uint32_t m,
                             uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     unsigned long long *acc = (unsigned long long *)c->ctr;  // legal, loop, exists, P_L
     const auto *in = (const unsigned long long *)d_in;
     auto *out = (unsigned long long *)d_out;
+    if (!c->small_pi) GESMC_TRY(dev_alloc(c, (void **)&c->small_pi, kSmallPiBytes));
     GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
     GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, c->err, (uint64_t)64));
+    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
+                     (uint64_t)(sizeof(StepCounters) / 4)));
     if (m <= kSmallMax)
-        GESMC_TRY(launch(c, s, KID_SMALL, m, k_small_plain<kSmallMax, kSmallThreads, false>, dim3(1),
-                         dim3(kSmallThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+        GESMC_TRY((run_small_pieces<kSmallMax, kSmallThreads, false>(c, s, KID_SMALL, in, out, m, n, t0, r, pl, k0,
+                                                                     k1, acc)));
     else if (m <= kMidMax)
-        GESMC_TRY(launch(c, s, KID_SMALL_MID, m, k_small_plain<kMidMax, kMidThreads, false>, dim3(1),
-                         dim3(kMidThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+        GESMC_TRY((run_small_pieces<kMidMax, kMidThreads, false>(c, s, KID_SMALL_MID, in, out, m, n, t0, r, pl, k0,
+                                                                 k1, acc)));
     else
-        GESMC_TRY(launch(c, s, KID_SMALL_CMP, m, k_small_plain<kCmpMax, kCmpThreads, true>, dim3(1),
-                         dim3(kCmpThreads), 0, in, out, m, n, t0, r, pl, k0, k1, acc, c->err));
+        GESMC_TRY((run_small_pieces<kCmpMax, kCmpThreads, true>(c, s, KID_SMALL_CMP, in, out, m, n, t0, r, pl, k0,
+                                                                k1, acc)));
     GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
@@ -1246,6 +1276,7 @@ struct RunBuffers {
     uint32_t *counts1, *counts2, *partial;
     uint64_t cap_counts1, cap_counts2, cap_partial;
     uint32_t *small;
+    uint16_t *small_pi;
     uint4 *bslot;
     StepCounters *ctr;
     uint64_t ctr_cap;
@@ -1276,6 +1307,7 @@ RunBuffers take_buffers(const gesmc_ctx *c) {
     b.cap_counts2 = c->cap_counts2;
     b.cap_partial = c->cap_partial;
     b.small = c->small;
+    b.small_pi = c->small_pi;
     b.bslot = c->bslot;
     b.ctr = c->ctr;
     b.ctr_cap = c->ctr_cap;
@@ -1312,6 +1344,7 @@ void put_buffers(gesmc_ctx *c, const RunBuffers &b) {
     c->cap_counts2 = b.cap_counts2;
     c->cap_partial = b.cap_partial;
     c->small = b.small;
+    c->small_pi = b.small_pi;
     c->bslot = b.bslot;
     c->ctr = b.ctr;
     c->ctr_cap = b.ctr_cap;
@@ -1374,6 +1407,7 @@ uint64_t carve_buffers(const gesmc_ctx *c, unsigned char *base, uint64_t m, RunB
     b.cap_counts2 = w2;
     const uint64_t nc = ((uint64_t)1 << kMaxCoarseBits) + 8;
     b.small = (uint32_t *)take((16 + 16 + 2 * nc + 8 + nfine + 8) * 4);
+    b.small_pi = (uint16_t *)take(kSmallPiBytes);
     b.bslot = (uint4 *)take((kEmitSlotsMax + 2 * (uint64_t)grid_stride_blocks(c, ~0ull >> 1)) * sizeof(uint4));
     b.ctr = (StepCounters *)take(kNoAllocChunk * sizeof(StepCounters));
     b.ctr_cap = kNoAllocChunk;
@@ -2032,6 +2066,7 @@ void gesmc_destroy(gesmc_ctx *c) {
     free_buffers(c);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->small) dev_free(c, c->small);
+    if (c->small_pi) dev_free(c, c->small_pi);
     if (c->bslot) dev_free(c, c->bslot);
     for (void *q : {(void *)c->gr, (void *)c->in_off, (void *)c->rank_of, (void *)c->gacc, (void *)c->pg,
                     (void *)c->bk, (void *)c->gerr, (void *)c->small_list, (void *)c->rrank, (void *)c->chunks})
