@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(const uint4 *__restrict__ ch
 //   m <= 6144 on 1024 threads with every vertex id below 2^16 ("compact":
 //   edge keys (min << 16) | max and 32-bit sort words, 151 KB).
 // Each thread holds kMax / kThreads permutation items and half as many
-// switches; there are four sort cells per thread.
+// switches; there are eight sort cells per thread.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSmallMax = 1024, kSmallThreads = 256;  // edges, threads
 constexpr uint32_t kMidMax = 4096, kMidThreads = 1024;
@@ -272,51 +272,89 @@ struct SmallLds {
     uint32_t info[kMax];              // per target 2k+h: eraser << 16 | predecessor
     uint16_t pi[kMax];                // the permutation of this superstep
     uint16_t sT[2 * kMax];            // sorted local index, then sorted tuple tag
-    uint32_t cell[4 * kThreads + 1];  // sort cells, four per thread
+    // sort cells: 16-bit counts, then offsets, eight per thread (two per
+    // word), and the total after them at entry 8 kThreads
+    alignas(16) uint32_t cellw[4 * kThreads + 4];
     uint32_t tmp[kThreads / 64 + 2];
     uint8_t st[kMax / 2];
-    uint32_t undecided, flags;
+    uint32_t und[3], flags;  // undecided counts of rounds 0, 1, 2 mod 3
     uint32_t cnt[4];
+    __device__ __forceinline__ uint32_t cell(uint32_t c) const {
+        return reinterpret_cast<const uint16_t *>(cellw)[c];
+    }
 };
 static_assert(kCmpMax / 2 < kSmTagStays && 2 * kCmpMax <= 0x10000, "small-graph tags are 16 bits");
 static_assert(kSmallMax % (2 * kSmallThreads) == 0 && kMidMax % (2 * kMidThreads) == 0 &&
                   kCmpMax % (2 * kCmpThreads) == 0, "whole switches per thread");
 
 template <uint32_t kThreads>
-constexpr int small_cell_bits() {  // 4 kThreads cells
-    return kThreads == 256 ? 10 : kThreads == 512 ? 11 : 12;
+constexpr int small_cell_bits() {  // 8 kThreads cells
+    return kThreads == 256 ? 11 : kThreads == 512 ? 12 : 13;
+}
+
+// The sort cells' 16-bit counters share 32-bit words (no count reaches 2^16,
+// so a half never carries into the other).  Zeroing: four words per thread.
+template <uint32_t kThreads>
+__device__ __forceinline__ void small_cells_zero(uint32_t *cellw) {
+    reinterpret_cast<uint4 *>(cellw)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Adds one to cell c; returns its count before.
+__device__ __forceinline__ uint32_t small_cell_add(uint32_t *cellw, uint32_t c) {
+    const uint32_t sh = (c & 1u) << 4;
+    return (atomicAdd(&cellw[c >> 1], 1u << sh) >> sh) & 0xFFFFu;
+}
+
+// Counts -> exclusive offsets in place (each thread its own eight cells),
+// the total at entry 8 kThreads.  Returns with a barrier passed.
+template <uint32_t kThreads>
+__device__ __forceinline__ void small_cells_scan(uint32_t *cellw, uint32_t *tmp) {
+    const uint32_t tid = threadIdx.x;
+    const uint4 q = reinterpret_cast<const uint4 *>(cellw)[tid];
+    uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sum += (w[i] & 0xFFFFu) + (w[i] >> 16);
+    uint32_t total;
+    uint32_t acc = block_exclusive_sum<kThreads>(sum, tmp, &total);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t c0 = w[i] & 0xFFFFu, c1 = w[i] >> 16;
+        w[i] = acc | ((acc + c0) << 16);
+        acc += c0 + c1;
+    }
+    reinterpret_cast<uint4 *>(cellw)[tid] = make_uint4(w[0], w[1], w[2], w[3]);
+    if (tid == 0) cellw[4 * kThreads] = total;
+    __syncthreads();
 }
 
 // Groups up to 2 kMax items by the top cell bits of their word: they sit in
 // registers (w[q], g[q] for q < kPer where present[q]); a counting sort puts
-// them in cell order into sK / sT (cell c spans [L.cell[c], L.cell[c + 1])).
-// Within a cell the order is arbitrary; callers then walk whole cells, four
-// per thread, so no per-item state outlives the grouping.  Returns with a
-// barrier passed.
+// them in cell order into sK / sT (cell c spans [L.cell(c), L.cell(c + 1))).
+// Within a cell the order is arbitrary; callers then walk whole cells, so no
+// per-item state outlives the grouping.  Returns with a barrier passed.
 template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact>
 __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads, kCompact> &L,
                                             const typename SmallKeys<kCompact>::Word *w, const uint16_t *g,
                                             const bool *present) {
     constexpr int kShift = 8 * (int)sizeof(typename SmallKeys<kCompact>::Word) - small_cell_bits<kThreads>();
-    constexpr uint32_t kCells = 4 * kThreads;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t c = tid; c < kCells; c += kThreads) L.cell[c] = 0;
+    (void)tid;
+    small_cells_zero<kThreads>(L.cellw);
     __syncthreads();
     uint32_t cl[kPer], rank[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
         cl[q] = (uint32_t)(w[q] >> kShift);
-        rank[q] = atomicAdd(&L.cell[cl[q]], 1u);
+        rank[q] = small_cell_add(L.cellw, cl[q]);
     }
     __syncthreads();
-    const uint32_t total = block_exclusive_scan<kThreads>(L.cell, kCells, L.tmp);
-    if (tid == 0) L.cell[kCells] = total;
-    __syncthreads();
+    small_cells_scan<kThreads>(L.cellw, L.tmp);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
-        const uint32_t slot = L.cell[cl[q]] + rank[q];
+        const uint32_t slot = L.cell(cl[q]) + rank[q];
         L.sK[slot] = w[q];
         L.sT[slot] = g[q];
     }
@@ -331,9 +369,7 @@ template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact, typename It
 __device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact> &L, Item item, Placed placed) {
     using Word = typename SmallKeys<kCompact>::Word;
     constexpr int kShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
-    constexpr uint32_t kCells = 4 * kThreads;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t c = tid; c < kCells; c += kThreads) L.cell[c] = 0;
+    small_cells_zero<kThreads>(L.cellw);
     __syncthreads();
     uint32_t cr[kPer];  // cell << 16 | rank within the cell (cells and ranks are below 2^16)
 #pragma unroll
@@ -342,23 +378,36 @@ __device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact
         uint16_t g;
         if (!item(q, &w, &g)) continue;
         const uint32_t cl = (uint32_t)(w >> kShift);
-        cr[q] = (cl << 16) | atomicAdd(&L.cell[cl], 1u);
+        cr[q] = (cl << 16) | small_cell_add(L.cellw, cl);
     }
     __syncthreads();
-    const uint32_t total = block_exclusive_scan<kThreads>(L.cell, kCells, L.tmp);
-    if (tid == 0) L.cell[kCells] = total;
-    __syncthreads();
+    small_cells_scan<kThreads>(L.cellw, L.tmp);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         Word w;
         uint16_t g;
         if (!item(q, &w, &g)) continue;
-        const uint32_t slot = L.cell[cr[q] >> 16] + (cr[q] & 0xFFFFu);
+        const uint32_t slot = L.cell(cr[q] >> 16) + (cr[q] & 0xFFFFu);
         L.sK[slot] = w;
         L.sT[slot] = g;
         placed(q, slot);
     }
     __syncthreads();
+}
+
+// Calls fn(z) for every slot z != self of the cell [a, e) whose word equals
+// wy.  The words are loaded four at a time, so a walk has several LDS loads
+// in flight instead of one after another.
+template <typename W, typename Fn>
+__device__ __forceinline__ void cell_matches(const W *sK, uint32_t a, uint32_t e, uint32_t self, W wy, Fn fn) {
+    for (uint32_t z0 = a; z0 < e; z0 += 4) {
+        W wz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) wz[u] = z0 + u < e ? sK[z0 + u] : wy;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (z0 + u < e && z0 + u != self && wz[u] == wy) fn(z0 + u);
+    }
 }
 
 // Alg. 1's rule for target 2k+h from its packed record (see judge_target_chain).
@@ -417,21 +466,29 @@ __device__ __forceinline__ void small_permute(SmallLds<kMax, kThreads, kCompact>
         const Word wy = L.sK[y];
         const uint16_t gy = L.sT[y];
         const uint32_t cc = (uint32_t)(wy >> kCellShift);
-        const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+        const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
         uint32_t rank = 0;
-        for (uint32_t z = a; z < e; ++z) {
-            const Word wz = L.sK[z];
-            const uint16_t gz = L.sT[z];
-            bool less = wz < wy;
-            if (wz == wy && gz != gy) {
-                if (kCompact) {  // equal high words (rare): compare the full keys
-                    const unsigned long long fz = perm_key(gz, t, k0, k1), fy = perm_key(gy, t, k0, k1);
-                    less = fz < fy || (fz == fy && gz < gy);
-                } else {
-                    less = gz < gy;
-                }
+        for (uint32_t z0 = a; z0 < e; z0 += 4) {  // four loads in flight
+            Word wz[4];
+            uint16_t gz[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                wz[u] = z0 + u < e ? L.sK[z0 + u] : wy;
+                gz[u] = z0 + u < e ? L.sT[z0 + u] : gy;
             }
-            rank += less;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bool less = wz[u] < wy;
+                if (wz[u] == wy && gz[u] != gy) {
+                    if (kCompact) {  // equal high words (rare): compare the full keys
+                        const unsigned long long fz = perm_key(gz[u], t, k0, k1), fy = perm_key(gy, t, k0, k1);
+                        less = fz < fy || (fz == fy && gz[u] < gy);
+                    } else {
+                        less = gz[u] < gy;
+                    }
+                }
+                rank += less;
+            }
         }
         L.pi[a + rank] = gy;
     }
@@ -442,11 +499,13 @@ __device__ __forceinline__ void small_permute(SmallLds<kMax, kThreads, kCompact>
 // one workgroup each: row s of pi (kMax entries, the first m used) is the
 // permutation of superstep t0 + s.  They depend on nothing but (m, t, seed),
 // so k_small_plain takes them from here instead of computing them on its one
-// workgroup between supersteps.
+// workgroup between supersteps.  zero: null, or 16 words to clear first (the
+// call's error word and counts, read by the k_small_plain launches after it).
 template <uint32_t kMax, uint32_t kThreads, bool kCompact>
 __global__ __launch_bounds__(kThreads) void k_small_perm(uint32_t m, uint32_t t0, uint32_t k0, uint32_t k1,
-                                                         uint16_t *__restrict__ pi) {
+                                                         uint16_t *__restrict__ pi, uint32_t *__restrict__ zero) {
     __shared__ SmallLds<kMax, kThreads, kCompact> L;
+    if (zero && blockIdx.x == 0 && threadIdx.x < 16) zero[threadIdx.x] = 0;
     small_permute(L, m, t0 + blockIdx.x, k0, k1);
     uint16_t *row = pi + (size_t)blockIdx.x * kMax;
     for (uint32_t x = threadIdx.x; x < m; x += kThreads) row[x] = L.pi[x];
@@ -502,9 +561,16 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
             small_permute(L, m, t, k0, k1);
         }
         // switches: local checks; this thread's switches (k = tid + y kThreads)
-        // keep their indices and status (byte y of sst) in registers
+        // keep their indices and status (byte y of sst) in registers, and with
+        // kPre (no permutation code beside them) their edge keys too
         uint32_t sij[kSw];
         uint32_t sst = 0;
+        constexpr int kSe = kPre ? kSw : 1;
+        typename K::Key se[kSe][2];
+        auto key_of = [&](int y, uint32_t h) -> typename K::Key {
+            if (kPre) return se[y < kSe ? y : 0][h];
+            return L.E[h ? sij[y] >> 16 : sij[y] & 0xFFFFu];
+        };
         auto st_of = [&](int y) -> uint32_t { return (sst >> (8 * y)) & 0xFFu; };
         auto set_st = [&](int y, uint32_t v) { sst = (sst & ~(0xFFu << (8 * y))) | (v << (8 * y)); };
 #pragma unroll
@@ -515,7 +581,12 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
             if (k >= ell) continue;
             const uint32_t i = L.pi[2 * k], j = L.pi[2 * k + 1];
             sij[y] = i | (j << 16);
-            const unsigned long long e1 = K::unpack(L.E[i]), e2 = K::unpack(L.E[j]);
+            const typename K::Key ki = L.E[i], kj = L.E[j];
+            if (kPre) {
+                se[y < kSe ? y : 0][0] = ki;
+                se[y < kSe ? y : 0][1] = kj;
+            }
+            const unsigned long long e1 = K::unpack(ki), e2 = K::unpack(kj);
             uint8_t status = ST_UNDECIDED;
             if (pl_skip(k, t, pl, k0, k1)) {
                 status = ST_PL;
@@ -549,12 +620,12 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                 if (st_of(y) == kAbsent) return false;
                 const uint32_t i = sij[y] & 0xFFFFu, j = sij[y] >> 16;
                 if (h < 2) {
-                    *w = K::word(L.E[h ? j : i]);
+                    *w = K::word(key_of(y, h));
                     *g = st_of(y) == ST_UNDECIDED ? (uint16_t)k : kSmTagStays;
                     return true;
                 }
                 if (st_of(y) != ST_UNDECIDED) return false;
-                const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
+                const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
                 *w = K::word(K::pack(h == 2 ? T.A : T.B));
                 *g = (uint16_t)(kSmTagInsert | (k << 1) | (h - 2));
                 return true;
@@ -569,19 +640,18 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
         // superstep only: every later state is simple): an ERASE tuple with
         // another ERASE tuple of its key before it in (key, tag, slot) order.
         if (s == 0) {
-            const uint32_t ntu = L.cell[4 * kThreads];
+            const uint32_t ntu = L.cell(8 * kThreads);
             for (uint32_t y = tid; y < ntu; y += kThreads) {
                 const uint16_t ty = L.sT[y];
                 if (ty & kSmTagInsert) continue;
                 const Word wy = L.sK[y];
                 const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
                 bool before = false;
-                for (uint32_t z = a; z < e; ++z) {
-                    if (z == y || L.sK[z] != wy) continue;
+                cell_matches(L.sK, a, e, y, wy, [&](uint32_t z) {
                     const uint16_t tz = L.sT[z];
                     before |= tz < ty || (tz == ty && z < y);
-                }
+                });
                 if (before) atomicOr(&L.flags, 1u);
             }
         }
@@ -592,42 +662,50 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
         for (int y = 0; y < kSw; ++y) {
             if (st_of(y) != ST_UNDECIDED) continue;
             const uint32_t k = tid + (uint32_t)y * kThreads;
+            Word tw[2] = {0, 0};  // the two INSERT words, from the keys in registers (kPre)
+            if (kPre) {
+                const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)),
+                                                 (sij[y] & 0xFFFFu) < (sij[y] >> 16));
+                tw[0] = K::word(K::pack(T.A));
+                tw[1] = K::word(K::pack(T.B));
+            }
 #pragma unroll 1
             for (uint32_t h = 0; h < 2; ++h) {
                 const uint32_t sl = (islot[y] >> (16 * h)) & 0xFFFFu;
-                const Word wy = L.sK[sl];
+                const Word wy = kPre ? (h ? tw[1] : tw[0]) : L.sK[sl];
                 const uint32_t ty = kSmTagInsert | (k << 1) | h;
                 const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                const uint32_t a = L.cell[cc], e = L.cell[cc + 1];
+                const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
                 uint32_t first = ty, prev = 0;
                 bool before = false;
-                for (uint32_t z = a; z < e; ++z) {
-                    if (z == sl || L.sK[z] != wy) continue;
+                cell_matches(L.sK, a, e, sl, wy, [&](uint32_t z) {
                     const uint32_t tz = L.sT[z];
                     first = min(first, tz);
                     if (tz < ty) {  // INSERT tags are distinct
                         prev = before ? max(prev, tz) : tz;
                         before = true;
                     }
-                }
+                });
                 uint32_t eraser = kSmNone;
                 if (!(first & kSmTagInsert)) eraser = first == kSmTagStays ? kSmStays : first;
                 const uint32_t pred = (before && (prev & kSmTagInsert)) ? (prev & ~(uint32_t)kSmTagInsert) : kSmNone;
                 L.info[2 * k + h] = (eraser << 16) | pred;
             }
         }
+        if (tid == 0) L.und[0] = 0;
         __syncthreads();
-        // rounds of decisions until every switch is decided
-        for (;;) {
-            if (tid == 0) L.undecided = 0;
-            __syncthreads();
+        // rounds of decisions until every switch is decided, one barrier each:
+        // round x counts its waits in und[x mod 3] and clears und[x + 1 mod 3],
+        // which was last read in round x - 2
+        for (uint32_t x = 0;; x = x == 2 ? 0 : x + 1) {
+            if (tid == 0) L.und[x == 2 ? 0 : x + 1] = 0;
 #pragma unroll
             for (int y = 0; y < kSw; ++y) {
                 if (st_of(y) != ST_UNDECIDED) continue;
                 const uint32_t k = tid + (uint32_t)y * kThreads;
                 const int v = max(small_judge(L, L.info[2 * k], k), small_judge(L, L.info[2 * k + 1], k));
                 if (v == V_WAIT) {
-                    atomicAdd(&L.undecided, 1u);
+                    atomicAdd(&L.und[x], 1u);
                 } else {
                     const uint32_t d = v == V_OK ? ST_LEGAL : ST_EXISTS;
                     set_st(y, d);
@@ -635,9 +713,7 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                 }
             }
             __syncthreads();
-            const uint32_t left = L.undecided;
-            __syncthreads();
-            if (left == 0) break;
+            if (L.und[x] == 0) break;  // uniform: no count of round x changes after the barrier
         }
         // writes and counts
 #pragma unroll
@@ -645,7 +721,7 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
             const uint32_t sv = st_of(y);
             if (sv == ST_LEGAL) {
                 const uint32_t i = sij[y] & 0xFFFFu, j = sij[y] >> 16;
-                const Targets T = switch_targets(K::unpack(L.E[i]), K::unpack(L.E[j]), i < j);
+                const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
                 L.E[i] = K::pack(T.A);
                 L.E[j] = K::pack(T.B);
                 ++c[0];

@@ -1043,9 +1043,11 @@ gesmc_status map_err(uint32_t e) {
 
 // The plain form on a graph that fits one workgroup's LDS: per piece of at
 // most kSmallPiSteps supersteps, their permutations in parallel
-// (k_small_perm, one workgroup each), then the chain itself on one
-// workgroup (k_small_plain), which resumes from the previous piece's output.
-// Counts in the first counter record, no rounds recorded.
+// (k_small_perm, one workgroup each; the first also clears the error word
+// and the counts), then the chain itself on one workgroup (k_small_plain),
+// which resumes from the previous piece's output.  The counts (legal, loop,
+// exists, P_L) go to error words 8 .. 15, so one copy brings back both; no
+// rounds are recorded.
 template <uint32_t kMax, uint32_t kThreads, bool kCompact>
 gesmc_status run_small_pieces(gesmc_ctx *c, hipStream_t s, int kid, const unsigned long long *in,
                               unsigned long long *out, uint32_t m, uint32_t n, uint32_t t0, uint32_t r, uint32_t pl,
@@ -1054,7 +1056,7 @@ gesmc_status run_small_pieces(gesmc_ctx *c, hipStream_t s, int kid, const unsign
     for (uint32_t done = 0; done < r;) {
         const uint32_t rr = std::min<uint32_t>(r - done, kSmallPiSteps);
         GESMC_TRY(launch(c, s, KID_SMALL_PERM, (uint64_t)rr * m, k_small_perm<kMax, kThreads, kCompact>, dim3(rr),
-                         dim3(kThreads), 0, m, t0 + done, k0, k1, c->small_pi));
+                         dim3(kThreads), 0, m, t0 + done, k0, k1, c->small_pi, done ? nullptr : c->err));
         GESMC_TRY(launch(c, s, kid, m, k_small_plain<kMax, kThreads, kCompact>, dim3(1), dim3(kThreads), 0,
                          done ? (const unsigned long long *)out : in, out, m, n, t0 + done, rr, pl, k0, k1, acc,
                          c->err, (const uint16_t *)c->small_pi));
@@ -1066,14 +1068,11 @@ gesmc_status run_small_pieces(gesmc_ctx *c, hipStream_t s, int kid, const unsign
 gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, uint64_t *d_out, uint32_t m,
                             uint32_t n, uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    unsigned long long *acc = (unsigned long long *)c->ctr;  // legal, loop, exists, P_L
+    unsigned long long *acc = (unsigned long long *)(c->err + 8);  // legal, loop, exists, P_L
     const auto *in = (const unsigned long long *)d_in;
     auto *out = (unsigned long long *)d_out;
     if (!c->small_pi) GESMC_TRY(dev_alloc(c, (void **)&c->small_pi, kSmallPiBytes));
     GESMC_TRY(check_hip(hipEventRecord(c->call_a, s), "hipEventRecord"));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, c->err, (uint64_t)64));
-    GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(1), dim3(256), 0, (uint32_t *)c->ctr,
-                     (uint64_t)(sizeof(StepCounters) / 4)));
     if (m <= kSmallMax)
         GESMC_TRY((run_small_pieces<kSmallMax, kSmallThreads, false>(c, s, KID_SMALL, in, out, m, n, t0, r, pl, k0,
                                                                      k1, acc)));
@@ -1084,21 +1083,20 @@ gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, u
         GESMC_TRY((run_small_pieces<kCmpMax, kCmpThreads, true>(c, s, KID_SMALL_CMP, in, out, m, n, t0, r, pl, k0,
                                                                 k1, acc)));
     GESMC_TRY(check_hip(hipEventRecord(c->call_b, s), "hipEventRecord"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
-    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_ctr, c->ctr, sizeof(StepCounters), hipMemcpyDeviceToHost, s),
-                        "hipMemcpyAsync"));
+    GESMC_TRY(check_hip(hipMemcpyAsync(c->h_err, c->err, 64, hipMemcpyDeviceToHost, s), "hipMemcpyAsync"));
     GESMC_TRY(check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"));
     if (c->profile) collect_profile(c);
     GESMC_TRY(map_err(*c->h_err));
     if (stats) {
-        const StepCounters &h = c->h_ctr[0];
+        uint64_t h[4];
+        memcpy(h, c->h_err + 8, sizeof(h));
         memset(stats, 0, sizeof(*stats));
         stats->supersteps = r;
         stats->attempts = (uint64_t)r * (m / 2);
-        stats->legal = h.legal;
-        stats->rej_loop = h.rej_loop;
-        stats->rej_exists = h.rej_exists;
-        stats->rej_pl = h.rej_pl;
+        stats->legal = h[0];
+        stats->rej_loop = h[1];
+        stats->rej_exists = h[2];
+        stats->rej_pl = h[3];
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->call_a, c->call_b) == hipSuccess)
             stats->ms_device = ms;
