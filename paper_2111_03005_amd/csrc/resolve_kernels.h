@@ -36,6 +36,7 @@ namespace gesmc {
 constexpr uint32_t kNoPred = 0xFFFFFFFFu;
 constexpr uint32_t kWalked = 0xFFFFFFFEu;  // a resumed walk that reached the chain's end
 constexpr uint32_t kListEnd = 0xFFFFu;  // end of a cell list in k_resolve (slots are < 2^16)
+constexpr uint32_t kEpochNone = 0xFFFFu;  // k_resolve: no list partition yet (epochs are 0 .. 0xFFFE)
 #ifndef GESMC_RESOLVE_LISTS
 #define GESMC_RESOLVE_LISTS 1
 #endif
@@ -321,23 +322,26 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
     const uint32_t lds_cap = min(cap, (uint32_t)(kSortMaxItems * kBlock));
     const uint64_t code_mask = kPacked ? low_mask(pk.kb + 1) : 0ull;
 
-    for (uint32_t f = blockIdx.x; f < np; f += gridDim.x) {
-        const uint32_t begin = part_off[f], end = part_off[f + 1];
-        uint32_t c_tag[kSortMaxItems];
-        unsigned long long c_key[kSortMaxItems];
+    // cell lists: each cell word is (epoch << 16) | head slot, where the
+    // epoch counts this workgroup's list-resolved partitions; a word of an
+    // older epoch is an empty list, so no partition clears the cells
+    uint32_t epoch = kEpochNone;
+    // partition g's tuples (raw packed words, decoded at their first use)
+    uint32_t c_tag[kSortMaxItems];
+    unsigned long long c_key[kSortMaxItems];
+    uint32_t begin = 0, end = 0;
+    auto load_part = [&](uint32_t g) {
+        begin = part_off[g];
+        end = part_off[g + 1];
 #pragma unroll
         for (int q = 0; q < kSortMaxItems; ++q) {
             const uint32_t p = begin + tid + q * kBlock;
-            if (kPacked) {
-                // raw words, decoded at their first use below: the loads stay in
-                // flight across the cell initialisation and its barrier
-                c_tag[q] = 0u;
-                c_key[q] = p < end ? tu_key[p] : 0ull;
-            } else {
-                c_tag[q] = p < end ? tu_tag[p] : 0u;
-                c_key[q] = p < end ? tu_key[p] : 0ull;
-            }
+            c_tag[q] = (!kPacked && p < end) ? tu_tag[p] : 0u;
+            c_key[q] = p < end ? tu_key[p] : 0ull;
         }
+    };
+    if (blockIdx.x < np) load_part(blockIdx.x);
+    for (uint32_t f = blockIdx.x; f < np; f += gridDim.x) {
         const uint32_t c = end > begin ? end - begin : 0;
         if (kPacked && c > lds_cap) {
             // exact slow path over packed words: their order is (key, tag)
@@ -459,8 +463,14 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
             // Packed words stay whole in sK (key bits and tag code), with no
             // tag array: 10 bytes of LDS per tuple instead of 14.
             uint16_t *nxt = reinterpret_cast<uint16_t *>(kPacked ? reinterpret_cast<uint32_t *>(sK + cap) : sT + cap);
-            for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = kListEnd;
-            lds_barrier();
+            if (epoch >= kEpochNone - 1) {  // first list partition, or the epochs wrap: every list empty
+                for (uint32_t q = tid; q < kCells; q += kBlock) cell[q] = 0xFFFFFFFFu;
+                lds_barrier();
+                epoch = 0;
+            } else {
+                ++epoch;
+            }
+            const uint32_t ep = epoch << 16;
             uint32_t r_cell[kSortMaxItems];
 #pragma unroll
             for (int q = 0; q < kSortMaxItems; ++q) {
@@ -475,7 +485,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                     r_cell[q] = (uint32_t)((pbits >= 64 ? 0ull : (hsh << pbits)) >> sub_shift);
                     sK[p] = raw;
                     if (!kPacked) sT[p] = c_tag[q];
-                    nxt[p] = (uint16_t)atomicExch(&cell[r_cell[q]], p);
+                    const uint32_t old = atomicExch(&cell[r_cell[q]], ep | p);
+                    nxt[p] = (old & 0xFFFF0000u) == ep ? (uint16_t)old : (uint16_t)kListEnd;
                 }
             }
             lds_barrier();
@@ -491,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 const uint32_t tx = c_tag[q];
                 uint32_t first_tag = tx, prev_tag = 0;
                 bool before = false;
-                for (uint32_t y = cell[r_cell[q]]; y != kListEnd; y = nxt[y]) {
+                for (uint32_t y = cell[r_cell[q]] & 0xFFFFu; y != kListEnd; y = nxt[y]) {
                     const unsigned long long wy = sK[y];
                     if (y == p || (kPacked ? (wy & ~code_mask) : wy) != kx) continue;
                     const uint32_t ty = kPacked ? tag_of_code((uint32_t)(wy & code_mask), pk.kb) : sT[y];
@@ -559,8 +570,12 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t *__restrict__ tu_ta
                 }
                 resolve_one(tx, first_tag, before ? 1u : 0u, 0u, prev_tag, kx, f, pk, info, err, dup_bit, ge);
             }
-            lds_barrier();
         }
+        // the next partition's loads are issued before the barrier that ends
+        // this one (every walk done before the cells are linked again), so
+        // they are in flight while the slowest wave finishes
+        if (f + gridDim.x < np) load_part(f + gridDim.x);
+        lds_barrier();
     }
 }
 
