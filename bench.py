@@ -712,8 +712,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--plain-sample-stride", type=int, default=8)
     ap.add_argument("--no-served", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[10.0, 30.0, 100.0, 300.0, 1000.0])
-    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate (at most)")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[10.0, 30.0, 100.0, 300.0, 1000.0, 3000.0])
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per rate (at most)")
     ap.add_argument("--serve-window", type=float, default=4.0,
                     help="seconds of arrivals per rate at low rates (at least 40 requests)")
     ap.add_argument("--serve-pool", type=int, default=128)

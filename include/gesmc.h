@@ -498,7 +498,9 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
 #define GESMC_OPT_PACK_TUPLES 12   /* 1: dependency tuples travel as one 8-byte word (a bijective hash of
                                       the edge key on 2 x the vertex id bits, minus the bits the first
                                       partition pass implies, over a coded tag) wherever those bits and
-                                      the tag fit 64; 0: always (tag u32, key hash u64) (default 1)    */
+                                      the tag fit 64 -- in a batch too large for batch-wide switch ids,
+                                      with tags local to each graph; 0: always (tag u32, key hash u64);
+                                      2: as 1, with graph-local tags in every batch (default 1)        */
 #define GESMC_OPT_PROFILE_ONLY 7 /* kernel id whose launches are timed while profiling; -1 = every
                                     kernel (default).  Events between launches cost time, so timing
                                     one kernel disturbs the rest least                              */

@@ -209,7 +209,7 @@ struct gesmc_ctx {
     void *alloc_user = nullptr;
     std::unordered_map<void *, HookedBuffer> hooked;  // live buffers of caller allocators
     bool serving = false;                             // a gesmc_server owns the context
-    bool pack_tuples = true;                          // 8-byte tuple words where the bits allow
+    int pack_tuples = 1;  // 8-byte tuple words where the bits allow (2: batches always with graph-local tags)
     uint32_t tuple_bytes = 0;                         // tuple size of the call's last superstep
     StepCounters *ctr = nullptr;
     StepCounters *ctr_step = nullptr;  // counters of the superstep being enqueued
@@ -722,6 +722,7 @@ struct BatchStep {
     GraphErr ge;               // per-rank error attribution (gr = nullptr: none)
     uint64_t vend;             // vertex ids of the switched ranks are below this
     uint64_t dend;             // and so are the id offsets v - u of their edges (the largest n)
+    uint64_t mmax;             // the largest record count of a graph (even: mpad)
 };
 
 // Sorts the records of [0, m) of buffer `src` by (K_i, i) of superstep t --
@@ -799,28 +800,40 @@ int width_below(uint64_t x) {
 // left after the first level plus the tag code fit 64 bits, and at least
 // kCellBits hash bits remain below both levels for the resolve's cells.
 // w = 0: 12-byte tuples.
-TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_t vend, uint64_t dend) {
-    TuplePack pk{0, 0, 0, 0, 0};
+TuplePack tuple_pack(const gesmc_ctx *c, const Plan &p, uint32_t nslots, uint64_t vend, uint64_t dend,
+                     uint64_t mmax = 0) {
+    TuplePack pk{0, 0, 0, 0, 0, 0};
     if (!c->pack_tuples || vend < 2 || dend < 2) return pk;
     const int vb = width_below(vend), db = width_below(std::min(dend, vend)), w = vb + db;
-    const int kb = std::max(1, width_below(2ull * (nslots / 4) + 1));  // 2 ell < 2^kb, so ell < 2^kb - 1
+    int kb = std::max(1, width_below(2ull * (nslots / 4) + 1));  // 2 ell < 2^kb, so ell < 2^kb - 1
+    int local = 0;
+    if ((w - (int)p.b1 + kb + 1 > 64 || c->pack_tuples == 2) && mmax > 0) {
+        // a batch (mmax: its largest even record count): tags local to each
+        // graph, codes below mmax, so its switches k < mmax / 2 < 2^kb - 1
+        kb = std::max(1, width_below(mmax + 1));
+        local = 1;
+    }
     if (w > 62 || w - (int)p.b1 + kb + 1 > 64 || w - (int)p.bbits < kCellBits) return pk;
     pk.w = w;
     pk.db = db;
     pk.kb = kb;
     pk.b1 = (int)p.b1;
     pk.b2 = (int)p.b2;
+    pk.local = local;
     return pk;
 }
 
 gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots, uint32_t dup_bit,
                                    GraphErr ge = GraphErr{nullptr, 0, nullptr}, const EmitSource *emit = nullptr,
-                                   uint64_t vend = 0, uint64_t dend = 0, const EmitOut *eo = nullptr) {
+                                   uint64_t vend = 0, uint64_t dend = 0, const EmitOut *eo = nullptr,
+                                   uint64_t mmax = 0) {
     const Plan p = make_plan(c, nslots);
     int parts = 0;
     const uint32_t *poff = nullptr;
     uint32_t np = 0;
-    const TuplePack pk = emit ? tuple_pack(c, p, nslots, vend, dend) : TuplePack{0, 0, 0, 0, 0};
+    // graph-local tags need the graphs (emit: their first switches; resolve: the key's graph)
+    const TuplePack pk = emit ? tuple_pack(c, p, nslots, vend, dend, (ge.gr && emit->sa.pg) ? mmax : 0)
+                              : TuplePack{0, 0, 0, 0, 0, 0};
     c->tuple_bytes = pk.w ? 8u : 12u;
     if (pk.w) {
         SrcArgs sa = emit->sa;
@@ -852,7 +865,7 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
     GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<false>,
                      dim3(persistent_blocks(c, k_resolve<false>, rlds, np)), dim3(kBlock), rlds, c->tu_tag[parts],
                      c->tu_key[parts], c->tu_tag[scratch], c->tu_key[scratch], (int)p.bbits, poff, np, c->sort_cap,
-                     c->info, c->err, dup_bit, c->ctr_step, ge, TuplePack{0, 0, 0, 0, 0}));
+                     c->info, c->err, dup_bit, c->ctr_step, ge, TuplePack{0, 0, 0, 0, 0, 0}));
     return GESMC_OK;
 }
 
@@ -893,7 +906,7 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
                          si, sk, t, k0, k1, sa, nslots, c->tu_tag[0], c->tu_key[0]));
     GESMC_TRY(partition_and_resolve(c, s, nslots, dup_bit, bs ? bs->ge : GraphErr{nullptr, 0, nullptr},
                                     c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend, bs ? bs->dend : vend,
-                                    fused ? &eo : nullptr));
+                                    fused ? &eo : nullptr, bs ? bs->mmax : 0));
     if (p.ell == 0) return GESMC_OK;
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -1684,7 +1697,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
     c->h_mid.clear();
     c->h_cmp.clear();
     c->h_rrank.assign(G, 0);
-    uint64_t poff = 0, vbase = 0, bbase = 0, nmax = 0;
+    uint64_t poff = 0, vbase = 0, bbase = 0, nmax = 0, mmax = 0;
     uint32_t nactive = 0, rmax = 0;
     bool need_validation = false;
     for (uint32_t q = 0; q < G; ++q) {
@@ -1710,6 +1723,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         poff += b.mpad;
         vbase += nv[g];
         nmax = std::max<uint64_t>(nmax, nv[g]);
+        mmax = std::max<uint64_t>(mmax, b.mpad);
         bbase += b.nb;
         if (active) {
             ++nactive;
@@ -1821,7 +1835,7 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
             const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
             const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
             const Plan p = batch_plan(c, P, NB);
-            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase, nmax};
+            BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase, nmax, mmax};
             c->ctr_step = c->ctr + st;
             GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
         }
@@ -2399,8 +2413,8 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
             c->unpermute_buckets = v != 0;
             return GESMC_OK;
         case GESMC_OPT_PACK_TUPLES:
-            if (v < 0 || v > 1) break;
-            c->pack_tuples = v != 0;
+            if (v < 0 || v > 2) break;
+            c->pack_tuples = (int)v;
             return GESMC_OK;
         case GESMC_OPT_GRAPH:
             if (v < 0 || v > 1) break;

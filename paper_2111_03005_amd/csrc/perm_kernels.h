@@ -296,10 +296,16 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
     for (int j = 0; j < kTileItems / 4; ++j) {
         const uint32_t sl = 4 * (tid + j * kThreads);  // first local slot of this thread's switch
         Tuple tp[4] = {{0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}, {0u, kEmptyKey}};
-        if (sl < cnt) emit_switch((begin + sl) >> 2, si, sk, t, k0, k1, sa, tp);
+        uint32_t kbase = 0;  // first switch of the switch's graph (graph-local tags)
+        if (sl < cnt) {
+            const uint32_t k = (begin + sl) >> 2;
+            emit_switch(k, si, sk, t, k0, k1, sa, tp);
+            if (kPacked && sa.pk.local && k < (sa.m >> 1)) kbase = sa.gr[sa.pg[2 * (size_t)k]].poff >> 1;
+        }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            tag[4 * j + h] = kPacked ? tag_code(tp[h].tag, sa.pk.kb) : tp[h].tag;
+            tag[4 * j + h] = kPacked ? tag_code(sa.pk.local ? tag_shift(tp[h].tag, kbase, true) : tp[h].tag, sa.pk.kb)
+                                     : tp[h].tag;
             key[4 * j + h] = sl + h < cnt ? emitted_word<kPacked>(tp[h].key, sa) : kEmptyKey;
         }
     }

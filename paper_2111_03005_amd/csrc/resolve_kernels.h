@@ -254,27 +254,33 @@ struct GraphErr {
 // `key` is a tuple hash, or (pk.w > 0) a packed word with its tag code
 // cleared; f is the tuple's partition, whose first-level digit restores the
 // hash bits the packed word dropped.
+// The rank of the graph holding the key of a tuple of fine partition f
+// (ge.gr must be set): its smaller endpoint, by inverting the hash with the
+// first level's digit restored, then the graph whose vertex range holds it.
+__device__ __forceinline__ uint32_t graph_of_tuple(unsigned long long key, uint32_t f, const TuplePack &pk,
+                                                   const GraphErr &ge) {
+    uint32_t v;
+    if (pk.w) {
+        const uint64_t h = ((uint64_t)(f >> pk.b2) << (pk.w - pk.b1)) | (key >> (64 - pk.w + pk.b1));
+        v = key_hash_w_vertex(h, pk.db, pk.w);
+    } else {
+        v = (uint32_t)(tuple_key_of(key) >> 32);
+    }
+    uint32_t lo = 0, hi = ge.ngraphs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (ge.gr[mid].vbase <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void flag_duplicate(unsigned long long key, uint32_t f, const TuplePack &pk, uint32_t *err,
                                                uint32_t dup_bit, const GraphErr &ge) {
     if (dup_bit) atomicOr(err, dup_bit);
-    if (ge.gr) {
-        uint32_t v;
-        if (pk.w) {
-            const uint64_t h = ((uint64_t)(f >> pk.b2) << (pk.w - pk.b1)) | (key >> (64 - pk.w + pk.b1));
-            v = key_hash_w_vertex(h, pk.db, pk.w);
-        } else {
-            v = (uint32_t)(tuple_key_of(key) >> 32);
-        }
-        uint32_t lo = 0, hi = ge.ngraphs - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (ge.gr[mid].vbase <= v)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        atomicOr(&ge.gerr[lo], ERR_DUP);
-    }
+    if (ge.gr) atomicOr(&ge.gerr[graph_of_tuple(key, f, pk, ge)], ERR_DUP);
 }
 
 // Writes the records of the tuple at sorted position p, given the position
@@ -291,8 +297,16 @@ __device__ __forceinline__ void resolve_one(uint32_t tag, uint32_t first_tag, ui
     }
     uint32_t eraser = kNoEraser;
     if (!(first_tag & kTagInsert)) eraser = (first_tag == kTagStays) ? kStays : first_tag;
-    const uint32_t pred = (p > first && (prev_tag & kTagInsert)) ? (prev_tag & ~kTagInsert) : kNoPred;
-    if (eraser != kNoEraser || pred != kNoPred) info[tag & ~kTagInsert] = make_uint2(eraser, pred);
+    uint32_t pred = (p > first && (prev_tag & kTagInsert)) ? (prev_tag & ~kTagInsert) : kNoPred;
+    if (eraser == kNoEraser && pred == kNoPred) return;
+    uint32_t slot = tag & ~kTagInsert;
+    if (pk.local) {  // graph-local tags (all of one key): back to batch-wide switch ids
+        const uint32_t kbase = ge.gr[graph_of_tuple(key, f, pk, ge)].poff >> 1;
+        slot += 2 * kbase;
+        if (eraser != kStays && eraser != kNoEraser) eraser += kbase;
+        if (pred != kNoPred) pred += 2 * kbase;
+    }
+    info[slot] = make_uint2(eraser, pred);
 }
 
 // One workgroup per fine partition (grid-stride if the grid is smaller).

@@ -253,7 +253,7 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
     const uint32_t G = (uint32_t)ranks.size();
     S->h_gr.assign(G, BatchGraph{});
     S->h_mv.assign(G, make_uint2(0xFFFFFFFFu, 0));
-    uint64_t poff = 0, vbase = 0, bbase = 0, stage = 0, nmax = 0;
+    uint64_t poff = 0, vbase = 0, bbase = 0, stage = 0, nmax = 0, mmax = 0;
     uint32_t pl_any = 0;
     S->h_stage_off.clear();
     S->h_stage_rank.clear();
@@ -286,6 +286,7 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
         poff += b.mpad;
         vbase += R->n;
         nmax = std::max<uint64_t>(nmax, R->n);
+        mmax = std::max<uint64_t>(mmax, b.mpad);
         bbase += b.nb;
     }
     S->h_stage_off.push_back(stage);
@@ -389,7 +390,7 @@ gesmc_status serve_enqueue(gesmc_server *S, ServeFlight &F, const std::vector<Se
     GESMC_TRY(up_end(c, s));
     const Plan p = batch_plan(c, npos, bbase);
     for (uint32_t st = 0; st < k; ++st) {
-        BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}, vbase, nmax};
+        BatchStep bs{c->gr, G, st, c->pg, c->bk, c->gacc, GraphErr{c->gr, G, c->gerr}, vbase, nmax, mmax};
         c->ctr_step = c->ctr + st;
         GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl_any, 0u, &bs));
     }

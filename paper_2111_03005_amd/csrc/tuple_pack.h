@@ -26,13 +26,18 @@ constexpr uint32_t kTagStays = 0x7FFFFFFEu;
 // STAYS -> 2^kb - 1, INSERT (k, h) -> 2^kb | 2k+h (2 ell < 2^kb).  The first
 // partition pass writes (H << (64 - w + b1)) | code: the b1 hash bits it
 // partitioned by are implied by the partition and dropped, the rest stays on
-// top for the second level's digits and the resolve's cells.
+// top for the second level's digits and the resolve's cells.  In a batch too
+// large for batch-wide switch ids in the code, tags are local to the
+// tuple's graph (switch k - poff / 2 of its graph): all tuples of one key
+// belong to one graph, so their order is the same, and kb then covers only
+// the largest graph.
 struct TuplePack {
-    int w;   // hash bits vb + db (0: 12-byte tuples)
-    int db;  // bits of the larger endpoint's offset v - u
-    int kb;  // tag code bits below the INSERT flag
-    int b1;  // hash bits dropped by the first partition pass
-    int b2;  // hash bits of the second partition pass
+    int w;      // hash bits vb + db (0: 12-byte tuples)
+    int db;     // bits of the larger endpoint's offset v - u
+    int kb;     // tag code bits below the INSERT flag
+    int b1;     // hash bits dropped by the first partition pass
+    int b2;     // hash bits of the second partition pass
+    int local;  // tags local to the tuple's graph (batches)
 };
 
 __host__ __device__ __forceinline__ uint64_t low_mask(int w) { return w >= 64 ? ~0ull : ((1ull << w) - 1); }
@@ -94,6 +99,14 @@ __host__ __device__ __forceinline__ uint32_t tag_code(uint32_t tag, int kb) {
 __host__ __device__ __forceinline__ uint32_t tag_of_code(uint32_t code, int kb) {
     if (code >> kb) return kTagInsert | (code & ((1u << kb) - 1u));
     return code == (1u << kb) - 1u ? kTagStays : code;
+}
+
+// A tag moved by kbase switches (kbase = the first switch of the tuple's
+// graph): to_local subtracts it, to_global adds it back.  STAYS is unchanged.
+__host__ __device__ __forceinline__ uint32_t tag_shift(uint32_t tag, uint32_t kbase, bool to_local) {
+    if (tag == kTagStays) return tag;
+    const uint32_t d = (tag & kTagInsert) ? 2u * kbase : kbase;
+    return to_local ? tag - d : tag + d;
 }
 
 }  // namespace gesmc

@@ -6,7 +6,8 @@ The cases cover the LDS resolve and its exact slow path (hub keys, small
 sort capacities), both radix level splits, odd m and P_L, the word filled
 to exactly 64 bits, one bit too many (12-byte fallback), and in batches the
 per-graph attribution of a duplicate edge (whose vertex the packed word
-recovers by inverting the key hash).
+recovers by inverting the key hash) and graph-local tags (forced with
+option value 2, and where batch-wide switch ids no longer fit the word).
 """
 import numpy as np
 import pytest
@@ -125,11 +126,11 @@ def test_packed_word_exactly_full_and_one_bit_over():
     assert run_both(E, (1 << 31) + 5, 13, 0, 2, label="wide_ids") == 12
 
 
-@pytest.mark.parametrize("pack", [1, 0])
+@pytest.mark.parametrize("pack", [1, 0, 2])
 def test_packed_batch_and_duplicate_attribution(pack):
     """Multi-kernel batch supersteps (the LDS small-graph path off) with and
-    without packing equal the oracle per graph; a duplicate edge in one graph
-    is reported for that graph."""
+    without packing, and with graph-local tags (2), equal the oracle per
+    graph; a duplicate edge in one graph is reported for that graph."""
     _require_gpu()
     import paper_2111_03005_amd as gesmc
     graphs = graphgen.batch_graphs(12, 41, 1e2, 2e4)
@@ -228,3 +229,59 @@ def test_packed_batch_wide_vertex_range():
                 assert stats[g][k] == sum(x[k] for x in counts), (g, k)
     finally:
         c.close()
+
+
+def check_batch(c, graphs, seeds, rs, tuple_bytes, label):
+    E_all, offs, ns = graphgen.concat(graphs)
+    print("%s: G=%d total m=%d" % (label, len(graphs), offs[-1]), flush=True)
+    out, stats, tot = c.run_batch(to_dev(E_all), offs, ns, seeds, rs)
+    assert tot["tuple_bytes"] == tuple_bytes, (label, tot)
+    got = to_host(out)
+    for g, (E, n) in enumerate(graphs):
+        rc, exp, counts, _ = oracle.run(E, n, seeds[g], 0, rs[g])
+        assert rc == 0
+        assert np.array_equal(got[offs[g]:offs[g + 1]], exp), (label, g)
+        for k in ("legal", "rej_loop", "rej_exists"):
+            assert stats[g][k] == sum(x[k] for x in counts), (label, g, k)
+
+
+def test_packed_batch_graph_local_tags_natural():
+    """16 sparse graphs of 2^24 vertices, 20000 edges each: 52 hash bits, and
+    batch-wide switch ids (19-bit codes) would need 67 bits, so the batch
+    packs with tags local to each graph (15-bit codes, 63 bits) instead of
+    falling back to 12-byte tuples.  Every graph equals the oracle."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    graphs = [(random_simple(1 << 24, 20000, 300 + g), 1 << 24) for g in range(16)]
+    rng = np.random.default_rng(13)
+    seeds = [int(x) for x in rng.integers(0, 2**63, len(graphs))]
+    rs = [int(x) for x in rng.integers(1, 4, len(graphs))]
+    c = gesmc.Context(0)
+    try:
+        c.set_option(gesmc.OPT_SMALL_GRAPHS, 0)
+        check_batch(c, graphs, seeds, rs, 8, "local tags")
+    finally:
+        c.close()
+
+
+def test_packed_batch_graph_local_tags_hubs_slow_path():
+    """Graph-local tags through the exact slow path: hub graphs (thousands of
+    inserters of one key) beside power-law graphs, with small LDS capacities,
+    in one batch; every graph equals the oracle."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    hub = keys([(a, b) for a in range(6) for b in range(6, 3000) if (a + b) % 3 != 0])
+    graphs = [(hub, 3000), (graphgen.powerlaw_graph(20000, 2.05, 1, 300, 5), 20000), (hub, 3000),
+              (graphgen.powerlaw_graph(5000, 2.3, 2, 70, 6), 5000)]
+    seeds = [5, 6, 7, 8]
+    rs = [3, 2, 3, 1]
+    for opts in ([], [(gesmc.OPT_SORT_CAP, 64)], [(gesmc.OPT_BUCKET_AVG, 96), (gesmc.OPT_SORT_CAP, 128)]):
+        c = gesmc.Context(0)
+        try:
+            c.set_option(gesmc.OPT_SMALL_GRAPHS, 0)
+            c.set_option(gesmc.OPT_PACK_TUPLES, 2)
+            for opt, val in opts:
+                c.set_option(opt, val)
+            check_batch(c, graphs, seeds, rs, 8, "local tags hubs %s" % (opts,))
+        finally:
+            c.close()
