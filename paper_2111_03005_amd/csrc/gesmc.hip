@@ -526,6 +526,7 @@ void set_scatter_lds_limits_one() {
                           (const void *)k_scatter<kSrcEmit, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcHashed, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcEmitPacked, kTile, scatter_threads(kTile), kOne>,
+                          (const void *)k_scatter<kSrcEmitPackedLocal, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcPacked, kTile, scatter_threads(kTile), kOne>,
                           (const void *)k_scatter<kSrcIdx, kTile, scatter_threads(kTile), kOne>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -636,7 +637,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(ensure_words(c, &c->partial, &c->cap_partial, rw.partial));
     const int shift1 = p.b1 > 0 ? 64 - (int)p.b1 : 63;  // level 1: one segment [0, n), passed by value
     bool fused_emit = false;
-    if constexpr (kSrc1 == kSrcEmit || kSrc1 == kSrcEmitPacked) {
+    if constexpr (kSrc1 == kSrcEmit || src_emits_packed<kSrc1>()) {
         if (eo) {  // the emit's outputs in the same pass
             GESMC_TRY(launch(c, s, kid_counts1, n, k_emit_counts<kSrc1, kTile>, dim3(eo->grid), dim3(kBlock),
                              (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, n, c->counts1, ba1,
@@ -660,7 +661,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
-    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, kSrc1 != kSrcEmitPacked);
+    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, !src_emits_packed<kSrc1>());
     const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked,
                                           kSrc2 != kSrcPacked && kSrc2 != kSrcHashed);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
@@ -838,10 +839,16 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
     if (pk.w) {
         SrcArgs sa = emit->sa;
         sa.pk = pk;
-        GESMC_TRY((radix_distribute<kSrcEmitPacked, kSrcPacked>(
-            c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts,
-            &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
-            emit->sk, eo)));
+        if (pk.local)
+            GESMC_TRY((radix_distribute<kSrcEmitPackedLocal, kSrcPacked>(
+                c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts,
+                &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
+                emit->sk, eo)));
+        else
+            GESMC_TRY((radix_distribute<kSrcEmitPacked, kSrcPacked>(
+                c, s, p, nslots, emit->t, emit->k0, emit->k1, c->tu_tag, c->tu_key, 0, 1, p.b2 > 0 ? 2 : 1, &parts,
+                &poff, &np, KID_TCOUNTS1, KID_TSCATTER1, KID_TCOUNTS2, KID_TSCATTER2, sa, SrcArgs{}, emit->si,
+                emit->sk, eo)));
         const int scratch = parts == 2 ? 1 : 0;
         const size_t rlds = resolve_lds_bytes(c->sort_cap, true);
         GESMC_TRY(launch(c, s, KID_RESOLVE, nslots, k_resolve<true>,

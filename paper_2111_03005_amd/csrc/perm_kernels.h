@@ -167,7 +167,8 @@ enum RadixSrc : int {
     kSrcHashed = 5,
     kSrcEmitPacked = 6,
     kSrcPacked = 7,
-    kSrcIdx = 8
+    kSrcIdx = 8,
+    kSrcEmitPackedLocal = 9  // kSrcEmitPacked with tags local to each graph (TuplePack.local)
 };
 
 struct SrcArgs {
@@ -195,12 +196,17 @@ __device__ __forceinline__ constexpr bool src_reads_aux() { return kSrc == kSrcB
 // packed words has none (every word is a tuple, and any word value occurs).
 template <int kSrc>
 __device__ __forceinline__ constexpr bool src_is_tuple() {
-    return kSrc == kSrcHash || kSrc == kSrcEmit || kSrc == kSrcHashed || kSrc == kSrcEmitPacked;
+    return kSrc == kSrcHash || kSrc == kSrcEmit || kSrc == kSrcHashed || kSrc == kSrcEmitPacked ||
+           kSrc == kSrcEmitPackedLocal;
 }
 template <int kSrc>
-__device__ __forceinline__ constexpr bool src_emits() { return kSrc == kSrcEmit || kSrc == kSrcEmitPacked; }
+__device__ __host__ __forceinline__ constexpr bool src_emits_packed() {
+    return kSrc == kSrcEmitPacked || kSrc == kSrcEmitPackedLocal;
+}
 template <int kSrc>
-__device__ __forceinline__ constexpr bool src_packed() { return kSrc == kSrcEmitPacked || kSrc == kSrcPacked; }
+__device__ __forceinline__ constexpr bool src_emits() { return kSrc == kSrcEmit || src_emits_packed<kSrc>(); }
+template <int kSrc>
+__device__ __forceinline__ constexpr bool src_packed() { return src_emits_packed<kSrc>() || kSrc == kSrcPacked; }
 
 // Local outcome of switch k from its pair records (ij, ee): P_L skip, the
 // idle pair of a batch graph's padding record, a loop, or a target equal to
@@ -286,8 +292,8 @@ __device__ __forceinline__ unsigned long long emitted_word(unsigned long long ke
 // switch are items 4j .. 4j+3 of one thread (slot order inside a tile does
 // not matter: partitions are sorted later).  kPacked: tag codes and the
 // w-bit key hash aligned to the top of the word (the radix word); the
-// scatter packs them.
-template <int kTileItems, int kThreads, bool kPacked>
+// scatter packs them.  kLocal: tags local to the switch's graph.
+template <int kTileItems, int kThreads, bool kPacked, bool kLocal = false>
 __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const uint32_t *si,
                                           const unsigned long long *sk, uint32_t t, uint32_t k0, uint32_t k1,
                                           const SrcArgs &sa, uint32_t *tag, unsigned long long *key) {
@@ -300,11 +306,11 @@ __device__ __forceinline__ void emit_tile(uint32_t begin, uint32_t cnt, const ui
         if (sl < cnt) {
             const uint32_t k = (begin + sl) >> 2;
             emit_switch(k, si, sk, t, k0, k1, sa, tp);
-            if (kPacked && sa.pk.local && k < (sa.m >> 1)) kbase = sa.gr[sa.pg[2 * (size_t)k]].poff >> 1;
+            if (kLocal && k < (sa.m >> 1)) kbase = sa.gr[sa.pg[2 * (size_t)k]].poff >> 1;
         }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            tag[4 * j + h] = kPacked ? tag_code(sa.pk.local ? tag_shift(tp[h].tag, kbase, true) : tp[h].tag, sa.pk.kb)
+            tag[4 * j + h] = kPacked ? tag_code(kLocal ? tag_shift(tp[h].tag, kbase, true) : tp[h].tag, sa.pk.kb)
                                      : tp[h].tag;
             key[4 * j + h] = sl + h < cnt ? emitted_word<kPacked>(tp[h].key, sa) : kEmptyKey;
         }
@@ -409,7 +415,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const uint32_t *__restri
         uint32_t cur_i[kTileItems], cur_a[kTileItems];
         unsigned long long cur_k[kTileItems];
         if (src_emits<kSrc>()) {
-            emit_tile<kTileItems, kBlock, kSrc == kSrcEmitPacked>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba,
+            emit_tile<kTileItems, kBlock, src_emits_packed<kSrc>(), kSrc == kSrcEmitPackedLocal>(
+                ts.begin, ts.cnt, src_idx, src_key, t, k0, k1, ba,
                                                                   cur_i, cur_k);
         } else {
 #pragma unroll
@@ -652,7 +659,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
         uint32_t c_idx[kTileItems], c_aux[kTileItems];
         unsigned long long c_key[kTileItems];
         if (src_emits<kSrc>()) {
-            emit_tile<kTileItems, kThreads, kSrc == kSrcEmitPacked>(ts.begin, ts.cnt, src_idx, src_key, t, k0, k1,
+            emit_tile<kTileItems, kThreads, src_emits_packed<kSrc>(), kSrc == kSrcEmitPackedLocal>(
+                ts.begin, ts.cnt, src_idx, src_key, t, k0, k1,
                                                                     ba, c_idx, c_key);
         } else {
 #pragma unroll
@@ -694,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
                 const uint32_t lp = start[r_dig[q]] + r_rank[q];
                 if (!src_packed<kSrc>()) s_idx[lp] = c_idx[q];
                 // kSrcEmitPacked: the tag code goes below the hash bits left after this level's digit
-                s_key[lp] = kSrc == kSrcEmitPacked ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
+                s_key[lp] = src_emits_packed<kSrc>() ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
                 if (!kDigitOfWord) s_dig[lp] = (uint16_t)r_dig[q];
                 if (kSrc == kSrcBatch) s_bkt[lp] = r_bkt[q];
                 ++mine;

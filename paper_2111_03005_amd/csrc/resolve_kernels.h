@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_counts(const uint32_t *__restri
     extern __shared__ uint32_t hs[];
     __shared__ BlockCounts bc;
     constexpr int kSwitches = kTile / kBlock / 4;  // switches per thread and tile
-    constexpr bool kPacked = kSrc == kSrcEmitPacked;
+    constexpr bool kPacked = src_emits_packed<kSrc>();
     const uint32_t nt = max(1u, (nslots + kTile - 1) / kTile);
     const uint32_t nd = 1u << dbits, dmask = nd - 1, tid = threadIdx.x;
     const uint32_t m = sa.m, ell = m >> 1;
