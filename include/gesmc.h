@@ -97,9 +97,10 @@ const char *gesmc_last_error(void);
  * nullable): r records.  On any error d_out is left untouched and a negative
  * status is returned; GESMC_E_NOT_SIMPLE / GESMC_E_RANGE report invalid input.
  * m < 2 copies the canonicalised input.  A graph of at most 4096 edges (6144
- * with every vertex id below 2^16) runs all its supersteps in one
- * workgroup's LDS in a single launch (Sec. 7's base case for small graphs)
- * when steps is NULL and GESMC_OPT_SMALL_GRAPHS is on; its stats then count
+ * with every vertex id below 2^16) runs its supersteps in one workgroup's LDS
+ * (Sec. 7's base case for small graphs) when steps is NULL and
+ * GESMC_OPT_SMALL_GRAPHS is on: per piece of up to 32 supersteps, one launch
+ * computes their permutations and one runs the chain; its stats then count
  * no rounds.
  */
 gesmc_status gesmc_run(gesmc_ctx *ctx, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m, uint32_t n,
@@ -493,7 +494,8 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                       2^16, run all their supersteps in one workgroup's LDS -- in
                                       gesmc_run_batch one launch per size class (up to 1024 edges on
                                       256 threads, up to 4096 on 1024, up to 6144 with 32-bit keys on
-                                      1024), in gesmc_run one launch when steps is NULL; 0: every
+                                      1024), in gesmc_run two launches per 32 supersteps (their
+                                      permutations, then the chain) when steps is NULL; 0: every
                                       graph takes the multi-kernel supersteps (default 1)            */
 #define GESMC_OPT_PACK_TUPLES 12   /* 1: dependency tuples travel as one 8-byte word (a bijective hash of
                                       the edge key on 2 x the vertex id bits, minus the bits the first
