@@ -229,6 +229,28 @@ def test_full_batch_4096_exact(ctx):
     assert tot["attempts"] == sum(20 * (s // 2) for s in sizes)
 
 
+def test_large_batch_graph_local_tags_sampled_exact(ctx):
+    """512 power-law graphs, four copies of a pool of 128 with n log-uniform in
+    [1e3, 1e6] (about 2e8 edges): batch-wide switch ids no longer fit the packed
+    tuple word, so the tags are local to each graph and the tuples stay 8 bytes.
+    Every 16th graph against the oracle."""
+    pool = graphgen.batch_graphs(128, 5, 1e3, 1e6)
+    graphs = pool * 4
+    G = len(graphs)
+    seeds = [1000 + g for g in range(G)]
+    rs = [3] * G
+    got, offs, stats, tot = run_batch(ctx, graphs, seeds, rs)
+    assert tot["tuple_bytes"] == 8, tot
+    ids = list(range(0, G, 16))
+    exp = oracle_pool(graphs, seeds, rs, ids=ids)
+    for g in ids:
+        rc, e, counts = exp[g]
+        assert rc == 0
+        assert np.array_equal(got[offs[g]:offs[g + 1]], e), g
+        for k in ("legal", "rej_loop", "rej_exists"):
+            assert stats[g][k] == sum(c[k] for c in counts), (g, k)
+
+
 def test_autotuned_batch_computes_the_same():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
