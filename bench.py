@@ -193,6 +193,9 @@ def bench_batched(gesmc, torch, args, plain_value):
         times.append(time.perf_counter() - t)
     wall = sum(times)
     value = attempts * len(times) / wall
+    # the outcome counts of one more call (untimed) for the roofline's legal fraction
+    _, _, tot = ctx.run_batch(d_in, offs, ns, seeds, rs, out=d_out, stats=True)
+    legal_fraction = tot["legal"] / max(tot["attempts"], 1)
     # the same calls replayed from a hipGraph (captured on the second call of this shape)
     ctx.set_option(gesmc.OPT_GRAPH, 1)
     for _ in range(2):
@@ -243,6 +246,8 @@ def bench_batched(gesmc, torch, args, plain_value):
             "vs_plain_same_graphs": round(value / plain_same, 2),
             "autotuner": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in tuning.items()},
             "vs_plain_headline": round(value / plain_value, 3) if plain_value else None,
+            "legal_fraction": round(legal_fraction, 5),
+            "switch_roofline": switch_roofline(value, legal_fraction, measured_G()),
             "cpu_baseline": cpu_b,
             "hipgraph_replay": graph_rec,
             "small_batches_hipgraph": small}
