@@ -1148,8 +1148,9 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     GESMC_TRY(check_hip(hipSetDevice(c->device), "hipSetDevice"));
     hipStream_t s = (hipStream_t)stream;
     const uint32_t m = (uint32_t)m64;
-    // small graphs (Sec. 7's base case): every superstep in one workgroup's LDS,
-    // one launch, when no per-superstep records or outcome codes are asked for
+    // small graphs (Sec. 7's base case): every superstep in one workgroup's LDS
+    // (the permutations computed ahead), when no per-superstep records or
+    // outcome codes are asked for
     if (cls > CLS_ALL) {
         set_error("graph class %u has bits other than loops (1), multi-edges (2) and directed (4)", cls);
         return GESMC_E_INVAL;
