@@ -508,9 +508,11 @@ def test_round_limit_fails_the_call_and_leaves_output_untouched():
 @pytest.mark.parametrize("pl", [0, 1 << 31])
 def test_small_plain_path_exact(pl):
     """gesmc_run on graphs that fit one workgroup's LDS (at most 4096 edges,
-    6144 with ids below 2^16) runs every superstep in one launch: equal to
+    6144 with ids below 2^16) runs every superstep in LDS, with the
+    permutations computed ahead in pieces of up to 32 supersteps: equal to
     the oracle and to the multi-kernel supersteps (GESMC_OPT_SMALL_GRAPHS 0)
-    at every size limit, for long chains and with P_L."""
+    at every size limit, for long chains, with P_L, and over several pieces
+    (r = 70: 32 + 32 + 6)."""
     _require_gpu()
     import paper_2111_03005_amd as gesmc
     cases = []
@@ -531,6 +533,8 @@ def test_small_plain_path_exact(pl):
             st_off = check_run_plain(c_off, E, n, 11 + q, 5 * q, 30, pl, label + " (multi-kernel)")
             for k in COUNT_KEYS:
                 assert st_on[k] == st_off[k], (label, k)
+        for E, n, label in (cases[3], cases[9], cases[11]):  # 1024, 6144 (compact) and gnp_n1024_d10 edges
+            check_run_plain(c_on, E, n, 5, 3, 70, pl, label + ", 70 supersteps")
     finally:
         c_on.close()
         c_off.close()
@@ -550,8 +554,9 @@ def check_run_plain(ctx, E, n, seed, t0, r, pl, label):
 
 
 def test_small_plain_path_invalid_inputs():
-    """The one-launch small path checks its input as the multi-kernel path
-    does (loop, id out of range, duplicate) and leaves d_out untouched."""
+    """The small path checks its input as the multi-kernel path does (loop,
+    id out of range, duplicate) and leaves d_out untouched, also when the
+    call runs in several pieces (the later pieces see the error and stop)."""
     _require_gpu()
     import paper_2111_03005_amd as gesmc
     c = gesmc.Context(0)
@@ -561,9 +566,10 @@ def test_small_plain_path_invalid_inputs():
                             (np.concatenate([good[:100], keys([(5, 5)])]), gesmc.E_NOT_SIMPLE),
                             (np.concatenate([good[:3000], keys([(1, 900)])]), gesmc.E_RANGE)]:
             sentinel = torch.full((len(bad),), 3, dtype=torch.int64, device="cuda")
-            with pytest.raises(gesmc.GesmcError) as ei:
-                c.run(to_dev(bad), 900, 1, r=4, out=sentinel)
-            assert ei.value.status == status
-            assert bool((sentinel == 3).all())
+            for r in (4, 40):
+                with pytest.raises(gesmc.GesmcError) as ei:
+                    c.run(to_dev(bad), 900, 1, r=r, out=sentinel)
+                assert ei.value.status == status
+                assert bool((sentinel == 3).all())
     finally:
         c.close()
