@@ -469,6 +469,22 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                   const uint64_t *offsets, const uint32_t *n, const uint64_t *seed,
                                   uint32_t supersteps, gesmc_tuning *out);
 
+/*
+ * Tuning cache.  With GESMC_OPT_TUNE_CACHE on (the default), the autotuner
+ * keeps each choice per device (architecture and PCI address) and shape
+ * class (plain or batch; log2 of the edge count, of the largest vertex count
+ * and of the graph count), shared by every context of the process, and a
+ * later autotune of the same device and class sets the kept choice without
+ * timing anything (out->candidates = 0).  save writes the cache as a JSON
+ * array, one entry per line; load merges such a file into the cache
+ * (GESMC_E_INVAL if it cannot be read or is not in that form, cache
+ * unchanged).  Thread-safe; no device is needed.
+ */
+gesmc_status gesmc_tune_cache_save(const char *path);
+gesmc_status gesmc_tune_cache_load(const char *path);
+void gesmc_tune_cache_clear(void);
+uint32_t gesmc_tune_cache_size(void);
+
 /* Tuning knobs (values are validated; results never depend on them, except
  * that GESMC_OPT_ROUND_LIMIT can make a call fail). */
 #define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 1152, default 1152)  */
@@ -517,6 +533,8 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *ctx, void *stream, uint32_t G, cons
                                           order first gathers the records into buckets of consecutive
                                           indices, then writes each bucket's window of d_out XCD by XCD;
                                           0: one scattered write per edge over all of d_out          */
+#define GESMC_OPT_TUNE_CACHE 15  /* 1 (default): the autotuner reuses and keeps its choices per device and
+                                    shape class (see gesmc_tune_cache_save); 0: it always times       */
 gesmc_status gesmc_set_option(gesmc_ctx *ctx, int option, int64_t value);
 
 /*

@@ -11,9 +11,11 @@ call), ``Server`` (a request loop with continuous batching),
 dependencies).
 """
 from . import _binding
-from ._binding import Context, GesmcError, Server, default_context, load_library, run
+from ._binding import (Context, GesmcError, Server, default_context, load_library, run, tune_cache_clear,
+                       tune_cache_load, tune_cache_save, tune_cache_size)
 
 _CONSTANTS = [k for k in dir(_binding) if k.isupper() and not k.startswith("_")]
 globals().update({k: getattr(_binding, k) for k in _CONSTANTS})
 
-__all__ = ["Context", "Server", "GesmcError", "default_context", "load_library", "run"] + _CONSTANTS
+__all__ = ["Context", "Server", "GesmcError", "default_context", "load_library", "run", "tune_cache_clear",
+           "tune_cache_load", "tune_cache_save", "tune_cache_size"] + _CONSTANTS

@@ -28,6 +28,7 @@ OPT_SMALL_GRAPHS = 11
 OPT_PACK_TUPLES = 12
 OPT_ROUND_LIMIT = 13
 OPT_UNPERMUTE_BUCKETS = 14
+OPT_TUNE_CACHE = 15
 CHAIN_GLOBAL, CHAIN_ES = 0, 1
 CLASS_LOOPS, CLASS_MULTI, CLASS_DIRECTED = 1, 2, 4
 NOALLOC_MAX_EDGES = 2000000
@@ -118,7 +119,8 @@ EXPORTS = ["gesmc_create", "gesmc_destroy", "gesmc_last_error", "gesmc_run", "ge
            "gesmc_server_create", "gesmc_server_destroy", "gesmc_submit", "gesmc_poll", "gesmc_wait",
            "gesmc_cancel", "gesmc_result_free", "gesmc_server_info_get", "gesmc_autotune", "gesmc_autotune_batch",
            "gesmc_run_es", "gesmc_es_draws", "gesmc_mixing", "gesmc_run_class", "gesmc_gen_gnp",
-           "gesmc_gen_pld_degrees", "gesmc_gen_havel_hakimi", "gesmc_gen_relabel", "gesmc_set_allocator"]
+           "gesmc_gen_pld_degrees", "gesmc_gen_havel_hakimi", "gesmc_gen_relabel", "gesmc_set_allocator",
+           "gesmc_tune_cache_save", "gesmc_tune_cache_load", "gesmc_tune_cache_clear", "gesmc_tune_cache_size"]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -214,6 +216,14 @@ def load_library(path: str = LIB_PATH):
         lib.gesmc_gen_relabel.restype = i32
         lib.gesmc_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         lib.gesmc_set_allocator.restype = i32
+        lib.gesmc_tune_cache_save.argtypes = [ctypes.c_char_p]
+        lib.gesmc_tune_cache_save.restype = i32
+        lib.gesmc_tune_cache_load.argtypes = [ctypes.c_char_p]
+        lib.gesmc_tune_cache_load.restype = i32
+        lib.gesmc_tune_cache_clear.argtypes = []
+        lib.gesmc_tune_cache_clear.restype = None
+        lib.gesmc_tune_cache_size.argtypes = []
+        lib.gesmc_tune_cache_size.restype = u32
         _lib = lib
         return lib
 
@@ -589,6 +599,24 @@ class Server:
 
 
 _default = {}
+
+
+def tune_cache_save(path: str) -> None:
+    """Writes the autotuner's choices (per device and shape class) to a JSON file."""
+    _check(load_library().gesmc_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str) -> None:
+    """Merges a file written by tune_cache_save into the autotuner's choices."""
+    _check(load_library().gesmc_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_clear() -> None:
+    load_library().gesmc_tune_cache_clear()
+
+
+def tune_cache_size() -> int:
+    return int(load_library().gesmc_tune_cache_size())
 
 
 def default_context(device: int | None = None) -> Context:

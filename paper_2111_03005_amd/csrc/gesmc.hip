@@ -9,7 +9,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -180,6 +182,8 @@ struct gesmc_ctx {
     uint32_t *counts1 = nullptr, *counts2 = nullptr, *partial = nullptr;
     uint32_t *small = nullptr;  // counters, histograms, offsets (fixed size)
     uint16_t *small_pi = nullptr;  // permutations of the small-graph path (kSmallPiSteps rows of kCmpMax)
+    std::string device_key;        // architecture and PCI address (the tuning cache's device)
+    bool tune_cache = true;        // the autotuner reuses and keeps choices per device and shape class
     uint4 *bslot = nullptr;     // per-block counts of the grid-stride kernels (2 grids)
     // batches: per graph (rank order) and per position
     uint64_t cap_g = 0, cap_pos = 0;
@@ -2017,8 +2021,16 @@ gesmc_status gesmc_create(int hip_device, gesmc_ctx **out) {
     gesmc_ctx *c = new gesmc_ctx();
     c->device = hip_device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
-        c->num_cus = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+        if (prop.multiProcessorCount > 0) c->num_cus = prop.multiProcessorCount;
+        char key[128];
+        snprintf(key, sizeof(key), "%.32s:%04x:%02x:%02x", prop.gcnArchName, (unsigned)prop.pciDomainID,
+                 (unsigned)prop.pciBusID, (unsigned)prop.pciDeviceID);
+        c->device_key = key;
+    } else {
+        (void)hipGetLastError();
+        c->device_key = "device" + std::to_string(hip_device);
+    }
     // fixed-size area: err[16], ucount[16], coarse offsets / tile map, level-1 segment, fine offsets
     const size_t nf = (size_t)1 << kMaxFineBits;
     const size_t nc = ((size_t)1 << kMaxCoarseBits) + 8;
@@ -2126,15 +2138,51 @@ gesmc_status gesmc_run_batch(gesmc_ctx *ctx, void *stream, uint32_t G, const uin
 
 namespace {
 
+// Tuning choices per device and shape class: key "device|mode|m|n|g" (the
+// device's architecture and PCI address; the form; log2 of the edge count, of
+// the largest vertex count and of the graph count).  Shared by every context
+// of the process; gesmc_tune_cache_save / _load keep it in a file.
+std::mutex g_tune_mu;
+std::map<std::string, gesmc_tuning> g_tune;
+
+int log2_class(uint64_t x) {
+    int b = 0;
+    while (b < 63 && (1ull << (b + 1)) <= x) ++b;
+    return b;
+}
+
+std::string tune_key(const gesmc_ctx *c, const char *mode, uint64_t m, uint64_t nmax, uint64_t G) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|%s|%d|%d|%d", c->device_key.c_str(), mode, log2_class(m), log2_class(nmax),
+             log2_class(G));
+    return buf;
+}
+
 // Times every candidate setting with `trial` (device ms of one call; the
 // first call of a setting warms it up, the second is timed) and leaves the
 // fastest set.  Candidates: bucket mean 1/2 or 3/4 of the LDS capacity, an
 // even level split or an 8-bit first level, fused or unfused tuple pass.
+// With the cache on (GESMC_OPT_TUNE_CACHE), a choice already made for this
+// device and shape class is set instead, and a new choice is kept.
 template <typename Trial>
-gesmc_status autotune_impl(gesmc_ctx *c, Trial trial, gesmc_tuning *out) {
+gesmc_status autotune_impl(gesmc_ctx *c, Trial trial, gesmc_tuning *out, const std::string &key) {
     if (c->strategy != 0) {
         set_error("the autotuner needs the sorted-tuples strategy (GESMC_OPT_STRATEGY 0)");
         return GESMC_E_INVAL;
+    }
+    if (c->tune_cache) {  // a choice made before for this device and shape class
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            c->bucket_avg = it->second.bucket_avg;
+            c->level1_cap = it->second.level1_bits;
+            c->fuse_emit = it->second.fuse_emit != 0;
+            if (out) {
+                *out = it->second;
+                out->candidates = 0;  // nothing timed
+            }
+            return GESMC_OK;
+        }
     }
     const uint32_t avgs[2] = {3 * kLdsCap / 4, kLdsCap / 2};
     const uint32_t l1s[2] = {0, 8};
@@ -2175,7 +2223,12 @@ gesmc_status autotune_impl(gesmc_ctx *c, Trial trial, gesmc_tuning *out) {
     c->bucket_avg = best_avg;
     c->level1_cap = best_l1;
     c->fuse_emit = best_fuse;
-    if (out) *out = gesmc_tuning{best_avg, best_l1, best_fuse ? 1u : 0u, ncand, best, dflt};
+    const gesmc_tuning t{best_avg, best_l1, best_fuse ? 1u : 0u, ncand, best, dflt};
+    if (out) *out = t;
+    if (c->tune_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = t;
+    }
     return GESMC_OK;
 }
 
@@ -2201,7 +2254,7 @@ gesmc_status gesmc_autotune(gesmc_ctx *c, void *stream, const uint64_t *d_in, ui
             *ms = stt.ms_device;
             return s;
         },
-        out);
+        out, tune_key(c, "plain", m, n, 1));
     (void)hipStreamSynchronize((hipStream_t)stream);
     dev_free(c, tmp);
     return st;
@@ -2228,7 +2281,7 @@ gesmc_status gesmc_autotune_batch(gesmc_ctx *c, void *stream, uint32_t G, const 
             *ms = tot.ms_device;
             return s;
         },
-        out);
+        out, tune_key(c, "batch", total, n ? *std::max_element(n, n + G) : 0, G));
     (void)hipStreamSynchronize((hipStream_t)stream);
     dev_free(c, tmp);
     return st;
@@ -2372,6 +2425,83 @@ gesmc_status gesmc_permutation(gesmc_ctx *c, void *stream, uint64_t m64, uint64_
     return GESMC_OK;
 }
 
+gesmc_status gesmc_tune_cache_save(const char *path) {
+    if (!path) {
+        set_error("null path");
+        return GESMC_E_INVAL;
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) {
+        set_error("cannot write %s", path);
+        return GESMC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    fprintf(f, "[\n");
+    size_t i = 0;
+    for (const auto &kv : g_tune) {
+        const gesmc_tuning &t = kv.second;
+        fprintf(f,
+                "{\"key\": \"%s\", \"bucket_avg\": %u, \"level1_bits\": %u, \"fuse_emit\": %u, \"candidates\": %u, "
+                "\"best_ms\": %.6f, \"default_ms\": %.6f}%s\n",
+                kv.first.c_str(), t.bucket_avg, t.level1_bits, t.fuse_emit, t.candidates, t.best_ms, t.default_ms,
+                ++i < g_tune.size() ? "," : "");
+    }
+    fprintf(f, "]\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok) {
+        set_error("cannot write %s", path);
+        return GESMC_E_INVAL;
+    }
+    return GESMC_OK;
+}
+
+gesmc_status gesmc_tune_cache_load(const char *path) {
+    if (!path) {
+        set_error("null path");
+        return GESMC_E_INVAL;
+    }
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        set_error("cannot read %s", path);
+        return GESMC_E_INVAL;
+    }
+    std::map<std::string, gesmc_tuning> got;
+    char line[1024];
+    bool bad = false;
+    while (fgets(line, sizeof(line), f)) {
+        if (line[0] != '{') continue;  // "[" and "]"
+        char key[256];
+        gesmc_tuning t{};
+        if (sscanf(line,
+                   "{\"key\": \"%255[^\"]\", \"bucket_avg\": %u, \"level1_bits\": %u, \"fuse_emit\": %u, "
+                   "\"candidates\": %u, \"best_ms\": %lf, \"default_ms\": %lf}",
+                   key, &t.bucket_avg, &t.level1_bits, &t.fuse_emit, &t.candidates, &t.best_ms, &t.default_ms) != 7 ||
+            t.bucket_avg < 64 || t.bucket_avg > kLdsCap || t.level1_bits > kMaxCoarseBits || t.fuse_emit > 1) {
+            bad = true;
+            break;
+        }
+        got[key] = t;
+    }
+    fclose(f);
+    if (bad) {
+        set_error("%s is not a tuning cache written by gesmc_tune_cache_save", path);
+        return GESMC_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    return GESMC_OK;
+}
+
+void gesmc_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+uint32_t gesmc_tune_cache_size(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (uint32_t)g_tune.size();
+}
+
 gesmc_status gesmc_set_allocator(gesmc_ctx *c, gesmc_alloc_fn alloc, gesmc_free_fn free_fn, void *user) {
     if (!c || (alloc == nullptr) != (free_fn == nullptr)) {
         set_error("null context, or only one of the allocate and free functions given");
@@ -2419,6 +2549,10 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
         case GESMC_OPT_UNPERMUTE_BUCKETS:
             if (v < 0 || v > 1) break;
             c->unpermute_buckets = v != 0;
+            return GESMC_OK;
+        case GESMC_OPT_TUNE_CACHE:
+            if (v < 0 || v > 1) break;
+            c->tune_cache = v != 0;
             return GESMC_OK;
         case GESMC_OPT_PACK_TUPLES:
             if (v < 0 || v > 2) break;

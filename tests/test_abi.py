@@ -57,7 +57,7 @@ def test_binding_constants_match_header():
     assert d["GESMC_OK"] == gesmc.OK
     for name in ["E_INVAL", "E_NOT_SIMPLE", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_AGAIN", "E_CANCELED", "E_INTERNAL"]:
         assert d["GESMC_" + name] == getattr(gesmc, name), name
-    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH", "SMALL_GRAPHS", "PACK_TUPLES"]:
+    for name in ["BUCKET_AVG", "SORT_CAP", "FAST_ROUNDS", "PROFILE", "STRATEGY", "PERSIST", "PROFILE_ONLY", "LEVEL1_BITS", "FUSE_EMIT", "GRAPH", "SMALL_GRAPHS", "PACK_TUPLES", "ROUND_LIMIT", "UNPERMUTE_BUCKETS", "TUNE_CACHE"]:
         assert d["GESMC_OPT_" + name] == getattr(gesmc, "OPT_" + name), name
 
 
@@ -143,3 +143,38 @@ def test_null_context_rejected_without_gpu(lib):
     lib.gesmc_result_free(None)
     assert lib.gesmc_autotune(None, None, None, 0, 0, 0, 1, None) == gesmc.E_INVAL
     assert lib.gesmc_autotune_batch(None, None, 0, None, None, None, None, 1, None) == gesmc.E_INVAL
+
+
+def test_tune_cache_file_round_trip_without_gpu(lib, tmp_path):
+    """The autotuner's cache: a file in the saved form loads, saves back to
+    the same entries, a malformed file is rejected with the cache unchanged,
+    and clear empties it.  No device is needed."""
+    import json
+
+    import paper_2111_03005_amd as gesmc
+    gesmc.tune_cache_clear()
+    assert gesmc.tune_cache_size() == 0
+    entries = [
+        {"key": "gfx950:0000:05:00|plain|26|22|0", "bucket_avg": 768, "level1_bits": 0, "fuse_emit": 1,
+         "candidates": 8, "best_ms": 47.5, "default_ms": 47.9},
+        {"key": "gfx950:0000:05:00|batch|27|16|12", "bucket_avg": 512, "level1_bits": 8, "fuse_emit": 0,
+         "candidates": 8, "best_ms": 210.25, "default_ms": 215.5},
+    ]
+    src = tmp_path / "in.json"
+    src.write_text("[\n" + ",\n".join(json.dumps(e) for e in entries) + "\n]\n")
+    gesmc.tune_cache_load(str(src))
+    assert gesmc.tune_cache_size() == 2
+    dst = tmp_path / "out.json"
+    gesmc.tune_cache_save(str(dst))
+    back = sorted(json.loads(dst.read_text()), key=lambda e: e["key"])
+    assert back == sorted(entries, key=lambda e: e["key"])
+    bad = tmp_path / "bad.json"
+    bad.write_text('[\n{"key": "x", "bucket_avg": 5000, "level1_bits": 0, "fuse_emit": 1, "candidates": 8, '
+                   '"best_ms": 1.0, "default_ms": 1.0}\n]\n')
+    with pytest.raises(gesmc.GesmcError):
+        gesmc.tune_cache_load(str(bad))
+    with pytest.raises(gesmc.GesmcError):
+        gesmc.tune_cache_load(str(tmp_path / "missing.json"))
+    assert gesmc.tune_cache_size() == 2
+    gesmc.tune_cache_clear()
+    assert gesmc.tune_cache_size() == 0

@@ -257,11 +257,16 @@ def test_autotuned_batch_computes_the_same():
     import paper_2111_03005_amd as gesmc
     graphs, seeds, rs, t0s = mixed_batch(seed=23, G=20)
     E, offs, ns = graphgen.concat(graphs)
+    gesmc.tune_cache_clear()
     c = gesmc.Context(0)
     try:
         tu = c.autotune_batch(to_dev(E), offs, ns, seeds, supersteps=2)
         print("tuning:", tu, flush=True)
         assert tu["candidates"] == 8
+        again = c.autotune_batch(to_dev(E), offs, ns, seeds, supersteps=2)  # same device and shape class
+        assert again["candidates"] == 0
+        assert {k: again[k] for k in ("bucket_avg", "level1_bits", "fuse_emit")} == \
+            {k: tu[k] for k in ("bucket_avg", "level1_bits", "fuse_emit")}
         got, offs, stats, _ = run_batch(c, graphs, seeds, rs, t0s)
         check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, 0, range(len(graphs)))
     finally:

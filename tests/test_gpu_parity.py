@@ -4,6 +4,9 @@ Everything here is integer work, so the bar is exact equality: the output
 edge list in position order, every per-superstep count, the per-switch
 outcome codes, the permutation keys and the permutation itself.
 """
+import os
+import tempfile
+
 import numpy as np
 import pytest
 
@@ -467,6 +470,7 @@ def test_autotuned_context_computes_the_same():
     import paper_2111_03005_amd as gesmc
     E = graphgen.powerlaw_graph(60000, 2.3, 2, 244, 31)
     n = 60000
+    gesmc.tune_cache_clear()
     c = gesmc.Context(0)
     try:
         tu = c.autotune(to_dev(E), n, seed=5, supersteps=2)
@@ -474,6 +478,24 @@ def test_autotuned_context_computes_the_same():
         assert tu["candidates"] == 8 and tu["best_ms"] <= tu["default_ms"] + 1e-9
         assert tu["fuse_emit"] in (0, 1) and tu["level1_bits"] in (0, 8)
         check_run(c, E, n, 77, 1, 4, label="autotuned")
+    finally:
+        c.close()
+    choice = {k: tu[k] for k in ("bucket_avg", "level1_bits", "fuse_emit")}
+    assert gesmc.tune_cache_size() == 1
+    # a second context on the same device and shape class takes the kept choice without timing
+    path = os.path.join(tempfile.mkdtemp(), "tune.json")
+    gesmc.tune_cache_save(path)
+    gesmc.tune_cache_clear()
+    gesmc.tune_cache_load(path)
+    E2 = graphgen.powerlaw_graph(61000, 2.3, 2, 246, 32)  # same log2 classes of m and n
+    c = gesmc.Context(0)
+    try:
+        tu2 = c.autotune(to_dev(E2), 61000, seed=6, supersteps=2)
+        assert tu2["candidates"] == 0 and {k: tu2[k] for k in choice} == choice
+        check_run(c, E2, 61000, 78, 0, 3, label="cached tuning")
+        c.set_option(gesmc.OPT_TUNE_CACHE, 0)
+        tu3 = c.autotune(to_dev(E2), 61000, seed=6, supersteps=2)
+        assert tu3["candidates"] == 8
     finally:
         c.close()
 
