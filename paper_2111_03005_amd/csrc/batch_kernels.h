@@ -328,33 +328,36 @@ __device__ __forceinline__ void small_cells_scan(uint32_t *cellw, uint32_t *tmp)
     __syncthreads();
 }
 
+// First slot of cell c after small_group or small_group_fn (the end of cell c - 1).
+template <uint32_t kMax, uint32_t kThreads, bool kCompact>
+__device__ __forceinline__ uint32_t small_cell_begin(const SmallLds<kMax, kThreads, kCompact> &L, uint32_t c) {
+    return c ? L.cell(c - 1) : 0u;
+}
+
 // Groups up to 2 kMax items by the top cell bits of their word: they sit in
 // registers (w[q], g[q] for q < kPer where present[q]); a counting sort puts
-// them in cell order into sK / sT (cell c spans [L.cell(c), L.cell(c + 1))).
-// Within a cell the order is arbitrary; callers then walk whole cells, so no
-// per-item state outlives the grouping.  Returns with a barrier passed.
+// them in cell order into sK / sT.  The place pass takes each slot from an
+// atomic bump of its cell's offset, so no rank is kept between the passes:
+// within a cell the order is arbitrary (callers walk whole cells), and
+// afterwards L.cell(c) holds the END of cell c, which therefore spans
+// [small_cell_begin(L, c), L.cell(c)).  Returns with a barrier passed.
 template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact>
 __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads, kCompact> &L,
                                             const typename SmallKeys<kCompact>::Word *w, const uint16_t *g,
                                             const bool *present) {
     constexpr int kShift = 8 * (int)sizeof(typename SmallKeys<kCompact>::Word) - small_cell_bits<kThreads>();
-    const uint32_t tid = threadIdx.x;
-    (void)tid;
     small_cells_zero<kThreads>(L.cellw);
     __syncthreads();
-    uint32_t cl[kPer], rank[kPer];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        if (!present[q]) continue;
-        cl[q] = (uint32_t)(w[q] >> kShift);
-        rank[q] = small_cell_add(L.cellw, cl[q]);
-    }
+    for (int q = 0; q < kPer; ++q)
+        if (present[q]) small_cell_add(L.cellw, (uint32_t)(w[q] >> kShift));
     __syncthreads();
     small_cells_scan<kThreads>(L.cellw, L.tmp);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         if (!present[q]) continue;
-        const uint32_t slot = L.cell(cl[q]) + rank[q];
+        // an offset never passes the total (< 2^16), so a low half never carries
+        const uint32_t slot = small_cell_add(L.cellw, (uint32_t)(w[q] >> kShift));
         L.sK[slot] = w[q];
         L.sT[slot] = g[q];
     }
@@ -363,22 +366,20 @@ __device__ __forceinline__ void small_group(SmallLds<kMax, kThreads, kCompact> &
 
 // small_group with items produced on demand: item(q, &w, &g) returns whether
 // item q is present and sets its word and tag.  It is called twice per item
-// (count, then place), so only the cells and ranks stay in registers;
-// placed(q, slot) is told where each present item went.
+// (count, then place) and nothing per item is kept in between; placed(q,
+// slot) is told where each present item went.  Cells as in small_group.
 template <int kPer, uint32_t kMax, uint32_t kThreads, bool kCompact, typename Item, typename Placed>
 __device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact> &L, Item item, Placed placed) {
     using Word = typename SmallKeys<kCompact>::Word;
     constexpr int kShift = 8 * (int)sizeof(Word) - small_cell_bits<kThreads>();
     small_cells_zero<kThreads>(L.cellw);
     __syncthreads();
-    uint32_t cr[kPer];  // cell << 16 | rank within the cell (cells and ranks are below 2^16)
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         Word w;
         uint16_t g;
         if (!item(q, &w, &g)) continue;
-        const uint32_t cl = (uint32_t)(w >> kShift);
-        cr[q] = (cl << 16) | small_cell_add(L.cellw, cl);
+        small_cell_add(L.cellw, (uint32_t)(w >> kShift));
     }
     __syncthreads();
     small_cells_scan<kThreads>(L.cellw, L.tmp);
@@ -387,7 +388,7 @@ __device__ __forceinline__ void small_group_fn(SmallLds<kMax, kThreads, kCompact
         Word w;
         uint16_t g;
         if (!item(q, &w, &g)) continue;
-        const uint32_t slot = L.cell(cr[q] >> 16) + (cr[q] & 0xFFFFu);
+        const uint32_t slot = small_cell_add(L.cellw, (uint32_t)(w >> kShift));
         L.sK[slot] = w;
         L.sT[slot] = g;
         placed(q, slot);
@@ -466,7 +467,7 @@ __device__ __forceinline__ void small_permute(SmallLds<kMax, kThreads, kCompact>
         const Word wy = L.sK[y];
         const uint16_t gy = L.sT[y];
         const uint32_t cc = (uint32_t)(wy >> kCellShift);
-        const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
+        const uint32_t a = small_cell_begin(L, cc), e = L.cell(cc);
         uint32_t rank = 0;
         for (uint32_t z0 = a; z0 < e; z0 += 4) {  // four loads in flight
             Word wz[4];
@@ -646,7 +647,7 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                 if (ty & kSmTagInsert) continue;
                 const Word wy = L.sK[y];
                 const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
+                const uint32_t a = small_cell_begin(L, cc), e = L.cell(cc);
                 bool before = false;
                 cell_matches(L.sK, a, e, y, wy, [&](uint32_t z) {
                     const uint16_t tz = L.sT[z];
@@ -675,7 +676,7 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                 const Word wy = kPre ? (h ? tw[1] : tw[0]) : L.sK[sl];
                 const uint32_t ty = kSmTagInsert | (k << 1) | h;
                 const uint32_t cc = (uint32_t)(wy >> kCellShift);
-                const uint32_t a = L.cell(cc), e = L.cell(cc + 1);
+                const uint32_t a = small_cell_begin(L, cc), e = L.cell(cc);
                 uint32_t first = ty, prev = 0;
                 bool before = false;
                 cell_matches(L.sK, a, e, sl, wy, [&](uint32_t z) {
