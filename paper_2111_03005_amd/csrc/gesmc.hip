@@ -451,7 +451,17 @@ gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern k
 
 struct Plan {
     uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1, tile;
+    uint32_t dig_in_key = 0;  // the permutation's scatters stage digits in the keys' top byte (SrcArgs)
 };
+
+// Digits in the keys' top byte (SrcArgs::dig_in_key) when every vertex id is
+// below 2^24 and both levels have at most 8 digit bits; 0 disables it.
+#ifndef GESMC_DIGIT_IN_KEY
+#define GESMC_DIGIT_IN_KEY 1
+#endif
+uint32_t digit_in_key(const Plan &p, uint32_t n) {
+    return GESMC_DIGIT_IN_KEY && n <= (1u << 24) && p.b1 <= 8 && p.b2 <= 8 ? 1u : 0u;
+}
 
 uint32_t tile_for(uint32_t n) { return n >= kLargeTileRecords ? (uint32_t)kTileLarge : (uint32_t)kTileSmall; }
 
@@ -665,9 +675,10 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
-    const size_t lds1 = scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, !src_emits_packed<kSrc1>());
+    const size_t lds1 =
+        scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, !src_emits_packed<kSrc1>(), ba1.dig_in_key == 0);
     const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked,
-                                          kSrc2 != kSrcPacked && kSrc2 != kSrcHashed);
+                                          kSrc2 != kSrcPacked && kSrc2 != kSrcHashed && ba2.dig_in_key == 0);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
                      dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
                      k1, shift1, (int)p.b1, 0u, n, (const uint32_t *)nullptr, (const uint32_t *)nullptr,
@@ -769,9 +780,11 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
                                                            &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
                                                            KID_SCATTER2, ba1, ba2)));
     } else {
+        SrcArgs pa{};
+        pa.dig_in_key = p.dig_in_key;
         GESMC_TRY((radix_distribute<kSrcPerm, kSrcPerm>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
                                                         &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
-                                                        KID_SCATTER2, SrcArgs{}, SrcArgs{})));
+                                                        KID_SCATTER2, pa, pa)));
     }
     const int sorted = (dist == X) ? Y : X;  // sort into the buffer not holding the buckets
     GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(persistent_blocks(c, k_sort_buckets, sort_lds, nb)),
@@ -1174,7 +1187,8 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     if (m > 0)
         GESMC_TRY(launch(c, s, KID_LOAD, m, k_load, dim3(grid_stride_blocks(c, m)), dim3(kBlock), 0,
                          (const unsigned long long *)d_in, m, n, c->idx[0], c->key[0], c->err, cls));
-    const Plan p = make_plan(c, m);
+    Plan p = make_plan(c, m);
+    p.dig_in_key = digit_in_key(p, n);
     const uint32_t nslots = (uint32_t)c->tab_slots;
     // the graph classes run on the sorted tuples only (multi-edge classes
     // have no dependencies at all)
@@ -2412,7 +2426,8 @@ gesmc_status gesmc_permutation(gesmc_ctx *c, void *stream, uint64_t m64, uint64_
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_zero_words, dim3(4), dim3(256), 0, c->err, (uint64_t)64));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_identity_records, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0,
                          c->idx[0], c->key[0], m));
-        const Plan p = make_plan(c, m);
+        Plan p = make_plan(c, m);
+        p.dig_in_key = digit_in_key(p, 0);  // the records' keys are their indices (top byte zero)
         int sorted = 0;
         GESMC_TRY(permute(c, s, p, t, (uint32_t)seed, (uint32_t)(seed >> 32), 0, &sorted, false));
         GESMC_TRY(launch(c, s, KID_MISC, 0, k_extract_pi, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0,

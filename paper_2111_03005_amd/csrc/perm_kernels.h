@@ -184,6 +184,10 @@ struct SrcArgs {
     TuplePack pk;            // kSrcEmitPacked: hash width, offset and tag code bits
     uint32_t cls;            // graph class (CLS_* bits; multi-edge classes never come here)
     uint32_t ishift;         // kSrcIdx: 64 - (bits of the largest index)
+    // kSrcPerm: nonzero if every vertex id is below 2^24 and a level has at
+    // most 8 digit bits; the scatter then stages each record's digit in the
+    // edge key's top byte (zero in such keys) instead of a digit array
+    uint32_t dig_in_key;
 };
 
 template <int kSrc>
@@ -640,6 +644,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
     // second tuple level: a staged word (packed word or tuple hash, moved
     // unchanged) holds its own digit, so none is staged
     constexpr bool kDigitOfWord = kSrc == kSrcPacked || kSrc == kSrcHashed;
+    // permutation records whose key has a free top byte carry the digit there
+    // (no digit array: 51 KB instead of 59 KB at 4096 records, three
+    // workgroups per CU instead of two)
+    const bool dik = kSrc == kSrcPerm && ba.dig_in_key != 0;
+    constexpr unsigned long long kKeyLow56 = 0x00FFFFFFFFFFFFFFull;
     const uint32_t nd = 1u << dbits, dmask = nd - 1;
     uint32_t *cnt = lds;                 // nd
     uint32_t *start = cnt + nd;          // nd (exclusive scan of cnt)
@@ -702,8 +711,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
                 const uint32_t lp = start[r_dig[q]] + r_rank[q];
                 if (!src_packed<kSrc>()) s_idx[lp] = c_idx[q];
                 // kSrcEmitPacked: the tag code goes below the hash bits left after this level's digit
-                s_key[lp] = src_emits_packed<kSrc>() ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
-                if (!kDigitOfWord) s_dig[lp] = (uint16_t)r_dig[q];
+                if (dik) {
+                    s_key[lp] = (c_key[q] & kKeyLow56) | ((unsigned long long)r_dig[q] << 56);
+                } else {
+                    s_key[lp] = src_emits_packed<kSrc>() ? ((c_key[q] << dbits) | c_idx[q]) : c_key[q];
+                    if (!kDigitOfWord) s_dig[lp] = (uint16_t)r_dig[q];
+                }
                 if (kSrc == kSrcBatch) s_bkt[lp] = r_bkt[q];
                 ++mine;
             }
@@ -713,11 +726,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint32_t *__restrict
         const uint32_t staged = s_total;
         for (uint32_t lp = tid; lp < staged; lp += kThreads) {
             const unsigned long long word = s_key[lp];
-            const uint32_t d = kDigitOfWord ? (uint32_t)(word >> shift) & dmask : s_dig[lp];
+            const uint32_t d = kDigitOfWord ? (uint32_t)(word >> shift) & dmask
+                                            : dik ? (uint32_t)(word >> 56) : (uint32_t)s_dig[lp];
             const uint32_t g = base[d] + (lp - start[d]);
             if (g >= ts.seg_begin && g < ts.seg_end) {
                 if (!src_packed<kSrc>()) dst_idx[g] = s_idx[lp];
-                dst_key[g] = word;
+                dst_key[g] = dik ? word & kKeyLow56 : word;
                 if (kSrc == kSrcBatch) ba.aux_out[g] = s_bkt[lp];
             } else {
                 atomicOr(err, ERR_INTERNAL);
