@@ -459,6 +459,12 @@ struct Plan {
 #ifndef GESMC_DIGIT_IN_KEY
 #define GESMC_DIGIT_IN_KEY 1
 #endif
+// Level-1 counts of the next superstep taken in the first decision round
+// (k_decide_chain's NextCounts); 0 disables it.
+#ifndef GESMC_COUNT_AHEAD
+#define GESMC_COUNT_AHEAD 1
+#endif
+
 uint32_t digit_in_key(const Plan &p, uint32_t n) {
     return GESMC_DIGIT_IN_KEY && n <= (1u << 24) && p.b1 <= 8 && p.b2 <= 8 ? 1u : 0u;
 }
@@ -638,7 +644,8 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
                               int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
-                              const uint32_t *in_idx, const unsigned long long *in_key, const EmitOut *eo) {
+                              const uint32_t *in_idx, const unsigned long long *in_key, const EmitOut *eo,
+                              bool counts1_ready) {
     // level-1 input: buffer `src`, or the given arrays (the pair records of kSrcEmit)
     const uint32_t *src_i = in_idx ? in_idx : idx[src];
     const unsigned long long *src_k = in_key ? in_key : key[src];
@@ -663,7 +670,7 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
         set_error("internal: emit outputs need a tuple source computed from the pair records");
         return GESMC_E_INTERNAL;
     }
-    if (!fused_emit)
+    if (!fused_emit && !counts1_ready)  // (ready: counted by the previous superstep's first decision round)
         GESMC_TRY(launch(c, s, kid_counts1, n, k_tile_counts<kSrc1, kTile, true>,
                          dim3(persistent_blocks(c, k_tile_counts<kSrc1, kTile, true>, (size_t)nd1 * 4, p.ntiles1)),
                          dim3(kBlock), (size_t)nd1 * 4, src_i, src_k, t, k0, k1, shift1, (int)p.b1, 0u, n,
@@ -716,14 +723,15 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
                               int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
                               const uint32_t *in_idx = nullptr, const unsigned long long *in_key = nullptr,
-                              const EmitOut *eo = nullptr) {
+                              const EmitOut *eo = nullptr, bool counts1_ready = false) {
     if (p.tile == (uint32_t)kTileLarge)
         return radix_distribute_t<kSrc1, kSrc2, kTileLarge>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                             bucket_off, nbuckets, kid_counts1, kid_scatter1,
-                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key, eo);
+                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key, eo,
+                                                            counts1_ready);
     return radix_distribute_t<kSrc1, kSrc2, kTileSmall>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
                                                         bucket_off, nbuckets, kid_counts1, kid_scatter1, kid_counts2,
-                                                        kid_scatter2, ba1, ba2, in_idx, in_key, eo);
+                                                        kid_scatter2, ba1, ba2, in_idx, in_key, eo, counts1_ready);
 }
 
 // One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
@@ -745,8 +753,10 @@ struct BatchStep {
 // per graph with its own keys if `bs` describes a batch (plan bits then
 // number the global buckets).  Returns the buffer index holding the sorted
 // records.
+// counts1_ready: the first level's tile counts of superstep t are in
+// c->counts1 already (k_decide_chain of superstep t - 1 wrote them).
 gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1, int src,
-                     int *sorted_out, bool clear_table, const BatchStep *bs = nullptr) {
+                     int *sorted_out, bool clear_table, const BatchStep *bs = nullptr, bool counts1_ready = false) {
     const uint32_t m = p.m;
     const int X = (src + 1) % 3, Y = (src + 2) % 3;
     // the table strategy resets its table, statuses and list counters here;
@@ -784,7 +794,8 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
         pa.dig_in_key = p.dig_in_key;
         GESMC_TRY((radix_distribute<kSrcPerm, kSrcPerm>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
                                                         &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
-                                                        KID_SCATTER2, pa, pa)));
+                                                        KID_SCATTER2, pa, pa, nullptr, nullptr, nullptr,
+                                                        counts1_ready)));
     }
     const int sorted = (dist == X) ? Y : X;  // sort into the buffer not holding the buckets
     GESMC_TRY(launch(c, s, KID_SORT, m, k_sort_buckets, dim3(persistent_blocks(c, k_sort_buckets, sort_lds, nb)),
@@ -895,11 +906,14 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
 
 // One superstep with the partitioned resolution (state in buffer 0).
 // vend bounds the vertex ids of the keys (a batch: bs->vend, bs->dend).
+// counts1_ready: this superstep's first radix level was counted by the
+// previous one; count_next: count superstep t + 1's in the first decision
+// round (plain form only, a plan with a first radix level).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
                                    uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0,
-                                   uint32_t cls = 0) {
+                                   uint32_t cls = 0, bool counts1_ready = false, bool count_next = false) {
     int sorted = 0;
-    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs));
+    GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs, counts1_ready));
     const uint32_t *si = c->idx[sorted];
     const unsigned long long *sk = c->key[sorted];
     const uint32_t nslots = 4 * p.ell + (p.m & 1u);
@@ -932,17 +946,22 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
                                     c->fuse_emit ? &es : nullptr, bs ? bs->vend : vend, bs ? bs->dend : vend,
                                     fused ? &eo : nullptr, bs ? bs->mmax : 0));
     if (p.ell == 0) return GESMC_OK;
+    NextCounts nc{};
+    if (count_next) {
+        GESMC_TRY(ensure_words(c, &c->counts1, &c->cap_counts1, radix_words(p).counts1));
+        nc = NextCounts{c->counts1, t + 1, k0, k1, 64 - (int)p.b1, (int)p.b1, p.tile, p.m};
+    }
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
                      (const uint32_t *)nullptr, c->ulist[0], &c->ucount[0], (uint32_t *)nullptr, c->bslot + ge,
-                     c->ctr_step, cls));
+                     c->ctr_step, cls, nc));
     const uint32_t rblocks = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(p.ell, kBlock), c->num_cus * 4));
     int j = 0;
     for (; j < c->fast_rounds; ++j) {
         GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN, 0, k_decide_chain, dim3(rblocks), dim3(kBlock), 0, si, sk, p.ell,
                          c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)c->ulist[j % 2],
                          (const uint32_t *)&c->ucount[j % 3], c->ulist[(j + 1) % 2], &c->ucount[(j + 1) % 3],
-                         &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step, cls));
+                         &c->ucount[(j + 2) % 3], (uint4 *)nullptr, c->ctr_step, cls, NextCounts{}));
     }
     GESMC_TRY(launch(c, s, KID_FINISH_CHAIN, 0, k_finish_chain, dim3(1), dim3(kFinishBlock), 0, si, sk, p.ell,
                      c->info, c->st, c->idx[0], c->key[0], c->ulist[j % 2], &c->ucount[j % 3],
@@ -1208,6 +1227,9 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
         }
     }
     if (m >= 2) {
+        // supersteps after the first take their first radix level's counts
+        // from the previous superstep's first decision round
+        const bool chain_counts = GESMC_COUNT_AHEAD && p.bbits > 0 && p.b1 > 0 && p.ell > 0;
         for (uint32_t q = 0; q < r; ++q) {
             c->ctr_step = c->ctr + q;
             const uint32_t dup = q == 0 ? ERR_DUP : ERR_INTERNAL;
@@ -1216,7 +1238,8 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
             else if (table)
                 GESMC_TRY(superstep(c, s, p, t0 + q, k0, k1, pl, dup));
             else
-                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup, nullptr, n, cls));
+                GESMC_TRY(superstep_partitioned(c, s, p, t0 + q, k0, k1, pl, dup, nullptr, n, cls,
+                                                chain_counts && q > 0, chain_counts && q + 1 < r));
         }
     }
     if (d_outcome && p.ell > 0)

@@ -714,7 +714,21 @@ __device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint
     return false;
 }
 
+// The next superstep's first radix level, counted while round 1 runs: the
+// records' positions do not change in a superstep (the sorted records of
+// position p keep their index), so the level-1 digit counts of superstep
+// t + 1 over tiles of `tile` positions need only the indices, which round 1
+// reads anyway, and the Philox work hides under its memory traffic.
+struct NextCounts {
+    uint32_t *counts;  // [tile][digit], nullptr: none
+    uint32_t t, k0, k1;
+    int shift, dbits;
+    uint32_t tile, m;
+};
+
 // Round 1 (list == nullptr: every switch) or a later round over a list.
+// With nc.counts (round 1 only), each workgroup takes whole tiles of
+// nc.tile / 2 switches and also writes their counts.
 __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restrict__ s_idx,
                                                          const unsigned long long *__restrict__ s_key, uint32_t ell,
                                                          uint2 *info, uint8_t *st,
@@ -726,30 +740,60 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
                                                          uint32_t *__restrict__ next_count,
                                                          uint32_t *__restrict__ zero_count,
                                                          uint4 *__restrict__ bslot, StepCounters *ctr,
-                                                         uint32_t cls) {
+                                                         uint32_t cls, NextCounts nc) {
     __shared__ BlockCounts bc;
+    __shared__ uint32_t hs[1u << kMaxCoarseBits];
     if (threadIdx.x == 0) bc = BlockCounts{0, 0, 0, 0};
     __syncthreads();
     // the counter cleared here is the one the round after next fills
     if (zero_count && blockIdx.x == 0 && threadIdx.x == 0) *zero_count = 0;
+    auto decide_one = [&](uint32_t k, bool *wait, uint2 *ij_out) {
+        const uint8_t sk = st[k];
+        const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
+        const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
+        const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
+        *ij_out = ij;
+        if (sk == ST_UNDECIDED) *wait = decide_switch_chain(k, recs, ij, ee, info, st, out_idx, out_key, &bc, cls);
+    };
     const uint32_t n = list ? min(*count, ell) : ell;
-    const uint32_t stride = gridDim.x * kBlock;
-    const uint32_t trips = (n + stride - 1) / stride;
-    for (uint32_t r = 0; r < trips; ++r) {
-        const uint32_t q = r * stride + blockIdx.x * kBlock + threadIdx.x;
-        bool wait = false;
-        uint32_t k = 0;
-        if (q < n) {
-            k = list ? list[q] : q;
-            if (k < ell) {
-                const uint8_t sk = st[k];
-                const uint4 recs = reinterpret_cast<const uint4 *>(info)[k];
-                const uint2 ij = reinterpret_cast<const uint2 *>(s_idx)[k];
-                const ulonglong2 ee = reinterpret_cast<const ulonglong2 *>(s_key)[k];
-                if (sk == ST_UNDECIDED) wait = decide_switch_chain(k, recs, ij, ee, info, st, out_idx, out_key, &bc, cls);
+    if (nc.counts) {
+        const uint32_t nd = 1u << nc.dbits, dmask = nd - 1, half = nc.tile / 2;
+        const uint32_t ntiles = (nc.m + nc.tile - 1) / nc.tile;
+        auto digit = [&](uint32_t i) { return (uint32_t)(perm_key(i, nc.t, nc.k0, nc.k1) >> nc.shift) & dmask; };
+        for (uint32_t w = blockIdx.x; w < ntiles; w += gridDim.x) {
+            for (uint32_t d = threadIdx.x; d < nd; d += kBlock) hs[d] = 0;
+            __syncthreads();
+            for (uint32_t j = 0; j < half; j += kBlock) {
+                const uint32_t k = w * half + j + threadIdx.x;
+                bool wait = false;
+                if (k < ell) {
+                    uint2 ij;
+                    decide_one(k, &wait, &ij);
+                    atomicAdd(&hs[digit(ij.x)], 1u);
+                    atomicAdd(&hs[digit(ij.y)], 1u);
+                }
+                append_undecided(wait, k, next_list, next_count, &ctr->undecided_round1);
             }
+            if ((nc.m & 1u) && threadIdx.x == 0 && (nc.m - 1) / nc.tile == w)  // the idle record of odd m
+                atomicAdd(&hs[digit(s_idx[nc.m - 1])], 1u);
+            __syncthreads();
+            for (uint32_t d = threadIdx.x; d < nd; d += kBlock) nc.counts[(size_t)w * nd + d] = hs[d];
+            __syncthreads();
         }
-        append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
+    } else {
+        const uint32_t stride = gridDim.x * kBlock;
+        const uint32_t trips = (n + stride - 1) / stride;
+        for (uint32_t r = 0; r < trips; ++r) {
+            const uint32_t q = r * stride + blockIdx.x * kBlock + threadIdx.x;
+            bool wait = false;
+            uint32_t k = 0;
+            if (q < n) {
+                k = list ? list[q] : q;
+                uint2 ij;
+                if (k < ell) decide_one(k, &wait, &ij);
+            }
+            append_undecided(wait, k, next_list, next_count, list ? nullptr : &ctr->undecided_round1);
+        }
     }
     if (bslot)
         store_counts(&bc, bslot + blockIdx.x);
