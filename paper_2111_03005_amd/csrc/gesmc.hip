@@ -788,7 +788,8 @@ gesmc_status permute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uin
         const SrcArgs ba2{bs->gr, bs->bk, nullptr, bs->step, (int)p.bbits};
         GESMC_TRY((radix_distribute<kSrcBatch, kSrcBucket>(c, s, p, m, t, k0, k1, c->idx, c->key, src, mid, dst, &dist,
                                                            &boff, &nb, KID_COUNTS1, KID_SCATTER1, KID_COUNTS2,
-                                                           KID_SCATTER2, ba1, ba2)));
+                                                           KID_SCATTER2, ba1, ba2, nullptr, nullptr, nullptr,
+                                                           counts1_ready)));
     } else {
         SrcArgs pa{};
         pa.dig_in_key = p.dig_in_key;
@@ -908,10 +909,12 @@ gesmc_status partition_and_resolve(gesmc_ctx *c, hipStream_t s, uint32_t nslots,
 // vend bounds the vertex ids of the keys (a batch: bs->vend, bs->dend).
 // counts1_ready: this superstep's first radix level was counted by the
 // previous one; count_next: count superstep t + 1's in the first decision
-// round (plain form only, a plan with a first radix level).
+// round (a plan with a first radix level; a batch passes its next step's
+// plan, next_p, whose positions are a prefix of this step's).
 gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t t, uint32_t k0, uint32_t k1,
                                    uint32_t pl, uint32_t dup_bit, const BatchStep *bs = nullptr, uint64_t vend = 0,
-                                   uint32_t cls = 0, bool counts1_ready = false, bool count_next = false) {
+                                   uint32_t cls = 0, bool counts1_ready = false, bool count_next = false,
+                                   const Plan *next_p = nullptr) {
     int sorted = 0;
     GESMC_TRY(permute(c, s, p, t, k0, k1, 0, &sorted, false, bs, counts1_ready));
     const uint32_t *si = c->idx[sorted];
@@ -948,8 +951,10 @@ gesmc_status superstep_partitioned(gesmc_ctx *c, hipStream_t s, const Plan &p, u
     if (p.ell == 0) return GESMC_OK;
     NextCounts nc{};
     if (count_next) {
-        GESMC_TRY(ensure_words(c, &c->counts1, &c->cap_counts1, radix_words(p).counts1));
-        nc = NextCounts{c->counts1, t + 1, k0, k1, 64 - (int)p.b1, (int)p.b1, p.tile, p.m};
+        const Plan &q = next_p ? *next_p : p;
+        GESMC_TRY(ensure_words(c, &c->counts1, &c->cap_counts1, radix_words(q).counts1));
+        nc = NextCounts{c->counts1, t + 1, k0, k1, 64 - (int)q.b1, (int)q.b1, q.tile, q.m,
+                        bs ? bs->gr : nullptr, bs ? bs->pg : nullptr, bs ? bs->step + 1 : 0u, (int)q.bbits};
     }
     GESMC_TRY(launch(c, s, KID_DECIDE_CHAIN1, p.ell, k_decide_chain, dim3(gd), dim3(kBlock), 0, si, sk, p.ell,
                      c->info, c->st, c->idx[0], c->key[0], (const uint32_t *)nullptr,
@@ -1878,15 +1883,29 @@ gesmc_status run_batch_impl(gesmc_ctx *c, void *stream, uint32_t G, const uint64
         if (s1 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[0], s1), "hipEventRecord"));
         if (s2 != s) GESMC_TRY(check_hip(hipEventRecord(c->join_ev[1], s2), "hipEventRecord"));
         // superstep s switches the ranks [0, active_s): those with r > s
+        // (each step after the first takes its first radix level's counts from
+        // the previous step's first decision round)
+        auto active = [&](uint32_t st, uint32_t q) {
+            while (q > 0 && r_pipe(order[q - 1]) <= st) --q;
+            return q;
+        };
+        auto step_plan = [&](uint32_t q) {
+            return batch_plan(c, q < G ? gr[q].poff : npos, q < G ? gr[q].bbase : (uint32_t)bbase);
+        };
+        auto counts_ahead = [&](const Plan &q) { return GESMC_COUNT_AHEAD && q.bbits > 0 && q.b1 > 0 && q.m >= 2; };
         uint32_t qa = nactive;
+        bool ready = false;
         for (uint32_t st = 0; st < rmax; ++st) {
-            while (qa > 0 && r_pipe(order[qa - 1]) <= st) --qa;
-            const uint32_t P = qa < G ? gr[qa].poff : npos;  // positions of the switched ranks
-            const uint32_t NB = qa < G ? gr[qa].bbase : (uint32_t)bbase;
-            const Plan p = batch_plan(c, P, NB);
+            qa = active(st, qa);
+            const Plan p = step_plan(qa);
+            const uint32_t qn = st + 1 < rmax ? active(st + 1, qa) : 0;
+            const Plan pn = step_plan(qn);
+            const bool next = qn > 0 && counts_ahead(p) && counts_ahead(pn);
             BatchStep bs{c->gr, qa, st, c->pg, c->bk, stats ? c->gacc : nullptr, ge_all, vbase, nmax, mmax};
             c->ctr_step = c->ctr + st;
-            GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs));
+            GESMC_TRY(superstep_partitioned(c, s, p, 0u, 0u, 0u, pl, st == 0 ? ERR_DUP : ERR_INTERNAL, &bs, 0, 0,
+                                            ready, next, &pn));
+            ready = next;
         }
         if (s1 != s) GESMC_TRY(check_hip(hipStreamWaitEvent(s, c->join_ev[0], 0), "hipStreamWaitEvent"));
         if (s2 != s) GESMC_TRY(check_hip(hipStreamWaitEvent(s, c->join_ev[1], 0), "hipStreamWaitEvent"));

@@ -719,11 +719,17 @@ __device__ __forceinline__ bool decide_switch_chain(uint32_t k, uint4 recs, uint
 // position p keep their index), so the level-1 digit counts of superstep
 // t + 1 over tiles of `tile` positions need only the indices, which round 1
 // reads anyway, and the Philox work hides under its memory traffic.
+// A batch (gr != nullptr) counts the global buckets of its next step's
+// prefix of m positions (each position's graph from pg).
 struct NextCounts {
     uint32_t *counts;  // [tile][digit], nullptr: none
     uint32_t t, k0, k1;
     int shift, dbits;
     uint32_t tile, m;
+    const BatchGraph *gr;  // batch: graph records, the graph of each position,
+    const uint32_t *pg;    // the next step and its bucket bits
+    uint32_t step;
+    int bbits;
 };
 
 // Round 1 (list == nullptr: every switch) or a later round over a list.
@@ -758,8 +764,16 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
     const uint32_t n = list ? min(*count, ell) : ell;
     if (nc.counts) {
         const uint32_t nd = 1u << nc.dbits, dmask = nd - 1, half = nc.tile / 2;
-        const uint32_t ntiles = (nc.m + nc.tile - 1) / nc.tile;
-        auto digit = [&](uint32_t i) { return (uint32_t)(perm_key(i, nc.t, nc.k0, nc.k1) >> nc.shift) & dmask; };
+        // tiles of the next step's positions (a batch's prefix may shrink: the
+        // tiles then also cover this step's remaining switches, uncounted)
+        const uint32_t ncount = (nc.m + nc.tile - 1) / nc.tile;
+        const uint32_t ntiles = max(ncount, (ell + half - 1) / half);
+        auto digit = [&](uint32_t i, uint32_t pos) -> uint32_t {
+            if (!nc.gr) return (uint32_t)(perm_key(i, nc.t, nc.k0, nc.k1) >> nc.shift) & dmask;
+            const BatchGraph &g = nc.gr[nc.pg[pos]];
+            const uint64_t word = (uint64_t)batch_bucket(g, batch_perm_key(g, i, nc.step)) << (64 - nc.bbits);
+            return (uint32_t)(word >> nc.shift) & dmask;
+        };
         for (uint32_t w = blockIdx.x; w < ntiles; w += gridDim.x) {
             for (uint32_t d = threadIdx.x; d < nd; d += kBlock) hs[d] = 0;
             __syncthreads();
@@ -769,15 +783,18 @@ __global__ __launch_bounds__(kBlock) void k_decide_chain(const uint32_t *__restr
                 if (k < ell) {
                     uint2 ij;
                     decide_one(k, &wait, &ij);
-                    atomicAdd(&hs[digit(ij.x)], 1u);
-                    atomicAdd(&hs[digit(ij.y)], 1u);
+                    if (2 * k + 1 < nc.m) {  // both positions of a pair lie in one graph
+                        atomicAdd(&hs[digit(ij.x, 2 * k)], 1u);
+                        atomicAdd(&hs[digit(ij.y, 2 * k)], 1u);
+                    }
                 }
                 append_undecided(wait, k, next_list, next_count, &ctr->undecided_round1);
             }
             if ((nc.m & 1u) && threadIdx.x == 0 && (nc.m - 1) / nc.tile == w)  // the idle record of odd m
-                atomicAdd(&hs[digit(s_idx[nc.m - 1])], 1u);
+                atomicAdd(&hs[digit(s_idx[nc.m - 1], nc.m - 1)], 1u);
             __syncthreads();
-            for (uint32_t d = threadIdx.x; d < nd; d += kBlock) nc.counts[(size_t)w * nd + d] = hs[d];
+            if (w < ncount)
+                for (uint32_t d = threadIdx.x; d < nd; d += kBlock) nc.counts[(size_t)w * nd + d] = hs[d];
             __syncthreads();
         }
     } else {
