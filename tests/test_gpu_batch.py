@@ -94,6 +94,21 @@ def test_mixed_batch_exact(ctx, pl):
     assert tot["legal"] == sum(s["legal"] for s in stats)
 
 
+def test_batch_shrinking_prefix_exact(ctx):
+    """Graphs large enough for the radix pipeline (not the LDS chain) with r
+    from 1 to 6, so the switched prefix of ranks shrinks from step to step;
+    each step's first radix level is counted by the previous step's first
+    decision round for the next (smaller) prefix.  Every graph exact."""
+    graphs = graphgen.batch_graphs(12, 31, 1e4, 6e4)
+    assert all(len(E) > 6144 for E, _ in graphs)
+    rng = np.random.default_rng(31)
+    seeds = [int(x) for x in rng.integers(0, 2**63, len(graphs))]
+    rs = [1 + g % 6 for g in range(len(graphs))]
+    t0s = [int(x) for x in rng.integers(0, 100, len(graphs))]
+    got, offs, stats, _ = run_batch(ctx, graphs, seeds, rs, t0s)
+    check_against_oracle(graphs, got, offs, stats, seeds, rs, t0s, 0, range(len(graphs)))
+
+
 def test_batch_equals_single_runs(ctx):
     """Each graph's result is the same alone (gesmc_run) and in the mix."""
     graphs, seeds, rs, t0s = mixed_batch(seed=11, G=24)

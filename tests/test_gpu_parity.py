@@ -346,6 +346,17 @@ def test_unpermute_buckets_exact(ctx):
         assert torch.equal(one, two)
 
 
+def test_count_ahead_tile_edges(ctx):
+    """A superstep's first radix level is counted by the previous superstep's
+    first decision round, over tiles of 2048 positions.  Edge counts around
+    tile ends (odd m puts the idle record alone in the last tile at 2049,
+    4097 and 6145), several supersteps, a nonzero t0: exact against the oracle."""
+    base = graphgen.gnp(3000, 0.0025, 21)
+    assert len(base) >= 6145
+    for m in (2049, 2050, 4095, 4096, 4097, 6144, 6145):
+        check_run(ctx, base[:m].copy(), 3000, 70 + m, 5, 3, label="tile edge m=%d" % m)
+
+
 def test_repeat_determinism(ctx):
     E = graphgen.powerlaw_graph(100000, 2.3, 2, 316, 4)
     outs = [to_host(ctx.run(to_dev(E), 100000, 8, r=3)[0]) for _ in range(3)]
