@@ -491,6 +491,9 @@ uint32_t level1_bits(uint32_t B, uint32_t cap) {
 }
 
 // Plan of a batch permutation: global buckets [0, nb) over m records.
+#ifndef GESMC_BATCH_SMALL_TILES
+#define GESMC_BATCH_SMALL_TILES 1
+#endif
 Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
     Plan p;
     p.m = m;
@@ -502,7 +505,7 @@ Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
     p.b2 = B - p.b1;
     p.ncoarse = 1u << p.b1;
     p.nfine = 1u << B;
-    p.tile = tile_for(m);
+    p.tile = GESMC_BATCH_SMALL_TILES ? (uint32_t)kTileSmall : tile_for(m);
     p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, p.tile));
     return p;
 }
