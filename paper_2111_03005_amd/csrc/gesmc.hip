@@ -483,9 +483,12 @@ uint32_t scan_chunk(uint32_t ntiles) {
 }
 
 // Digit bits of the first level: an even split of B (so both levels write
-// runs of similar length), or at most `cap` bits if the option sets one.
-uint32_t level1_bits(uint32_t B, uint32_t cap) {
-    if (cap == 0) return std::min<uint32_t>(kMaxCoarseBits, (B + 1) / 2);
+// runs of similar length; from 17 bits on, an odd B gives the first level
+// the smaller half, whose scatter then writes longer runs per digit, unless
+// `ceil_half`: batch permutations, whose first level stages more per record,
+// keep the larger half), or at most `cap` bits if the option sets one.
+uint32_t level1_bits(uint32_t B, uint32_t cap, bool ceil_half = false) {
+    if (cap == 0) return std::min<uint32_t>(kMaxCoarseBits, B >= 17 && !ceil_half ? B / 2 : (B + 1) / 2);
     // the second level keeps at most kMaxLevelBits (its LDS counters)
     return std::min<uint32_t>(B, std::max<uint32_t>(cap, B > kMaxLevelBits ? B - kMaxLevelBits : 0));
 }
@@ -501,7 +504,7 @@ Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
     uint32_t B = 0;
     while ((1ull << B) < nb) ++B;
     p.bbits = B;
-    p.b1 = level1_bits(B, c->level1_cap);
+    p.b1 = level1_bits(B, c->level1_cap, true);
     p.b2 = B - p.b1;
     p.ncoarse = 1u << p.b1;
     p.nfine = 1u << B;
