@@ -525,6 +525,7 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
     using Word = typename K::Word;
     constexpr int kPer = (int)(kMax / kThreads);  // permutation items per thread
     constexpr int kSw = kPer / 2;                 // switches per thread
+    static_assert(kSw <= 4, "a thread's switch statuses are the bytes of one 32-bit word");
     constexpr int kTu = 4 * kSw + 1;              // tuples per thread (+ the idle record of odd m)
     constexpr int kPiW = kPer / 2;                // 32-bit words of a permutation row per thread
     constexpr uint8_t kAbsent = 0xFF;             // a switch index at or beyond ell
