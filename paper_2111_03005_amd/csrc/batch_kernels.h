@@ -569,6 +569,12 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
         uint32_t sst = 0;
         constexpr int kSe = kPre ? kSw : 1;
         typename K::Key se[kSe][2];
+        // compact keys with kPre: the targets too, computed once per superstep
+        // (fewer VALU instructions on the chain's one CU; the 64-bit keys of
+        // the other classes would not fit the registers)
+        constexpr bool kTg = kPre && kCompact;
+        constexpr int kTe = kTg ? kSw : 1;
+        typename K::Key tg[kTe][2];
         auto key_of = [&](int y, uint32_t h) -> typename K::Key {
             if (kPre) return se[y < kSe ? y : 0][h];
             return L.E[h ? sij[y] >> 16 : sij[y] & 0xFFFFu];
@@ -594,6 +600,10 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                 status = ST_PL;
             } else {
                 const Targets T = switch_targets(e1, e2, i < j);
+                if (kTg) {
+                    tg[y < kTe ? y : 0][0] = K::pack(T.A);
+                    tg[y < kTe ? y : 0][1] = K::pack(T.B);
+                }
                 if (T.loop)
                     status = ST_LOOP;
                 else if (T.A == e1 || T.A == e2 || T.B == e1 || T.B == e2)
@@ -627,8 +637,12 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
                     return true;
                 }
                 if (st_of(y) != ST_UNDECIDED) return false;
-                const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
-                *w = K::word(K::pack(h == 2 ? T.A : T.B));
+                if (kTg) {
+                    *w = K::word(tg[y < kTe ? y : 0][h - 2]);
+                } else {
+                    const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
+                    *w = K::word(K::pack(h == 2 ? T.A : T.B));
+                }
                 *g = (uint16_t)(kSmTagInsert | (k << 1) | (h - 2));
                 return true;
             };
@@ -665,7 +679,10 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
             if (st_of(y) != ST_UNDECIDED) continue;
             const uint32_t k = tid + (uint32_t)y * kThreads;
             Word tw[2] = {0, 0};  // the two INSERT words, from the keys in registers (kPre)
-            if (kPre) {
+            if (kTg) {
+                tw[0] = K::word(tg[y < kTe ? y : 0][0]);
+                tw[1] = K::word(tg[y < kTe ? y : 0][1]);
+            } else if (kPre) {
                 const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)),
                                                  (sij[y] & 0xFFFFu) < (sij[y] >> 16));
                 tw[0] = K::word(K::pack(T.A));
@@ -723,9 +740,14 @@ __device__ __forceinline__ void small_chain_body(SmallLds<kMax, kThreads, kCompa
             const uint32_t sv = st_of(y);
             if (sv == ST_LEGAL) {
                 const uint32_t i = sij[y] & 0xFFFFu, j = sij[y] >> 16;
-                const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
-                L.E[i] = K::pack(T.A);
-                L.E[j] = K::pack(T.B);
+                if (kTg) {
+                    L.E[i] = tg[y < kTe ? y : 0][0];
+                    L.E[j] = tg[y < kTe ? y : 0][1];
+                } else {
+                    const Targets T = switch_targets(K::unpack(key_of(y, 0)), K::unpack(key_of(y, 1)), i < j);
+                    L.E[i] = K::pack(T.A);
+                    L.E[j] = K::pack(T.B);
+                }
                 ++c[0];
             }
             c[1] += sv == ST_LOOP;
