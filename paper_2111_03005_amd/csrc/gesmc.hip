@@ -452,6 +452,7 @@ gesmc_status launch(gesmc_ctx *c, hipStream_t s, int kid, uint64_t items, Kern k
 struct Plan {
     uint32_t m, ell, bbits, b1, b2, ncoarse, nfine, ntiles1, tile;
     uint32_t dig_in_key = 0;  // the permutation's scatters stage digits in the keys' top byte (SrcArgs)
+    uint32_t tile2 = 0;       // second-level tile records (0: tile)
 };
 
 // Digits in the keys' top byte (SrcArgs::dig_in_key) when every vertex id is
@@ -493,9 +494,12 @@ uint32_t level1_bits(uint32_t B, uint32_t cap, bool ceil_half = false) {
     return std::min<uint32_t>(B, std::max<uint32_t>(cap, B > kMaxLevelBits ? B - kMaxLevelBits : 0));
 }
 
-// Plan of a batch permutation: global buckets [0, nb) over m records.
-#ifndef GESMC_BATCH_SMALL_TILES
-#define GESMC_BATCH_SMALL_TILES 1
+// Plan of a batch permutation: global buckets [0, nb) over m records.  The
+// second level runs on 2048-record tiles at every size (its scatter stages
+// 14 bytes per record: smaller workgroups, more of them per CU), the first
+// on the size's usual tile; 0: both levels on the usual tile.
+#ifndef GESMC_BATCH_LEVEL2_SMALL_TILES
+#define GESMC_BATCH_LEVEL2_SMALL_TILES 1
 #endif
 Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
     Plan p;
@@ -508,7 +512,8 @@ Plan batch_plan(const gesmc_ctx *c, uint32_t m, uint64_t nb) {
     p.b2 = B - p.b1;
     p.ncoarse = 1u << p.b1;
     p.nfine = 1u << B;
-    p.tile = GESMC_BATCH_SMALL_TILES ? (uint32_t)kTileSmall : tile_for(m);
+    p.tile = tile_for(m);
+    p.tile2 = GESMC_BATCH_LEVEL2_SMALL_TILES ? (uint32_t)kTileSmall : 0u;
     p.ntiles1 = std::max<uint32_t>(1, ceil_div(m, p.tile));
     return p;
 }
@@ -613,11 +618,18 @@ struct RadixWords {
     uint64_t counts1, partial, counts2;
 };
 
+// An upper bound of the second level's tiles, less the coarse segment count
+// (a segment's last tile may be partial).
+uint64_t level2_tiles(const Plan &p) {
+    const uint32_t t2 = p.tile2 ? p.tile2 : p.tile;
+    return std::max<uint64_t>(1, ceil_div((uint64_t)p.m, t2));
+}
+
 RadixWords radix_words(const Plan &p) {
     const uint64_t nd1 = 1ull << p.b1, nd2 = 1ull << p.b2;
     const uint64_t nchunks = ceil_div(p.ntiles1, scan_chunk(p.ntiles1));
     return RadixWords{(uint64_t)p.ntiles1 * nd1, nchunks * nd1,
-                      p.b2 > 0 ? ((uint64_t)p.ntiles1 + p.ncoarse) * nd2 : 0};
+                      p.b2 > 0 ? ((uint64_t)level2_tiles(p) + p.ncoarse) * nd2 : 0};
 }
 
 // 1: with fused tuple passes, the emit runs inside the first tuple count pass
@@ -645,7 +657,7 @@ constexpr uint32_t kEmitSlotsMax = 8192;  // workgroups of k_emit_counts (count 
 // batch arguments ba1 / ba2 of those levels.  Leaves c->coarse_off /
 // c->fine_off as the bucket boundaries; returns the buffer index holding the
 // result in *out.
-template <int kSrc1, int kSrc2, int kTile>
+template <int kSrc1, int kSrc2, int kTile, int kTile2>
 gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32_t n, uint32_t t, uint32_t k0,
                               uint32_t k1, uint32_t *const *idx, unsigned long long *const *key, int src, int mid,
                               int dst, int *out, const uint32_t **bucket_off, uint32_t *nbuckets, int kid_counts1,
@@ -684,13 +696,13 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colsum, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colscan_top, dim3(1), dim3(kTopThreads), 0, c->partial, nchunks, (int)p.b1,
-                     c->coarse_off, c->tile_first, (uint32_t)kTile));
+                     c->coarse_off, c->tile_first, (uint32_t)kTile2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_colapply, dim3(nchunks), dim3(scan_threads), 0, c->counts1, p.ntiles1,
                      (int)p.b1, chunk, c->partial, c->coarse_off));
     const int lvl1_out = p.b2 > 0 ? mid : dst;
     const size_t lds1 =
         scatter_lds_bytes(p.b1, kTile, kSrc1 == kSrcBatch, !src_emits_packed<kSrc1>(), ba1.dig_in_key == 0);
-    const size_t lds2 = scatter_lds_bytes(p.b2, kTile, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked,
+    const size_t lds2 = scatter_lds_bytes(p.b2, kTile2, kSrc2 == kSrcBatch, kSrc2 != kSrcPacked,
                                           kSrc2 != kSrcPacked && kSrc2 != kSrcHashed && ba2.dig_in_key == 0);
     GESMC_TRY(launch(c, s, kid_scatter1, n, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>,
                      dim3(persistent_blocks(c, k_scatter<kSrc1, kTile, scatter_threads(kTile), true>, lds1, p.ntiles1, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds1, src_i, src_k, idx[lvl1_out], key[lvl1_out], t, k0,
@@ -703,18 +715,18 @@ gesmc_status radix_distribute_t(gesmc_ctx *c, hipStream_t s, const Plan &p, uint
         return GESMC_OK;
     }
     const uint32_t nd2 = 1u << p.b2;
-    const uint32_t tiles2 = p.ntiles1 + p.ncoarse;  // >= sum over segments of their tiles
+    const uint32_t tiles2 = (uint32_t)level2_tiles(p) + p.ncoarse;  // >= sum over segments of their tiles
     GESMC_TRY(ensure_words(c, &c->counts2, &c->cap_counts2, rw.counts2));
     // packed words lost the first level's bits: the second level's are on top
     const int shift2 = kSrc2 == kSrcPacked ? 64 - (int)p.b2 : 64 - (int)p.bbits;
-    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile, false>,
-                     dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile, false>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
+    GESMC_TRY(launch(c, s, kid_counts2, n, k_tile_counts<kSrc2, kTile2, false>,
+                     dim3(persistent_blocks(c, k_tile_counts<kSrc2, kTile2, false>, (size_t)nd2 * 4, tiles2)), dim3(kBlock),
                      (size_t)nd2 * 4, idx[mid], key[mid], t, k0, k1, shift2, (int)p.b2, p.ncoarse, 0u,
                      (const uint32_t *)c->coarse_off, (const uint32_t *)c->tile_first, c->counts2, ba2));
     GESMC_TRY(launch(c, s, KID_SCAN, 0, k_segscan, dim3(p.ncoarse), dim3(kBlock), ((size_t)nd2 + kBlock + 1) * 4,
                      c->counts2, (int)p.b2, p.ncoarse, c->coarse_off, c->tile_first, c->fine_off));
-    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile, scatter_threads(kTile), false>,
-                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile, scatter_threads(kTile), false>, lds2, tiles2, scatter_threads(kTile))), dim3(scatter_threads(kTile)), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
+    GESMC_TRY(launch(c, s, kid_scatter2, n, k_scatter<kSrc2, kTile2, scatter_threads(kTile2), false>,
+                     dim3(persistent_blocks(c, k_scatter<kSrc2, kTile2, scatter_threads(kTile2), false>, lds2, tiles2, scatter_threads(kTile2))), dim3(scatter_threads(kTile2)), lds2, idx[mid], key[mid], idx[dst], key[dst], t, k0, k1, shift2, (int)p.b2,
                      p.ncoarse, 0u, (const uint32_t *)c->coarse_off, (const uint32_t *)c->tile_first,
                      (const uint32_t *)c->counts2, c->err, ba2));
     *out = dst;
@@ -730,14 +742,15 @@ gesmc_status radix_distribute(gesmc_ctx *c, hipStream_t s, const Plan &p, uint32
                               int kid_scatter1, int kid_counts2, int kid_scatter2, SrcArgs ba1, SrcArgs ba2,
                               const uint32_t *in_idx = nullptr, const unsigned long long *in_key = nullptr,
                               const EmitOut *eo = nullptr, bool counts1_ready = false) {
+#define GESMC_RADIX_T(T1, T2)                                                                                   \
+    radix_distribute_t<kSrc1, kSrc2, T1, T2>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out, bucket_off, nbuckets, \
+                                             kid_counts1, kid_scatter1, kid_counts2, kid_scatter2, ba1, ba2, in_idx,  \
+                                             in_key, eo, counts1_ready)
+    const uint32_t t2 = p.tile2 ? p.tile2 : p.tile;
     if (p.tile == (uint32_t)kTileLarge)
-        return radix_distribute_t<kSrc1, kSrc2, kTileLarge>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
-                                                            bucket_off, nbuckets, kid_counts1, kid_scatter1,
-                                                            kid_counts2, kid_scatter2, ba1, ba2, in_idx, in_key, eo,
-                                                            counts1_ready);
-    return radix_distribute_t<kSrc1, kSrc2, kTileSmall>(c, s, p, n, t, k0, k1, idx, key, src, mid, dst, out,
-                                                        bucket_off, nbuckets, kid_counts1, kid_scatter1, kid_counts2,
-                                                        kid_scatter2, ba1, ba2, in_idx, in_key, eo, counts1_ready);
+        return t2 == (uint32_t)kTileLarge ? GESMC_RADIX_T(kTileLarge, kTileLarge) : GESMC_RADIX_T(kTileLarge, kTileSmall);
+    return GESMC_RADIX_T(kTileSmall, kTileSmall);
+#undef GESMC_RADIX_T
 }
 
 // One superstep of a batch: the graphs switched (ranks [0, ngraphs), a
