@@ -152,6 +152,10 @@ struct gesmc_ctx {
     uint32_t bucket_avg = 3 * kLdsCap / 4;  // partition means fall in (avg / 2, avg]
     uint32_t sort_cap = kLdsCap;
     int fast_rounds = 2;
+    // GESMC_OPT_FAST_ROUNDS never set: a plain call runs adapt_rounds
+    // multi-workgroup rounds, taken from the previous plain call's rounds
+    bool fast_rounds_auto = true;
+    int adapt_rounds = 2;
     uint32_t round_limit = 0;  // decision rounds per superstep before GESMC_E_ROUNDS (0: none)
     int persist_mult = 0;  // persistent grids: resident workgroups x this (0: one workgroup per unit)
     uint32_t level1_cap = 0;  // first-level digit bits (0: even split)
@@ -1186,6 +1190,14 @@ gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, u
     return GESMC_OK;
 }
 
+// Adaptive multi-workgroup rounds of plain calls: after a call whose
+// supersteps took more than kAdaptRoundsAbove decision rounds, the next
+// plain call of the context runs kAdaptRoundsMany (power-law gamma = 2.01,
+// n = 2^20: 2.4e8 -> 3.2e8 attempts/s), else kAdaptRoundsFew (each extra
+// round is a launch, most of them empty on graphs without hubs).
+constexpr uint64_t kAdaptRoundsAbove = 16;
+constexpr int kAdaptRoundsMany = 64, kAdaptRoundsFew = 2;
+
 gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m64, uint32_t n,
                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats,
                       gesmc_step_stats *steps, uint8_t *d_outcome, uint32_t cls = 0) {
@@ -1219,6 +1231,13 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
         (m <= kMidMax || (m <= kCmpMax && n <= kCmpMaxN)))
         return run_small_impl(c, s, d_in, d_out, m, n, seed, t0, r, pl, stats);
     GESMC_TRY(ensure_capacity(c, m, cls != 0 && !(cls & CLS_MULTI)));
+    // the multi-workgroup decision rounds of this call (restored on return)
+    struct FastRounds {
+        gesmc_ctx *c;
+        int saved;
+        ~FastRounds() { c->fast_rounds = saved; }
+    } fast_rounds_guard{c, c->fast_rounds};
+    if (c->fast_rounds_auto) c->fast_rounds = c->adapt_rounds;
     GESMC_TRY(ensure_counters(c, r));
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     c->tuple_bytes = 0;
@@ -1280,6 +1299,14 @@ gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t
     if (c->profile) collect_profile(c);
     const gesmc_status st = map_err(*c->h_err);
     if (st != GESMC_OK) return st;
+    if (c->fast_rounds_auto && m >= 2 && r > 0) {
+        // supersteps with long dependency chains (hub edges) finish faster
+        // with many multi-workgroup rounds before the one-workgroup finisher;
+        // short ones would only pay empty launches
+        uint64_t maxr = 0;
+        for (uint32_t q = 0; q < r; ++q) maxr = std::max<uint64_t>(maxr, c->h_ctr[q].rounds);
+        c->adapt_rounds = maxr > kAdaptRoundsAbove ? kAdaptRoundsMany : kAdaptRoundsFew;
+    }
     const uint64_t att = (m >= 2) ? p.ell : 0;
     if (steps) {
         for (uint32_t q = 0; q < r; ++q) {
@@ -2610,6 +2637,7 @@ gesmc_status gesmc_set_option(gesmc_ctx *c, int option, int64_t v) {
         case GESMC_OPT_FAST_ROUNDS:
             if (v < 0 || v > 64) break;
             c->fast_rounds = (int)v;
+            c->fast_rounds_auto = false;
             return GESMC_OK;
         case GESMC_OPT_PROFILE:
             c->profile = v != 0;
