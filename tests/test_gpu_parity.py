@@ -387,6 +387,27 @@ def test_hub_heavy_powerlaw_exact(ctx):
     print("rounds per superstep:", [s["rounds"] for s in steps], flush=True)
 
 
+def test_adaptive_rounds_exact():
+    """With GESMC_OPT_FAST_ROUNDS unset, a plain call after one that needed
+    more than 16 decision rounds per superstep runs 64 multi-workgroup rounds
+    (then a graph without hubs brings the context back to 2).  Every call is
+    exact against the oracle whatever the schedule."""
+    _require_gpu()
+    import paper_2111_03005_amd as gesmc
+    n = 20000
+    E = graphgen.powerlaw_graph(n, 2.01, 1, int(n ** (1 / 1.01)), 3)
+    G = graphgen.gnp(3000, 0.004, 9)
+    c = gesmc.Context(0)
+    try:
+        _, steps = check_run(c, E, n, 11, 0, 3, label="hubs, first call")
+        assert max(s["rounds"] for s in steps) > 16, "the hub graph must need long chains"
+        check_run(c, E, n, 12, 3, 3, label="hubs, adapted rounds")
+        check_run(c, G, 3000, 13, 0, 3, label="no hubs after hubs")
+        check_run(c, E, n, 14, 0, 2, label="hubs again")
+    finally:
+        c.close()
+
+
 def test_full_gnp_n2p22_one_superstep_exact(ctx):
     E, n = graphgen.workload_gnp_large()
     check_run(ctx, E, n, 42, 0, 1, label="gnp_n2^22_d32 r=1")
