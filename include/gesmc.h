@@ -490,7 +490,7 @@ uint32_t gesmc_tune_cache_size(void);
 #define GESMC_OPT_BUCKET_AVG 1  /* largest mean records per sort bucket (64 .. 1152, default 1152)  */
 #define GESMC_OPT_SORT_CAP 2    /* records sorted in LDS per bucket (64 .. 1536, default 1536)     */
 #define GESMC_OPT_FAST_ROUNDS 3 /* multi-workgroup rounds before the 1-workgroup finisher (0 .. 64);
-                                   unset: 2, or 64 for a plain call after one on this context whose
+                                   unset: 2, or 128 for a plain call after one on this context whose
                                    supersteps needed more than 16 decision rounds (hub edges)      */
 #define GESMC_OPT_PROFILE 4     /* 1: time every kernel launch with HIP events                      */
 #define GESMC_OPT_STRATEGY 5    /* dependency resolution: 0 = tuples sorted by edge key per hash

@@ -1193,10 +1193,10 @@ gesmc_status run_small_impl(gesmc_ctx *c, hipStream_t s, const uint64_t *d_in, u
 // Adaptive multi-workgroup rounds of plain calls: after a call whose
 // supersteps took more than kAdaptRoundsAbove decision rounds, the next
 // plain call of the context runs kAdaptRoundsMany (power-law gamma = 2.01,
-// n = 2^20: 2.4e8 -> 3.2e8 attempts/s), else kAdaptRoundsFew (each extra
+// n = 2^20: 2.4e8 -> 3.4e8 attempts/s), else kAdaptRoundsFew (each extra
 // round is a launch, most of them empty on graphs without hubs).
 constexpr uint64_t kAdaptRoundsAbove = 16;
-constexpr int kAdaptRoundsMany = 64, kAdaptRoundsFew = 2;
+constexpr int kAdaptRoundsMany = 128, kAdaptRoundsFew = 2;
 
 gesmc_status run_impl(gesmc_ctx *c, void *stream, const uint64_t *d_in, uint64_t *d_out, uint64_t m64, uint32_t n,
                       uint64_t seed, uint32_t t0, uint32_t r, uint32_t pl, gesmc_stats *stats,
